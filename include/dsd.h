@@ -1,0 +1,135 @@
+/*
+ * libdsd -- k-clique-core densest-subgraph discovery on one AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * Method: Fang, Yu, Cheng, Lakshmanan, Lin, "Efficient Algorithms for
+ * Densest Subgraph Discovery", PVLDB 12(11), 2019.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns a dsd_status; DSD_OK == 0.  No C++ exception crosses
+ *    the ABI.  dsd_last_error() returns a thread-local message for the last
+ *    failing call.
+ *  - Psi is the h-clique, 2 <= h <= 6 (Definition 2 requires h >= 2; the paper
+ *    evaluates h in [2, 6], Section 8).  Other h -> DSD_EINVAL.
+ *  - Vertex ids are int32 in [0, n).  Outputs indexed by vertex use the
+ *    caller's ids.
+ *  - mem flags: DSD_MEM_HOST (0) means host memory; DSD_MEM_DEVICE (1) means
+ *    device memory of the current HIP device (e.g. a torch tensor's
+ *    data_ptr()).  Output buffers are caller-allocated, length n.
+ *  - Every call is synchronous: on return the outputs are written, on the
+ *    stream passed to dsd_build_csr (NULL = the null stream).
+ *  - Counts are exact unsigned 64-bit integers; a count that would not fit
+ *    returns DSD_EOVERFLOW.  Densities are exact reduced rationals num/den.
+ *  - A graph without any h-clique has density 0/1 and an empty member set
+ *    (also when n <= 1).
+ *  - There is no CPU fallback: without a usable GPU every compute call
+ *    returns DSD_EDEVICE.
+ */
+#ifndef DSD_H
+#define DSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSD_OK = 0,
+    DSD_EINVAL = -1,     /* bad argument: h outside [2,6], id outside [0,n), n < 0, NULL pointer */
+    DSD_ENOMEM = -2,     /* device or host allocation failed */
+    DSD_EDEVICE = -3,    /* HIP runtime error or no GPU */
+    DSD_EOVERFLOW = -4,  /* a count or a scaled flow capacity would overflow 64 bits */
+    DSD_EUNSUPPORTED = -5 /* graph shape beyond a documented kernel limit */
+} dsd_status;
+
+enum { DSD_MEM_HOST = 0, DSD_MEM_DEVICE = 1 };
+
+typedef struct dsd_graph_s *dsd_graph;
+
+/* Exact density mu/|V| (Definition 4), reduced; 0/1 when there is no clique. */
+typedef struct { uint64_t num, den; } dsd_rational;
+
+/* Per-call timing and size statistics (all times in milliseconds, measured
+ * with HIP events on the graph's stream).  Filled by every compute call when
+ * the caller passes a non-NULL pointer to dsd_last_stats. */
+typedef struct {
+    double t_orient_ms, t_enum_ms, t_peel_ms, t_locate_ms, t_exact_ms, t_total_ms;
+    uint64_t num_cliques;        /* mu(G, Psi) */
+    uint64_t peel_rounds;        /* round-synchronous sub-rounds of the peel */
+    uint64_t peel_levels;        /* distinct core values */
+    uint64_t flow_calls;         /* min-cut computations of the exact step */
+    uint64_t flow_nodes_max;     /* largest flow network built */
+    uint64_t located_vertices;   /* vertices handed to the exact step */
+} dsd_stats;
+
+/*
+ * Build a graph handle from raw vertex pairs (Section 3, data model: the graph
+ * is undirected, unweighted and simple).  The pairs are copied, symmetrised,
+ * and duplicates and self-loops dropped; the caller may free src/dst on
+ * return.  The handle owns every device buffer until dsd_graph_free.
+ * in_mem says where src/dst live.  stream: a hipStream_t or NULL.
+ * Errors: DSD_EINVAL (n < 0, num_pairs < 0, NULL arrays with num_pairs > 0,
+ * an id outside [0, n)), DSD_ENOMEM, DSD_EDEVICE.
+ */
+dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const int32_t *dst,
+                         int in_mem, void *stream, dsd_graph *out);
+
+/* n and the number of undirected edges after de-duplication. */
+dsd_status dsd_graph_info(dsd_graph g, int32_t *n, int64_t *m);
+
+/* Release the handle and its device memory.  NULL is accepted. */
+dsd_status dsd_graph_free(dsd_graph g);
+
+/*
+ * Clique-degree (Definition 3): deg[v] = number of h-clique instances that
+ * contain v; *num_cliques = mu(G, Psi) (Definition 4).  deg: length n,
+ * residency out_mem.  num_cliques may be NULL.
+ */
+dsd_status dsd_clique_degrees(dsd_graph g, int h, int out_mem, uint64_t *deg,
+                              uint64_t *num_cliques);
+
+/*
+ * (k, Psi)-core decomposition (Definition 6, Algorithm 3): core[v] = the
+ * clique-core number of v; *kmax = the largest one.  Computed by a
+ * round-synchronous peel that removes every vertex of clique-degree <= k at
+ * once.  core: length n, residency out_mem.  kmax may be NULL.
+ */
+dsd_status dsd_clique_core(dsd_graph g, int h, int out_mem, uint64_t *core, uint64_t *kmax);
+
+/*
+ * CoreApp (Algorithm 6): the (k_max, Psi)-core, which is a 1/h-approximation
+ * of the densest subgraph (Lemma 8).  member[v] = 1 iff core(v) == k_max
+ * (exactly the whole core, not a subset).  density = mu/|V| of that core.
+ * member: length n bytes, residency out_mem.  kmax/density may be NULL.
+ */
+dsd_status dsd_core_app(dsd_graph g, int h, int out_mem, uint8_t *member, uint64_t *kmax,
+                        dsd_rational *density);
+
+/*
+ * CoreExact (Algorithm 4): the clique-densest subgraph (Problem 1).  The GPU
+ * decomposes the graph, locates the densest subgraph with Pruning1 and
+ * Pruning2 and labels the components of the located core; the binary search
+ * over alpha with minimum cuts (Algorithm 1's network, Goldberg's network for
+ * h = 2) runs on the host over those components only.  member[v] = 1 for the
+ * vertices of one densest subgraph; rho_opt its exact density.
+ * member: length n bytes, residency out_mem.  rho_opt may be NULL.
+ */
+dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
+                          dsd_rational *rho_opt);
+
+/* Statistics of the last compute call on g. */
+dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out);
+
+/* Human-readable name of a status; never NULL. */
+const char *dsd_status_str(dsd_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dsd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,90 @@
+"""Brute-force references written straight from the paper's definitions.
+
+Pure Python / numpy, for tiny graphs only.  They share nothing with the oracle
+or the GPU library; tests use them to pin both.
+
+* clique_degrees  -- Definition 3 by testing every h-subset of vertices.
+* core_fixpoint   -- Definition 6: R_k is what remains after repeatedly
+                     deleting vertices whose clique-degree (Definition 3, in
+                     the current subgraph) is below k; core(v) = max k with v in R_k.
+* densest         -- Problem 1 by trying every non-empty vertex subset.
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+
+
+def adjacency_sets(n, edges):
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        u, v = int(u), int(v)
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    return adj
+
+
+def cliques(n, edges, h, vertices=None):
+    adj = adjacency_sets(n, edges)
+    vs = sorted(range(n) if vertices is None else vertices)
+    out = []
+    for S in itertools.combinations(vs, h):
+        if all(b in adj[a] for a, b in itertools.combinations(S, 2)):
+            out.append(S)
+    return out
+
+
+def clique_degrees(n, edges, h, vertices=None):
+    deg = [0] * n
+    cl = cliques(n, edges, h, vertices)
+    for S in cl:
+        for v in S:
+            deg[v] += 1
+    return deg, len(cl)
+
+
+def core_fixpoint(n, edges, h):
+    core = [0] * n
+    k = 0
+    while True:
+        alive = set(range(n))
+        while True:
+            deg, _ = clique_degrees(n, edges, h, alive)
+            drop = {v for v in alive if deg[v] < k}
+            if not drop:
+                break
+            alive -= drop
+        if not alive:
+            break
+        for v in alive:
+            core[v] = k
+        k += 1
+    return core
+
+
+def densest(n, edges, h):
+    """max over non-empty S of mu(S)/|S|, and every maximiser (as bitmasks)."""
+    cl = cliques(n, edges, h)
+    if n == 0:
+        return Fraction(0), []
+    masks = np.array([sum(1 << v for v in S) for S in cl], dtype=np.int64)
+    allS = np.arange(1, 1 << n, dtype=np.int64)
+    mu = np.zeros(allS.size, dtype=np.int64)
+    for c in masks:
+        mu += ((allS & c) == c)
+    size = np.array([bin(int(s)).count("1") for s in allS], dtype=np.int64)
+    ratio = mu / size
+    top = ratio.max()
+    best = max(Fraction(int(mu[i]), int(size[i])) for i in np.nonzero(ratio >= top - 1e-9)[0])
+    arg = [int(allS[i]) for i in range(allS.size) if mu[i] * best.denominator == best.numerator * size[i]]
+    if best == 0:
+        arg = []
+    return best, arg
+
+
+def random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    return [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]

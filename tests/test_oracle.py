@@ -1,0 +1,383 @@
+"""Pins of the CPU oracle against things other than itself (CPU only).
+
+Every oracle function is checked against at least one of: a value the paper
+prints for one of its examples (tests/golden/fixtures.json, each with its
+citation), a closed form, a library routine (dense matrix product), the
+brute-force definitions in tests/brute.py, or an independent exact route.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import synth
+from tests import brute
+
+
+def G(n, edges):
+    e = np.asarray(edges, dtype=np.int32).reshape(-1, 2)
+    return oracle.Graph(n, e[:, 0], e[:, 1])
+
+
+def members(mask):
+    return sorted(np.nonzero(np.asarray(mask))[0].tolist())
+
+
+# ---------------------------------------------------------------- graph model
+
+def test_graph_is_simple_and_symmetric():
+    g = oracle.Graph(5, np.array([0, 1, 1, 2, 3, 3], np.int32), np.array([1, 0, 1, 3, 2, 4], np.int32))
+    off, adj = g.adjacency()
+    assert g.m == 3                       # {0,1}, {2,3}, {3,4}; the loop and the repeat dropped
+    assert off.tolist() == [0, 1, 2, 3, 5, 6]
+    assert adj.tolist() == [1, 0, 3, 2, 4, 3]
+
+
+def test_graph_rejects_bad_ids():
+    with pytest.raises(ValueError):
+        oracle.Graph(3, np.array([0, 3], np.int32), np.array([1, 1], np.int32))
+
+
+# --------------------------------------------------- Definition 3 (clique-degree)
+
+def test_fig1_triangle_degrees(fixtures):
+    f = fixtures["F1"]
+    g = G(f["n"], f["edges"])
+    deg, mu = g.clique_degrees(3)
+    A, B, C = f["labels"]["A"], f["labels"]["B"], f["labels"]["C"]
+    assert [int(deg[A]), int(deg[B]), int(deg[C])] == f["expect"]["h3_deg_ABC"]
+    assert int(deg.sum()) == 3 * mu
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 14])
+@pytest.mark.parametrize("h", [2, 3, 4, 5, 6])
+def test_complete_graph_closed_form(n, h):
+    g = oracle.Graph(*synth.complete_graph(n))
+    deg, mu = g.clique_degrees(h)
+    assert mu == math.comb(n, h)
+    assert deg.tolist() == [math.comb(n - 1, h - 1)] * n
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("h", [2, 3, 4, 5])
+def test_clique_degrees_brute_force(seed, h):
+    n = 16
+    edges = brute.random_graph(n, 0.5, seed)
+    g = G(n, edges)
+    deg, mu = g.clique_degrees(h)
+    bdeg, bmu = brute.clique_degrees(n, edges, h)
+    assert deg.tolist() == bdeg and mu == bmu
+    for v in range(n):
+        assert g.clique_degree_of(h, v) == bdeg[v]
+
+
+def test_edge_degree_is_degree():
+    n, s, d = synth.er_planted(n=300, m=1500, plant=20, p=0.5, seed=3)
+    g = oracle.Graph(n, s, d)
+    off, _ = g.adjacency()
+    deg, mu = g.clique_degrees(2)
+    assert deg.tolist() == np.diff(off).tolist() and mu == g.m
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_triangle_degree_matches_dense_matmul(seed):
+    # t(v) = (A^3)_vv / 2, by a dense integer matrix product
+    n, s, d = synth.er_planted(n=2000, m=10000, plant=60, p=0.4, seed=seed)
+    g = oracle.Graph(n, s, d)
+    off, adj = g.adjacency()
+    A = np.zeros((n, n), dtype=np.int64)
+    rows = np.repeat(np.arange(n), np.diff(off))
+    A[rows, adj] = 1
+    t = np.einsum("ij,ji->i", A @ A, A) // 2
+    deg, mu = g.clique_degrees(3)
+    assert deg.tolist() == t.tolist()
+    assert 3 * mu == int(t.sum())
+
+
+# ------------------------------------------- Definition 6 / Algorithm 3 (cores)
+
+def test_fig3_cores(fixtures):
+    f = fixtures["F2"]
+    g = G(f["n"], f["edges"])
+    c2, k2 = g.core_decomposition(2)
+    c3, k3 = g.core_decomposition(3)
+    assert members(c2 >= 3) == f["expect"]["h2_core3"]
+    assert members(c3 >= 3) == f["expect"]["h3_core3"]
+    assert k2 == 3 and k3 == 3
+    # the k-cores and (k, triangle)-cores differ for k = 1 and 2
+    for k in (1, 2):
+        assert members(c2 >= k) != members(c3 >= k)
+    loc = g.locate(2, np.zeros(f["n"], np.uint64))          # k' from an all-zero core = 0-core
+    assert loc["k1"] >= 0
+
+
+def test_fig1_edge_core(fixtures):
+    f = fixtures["F1"]
+    g = G(f["n"], f["edges"])
+    c, k = g.core_decomposition(2)
+    assert k == 3 and members(c >= 3) == f["expect"]["h2_kcore3"]
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+@pytest.mark.parametrize("h", [2, 3, 4, 6])
+def test_complete_graph_cores(n, h):
+    g = oracle.Graph(*synth.complete_graph(n))
+    core, kmax = g.core_decomposition(h)
+    assert core.tolist() == [math.comb(n - 1, h - 1)] * n and kmax == math.comb(n - 1, h - 1)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_cores_match_fixpoint_definition(seed, h):
+    n = 13
+    edges = brute.random_graph(n, 0.45, 100 + seed)
+    g = G(n, edges)
+    core, kmax = g.core_decomposition(h)
+    ref = brute.core_fixpoint(n, edges, h)
+    assert core.tolist() == ref and kmax == max(ref)
+    deg, _ = g.clique_degrees(h)
+    assert all(int(c) <= int(d) for c, d in zip(core, deg))        # core <= deg (Section 5.1)
+
+
+def _kcore_by_deletion(off, adj, n, k):
+    """Textbook k-core (Definition 5): delete vertices of degree < k until none is left."""
+    alive = np.ones(n, dtype=bool)
+    deg = np.diff(off).astype(np.int64)
+    stack = list(np.nonzero(deg < k)[0])
+    gone = np.zeros(n, dtype=bool)
+    gone[stack] = True
+    while stack:
+        v = stack.pop()
+        alive[v] = False
+        for w in adj[off[v]:off[v + 1]]:
+            if not gone[w]:
+                deg[w] -= 1
+                if deg[w] < k:
+                    gone[w] = True
+                    stack.append(w)
+    return alive
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_cores_match_deletion_on_larger_graph(seed):
+    n, s, d = synth.chung_lu(n=3000, avg_deg=8, beta=2.3, planted=1, plant_size=40, p=0.6, seed=seed)
+    g = oracle.Graph(n, s, d)
+    off, adj = g.adjacency()
+    core, kmax = g.core_decomposition(2)
+    for k in sorted(set(core.tolist()) | {kmax + 1}):
+        assert (_kcore_by_deletion(off, adj, n, k) == (core >= k)).all()
+
+
+# --------------------------------------------------- Theorem 1, Lemmas 5, 7, 8
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_bounds_and_exact_on_random_small(seed, h):
+    n = 12
+    edges = brute.random_graph(n, 0.5, 200 + seed)
+    g = G(n, edges)
+    best, argmax = brute.densest(n, edges, h)
+    core, kmax = g.core_decomposition(h)
+    for route in ("whole", "core"):
+        mem, rho, _ = g.exact(h, route)
+        assert rho == best, (route, rho, best)
+        if best > 0:
+            m = sum(1 << v for v in members(mem))
+            assert m in argmax
+    if best > 0:
+        # Theorem 1 / Lemma 5: kmax/h <= rho_opt <= kmax
+        assert Fraction(kmax, h) <= best <= kmax
+        # Lemma 7: every densest subgraph lies in the ceil(rho_opt)-core
+        kk = math.ceil(best)
+        for m in argmax:
+            assert all(core[v] >= kk for v in range(n) if m >> v & 1)
+        # Theorem 1 lower bound on every R_k
+        lv, rs, rm = g.level_table(h, core)
+        for k, size, mu in zip(lv.tolist(), rs.tolist(), rm.tolist()):
+            if size:
+                assert Fraction(mu, size) >= Fraction(k, h)
+        # Lemma 8: the kmax-core is a 1/h approximation
+        _, km, dens = g.inc_app(h)
+        assert km == kmax and h * dens >= best
+
+
+# ------------------------------------------------------- Section 6.1 pruning
+
+def test_fig6_locate(fixtures):
+    f = fixtures["F4"]
+    g = G(f["n"], f["edges"])
+    core, kmax = g.core_decomposition(2)
+    e = f["expect"]
+    assert kmax == e["kmax"] and members(core == kmax) == e["kmax_core"]
+    loc = g.locate(2, core)
+    assert loc["rho1"] == Fraction(*e["rho1"]) and loc["k1"] == e["k1"]
+    comps = {}
+    for v, l in enumerate(loc["label"].tolist()):
+        if l >= 0:
+            comps.setdefault(l, []).append(v)
+    assert sorted(comps.values()) == sorted(e["components_k1"])
+    assert loc["rho2"] == Fraction(15, 7) and loc["k2"] == 3
+    for route in ("whole", "core"):
+        mem, rho, _ = g.exact(2, route)
+        assert rho == Fraction(*e["rho_opt"]) and members(mem) == e["eds"]
+    mem, km, dens = g.inc_app(2)
+    assert members(mem) == e["kmax_core"] and dens == 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("h", [2, 3])
+def test_level_table_against_brute_force(seed, h):
+    n = 14
+    edges = brute.random_graph(n, 0.45, 300 + seed)
+    g = G(n, edges)
+    core = brute.core_fixpoint(n, edges, h)
+    lv, rs, rm = g.level_table(h, np.array(core, np.uint64))
+    levels = sorted(set(core) | {0})
+    assert lv.tolist() == levels
+    for k, size, mu in zip(lv.tolist(), rs.tolist(), rm.tolist()):
+        R = [v for v in range(n) if core[v] >= k]
+        assert size == len(R)
+        assert mu == len(brute.cliques(n, edges, h, R))
+    loc = g.locate(h, np.array(core, np.uint64))
+    rho1 = max((Fraction(int(m), int(s)) for m, s in zip(rm, rs) if s), default=Fraction(0))
+    assert loc["rho1"] == rho1 and loc["k1"] == math.ceil(rho1)
+
+
+# ------------------------------------------------------ Section 2 exact / K_n
+
+def test_fig1_densest(fixtures):
+    f = fixtures["F1"]
+    g = G(f["n"], f["edges"])
+    for route in ("whole", "core"):
+        mem, rho, _ = g.exact(2, route)
+        assert rho == Fraction(*f["expect"]["h2_rho_opt"]) and members(mem) == f["expect"]["h2_cds"]
+        mem, rho, _ = g.exact(3, route)
+        assert members(mem) == f["expect"]["h3_cds"] and rho == Fraction(1, 2)
+
+
+def test_example4_bounds(fixtures):
+    f = fixtures["F3"]["cycle4"]
+    g = G(f["n"], f["edges"])
+    mem, kmax, dens = g.inc_app(2)
+    assert kmax == 2 and dens == Fraction(*f["expect"]["density"])
+    for x in (1, 2, 3, 6):
+        edges = [(0, 1)] + [(0, 2 + i) for i in range(2 * x)] + [(1, 2 + i) for i in range(2 * x)]
+        g = G(2 + 2 * x, edges)
+        mem, kmax, dens = g.inc_app(2)
+        assert kmax == 2 and dens == Fraction(1 + 4 * x, 2 + 2 * x)
+        _, rho, _ = g.exact(2, "core")
+        assert rho == Fraction(1 + 4 * x, 2 + 2 * x)
+
+
+@pytest.mark.parametrize("h", [2, 3, 4, 5, 6])
+def test_table_density_k13(fixtures, h):
+    t = fixtures["KN_DENSITY"]["K13"]
+    want = Fraction(*t["density"][t["h"].index(h)])
+    n, s, d = synth.complete_graph(13)
+    # K13 plus a sparse tail: the densest subgraph is still K13
+    s = np.concatenate([s, np.arange(13, 30, dtype=np.int32)])
+    d = np.concatenate([d, np.arange(12, 29, dtype=np.int32)])
+    g = oracle.Graph(30, s, d)
+    mem, rho, _ = g.exact(h, "core")
+    assert rho == want and members(mem) == list(range(13))
+
+
+@pytest.mark.parametrize("h,printed", [(2, 9.50), (4, 242.3), (5, 775.2), (6, 1938.0)])
+def test_table_density_k20(fixtures, h, printed):
+    g = oracle.Graph(*synth.complete_graph(20))
+    _, rho, _ = g.exact(h, "core")
+    assert rho == Fraction(math.comb(20, h), 20)
+    assert abs(float(rho) - printed) < 0.06
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_two_exact_routes_agree(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(8, 60))
+    h = int(rng.integers(2, 6))
+    edges = brute.random_graph(n, float(rng.uniform(0.08, 0.5)), 400 + seed)
+    g = G(n, edges)
+    m1, r1, _ = g.exact(h, "whole")
+    m2, r2, _ = g.exact(h, "core")
+    assert r1 == r2
+    for m in (m1, m2):
+        if r1 > 0:
+            _, mu = brute.clique_degrees(n, edges, h, members(m)) if n <= 30 else (None, None)
+            if mu is not None:
+                assert Fraction(mu, len(members(m))) == r1
+
+
+def test_exact_routes_agree_on_er_config():
+    n, s, d = synth.er_planted(seed=1)
+    g = oracle.Graph(n, s, d)
+    for h in (2, 3):
+        m1, r1, c1 = g.exact(h, "whole")
+        m2, r2, c2 = g.exact(h, "core")
+        assert r1 == r2 and r1 > 0
+        core, kmax = g.core_decomposition(h)
+        assert all(core[members(m2)] >= math.ceil(r2))               # Lemma 7
+        assert Fraction(kmax, h) <= r2 <= kmax                        # Theorem 1 / Lemma 5
+
+
+def test_strict_test_is_strict():
+    # Lemma 14: at alpha equal to rho_opt no subgraph is strictly denser
+    g = oracle.Graph(*synth.complete_graph(6))
+    found, _ = g.denser_than(2, Fraction(5, 2))
+    assert not found
+    found, mem = g.denser_than(2, Fraction(5, 2) - Fraction(1, 100))
+    assert found and members(mem) == list(range(6))
+
+
+def test_empty_and_tiny():
+    for n in (0, 1, 2):
+        g = oracle.Graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+        for h in (2, 3):
+            mem, rho, _ = g.exact(h, "core")
+            assert rho == 0 and not mem.any()
+            mem, kmax, dens, _ = g.core_app(h)
+            assert kmax == 0 and dens == 0
+
+
+# ---------------------------------------------------------- Algorithm 6 CoreApp
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_core_app_equals_kmax_core(seed, h):
+    n, s, d = synth.chung_lu(n=600, avg_deg=10, beta=2.2, planted=2, plant_size=18, p=0.7, seed=seed)
+    g = oracle.Graph(n, s, d)
+    m1, k1, d1 = g.inc_app(h)
+    for w0 in (0, 1, 5, 64):
+        m2, k2, d2, it = g.core_app(h, literal=False, w0=w0)
+        assert k2 == k1 and d2 == d1 and (m1 == m2).all()
+
+
+def _k7_path():
+    e = list(itertools.combinations(range(7), 2)) + [(6, 7), (7, 8), (8, 9), (9, 10)]
+    return 11, e
+
+
+@pytest.mark.parametrize("h,truth,literal", [(2, 6, 3), (3, 15, 3), (4, 20, 1)])
+def test_core_app_literal_reading_diverges(h, truth, literal):
+    # The loop as printed tests its stop rule on a doubled, never-processed W;
+    # the corrected reading processes W first.
+    n, e = _k7_path()
+    g = G(n, e)
+    _, kc, _, _ = g.core_app(h, literal=False, w0=4)
+    _, kl, _, _ = g.core_app(h, literal=True, w0=4)
+    assert kc == truth and kl == literal
+
+
+def test_core_app_literal_keeps_stale_core():
+    # two disjoint K5: the printed update rule never refreshes S* with the
+    # second copy of the same core
+    e = list(itertools.combinations(range(5), 2)) + list(itertools.combinations(range(5, 10), 2))
+    g = G(10, e)
+    mc, kc, _, _ = g.core_app(2, literal=False, w0=5)
+    ml, kl, _, _ = g.core_app(2, literal=True, w0=5)
+    assert kc == kl == 4
+    assert members(mc) == list(range(10)) and members(ml) != list(range(10))
