@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It wraps the
 plain single-threaded C library in ``oracle.c`` (built with gcc by
-``oracle/build.py``) and shares no code with the GPU library.
+``oracle/buildlib.py``) and shares no code with the GPU library.
 
 All counts are exact integers and all densities are ``fractions.Fraction``.
 """
@@ -21,7 +21,7 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    from . import build as _b
+    from . import buildlib as _b
     return _b.build(force=force)
 
 

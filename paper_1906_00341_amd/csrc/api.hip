@@ -1,0 +1,458 @@
+// C ABI of libdsd (declared in include/dsd.h) and the drivers that chain the
+// kernels: clique-degrees, (k, Psi)-core decomposition, CoreApp (Algorithm 6)
+// and CoreExact (Algorithm 4, exact step on the host).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dsd.h"
+#include "exact.hpp"
+#include "graph.hpp"
+
+using namespace dsd;
+
+struct dsd_graph_s {
+    DevGraph g;
+    hipStream_t stream = nullptr;
+    Scratch sc;
+    dsd_stats stats{};
+    ~dsd_graph_s() { free_graph(g); }
+};
+
+static thread_local std::string g_err;
+
+static dsd_status fail(int st, const std::string &msg) {
+    g_err = msg;
+    return (dsd_status)st;
+}
+
+#define DSD_TRY(...)                                                      \
+    try {                                                                 \
+        __VA_ARGS__                                                       \
+    } catch (const dsd::Error &e) {                                       \
+        return fail(e.status, e.what());                                  \
+    } catch (const std::bad_alloc &) {                                    \
+        return fail(DSD_ENOMEM, "host allocation failed");                \
+    } catch (const std::exception &e) {                                   \
+        return fail(DSD_EDEVICE, e.what());                               \
+    }
+
+namespace {
+
+struct Timer {
+    hipStream_t s;
+    hipEvent_t a, b;
+    explicit Timer(hipStream_t st) : s(st) {
+        DSD_HIP(hipEventCreate(&a));
+        DSD_HIP(hipEventCreate(&b));
+        DSD_HIP(hipEventRecord(a, s));
+    }
+    double stop() {
+        DSD_HIP(hipEventRecord(b, s));
+        DSD_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        DSD_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+void check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) throw Error(DSD_EDEVICE, "no HIP device available");
+}
+
+void check_h(int h) {
+    if (h < 2 || h > 6) throw Error(DSD_EINVAL, "h must be in [2, 6]");
+}
+
+void check_out(const void *p, int mem) {
+    if (!p) throw Error(DSD_EINVAL, "NULL output pointer");
+    if (mem != DSD_MEM_HOST && mem != DSD_MEM_DEVICE) throw Error(DSD_EINVAL, "bad memory flag");
+}
+
+u64 gcd64(u64 a, u64 b) {
+    while (b) {
+        u64 t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+dsd_rational make_rational(u64 num, u64 den) {
+    if (num == 0 || den == 0) return {0, 1};
+    u64 g = gcd64(num, den);
+    return {num / g, den / g};
+}
+
+bool rat_gt(u64 a, u64 b, u64 c, u64 d) { return (unsigned __int128)a * d > (unsigned __int128)c * b; }
+
+u64 ceil_div_u(u64 a, u64 b) { return a / b + (a % b != 0); }
+
+// clique-degrees (rank space) and mu; throws on overflow
+u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg) {
+    hipStream_t s = G->stream;
+    if (!clique_degrees(G->g, h, mask, deg, s, G->sc))
+        throw Error(DSD_EOVERFLOW, "clique counts could exceed 64 bits");
+    u64 *sum = G->sc.get_n<u64>(2);
+    sum_u64_128(deg, G->g.n, sum, s, G->sc);
+    u64 hs[2];
+    DSD_HIP(hipMemcpyAsync(hs, sum, sizeof(hs), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (hs[1] != 0) throw Error(DSD_EOVERFLOW, "sum of clique-degrees exceeds 64 bits");
+    if (hs[0] % (u64)h != 0) throw Error(DSD_EDEVICE, "clique-degree sum not divisible by h");
+    return hs[0] / (u64)h;
+}
+
+template <typename T>
+void write_out(dsd_graph_s *G, const T *rank_space, T *out, int mem,
+               void (*gather)(const DevGraph &, const T *, T *, hipStream_t)) {
+    hipStream_t s = G->stream;
+    const int32_t n = G->g.n;
+    if (n == 0) return;
+    if (mem == DSD_MEM_DEVICE) {
+        gather(G->g, rank_space, out, s);
+        DSD_HIP(hipStreamSynchronize(s));
+    } else {
+        T *tmp = G->sc.get_n<T>(n);
+        gather(G->g, rank_space, tmp, s);
+        DSD_HIP(hipMemcpyAsync(out, tmp, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+    }
+}
+
+void write_u64(dsd_graph_s *G, const u64 *r, uint64_t *out, int mem) {
+    write_out<u64>(G, r, (u64 *)out, mem, gather_to_orig_u64);
+}
+void write_u8(dsd_graph_s *G, const uint8_t *r, uint8_t *out, int mem) {
+    write_out<uint8_t>(G, r, out, mem, gather_to_orig_u8);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dsd_status_str(dsd_status s) {
+    switch (s) {
+        case DSD_OK: return "DSD_OK";
+        case DSD_EINVAL: return "DSD_EINVAL";
+        case DSD_ENOMEM: return "DSD_ENOMEM";
+        case DSD_EDEVICE: return "DSD_EDEVICE";
+        case DSD_EOVERFLOW: return "DSD_EOVERFLOW";
+        case DSD_EUNSUPPORTED: return "DSD_EUNSUPPORTED";
+    }
+    return "DSD_UNKNOWN";
+}
+
+const char *dsd_last_error(void) { return g_err.c_str(); }
+
+dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const int32_t *dst, int in_mem,
+                         void *stream, dsd_graph *out) {
+    if (!out) return fail(DSD_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (n < 0 || num_pairs < 0) return fail(DSD_EINVAL, "negative n or pair count");
+    if (num_pairs > 0 && (!src || !dst)) return fail(DSD_EINVAL, "NULL pair arrays");
+    if (in_mem != DSD_MEM_HOST && in_mem != DSD_MEM_DEVICE) return fail(DSD_EINVAL, "bad memory flag");
+    std::unique_ptr<dsd_graph_s> holder;
+    DSD_TRY({
+        check_device();
+        holder.reset(new dsd_graph_s());
+        dsd_graph_s *G = holder.get();
+        G->stream = (hipStream_t)stream;
+        hipStream_t s = G->stream;
+        const int32_t *ds = src, *dd = dst;
+        if (in_mem == DSD_MEM_HOST && num_pairs > 0) {
+            int32_t *a = G->sc.get_n<int32_t>(num_pairs), *b = G->sc.get_n<int32_t>(num_pairs);
+            DSD_HIP(hipMemcpyAsync(a, src, (size_t)num_pairs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DSD_HIP(hipMemcpyAsync(b, dst, (size_t)num_pairs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            ds = a;
+            dd = b;
+        }
+        float t = 0;
+        Timer tm(s);
+        build_graph(n, num_pairs, ds, dd, G->g, s, G->sc, &t);
+        G->stats = dsd_stats{};
+        G->stats.t_total_ms = tm.stop();
+        G->stats.t_orient_ms = t;
+        G->sc.reset();
+        *out = holder.release();
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_graph_info(dsd_graph g, int32_t *n, int64_t *m) {
+    if (!g) return fail(DSD_EINVAL, "NULL graph");
+    if (n) *n = g->g.n;
+    if (m) *m = g->g.m;
+    return DSD_OK;
+}
+
+dsd_status dsd_graph_free(dsd_graph g) {
+    if (!g) return DSD_OK;
+    DSD_TRY({
+        (void)hipStreamSynchronize(g->stream);
+        delete g;
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out) {
+    if (!g || !out) return fail(DSD_EINVAL, "NULL argument");
+    *out = g->stats;
+    return DSD_OK;
+}
+
+dsd_status dsd_clique_degrees(dsd_graph G, int h, int out_mem, uint64_t *deg, uint64_t *num_cliques) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    DSD_TRY({
+        check_h(h);
+        if (G->g.n > 0) check_out(deg, out_mem);
+        G->sc.reset();
+        G->stats = dsd_stats{};
+        Timer tm(G->stream);
+        u64 *d = G->sc.get_n<u64>(G->g.n);
+        u64 mu = degrees_and_mu(G, h, nullptr, d);
+        G->stats.t_enum_ms = tm.stop();
+        write_u64(G, d, deg, out_mem);
+        if (num_cliques) *num_cliques = mu;
+        G->stats.num_cliques = mu;
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_clique_core(dsd_graph G, int h, int out_mem, uint64_t *core, uint64_t *kmax) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    DSD_TRY({
+        check_h(h);
+        if (G->g.n > 0) check_out(core, out_mem);
+        G->sc.reset();
+        G->stats = dsd_stats{};
+        hipStream_t s = G->stream;
+        Timer tm(s);
+        const int32_t n = G->g.n;
+        u64 *d = G->sc.get_n<u64>(n), *c = G->sc.get_n<u64>(n);
+        u64 mu = degrees_and_mu(G, h, nullptr, d);
+        G->stats.t_enum_ms = tm.stop();
+        Timer tp(s);
+        PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, c, s, G->sc);
+        G->stats.t_peel_ms = tp.stop();
+        write_u64(G, c, core, out_mem);
+        if (kmax) *kmax = pr.kmax;
+        G->stats.num_cliques = mu;
+        G->stats.peel_rounds = pr.rounds;
+        G->stats.peel_levels = pr.levels;
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+// C(x, r) saturating at 2^64 - 1
+static u64 binom_sat(u64 x, int r) {
+    if ((u64)r > x) return 0;
+    unsigned __int128 acc = 1;
+    for (int i = 1; i <= r; i++) {
+        acc = acc * (unsigned __int128)(x - (u64)r + (u64)i) / (unsigned __int128)i;
+        if (acc > (unsigned __int128)~0ull) return ~0ull;
+    }
+    return (u64)acc;
+}
+
+__global__ void k_gamma_keys(const u64 *x, int32_t n, int bits, u64 xsat, u64 keymax, int r, u64 *keys) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        u64 xv = x[v];
+        u64 g = xv < (u64)r ? 0 : (xv < xsat ? xv : xsat);   // gamma = C(g, r) is increasing in g
+        keys[v] = ((keymax - g) << bits) | (u64)v;
+    }
+}
+
+__global__ void k_count_top(const u64 *keys, int32_t n, int bits, int32_t *cnt) {
+    const u64 top = keys[0] >> bits;
+    int32_t c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += (keys[i] >> bits) == top ? 1 : 0;
+    c = wave_sum(c);
+    if (lane() == 0 && c) atomicAdd(cnt, c);
+}
+
+dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64_t *kmax_out,
+                        dsd_rational *density) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    DSD_TRY({
+        check_h(h);
+        const int32_t n = G->g.n;
+        if (n > 0) check_out(member, out_mem);
+        G->sc.reset();
+        G->stats = dsd_stats{};
+        hipStream_t s = G->stream;
+        Timer tm(s);
+        u64 kmax = 0, best_mu = 0, best_size = 0;
+        uint8_t *best = G->sc.get_n<uint8_t>(n);
+        fill_u8(best, 0, n, s);
+        if (n > 0) {
+            // gamma(v) = C(x_v, h-1) from the classic core numbers x_v (Section 6.2)
+            u64 *d = G->sc.get_n<u64>(n), *x = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
+            u64 m = degrees_and_mu(G, 2, nullptr, d);
+            Timer tp(s);
+            PeelResult xr = peel(G->g, 2, nullptr, d, m, 0, x, s, G->sc);
+            G->stats.t_peel_ms += tp.stop();
+            u64 xsat = 0;
+            while (xsat <= (u64)n && binom_sat(xsat, h - 1) != ~0ull) xsat++;
+            const u64 keymax = std::min<u64>(xsat, (u64)n);
+            u64 *keys = G->sc.get_n<u64>(n), *tmp = G->sc.get_n<u64>(n);
+            k_gamma_keys<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(x, n, G->g.bits, keymax, keymax, h - 1, keys);
+            int kb = G->g.bits + 1;
+            while ((keymax >> (kb - G->g.bits)) != 0) kb++;
+            radix_sort_u64(keys, tmp, n, kb, s, G->sc);
+            int32_t *cnt = G->sc.get_n<int32_t>(1);
+            fill_i32(cnt, 0, 1, s);
+            k_count_top<<<grid_for(n, BLOCK, 2048), BLOCK, 0, s>>>(keys, n, G->g.bits, cnt);
+            int32_t ntop = 0;
+            DSD_HIP(hipMemcpyAsync(&ntop, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DSD_HIP(hipStreamSynchronize(s));
+            auto gamma_at = [&](int64_t i) -> u64 {
+                u64 k = 0;
+                DSD_HIP(hipMemcpyAsync(&k, keys + i, sizeof(u64), hipMemcpyDeviceToHost, s));
+                DSD_HIP(hipStreamSynchronize(s));
+                return binom_sat(keymax - (k >> G->g.bits), h - 1);
+            };
+            int64_t w = std::min<int64_t>(n, std::max<int64_t>(64, ntop));
+            uint8_t *inW = G->sc.get_n<uint8_t>(n);
+            u64 *mn = G->sc.get_n<u64>(1);
+            while (true) {
+                mask_from_order_prefix(keys, n, w, G->g.bits, inW, s);
+                Timer te(s);
+                u64 muW = degrees_and_mu(G, h, inW, d);
+                G->stats.t_enum_ms += te.stop();
+                masked_min_u64(d, inW, n, mn, s);
+                u64 kl = 0;
+                DSD_HIP(hipMemcpyAsync(&kl, mn, sizeof(u64), hipMemcpyDeviceToHost, s));
+                DSD_HIP(hipStreamSynchronize(s));
+                const u64 k0 = std::max(kl, kmax);
+                const u64 floor_k = k0 > 0 ? k0 - 1 : 0;
+                Timer tq(s);
+                PeelResult pr = peel(G->g, h, inW, d, muW, floor_k, core, s, G->sc);
+                G->stats.t_peel_ms += tq.stop();
+                G->stats.peel_rounds += pr.rounds;
+                G->stats.peel_levels += pr.levels;
+                if (pr.levels > 0 && pr.kmax > 0 && pr.kmax >= k0) {
+                    kmax = pr.kmax;
+                    best_mu = pr.level_mu.back();
+                    best_size = pr.level_size.back();
+                    mask_core_equal(core, n, kmax, best, s);
+                }
+                // stop once every vertex outside W has gamma < kmax (its clique-core number is smaller)
+                if (w >= n || gamma_at(w) < kmax) break;
+                w = std::min<int64_t>(n, 2 * w);
+            }
+        }
+        write_u8(G, best, member, out_mem);
+        if (kmax_out) *kmax_out = kmax;
+        if (density) *density = kmax > 0 ? make_rational(best_mu, best_size) : dsd_rational{0, 1};
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_rational *rho_opt) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    DSD_TRY({
+        check_h(h);
+        const int32_t n = G->g.n;
+        if (n > 0) check_out(member, out_mem);
+        G->sc.reset();
+        G->stats = dsd_stats{};
+        hipStream_t s = G->stream;
+        Timer tm(s);
+        uint8_t *res = G->sc.get_n<uint8_t>(n);
+        fill_u8(res, 0, n, s);
+        dsd_rational rho{0, 1};
+        u64 *d = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
+        u64 mu = n > 0 ? degrees_and_mu(G, h, nullptr, d) : 0;
+        G->stats.t_enum_ms = tm.stop();
+        G->stats.num_cliques = mu;
+        if (mu > 0) {
+            Timer tp(s);
+            PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, core, s, G->sc);
+            G->stats.t_peel_ms = tp.stop();
+            G->stats.peel_rounds = pr.rounds;
+            G->stats.peel_levels = pr.levels;
+            Timer tl(s);
+            // Pruning1: rho' = max over levels of mu(R_k) / |R_k|
+            u64 a = 0, b = 1;
+            for (int64_t i = 0; i < pr.levels; i++)
+                if (pr.level_size[i] > 0 && rat_gt(pr.level_mu[i], pr.level_size[i], a, b)) {
+                    a = pr.level_mu[i];
+                    b = pr.level_size[i];
+                }
+            const u64 k1 = ceil_div_u(a, b);
+            // Pruning2: components of R_{k'} and their densities
+            uint8_t *m1 = G->sc.get_n<uint8_t>(n);
+            int32_t *lab1 = G->sc.get_n<int32_t>(n);
+            u64 *d1 = G->sc.get_n<u64>(n), *sz = G->sc.get_n<u64>(n), *ds = G->sc.get_n<u64>(n);
+            mask_core_at_least(core, n, k1, m1, s);
+            components(G->g, m1, lab1, s, G->sc);
+            degrees_and_mu(G, h, m1, d1);
+            component_sums(lab1, d1, n, sz, ds, s);
+            std::vector<CompInfo> c1;
+            collect_components(lab1, sz, ds, n, c1, s, G->sc);
+            u64 rn = 0, rd = 1;
+            int32_t best_root = -1;
+            for (const CompInfo &c : c1)
+                if (c.size > 0 && c.dsum > 0 && (best_root < 0 || rat_gt(c.dsum, c.size * (u64)h, rn, rd))) {
+                    rn = c.dsum;
+                    rd = c.size * (u64)h;
+                    best_root = c.root;
+                }
+            dsd_rational r2 = make_rational(rn, rd);
+            const u64 k2 = std::max(k1, ceil_div_u(r2.num, r2.den));
+            // D starts as the component attaining rho''
+            if (best_root >= 0) mask_label_equal(lab1, n, best_root, res, s);
+            rho = r2;
+            // components of R_{k''} go to the host
+            uint8_t *m2 = m1;
+            int32_t *lab2 = lab1;
+            if (k2 > k1) {
+                m2 = G->sc.get_n<uint8_t>(n);
+                lab2 = G->sc.get_n<int32_t>(n);
+                mask_core_at_least(core, n, k2, m2, s);
+                components(G->g, m2, lab2, s, G->sc);
+            }
+            LocatedCore lc;
+            extract_induced(G->g, m2, lab2, core, lc, s, G->sc);
+            G->stats.located_vertices = lc.rank.size();
+            G->stats.t_locate_ms = tl.stop();
+            auto t0 = std::chrono::steady_clock::now();
+            Rational l{rho.num, rho.den};
+            std::vector<int32_t> bestset;
+            ExactStats es;
+            bool improved = exact_search(lc, h, k2, l, bestset, es);
+            G->stats.t_exact_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            G->stats.flow_calls = es.flow_calls;
+            G->stats.flow_nodes_max = es.max_nodes;
+            if (improved) {
+                rho = dsd_rational{l.num, l.den};
+                std::vector<uint8_t> hm(n, 0);
+                for (int32_t v : bestset) hm[lc.rank[v]] = 1;
+                DSD_HIP(hipMemcpyAsync(res, hm.data(), n, hipMemcpyHostToDevice, s));
+                DSD_HIP(hipStreamSynchronize(s));
+            }
+        }
+        write_u8(G, res, member, out_mem);
+        if (rho_opt) *rho_opt = rho;
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+}  // extern "C"

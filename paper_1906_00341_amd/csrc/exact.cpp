@@ -1,0 +1,476 @@
+// Host exact step of CoreExact (Algorithm 4): minimum cuts over the located
+// core, component by component.
+//
+// Networks (capacities scaled by the denominator b of alpha = a/b so that
+// every capacity is an integer):
+//   h = 2 (Goldberg's network, Section 4.1): s->v: b*m, v->t: b*m + 2a -
+//         b*deg(v), u<->v: b for every edge.
+//   h >= 3 (Algorithm 1): s->v: b*deg(v, Psi), v->t: h*a, psi->v: infinite
+//         for v in psi, v->psi: b when psi + v is an h-clique; psi ranges over
+//         the (h-1)-cliques that extend to an h-clique (the others carry no
+//         flow).
+// A subgraph denser than alpha exists iff the maximum flow is below the
+// total source capacity (Lemma 14); the source side of the maximal minimum
+// cut then maximises mu(S) - alpha |S| and so has density > alpha.
+//
+// Search: each component C (in descending density) is first tested at the
+// best density l found so far; if nothing in C beats l it is skipped.
+// Otherwise the density l is raised to that of the set just found and the
+// test repeated until it fails (a parametric / Dinkelbach iteration on the
+// same networks as Algorithm 4's binary search; densities strictly increase,
+// so it ends, and the last set found is densest in C).  Before every test C
+// is cut down to the ceil(l)-clique-core (Lemma 7), as Algorithm 4 does when
+// its lower bound rises.
+#include "exact.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <numeric>
+
+#include "common.hpp"
+
+namespace dsd {
+
+typedef __int128 i128;
+static const int64_t CAP_LIMIT = (int64_t)1 << 62;
+
+// ---------------------------------------------------------------- push-relabel
+
+class PushRelabel {
+public:
+    explicit PushRelabel(int n) : n_(n) {}
+    int arc(int u, int v) {   // capacities are set per test
+        eu_.push_back(u);
+        ev_.push_back(v);
+        return (int)eu_.size() - 1;
+    }
+    void build() {
+        first_.assign(n_ + 1, 0);
+        for (size_t i = 0; i < eu_.size(); i++) {
+            first_[eu_[i] + 1]++;
+            first_[ev_[i] + 1]++;
+        }
+        for (int i = 0; i < n_; i++) first_[i + 1] += first_[i];
+        std::vector<int> fill(first_.begin(), first_.end() - 1);
+        const size_t A = 2 * eu_.size();
+        to_.assign(A, 0);
+        rev_.assign(A, 0);
+        fwd_.assign(eu_.size(), 0);
+        for (size_t i = 0; i < eu_.size(); i++) {
+            int pu = fill[eu_[i]]++, pv = fill[ev_[i]]++;
+            to_[pu] = ev_[i];
+            to_[pv] = eu_[i];
+            rev_[pu] = pv;
+            rev_[pv] = pu;
+            fwd_[i] = pu;
+        }
+        cap_.assign(A, 0);
+    }
+    // capacity of arc i (forward) and of its reverse
+    void set(int i, int64_t c, int64_t rc = 0) {
+        cap_[fwd_[i]] = c;
+        cap_[rev_[fwd_[i]]] = rc;
+    }
+    int nodes() const { return n_; }
+
+    int64_t maxflow(int s, int t) {
+        ex_.assign(n_, 0);
+        ht_.assign(n_, 0);
+        cnt_.assign(2 * n_ + 2, 0);
+        cur_.assign(first_.begin(), first_.end() - 1);
+        s_ = s;
+        t_ = t;
+        for (int a = first_[s]; a < first_[s + 1]; a++) {
+            int64_t f = cap_[a];
+            if (f <= 0) continue;
+            cap_[a] = 0;
+            cap_[rev_[a]] += f;
+            ex_[to_[a]] += f;
+            ex_[s] -= f;
+        }
+        global_relabel();
+        int64_t work = 0;
+        while (!q_.empty()) {
+            int u = q_.front();
+            q_.pop_front();
+            inq_[u] = 0;
+            if (ht_[u] >= n_ || ex_[u] <= 0) continue;
+            discharge(u, work);
+            if (work > 6 * (int64_t)n_ + (int64_t)to_.size() / 2) {
+                work = 0;
+                global_relabel();
+            }
+        }
+        return ex_[t];
+    }
+
+    // nodes that still reach t in the residual network
+    void reach_sink(int t, std::vector<char> &seen) const {
+        seen.assign(n_, 0);
+        std::vector<int> st{t};
+        seen[t] = 1;
+        while (!st.empty()) {
+            int v = st.back();
+            st.pop_back();
+            for (int a = first_[v]; a < first_[v + 1]; a++) {
+                int u = to_[a];
+                if (!seen[u] && cap_[rev_[a]] > 0) {
+                    seen[u] = 1;
+                    st.push_back(u);
+                }
+            }
+        }
+    }
+
+private:
+    void global_relabel() {
+        std::fill(ht_.begin(), ht_.end(), n_);
+        std::fill(cnt_.begin(), cnt_.end(), 0);
+        std::vector<int> bfs{t_};
+        ht_[t_] = 0;
+        for (size_t i = 0; i < bfs.size(); i++) {
+            int v = bfs[i];
+            for (int a = first_[v]; a < first_[v + 1]; a++) {
+                int u = to_[a];
+                if (ht_[u] == n_ && u != s_ && cap_[rev_[a]] > 0) {
+                    ht_[u] = ht_[v] + 1;
+                    bfs.push_back(u);
+                }
+            }
+        }
+        ht_[s_] = n_;
+        q_.clear();
+        inq_.assign(n_, 0);
+        for (int v = 0; v < n_; v++) {
+            if (ht_[v] < n_) cnt_[ht_[v]]++;
+            cur_[v] = first_[v];
+            if (v != s_ && v != t_ && ex_[v] > 0 && ht_[v] < n_) {
+                q_.push_back(v);
+                inq_[v] = 1;
+            }
+        }
+    }
+
+    void discharge(int u, int64_t &work) {
+        while (ex_[u] > 0) {
+            if (cur_[u] == first_[u + 1]) {
+                relabel(u);
+                work += first_[u + 1] - first_[u] + 12;
+                if (ht_[u] >= n_) return;
+                cur_[u] = first_[u];
+                continue;
+            }
+            int a = cur_[u], v = to_[a];
+            if (cap_[a] > 0 && ht_[u] == ht_[v] + 1) {
+                int64_t d = ex_[u] < cap_[a] ? ex_[u] : cap_[a];
+                cap_[a] -= d;
+                cap_[rev_[a]] += d;
+                ex_[u] -= d;
+                ex_[v] += d;
+                if (v != s_ && v != t_ && !inq_[v]) {
+                    q_.push_back(v);
+                    inq_[v] = 1;
+                }
+            } else {
+                cur_[u]++;
+            }
+        }
+    }
+
+    void relabel(int u) {
+        int old = ht_[u], nh = 2 * n_;
+        for (int a = first_[u]; a < first_[u + 1]; a++)
+            if (cap_[a] > 0 && ht_[to_[a]] + 1 < nh) nh = ht_[to_[a]] + 1;
+        if (old < n_ && --cnt_[old] == 0) {
+            // gap: nothing at height `old` any more, so nothing above it reaches t
+            for (int w = 0; w < n_; w++)
+                if (ht_[w] > old && ht_[w] < n_) {
+                    cnt_[ht_[w]]--;
+                    ht_[w] = n_;
+                }
+            ht_[u] = n_;
+            return;
+        }
+        ht_[u] = nh < n_ ? nh : n_;
+        if (ht_[u] < n_) cnt_[ht_[u]]++;
+    }
+
+    int n_, s_ = 0, t_ = 1;
+    std::vector<int> eu_, ev_, fwd_;
+    std::vector<int> first_, to_, rev_, ht_, cnt_, cur_;
+    std::vector<char> inq_;
+    std::vector<int64_t> cap_, ex_;
+    std::deque<int> q_;
+};
+
+// ---------------------------------------------------------------- host clique listing
+
+// Lists the cliques of size `size` inside `in` (membership over local ids) in
+// increasing id order; calls f(const int32_t *members).
+template <class F>
+static void list_cliques(const LocatedCore &lc, const std::vector<char> &in, int size, F &&f) {
+    const int32_t s = (int32_t)lc.rank.size();
+    std::vector<std::vector<int32_t>> cand(size + 1);
+    std::vector<int32_t> mem(size);
+    struct Rec {
+        const LocatedCore &lc;
+        int size;
+        std::vector<std::vector<int32_t>> &cand;
+        std::vector<int32_t> &mem;
+        F &f;
+        void go(int depth) {
+            const std::vector<int32_t> &c = cand[depth];
+            for (size_t i = 0; i < c.size(); i++) {
+                int32_t x = c[i];
+                mem[depth] = x;
+                if (depth + 1 == size) {
+                    f(mem.data());
+                    continue;
+                }
+                std::vector<int32_t> &nx = cand[depth + 1];
+                nx.clear();
+                const int32_t *a = lc.adj.data() + lc.off[x], *ae = lc.adj.data() + lc.off[x + 1];
+                size_t j = i + 1;
+                while (j < c.size() && a < ae) {
+                    if (c[j] < *a) j++;
+                    else if (c[j] > *a) a++;
+                    else { nx.push_back(c[j]); j++; a++; }
+                }
+                if (!nx.empty()) go(depth + 1);
+            }
+        }
+    } rec{lc, size, cand, mem, f};
+    for (int32_t v = 0; v < s; v++) {
+        if (!in[v]) continue;
+        mem[0] = v;
+        if (size == 1) { f(mem.data()); continue; }
+        cand[1].clear();
+        for (int64_t e = lc.off[v]; e < lc.off[v + 1]; e++) {
+            int32_t w = lc.adj[e];
+            if (w > v && in[w]) cand[1].push_back(w);
+        }
+        if (!cand[1].empty()) {
+            // reuse go() from depth 1 with the first member fixed
+            rec.go(1);
+        }
+    }
+}
+
+uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int32_t> &verts) {
+    std::vector<char> in(lc.rank.size(), 0);
+    for (int32_t v : verts) in[v] = 1;
+    uint64_t c = 0;
+    list_cliques(lc, in, h, [&](const int32_t *) { c++; });
+    return c;
+}
+
+// ---------------------------------------------------------------- one component
+
+static uint64_t ceil_div_u(uint64_t a, uint64_t b) { return a / b + (a % b != 0); }
+static bool frac_less(const Rational &x, const Rational &y) {   // x < y
+    return (unsigned __int128)x.num * y.den < (unsigned __int128)y.num * x.den;
+}
+static Rational reduced(uint64_t a, uint64_t b) {
+    if (a == 0) return {0, 1};
+    uint64_t x = a, y = b;
+    while (y) { uint64_t t = x % y; x = y; y = t; }
+    return {a / x, b / x};
+}
+
+// Network over the vertex set `verts` of one component.
+class CompNet {
+public:
+    CompNet(const LocatedCore &lc, int h, const std::vector<int32_t> &verts) : lc_(lc), h_(h), verts_(verts) {
+        const int32_t S = (int32_t)lc.rank.size();
+        in_.assign(S, 0);
+        for (int32_t v : verts) in_[v] = 1;
+        idx_.assign(S, -1);
+        for (size_t i = 0; i < verts.size(); i++) idx_[verts[i]] = (int32_t)i;
+        const int nv = (int)verts.size();
+        deg_.assign(nv, 0);
+        if (h == 2) {
+            net_ = new PushRelabel(2 + nv);
+            m_ = 0;
+            for (int i = 0; i < nv; i++) {
+                src_.push_back(net_->arc(0, 2 + i));
+                snk_.push_back(net_->arc(2 + i, 1));
+                int32_t v = verts[i];
+                for (int64_t e = lc.off[v]; e < lc.off[v + 1]; e++) {
+                    int32_t w = lc.adj[e];
+                    if (!in_[w]) continue;
+                    deg_[i]++;
+                    if (w > v) {
+                        mid_.push_back(net_->arc(2 + i, 2 + idx_[w]));
+                        m_++;
+                    }
+                }
+            }
+            mu_ = m_;
+        } else {
+            // h-cliques, and the (h-1)-cliques they contain, as sorted tuples
+            const int r = h - 1;
+            std::vector<int32_t> cl;
+            list_cliques(lc, in_, h, [&](const int32_t *mem) { cl.insert(cl.end(), mem, mem + h); });
+            mu_ = cl.size() / h;
+            std::vector<int32_t> tup;
+            tup.reserve(mu_ * h * r);
+            for (uint64_t c = 0; c < mu_; c++) {
+                const int32_t *K = &cl[c * h];
+                for (int i = 0; i < h; i++) deg_[idx_[K[i]]]++;
+                for (int drop = 0; drop < h; drop++)
+                    for (int i = 0; i < h; i++)
+                        if (i != drop) tup.push_back(K[i]);
+            }
+            const uint64_t T = mu_ * h;
+            std::vector<uint32_t> ord(T);
+            std::iota(ord.begin(), ord.end(), 0u);
+            std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+                return std::lexicographical_compare(&tup[a * r], &tup[a * r] + r, &tup[b * r], &tup[b * r] + r);
+            });
+            std::vector<int32_t> psi_of(T);
+            int64_t npsi = 0;
+            for (uint64_t i = 0; i < T; i++) {
+                if (i > 0 && std::equal(&tup[ord[i] * r], &tup[ord[i] * r] + r, &tup[ord[i - 1] * r])) {
+                    psi_of[ord[i]] = psi_of[ord[i - 1]];
+                } else {
+                    psi_of[ord[i]] = (int32_t)npsi;
+                    psi_first_.push_back(ord[i]);
+                    npsi++;
+                }
+            }
+            const int64_t base = 2 + nv;
+            if (base + npsi > 0x7fffffff) throw Error(-5, "flow network too large");
+            net_ = new PushRelabel((int)(base + npsi));
+            for (int i = 0; i < nv; i++) {
+                src_.push_back(net_->arc(0, 2 + i));
+                snk_.push_back(net_->arc(2 + i, 1));
+            }
+            for (int64_t p = 0; p < npsi; p++)
+                for (int i = 0; i < r; i++)
+                    inf_.push_back(net_->arc((int)(base + p), 2 + idx_[tup[psi_first_[p] * r + i]]));
+            for (uint64_t c = 0; c < mu_; c++) {
+                const int32_t *K = &cl[c * h];
+                for (int drop = 0; drop < h; drop++)
+                    mid_.push_back(net_->arc(2 + idx_[K[drop]], (int)(base + psi_of[c * h + drop])));
+            }
+        }
+        net_->build();
+    }
+    ~CompNet() { delete net_; }
+    CompNet(const CompNet &) = delete;
+    CompNet &operator=(const CompNet &) = delete;
+
+    uint64_t mu() const { return mu_; }
+    int nodes() const { return net_->nodes(); }
+
+    // Strict test at alpha = a/b.  Returns true and the found set (local ids)
+    // when some subgraph of this vertex set is denser than alpha.
+    bool denser_than(uint64_t a, uint64_t b, std::vector<int32_t> &found) {
+        const int nv = (int)verts_.size();
+        i128 srcsum = 0;
+        if (h_ == 2) {
+            const i128 bm = (i128)b * (i128)m_;
+            for (int i = 0; i < nv; i++) {
+                i128 cs = bm, ct = bm + 2 * (i128)a - (i128)b * (i128)deg_[i];
+                if (cs >= CAP_LIMIT || ct >= CAP_LIMIT || ct < 0) throw Error(-4, "scaled capacity overflow");
+                net_->set(src_[i], (int64_t)cs);
+                net_->set(snk_[i], (int64_t)ct);
+                srcsum += cs;
+            }
+            for (int e : mid_) net_->set(e, (int64_t)b, (int64_t)b);
+        } else {
+            for (int i = 0; i < nv; i++) {
+                i128 cs = (i128)b * (i128)deg_[i], ct = (i128)h_ * (i128)a;
+                if (cs >= CAP_LIMIT || ct >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+                net_->set(src_[i], (int64_t)cs);
+                net_->set(snk_[i], (int64_t)ct);
+                srcsum += cs;
+            }
+            if (srcsum * 2 >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+            const int64_t inf = (int64_t)srcsum + 1;
+            for (int e : inf_) net_->set(e, inf);
+            for (int e : mid_) net_->set(e, (int64_t)b);
+        }
+        if (srcsum >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+        int64_t f = net_->maxflow(0, 1);
+        if ((i128)f >= srcsum) return false;
+        std::vector<char> reach;
+        net_->reach_sink(1, reach);
+        found.clear();
+        for (int i = 0; i < nv; i++)
+            if (!reach[2 + i]) found.push_back(verts_[i]);
+        return !found.empty();
+    }
+
+private:
+    const LocatedCore &lc_;
+    int h_;
+    std::vector<int32_t> verts_;
+    std::vector<char> in_;
+    std::vector<int32_t> idx_;
+    std::vector<uint64_t> deg_;
+    std::vector<int> src_, snk_, mid_, inf_;
+    std::vector<uint32_t> psi_first_;
+    uint64_t mu_ = 0, m_ = 0;
+    PushRelabel *net_ = nullptr;
+};
+
+bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::vector<int32_t> &best,
+                  ExactStats &st) {
+    const int32_t S = (int32_t)lc.rank.size();
+    // group vertices by component
+    std::vector<int32_t> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return lc.label[a] != lc.label[b] ? lc.label[a] < lc.label[b] : a < b;
+    });
+    struct Comp {
+        std::vector<int32_t> v;
+        Rational dens;
+    };
+    std::vector<Comp> comps;
+    for (int32_t i = 0; i < S;) {
+        int32_t j = i;
+        Comp c;
+        while (j < S && lc.label[order[j]] == lc.label[order[i]]) c.v.push_back(order[j++]);
+        i = j;
+        if (c.v.size() < 2) continue;
+        c.dens = reduced(count_cliques_host(lc, h, c.v), c.v.size());
+        comps.push_back(std::move(c));
+    }
+    std::stable_sort(comps.begin(), comps.end(), [](const Comp &a, const Comp &b) { return frac_less(b.dens, a.dens); });
+    bool improved = false;
+    std::vector<int32_t> found, cur, built;
+    for (const Comp &c : comps) {
+        Rational lc_l = l;
+        std::vector<int32_t> U;
+        std::unique_ptr<CompNet> net;
+        while (true) {
+            // Lemma 7: anything denser than l lies in the ceil(l)-clique-core
+            uint64_t floor_k = std::max<uint64_t>(kpp, ceil_div_u(lc_l.num, lc_l.den));
+            cur.clear();
+            for (int32_t v : c.v)
+                if (lc.core[v] >= floor_k) cur.push_back(v);
+            if (cur.size() < 2) break;
+            if (!net || cur != built) {
+                net.reset(new CompNet(lc, h, cur));
+                built = cur;
+            }
+            st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
+            st.flow_calls++;
+            if (!net->denser_than(lc_l.num, lc_l.den, found)) break;
+            U = found;
+            lc_l = reduced(count_cliques_host(lc, h, U), U.size());
+        }
+        if (!U.empty() && frac_less(l, lc_l)) {
+            l = lc_l;
+            best = U;
+            improved = true;
+        }
+    }
+    return improved;
+}
+
+}  // namespace dsd

@@ -1,0 +1,83 @@
+// Device graph layout and the internal launchers of every kernel family.
+//
+// All kernels work in *rank space*: vertex r is the vertex of rank r in the
+// degree order (deg, id) ascending.  Row r of the CSR lists N(r) sorted by
+// rank; its tail from dag_off[r] on is N+(r), the out-neighbours of r in the
+// degree-ordered DAG (every h-clique is reached once from its lowest-rank
+// member).  Outputs are mapped back to the caller's ids through orig_of /
+// rank_of.
+#pragma once
+
+#include "exact.hpp"
+#include "primitives.hpp"
+
+namespace dsd {
+
+struct DevGraph {
+    int32_t n = 0;
+    int64_t m = 0;            // undirected edges
+    int bits = 1;             // bits needed to hold n (ids < 2^bits - 1)
+    int64_t *row_ptr = nullptr;  // [n+1]
+    int32_t *col = nullptr;      // [2m]
+    int64_t *dag_off = nullptr;  // [n]
+    int32_t *orig_of = nullptr;  // [n] rank -> caller id
+    int32_t *rank_of = nullptr;  // [n] caller id -> rank
+    int32_t maxdeg = 0, maxdout = 0;
+};
+
+// ---- K1 + K2: CSR build and degree-ordered orientation ----
+// src/dst: device arrays of num_pairs raw pairs.  Throws Error(EINVAL) on an
+// id outside [0, n).  t_orient receives the time of the orientation part.
+void build_graph(int32_t n, int64_t num_pairs, const int32_t *src, const int32_t *dst, DevGraph &g,
+                 hipStream_t s, Scratch &sc, float *t_orient_ms);
+void free_graph(DevGraph &g);
+
+// ---- K3: clique-degrees ----
+// deg[r] (rank space, length n) = number of h-cliques containing r inside the
+// subgraph induced by mask (mask == nullptr: whole graph).  deg is
+// overwritten.  Returns false if the counts could overflow 64 bits.
+bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc);
+
+// ---- K4: round-synchronous peel ----
+struct PeelResult {
+    int64_t rounds = 0;
+    int64_t levels = 0;
+    std::vector<u64> level_k, level_size, level_mu;  // R_k for every level k reached
+    u64 kmax = 0;
+};
+// alive0 (nullable): vertices taking part (others are ignored).  deg: clique
+// degrees inside the alive set (consumed).  mu: cliques inside the alive set.
+// k_floor: every vertex of degree <= k_floor goes in the first level (CoreApp
+// starts its peel there); 0 for a full decomposition.  core: rank space.
+PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
+                hipStream_t s, Scratch &sc);
+
+// ---- K5: connected components of the subgraph induced by mask ----
+// label[r] = smallest rank of r's component for r in mask, -1 outside.
+void components(const DevGraph &g, const uint8_t *mask, int32_t *label, hipStream_t s, Scratch &sc);
+
+// ---- small kernels used by the drivers ----
+void mask_core_at_least(const u64 *core, int32_t n, u64 k, uint8_t *mask, hipStream_t s);
+void mask_from_order_prefix(const u64 *order, int32_t n, int64_t w, int bits, uint8_t *mask, hipStream_t s);
+// out[id] = in[rank_of[id]]
+void gather_to_orig_u64(const DevGraph &g, const u64 *in, u64 *out, hipStream_t s);
+void gather_to_orig_u8(const DevGraph &g, const uint8_t *in, uint8_t *out, hipStream_t s);
+void mask_core_equal(const u64 *core, int32_t n, u64 k, uint8_t *mask, hipStream_t s);
+// per-component (size, sum of deg) keyed by label root; out arrays length n
+void component_sums(const int32_t *label, const u64 *deg, int32_t n, u64 *size, u64 *dsum, hipStream_t s);
+// max of a u64 array over mask (mask nullable) -> out[0] (device)
+void masked_max_u64(const u64 *a, const uint8_t *mask, int32_t n, u64 *out, hipStream_t s);
+void masked_min_u64(const u64 *a, const uint8_t *mask, int32_t n, u64 *out, hipStream_t s);
+void mask_label_equal(const int32_t *label, int32_t n, int32_t l, uint8_t *mask, hipStream_t s);
+
+// ---- hand-over of a located core to the host exact step ----
+void extract_induced(const DevGraph &g, const uint8_t *mask, const int32_t *label, const u64 *core,
+                     LocatedCore &out, hipStream_t s, Scratch &sc);
+struct CompInfo {
+    int32_t root;
+    u64 size, dsum;   // |C| and the sum of clique-degrees inside C (= h * mu(C))
+};
+void collect_components(const int32_t *label, const u64 *size, const u64 *dsum, int32_t n,
+                        std::vector<CompInfo> &out, hipStream_t s, Scratch &sc);
+
+}  // namespace dsd

@@ -1,0 +1,199 @@
+"""Thin ctypes binding of libdsd (include/dsd.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module only converts numpy
+arrays / torch tensors to pointers and status codes to exceptions.  There is
+no CPU fallback: a missing library or GPU raises.
+
+Names follow the C ABI: ``build_csr``, ``clique_degrees``, ``clique_core``,
+``core_app``, ``core_exact``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsd.so")
+
+DSD_MEM_HOST = 0
+DSD_MEM_DEVICE = 1
+
+STATUS = {0: "DSD_OK", -1: "DSD_EINVAL", -2: "DSD_ENOMEM", -3: "DSD_EDEVICE",
+          -4: "DSD_EOVERFLOW", -5: "DSD_EUNSUPPORTED"}
+
+EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
+           "dsd_clique_core", "dsd_core_app", "dsd_core_exact", "dsd_last_stats",
+           "dsd_status_str", "dsd_last_error"]
+
+
+class DsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Rational(C.Structure):
+    _fields_ = [("num", C.c_uint64), ("den", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("t_orient_ms", C.c_double), ("t_enum_ms", C.c_double), ("t_peel_ms", C.c_double),
+                ("t_locate_ms", C.c_double), ("t_exact_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("num_cliques", C.c_uint64), ("peel_rounds", C.c_uint64), ("peel_levels", C.c_uint64),
+                ("flow_calls", C.c_uint64), ("flow_nodes_max", C.c_uint64),
+                ("located_vertices", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdsd.so (built by paper_1906_00341_amd/build.py); raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libdsd.so not built at {path}; run paper_1906_00341_amd/build.py")
+    lib = C.CDLL(path)
+    P, I32, I64, I = C.c_void_p, C.c_int32, C.c_int64, C.c_int
+    lib.dsd_build_csr.argtypes = [I32, I64, P, P, I, P, C.POINTER(P)]
+    lib.dsd_graph_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64)]
+    lib.dsd_graph_free.argtypes = [P]
+    lib.dsd_clique_degrees.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_clique_core.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
+    lib.dsd_core_exact.argtypes = [P, I, I, P, C.POINTER(Rational)]
+    lib.dsd_last_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.dsd_status_str.argtypes = [I]
+    lib.dsd_status_str.restype = C.c_char_p
+    lib.dsd_last_error.restype = C.c_char_p
+    for f in EXPORTS[:8]:
+        getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise DsdError(rc, (_lib.dsd_last_error() or b"").decode())
+
+
+def _ptr(a):
+    """(pointer, mem flag, keepalive) for a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be contiguous")
+        return a.ctypes.data, DSD_MEM_HOST, a
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), (DSD_MEM_DEVICE if a.is_cuda else DSD_MEM_HOST), a
+    raise TypeError(f"unsupported buffer type {type(a)}")
+
+
+class Graph:
+    """A device-resident graph handle (dsd_graph)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n, m = C.c_int32(), C.c_int64()
+        _check(_lib.dsd_graph_info(self._h, C.byref(n), C.byref(m)))
+        return int(n.value), int(m.value)
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            _lib.dsd_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.free()
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.dsd_last_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+
+def build_csr(n: int, src, dst, stream=None) -> Graph:
+    """dsd_build_csr: src/dst int32 numpy arrays (host) or torch int32 tensors (host or device)."""
+    lib = load()
+    ps, ms, ks = _ptr(src)
+    pd, md, kd = _ptr(dst)
+    if ms != md:
+        raise ValueError("src and dst must live in the same memory")
+    if len(src) != len(dst):
+        raise ValueError("src and dst differ in length")
+    h = C.c_void_p()
+    _check(lib.dsd_build_csr(int(n), int(len(src)), ps, pd, ms, stream, C.byref(h)))
+    del ks, kd
+    return Graph(h)
+
+
+def _out_u64(g: Graph, out):
+    n, _ = g.info()
+    if out is None:
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+    p, mem, keep = _ptr(out)
+    return out, p, mem
+
+
+def clique_degrees(g: Graph, h: int, out=None):
+    """dsd_clique_degrees -> (deg[n], mu)."""
+    out, p, mem = _out_u64(g, out)
+    mu = C.c_uint64()
+    _check(_lib.dsd_clique_degrees(g.handle, int(h), mem, p, C.byref(mu)))
+    n, _ = g.info()
+    return out[:n] if isinstance(out, np.ndarray) else out, int(mu.value)
+
+
+def clique_core(g: Graph, h: int, out=None):
+    """dsd_clique_core -> (core[n], kmax)."""
+    out, p, mem = _out_u64(g, out)
+    km = C.c_uint64()
+    _check(_lib.dsd_clique_core(g.handle, int(h), mem, p, C.byref(km)))
+    n, _ = g.info()
+    return out[:n] if isinstance(out, np.ndarray) else out, int(km.value)
+
+
+def _out_u8(g: Graph, out):
+    n, _ = g.info()
+    if out is None:
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+    p, mem, keep = _ptr(out)
+    return out, p, mem, n
+
+
+def core_app(g: Graph, h: int, out=None):
+    """dsd_core_app -> (member[n] uint8, kmax, density Fraction)."""
+    out, p, mem, n = _out_u8(g, out)
+    km, r = C.c_uint64(), Rational()
+    _check(_lib.dsd_core_app(g.handle, int(h), mem, p, C.byref(km), C.byref(r)))
+    return (out[:n] if isinstance(out, np.ndarray) else out), int(km.value), Fraction(r.num, r.den)
+
+
+def core_exact(g: Graph, h: int, out=None):
+    """dsd_core_exact -> (member[n] uint8, rho_opt Fraction)."""
+    out, p, mem, n = _out_u8(g, out)
+    r = Rational()
+    _check(_lib.dsd_core_exact(g.handle, int(h), mem, p, C.byref(r)))
+    return (out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den)
+
+
+def status_str(s: int) -> str:
+    return load().dsd_status_str(int(s)).decode()

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point include/dsd.h declares (CPU only)."""
+import ctypes
+import os
+import re
+
+from paper_1906_00341_amd import dsd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "dsd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_path():
+    syms = declared_symbols()
+    for s in ("dsd_build_csr", "dsd_clique_degrees", "dsd_clique_core", "dsd_core_app", "dsd_core_exact"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(dsd.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(dsd.EXPORTS) == declared_symbols()
+
+
+def test_status_strings():
+    lib = dsd.load()
+    for code, name in dsd.STATUS.items():
+        assert dsd.status_str(code) == name
+    assert lib.dsd_last_error() is not None
+
+
+def test_null_and_bad_arguments_are_rejected_without_touching_a_gpu():
+    lib = dsd.load()
+    h = ctypes.c_void_p()
+    assert lib.dsd_build_csr(-1, 0, None, None, 0, None, ctypes.byref(h)) == -1
+    assert lib.dsd_build_csr(3, 2, None, None, 0, None, ctypes.byref(h)) == -1
+    assert lib.dsd_build_csr(3, 0, None, None, 7, None, ctypes.byref(h)) == -1
+    assert lib.dsd_graph_free(None) == 0
+    assert lib.dsd_clique_degrees(None, 3, 0, None, None) == -1

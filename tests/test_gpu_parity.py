@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer results (clique-degrees, core numbers, k_max, member sets of the
+k_max-core) must match bit for bit; densities are compared as exact
+rationals.  Densest subgraphs need not be unique, so for CoreExact the
+returned set must attain rho_opt and lie inside the ceil(rho_opt)-core
+(Lemma 7 holds for every densest subgraph).
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import dsd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    dsd.load()          # fails loudly when the library is missing
+
+
+def both(n, s, d):
+    return oracle.Graph(n, s, d), dsd.build_csr(n, np.ascontiguousarray(s, np.int32), np.ascontiguousarray(d, np.int32))
+
+
+def density_of(og: oracle.Graph, h: int, member) -> Fraction:
+    idx = np.nonzero(np.asarray(member))[0]
+    if idx.size == 0:
+        return Fraction(0)
+    off, adj = og.adjacency()
+    keep = np.zeros(og.n, dtype=bool)
+    keep[idx] = True
+    rows = np.repeat(np.arange(og.n), np.diff(off))
+    e = keep[rows] & keep[adj] & (rows < adj)
+    sub = oracle.Graph(og.n, rows[e].astype(np.int32), adj[e].astype(np.int32))
+    _, mu = sub.clique_degrees(h)
+    return Fraction(mu, idx.size)
+
+
+def check_all(n, s, d, h, exact=True, app=True):
+    og, gg = both(n, s, d)
+    deg_o, mu_o = og.clique_degrees(h)
+    deg_g, mu_g = dsd.clique_degrees(gg, h)
+    assert mu_g == mu_o
+    np.testing.assert_array_equal(deg_g, deg_o)
+    core_o, km_o = og.core_decomposition(h)
+    core_g, km_g = dsd.clique_core(gg, h)
+    assert km_g == km_o
+    np.testing.assert_array_equal(core_g, core_o)
+    if app:
+        mem_o, km2, dens_o = og.inc_app(h)
+        mem_g, km3, dens_g = dsd.core_app(gg, h)
+        assert km3 == km2 and dens_g == dens_o
+        np.testing.assert_array_equal(mem_g.astype(bool), mem_o)
+    if exact:
+        _, rho_o, _ = og.exact(h, "core")
+        mem_g, rho_g = dsd.core_exact(gg, h)
+        assert rho_g == rho_o
+        if rho_o > 0:
+            assert density_of(og, h, mem_g) == rho_o
+            kk = math.ceil(rho_o)
+            assert (core_o[mem_g.astype(bool)] >= kk).all()
+        else:
+            assert not mem_g.any()
+    return gg
+
+
+# ------------------------------------------------------------------ fixtures
+
+@pytest.mark.parametrize("name", ["F1", "F2", "F4"])
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_paper_examples(fixtures, name, h):
+    f = fixtures[name]
+    e = np.asarray(f["edges"], np.int32)
+    check_all(f["n"], e[:, 0], e[:, 1], h)
+
+
+def test_fig1_values(fixtures):
+    f = fixtures["F1"]
+    e = np.asarray(f["edges"], np.int32)
+    g = dsd.build_csr(f["n"], e[:, 0], e[:, 1])
+    mem, rho = dsd.core_exact(g, 2)
+    assert rho == Fraction(11, 7) and np.nonzero(mem)[0].tolist() == f["expect"]["h2_cds"]
+    mem, rho = dsd.core_exact(g, 3)
+    assert rho == Fraction(1, 2) and np.nonzero(mem)[0].tolist() == f["expect"]["h3_cds"]
+    deg, _ = dsd.clique_degrees(g, 3)
+    A, B, C = f["labels"]["A"], f["labels"]["B"], f["labels"]["C"]
+    assert [int(deg[A]), int(deg[B]), int(deg[C])] == [2, 1, 2]
+
+
+# ------------------------------------------------------------------ random small graphs
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("h", [2, 3, 4, 5, 6])
+def test_random_small(seed, h):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(20, 160))
+    p = float(rng.uniform(0.05, 0.45))
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < p
+    check_all(n, iu[keep].astype(np.int32), ju[keep].astype(np.int32), h, exact=(n <= 80 or h <= 3))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5])
+@pytest.mark.parametrize("h", [2, 3, 6])
+def test_tiny_and_empty(n, h):
+    z = np.zeros(0, np.int32)
+    g = dsd.build_csr(n, z, z)
+    assert g.info() == (n, 0)
+    if n == 0:
+        return
+    deg, mu = dsd.clique_degrees(g, h)
+    assert mu == 0 and not deg.any()
+    core, km = dsd.clique_core(g, h)
+    assert km == 0 and not core.any()
+    mem, km, dens = dsd.core_app(g, h)
+    assert km == 0 and dens == 0 and not mem.any()
+    mem, rho = dsd.core_exact(g, h)
+    assert rho == 0 and not mem.any()
+
+
+def test_duplicates_and_self_loops_are_dropped():
+    s = np.array([0, 1, 1, 2, 2, 3, 0, 0], np.int32)
+    d = np.array([1, 0, 1, 0, 2, 3, 2, 1], np.int32)
+    g = dsd.build_csr(4, s, d)
+    assert g.info() == (4, 3)
+    deg, mu = dsd.clique_degrees(g, 3)
+    assert mu == 1 and deg.tolist() == [1, 1, 1, 0]
+
+
+@pytest.mark.parametrize("h", [2, 3, 4, 5, 6])
+def test_complete_graph(h):
+    n, s, d = synth.complete_graph(40)
+    g = dsd.build_csr(n, s, d)
+    deg, mu = dsd.clique_degrees(g, h)
+    assert mu == math.comb(40, h) and (deg == math.comb(39, h - 1)).all()
+    core, km = dsd.clique_core(g, h)
+    assert km == math.comb(39, h - 1) and (core == km).all()
+    mem, rho = dsd.core_exact(g, h)
+    assert rho == Fraction(math.comb(40, h), 40) and mem.all()
+
+
+def test_bad_arguments():
+    g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    for h in (0, 1, 7):
+        with pytest.raises(dsd.DsdError) as e:
+            dsd.clique_degrees(g, h)
+        assert e.value.status == -1
+    with pytest.raises(dsd.DsdError) as e:
+        dsd.build_csr(3, np.array([0, 3], np.int32), np.array([1, 2], np.int32))
+    assert e.value.status == -1
+    with pytest.raises(dsd.DsdError) as e:
+        dsd.build_csr(3, np.array([0, -1], np.int32), np.array([1, 2], np.int32))
+    assert e.value.status == -1
+
+
+# ------------------------------------------------------------------ configuration-shaped graphs
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_er_planted_config(seed):
+    n, s, d = synth.er_planted(seed=seed)
+    for h in (2, 3):
+        check_all(n, s, d, h)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_chung_lu_medium(seed):
+    n, s, d = synth.chung_lu(n=30000, avg_deg=12, beta=2.1, planted=2, plant_size=60, p=0.7, seed=seed)
+    check_all(n, s, d, 3)
+    check_all(n, s, d, 4, exact=False)
+
+
+@pytest.mark.parametrize("scale,h", [(11, 4), (11, 5), (12, 4), (10, 6)])
+def test_rmat_small(scale, h):
+    n, s, d = synth.rmat(scale=scale, edge_factor=16, seed=scale)
+    check_all(n, s, d, h, exact=False)
+
+
+def test_device_buffers():
+    torch = pytest.importorskip("torch")
+    n, s, d = synth.er_planted(seed=4)
+    og = oracle.Graph(n, s, d)
+    ts, td = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    g = dsd.build_csr(n, ts, td)
+    out = torch.zeros(n, dtype=torch.uint64, device="cuda")
+    dsd.clique_degrees(g, 3, out=out)
+    deg_o, _ = og.clique_degrees(3)
+    np.testing.assert_array_equal(out.cpu().numpy(), deg_o)
+    dsd.clique_core(g, 3, out=out)
+    core_o, _ = og.core_decomposition(3)
+    np.testing.assert_array_equal(out.cpu().numpy(), core_o)
+    mem = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    _, km, _ = dsd.core_app(g, 3, out=mem)
+    m_o, km_o, _ = og.inc_app(3)
+    assert km == km_o
+    np.testing.assert_array_equal(mem.cpu().numpy().astype(bool), m_o)
+
+
+def test_repeat_calls_are_identical():
+    n, s, d = synth.chung_lu(n=20000, avg_deg=10, beta=2.3, planted=1, plant_size=50, p=0.6, seed=9)
+    g = dsd.build_csr(n, s, d)
+    ref = [dsd.clique_degrees(g, 3)[0].copy(), dsd.clique_core(g, 3)[0].copy()]
+    for _ in range(3):
+        np.testing.assert_array_equal(dsd.clique_degrees(g, 3)[0], ref[0])
+        np.testing.assert_array_equal(dsd.clique_core(g, 3)[0], ref[1])
