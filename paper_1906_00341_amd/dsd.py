@@ -60,6 +60,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError(f"libdsd.so not built at {path}; run paper_1906_00341_amd/build.py")
+    # torch provides device memory and streams; loading it first makes libdsd
+    # bind to the same HIP runtime (both carry the soname libamdhip64.so.7)
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover
+        pass
     lib = C.CDLL(path)
     P, I32, I64, I = C.c_void_p, C.c_int32, C.c_int64, C.c_int
     lib.dsd_build_csr.argtypes = [I32, I64, P, P, I, P, C.POINTER(P)]
@@ -133,6 +139,10 @@ class Graph:
 def build_csr(n: int, src, dst, stream=None) -> Graph:
     """dsd_build_csr: src/dst int32 numpy arrays (host) or torch int32 tensors (host or device)."""
     lib = load()
+    if isinstance(src, np.ndarray):
+        src = np.ascontiguousarray(src, dtype=np.int32)
+    if isinstance(dst, np.ndarray):
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
     ps, ms, ks = _ptr(src)
     pd, md, kd = _ptr(dst)
     if ms != md:

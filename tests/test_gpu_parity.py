@@ -126,8 +126,8 @@ def test_tiny_and_empty(n, h):
 
 
 def test_duplicates_and_self_loops_are_dropped():
-    s = np.array([0, 1, 1, 2, 2, 3, 0, 0], np.int32)
-    d = np.array([1, 0, 1, 0, 2, 3, 2, 1], np.int32)
+    s = np.array([0, 1, 1, 2, 2, 3, 0, 0, 2], np.int32)
+    d = np.array([1, 0, 1, 0, 2, 3, 2, 1, 1], np.int32)
     g = dsd.build_csr(4, s, d)
     assert g.info() == (4, 3)
     deg, mu = dsd.clique_degrees(g, 3)
