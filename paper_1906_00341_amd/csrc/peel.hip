@@ -10,10 +10,12 @@
 // When no frontier is left, k jumps to the smallest alive degree (a new
 // level; no level in between can remove anything).
 //
-// State lives on the device (PeelCtl).  One step is a fixed sequence of
-// kernels (level-min, level-build, process, [finalize]) that read the state
-// themselves, so the host enqueues many steps without waiting and only polls
-// the number of alive vertices now and then.
+// State lives on the device (PeelCtl).  While many vertices are alive, one
+// round is a fixed sequence of grid-wide kernels (level-min, level-build,
+// process) that read the state themselves, so the host enqueues many rounds
+// without waiting.  Once few vertices are left, the rounds are short and
+// many (one per distinct core value at least), so a single workgroup
+// finishes the peel in one launch with workgroup barriers between rounds.
 #include "engine.hpp"
 #include "graph.hpp"
 
@@ -25,29 +27,43 @@ struct PeelCtl {
     u64 mu_alive;   // cliques among alive vertices
     u64 destroyed;  // cliques destroyed in this round
     int64_t n_alive;
+    int64_t tail_T;    // the single-workgroup tail takes over at or below this many alive vertices
     int32_t round;
     int32_t cur;       // frontier buffer in use
     int32_t nF[2];     // frontier sizes
+    int32_t nB[2];     // chunk items of large frontier vertices (h = 3)
     int32_t nlist[2];  // alive-list sizes
     int32_t lcur;      // alive list in use
     int32_t nlevels;
     uint32_t done;     // finished blocks (last-block finalisation)
-    int32_t selecting; // set by level-min: this step starts a new level
+    int32_t selecting; // set by level-min: this round starts a new level
     int32_t nitems[8]; // (v, w) work items per class (h >= 4)
 };
 
 struct PeelBufs {
     PeelCtl *ctl;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const int64_t *dag_off;
     int32_t *stamp;    // ALIVE, removal round, or -1 (not taking part)
     u64 *deg;          // current clique-degree
     u64 *core;
     int32_t *F;        // [2][n] frontiers
+    int64_t *B;        // [2][bcap] (v << 32 | chunk) for frontier vertices of degree > SMALL_DEG
+    int64_t bcap;
     int32_t *lists;    // [2][n] alive lists
     u64 *lv_k, *lv_size, *lv_mu;  // level table [n + 1]
-    int32_t *item_v, *item_w;     // [8][cap] work items (h >= 4)
+    int32_t *item_v, *item_w;     // [5][cap] work items (h >= 4)
     int64_t item_cap;
     int32_t n;
+    int32_t h;
 };
+
+constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
+constexpr int CHUNK = 512;              // neighbours per chunk item
+constexpr int BIG_HASH_BITS = 14;       // 16384 slots = 64 KB of LDS
+constexpr int BIG_HASH_CAP = 8192;      // larger neighbourhoods use binary search
+constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
 
 // all lanes of the wave must call this together
 __device__ __forceinline__ void wave_push(bool pred, int32_t val, int32_t *arr, int32_t *counter) {
@@ -70,24 +86,45 @@ __device__ __forceinline__ bool last_block(uint32_t *done) {
     return is_last;
 }
 
+// chunk items of a large frontier vertex (h = 3)
+__device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int which) {
+    if (b.h != 3) return;
+    int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
+    if (d <= SMALL_DEG) return;
+    int32_t nc = (int32_t)((d + CHUNK - 1) / CHUNK);
+    int32_t base = atomicAdd(&b.ctl->nB[which], nc);
+    int64_t *Bw = b.B + (size_t)which * b.bcap;
+    for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
+}
+
 __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, u64 k, int32_t r) {
     u64 old = atomic_sub_u64(&b.deg[x], c);
     if (old > k && old - c <= k) {
-        int32_t *Fn = b.F + (size_t)(b.ctl->cur ^ 1) * b.n;
-        int32_t pos = atomicAdd(&b.ctl->nF[b.ctl->cur ^ 1], 1);
+        const int nx = b.ctl->cur ^ 1;
+        int32_t *Fn = b.F + (size_t)nx * b.n;
+        int32_t pos = atomicAdd(&b.ctl->nF[nx], 1);
         Fn[pos] = x;
         b.stamp[x] = r + 1;
         b.core[x] = k;
+        push_chunks(b, x, nx);
     }
 }
 
+// a clique through frontier vertex v may use x iff x was alive at the start
+// of the round and is not a frontier vertex of smaller rank (owner rule)
+__device__ __forceinline__ bool allowed(int32_t st, int32_t r, int32_t x, int32_t v) {
+    return st > r || (st == r && x > v);
+}
+
 // ---------------------------------------------------------------- level selection
+
+__device__ __forceinline__ bool grid_rounds_on(const PeelCtl *c) { return c->n_alive > c->tail_T; }
 
 __global__ __launch_bounds__(BLOCK) void k_level_min(PeelBufs b) {
     PeelCtl *c = b.ctl;
     // nF and n_alive do not change during this kernel, so every block takes
     // the same decision; level-build reads the flag because it grows nF itself
-    const bool sel = c->nF[c->cur] == 0 && c->n_alive > 0;
+    const bool sel = c->nF[c->cur] == 0 && c->n_alive > 0 && grid_rounds_on(c);
     if (blockIdx.x == 0 && threadIdx.x == 0) c->selecting = sel ? 1 : 0;
     if (!sel) return;
     const int32_t *list = b.lists + (size_t)c->lcur * b.n;
@@ -102,6 +139,18 @@ __global__ __launch_bounds__(BLOCK) void k_level_min(PeelBufs b) {
     }
     m = wave_min(m);
     if (lane() == 0 && m != ~0ull) atomicMin(&c->kcand, m);
+}
+
+__device__ __forceinline__ void record_level(const PeelBufs &b, PeelCtl *c, u64 k) {
+    int32_t L = c->nlevels;
+    b.lv_k[L] = k;
+    b.lv_size[L] = (u64)c->n_alive;
+    b.lv_mu[L] = c->mu_alive;
+    c->nlevels = L + 1;
+    c->k = k;
+    c->kcand = ~0ull;
+    c->nlist[c->lcur] = 0;
+    c->lcur ^= 1;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
@@ -126,20 +175,13 @@ __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
         if (take) {
             b.stamp[v] = r;
             b.core[v] = k;
+            push_chunks(b, v, cur);
         }
         wave_push(take, v, F, &c->nF[cur]);
         wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
     }
     if (last_block(&c->done) && threadIdx.x == 0) {
-        int32_t L = c->nlevels;
-        b.lv_k[L] = k;
-        b.lv_size[L] = (u64)c->n_alive;
-        b.lv_mu[L] = c->mu_alive;
-        c->nlevels = L + 1;
-        c->k = k;
-        c->kcand = ~0ull;
-        c->nlist[lc] = 0;
-        c->lcur = lc ^ 1;
+        record_level(b, c, k);
         c->done = 0;
     }
 }
@@ -151,6 +193,7 @@ __device__ __forceinline__ void finish_round(PeelCtl *c) {
     c->mu_alive -= c->destroyed;
     c->destroyed = 0;
     c->nF[cur] = 0;
+    c->nB[cur] = 0;
     c->cur = cur ^ 1;
     c->round += 1;
     c->done = 0;
@@ -159,10 +202,10 @@ __device__ __forceinline__ void finish_round(PeelCtl *c) {
 
 // ---------------------------------------------------------------- h = 2
 
-__global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b, const int64_t *row_ptr, const int32_t *col) {
+__global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0) return;
+    if (nF == 0 || !grid_rounds_on(c)) return;
     const int32_t r = c->round;
     const u64 k = c->k;
     const int32_t *F = b.F + (size_t)cur * b.n;
@@ -170,8 +213,8 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b, const int64_t 
     const int wv = threadIdx.x / WAVE;
     for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nF; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[i];
-        for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) {
-            int32_t w = col[e];
+        for (int64_t e = b.row_ptr[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
+            int32_t w = b.col[e];
             int32_t st = b.stamp[w];
             if (st == r) {
                 destroyed += (v < w) ? 1 : 0;       // both ends leave: count the edge once
@@ -188,91 +231,334 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b, const int64_t 
 
 // ---------------------------------------------------------------- h = 3
 
-constexpr int H3_HASH_BITS = 10;              // 1024 slots per wave
-constexpr int H3_HASH_CAP = 512;              // neighbourhoods up to this size use the hash
+// LDS hash over the allowed neighbourhood of frontier vertex v.  The value of
+// a slot counts the cliques through v found so far that contain that
+// neighbour; the counts go to global memory once per neighbour (flush), so
+// the pair loop itself never waits on a global atomic.
+struct NbHash {
+    int32_t *keys;
+    uint32_t *vals;
+    int bits;
+    __device__ __forceinline__ int find(int32_t x) const {
+        uint32_t m = (1u << bits) - 1u, slot = hash_slot(x, bits);
+        while (true) {
+            int32_t key = keys[slot];
+            if (key == x) return (int)slot;
+            if (key == HASH_EMPTY) return -1;
+            slot = (slot + 1) & m;
+        }
+    }
+    __device__ __forceinline__ void put(int32_t x) const {
+        uint32_t m = (1u << bits) - 1u, slot = hash_slot(x, bits);
+        while (true) {
+            int32_t prev = atomicCAS(&keys[slot], HASH_EMPTY, x);
+            if (prev == HASH_EMPTY || prev == x) return;
+            slot = (slot + 1) & m;
+        }
+    }
+};
 
-__global__ __launch_bounds__(BLOCK) void k_process_h3(PeelBufs b, const int64_t *row_ptr, const int32_t *col,
-                                                      const int64_t *dag_off) {
-    __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << H3_HASH_BITS];
-    __shared__ int32_t sVal[WAVES_PER_BLOCK][1 << H3_HASH_BITS];
+__device__ __forceinline__ int hash_bits_for(int64_t d) {
+    int bits = 7;
+    while (bits < BIG_HASH_BITS && ((int64_t)1 << bits) < 2 * d) bits++;
+    return bits;
+}
+
+// insert the allowed neighbours N(v)[rv0, rv1) (threads t, t + step, ...)
+__device__ __forceinline__ void hash_fill(const PeelBufs &b, const NbHash &hs, int32_t v, int64_t rv0, int64_t rv1,
+                                          int32_t r, int t, int step) {
+    for (int64_t e = rv0 + t; e < rv1; e += step) {
+        int32_t x = b.col[e];
+        if (allowed(b.stamp[x], r, x, v)) hs.put(x);
+    }
+}
+
+// apply the pending counts of slots t, t + step, ... and empty them
+__device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, int32_t r, u64 k, int t, int step) {
+    for (int i = t; i < (1 << hs.bits); i += step) {
+        int32_t key = hs.keys[i];
+        if (key == HASH_EMPTY) continue;
+        uint32_t c = hs.vals[i];
+        if (c && b.stamp[key] > r) dec_deg(b, key, c, k, r);
+        hs.keys[i] = HASH_EMPTY;
+        hs.vals[i] = 0;
+    }
+}
+
+// One wave handles the neighbours N(v)[lo, hi) of frontier vertex v: for each
+// allowed neighbour w it probes N+(w) against the allowed neighbourhood of v,
+// so every triangle {v, w, x} with w before x is seen once.  HASHED: counts
+// go to the hash values; otherwise membership is a binary search in the
+// sorted row N(v)[rv0, rv1) and survivors are decremented at once.
+// sPre/sSt/sW/sCnt: this wave's 64-entry LDS scratch.
+template <bool HASHED>
+__device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int64_t rv0,
+                                            int64_t rv1, int32_t r, u64 k, const NbHash &hs, int32_t *sPre,
+                                            int64_t *sSt, int32_t *sW, uint32_t *sCnt) {
+    const int L = lane();
+    u64 destroyed = 0;
+    for (int64_t base = lo; base < hi; base += WAVE) {
+        int32_t w = -1, len = 0, wslot = -1;
+        int64_t st0 = 0;
+        if (base + L < hi) {
+            w = b.col[base + L];
+            if (allowed(b.stamp[w], r, w, v)) {
+                st0 = b.dag_off[w];
+                len = (int32_t)(b.row_ptr[w + 1] - st0);
+                if (HASHED) wslot = hs.find(w);
+            }
+        }
+        int32_t inc = wave_incl_scan(len);
+        sPre[L] = inc;
+        sSt[L] = st0;
+        sW[L] = HASHED ? wslot : w;
+        sCnt[L] = 0;
+        const int32_t total = __shfl(inc, WAVE - 1, WAVE);
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t pb = 0; pb < total; pb += WAVE) {
+            int32_t p = pb + L;
+            if (p < total) {
+                int i = upper_bound_i32(sPre, WAVE, p);
+                int32_t off = p - (i ? sPre[i - 1] : 0);
+                int32_t x = b.col[sSt[i] + off];
+                if (HASHED) {
+                    int slot = hs.find(x);
+                    if (slot >= 0) {                      // triangle {v, w, x}, owned by v
+                        destroyed++;
+                        atomicAdd(&sCnt[i], 1u);
+                        atomicAdd(&hs.vals[slot], 1u);
+                    }
+                } else if (allowed(b.stamp[x], r, x, v) && bsearch_i32(b.col, rv0, rv1, x) >= 0) {
+                    destroyed++;
+                    atomicAdd(&sCnt[i], 1u);
+                    if (b.stamp[x] > r) dec_deg(b, x, 1, k, r);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t cw = sCnt[L];
+        if (cw) {
+            if (HASHED) atomicAdd(&hs.vals[sW[L]], cw);
+            else if (b.stamp[sW[L]] > r) dec_deg(b, sW[L], cw, k, r);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    return destroyed;
+}
+
+// small frontier vertices (degree <= SMALL_DEG): one wave each, per-wave hash
+__global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
+    __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
+    __shared__ uint32_t sVal[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
     __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
     __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
     __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
     __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0) return;
+    if (nF == 0 || !grid_rounds_on(c)) return;
     const int32_t r = c->round;
     const u64 k = c->k;
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE, L = lane();
+    const NbHash hs{sKey[wv], sVal[wv], SMALL_HASH_BITS};
     u64 destroyed = 0;
-    for (int i = L; i < (1 << H3_HASH_BITS); i += WAVE) sKey[wv][i] = HASH_EMPTY;
+    for (int i = L; i < (1 << SMALL_HASH_BITS); i += WAVE) {
+        hs.keys[i] = HASH_EMPTY;
+        hs.vals[i] = 0;
+    }
     __builtin_amdgcn_wave_barrier();
     for (int64_t fi = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; fi < nF; fi += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[fi];
-        const int64_t rv0 = row_ptr[v], rv1 = row_ptr[v + 1];
-        const int64_t dv = rv1 - rv0;
-        const bool use_hash = dv <= H3_HASH_CAP;
-        if (use_hash) {
-            for (int64_t e = rv0 + L; e < rv1; e += WAVE) {
-                int32_t x = col[e];
-                int32_t st = b.stamp[x];
-                if (st > r || (st == r && x > v)) hash_insert(sKey[wv], sVal[wv], H3_HASH_BITS, x, 0);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int64_t base = 0; base < dv; base += WAVE) {
-            int32_t w = -1, len = 0;
-            int64_t st0 = 0;
-            if (base + L < dv) {
-                w = col[rv0 + base + L];
-                int32_t st = b.stamp[w];
-                if (st > r || (st == r && w > v)) {
-                    st0 = dag_off[w];
-                    len = (int32_t)(row_ptr[w + 1] - st0);
-                }
-            }
-            int32_t inc = wave_incl_scan(len);
-            sPre[wv][L] = inc;
-            sSt[wv][L] = st0;
-            sW[wv][L] = w;
-            sCnt[wv][L] = 0;
-            const int32_t total = __shfl(inc, WAVE - 1, WAVE);
-            __builtin_amdgcn_wave_barrier();
-            for (int32_t pb = 0; pb < total; pb += WAVE) {
-                int32_t p = pb + L;
-                if (p < total) {
-                    int i = upper_bound_i32(sPre[wv], WAVE, p);
-                    int32_t off = p - (i ? sPre[wv][i - 1] : 0);
-                    int32_t x = col[sSt[wv][i] + off];
-                    bool found;
-                    if (use_hash) {
-                        found = hash_find(sKey[wv], sVal[wv], H3_HASH_BITS, x) >= 0;
-                    } else {
-                        int32_t st = b.stamp[x];
-                        found = (st > r || (st == r && x > v)) && bsearch_i32(col, rv0, rv1, x) >= 0;
-                    }
-                    if (found) {                       // triangle {v, w, x}, owned by v
-                        destroyed++;
-                        atomicAdd(&sCnt[wv][i], 1u);
-                        if (b.stamp[x] > r) dec_deg(b, x, 1, k, r);
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            uint32_t cw = sCnt[wv][L];
-            if (cw && b.stamp[sW[wv][L]] > r) dec_deg(b, sW[wv][L], cw, k, r);
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (use_hash) {
-            for (int i = L; i < (1 << H3_HASH_BITS); i += WAVE) sKey[wv][i] = HASH_EMPTY;
-            __builtin_amdgcn_wave_barrier();
-        }
+        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+        if (rv1 - rv0 > SMALL_DEG) continue;                     // chunk items cover it
+        hash_fill(b, hs, v, rv0, rv1, r, L, WAVE);
+        __builtin_amdgcn_wave_barrier();
+        destroyed += h3_wave_range<true>(b, v, rv0, rv1, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
+        __builtin_amdgcn_wave_barrier();
+        hash_flush(b, hs, r, k, L, WAVE);
+        __builtin_amdgcn_wave_barrier();
     }
     destroyed = wave_sum(destroyed);
     if (L == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
+}
+
+// All waves of a workgroup handle the neighbours N(v)[lo, hi) of v (64 at a
+// time, round-robin); the hash covers all of N(v).  Used by the grid kernel
+// for chunk items and by the tail for whole frontier vertices.
+template <int NW>
+__device__ __forceinline__ u64 h3_block_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int32_t r, u64 k,
+                                             int32_t *keys, uint32_t *vals, int32_t (*sPre)[WAVE],
+                                             int64_t (*sSt)[WAVE], int32_t (*sW)[WAVE], uint32_t (*sCnt)[WAVE]) {
+    const int wv = threadIdx.x / WAVE;
+    const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+    const bool hashed = rv1 - rv0 <= BIG_HASH_CAP;
+    const NbHash hs{keys, vals, hash_bits_for(rv1 - rv0)};
+    u64 destroyed = 0;
+    if (hashed) hash_fill(b, hs, v, rv0, rv1, r, threadIdx.x, NW * WAVE);
+    __syncthreads();
+    for (int64_t plo = lo + (int64_t)wv * WAVE; plo < hi; plo += (int64_t)NW * WAVE) {
+        const int64_t phi = min(hi, plo + WAVE);
+        if (hashed)
+            destroyed += h3_wave_range<true>(b, v, plo, phi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
+        else
+            destroyed += h3_wave_range<false>(b, v, plo, phi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
+    }
+    __syncthreads();
+    if (hashed) hash_flush(b, hs, r, k, threadIdx.x, NW * WAVE);
+    __syncthreads();
+    return destroyed;
+}
+
+// larger frontier vertices: one workgroup per chunk of CHUNK neighbours;
+// finishes the round
+__global__ __launch_bounds__(BLOCK) void k_process_h3_big(PeelBufs b) {
+    __shared__ int32_t sKey[1 << BIG_HASH_BITS];
+    __shared__ uint32_t sVal[1 << BIG_HASH_BITS];
+    __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
+    __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
+    __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
+    __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur, nF = c->nF[cur];
+    if (nF == 0 || !grid_rounds_on(c)) return;
+    const int32_t r = c->round;
+    const u64 k = c->k;
+    const int32_t nB = c->nB[cur];
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    u64 destroyed = 0;
+    if (nB > (int32_t)blockIdx.x) {
+        for (int i = threadIdx.x; i < (1 << BIG_HASH_BITS); i += BLOCK) {
+            sKey[i] = HASH_EMPTY;
+            sVal[i] = 0;
+        }
+    }
+    __syncthreads();
+    for (int64_t it = blockIdx.x; it < nB; it += gridDim.x) {
+        const int64_t item = Bc[it];
+        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+        const int64_t lo = rv0 + (int64_t)ch * CHUNK, hi = min(rv1, lo + CHUNK);
+        destroyed += h3_block_range<WAVES_PER_BLOCK>(b, v, lo, hi, r, k, sKey, sVal, sPre, sSt, sW, sCnt);
+    }
+    destroyed = wave_sum(destroyed);
+    if (lane() == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
     if (last_block(&c->done) && threadIdx.x == 0) finish_round(c);
+}
+
+// ---------------------------------------------------------------- tail: one workgroup
+
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_WAVES = TAIL_THREADS / WAVE;
+
+// Runs every remaining round inside one workgroup: level selection, frontier
+// build and clique destruction are separated by workgroup barriers.  Each
+// frontier vertex is handled by the whole workgroup in turn.
+template <int H>
+__global__ __launch_bounds__(TAIL_THREADS) void k_peel_tail(PeelBufs b) {
+    __shared__ int32_t sKey[1 << BIG_HASH_BITS];
+    __shared__ uint32_t sVal[1 << BIG_HASH_BITS];
+    __shared__ int32_t sPre[TAIL_WAVES][WAVE];
+    __shared__ int64_t sSt[TAIL_WAVES][WAVE];
+    __shared__ int32_t sW[TAIL_WAVES][WAVE];
+    __shared__ uint32_t sCnt[TAIL_WAVES][WAVE];
+    __shared__ u64 sRed[TAIL_WAVES];
+    __shared__ u64 sK;
+    __shared__ int64_t sAlive;
+    __shared__ int32_t sCur, sNF;
+    PeelCtl *c = b.ctl;
+    const int wv = threadIdx.x / WAVE, L = lane();
+    for (int i = threadIdx.x; i < (1 << BIG_HASH_BITS); i += TAIL_THREADS) {
+        sKey[i] = HASH_EMPTY;
+        sVal[i] = 0;
+    }
+    while (true) {
+        // one thread reads the control state, so every wave takes the same path
+        // (other waves' pushes would otherwise be visible to some reads only)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sAlive = c->n_alive;
+            sCur = c->cur;
+            sNF = c->nF[c->cur];
+        }
+        __syncthreads();
+        if (sAlive == 0) break;
+        const int32_t cur = sCur;
+        if (sNF == 0) {
+            // new level: k = max(k, smallest alive degree)
+            const int32_t lc = c->lcur, cnt = c->nlist[lc];
+            const int32_t *in = b.lists + (size_t)lc * b.n;
+            u64 m = ~0ull;
+            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_THREADS) {
+                int32_t v = in[i];
+                if (b.stamp[v] == ALIVE) m = b.deg[v] < m ? b.deg[v] : m;
+            }
+            m = wave_min(m);
+            if (L == 0) sRed[wv] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                u64 mm = ~0ull;
+                for (int i = 0; i < TAIL_WAVES; i++) mm = sRed[i] < mm ? sRed[i] : mm;
+                sK = c->k > mm ? c->k : mm;
+            }
+            __syncthreads();
+            const u64 k = sK;
+            const int32_t r = c->round;
+            int32_t *out = b.lists + (size_t)(lc ^ 1) * b.n;
+            int32_t *F = b.F + (size_t)cur * b.n;
+            const int32_t lim = (cnt + WAVE - 1) / WAVE * WAVE;
+            for (int32_t i = threadIdx.x; i - L < lim; i += TAIL_THREADS) {
+                int32_t v = -1;
+                bool alive = false, take = false;
+                if (i < cnt) {
+                    v = in[i];
+                    alive = b.stamp[v] == ALIVE;
+                    take = alive && b.deg[v] <= k;
+                }
+                if (take) {
+                    b.stamp[v] = r;
+                    b.core[v] = k;
+                }
+                wave_push(take, v, F, &c->nF[cur]);
+                wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) record_level(b, c, k);
+            __syncthreads();
+        }
+        // destroy the cliques through the frontier, one frontier vertex at a time
+        const int32_t nF = c->nF[cur], r = c->round;
+        const u64 k = c->k;
+        const int32_t *F = b.F + (size_t)cur * b.n;
+        u64 destroyed = 0;
+        for (int32_t fi = 0; fi < nF; fi++) {
+            const int32_t v = F[fi];
+            const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+            if constexpr (H == 2) {
+                for (int64_t e = rv0 + threadIdx.x; e < rv1; e += TAIL_THREADS) {
+                    int32_t w = b.col[e];
+                    int32_t st = b.stamp[w];
+                    if (st == r) {
+                        destroyed += (v < w) ? 1 : 0;
+                    } else if (st > r) {
+                        destroyed += 1;
+                        dec_deg(b, w, 1, k, r);
+                    }
+                }
+            } else {
+                destroyed += h3_block_range<TAIL_WAVES>(b, v, rv0, rv1, r, k, sKey, sVal, sPre, sSt, sW, sCnt);
+            }
+        }
+        destroyed = wave_sum(destroyed);
+        if (L == 0) sRed[wv] = destroyed;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 t = 0;
+            for (int i = 0; i < TAIL_WAVES; i++) t += sRed[i];
+            c->destroyed += t;
+            finish_round(c);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- h >= 4
@@ -281,16 +567,12 @@ __global__ __launch_bounds__(BLOCK) void k_process_h3(PeelBufs b, const int64_t 
 // counts the (h-2)-cliques of the sub-DAG on N+(w) ∩ N(v) ∩ allowed.
 struct PeelCtx {
     PeelBufs b;
-    const int64_t *row_ptr;
-    const int32_t *col;
     int cls;
     __device__ __forceinline__ int32_t root(int64_t it) const { return b.item_w[cls * b.item_cap + it]; }
     __device__ __forceinline__ bool accept(int64_t it, int32_t x) const {
         const int32_t v = b.item_v[cls * b.item_cap + it];
-        const int32_t r = b.ctl->round;
-        const int32_t st = b.stamp[x];
-        if (!(st > r || (st == r && x > v))) return false;
-        return bsearch_i32(col, row_ptr[v], row_ptr[v + 1], x) >= 0;
+        if (!allowed(b.stamp[x], b.ctl->round, x, v)) return false;
+        return bsearch_i32(b.col, b.row_ptr[v], b.row_ptr[v + 1], x) >= 0;
     }
     __device__ __forceinline__ void add(int32_t x, u64 cnt) const {
         const int32_t r = b.ctl->round;
@@ -314,8 +596,7 @@ __device__ __forceinline__ int item_class(int d, int R) {
     return 4;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, const int64_t *row_ptr, const int32_t *col,
-                                                      const int64_t *dag_off, int R) {
+__global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, int R) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
     if (nF == 0) return;
@@ -324,14 +605,13 @@ __global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, const int64_t 
     const int wv = threadIdx.x / WAVE;
     for (int64_t fi = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; fi < nF; fi += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[fi];
-        const int64_t e1 = row_ptr[v + 1];
-        for (int64_t e = row_ptr[v]; e < e1; e += WAVE) {
+        const int64_t e1 = b.row_ptr[v + 1];
+        for (int64_t e = b.row_ptr[v]; e < e1; e += WAVE) {
             int cls = -1;
             int32_t w = -1;
             if (e + lane() < e1) {
-                w = col[e + lane()];
-                int32_t st = b.stamp[w];
-                if (st > r || (st == r && w > v)) cls = item_class((int)(row_ptr[w + 1] - dag_off[w]), R);
+                w = b.col[e + lane()];
+                if (allowed(b.stamp[w], r, w, v)) cls = item_class((int)(b.row_ptr[w + 1] - b.dag_off[w]), R);
             }
             for (int q = 0; q < 5; q++) {
                 u64 m = __ballot(cls == q);
@@ -356,6 +636,100 @@ __global__ void k_finish_round(PeelBufs b) {
     finish_round(c);
 }
 
+// ---------------------------------------------------------------- adjacency compaction
+//
+// Between rounds, rows of removed vertices and entries pointing at them are
+// dead weight for every later round.  Compaction rebuilds the CSR over the
+// vertices still taking part (stamp >= current round: alive, or in the
+// pending frontier), keeping each row sorted by rank so that N+(v) is again
+// the tail of row v.  Vertex ids do not change.
+
+// one wave per vertex: kept neighbours, and kept out-neighbours
+__global__ __launch_bounds__(BLOCK) void k_compact_count(PeelBufs b, int64_t *cnt, int32_t *cnt_out) {
+    const int32_t r = b.ctl->round;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < b.n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        int64_t c = 0;
+        int32_t co = 0;
+        if (b.stamp[v] >= r) {
+            for (int64_t e = b.row_ptr[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
+                int32_t w = b.col[e];
+                bool keep = b.stamp[w] >= r;
+                c += keep ? 1 : 0;
+                co += (keep && w > (int32_t)v) ? 1 : 0;
+            }
+        }
+        c = wave_sum(c);
+        co = wave_sum(co);
+        if (lane() == 0) {
+            cnt[v] = c;
+            cnt_out[v] = co;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_compact_fill(PeelBufs b, const int64_t *nrow, const int32_t *cnt_out,
+                                                         int32_t *ncol, int64_t *ndag) {
+    const int32_t r = b.ctl->round;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < b.n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        int64_t o = nrow[v];
+        if (lane() == 0) ndag[v] = nrow[v + 1] - cnt_out[v];
+        if (b.stamp[v] < r) continue;
+        const int64_t e1 = b.row_ptr[v + 1];
+        for (int64_t e = b.row_ptr[v]; e < e1; e += WAVE) {
+            int32_t w = -1;
+            bool keep = false;
+            if (e + lane() < e1) {
+                w = b.col[e + lane()];
+                keep = b.stamp[w] >= r;
+            }
+            u64 m = __ballot(keep);
+            if (keep) ncol[o + __popcll(m & lanemask_lt())] = w;
+            o += __popcll(m);
+        }
+    }
+}
+
+// the pending frontier's chunk items were cut for the old row lengths: redo them
+__global__ void k_reset_chunks(PeelBufs b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.ctl->nB[b.ctl->cur] = 0;
+}
+__global__ void k_rechunk(PeelBufs b) {
+    const int32_t cur = b.ctl->cur, nF = b.ctl->nF[cur];
+    const int32_t *F = b.F + (size_t)cur * b.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nF; i += (int64_t)gridDim.x * blockDim.x)
+        push_chunks(b, F[i], cur);
+}
+
+__global__ void k_last_row(int64_t *nrow, const int64_t *cnt, int32_t n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) nrow[n] = nrow[n - 1] + cnt[n - 1];
+}
+
+// Rebuild b.row_ptr / b.col / b.dag_off over the vertices still taking part.
+static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
+    const int32_t n = b.n;
+    int64_t *cnt = sc.get_n<int64_t>(n);
+    int32_t *cnt_out = sc.get_n<int32_t>(n);
+    int64_t *nrow = sc.get_n<int64_t>((int64_t)n + 1);
+    k_compact_count<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cnt, cnt_out);
+    scan_exclusive_i64(cnt, nrow, n, s, sc);
+    k_last_row<<<1, 1, 0, s>>>(nrow, cnt, n);
+    int64_t total = 0;
+    DSD_HIP(hipMemcpyAsync(&total, nrow + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    int32_t *ncol = sc.get_n<int32_t>(total);
+    int64_t *ndag = sc.get_n<int64_t>(n);
+    k_compact_fill<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, nrow, cnt_out, ncol, ndag);
+    b.row_ptr = nrow;
+    b.col = ncol;
+    b.dag_off = ndag;
+    if (b.h == 3) {
+        k_reset_chunks<<<1, 1, 0, s>>>(b);
+        k_rechunk<<<256, BLOCK, 0, s>>>(b);
+    }
+}
+
 // ---------------------------------------------------------------- host driver
 
 __global__ void k_peel_init(PeelBufs b, const uint8_t *alive0, int32_t *list0, int32_t *count) {
@@ -377,9 +751,8 @@ __global__ void k_set_alive(PeelBufs b) {
 
 template <int R>
 static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t s, u64 *gS) {
-    PeelCtx ctx{b, g.row_ptr, g.col, 0};
+    PeelCtx ctx{b, 0};
     const int32_t *ni = &b.ctl->nitems[0];
-    ctx.cls = 0;
     k_engine_wave<R, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off, 0, ni + 0);
     if constexpr (R <= 2) {
         ctx.cls = 1;
@@ -400,6 +773,12 @@ static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t 
     }
 }
 
+static int64_t tail_threshold(int h) {
+    if (h > 3) return 0;
+    const char *e = getenv("DSD_TAIL_T");
+    return e ? atoll(e) : 16384;
+}
+
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
                 hipStream_t s, Scratch &sc) {
     PeelResult res;
@@ -407,6 +786,10 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     if (n == 0) return res;
     PeelBufs b{};
     b.n = n;
+    b.h = h;
+    b.row_ptr = g.row_ptr;
+    b.col = g.col;
+    b.dag_off = g.dag_off;
     b.ctl = sc.get_n<PeelCtl>(1);
     b.stamp = sc.get_n<int32_t>(n);
     b.deg = deg;
@@ -416,6 +799,11 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.lv_k = sc.get_n<u64>(n + 1);
     b.lv_size = sc.get_n<u64>(n + 1);
     b.lv_mu = sc.get_n<u64>(n + 1);
+    if (h == 3) {
+        // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK
+        b.bcap = (int64_t)n + 2 * g.m / CHUNK + 1;
+        b.B = sc.get_n<int64_t>(2 * b.bcap);
+    }
     const int R = h - 2;
     u64 *gS = nullptr;
     if (h >= 4) {
@@ -431,6 +819,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     init.k = k_floor;
     init.kcand = ~0ull;
     init.mu_alive = mu;
+    init.tail_T = tail_threshold(h);
     DSD_HIP(hipMemcpyAsync(b.ctl, &init, sizeof(PeelCtl), hipMemcpyHostToDevice, s));
     k_peel_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b, alive0, b.lists, &b.ctl->nlist[0]);
     k_set_alive<<<1, 1, 0, s>>>(b);
@@ -442,16 +831,27 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     const int gmin = 1024, gbuild = 1024, gproc = 2048;
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
-    while (n_alive > 0) {
+    const bool compacting = h <= 3;
+    int64_t compacted_at = n;
+    if (compacting && n_alive > 0 && n_alive < n / 2) {
+        compact_adjacency(b, s, sc);
+        compacted_at = n_alive;
+    }
+    while (n_alive > init.tail_T) {
+        if (compacting && n_alive < compacted_at / 2) {
+            compact_adjacency(b, s, sc);
+            compacted_at = n_alive;
+        }
         for (int64_t i = 0; i < chunk; i++) {
             k_level_min<<<gmin, BLOCK, 0, s>>>(b);
             k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
             if (h == 2) {
-                k_process_h2<<<gproc, BLOCK, 0, s>>>(b, g.row_ptr, g.col);
+                k_process_h2<<<gproc, BLOCK, 0, s>>>(b);
             } else if (h == 3) {
-                k_process_h3<<<gproc, BLOCK, 0, s>>>(b, g.row_ptr, g.col, g.dag_off);
+                k_process_h3_small<<<gproc, BLOCK, 0, s>>>(b);
+                k_process_h3_big<<<gproc, BLOCK, 0, s>>>(b);
             } else {
-                k_peel_items<<<gproc, BLOCK, 0, s>>>(b, g.row_ptr, g.col, g.dag_off, R);
+                k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
                     case 2: launch_peel_items<2>(g, b, s, gS); break;
                     case 3: launch_peel_items<3>(g, b, s, gS); break;
@@ -469,12 +869,18 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             (void)hipHostFree(pinned);
             throw Error(-3, "peel did not converge");
         }
-        if (chunk < 64) chunk *= 2;
+        if (chunk < 32) chunk *= 2;
+    }
+    if (n_alive > 0) {
+        if (compacting && n_alive < compacted_at) compact_adjacency(b, s, sc);
+        if (h == 2) k_peel_tail<2><<<1, TAIL_THREADS, 0, s>>>(b);
+        else k_peel_tail<3><<<1, TAIL_THREADS, 0, s>>>(b);
     }
     (void)hipHostFree(pinned);
     PeelCtl fin;
     DSD_HIP(hipMemcpyAsync(&fin, b.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
+    if (fin.n_alive != 0) throw Error(-3, "peel ended with alive vertices");
     res.rounds = fin.round;
     res.levels = fin.nlevels;
     res.level_k.resize(fin.nlevels);
