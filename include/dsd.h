@@ -63,6 +63,13 @@ typedef struct {
     uint64_t flow_calls;         /* min-cut computations of the exact step */
     uint64_t flow_nodes_max;     /* largest flow network built */
     uint64_t located_vertices;   /* vertices handed to the exact step */
+    /* kernel families timed with HIP events on the graph's stream (whole-graph calls only):
+     * k3 = clique-degree engine kernels, k4 = the peel (all of its kernels) */
+    double k3_ms, k4_ms;
+    uint64_t k3_launches, k4_launches;
+    /* graph shape for the algorithmic byte model: n, m, the DAG's directed
+     * 2-paths w2 = sum_v d-(v) d+(v) and s2 = sum_v deg(v) d+(v) */
+    uint64_t n, m, w2, s2;
 } dsd_stats;
 
 /*

@@ -98,10 +98,25 @@ bool rat_gt(u64 a, u64 b, u64 c, u64 d) { return (unsigned __int128)a * d > (uns
 
 u64 ceil_div_u(u64 a, u64 b) { return a / b + (a % b != 0); }
 
+void begin_stats(dsd_graph_s *G) {
+    begin_stats(G);
+    G->stats.n = (uint64_t)G->g.n;
+    G->stats.m = (uint64_t)G->g.m;
+    G->stats.w2 = G->g.w2;
+    G->stats.s2 = G->g.s2;
+}
+
+void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
+    G->stats.k3_ms = kt.k3_ms;
+    G->stats.k4_ms = kt.k4_ms;
+    G->stats.k3_launches = kt.k3_launches;
+    G->stats.k4_launches = kt.k4_launches;
+}
+
 // clique-degrees (rank space) and mu; throws on overflow
-u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg) {
+u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelTimes *kt = nullptr) {
     hipStream_t s = G->stream;
-    if (!clique_degrees(G->g, h, mask, deg, s, G->sc))
+    if (!clique_degrees(G->g, h, mask, deg, s, G->sc, kt))
         throw Error(DSD_EOVERFLOW, "clique counts could exceed 64 bits");
     u64 *sum = G->sc.get_n<u64>(2);
     sum_u64_128(deg, G->g.n, sum, s, G->sc);
@@ -180,7 +195,7 @@ dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const
         float t = 0;
         Timer tm(s);
         build_graph(n, num_pairs, ds, dd, G->g, s, G->sc, &t);
-        G->stats = dsd_stats{};
+        begin_stats(G);
         G->stats.t_total_ms = tm.stop();
         G->stats.t_orient_ms = t;
         G->sc.reset();
@@ -217,11 +232,13 @@ dsd_status dsd_clique_degrees(dsd_graph G, int h, int out_mem, uint64_t *deg, ui
         check_h(h);
         if (G->g.n > 0) check_out(deg, out_mem);
         G->sc.reset();
-        G->stats = dsd_stats{};
+        begin_stats(G);
         Timer tm(G->stream);
         u64 *d = G->sc.get_n<u64>(G->g.n);
-        u64 mu = degrees_and_mu(G, h, nullptr, d);
+        KernelTimes kt;
+        u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);
         G->stats.t_enum_ms = tm.stop();
+        end_stats(G, kt);
         write_u64(G, d, deg, out_mem);
         if (num_cliques) *num_cliques = mu;
         G->stats.num_cliques = mu;
@@ -236,16 +253,18 @@ dsd_status dsd_clique_core(dsd_graph G, int h, int out_mem, uint64_t *core, uint
         check_h(h);
         if (G->g.n > 0) check_out(core, out_mem);
         G->sc.reset();
-        G->stats = dsd_stats{};
+        begin_stats(G);
         hipStream_t s = G->stream;
         Timer tm(s);
         const int32_t n = G->g.n;
         u64 *d = G->sc.get_n<u64>(n), *c = G->sc.get_n<u64>(n);
-        u64 mu = degrees_and_mu(G, h, nullptr, d);
+        KernelTimes kt;
+        u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);
         G->stats.t_enum_ms = tm.stop();
         Timer tp(s);
-        PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, c, s, G->sc);
+        PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, c, s, G->sc, &kt);
         G->stats.t_peel_ms = tp.stop();
+        end_stats(G, kt);
         write_u64(G, c, core, out_mem);
         if (kmax) *kmax = pr.kmax;
         G->stats.num_cliques = mu;
@@ -292,7 +311,7 @@ dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64
         const int32_t n = G->g.n;
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
-        G->stats = dsd_stats{};
+        begin_stats(G);
         hipStream_t s = G->stream;
         Timer tm(s);
         u64 kmax = 0, best_mu = 0, best_size = 0;
@@ -370,20 +389,22 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
         const int32_t n = G->g.n;
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
-        G->stats = dsd_stats{};
+        begin_stats(G);
         hipStream_t s = G->stream;
         Timer tm(s);
         uint8_t *res = G->sc.get_n<uint8_t>(n);
         fill_u8(res, 0, n, s);
         dsd_rational rho{0, 1};
         u64 *d = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
-        u64 mu = n > 0 ? degrees_and_mu(G, h, nullptr, d) : 0;
+        KernelTimes kt;
+        u64 mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &kt) : 0;
         G->stats.t_enum_ms = tm.stop();
         G->stats.num_cliques = mu;
         if (mu > 0) {
             Timer tp(s);
-            PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, core, s, G->sc);
+            PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, core, s, G->sc, &kt);
             G->stats.t_peel_ms = tp.stop();
+            end_stats(G, kt);
             G->stats.peel_rounds = pr.rounds;
             G->stats.peel_levels = pr.levels;
             Timer tl(s);

@@ -118,6 +118,21 @@ __global__ void k_dag_off(const int64_t *row_ptr, const int32_t *col, int32_t n,
     }
 }
 
+__global__ void k_wedges(const int64_t *row_ptr, const int64_t *dag_off, int32_t n, u64 *out) {
+    u64 w2 = 0, s2 = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        u64 din = (u64)(dag_off[v] - row_ptr[v]), dout = (u64)(row_ptr[v + 1] - dag_off[v]);
+        w2 += din * dout;
+        s2 += (din + dout) * dout;
+    }
+    w2 = wave_sum(w2);
+    s2 = wave_sum(s2);
+    if (lane() == 0) {
+        atomicAdd(&out[0], w2);
+        atomicAdd(&out[1], s2);
+    }
+}
+
 void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, DevGraph &g, hipStream_t s,
                  Scratch &sc, float *t_orient_ms) {
     g.n = n;
@@ -181,9 +196,16 @@ void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, D
     k_csr_from_keys<<<grid_for(E + 1, BLOCK, 8192), BLOCK, 0, s>>>(k3, E, n, bits, g.col, g.row_ptr);
     if (n > 0) k_dag_off<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, n, g.dag_off, maxes);
     DSD_HIP(hipEventRecord(e1, s));
+    u64 *wed = sc.get_n<u64>(2);
+    fill_u64(wed, 0, 2, s);
+    if (n > 0) k_wedges<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(g.row_ptr, g.dag_off, n, wed);
     int32_t hm[2] = {0, 0};
+    u64 hw[2] = {0, 0};
     DSD_HIP(hipMemcpyAsync(hm, maxes, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(hw, wed, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
+    g.w2 = hw[0];
+    g.s2 = hw[1];
     g.maxdeg = hm[0];
     g.maxdout = hm[1];
     if (t_orient_ms) DSD_HIP(hipEventElapsedTime(t_orient_ms, e0, e1));

@@ -138,7 +138,8 @@ static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t 
     }
 }
 
-bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc) {
+bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
+                    KernelTimes *kt) {
     const int32_t n = g.n;
     if (n == 0) return true;
     if (h == 2) {
@@ -169,12 +170,28 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
     DSD_HIP(hipMemsetAsync(cursor, 0, NCLASS * sizeof(int32_t), s));
     k_classify<<<blocks, BLOCK, 0, s>>>(g.row_ptr, g.dag_off, mask, n, R, 1, cursor, lists, d_off, bound);
     EnumCtx ctx{nullptr, mask, deg};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt) {
+        DSD_HIP(hipEventCreate(&e0));
+        DSD_HIP(hipEventCreate(&e1));
+        DSD_HIP(hipEventRecord(e0, s));
+    }
     switch (R) {
         case 2: launch_engine<2>(g, ctx, lists, off, hc, s, sc); break;
         case 3: launch_engine<3>(g, ctx, lists, off, hc, s, sc); break;
         case 4: launch_engine<4>(g, ctx, lists, off, hc, s, sc); break;
         case 5: launch_engine<5>(g, ctx, lists, off, hc, s, sc); break;
         default: throw Error(-1, "h outside [2, 6]");
+    }
+    if (kt) {
+        DSD_HIP(hipEventRecord(e1, s));
+        DSD_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+        kt->k3_ms += ms;
+        for (int c = 0; c < NCLASS; c++) kt->k3_launches += hc[c] ? 1 : 0;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
     }
     // the host copy of `off` must outlive the async H2D copy above
     DSD_HIP(hipStreamSynchronize(s));

@@ -23,6 +23,14 @@ struct DevGraph {
     int32_t *orig_of = nullptr;  // [n] rank -> caller id
     int32_t *rank_of = nullptr;  // [n] caller id -> rank
     int32_t maxdeg = 0, maxdout = 0;
+    u64 w2 = 0;   // sum_v d-(v) d+(v): directed 2-paths of the DAG (pairs the enumeration probes)
+    u64 s2 = 0;   // sum_v deg(v) d+(v): out-list entries the peel probes over all removed vertices
+};
+
+// HIP-event timing of the two kernel families, accumulated per call
+struct KernelTimes {
+    double k3_ms = 0, k4_ms = 0;
+    u64 k3_launches = 0, k4_launches = 0;
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----
@@ -36,7 +44,8 @@ void free_graph(DevGraph &g);
 // deg[r] (rank space, length n) = number of h-cliques containing r inside the
 // subgraph induced by mask (mask == nullptr: whole graph).  deg is
 // overwritten.  Returns false if the counts could overflow 64 bits.
-bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc);
+bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
+                    KernelTimes *kt = nullptr);
 
 // ---- K4: round-synchronous peel ----
 struct PeelResult {
@@ -50,7 +59,7 @@ struct PeelResult {
 // k_floor: every vertex of degree <= k_floor goes in the first level (CoreApp
 // starts its peel there); 0 for a full decomposition.  core: rank space.
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc);
+                hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr);
 
 // ---- K5: connected components of the subgraph induced by mask ----
 // label[r] = smallest rank of r's component for r in mask, -1 outside.

@@ -780,7 +780,7 @@ static int64_t tail_threshold(int h) {
 }
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc) {
+                hipStream_t s, Scratch &sc, KernelTimes *kt) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
@@ -828,6 +828,12 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     int64_t n_alive = pinned[0];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt) {
+        DSD_HIP(hipEventCreate(&e0));
+        DSD_HIP(hipEventCreate(&e1));
+        DSD_HIP(hipEventRecord(e0, s));
+    }
     const int gmin = 1024, gbuild = 1024, gproc = 2048;
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
@@ -877,6 +883,16 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         else k_peel_tail<3><<<1, TAIL_THREADS, 0, s>>>(b);
     }
     (void)hipHostFree(pinned);
+    if (kt) {
+        DSD_HIP(hipEventRecord(e1, s));
+        DSD_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+        kt->k4_ms += ms;
+        kt->k4_launches += 1;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
     PeelCtl fin;
     DSD_HIP(hipMemcpyAsync(&fin, b.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));

@@ -44,7 +44,10 @@ class Stats(C.Structure):
                 ("t_locate_ms", C.c_double), ("t_exact_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("num_cliques", C.c_uint64), ("peel_rounds", C.c_uint64), ("peel_levels", C.c_uint64),
                 ("flow_calls", C.c_uint64), ("flow_nodes_max", C.c_uint64),
-                ("located_vertices", C.c_uint64)]
+                ("located_vertices", C.c_uint64),
+                ("k3_ms", C.c_double), ("k4_ms", C.c_double),
+                ("k3_launches", C.c_uint64), ("k4_launches", C.c_uint64),
+                ("n", C.c_uint64), ("m", C.c_uint64), ("w2", C.c_uint64), ("s2", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
