@@ -61,7 +61,7 @@ def k4_bytes(st: dict, h: int) -> float:
 
 def cpu_baseline(workload: str, seed: int):
     """The CPU oracle, single-threaded, on a bounded sample of the same
-    workload.  Chung-Lu: the same generator at n = 300,000 (same degree law
+    workload.  Chung-Lu: the same generator at n = 600,000 (same degree law
     and planted blocks), clique-degrees + core decomposition + CoreApp; the
     oracle's exact step (Dinic on 128-bit capacities over the whole located
     core) alone runs for many minutes on this graph family, so it is left out
@@ -74,7 +74,7 @@ def cpu_baseline(workload: str, seed: int):
         n, s, d = synth.er_planted(seed=seed, **w["kw"])
         stages = "clique-degrees + core decomposition + CoreApp + CoreExact"
     else:
-        kw = dict(w["kw"], n=300_000)
+        kw = dict(w["kw"], n=600_000)
         n, s, d = synth.chung_lu(seed=seed, **kw)
         stages = "clique-degrees + core decomposition + CoreApp"
     g = oracle.Graph(n, s, d)

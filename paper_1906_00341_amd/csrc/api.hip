@@ -99,7 +99,7 @@ bool rat_gt(u64 a, u64 b, u64 c, u64 d) { return (unsigned __int128)a * d > (uns
 u64 ceil_div_u(u64 a, u64 b) { return a / b + (a % b != 0); }
 
 void begin_stats(dsd_graph_s *G) {
-    begin_stats(G);
+    G->stats = dsd_stats{};
     G->stats.n = (uint64_t)G->g.n;
     G->stats.m = (uint64_t)G->g.m;
     G->stats.w2 = G->g.w2;
