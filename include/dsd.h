@@ -70,6 +70,8 @@ typedef struct {
     /* graph shape for the algorithmic byte model: n, m, the DAG's directed
      * 2-paths w2 = sum_v d-(v) d+(v) and s2 = sum_v deg(v) d+(v) */
     uint64_t n, m, w2, s2;
+    /* host exact step: network construction and maximum-flow time */
+    double t_flow_build_ms, t_flow_ms;
 } dsd_stats;
 
 /*
@@ -127,7 +129,10 @@ dsd_status dsd_core_app(dsd_graph g, int h, int out_mem, uint8_t *member, uint64
 dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
                           dsd_rational *rho_opt);
 
-/* Statistics of the last compute call on g. */
+/* Statistics of the last compute call on g.  A handle keeps the core
+ * decomposition of every h it has computed, so dsd_clique_core and
+ * dsd_core_exact reuse it (their enumeration and peel figures then repeat
+ * those of the call that computed it). */
 dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out);
 
 /* Human-readable name of a status; never NULL. */

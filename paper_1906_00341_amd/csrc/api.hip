@@ -16,12 +16,27 @@
 
 using namespace dsd;
 
+// A full (k, Psi)-core decomposition, kept on the handle: the graph never
+// changes, so later calls with the same h reuse it.
+struct Decomp {
+    bool valid = false;
+    u64 mu = 0;
+    u64 *core = nullptr;            // device, rank space, length n
+    PeelResult levels;              // level table
+    double t_enum_ms = 0, t_peel_ms = 0;
+    KernelTimes kt;
+};
+
 struct dsd_graph_s {
     DevGraph g;
     hipStream_t stream = nullptr;
     Scratch sc;
     dsd_stats stats{};
-    ~dsd_graph_s() { free_graph(g); }
+    Decomp dec[7];                  // by h
+    ~dsd_graph_s() {
+        for (Decomp &d : dec) (void)hipFree(d.core);
+        free_graph(g);
+    }
 };
 
 static thread_local std::string g_err;
@@ -126,6 +141,42 @@ u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelT
     if (hs[1] != 0) throw Error(DSD_EOVERFLOW, "sum of clique-degrees exceeds 64 bits");
     if (hs[0] % (u64)h != 0) throw Error(DSD_EDEVICE, "clique-degree sum not divisible by h");
     return hs[0] / (u64)h;
+}
+
+// The decomposition for h, computed once per handle (Algorithm 3 via the
+// round-synchronous peel).
+const Decomp &decompose(dsd_graph_s *G, int h) {
+    Decomp &D = G->dec[h];
+    if (D.valid) return D;
+    hipStream_t s = G->stream;
+    const int32_t n = G->g.n;
+    if (!D.core) {
+        if (hipMalloc(&D.core, (size_t)(n > 0 ? n : 1) * sizeof(u64)) != hipSuccess)
+            throw Error(DSD_ENOMEM, "device allocation of core numbers failed");
+    }
+    D.kt = KernelTimes();
+    Timer te(s);
+    u64 *d = G->sc.get_n<u64>(n);
+    D.mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &D.kt) : 0;
+    D.t_enum_ms = te.stop();
+    Timer tp(s);
+    D.levels = PeelResult();
+    if (n > 0) {
+        if (D.mu > 0) D.levels = peel(G->g, h, nullptr, d, D.mu, 0, D.core, s, G->sc, &D.kt);
+        else fill_u64(D.core, 0, n, s);
+    }
+    D.t_peel_ms = tp.stop();
+    D.valid = true;
+    return D;
+}
+
+void decomp_stats(dsd_graph_s *G, const Decomp &D) {
+    G->stats.t_enum_ms = D.t_enum_ms;
+    G->stats.t_peel_ms = D.t_peel_ms;
+    G->stats.num_cliques = D.mu;
+    G->stats.peel_rounds = D.levels.rounds;
+    G->stats.peel_levels = D.levels.levels;
+    end_stats(G, D.kt);
 }
 
 template <typename T>
@@ -254,28 +305,17 @@ dsd_status dsd_clique_core(dsd_graph G, int h, int out_mem, uint64_t *core, uint
         if (G->g.n > 0) check_out(core, out_mem);
         G->sc.reset();
         begin_stats(G);
-        hipStream_t s = G->stream;
-        Timer tm(s);
-        const int32_t n = G->g.n;
-        u64 *d = G->sc.get_n<u64>(n), *c = G->sc.get_n<u64>(n);
-        KernelTimes kt;
-        u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);
-        G->stats.t_enum_ms = tm.stop();
-        Timer tp(s);
-        PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, c, s, G->sc, &kt);
-        G->stats.t_peel_ms = tp.stop();
-        end_stats(G, kt);
-        write_u64(G, c, core, out_mem);
-        if (kmax) *kmax = pr.kmax;
-        G->stats.num_cliques = mu;
-        G->stats.peel_rounds = pr.rounds;
-        G->stats.peel_levels = pr.levels;
+        Timer tm(G->stream);
+        const Decomp &D = decompose(G, h);
+        decomp_stats(G, D);
+        write_u64(G, D.core, core, out_mem);
+        if (kmax) *kmax = D.levels.kmax;
         G->stats.t_total_ms = tm.stop();
         return DSD_OK;
     })
 }
 
-// C(x, r) saturating at 2^64 - 1
+// C(x, r), saturating at 2^64 - 1
 static u64 binom_sat(u64 x, int r) {
     if ((u64)r > x) return 0;
     unsigned __int128 acc = 1;
@@ -392,28 +432,24 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
         begin_stats(G);
         hipStream_t s = G->stream;
         Timer tm(s);
+        const Decomp &D = decompose(G, h);
+        decomp_stats(G, D);
         uint8_t *res = G->sc.get_n<uint8_t>(n);
         fill_u8(res, 0, n, s);
         dsd_rational rho{0, 1};
-        u64 *d = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
-        KernelTimes kt;
-        u64 mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &kt) : 0;
-        G->stats.t_enum_ms = tm.stop();
-        G->stats.num_cliques = mu;
+        const u64 mu = D.mu;
+        u64 *core = D.core;
         if (mu > 0) {
-            Timer tp(s);
-            PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, core, s, G->sc, &kt);
-            G->stats.t_peel_ms = tp.stop();
-            end_stats(G, kt);
-            G->stats.peel_rounds = pr.rounds;
-            G->stats.peel_levels = pr.levels;
+            const PeelResult &pr = D.levels;
             Timer tl(s);
             // Pruning1: rho' = max over levels of mu(R_k) / |R_k|
             u64 a = 0, b = 1;
+            int64_t best_level = -1;
             for (int64_t i = 0; i < pr.levels; i++)
                 if (pr.level_size[i] > 0 && rat_gt(pr.level_mu[i], pr.level_size[i], a, b)) {
                     a = pr.level_mu[i];
                     b = pr.level_size[i];
+                    best_level = i;
                 }
             const u64 k1 = ceil_div_u(a, b);
             // Pruning2: components of R_{k'} and their densities
@@ -436,9 +472,15 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
                 }
             dsd_rational r2 = make_rational(rn, rd);
             const u64 k2 = std::max(k1, ceil_div_u(r2.num, r2.den));
-            // D starts as the component attaining rho''
-            if (best_root >= 0) mask_label_equal(lab1, n, best_root, res, s);
-            rho = r2;
+            // D starts as the better of the level set attaining rho' and the
+            // component attaining rho''; both densities are lower bounds on rho_opt
+            if (rat_gt(a, b, r2.num, r2.den) && best_level >= 0) {
+                mask_core_at_least(core, n, pr.level_k[best_level], res, s);
+                rho = make_rational(a, b);
+            } else {
+                if (best_root >= 0) mask_label_equal(lab1, n, best_root, res, s);
+                rho = r2;
+            }
             // components of R_{k''} go to the host
             uint8_t *m2 = m1;
             int32_t *lab2 = lab1;
@@ -461,6 +503,8 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             G->stats.flow_calls = es.flow_calls;
             G->stats.flow_nodes_max = es.max_nodes;
+            G->stats.t_flow_build_ms = es.build_ms;
+            G->stats.t_flow_ms = es.flow_ms;
             if (improved) {
                 rho = dsd_rational{l.num, l.den};
                 std::vector<uint8_t> hm(n, 0);

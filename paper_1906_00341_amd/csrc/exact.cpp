@@ -24,6 +24,7 @@
 #include "exact.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -41,6 +42,10 @@ static const int64_t CAP_LIMIT = (int64_t)1 << 62;
 class PushRelabel {
 public:
     explicit PushRelabel(int n) : n_(n) {}
+    void reserve(int64_t arcs) {
+        eu_.reserve(arcs);
+        ev_.reserve(arcs);
+    }
     int arc(int u, int v) {   // capacities are set per test
         eu_.push_back(u);
         ev_.push_back(v);
@@ -308,6 +313,8 @@ public:
                 }
             }
             mu_ = m_;
+        } else if (h == 3) {
+            build_triangle_net(verts);
         } else {
             // h-cliques, and the (h-1)-cliques they contain, as sorted tuples
             const int r = h - 1;
@@ -358,6 +365,79 @@ public:
         }
         net_->build();
     }
+    // h = 3: psi ranges over the edges of the vertex set (an edge is the
+    // 2-clique left when one vertex of a triangle is taken away).  Triangles
+    // i < j < k come from merging the forward parts of rows i and j; the
+    // merge yields the positions, and hence the edge ids, of (i,k) and (j,k).
+    void build_triangle_net(const std::vector<int32_t> &verts) {
+        const int nv = (int)verts.size();
+        std::vector<int64_t> so(nv + 1, 0);
+        std::vector<int32_t> sa;
+        for (int i = 0; i < nv; i++) {
+            int32_t v = verts[i];
+            for (int64_t e = lc_.off[v]; e < lc_.off[v + 1]; e++)
+                if (in_[lc_.adj[e]]) sa.push_back(idx_[lc_.adj[e]]);   // idx_ is increasing: rows stay sorted
+            so[i + 1] = (int64_t)sa.size();
+        }
+        std::vector<int64_t> fwd(nv);
+        std::vector<int32_t> eid(sa.size(), -1);
+        int64_t npsi = 0;
+        for (int i = 0; i < nv; i++) {
+            int64_t a = so[i];
+            while (a < so[i + 1] && sa[a] < i) a++;
+            fwd[i] = a;
+            for (int64_t e = a; e < so[i + 1]; e++) eid[e] = (int32_t)npsi++;
+        }
+        const int64_t base = 2 + nv;
+        if (base + npsi > 0x7fffffff) throw Error(-5, "flow network too large");
+        // count triangles first so that the arc arrays are sized once
+        uint64_t tri = 0;
+        for (int i = 0; i < nv; i++)
+            for (int64_t a = fwd[i]; a < so[i + 1]; a++) {
+                int j = sa[a];
+                int64_t p = a + 1, q = fwd[j];
+                while (p < so[i + 1] && q < so[j + 1]) {
+                    if (sa[p] < sa[q]) p++;
+                    else if (sa[p] > sa[q]) q++;
+                    else { tri++; p++; q++; }
+                }
+            }
+        mu_ = tri;
+        net_ = new PushRelabel((int)(base + npsi));
+        net_->reserve(2 * (int64_t)nv + 2 * npsi + 3 * (int64_t)tri);
+        for (int i = 0; i < nv; i++) {
+            src_.push_back(net_->arc(0, 2 + i));
+            snk_.push_back(net_->arc(2 + i, 1));
+        }
+        inf_.reserve(2 * npsi);
+        for (int i = 0; i < nv; i++)
+            for (int64_t a = fwd[i]; a < so[i + 1]; a++) {
+                inf_.push_back(net_->arc((int)(base + eid[a]), 2 + i));
+                inf_.push_back(net_->arc((int)(base + eid[a]), 2 + sa[a]));
+            }
+        mid_.reserve(3 * tri);
+        for (int i = 0; i < nv; i++)
+            for (int64_t a = fwd[i]; a < so[i + 1]; a++) {
+                const int j = sa[a];
+                int64_t p = a + 1, q = fwd[j];
+                while (p < so[i + 1] && q < so[j + 1]) {
+                    if (sa[p] < sa[q]) p++;
+                    else if (sa[p] > sa[q]) q++;
+                    else {
+                        const int k = sa[p];
+                        mid_.push_back(net_->arc(2 + i, (int)(base + eid[q])));   // i with edge (j, k)
+                        mid_.push_back(net_->arc(2 + j, (int)(base + eid[p])));   // j with edge (i, k)
+                        mid_.push_back(net_->arc(2 + k, (int)(base + eid[a])));   // k with edge (i, j)
+                        deg_[i]++;
+                        deg_[j]++;
+                        deg_[k]++;
+                        p++;
+                        q++;
+                    }
+                }
+            }
+    }
+
     ~CompNet() { delete net_; }
     CompNet(const CompNet &) = delete;
     CompNet &operator=(const CompNet &) = delete;
@@ -454,13 +534,19 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             for (int32_t v : c.v)
                 if (lc.core[v] >= floor_k) cur.push_back(v);
             if (cur.size() < 2) break;
+            auto t0 = std::chrono::steady_clock::now();
             if (!net || cur != built) {
                 net.reset(new CompNet(lc, h, cur));
                 built = cur;
             }
+            auto t1 = std::chrono::steady_clock::now();
             st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
             st.flow_calls++;
-            if (!net->denser_than(lc_l.num, lc_l.den, found)) break;
+            bool denser = net->denser_than(lc_l.num, lc_l.den, found);
+            auto t2 = std::chrono::steady_clock::now();
+            st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+            st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+            if (!denser) break;
             U = found;
             lc_l = reduced(count_cliques_host(lc, h, U), U.size());
         }
