@@ -42,7 +42,8 @@ typedef enum {
     DSD_ENOMEM = -2,     /* device or host allocation failed */
     DSD_EDEVICE = -3,    /* HIP runtime error or no GPU */
     DSD_EOVERFLOW = -4,  /* a count or a scaled flow capacity would overflow 64 bits */
-    DSD_EUNSUPPORTED = -5 /* graph shape beyond a documented kernel limit */
+    DSD_EUNSUPPORTED = -5 /* graph shape beyond a documented limit: an out-neighbourhood above 1280
+                             vertices for h >= 4, or an exact-step component above 10^8 h-cliques */
 } dsd_status;
 
 enum { DSD_MEM_HOST = 0, DSD_MEM_DEVICE = 1 };
@@ -125,6 +126,8 @@ dsd_status dsd_core_app(dsd_graph g, int h, int out_mem, uint8_t *member, uint64
  * h = 2) runs on the host over those components only.  member[v] = 1 for the
  * vertices of one densest subgraph; rho_opt its exact density.
  * member: length n bytes, residency out_mem.  rho_opt may be NULL.
+ * DSD_EUNSUPPORTED when a located component holds more than 10^8 h-cliques
+ * (its network, about h arcs per clique, would not fit the host step).
  */
 dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
                           dsd_rational *rho_opt);

@@ -36,6 +36,9 @@ namespace dsd {
 
 typedef __int128 i128;
 static const int64_t CAP_LIMIT = (int64_t)1 << 62;
+// Every network is built over a subset of one component, so bounding the
+// h-cliques of each component bounds every network (about h arcs per clique).
+static const uint64_t MAX_HOST_CLIQUES = 100000000ull;
 
 // ---------------------------------------------------------------- push-relabel
 
@@ -267,7 +270,11 @@ uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int3
     std::vector<char> in(lc.rank.size(), 0);
     for (int32_t v : verts) in[v] = 1;
     uint64_t c = 0;
-    list_cliques(lc, in, h, [&](const int32_t *) { c++; });
+    list_cliques(lc, in, h, [&](const int32_t *) {
+        if (++c > MAX_HOST_CLIQUES)
+            throw Error(-5, "a located component holds more than 1e8 h-cliques: its flow network is beyond "
+                            "the host exact step's limit");
+    });
     return c;
 }
 

@@ -44,6 +44,22 @@ def complete_graph(n: int) -> tuple[int, np.ndarray, np.ndarray]:
     return int(n), iu.astype(np.int32), ju.astype(np.int32)
 
 
+def complete_multipartite(parts, seed: int = 0) -> tuple[int, np.ndarray, np.ndarray]:
+    """Complete multipartite graph with the given part sizes: every pair of
+    vertices in different parts is an edge.  Vertex ids are a seeded random
+    permutation, so parts are not contiguous id ranges.  Returns the edge
+    list and, as a fourth value, the part index of every vertex."""
+    sizes = [int(a) for a in parts]
+    n = sum(sizes)
+    part = np.repeat(np.arange(len(sizes)), sizes)
+    perm = np.random.default_rng(seed).permutation(n)
+    part_of = np.empty(n, dtype=np.int64)
+    part_of[perm] = part
+    iu, ju = np.triu_indices(n, 1)
+    keep = part_of[iu] != part_of[ju]
+    return int(n), iu[keep].astype(np.int32), ju[keep].astype(np.int32), part_of
+
+
 def plant_block(rng: np.random.Generator, n: int, size: int, p: float,
                 exclude: np.ndarray | None = None):
     """Pick ``size`` distinct vertex ids (avoiding ``exclude``) and keep each of

@@ -88,3 +88,36 @@ def densest(n, edges, h):
 def random_graph(n, p, seed):
     rng = np.random.default_rng(seed)
     return [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
+
+
+def elementary_symmetric(values, r):
+    """e_r(values): the sum, over all r-element subsets, of their products."""
+    e = [1] + [0] * r
+    for a in values:
+        for j in range(r, 0, -1):
+            e[j] += e[j - 1] * a
+    return e[r]
+
+
+def multipartite_closed_form(parts, h):
+    """Clique-degrees and clique-core numbers, per part, of the complete
+    multipartite graph with the given part sizes.
+
+    An h-clique takes one vertex from each of h distinct parts, so a vertex of
+    part i lies in e_{h-1}(a_j : j != i) of them.  The vertices of a part are
+    alike and pairwise non-adjacent, so a peel removes a part whole: the part
+    of least remaining clique-degree (the largest part left) goes at level
+    k = max(k, its degree), and every part whose degree then drops to k or
+    below follows at the same level."""
+    p = len(parts)
+    deg = [elementary_symmetric([parts[j] for j in range(p) if j != i], h - 1) for i in range(p)]
+    core = [0] * p
+    alive = set(range(p))
+    k = 0
+    while alive:
+        cur = {i: elementary_symmetric([parts[j] for j in alive if j != i], h - 1) for i in alive}
+        k = max(k, min(cur.values()))
+        for i in [i for i in alive if cur[i] <= k]:
+            core[i] = k
+            alive.remove(i)
+    return deg, core

@@ -1,0 +1,66 @@
+"""Parity at the benchmark's full size, in the configuration bench.py times.
+
+Chung-Lu, n = 10^6, average degree 20, exponent 2.1, five planted 200-vertex
+blocks at pair probability 0.7, h = 3: clique-degrees, core numbers and the
+k_max-core are compared with the CPU oracle element by element over the whole
+graph.  The oracle's exact step (Dinic on 128-bit capacities) would take many
+minutes here, so CoreExact's answer is checked by properties that hold for
+every densest subgraph: its density is the returned rho_opt (counted by the
+oracle), it lies in the ceil(rho_opt)-core (Lemma 7), and rho_opt lies between
+the density of the k_max-core and k_max (Lemma 8 and Theorem 1).
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import dsd, synth
+
+pytestmark = pytest.mark.gpu
+
+CHUNG_LU_1E6 = dict(n=1_000_000, avg_deg=20.0, beta=2.1, planted=5, plant_size=200, p=0.7)
+
+
+def induced_mu(og, h, mask):
+    off, adj = og.adjacency()
+    rows = np.repeat(np.arange(og.n), np.diff(off))
+    e = mask[rows] & mask[adj] & (rows < adj)
+    sub = oracle.Graph(og.n, rows[e].astype(np.int32), adj[e].astype(np.int32))
+    return sub.clique_degrees(h)[1]
+
+
+@pytest.mark.timeout(600)
+def test_chung_lu_1e6_triangles_whole_graph():
+    torch = pytest.importorskip("torch")
+    h = 3
+    n, s, d = synth.chung_lu(seed=1, **CHUNG_LU_1E6)
+    # the library reads the edge list from device memory, as the benchmark does
+    g = dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    deg_g, mu_g = dsd.clique_degrees(g, h)
+    core_g, km_g = dsd.clique_core(g, h)
+    mem_app, km_app, dens_app = dsd.core_app(g, h)
+    mem_x, rho = dsd.core_exact(g, h)
+    print(f"gpu: mu={mu_g} kmax={km_g} rho_app={dens_app} rho_opt={rho}", flush=True)
+
+    og = oracle.Graph(n, s, d)
+    deg_o, mu_o = og.clique_degrees(h)
+    assert mu_g == mu_o
+    np.testing.assert_array_equal(deg_g, deg_o)
+    core_o, km_o = og.core_decomposition(h)
+    assert km_g == km_o
+    np.testing.assert_array_equal(core_g, core_o)
+
+    top = core_o == km_o
+    assert km_app == km_o
+    np.testing.assert_array_equal(mem_app.astype(bool), top)
+    assert dens_app == Fraction(induced_mu(og, h, top), int(top.sum()))
+
+    sel = mem_x.astype(bool)
+    assert sel.any()
+    assert Fraction(induced_mu(og, h, sel), int(sel.sum())) == rho
+    assert (core_o[sel] >= math.ceil(rho)).all()
+    assert dens_app <= rho <= km_o

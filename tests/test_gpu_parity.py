@@ -146,6 +146,80 @@ def test_complete_graph(h):
     assert rho == Fraction(math.comb(40, h), 40) and mem.all()
 
 
+@pytest.mark.parametrize("n,h", [(300, 4), (800, 4), (1281, 4), (300, 5), (100, 6)])
+def test_complete_graph_wide_neighbourhoods(n, h):
+    # out-neighbourhoods up to n - 1 vertices: every bitmap class of the
+    # engine, up to its 1280-vertex limit
+    _, s, d = synth.complete_graph(n)
+    g = dsd.build_csr(n, s, d)
+    deg, mu = dsd.clique_degrees(g, h)
+    assert mu == math.comb(n, h) and (deg == math.comb(n - 1, h - 1)).all()
+    core, km = dsd.clique_core(g, h)
+    assert km == math.comb(n - 1, h - 1) and (core == km).all()
+    mem, km2, dens = dsd.core_app(g, h)
+    assert km2 == km and mem.all() and dens == Fraction(math.comb(n, h), n)
+
+
+def test_out_degree_limit():
+    n, s, d = synth.complete_graph(1282)
+    g = dsd.build_csr(n, s, d)
+    with pytest.raises(dsd.DsdError) as e:
+        dsd.clique_degrees(g, 4)
+    assert e.value.status == -5
+    deg, mu = dsd.clique_degrees(g, 3)      # h <= 3 has no such limit
+    assert mu == math.comb(1282, 3) and (deg == math.comb(1281, 2)).all()
+
+
+@pytest.mark.parametrize("parts,hs", [([400, 300, 250, 200, 100], (2, 3, 4)),
+                                      ([40, 30, 30, 20, 10, 5], (5, 6)),
+                                      ([600, 90, 90, 80], (3, 4))])
+def test_complete_multipartite(parts, hs):
+    from tests import brute
+    n, s, d, part = synth.complete_multipartite(parts, seed=len(parts))
+    g = dsd.build_csr(n, s, d)
+    for h in hs:
+        deg, core = brute.multipartite_closed_form(parts, h)
+        got, mu = dsd.clique_degrees(g, h)
+        assert mu == brute.elementary_symmetric(parts, h)
+        np.testing.assert_array_equal(got, np.asarray(deg, np.uint64)[part])
+        got, km = dsd.clique_core(g, h)
+        assert km == max(core)
+        np.testing.assert_array_equal(got, np.asarray(core, np.uint64)[part])
+        top = [i for i in range(len(parts)) if core[i] == km]
+        mem, km2, dens = dsd.core_app(g, h)
+        assert km2 == km
+        np.testing.assert_array_equal(mem.astype(bool), np.isin(part, top))
+        assert dens == Fraction(brute.elementary_symmetric([parts[i] for i in top], h),
+                                sum(parts[i] for i in top))
+
+
+@pytest.mark.parametrize("h", [3, 4])
+def test_union_of_complete_graphs(h):
+    # one core level per clique size, out-neighbourhoods up to 1280 vertices
+    sizes = [1281, 900, 500, 300, 70, 5]
+    src, dst, size_of, base = [], [], [], 0
+    for a in sizes:
+        _, s, d = synth.complete_graph(a)
+        src.append(s + base)
+        dst.append(d + base)
+        size_of += [a] * a
+        base += a
+    perm = np.random.default_rng(7).permutation(base).astype(np.int32)
+    s, d = perm[np.concatenate(src)], perm[np.concatenate(dst)]
+    size_of = np.asarray(size_of)[np.argsort(perm)]
+    g = dsd.build_csr(base, s, d)
+    want = np.array([math.comb(a - 1, h - 1) for a in size_of], np.uint64)
+    deg, mu = dsd.clique_degrees(g, h)
+    assert mu == sum(math.comb(a, h) for a in sizes)
+    np.testing.assert_array_equal(deg, want)
+    core, km = dsd.clique_core(g, h)
+    np.testing.assert_array_equal(core, want)
+    mem, km2, dens = dsd.core_app(g, h)
+    assert km2 == km == math.comb(1280, h - 1)
+    np.testing.assert_array_equal(mem.astype(bool), size_of == 1281)
+    assert dens == Fraction(math.comb(1281, h), 1281)
+
+
 def test_bad_arguments():
     g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     for h in (0, 1, 7):

@@ -131,6 +131,33 @@ def test_complete_graph_cores(n, h):
     assert core.tolist() == [math.comb(n - 1, h - 1)] * n and kmax == math.comb(n - 1, h - 1)
 
 
+MULTIPARTITE = [[4, 2, 1], [5, 3, 3, 2, 1], [3, 3, 3], [6, 1, 1, 1, 1], [7, 5, 4, 4, 2, 1]]
+
+
+@pytest.mark.parametrize("parts", [[3, 2, 2, 1], [4, 1, 1], [2, 2, 2]])
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_multipartite_closed_form_is_the_definition(parts, h):
+    # the closed form used below (and by the GPU tests) against brute force
+    n, s, d, part = synth.complete_multipartite(parts, seed=3)
+    edges = list(zip(s.tolist(), d.tolist()))
+    deg, core = brute.multipartite_closed_form(parts, h)
+    assert brute.clique_degrees(n, edges, h)[0] == [deg[p] for p in part]
+    assert brute.core_fixpoint(n, edges, h) == [core[p] for p in part]
+
+
+@pytest.mark.parametrize("parts", MULTIPARTITE)
+@pytest.mark.parametrize("h", [2, 3, 4, 5])
+def test_multipartite_clique_degrees_and_cores(parts, h):
+    n, s, d, part = synth.complete_multipartite(parts, seed=len(parts))
+    g = oracle.Graph(n, s, d)
+    deg, core = brute.multipartite_closed_form(parts, h)
+    got_deg, mu = g.clique_degrees(h)
+    assert got_deg.tolist() == [deg[p] for p in part]
+    assert mu == brute.elementary_symmetric(parts, h)
+    got_core, kmax = g.core_decomposition(h)
+    assert got_core.tolist() == [core[p] for p in part] and kmax == max(core)
+
+
 @pytest.mark.parametrize("seed", range(8))
 @pytest.mark.parametrize("h", [2, 3, 4])
 def test_cores_match_fixpoint_definition(seed, h):
