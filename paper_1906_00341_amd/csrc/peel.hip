@@ -10,12 +10,14 @@
 // When no frontier is left, k jumps to the smallest alive degree (a new
 // level; no level in between can remove anything).
 //
-// State lives on the device (PeelCtl).  While many vertices are alive, one
-// round is a fixed sequence of grid-wide kernels (level-min, level-build,
-// process) that read the state themselves, so the host enqueues many rounds
-// without waiting.  Once few vertices are left, the rounds are short and
-// many (one per distinct core value at least), so a single workgroup
-// finishes the peel in one launch with workgroup barriers between rounds.
+// State lives on the device (PeelCtl).  One round is a fixed sequence of
+// grid-wide kernels (level-min, level-build, process, finish) that read the
+// state themselves, so the host enqueues many rounds without waiting.  For
+// h = 3 a large frontier vertex is split into items of CHUNK neighbours plus
+// one item per neighbour with a long out-list, so that even a round that
+// removes a single hub keeps thousands of waves busy; its neighbourhood hash
+// sits in global memory, shared by those items.  An optional single-workgroup
+// tail (DSD_TAIL_T) runs the last rounds in one launch instead.
 #include "engine.hpp"
 #include "graph.hpp"
 
@@ -38,6 +40,8 @@ struct PeelCtl {
     uint32_t done;     // finished blocks (last-block finalisation)
     int32_t selecting; // set by level-min: this round starts a new level
     int32_t nitems[8]; // (v, w) work items per class (h >= 4)
+    int64_t htop[2];   // slots handed out in the global neighbourhood hashes (h = 3)
+    int64_t nW;        // wide (v, w) items of this round (h = 3)
 };
 
 struct PeelBufs {
@@ -55,13 +59,21 @@ struct PeelBufs {
     u64 *lv_k, *lv_size, *lv_mu;  // level table [n + 1]
     int32_t *item_v, *item_w;     // [5][cap] work items (h >= 4)
     int64_t item_cap;
+    int32_t *hkey;     // [2][hcap] global hashes of N(v) for large frontier vertices (h = 3)
+    uint32_t *hval;
+    int64_t hcap;
+    int64_t *hbase;    // [n] first slot of v's hash in its round's half
+    int64_t *W;        // [wcap] wide items (v << 32 | w): w with a long out-list (h = 3)
+    int64_t wcap;
     int32_t n;
     int32_t h;
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
-constexpr int CHUNK = 512;              // neighbours per chunk item
-constexpr int BIG_HASH_BITS = 14;       // 16384 slots = 64 KB of LDS
+constexpr int CHUNK = 32;               // neighbours per chunk item (one wave)
+constexpr int SLOTS_PER_CHUNK = 64;     // global hash slots per chunk (load factor <= 1/2)
+constexpr int WIDE_OUT = 32;            // neighbours w with |N+(w)| >= this get a wave of their own
+constexpr int BIG_HASH_BITS = 14;       // single-workgroup tail: 16384 slots = 64 KB of LDS
 constexpr int BIG_HASH_CAP = 8192;      // larger neighbourhoods use binary search
 constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
 
@@ -76,6 +88,28 @@ __device__ __forceinline__ void wave_push(bool pred, int32_t val, int32_t *arr, 
     if (pred) arr[base + __popcll(m & lanemask_lt())] = val;
 }
 
+// all threads of the block call this together; one atomic per block
+__device__ __forceinline__ void block_push(bool pred, int32_t val, int32_t *arr, int32_t *counter) {
+    __shared__ int32_t sOff[WAVES_PER_BLOCK];
+    __shared__ int32_t sBase;
+    const u64 m = __ballot(pred);
+    const int wv = threadIdx.x / WAVE;
+    if (lane() == 0) sOff[wv] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int i = 0; i < WAVES_PER_BLOCK; i++) {
+            int32_t t = sOff[i];
+            sOff[i] = tot;
+            tot += t;
+        }
+        sBase = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    if (pred) arr[sBase + sOff[wv] + __popcll(m & lanemask_lt())] = val;
+    __syncthreads();
+}
+
 // the last block to arrive returns true (block-uniform)
 __device__ __forceinline__ bool last_block(uint32_t *done) {
     __shared__ bool is_last;
@@ -86,13 +120,16 @@ __device__ __forceinline__ bool last_block(uint32_t *done) {
     return is_last;
 }
 
-// chunk items of a large frontier vertex (h = 3)
+// chunk items of a large frontier vertex, and the slots of its neighbourhood
+// hash (h = 3)
 __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int which) {
     if (b.h != 3) return;
     int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
     if (d <= SMALL_DEG) return;
     int32_t nc = (int32_t)((d + CHUNK - 1) / CHUNK);
     int32_t base = atomicAdd(&b.ctl->nB[which], nc);
+    b.hbase[x] = (int64_t)atomicAdd((unsigned long long *)&b.ctl->htop[which],
+                                    (unsigned long long)nc * SLOTS_PER_CHUNK);
     int64_t *Bw = b.B + (size_t)which * b.bcap;
     for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
 }
@@ -120,6 +157,21 @@ __device__ __forceinline__ bool allowed(int32_t st, int32_t r, int32_t x, int32_
 
 __device__ __forceinline__ bool grid_rounds_on(const PeelCtl *c) { return c->n_alive > c->tail_T; }
 
+// the level of the current round: a round that opens a level records it only
+// when it finishes, so until then the level is max(k, smallest alive degree)
+__device__ __forceinline__ u64 round_level(const PeelCtl *c) {
+    return c->selecting ? (c->k > c->kcand ? c->k : c->kcand) : c->k;
+}
+
+// the alive list is copied (compacted) by level-build once more than an
+// eighth of it are removed vertices; n_alive and the list length do not
+// change between level-build and the end of the round, so every reader of
+// this test agrees
+__device__ __forceinline__ bool list_compacts(const PeelCtl *c) {
+    const int32_t cnt = c->nlist[c->lcur];
+    return (int64_t)(cnt - c->n_alive) * 8 > (int64_t)cnt;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_level_min(PeelBufs b) {
     PeelCtl *c = b.ctl;
     // nF and n_alive do not change during this kernel, so every block takes
@@ -137,11 +189,18 @@ __global__ __launch_bounds__(BLOCK) void k_level_min(PeelBufs b) {
             m = d < m ? d : m;
         }
     }
+    __shared__ u64 sMin[WAVES_PER_BLOCK];
     m = wave_min(m);
-    if (lane() == 0 && m != ~0ull) atomicMin(&c->kcand, m);
+    if (lane() == 0) sMin[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < WAVES_PER_BLOCK; i++) m = sMin[i] < m ? sMin[i] : m;
+        if (m != ~0ull) atomicMin(&c->kcand, m);
+    }
 }
 
-__device__ __forceinline__ void record_level(const PeelBufs &b, PeelCtl *c, u64 k) {
+// compacted: the survivors were copied to the other alive list
+__device__ __forceinline__ void record_level(const PeelBufs &b, PeelCtl *c, u64 k, bool compacted) {
     int32_t L = c->nlevels;
     b.lv_k[L] = k;
     b.lv_size[L] = (u64)c->n_alive;
@@ -149,22 +208,25 @@ __device__ __forceinline__ void record_level(const PeelBufs &b, PeelCtl *c, u64 
     c->nlevels = L + 1;
     c->k = k;
     c->kcand = ~0ull;
-    c->nlist[c->lcur] = 0;
-    c->lcur ^= 1;
+    if (compacted) {
+        c->nlist[c->lcur] = 0;
+        c->lcur ^= 1;
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
     PeelCtl *c = b.ctl;
     if (!c->selecting) return;
-    const u64 k = c->k > c->kcand ? c->k : c->kcand;
+    const u64 k = round_level(c);
     const int32_t r = c->round, lc = c->lcur, cur = c->cur;
     const int32_t *in = b.lists + (size_t)lc * b.n;
     int32_t *out = b.lists + (size_t)(lc ^ 1) * b.n;
     int32_t *F = b.F + (size_t)cur * b.n;
     const int32_t cnt = c->nlist[lc];
+    const bool compact = list_compacts(c);
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    const int64_t lim = ((int64_t)cnt + WAVE - 1) / WAVE * WAVE;
-    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i - lane() < lim; i += stride) {
+    for (int64_t base = blockIdx.x * (int64_t)BLOCK; base < cnt; base += stride) {
+        const int64_t i = base + threadIdx.x;
         int32_t v = -1;
         bool alive = false, take = false;
         if (i < cnt) {
@@ -178,11 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
             push_chunks(b, v, cur);
         }
         wave_push(take, v, F, &c->nF[cur]);
-        wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
-    }
-    if (last_block(&c->done) && threadIdx.x == 0) {
-        record_level(b, c, k);
-        c->done = 0;
+        if (compact) block_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
     }
 }
 
@@ -194,6 +252,8 @@ __device__ __forceinline__ void finish_round(PeelCtl *c) {
     c->destroyed = 0;
     c->nF[cur] = 0;
     c->nB[cur] = 0;
+    c->htop[cur] = 0;
+    c->nW = 0;
     c->cur = cur ^ 1;
     c->round += 1;
     c->done = 0;
@@ -207,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     const int32_t cur = c->cur, nF = c->nF[cur];
     if (nF == 0 || !grid_rounds_on(c)) return;
     const int32_t r = c->round;
-    const u64 k = c->k;
+    const u64 k = round_level(c);
     const int32_t *F = b.F + (size_t)cur * b.n;
     u64 destroyed = 0;
     const int wv = threadIdx.x / WAVE;
@@ -226,7 +286,6 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     }
     destroyed = wave_sum(destroyed);
     if (lane() == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
-    if (last_block(&c->done) && threadIdx.x == 0) finish_round(c);
 }
 
 // ---------------------------------------------------------------- h = 3
@@ -235,25 +294,31 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
 // a slot counts the cliques through v found so far that contain that
 // neighbour; the counts go to global memory once per neighbour (flush), so
 // the pair loop itself never waits on a global atomic.
+// size: any number of slots >= 2 (a power of two in LDS; chunk-sized in
+// global memory); at most half of them are ever filled
 struct NbHash {
     int32_t *keys;
     uint32_t *vals;
-    int bits;
+    uint32_t size;
+    __device__ __forceinline__ uint32_t start(int32_t x) const {
+        return (uint32_t)(((u64)((uint32_t)x * 2654435761u) * size) >> 32);
+    }
+    __device__ __forceinline__ uint32_t next(uint32_t slot) const { return slot + 1 == size ? 0 : slot + 1; }
     __device__ __forceinline__ int find(int32_t x) const {
-        uint32_t m = (1u << bits) - 1u, slot = hash_slot(x, bits);
+        uint32_t slot = start(x);
         while (true) {
             int32_t key = keys[slot];
             if (key == x) return (int)slot;
             if (key == HASH_EMPTY) return -1;
-            slot = (slot + 1) & m;
+            slot = next(slot);
         }
     }
     __device__ __forceinline__ void put(int32_t x) const {
-        uint32_t m = (1u << bits) - 1u, slot = hash_slot(x, bits);
+        uint32_t slot = start(x);
         while (true) {
             int32_t prev = atomicCAS(&keys[slot], HASH_EMPTY, x);
             if (prev == HASH_EMPTY || prev == x) return;
-            slot = (slot + 1) & m;
+            slot = next(slot);
         }
     }
 };
@@ -275,7 +340,7 @@ __device__ __forceinline__ void hash_fill(const PeelBufs &b, const NbHash &hs, i
 
 // apply the pending counts of slots t, t + step, ... and empty them
 __device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, int32_t r, u64 k, int t, int step) {
-    for (int i = t; i < (1 << hs.bits); i += step) {
+    for (uint32_t i = t; i < hs.size; i += step) {
         int32_t key = hs.keys[i];
         if (key == HASH_EMPTY) continue;
         uint32_t c = hs.vals[i];
@@ -291,10 +356,13 @@ __device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, 
 // go to the hash values; otherwise membership is a binary search in the
 // sorted row N(v)[rv0, rv1) and survivors are decremented at once.
 // sPre/sSt/sW/sCnt: this wave's 64-entry LDS scratch.
+// Neighbours w whose out-list holds wide_out or more entries are skipped (a
+// wide item of their own covers them).
 template <bool HASHED>
 __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int64_t rv0,
                                             int64_t rv1, int32_t r, u64 k, const NbHash &hs, int32_t *sPre,
-                                            int64_t *sSt, int32_t *sW, uint32_t *sCnt) {
+                                            int64_t *sSt, int32_t *sW, uint32_t *sCnt,
+                                            int32_t wide_out = 0x7fffffff) {
     const int L = lane();
     u64 destroyed = 0;
     for (int64_t base = lo; base < hi; base += WAVE) {
@@ -305,6 +373,7 @@ __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64
             if (allowed(b.stamp[w], r, w, v)) {
                 st0 = b.dag_off[w];
                 len = (int32_t)(b.row_ptr[w + 1] - st0);
+                if (len >= wide_out) len = 0;
                 if (HASHED) wslot = hs.find(w);
             }
         }
@@ -358,10 +427,10 @@ __global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
     const int32_t cur = c->cur, nF = c->nF[cur];
     if (nF == 0 || !grid_rounds_on(c)) return;
     const int32_t r = c->round;
-    const u64 k = c->k;
+    const u64 k = round_level(c);
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE, L = lane();
-    const NbHash hs{sKey[wv], sVal[wv], SMALL_HASH_BITS};
+    const NbHash hs{sKey[wv], sVal[wv], 1u << SMALL_HASH_BITS};
     u64 destroyed = 0;
     for (int i = L; i < (1 << SMALL_HASH_BITS); i += WAVE) {
         hs.keys[i] = HASH_EMPTY;
@@ -393,7 +462,7 @@ __device__ __forceinline__ u64 h3_block_range(const PeelBufs &b, int32_t v, int6
     const int wv = threadIdx.x / WAVE;
     const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
     const bool hashed = rv1 - rv0 <= BIG_HASH_CAP;
-    const NbHash hs{keys, vals, hash_bits_for(rv1 - rv0)};
+    const NbHash hs{keys, vals, 1u << hash_bits_for(rv1 - rv0)};
     u64 destroyed = 0;
     if (hashed) hash_fill(b, hs, v, rv0, rv1, r, threadIdx.x, NW * WAVE);
     __syncthreads();
@@ -410,40 +479,124 @@ __device__ __forceinline__ u64 h3_block_range(const PeelBufs &b, int32_t v, int6
     return destroyed;
 }
 
-// larger frontier vertices: one workgroup per chunk of CHUNK neighbours;
-// finishes the round
-__global__ __launch_bounds__(BLOCK) void k_process_h3_big(PeelBufs b) {
-    __shared__ int32_t sKey[1 << BIG_HASH_BITS];
-    __shared__ uint32_t sVal[1 << BIG_HASH_BITS];
+// Larger frontier vertices (degree > SMALL_DEG) are cut into chunks of CHUNK
+// neighbours, one wave each, so that the pairs of a hub spread over the whole
+// chip.  Their neighbourhood hashes live in global memory (SLOTS_PER_CHUNK
+// slots per chunk): fill inserts the allowed neighbours, probe counts the
+// triangles, flush hands each neighbour's count to dec_deg once and empties
+// the slots for later rounds.
+
+__device__ __forceinline__ NbHash big_hash(const PeelBufs &b, int32_t cur, int32_t v, int64_t d) {
+    const int64_t nc = (d + CHUNK - 1) / CHUNK;
+    const size_t off = (size_t)cur * b.hcap + b.hbase[v];
+    return NbHash{b.hkey + off, b.hval + off, (uint32_t)(nc * SLOTS_PER_CHUNK)};
+}
+
+__global__ __launch_bounds__(BLOCK) void k_h3_fill(PeelBufs b) {
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    const int32_t r = c->round, nB = c->nB[cur];
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int64_t item = Bc[it];
+        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+        const int64_t e = rv0 + (int64_t)ch * CHUNK + lane();
+        bool wide = false;
+        int32_t x = -1;
+        if (e < rv1 && lane() < CHUNK) {
+            x = b.col[e];
+            if (allowed(b.stamp[x], r, x, v)) {
+                big_hash(b, cur, v, rv1 - rv0).put(x);
+                wide = b.row_ptr[x + 1] - b.dag_off[x] >= WIDE_OUT;
+            }
+        }
+        const u64 m = __ballot(wide);
+        if (m) {
+            const int leader = __builtin_ctzll(m);
+            int64_t base = 0;
+            if (lane() == leader) base = (int64_t)atomicAdd((unsigned long long *)&c->nW, (unsigned long long)__popcll(m));
+            base = __shfl(base, leader, WAVE);
+            if (wide) b.W[base + __popcll(m & lanemask_lt())] = ((int64_t)v << 32) | (uint32_t)x;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
     __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
     __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
     __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
     __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
     PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0 || !grid_rounds_on(c)) return;
-    const int32_t r = c->round;
-    const u64 k = c->k;
-    const int32_t nB = c->nB[cur];
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    const int32_t r = c->round, nB = c->nB[cur];
+    const int64_t nW = c->nW;
+    const u64 k = round_level(c);
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    const int wv = threadIdx.x / WAVE;
     u64 destroyed = 0;
-    if (nB > (int32_t)blockIdx.x) {
-        for (int i = threadIdx.x; i < (1 << BIG_HASH_BITS); i += BLOCK) {
-            sKey[i] = HASH_EMPTY;
-            sVal[i] = 0;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB + nW; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        if (it < nB) {
+            // chunk item: the neighbours with short out-lists, their pairs flattened over the wave
+            const int64_t item = Bc[it];
+            const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+            const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+            const int64_t lo = rv0 + (int64_t)ch * CHUNK, hi = min(rv1, lo + CHUNK);
+            const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
+            destroyed += h3_wave_range<true>(b, v, lo, hi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv],
+                                             WIDE_OUT);
+        } else {
+            // wide item (v, w): the lanes walk N+(w)
+            const int64_t item = b.W[it - nB];
+            const int32_t v = (int32_t)(item >> 32), w = (int32_t)(item & 0xffffffff);
+            const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+            const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
+            uint32_t cw = 0;
+            for (int64_t e = b.dag_off[w] + lane(); e < b.row_ptr[w + 1]; e += WAVE) {
+                const int slot = hs.find(b.col[e]);
+                if (slot >= 0) {                          // triangle {v, w, x}, owned by v
+                    cw++;
+                    atomicAdd(&hs.vals[slot], 1u);
+                }
+            }
+            cw = wave_sum(cw);
+            if (lane() == 0 && cw) {
+                const int ws = hs.find(w);                // present: fill inserted every allowed neighbour
+                if (ws >= 0) atomicAdd(&hs.vals[ws], cw);
+            }
+            destroyed += lane() == 0 ? cw : 0;
         }
-    }
-    __syncthreads();
-    for (int64_t it = blockIdx.x; it < nB; it += gridDim.x) {
-        const int64_t item = Bc[it];
-        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
-        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
-        const int64_t lo = rv0 + (int64_t)ch * CHUNK, hi = min(rv1, lo + CHUNK);
-        destroyed += h3_block_range<WAVES_PER_BLOCK>(b, v, lo, hi, r, k, sKey, sVal, sPre, sSt, sW, sCnt);
     }
     destroyed = wave_sum(destroyed);
     if (lane() == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
-    if (last_block(&c->done) && threadIdx.x == 0) finish_round(c);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    const int32_t r = c->round, nB = c->nB[cur];
+    const u64 k = round_level(c);
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int64_t item = Bc[it];
+        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+        const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
+        const uint32_t s0 = (uint32_t)ch * SLOTS_PER_CHUNK;
+        for (uint32_t i = s0 + lane(); i < s0 + SLOTS_PER_CHUNK && i < hs.size; i += WAVE) {
+            const int32_t key = hs.keys[i];
+            if (key == HASH_EMPTY) continue;
+            const uint32_t cnt = hs.vals[i];
+            if (cnt && b.stamp[key] > r) dec_deg(b, key, cnt, k, r);
+            hs.keys[i] = HASH_EMPTY;
+            hs.vals[i] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- tail: one workgroup
@@ -523,7 +676,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_peel_tail(PeelBufs b) {
                 wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
             }
             __syncthreads();
-            if (threadIdx.x == 0) record_level(b, c, k);
+            if (threadIdx.x == 0) record_level(b, c, k, true);
             __syncthreads();
         }
         // destroy the cliques through the frontier, one frontier vertex at a time
@@ -576,12 +729,12 @@ struct PeelCtx {
     }
     __device__ __forceinline__ void add(int32_t x, u64 cnt) const {
         const int32_t r = b.ctl->round;
-        if (b.stamp[x] > r) dec_deg(b, x, cnt, b.ctl->k, r);
+        if (b.stamp[x] > r) dec_deg(b, x, cnt, round_level(b.ctl), r);
     }
     __device__ __forceinline__ void add_prefix(int64_t it, u64 t) const {
         const int32_t r = b.ctl->round;
         const int32_t w = root(it);
-        if (b.stamp[w] > r) dec_deg(b, w, t, b.ctl->k, r);
+        if (b.stamp[w] > r) dec_deg(b, w, t, round_level(b.ctl), r);
         atomicAdd(&b.ctl->destroyed, t);
     }
 };
@@ -630,8 +783,14 @@ __global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, int R) {
     }
 }
 
+// end of every grid round: a round that opened a level records it, then the
+// frontier is retired
 __global__ void k_finish_round(PeelBufs b) {
     PeelCtl *c = b.ctl;
+    if (c->selecting) {
+        record_level(b, c, round_level(c), list_compacts(c));
+        c->selecting = 0;
+    }
     if (c->nF[c->cur] == 0) return;
     finish_round(c);
 }
@@ -693,7 +852,10 @@ __global__ __launch_bounds__(BLOCK) void k_compact_fill(PeelBufs b, const int64_
 
 // the pending frontier's chunk items were cut for the old row lengths: redo them
 __global__ void k_reset_chunks(PeelBufs b) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.ctl->nB[b.ctl->cur] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.ctl->nB[b.ctl->cur] = 0;
+        b.ctl->htop[b.ctl->cur] = 0;
+    }
 }
 __global__ void k_rechunk(PeelBufs b) {
     const int32_t cur = b.ctl->cur, nF = b.ctl->nF[cur];
@@ -773,10 +935,14 @@ static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t 
     }
 }
 
+// Alive-vertex count at or below which the single-workgroup tail finishes the
+// peel (h <= 3).  Grid rounds spread a hub's pairs over the whole chip and
+// beat the tail on power-law graphs, so by default the tail is off;
+// DSD_TAIL_T sets it for experiments.
 static int64_t tail_threshold(int h) {
     if (h > 3) return 0;
     const char *e = getenv("DSD_TAIL_T");
-    return e ? atoll(e) : 16384;
+    return e ? atoll(e) : 0;
 }
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
@@ -803,6 +969,17 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK
         b.bcap = (int64_t)n + 2 * g.m / CHUNK + 1;
         b.B = sc.get_n<int64_t>(2 * b.bcap);
+        // a vertex of degree d > CHUNK takes SLOTS_PER_CHUNK * ceil(d / CHUNK) <= 4d
+        // slots, and no vertex is in two frontiers: 8m slots per half suffice
+        b.hcap = 8 * g.m + SLOTS_PER_CHUNK;
+        b.hkey = sc.get_n<int32_t>(2 * b.hcap);
+        b.hval = sc.get_n<uint32_t>(2 * b.hcap);
+        b.hbase = sc.get_n<int64_t>(n);
+        fill_i32(b.hkey, HASH_EMPTY, 2 * b.hcap, s);
+        fill_i32((int32_t *)b.hval, 0, 2 * b.hcap, s);
+        // one wide item per (frontier vertex, neighbour): at most 2m per round
+        b.wcap = 2 * g.m + 1;
+        b.W = sc.get_n<int64_t>(b.wcap);
     }
     const int R = h - 2;
     u64 *gS = nullptr;
@@ -834,7 +1011,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipEventCreate(&e1));
         DSD_HIP(hipEventRecord(e0, s));
     }
-    const int gmin = 1024, gbuild = 1024, gproc = 2048;
+    const int gmin = 256, gbuild = 1024, gproc = 2048;
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
     const bool compacting = h <= 3;
@@ -853,9 +1030,13 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
             if (h == 2) {
                 k_process_h2<<<gproc, BLOCK, 0, s>>>(b);
+                k_finish_round<<<1, 1, 0, s>>>(b);
             } else if (h == 3) {
                 k_process_h3_small<<<gproc, BLOCK, 0, s>>>(b);
-                k_process_h3_big<<<gproc, BLOCK, 0, s>>>(b);
+                k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
+                k_h3_probe<<<gproc, BLOCK, 0, s>>>(b);
+                k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
+                k_finish_round<<<1, 1, 0, s>>>(b);
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
