@@ -48,18 +48,31 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
                     KernelTimes *kt = nullptr);
 
 // ---- K4: round-synchronous peel ----
+// A batch of graphs is peeled as one disjoint union in which every graph
+// keeps its own level: a round moves every graph on by one step, so the
+// batch takes as many rounds as its slowest graph.
+struct PeelGroups {
+    int32_t G = 1;
+    const int32_t *gid = nullptr;      // [n] graph of every rank-space vertex
+    const u64 *mu = nullptr;           // [G] cliques inside each graph's alive set (device)
+    const int64_t *lv_base = nullptr;  // [G] first entry of each graph's level table (device)
+    int64_t lv_total = 0;              // entries of all tables together (graph g needs n_g + 1)
+};
 struct PeelResult {
     int64_t rounds = 0;
-    int64_t levels = 0;
-    std::vector<u64> level_k, level_size, level_mu;  // R_k for every level k reached
-    u64 kmax = 0;
+    int64_t levels = 0;                // summed over the graphs
+    std::vector<u64> level_k, level_size, level_mu;  // R_k for every level k reached (batch: every
+                                                      // graph's table at its base)
+    std::vector<int32_t> graph_levels; // batch: levels of each graph
+    u64 kmax = 0;                      // single graph
 };
 // alive0 (nullable): vertices taking part (others are ignored).  deg: clique
-// degrees inside the alive set (consumed).  mu: cliques inside the alive set.
-// k_floor: every vertex of degree <= k_floor goes in the first level (CoreApp
-// starts its peel there); 0 for a full decomposition.  core: rank space.
+// degrees inside the alive set (consumed).  mu: cliques inside the alive set
+// (single graph; grp->mu for a batch).  k_floor: every vertex of degree <=
+// k_floor goes in the first level (CoreApp starts its peel there); 0 for a
+// full decomposition.  core: rank space.
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr);
+                hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr, const PeelGroups *grp = nullptr);
 
 // ---- K5: connected components of the subgraph induced by mask ----
 // label[r] = smallest rank of r's component for r in mask, -1 outside.

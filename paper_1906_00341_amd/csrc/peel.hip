@@ -10,42 +10,54 @@
 // When no frontier is left, k jumps to the smallest alive degree (a new
 // level; no level in between can remove anything).
 //
-// State lives on the device (PeelCtl).  One round is a fixed sequence of
-// grid-wide kernels (level-min, level-build, process, finish) that read the
-// state themselves, so the host enqueues many rounds without waiting.  For
-// h = 3 a large frontier vertex is split into items of CHUNK neighbours plus
-// one item per neighbour with a long out-list, so that even a round that
-// removes a single hub keeps thousands of waves busy; its neighbourhood hash
-// sits in global memory, shared by those items.  An optional single-workgroup
-// tail (DSD_TAIL_T) runs the last rounds in one launch instead.
+// A batch of graphs is peeled as one disjoint union in which every graph
+// keeps its own level k (GraphState): cliques never cross graphs, so each
+// graph's peel is exactly its own, and one round advances all of them.
+//
+// State lives on the device (PeelCtl, GraphState).  One round is a fixed
+// sequence of grid-wide kernels (level-min, level-build, process, finish)
+// that read the state themselves, so the host enqueues many rounds without
+// waiting.  For h = 3 a large frontier vertex is split into items of CHUNK
+// neighbours plus one item per neighbour with a long out-list, so that even a
+// round that removes a single hub keeps thousands of waves busy; its
+// neighbourhood hash sits in global memory, shared by those items.
 #include "engine.hpp"
 #include "graph.hpp"
 
 namespace dsd {
 
 struct PeelCtl {
-    u64 k;          // current level
-    u64 kcand;      // smallest alive degree (next level)
-    u64 mu_alive;   // cliques among alive vertices
-    u64 destroyed;  // cliques destroyed in this round
-    int64_t n_alive;
-    int64_t tail_T;    // the single-workgroup tail takes over at or below this many alive vertices
+    int64_t n_alive;   // alive vertices over all graphs (the host polls it)
     int32_t round;
     int32_t cur;       // frontier buffer in use
-    int32_t nF[2];     // frontier sizes
+    int32_t nF[2];     // frontier sizes (all graphs)
     int32_t nB[2];     // chunk items of large frontier vertices (h = 3)
     int32_t nlist[2];  // alive-list sizes
     int32_t lcur;      // alive list in use
-    int32_t nlevels;
-    uint32_t done;     // finished blocks (last-block finalisation)
-    int32_t selecting; // set by level-min: this round starts a new level
+    int32_t nsel[2];   // graphs that open a level in the round using buffer 0 / 1
     int32_t nitems[8]; // (v, w) work items per class (h >= 4)
     int64_t htop[2];   // slots handed out in the global neighbourhood hashes (h = 3)
     int64_t nW;        // wide (v, w) items of this round (h = 3)
 };
 
+// one graph of the batch (a single graph is a batch of one)
+struct GraphState {
+    u64 k;             // current level
+    u64 kcand;         // smallest alive degree, gathered when a level opens
+    u64 mu_alive;      // cliques among the graph's alive vertices
+    u64 destroyed;     // cliques destroyed in this round
+    int64_t n_alive;
+    int64_t lv_base;   // first entry of the graph's level table
+    int32_t nF[2];     // the graph's frontier sizes
+    int32_t nlevels;
+    int32_t sel;       // this round opens a new level (fixed for the whole round)
+};
+
 struct PeelBufs {
     PeelCtl *ctl;
+    GraphState *gs;
+    const int32_t *gid;  // [n] graph of every vertex (nullptr: one graph)
+    int32_t G;
     const int64_t *row_ptr;
     const int32_t *col;
     const int64_t *dag_off;
@@ -56,7 +68,7 @@ struct PeelBufs {
     int64_t *B;        // [2][bcap] (v << 32 | chunk) for frontier vertices of degree > SMALL_DEG
     int64_t bcap;
     int32_t *lists;    // [2][n] alive lists
-    u64 *lv_k, *lv_size, *lv_mu;  // level table [n + 1]
+    u64 *lv_k, *lv_size, *lv_mu;  // level tables
     int32_t *item_v, *item_w;     // [5][cap] work items (h >= 4)
     int64_t item_cap;
     int32_t *hkey;     // [2][hcap] global hashes of N(v) for large frontier vertices (h = 3)
@@ -73,9 +85,27 @@ constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are s
 constexpr int CHUNK = 32;               // neighbours per chunk item (one wave)
 constexpr int SLOTS_PER_CHUNK = 64;     // global hash slots per chunk (load factor <= 1/2)
 constexpr int WIDE_OUT = 32;            // neighbours w with |N+(w)| >= this get a wave of their own
-constexpr int BIG_HASH_BITS = 14;       // single-workgroup tail: 16384 slots = 64 KB of LDS
-constexpr int BIG_HASH_CAP = 8192;      // larger neighbourhoods use binary search
 constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
+
+__device__ __forceinline__ int32_t graph_of(const PeelBufs &b, int32_t v) { return b.gid ? b.gid[v] : 0; }
+
+// the level of graph g in the current round: a round that opens a level
+// records it only when it finishes, so until then it is max(k, smallest
+// alive degree)
+__device__ __forceinline__ u64 level_of(const PeelBufs &b, int32_t g) {
+    const GraphState &s = b.gs[g];
+    if (!s.sel) return s.k;
+    return s.k > s.kcand ? s.k : s.kcand;
+}
+
+// the alive list is copied (compacted) by level-build once more than an
+// eighth of it are removed vertices; n_alive and the list length do not
+// change between level-build and the end of the round, so every reader of
+// this test agrees
+__device__ __forceinline__ bool list_compacts(const PeelCtl *c) {
+    const int32_t cnt = c->nlist[c->lcur];
+    return (int64_t)(cnt - c->n_alive) * 8 > (int64_t)cnt;
+}
 
 // all lanes of the wave must call this together
 __device__ __forceinline__ void wave_push(bool pred, int32_t val, int32_t *arr, int32_t *counter) {
@@ -110,14 +140,21 @@ __device__ __forceinline__ void block_push(bool pred, int32_t val, int32_t *arr,
     __syncthreads();
 }
 
-// the last block to arrive returns true (block-uniform)
-__device__ __forceinline__ bool last_block(uint32_t *done) {
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    return is_last;
+// Per-graph counter increments: the lanes of a wave usually belong to one
+// graph (the alive list runs in id order), so the wave adds once; otherwise
+// every lane adds for itself.  All lanes call together; g < 0: nothing to
+// add.  The counter of graph g is at base[g * stride].
+template <typename T>
+__device__ __forceinline__ void wave_add_by_graph(int32_t g, T *base, size_t stride) {
+    const u64 act = __ballot(g >= 0);
+    if (!act) return;
+    const int first = __builtin_ctzll(act);
+    const int32_t g0 = __shfl(g, first, WAVE);
+    if (__ballot(g >= 0 && g != g0) == 0) {
+        if (lane() == first) atomicAdd(base + (size_t)g0 * stride, (T)__popcll(act));
+    } else if (g >= 0) {
+        atomicAdd(base + (size_t)g * stride, (T)1);
+    }
 }
 
 // chunk items of a large frontier vertex, and the slots of its neighbourhood
@@ -134,17 +171,27 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
     for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
 }
 
-__device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, u64 k, int32_t r) {
+// a survivor x loses c cliques; if that takes it to the level of its graph it
+// joins the next frontier with that core number
+__device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int32_t r) {
+    const int32_t g = graph_of(b, x);
+    const u64 k = level_of(b, g);
     u64 old = atomic_sub_u64(&b.deg[x], c);
     if (old > k && old - c <= k) {
         const int nx = b.ctl->cur ^ 1;
         int32_t *Fn = b.F + (size_t)nx * b.n;
         int32_t pos = atomicAdd(&b.ctl->nF[nx], 1);
         Fn[pos] = x;
+        atomicAdd(&b.gs[g].nF[nx], 1);
         b.stamp[x] = r + 1;
         b.core[x] = k;
         push_chunks(b, x, nx);
     }
+}
+
+// cliques destroyed through frontier vertex v
+__device__ __forceinline__ void add_destroyed(const PeelBufs &b, int32_t v, u64 t) {
+    if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed, t);
 }
 
 // a clique through frontier vertex v may use x iff x was alive at the start
@@ -155,109 +202,158 @@ __device__ __forceinline__ bool allowed(int32_t st, int32_t r, int32_t x, int32_
 
 // ---------------------------------------------------------------- level selection
 
-__device__ __forceinline__ bool grid_rounds_on(const PeelCtl *c) { return c->n_alive > c->tail_T; }
-
-// the level of the current round: a round that opens a level records it only
-// when it finishes, so until then the level is max(k, smallest alive degree)
-__device__ __forceinline__ u64 round_level(const PeelCtl *c) {
-    return c->selecting ? (c->k > c->kcand ? c->k : c->kcand) : c->k;
-}
-
-// the alive list is copied (compacted) by level-build once more than an
-// eighth of it are removed vertices; n_alive and the list length do not
-// change between level-build and the end of the round, so every reader of
-// this test agrees
-__device__ __forceinline__ bool list_compacts(const PeelCtl *c) {
-    const int32_t cnt = c->nlist[c->lcur];
-    return (int64_t)(cnt - c->n_alive) * 8 > (int64_t)cnt;
-}
-
+// smallest alive degree of every graph that opens a level
 __global__ __launch_bounds__(BLOCK) void k_level_min(PeelBufs b) {
     PeelCtl *c = b.ctl;
-    // nF and n_alive do not change during this kernel, so every block takes
-    // the same decision; level-build reads the flag because it grows nF itself
-    const bool sel = c->nF[c->cur] == 0 && c->n_alive > 0 && grid_rounds_on(c);
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->selecting = sel ? 1 : 0;
-    if (!sel) return;
+    if (c->nsel[c->cur] == 0) return;
     const int32_t *list = b.lists + (size_t)c->lcur * b.n;
     const int32_t cnt = c->nlist[c->lcur];
-    u64 m = ~0ull;
-    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * BLOCK) {
-        int32_t v = list[i];
-        if (b.stamp[v] == ALIVE) {
-            u64 d = b.deg[v];
-            m = d < m ? d : m;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    if (b.G == 1) {
+        u64 m = ~0ull;
+        for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < cnt; i += stride) {
+            int32_t v = list[i];
+            if (b.stamp[v] == ALIVE) {
+                u64 d = b.deg[v];
+                m = d < m ? d : m;
+            }
+        }
+        __shared__ u64 sMin[WAVES_PER_BLOCK];
+        m = wave_min(m);
+        if (lane() == 0) sMin[threadIdx.x / WAVE] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < WAVES_PER_BLOCK; i++) m = sMin[i] < m ? sMin[i] : m;
+            if (m != ~0ull) atomicMin(&b.gs[0].kcand, m);
+        }
+        return;
+    }
+    for (int64_t base = blockIdx.x * (int64_t)BLOCK; base < cnt; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        int32_t g = -1;
+        u64 d = ~0ull;
+        if (i < cnt) {
+            const int32_t v = list[i];
+            if (b.stamp[v] == ALIVE) {
+                const int32_t gv = b.gid[v];
+                if (b.gs[gv].sel) {
+                    g = gv;
+                    d = b.deg[v];
+                }
+            }
+        }
+        const u64 act = __ballot(g >= 0);
+        if (!act) continue;
+        const int first = __builtin_ctzll(act);
+        const int32_t g0 = __shfl(g, first, WAVE);
+        if (__ballot(g >= 0 && g != g0) == 0) {
+            const u64 m = wave_min(d);
+            if (lane() == first) atomicMin(&b.gs[g0].kcand, m);
+        } else if (g >= 0) {
+            atomicMin(&b.gs[g].kcand, d);
         }
     }
-    __shared__ u64 sMin[WAVES_PER_BLOCK];
-    m = wave_min(m);
-    if (lane() == 0) sMin[threadIdx.x / WAVE] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < WAVES_PER_BLOCK; i++) m = sMin[i] < m ? sMin[i] : m;
-        if (m != ~0ull) atomicMin(&c->kcand, m);
-    }
 }
 
-// compacted: the survivors were copied to the other alive list
-__device__ __forceinline__ void record_level(const PeelBufs &b, PeelCtl *c, u64 k, bool compacted) {
-    int32_t L = c->nlevels;
-    b.lv_k[L] = k;
-    b.lv_size[L] = (u64)c->n_alive;
-    b.lv_mu[L] = c->mu_alive;
-    c->nlevels = L + 1;
-    c->k = k;
-    c->kcand = ~0ull;
-    if (compacted) {
-        c->nlist[c->lcur] = 0;
-        c->lcur ^= 1;
-    }
-}
-
+// frontier of every graph that opens a level: its alive vertices of degree <= k
 __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
     PeelCtl *c = b.ctl;
-    if (!c->selecting) return;
-    const u64 k = round_level(c);
-    const int32_t r = c->round, lc = c->lcur, cur = c->cur;
+    const int32_t cur = c->cur;
+    if (c->nsel[cur] == 0) return;
+    const int32_t r = c->round, lc = c->lcur;
     const int32_t *in = b.lists + (size_t)lc * b.n;
     int32_t *out = b.lists + (size_t)(lc ^ 1) * b.n;
     int32_t *F = b.F + (size_t)cur * b.n;
     const int32_t cnt = c->nlist[lc];
     const bool compact = list_compacts(c);
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
     for (int64_t base = blockIdx.x * (int64_t)BLOCK; base < cnt; base += stride) {
         const int64_t i = base + threadIdx.x;
-        int32_t v = -1;
+        int32_t v = -1, g = 0;
         bool alive = false, take = false;
         if (i < cnt) {
             v = in[i];
             alive = b.stamp[v] == ALIVE;
-            take = alive && b.deg[v] <= k;
-        }
-        if (take) {
-            b.stamp[v] = r;
-            b.core[v] = k;
-            push_chunks(b, v, cur);
+            if (alive) {
+                g = graph_of(b, v);
+                if (b.gs[g].sel) {
+                    const u64 k = level_of(b, g);
+                    take = b.deg[v] <= k;
+                    if (take) {
+                        b.stamp[v] = r;
+                        b.core[v] = k;
+                        push_chunks(b, v, cur);
+                    }
+                }
+            }
         }
         wave_push(take, v, F, &c->nF[cur]);
+        wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
         if (compact) block_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
     }
 }
 
-// end of a round: the frontier is gone
-__device__ __forceinline__ void finish_round(PeelCtl *c) {
-    int32_t cur = c->cur;
+// End of a round, per graph: a graph that opened a level records it; its
+// frontier is retired; it opens a level next round if nothing is pending.
+__device__ __forceinline__ void finish_graph(const PeelBufs &b, int32_t g) {
+    PeelCtl *c = b.ctl;
+    GraphState &s = b.gs[g];
+    const int32_t cur = c->cur, nx = cur ^ 1;
+    if (!s.sel && s.nF[cur] == 0) return;          // finished graph: nothing happened
+    if (s.sel) {
+        const u64 k = level_of(b, g);
+        if (s.nF[cur] > 0) {
+            const int64_t L = s.lv_base + s.nlevels;
+            b.lv_k[L] = k;
+            b.lv_size[L] = (u64)s.n_alive;
+            b.lv_mu[L] = s.mu_alive;
+            s.nlevels += 1;
+        }
+        s.k = k;
+        s.kcand = ~0ull;
+    }
+    s.n_alive -= s.nF[cur];
+    s.mu_alive -= s.destroyed;
+    s.destroyed = 0;
+    s.nF[cur] = 0;
+    s.sel = (s.nF[nx] == 0 && s.n_alive > 0) ? 1 : 0;
+    if (s.sel) atomicAdd(&c->nsel[nx], 1);
+}
+
+// End of a round, global part (after every graph's part).
+__device__ __forceinline__ void finish_global(PeelCtl *c) {
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0 && c->nsel[cur] == 0) return;   // nothing happened
+    if (c->nsel[cur] > 0 && list_compacts(c)) {
+        c->nlist[c->lcur] = 0;
+        c->lcur ^= 1;
+    }
     c->n_alive -= c->nF[cur];
-    c->mu_alive -= c->destroyed;
-    c->destroyed = 0;
+    c->nsel[cur] = 0;
     c->nF[cur] = 0;
     c->nB[cur] = 0;
     c->htop[cur] = 0;
     c->nW = 0;
+    for (int i = 0; i < 8; i++) c->nitems[i] = 0;
     c->cur = cur ^ 1;
     c->round += 1;
-    c->done = 0;
-    for (int i = 0; i < 8; i++) c->nitems[i] = 0;
+}
+
+__global__ void k_finish_one(PeelBufs b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        finish_graph(b, 0);
+        finish_global(b.ctl);
+    }
+}
+
+__global__ void k_finish_graphs(PeelBufs b) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < b.G) finish_graph(b, g);
+}
+
+__global__ void k_finish_global(PeelBufs b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) finish_global(b.ctl);
 }
 
 // ---------------------------------------------------------------- h = 2
@@ -265,14 +361,13 @@ __device__ __forceinline__ void finish_round(PeelCtl *c) {
 __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0 || !grid_rounds_on(c)) return;
+    if (nF == 0) return;
     const int32_t r = c->round;
-    const u64 k = round_level(c);
     const int32_t *F = b.F + (size_t)cur * b.n;
-    u64 destroyed = 0;
     const int wv = threadIdx.x / WAVE;
     for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nF; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[i];
+        u64 destroyed = 0;
         for (int64_t e = b.row_ptr[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
             int32_t w = b.col[e];
             int32_t st = b.stamp[w];
@@ -280,22 +375,22 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
                 destroyed += (v < w) ? 1 : 0;       // both ends leave: count the edge once
             } else if (st > r) {
                 destroyed += 1;
-                dec_deg(b, w, 1, k, r);
+                dec_deg(b, w, 1, r);
             }
         }
+        destroyed = wave_sum(destroyed);
+        if (lane() == 0) add_destroyed(b, v, destroyed);
     }
-    destroyed = wave_sum(destroyed);
-    if (lane() == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
 }
 
 // ---------------------------------------------------------------- h = 3
 
-// LDS hash over the allowed neighbourhood of frontier vertex v.  The value of
-// a slot counts the cliques through v found so far that contain that
-// neighbour; the counts go to global memory once per neighbour (flush), so
-// the pair loop itself never waits on a global atomic.
-// size: any number of slots >= 2 (a power of two in LDS; chunk-sized in
-// global memory); at most half of them are ever filled
+// Hash over the allowed neighbourhood of frontier vertex v.  The value of a
+// slot counts the cliques through v found so far that contain that
+// neighbour; the counts go to dec_deg once per neighbour (flush), so the pair
+// loop itself never waits on a global atomic.  size: any number of slots >=
+// 2 (a power of two in LDS, chunk-sized in global memory); at most half of
+// them are ever filled.
 struct NbHash {
     int32_t *keys;
     uint32_t *vals;
@@ -323,12 +418,6 @@ struct NbHash {
     }
 };
 
-__device__ __forceinline__ int hash_bits_for(int64_t d) {
-    int bits = 7;
-    while (bits < BIG_HASH_BITS && ((int64_t)1 << bits) < 2 * d) bits++;
-    return bits;
-}
-
 // insert the allowed neighbours N(v)[rv0, rv1) (threads t, t + step, ...)
 __device__ __forceinline__ void hash_fill(const PeelBufs &b, const NbHash &hs, int32_t v, int64_t rv0, int64_t rv1,
                                           int32_t r, int t, int step) {
@@ -338,31 +427,28 @@ __device__ __forceinline__ void hash_fill(const PeelBufs &b, const NbHash &hs, i
     }
 }
 
-// apply the pending counts of slots t, t + step, ... and empty them
-__device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, int32_t r, u64 k, int t, int step) {
-    for (uint32_t i = t; i < hs.size; i += step) {
+// apply the pending counts of slots [s0, s1) (threads t, t + step, ...) and empty them
+__device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, int32_t r, uint32_t s0, uint32_t s1,
+                                           int t, int step) {
+    for (uint32_t i = s0 + t; i < s1; i += step) {
         int32_t key = hs.keys[i];
         if (key == HASH_EMPTY) continue;
         uint32_t c = hs.vals[i];
-        if (c && b.stamp[key] > r) dec_deg(b, key, c, k, r);
+        if (c && b.stamp[key] > r) dec_deg(b, key, c, r);
         hs.keys[i] = HASH_EMPTY;
         hs.vals[i] = 0;
     }
 }
 
 // One wave handles the neighbours N(v)[lo, hi) of frontier vertex v: for each
-// allowed neighbour w it probes N+(w) against the allowed neighbourhood of v,
-// so every triangle {v, w, x} with w before x is seen once.  HASHED: counts
-// go to the hash values; otherwise membership is a binary search in the
-// sorted row N(v)[rv0, rv1) and survivors are decremented at once.
-// sPre/sSt/sW/sCnt: this wave's 64-entry LDS scratch.
+// allowed neighbour w it probes N+(w) against the hash of v's allowed
+// neighbourhood, so every triangle {v, w, x} with w before x is seen once.
 // Neighbours w whose out-list holds wide_out or more entries are skipped (a
-// wide item of their own covers them).
-template <bool HASHED>
-__device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int64_t rv0,
-                                            int64_t rv1, int32_t r, u64 k, const NbHash &hs, int32_t *sPre,
-                                            int64_t *sSt, int32_t *sW, uint32_t *sCnt,
-                                            int32_t wide_out = 0x7fffffff) {
+// wide item of their own covers them).  sPre/sSt/sW/sCnt: this wave's
+// 64-entry LDS scratch.
+__device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int32_t r,
+                                            const NbHash &hs, int32_t *sPre, int64_t *sSt, int32_t *sW,
+                                            uint32_t *sCnt, int32_t wide_out) {
     const int L = lane();
     u64 destroyed = 0;
     for (int64_t base = lo; base < hi; base += WAVE) {
@@ -374,13 +460,13 @@ __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64
                 st0 = b.dag_off[w];
                 len = (int32_t)(b.row_ptr[w + 1] - st0);
                 if (len >= wide_out) len = 0;
-                if (HASHED) wslot = hs.find(w);
+                wslot = hs.find(w);
             }
         }
         int32_t inc = wave_incl_scan(len);
         sPre[L] = inc;
         sSt[L] = st0;
-        sW[L] = HASHED ? wslot : w;
+        sW[L] = wslot;
         sCnt[L] = 0;
         const int32_t total = __shfl(inc, WAVE - 1, WAVE);
         __builtin_amdgcn_wave_barrier();
@@ -390,32 +476,23 @@ __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64
                 int i = upper_bound_i32(sPre, WAVE, p);
                 int32_t off = p - (i ? sPre[i - 1] : 0);
                 int32_t x = b.col[sSt[i] + off];
-                if (HASHED) {
-                    int slot = hs.find(x);
-                    if (slot >= 0) {                      // triangle {v, w, x}, owned by v
-                        destroyed++;
-                        atomicAdd(&sCnt[i], 1u);
-                        atomicAdd(&hs.vals[slot], 1u);
-                    }
-                } else if (allowed(b.stamp[x], r, x, v) && bsearch_i32(b.col, rv0, rv1, x) >= 0) {
+                int slot = hs.find(x);
+                if (slot >= 0) {                      // triangle {v, w, x}, owned by v
                     destroyed++;
                     atomicAdd(&sCnt[i], 1u);
-                    if (b.stamp[x] > r) dec_deg(b, x, 1, k, r);
+                    atomicAdd(&hs.vals[slot], 1u);
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         uint32_t cw = sCnt[L];
-        if (cw) {
-            if (HASHED) atomicAdd(&hs.vals[sW[L]], cw);
-            else if (b.stamp[sW[L]] > r) dec_deg(b, sW[L], cw, k, r);
-        }
+        if (cw) atomicAdd(&hs.vals[sW[L]], cw);
         __builtin_amdgcn_wave_barrier();
     }
     return destroyed;
 }
 
-// small frontier vertices (degree <= SMALL_DEG): one wave each, per-wave hash
+// small frontier vertices (degree <= SMALL_DEG): one wave each, per-wave LDS hash
 __global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
     __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
     __shared__ uint32_t sVal[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
@@ -425,13 +502,11 @@ __global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
     __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0 || !grid_rounds_on(c)) return;
+    if (nF == 0) return;
     const int32_t r = c->round;
-    const u64 k = round_level(c);
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE, L = lane();
     const NbHash hs{sKey[wv], sVal[wv], 1u << SMALL_HASH_BITS};
-    u64 destroyed = 0;
     for (int i = L; i < (1 << SMALL_HASH_BITS); i += WAVE) {
         hs.keys[i] = HASH_EMPTY;
         hs.vals[i] = 0;
@@ -443,48 +518,22 @@ __global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
         if (rv1 - rv0 > SMALL_DEG) continue;                     // chunk items cover it
         hash_fill(b, hs, v, rv0, rv1, r, L, WAVE);
         __builtin_amdgcn_wave_barrier();
-        destroyed += h3_wave_range<true>(b, v, rv0, rv1, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
+        u64 destroyed = h3_wave_range(b, v, rv0, rv1, r, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv], 0x7fffffff);
         __builtin_amdgcn_wave_barrier();
-        hash_flush(b, hs, r, k, L, WAVE);
+        hash_flush(b, hs, r, 0, hs.size, L, WAVE);
         __builtin_amdgcn_wave_barrier();
+        destroyed = wave_sum(destroyed);
+        if (L == 0) add_destroyed(b, v, destroyed);
     }
-    destroyed = wave_sum(destroyed);
-    if (L == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
-}
-
-// All waves of a workgroup handle the neighbours N(v)[lo, hi) of v (64 at a
-// time, round-robin); the hash covers all of N(v).  Used by the grid kernel
-// for chunk items and by the tail for whole frontier vertices.
-template <int NW>
-__device__ __forceinline__ u64 h3_block_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int32_t r, u64 k,
-                                             int32_t *keys, uint32_t *vals, int32_t (*sPre)[WAVE],
-                                             int64_t (*sSt)[WAVE], int32_t (*sW)[WAVE], uint32_t (*sCnt)[WAVE]) {
-    const int wv = threadIdx.x / WAVE;
-    const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
-    const bool hashed = rv1 - rv0 <= BIG_HASH_CAP;
-    const NbHash hs{keys, vals, 1u << hash_bits_for(rv1 - rv0)};
-    u64 destroyed = 0;
-    if (hashed) hash_fill(b, hs, v, rv0, rv1, r, threadIdx.x, NW * WAVE);
-    __syncthreads();
-    for (int64_t plo = lo + (int64_t)wv * WAVE; plo < hi; plo += (int64_t)NW * WAVE) {
-        const int64_t phi = min(hi, plo + WAVE);
-        if (hashed)
-            destroyed += h3_wave_range<true>(b, v, plo, phi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
-        else
-            destroyed += h3_wave_range<false>(b, v, plo, phi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv]);
-    }
-    __syncthreads();
-    if (hashed) hash_flush(b, hs, r, k, threadIdx.x, NW * WAVE);
-    __syncthreads();
-    return destroyed;
 }
 
 // Larger frontier vertices (degree > SMALL_DEG) are cut into chunks of CHUNK
 // neighbours, one wave each, so that the pairs of a hub spread over the whole
 // chip.  Their neighbourhood hashes live in global memory (SLOTS_PER_CHUNK
-// slots per chunk): fill inserts the allowed neighbours, probe counts the
-// triangles, flush hands each neighbour's count to dec_deg once and empties
-// the slots for later rounds.
+// slots per chunk): fill inserts the allowed neighbours (and queues a wide
+// item for each neighbour with a long out-list), probe counts the triangles,
+// flush hands each neighbour's count to dec_deg once and empties the slots
+// for later rounds.
 
 __device__ __forceinline__ NbHash big_hash(const PeelBufs &b, int32_t cur, int32_t v, int64_t d) {
     const int64_t nc = (d + CHUNK - 1) / CHUNK;
@@ -495,7 +544,7 @@ __device__ __forceinline__ NbHash big_hash(const PeelBufs &b, int32_t cur, int32
 __global__ __launch_bounds__(BLOCK) void k_h3_fill(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
-    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    if (c->nF[cur] == 0) return;
     const int32_t r = c->round, nB = c->nB[cur];
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const int wv = threadIdx.x / WAVE;
@@ -531,27 +580,29 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
     __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
-    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    if (c->nF[cur] == 0) return;
     const int32_t r = c->round, nB = c->nB[cur];
     const int64_t nW = c->nW;
-    const u64 k = round_level(c);
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const int wv = threadIdx.x / WAVE;
-    u64 destroyed = 0;
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB + nW; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        int32_t v;
+        u64 destroyed;
         if (it < nB) {
             // chunk item: the neighbours with short out-lists, their pairs flattened over the wave
             const int64_t item = Bc[it];
-            const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+            v = (int32_t)(item >> 32);
+            const int32_t ch = (int32_t)(item & 0xffffffff);
             const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
             const int64_t lo = rv0 + (int64_t)ch * CHUNK, hi = min(rv1, lo + CHUNK);
             const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
-            destroyed += h3_wave_range<true>(b, v, lo, hi, rv0, rv1, r, k, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv],
-                                             WIDE_OUT);
+            destroyed = h3_wave_range(b, v, lo, hi, r, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv], WIDE_OUT);
+            destroyed = wave_sum(destroyed);
         } else {
             // wide item (v, w): the lanes walk N+(w)
             const int64_t item = b.W[it - nB];
-            const int32_t v = (int32_t)(item >> 32), w = (int32_t)(item & 0xffffffff);
+            v = (int32_t)(item >> 32);
+            const int32_t w = (int32_t)(item & 0xffffffff);
             const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
             const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
             uint32_t cw = 0;
@@ -567,19 +618,17 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
                 const int ws = hs.find(w);                // present: fill inserted every allowed neighbour
                 if (ws >= 0) atomicAdd(&hs.vals[ws], cw);
             }
-            destroyed += lane() == 0 ? cw : 0;
+            destroyed = cw;
         }
+        if (lane() == 0) add_destroyed(b, v, destroyed);
     }
-    destroyed = wave_sum(destroyed);
-    if (lane() == 0 && destroyed) atomicAdd(&c->destroyed, destroyed);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
-    if (c->nF[cur] == 0 || !grid_rounds_on(c)) return;
+    if (c->nF[cur] == 0) return;
     const int32_t r = c->round, nB = c->nB[cur];
-    const u64 k = round_level(c);
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const int wv = threadIdx.x / WAVE;
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
@@ -588,129 +637,7 @@ __global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
         const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
         const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
         const uint32_t s0 = (uint32_t)ch * SLOTS_PER_CHUNK;
-        for (uint32_t i = s0 + lane(); i < s0 + SLOTS_PER_CHUNK && i < hs.size; i += WAVE) {
-            const int32_t key = hs.keys[i];
-            if (key == HASH_EMPTY) continue;
-            const uint32_t cnt = hs.vals[i];
-            if (cnt && b.stamp[key] > r) dec_deg(b, key, cnt, k, r);
-            hs.keys[i] = HASH_EMPTY;
-            hs.vals[i] = 0;
-        }
-    }
-}
-
-// ---------------------------------------------------------------- tail: one workgroup
-
-constexpr int TAIL_THREADS = 1024;
-constexpr int TAIL_WAVES = TAIL_THREADS / WAVE;
-
-// Runs every remaining round inside one workgroup: level selection, frontier
-// build and clique destruction are separated by workgroup barriers.  Each
-// frontier vertex is handled by the whole workgroup in turn.
-template <int H>
-__global__ __launch_bounds__(TAIL_THREADS) void k_peel_tail(PeelBufs b) {
-    __shared__ int32_t sKey[1 << BIG_HASH_BITS];
-    __shared__ uint32_t sVal[1 << BIG_HASH_BITS];
-    __shared__ int32_t sPre[TAIL_WAVES][WAVE];
-    __shared__ int64_t sSt[TAIL_WAVES][WAVE];
-    __shared__ int32_t sW[TAIL_WAVES][WAVE];
-    __shared__ uint32_t sCnt[TAIL_WAVES][WAVE];
-    __shared__ u64 sRed[TAIL_WAVES];
-    __shared__ u64 sK;
-    __shared__ int64_t sAlive;
-    __shared__ int32_t sCur, sNF;
-    PeelCtl *c = b.ctl;
-    const int wv = threadIdx.x / WAVE, L = lane();
-    for (int i = threadIdx.x; i < (1 << BIG_HASH_BITS); i += TAIL_THREADS) {
-        sKey[i] = HASH_EMPTY;
-        sVal[i] = 0;
-    }
-    while (true) {
-        // one thread reads the control state, so every wave takes the same path
-        // (other waves' pushes would otherwise be visible to some reads only)
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            sAlive = c->n_alive;
-            sCur = c->cur;
-            sNF = c->nF[c->cur];
-        }
-        __syncthreads();
-        if (sAlive == 0) break;
-        const int32_t cur = sCur;
-        if (sNF == 0) {
-            // new level: k = max(k, smallest alive degree)
-            const int32_t lc = c->lcur, cnt = c->nlist[lc];
-            const int32_t *in = b.lists + (size_t)lc * b.n;
-            u64 m = ~0ull;
-            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_THREADS) {
-                int32_t v = in[i];
-                if (b.stamp[v] == ALIVE) m = b.deg[v] < m ? b.deg[v] : m;
-            }
-            m = wave_min(m);
-            if (L == 0) sRed[wv] = m;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                u64 mm = ~0ull;
-                for (int i = 0; i < TAIL_WAVES; i++) mm = sRed[i] < mm ? sRed[i] : mm;
-                sK = c->k > mm ? c->k : mm;
-            }
-            __syncthreads();
-            const u64 k = sK;
-            const int32_t r = c->round;
-            int32_t *out = b.lists + (size_t)(lc ^ 1) * b.n;
-            int32_t *F = b.F + (size_t)cur * b.n;
-            const int32_t lim = (cnt + WAVE - 1) / WAVE * WAVE;
-            for (int32_t i = threadIdx.x; i - L < lim; i += TAIL_THREADS) {
-                int32_t v = -1;
-                bool alive = false, take = false;
-                if (i < cnt) {
-                    v = in[i];
-                    alive = b.stamp[v] == ALIVE;
-                    take = alive && b.deg[v] <= k;
-                }
-                if (take) {
-                    b.stamp[v] = r;
-                    b.core[v] = k;
-                }
-                wave_push(take, v, F, &c->nF[cur]);
-                wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) record_level(b, c, k, true);
-            __syncthreads();
-        }
-        // destroy the cliques through the frontier, one frontier vertex at a time
-        const int32_t nF = c->nF[cur], r = c->round;
-        const u64 k = c->k;
-        const int32_t *F = b.F + (size_t)cur * b.n;
-        u64 destroyed = 0;
-        for (int32_t fi = 0; fi < nF; fi++) {
-            const int32_t v = F[fi];
-            const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
-            if constexpr (H == 2) {
-                for (int64_t e = rv0 + threadIdx.x; e < rv1; e += TAIL_THREADS) {
-                    int32_t w = b.col[e];
-                    int32_t st = b.stamp[w];
-                    if (st == r) {
-                        destroyed += (v < w) ? 1 : 0;
-                    } else if (st > r) {
-                        destroyed += 1;
-                        dec_deg(b, w, 1, k, r);
-                    }
-                }
-            } else {
-                destroyed += h3_block_range<TAIL_WAVES>(b, v, rv0, rv1, r, k, sKey, sVal, sPre, sSt, sW, sCnt);
-            }
-        }
-        destroyed = wave_sum(destroyed);
-        if (L == 0) sRed[wv] = destroyed;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            u64 t = 0;
-            for (int i = 0; i < TAIL_WAVES; i++) t += sRed[i];
-            c->destroyed += t;
-            finish_round(c);
-        }
+        hash_flush(b, hs, r, s0, min(s0 + SLOTS_PER_CHUNK, hs.size), lane(), WAVE);
     }
 }
 
@@ -729,13 +656,13 @@ struct PeelCtx {
     }
     __device__ __forceinline__ void add(int32_t x, u64 cnt) const {
         const int32_t r = b.ctl->round;
-        if (b.stamp[x] > r) dec_deg(b, x, cnt, round_level(b.ctl), r);
+        if (b.stamp[x] > r) dec_deg(b, x, cnt, r);
     }
     __device__ __forceinline__ void add_prefix(int64_t it, u64 t) const {
         const int32_t r = b.ctl->round;
         const int32_t w = root(it);
-        if (b.stamp[w] > r) dec_deg(b, w, t, round_level(b.ctl), r);
-        atomicAdd(&b.ctl->destroyed, t);
+        if (b.stamp[w] > r) dec_deg(b, w, t, r);
+        add_destroyed(b, b.item_v[cls * b.item_cap + it], t);
     }
 };
 
@@ -781,18 +708,6 @@ __global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, int R) {
             }
         }
     }
-}
-
-// end of every grid round: a round that opened a level records it, then the
-// frontier is retired
-__global__ void k_finish_round(PeelBufs b) {
-    PeelCtl *c = b.ctl;
-    if (c->selecting) {
-        record_level(b, c, round_level(c), list_compacts(c));
-        c->selecting = 0;
-    }
-    if (c->nF[c->cur] == 0) return;
-    finish_round(c);
 }
 
 // ---------------------------------------------------------------- adjacency compaction
@@ -894,9 +809,21 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
 
 // ---------------------------------------------------------------- host driver
 
+__global__ void k_init_graphs(PeelBufs b, const u64 *mu, const int64_t *lv_base, u64 k_floor) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.G) return;
+    GraphState s{};
+    s.k = k_floor;
+    s.kcand = ~0ull;
+    s.mu_alive = mu[g];
+    s.lv_base = lv_base ? lv_base[g] : 0;
+    b.gs[g] = s;
+}
+
 __global__ void k_peel_init(PeelBufs b, const uint8_t *alive0, int32_t *list0, int32_t *count) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     const int64_t lim = ((int64_t)b.n + WAVE - 1) / WAVE * WAVE;
+    constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int64_t);
     for (int64_t v = blockIdx.x * (int64_t)BLOCK + threadIdx.x; v - lane() < lim; v += stride) {
         bool in = v < b.n && (alive0 == nullptr || alive0[v] != 0);
         if (v < b.n) {
@@ -904,11 +831,19 @@ __global__ void k_peel_init(PeelBufs b, const uint8_t *alive0, int32_t *list0, i
             b.core[v] = 0;
         }
         wave_push(in, (int32_t)v, list0, count);
+        wave_add_by_graph<unsigned long long>(in ? graph_of(b, (int32_t)v) : -1,
+                                              (unsigned long long *)&b.gs[0].n_alive, GS_STRIDE);
     }
 }
 
-__global__ void k_set_alive(PeelBufs b) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.ctl->n_alive = b.ctl->nlist[0];
+// every graph with alive vertices opens its first level
+__global__ void k_start_graphs(PeelBufs b) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < b.G && b.gs[g].n_alive > 0) {
+        b.gs[g].sel = 1;
+        atomicAdd(&b.ctl->nsel[0], 1);
+    }
+    if (g == 0) b.ctl->n_alive = b.ctl->nlist[0];
 }
 
 template <int R>
@@ -935,41 +870,36 @@ static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t 
     }
 }
 
-// Alive-vertex count at or below which the single-workgroup tail finishes the
-// peel (h <= 3).  Grid rounds spread a hub's pairs over the whole chip and
-// beat the tail on power-law graphs, so by default the tail is off;
-// DSD_TAIL_T sets it for experiments.
-static int64_t tail_threshold(int h) {
-    if (h > 3) return 0;
-    const char *e = getenv("DSD_TAIL_T");
-    return e ? atoll(e) : 0;
-}
-
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc, KernelTimes *kt) {
+                hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
+    const int32_t G = grp ? grp->G : 1;
     PeelBufs b{};
     b.n = n;
     b.h = h;
+    b.G = G;
+    b.gid = grp ? grp->gid : nullptr;
     b.row_ptr = g.row_ptr;
     b.col = g.col;
     b.dag_off = g.dag_off;
     b.ctl = sc.get_n<PeelCtl>(1);
+    b.gs = sc.get_n<GraphState>(G);
     b.stamp = sc.get_n<int32_t>(n);
     b.deg = deg;
     b.core = core;
     b.F = sc.get_n<int32_t>(2 * (int64_t)n);
     b.lists = sc.get_n<int32_t>(2 * (int64_t)n);
-    b.lv_k = sc.get_n<u64>(n + 1);
-    b.lv_size = sc.get_n<u64>(n + 1);
-    b.lv_mu = sc.get_n<u64>(n + 1);
+    const int64_t lv_total = grp ? grp->lv_total : (int64_t)n + 1;
+    b.lv_k = sc.get_n<u64>(lv_total);
+    b.lv_size = sc.get_n<u64>(lv_total);
+    b.lv_mu = sc.get_n<u64>(lv_total);
     if (h == 3) {
         // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK
         b.bcap = (int64_t)n + 2 * g.m / CHUNK + 1;
         b.B = sc.get_n<int64_t>(2 * b.bcap);
-        // a vertex of degree d > CHUNK takes SLOTS_PER_CHUNK * ceil(d / CHUNK) <= 4d
+        // a vertex of degree d > SMALL_DEG takes SLOTS_PER_CHUNK * ceil(d / CHUNK) < 4d
         // slots, and no vertex is in two frontiers: 8m slots per half suffice
         b.hcap = 8 * g.m + SLOTS_PER_CHUNK;
         b.hkey = sc.get_n<int32_t>(2 * b.hcap);
@@ -992,14 +922,16 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         if (g.maxdout > 1280 && R >= 3)
             throw Error(-5, "an out-neighbourhood exceeds 1280 vertices (limit of the bitmap kernels, h >= 5)");
     }
-    PeelCtl init{};
-    init.k = k_floor;
-    init.kcand = ~0ull;
-    init.mu_alive = mu;
-    init.tail_T = tail_threshold(h);
-    DSD_HIP(hipMemcpyAsync(b.ctl, &init, sizeof(PeelCtl), hipMemcpyHostToDevice, s));
+    const u64 *mu_dev = grp ? grp->mu : nullptr;
+    if (!mu_dev) {
+        u64 *m1 = sc.get_n<u64>(1);
+        fill_u64(m1, mu, 1, s);
+        mu_dev = m1;
+    }
+    fill_i32((int32_t *)b.ctl, 0, (int64_t)(sizeof(PeelCtl) / sizeof(int32_t)), s);
+    k_init_graphs<<<grid_for(G, 256), 256, 0, s>>>(b, mu_dev, grp ? grp->lv_base : nullptr, k_floor);
     k_peel_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b, alive0, b.lists, &b.ctl->nlist[0]);
-    k_set_alive<<<1, 1, 0, s>>>(b);
+    k_start_graphs<<<grid_for(G, 256), 256, 0, s>>>(b);
     int64_t *pinned = nullptr;
     DSD_HIP(hipHostMalloc((void **)&pinned, 2 * sizeof(int64_t), hipHostMallocDefault));
     DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1020,7 +952,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         compact_adjacency(b, s, sc);
         compacted_at = n_alive;
     }
-    while (n_alive > init.tail_T) {
+    while (n_alive > 0) {
         if (compacting && n_alive < compacted_at / 2) {
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;
@@ -1030,13 +962,11 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
             if (h == 2) {
                 k_process_h2<<<gproc, BLOCK, 0, s>>>(b);
-                k_finish_round<<<1, 1, 0, s>>>(b);
             } else if (h == 3) {
                 k_process_h3_small<<<gproc, BLOCK, 0, s>>>(b);
                 k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
                 k_h3_probe<<<gproc, BLOCK, 0, s>>>(b);
                 k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
-                k_finish_round<<<1, 1, 0, s>>>(b);
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
@@ -1045,7 +975,12 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                     case 4: launch_peel_items<4>(g, b, s, gS); break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
-                k_finish_round<<<1, 1, 0, s>>>(b);
+            }
+            if (G == 1) {
+                k_finish_one<<<1, 1, 0, s>>>(b);
+            } else {
+                k_finish_graphs<<<grid_for(G, 256), 256, 0, s>>>(b);
+                k_finish_global<<<1, 1, 0, s>>>(b);
             }
         }
         steps += chunk;
@@ -1057,11 +992,6 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             throw Error(-3, "peel did not converge");
         }
         if (chunk < 32) chunk *= 2;
-    }
-    if (n_alive > 0) {
-        if (compacting && n_alive < compacted_at) compact_adjacency(b, s, sc);
-        if (h == 2) k_peel_tail<2><<<1, TAIL_THREADS, 0, s>>>(b);
-        else k_peel_tail<3><<<1, TAIL_THREADS, 0, s>>>(b);
     }
     (void)hipHostFree(pinned);
     if (kt) {
@@ -1075,21 +1005,29 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         (void)hipEventDestroy(e1);
     }
     PeelCtl fin;
+    std::vector<GraphState> gst(G);
     DSD_HIP(hipMemcpyAsync(&fin, b.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(gst.data(), b.gs, G * sizeof(GraphState), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     if (fin.n_alive != 0) throw Error(-3, "peel ended with alive vertices");
     res.rounds = fin.round;
-    res.levels = fin.nlevels;
-    res.level_k.resize(fin.nlevels);
-    res.level_size.resize(fin.nlevels);
-    res.level_mu.resize(fin.nlevels);
-    if (fin.nlevels > 0) {
-        DSD_HIP(hipMemcpyAsync(res.level_k.data(), b.lv_k, fin.nlevels * sizeof(u64), hipMemcpyDeviceToHost, s));
-        DSD_HIP(hipMemcpyAsync(res.level_size.data(), b.lv_size, fin.nlevels * sizeof(u64), hipMemcpyDeviceToHost, s));
-        DSD_HIP(hipMemcpyAsync(res.level_mu.data(), b.lv_mu, fin.nlevels * sizeof(u64), hipMemcpyDeviceToHost, s));
-        DSD_HIP(hipStreamSynchronize(s));
-        res.kmax = res.level_k.back();
+    res.graph_levels.resize(G);
+    for (int32_t i = 0; i < G; i++) {
+        if (gst[i].n_alive != 0) throw Error(-3, "peel ended with alive vertices in a graph");
+        res.graph_levels[i] = gst[i].nlevels;
+        res.levels += gst[i].nlevels;
     }
+    const int64_t ncopy = G == 1 ? (int64_t)gst[0].nlevels : lv_total;
+    res.level_k.resize(ncopy);
+    res.level_size.resize(ncopy);
+    res.level_mu.resize(ncopy);
+    if (ncopy > 0) {
+        DSD_HIP(hipMemcpyAsync(res.level_k.data(), b.lv_k, ncopy * sizeof(u64), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipMemcpyAsync(res.level_size.data(), b.lv_size, ncopy * sizeof(u64), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipMemcpyAsync(res.level_mu.data(), b.lv_mu, ncopy * sizeof(u64), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+    }
+    if (G == 1 && gst[0].nlevels > 0) res.kmax = res.level_k.back();
     return res;
 }
 
