@@ -42,8 +42,11 @@ typedef enum {
     DSD_ENOMEM = -2,     /* device or host allocation failed */
     DSD_EDEVICE = -3,    /* HIP runtime error or no GPU */
     DSD_EOVERFLOW = -4,  /* a count or a scaled flow capacity would overflow 64 bits */
-    DSD_EUNSUPPORTED = -5 /* graph shape beyond a documented limit: an out-neighbourhood above 1280
-                             vertices for h >= 4, or an exact-step component above 10^8 h-cliques */
+    DSD_EUNSUPPORTED = -5, /* graph shape beyond a documented limit: an out-neighbourhood above 1280
+                              vertices for h >= 4, or an exact-step component above 10^8 h-cliques */
+    DSD_EBUSY = -6,       /* server: no free slot, or the request already runs */
+    DSD_ETIMEDOUT = -7,   /* server: the request is not done within the wait */
+    DSD_ECANCELED = -8    /* server: the request was cancelled */
 } dsd_status;
 
 enum { DSD_MEM_HOST = 0, DSD_MEM_DEVICE = 1 };
@@ -131,6 +134,85 @@ dsd_status dsd_core_app(dsd_graph g, int h, int out_mem, uint8_t *member, uint64
  */
 dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
                           dsd_rational *rho_opt);
+
+/* ------------------------------------------------------------------ batches
+ *
+ * dsd_batch_run runs one operation on many graphs at once and gives every
+ * graph the result its single-graph entry point would give. */
+typedef enum {
+    DSD_OP_DEGREES = 0,   /* dsd_clique_degrees */
+    DSD_OP_CORE = 1,      /* dsd_clique_core */
+    DSD_OP_APP = 2,       /* dsd_core_app */
+    DSD_OP_EXACT = 3      /* dsd_core_exact */
+} dsd_op;
+
+/* Scalar outcome for one graph of a batch or one served request. */
+typedef struct {
+    dsd_status status;       /* this graph's outcome */
+    int32_t h, op;
+    uint64_t num_cliques;    /* mu(G, Psi) (Definition 4) */
+    uint64_t kmax;           /* CORE, APP, EXACT: the largest clique-core number */
+    dsd_rational density;    /* APP: density of the (k_max, Psi)-core; EXACT: rho_opt */
+    uint64_t members;        /* APP, EXACT: size of the member set */
+    uint64_t peel_rounds;    /* rounds of the peel this graph took part in */
+    double t_ms;             /* wall time of the batch group that computed it */
+} dsd_result;
+
+/*
+ * Graphs with the same h are enumerated and peeled together as one disjoint
+ * union in which each graph keeps its own level: cliques never cross graphs,
+ * so Definition 3 and the (k, Psi)-cores of Definition 6 hold graph by
+ * graph, and the union needs as many peel rounds as its slowest graph
+ * instead of their sum.  Every graph's decomposition is kept on its handle,
+ * as a single-graph call would keep it.  DSD_OP_EXACT then runs the locate
+ * steps and the host exact search of Algorithm 4 graph by graph, on up to 16
+ * host threads.
+ *   graphs: count distinct handles (a handle twice -> DSD_EINVAL).
+ *   h:      count values in [2, 6].
+ *   outs:   NULL, or count pointers, each NULL or an array of n_i entries:
+ *           uint64_t for DEGREES (clique-degrees) and CORE (core numbers),
+ *           uint8_t member flags for APP and EXACT; residency out_mem.
+ *   results: count entries, written for every graph.
+ * Argument errors (DSD_EINVAL) are reported before any work.  Otherwise the
+ * call returns DSD_OK when every graph succeeded, else the status of the
+ * first graph that failed (its message in dsd_last_error); each graph's own
+ * status is in its result.  Synchronous.
+ */
+dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, const int *h, int op, int out_mem,
+                         void *const *outs, dsd_result *results);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A server owns one worker thread.  The worker takes the queued requests
+ * that fit the device-memory budget, groups them (distinct graphs, one op
+ * per group), runs every group through dsd_batch_run and completes their
+ * tickets.  A request's footprint is estimated as 160 bytes per vertex plus
+ * 192 bytes per edge (the peel's buffers dominate); requests start only while
+ * the running footprints fit in hbm_budget_bytes, and one that could never
+ * fit is refused at submit with DSD_ENOMEM.  At most max_slots requests are
+ * queued or running at once (DSD_EBUSY beyond). */
+typedef struct dsd_server_s *dsd_server;
+
+dsd_status dsd_server_create(size_t hbm_budget_bytes, int max_slots, dsd_server *out);
+
+/* Queue op (a dsd_op) with h on g.  out: NULL, or n entries as in
+ * dsd_batch_run, written before the ticket completes.  g must stay alive and
+ * unused elsewhere until then.  *ticket identifies the request. */
+dsd_status dsd_server_submit(dsd_server s, dsd_graph g, int h, int op, int out_mem, void *out, uint64_t *ticket);
+
+/* Wait up to timeout_us microseconds (< 0: without limit) for a ticket.
+ * DSD_OK: *out (may be NULL) holds the result and the ticket is released.
+ * DSD_ETIMEDOUT: not done yet.  DSD_ECANCELED: it was cancelled (released).
+ * DSD_EINVAL: unknown or already released ticket. */
+dsd_status dsd_server_wait(dsd_server s, uint64_t ticket, int64_t timeout_us, dsd_result *out);
+
+/* Cancel a request that has not started (DSD_OK); a started one runs to
+ * its end (DSD_EBUSY). */
+dsd_status dsd_server_cancel(dsd_server s, uint64_t ticket);
+
+/* Cancel every queued request, finish the running group, stop the worker
+ * and free the server.  NULL is accepted. */
+dsd_status dsd_server_destroy(dsd_server s);
 
 /* Statistics of the last compute call on g.  A handle keeps the core
  * decomposition of every h it has computed, so dsd_clique_core and

@@ -10,75 +10,20 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dsd.h"
-#include "exact.hpp"
-#include "graph.hpp"
+#include "handle.hpp"
 
 using namespace dsd;
 
-// A full (k, Psi)-core decomposition, kept on the handle: the graph never
-// changes, so later calls with the same h reuse it.
-struct Decomp {
-    bool valid = false;
-    u64 mu = 0;
-    u64 *core = nullptr;            // device, rank space, length n
-    PeelResult levels;              // level table
-    double t_enum_ms = 0, t_peel_ms = 0;
-    KernelTimes kt;
-};
-
-struct dsd_graph_s {
-    DevGraph g;
-    hipStream_t stream = nullptr;
-    Scratch sc;
-    dsd_stats stats{};
-    Decomp dec[7];                  // by h
-    ~dsd_graph_s() {
-        for (Decomp &d : dec) (void)hipFree(d.core);
-        free_graph(g);
-    }
-};
-
 static thread_local std::string g_err;
 
-static dsd_status fail(int st, const std::string &msg) {
+namespace dsd {
+
+dsd_status fail(int st, const std::string &msg) {
     g_err = msg;
     return (dsd_status)st;
 }
 
-#define DSD_TRY(...)                                                      \
-    try {                                                                 \
-        __VA_ARGS__                                                       \
-    } catch (const dsd::Error &e) {                                       \
-        return fail(e.status, e.what());                                  \
-    } catch (const std::bad_alloc &) {                                    \
-        return fail(DSD_ENOMEM, "host allocation failed");                \
-    } catch (const std::exception &e) {                                   \
-        return fail(DSD_EDEVICE, e.what());                               \
-    }
 
-namespace {
-
-struct Timer {
-    hipStream_t s;
-    hipEvent_t a, b;
-    explicit Timer(hipStream_t st) : s(st) {
-        DSD_HIP(hipEventCreate(&a));
-        DSD_HIP(hipEventCreate(&b));
-        DSD_HIP(hipEventRecord(a, s));
-    }
-    double stop() {
-        DSD_HIP(hipEventRecord(b, s));
-        DSD_HIP(hipEventSynchronize(b));
-        float ms = 0;
-        DSD_HIP(hipEventElapsedTime(&ms, a, b));
-        return ms;
-    }
-    ~Timer() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-    }
-};
 
 void check_device() {
     int n = 0;
@@ -129,7 +74,7 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
 }
 
 // clique-degrees (rank space) and mu; throws on overflow
-u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelTimes *kt = nullptr) {
+u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelTimes *kt) {
     hipStream_t s = G->stream;
     if (!clique_degrees(G->g, h, mask, deg, s, G->sc, kt))
         throw Error(DSD_EOVERFLOW, "clique counts could exceed 64 bits");
@@ -203,7 +148,95 @@ void write_u8(dsd_graph_s *G, const uint8_t *r, uint8_t *out, int mem) {
     write_out<uint8_t>(G, r, out, mem, gather_to_orig_u8);
 }
 
-}  // namespace
+
+// CoreExact (Algorithm 4) on a handle: Pruning1 and Pruning2 on the GPU from
+// the cached decomposition, the exact search over the located components on
+// the host.
+dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
+    const int32_t n = G->g.n;
+    hipStream_t s = G->stream;
+    const Decomp &D = decompose(G, h);
+    decomp_stats(G, D);
+    fill_u8(res, 0, n, s);
+    dsd_rational rho{0, 1};
+    const u64 mu = D.mu;
+    u64 *core = D.core;
+    if (mu == 0) return rho;
+    const PeelResult &pr = D.levels;
+    Timer tl(s);
+    // Pruning1: rho' = max over levels of mu(R_k) / |R_k|
+    u64 a = 0, b = 1;
+    int64_t best_level = -1;
+    for (int64_t i = 0; i < (int64_t)pr.level_k.size(); i++)
+        if (pr.level_size[i] > 0 && rat_gt(pr.level_mu[i], pr.level_size[i], a, b)) {
+            a = pr.level_mu[i];
+            b = pr.level_size[i];
+            best_level = i;
+        }
+    const u64 k1 = ceil_div_u(a, b);
+    // Pruning2: components of R_{k'} and their densities
+    uint8_t *m1 = G->sc.get_n<uint8_t>(n);
+    int32_t *lab1 = G->sc.get_n<int32_t>(n);
+    u64 *d1 = G->sc.get_n<u64>(n), *sz = G->sc.get_n<u64>(n), *ds = G->sc.get_n<u64>(n);
+    mask_core_at_least(core, n, k1, m1, s);
+    components(G->g, m1, lab1, s, G->sc);
+    degrees_and_mu(G, h, m1, d1);
+    component_sums(lab1, d1, n, sz, ds, s);
+    std::vector<CompInfo> c1;
+    collect_components(lab1, sz, ds, n, c1, s, G->sc);
+    u64 rn = 0, rd = 1;
+    int32_t best_root = -1;
+    for (const CompInfo &c : c1)
+        if (c.size > 0 && c.dsum > 0 && (best_root < 0 || rat_gt(c.dsum, c.size * (u64)h, rn, rd))) {
+            rn = c.dsum;
+            rd = c.size * (u64)h;
+            best_root = c.root;
+        }
+    dsd_rational r2 = make_rational(rn, rd);
+    const u64 k2 = std::max(k1, ceil_div_u(r2.num, r2.den));
+    // D starts as the better of the level set attaining rho' and the
+    // component attaining rho''; both densities are lower bounds on rho_opt
+    if (rat_gt(a, b, r2.num, r2.den) && best_level >= 0) {
+        mask_core_at_least(core, n, pr.level_k[best_level], res, s);
+        rho = make_rational(a, b);
+    } else {
+        if (best_root >= 0) mask_label_equal(lab1, n, best_root, res, s);
+        rho = r2;
+    }
+    // components of R_{k''} go to the host
+    uint8_t *m2 = m1;
+    int32_t *lab2 = lab1;
+    if (k2 > k1) {
+        m2 = G->sc.get_n<uint8_t>(n);
+        lab2 = G->sc.get_n<int32_t>(n);
+        mask_core_at_least(core, n, k2, m2, s);
+        components(G->g, m2, lab2, s, G->sc);
+    }
+    LocatedCore lc;
+    extract_induced(G->g, m2, lab2, core, lc, s, G->sc);
+    G->stats.located_vertices = lc.rank.size();
+    G->stats.t_locate_ms = tl.stop();
+    auto t0 = std::chrono::steady_clock::now();
+    Rational l{rho.num, rho.den};
+    std::vector<int32_t> bestset;
+    ExactStats es;
+    bool improved = exact_search(lc, h, k2, l, bestset, es);
+    G->stats.t_exact_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    G->stats.flow_calls = es.flow_calls;
+    G->stats.flow_nodes_max = es.max_nodes;
+    G->stats.t_flow_build_ms = es.build_ms;
+    G->stats.t_flow_ms = es.flow_ms;
+    if (improved) {
+        rho = dsd_rational{l.num, l.den};
+        std::vector<uint8_t> hm(n, 0);
+        for (int32_t v : bestset) hm[lc.rank[v]] = 1;
+        DSD_HIP(hipMemcpyAsync(res, hm.data(), n, hipMemcpyHostToDevice, s));
+        DSD_HIP(hipStreamSynchronize(s));
+    }
+    return rho;
+}
+
+}  // namespace dsd
 
 extern "C" {
 
@@ -215,6 +248,9 @@ const char *dsd_status_str(dsd_status s) {
         case DSD_EDEVICE: return "DSD_EDEVICE";
         case DSD_EOVERFLOW: return "DSD_EOVERFLOW";
         case DSD_EUNSUPPORTED: return "DSD_EUNSUPPORTED";
+        case DSD_EBUSY: return "DSD_EBUSY";
+        case DSD_ETIMEDOUT: return "DSD_ETIMEDOUT";
+        case DSD_ECANCELED: return "DSD_ECANCELED";
     }
     return "DSD_UNKNOWN";
 }
@@ -430,89 +466,9 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
         begin_stats(G);
-        hipStream_t s = G->stream;
-        Timer tm(s);
-        const Decomp &D = decompose(G, h);
-        decomp_stats(G, D);
+        Timer tm(G->stream);
         uint8_t *res = G->sc.get_n<uint8_t>(n);
-        fill_u8(res, 0, n, s);
-        dsd_rational rho{0, 1};
-        const u64 mu = D.mu;
-        u64 *core = D.core;
-        if (mu > 0) {
-            const PeelResult &pr = D.levels;
-            Timer tl(s);
-            // Pruning1: rho' = max over levels of mu(R_k) / |R_k|
-            u64 a = 0, b = 1;
-            int64_t best_level = -1;
-            for (int64_t i = 0; i < pr.levels; i++)
-                if (pr.level_size[i] > 0 && rat_gt(pr.level_mu[i], pr.level_size[i], a, b)) {
-                    a = pr.level_mu[i];
-                    b = pr.level_size[i];
-                    best_level = i;
-                }
-            const u64 k1 = ceil_div_u(a, b);
-            // Pruning2: components of R_{k'} and their densities
-            uint8_t *m1 = G->sc.get_n<uint8_t>(n);
-            int32_t *lab1 = G->sc.get_n<int32_t>(n);
-            u64 *d1 = G->sc.get_n<u64>(n), *sz = G->sc.get_n<u64>(n), *ds = G->sc.get_n<u64>(n);
-            mask_core_at_least(core, n, k1, m1, s);
-            components(G->g, m1, lab1, s, G->sc);
-            degrees_and_mu(G, h, m1, d1);
-            component_sums(lab1, d1, n, sz, ds, s);
-            std::vector<CompInfo> c1;
-            collect_components(lab1, sz, ds, n, c1, s, G->sc);
-            u64 rn = 0, rd = 1;
-            int32_t best_root = -1;
-            for (const CompInfo &c : c1)
-                if (c.size > 0 && c.dsum > 0 && (best_root < 0 || rat_gt(c.dsum, c.size * (u64)h, rn, rd))) {
-                    rn = c.dsum;
-                    rd = c.size * (u64)h;
-                    best_root = c.root;
-                }
-            dsd_rational r2 = make_rational(rn, rd);
-            const u64 k2 = std::max(k1, ceil_div_u(r2.num, r2.den));
-            // D starts as the better of the level set attaining rho' and the
-            // component attaining rho''; both densities are lower bounds on rho_opt
-            if (rat_gt(a, b, r2.num, r2.den) && best_level >= 0) {
-                mask_core_at_least(core, n, pr.level_k[best_level], res, s);
-                rho = make_rational(a, b);
-            } else {
-                if (best_root >= 0) mask_label_equal(lab1, n, best_root, res, s);
-                rho = r2;
-            }
-            // components of R_{k''} go to the host
-            uint8_t *m2 = m1;
-            int32_t *lab2 = lab1;
-            if (k2 > k1) {
-                m2 = G->sc.get_n<uint8_t>(n);
-                lab2 = G->sc.get_n<int32_t>(n);
-                mask_core_at_least(core, n, k2, m2, s);
-                components(G->g, m2, lab2, s, G->sc);
-            }
-            LocatedCore lc;
-            extract_induced(G->g, m2, lab2, core, lc, s, G->sc);
-            G->stats.located_vertices = lc.rank.size();
-            G->stats.t_locate_ms = tl.stop();
-            auto t0 = std::chrono::steady_clock::now();
-            Rational l{rho.num, rho.den};
-            std::vector<int32_t> bestset;
-            ExactStats es;
-            bool improved = exact_search(lc, h, k2, l, bestset, es);
-            G->stats.t_exact_ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            G->stats.flow_calls = es.flow_calls;
-            G->stats.flow_nodes_max = es.max_nodes;
-            G->stats.t_flow_build_ms = es.build_ms;
-            G->stats.t_flow_ms = es.flow_ms;
-            if (improved) {
-                rho = dsd_rational{l.num, l.den};
-                std::vector<uint8_t> hm(n, 0);
-                for (int32_t v : bestset) hm[lc.rank[v]] = 1;
-                DSD_HIP(hipMemcpyAsync(res, hm.data(), n, hipMemcpyHostToDevice, s));
-                DSD_HIP(hipStreamSynchronize(s));
-            }
-        }
+        const dsd_rational rho = core_exact_run(G, h, res);
         write_u8(G, res, member, out_mem);
         if (rho_opt) *rho_opt = rho;
         G->stats.t_total_ms = tm.stop();

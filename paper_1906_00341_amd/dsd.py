@@ -5,7 +5,8 @@ arrays / torch tensors to pointers and status codes to exceptions.  There is
 no CPU fallback: a missing library or GPU raises.
 
 Names follow the C ABI: ``build_csr``, ``clique_degrees``, ``clique_core``,
-``core_app``, ``core_exact``.
+``core_app``, ``core_exact``, ``batch_run`` and the ``Server`` class
+(``dsd_server_*``).
 """
 from __future__ import annotations
 
@@ -22,11 +23,17 @@ DSD_MEM_HOST = 0
 DSD_MEM_DEVICE = 1
 
 STATUS = {0: "DSD_OK", -1: "DSD_EINVAL", -2: "DSD_ENOMEM", -3: "DSD_EDEVICE",
-          -4: "DSD_EOVERFLOW", -5: "DSD_EUNSUPPORTED"}
+          -4: "DSD_EOVERFLOW", -5: "DSD_EUNSUPPORTED", -6: "DSD_EBUSY", -7: "DSD_ETIMEDOUT",
+          -8: "DSD_ECANCELED"}
+DSD_EBUSY, DSD_ETIMEDOUT, DSD_ECANCELED = -6, -7, -8
+
+OP_DEGREES, OP_CORE, OP_APP, OP_EXACT = 0, 1, 2, 3
+OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT}
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
            "dsd_clique_core", "dsd_core_app", "dsd_core_exact", "dsd_last_stats",
-           "dsd_status_str", "dsd_last_error"]
+           "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
+           "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
 
 
 class DsdError(RuntimeError):
@@ -54,6 +61,19 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Result(C.Structure):
+    """dsd_result: the scalar outcome of one graph of a batch or one served request."""
+    _fields_ = [("status", C.c_int), ("h", C.c_int32), ("op", C.c_int32),
+                ("num_cliques", C.c_uint64), ("kmax", C.c_uint64), ("density", Rational),
+                ("members", C.c_uint64), ("peel_rounds", C.c_uint64), ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "density"}
+        d["density"] = Fraction(self.density.num, self.density.den or 1)
+        return d
+
+
+_NOT_WRITTEN = -999
 _lib = None
 
 
@@ -80,10 +100,16 @@ def load(path: str = LIB_PATH):
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
     lib.dsd_core_exact.argtypes = [P, I, I, P, C.POINTER(Rational)]
     lib.dsd_last_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.dsd_batch_run.argtypes = [I32, C.POINTER(P), C.POINTER(I), I, I, C.POINTER(P), C.POINTER(Result)]
+    lib.dsd_server_create.argtypes = [C.c_size_t, I, C.POINTER(P)]
+    lib.dsd_server_submit.argtypes = [P, P, I, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_server_wait.argtypes = [P, C.c_uint64, I64, C.POINTER(Result)]
+    lib.dsd_server_cancel.argtypes = [P, C.c_uint64]
+    lib.dsd_server_destroy.argtypes = [P]
     lib.dsd_status_str.argtypes = [I]
     lib.dsd_status_str.restype = C.c_char_p
     lib.dsd_last_error.restype = C.c_char_p
-    for f in EXPORTS[:8]:
+    for f in EXPORTS[:-2]:
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -211,3 +237,85 @@ def core_exact(g: Graph, h: int, out=None):
 
 def status_str(s: int) -> str:
     return load().dsd_status_str(int(s)).decode()
+
+
+def _op(op) -> int:
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def batch_run(graphs, hs, op, outs=None, out_mem=None):
+    """dsd_batch_run -> list of result dicts (one per graph, each with its own
+    ``status``).  outs: None or a list (entries None, numpy arrays or torch
+    tensors of n_i entries: uint64 for degrees/core, uint8 for app/exact; all
+    in the same memory).  Raises DsdError for argument errors."""
+    lib = load()
+    cnt = len(graphs)
+    if isinstance(hs, int):
+        hs = [hs] * cnt
+    arr_g = (C.c_void_p * cnt)(*[g.handle for g in graphs])
+    arr_h = (C.c_int * cnt)(*[int(x) for x in hs])
+    res = (Result * cnt)()
+    for r in res:
+        r.status = _NOT_WRITTEN
+    keep, arr_o, mem = [], None, DSD_MEM_HOST
+    if outs is not None:
+        ptrs = []
+        for o in outs:
+            if o is None:
+                ptrs.append(None)
+                continue
+            p, m, k = _ptr(o)
+            ptrs.append(p)
+            keep.append(k)
+            mem = m
+        arr_o = (C.c_void_p * cnt)(*ptrs)
+    if out_mem is not None:
+        mem = out_mem
+    rc = lib.dsd_batch_run(cnt, arr_g, arr_h, _op(op), mem, arr_o, res)
+    if cnt and res[0].status == _NOT_WRITTEN:
+        _check(rc)
+    return [r.as_dict() for r in res]
+
+
+class Server:
+    """dsd_server_*: queued requests served in batches by a worker thread."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        lib = load()
+        self._s = C.c_void_p()
+        _check(lib.dsd_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(self._s)))
+        self._keep = {}
+
+    def submit(self, g: Graph, h: int, op, out=None) -> int:
+        p, mem, k = (None, DSD_MEM_HOST, None) if out is None else _ptr(out)
+        t = C.c_uint64()
+        _check(_lib.dsd_server_submit(self._s, g.handle, int(h), _op(op), mem, p, C.byref(t)))
+        self._keep[int(t.value)] = (g, k)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """(status, result dict or None): status 0, DSD_ETIMEDOUT or DSD_ECANCELED."""
+        r = Result()
+        rc = _lib.dsd_server_wait(self._s, int(ticket), int(timeout_us), C.byref(r))
+        if rc == DSD_ETIMEDOUT:
+            return rc, None
+        self._keep.pop(int(ticket), None)
+        if rc == DSD_ECANCELED:
+            return rc, None
+        _check(rc)
+        return 0, r.as_dict()
+
+    def cancel(self, ticket: int) -> int:
+        rc = _lib.dsd_server_cancel(self._s, int(ticket))
+        if rc not in (0, DSD_EBUSY):
+            _check(rc)
+        return rc
+
+    def close(self):
+        if self._s is not None and _lib is not None:
+            _lib.dsd_server_destroy(self._s)
+            self._s = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()

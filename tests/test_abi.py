@@ -42,3 +42,23 @@ def test_null_and_bad_arguments_are_rejected_without_touching_a_gpu():
     assert lib.dsd_build_csr(3, 0, None, None, 7, None, ctypes.byref(h)) == -1
     assert lib.dsd_graph_free(None) == 0
     assert lib.dsd_clique_degrees(None, 3, 0, None, None) == -1
+
+
+def test_batch_and_server_arguments_are_rejected_without_touching_a_gpu():
+    lib = dsd.load()
+    res = (dsd.Result * 1)()
+    assert lib.dsd_batch_run(-1, None, None, 0, 0, None, res) == -1
+    assert lib.dsd_batch_run(0, None, None, 0, 0, None, res) == 0          # empty batch
+    assert lib.dsd_batch_run(1, None, None, 0, 0, None, res) == -1         # NULL arrays
+    g = (ctypes.c_void_p * 1)(None)
+    hs = (ctypes.c_int * 1)(3)
+    assert lib.dsd_batch_run(1, g, hs, 0, 0, None, res) == -1              # NULL handle
+    assert lib.dsd_batch_run(1, g, hs, 9, 0, None, res) == -1              # unknown op
+    s = ctypes.c_void_p()
+    assert lib.dsd_server_create(0, 4, ctypes.byref(s)) == -1
+    assert lib.dsd_server_create(1 << 30, 0, ctypes.byref(s)) == -1
+    t = ctypes.c_uint64()
+    assert lib.dsd_server_submit(None, None, 3, 0, 0, None, ctypes.byref(t)) == -1
+    assert lib.dsd_server_wait(None, 1, 0, None) == -1
+    assert lib.dsd_server_cancel(None, 1) == -1
+    assert lib.dsd_server_destroy(None) == 0

@@ -1,0 +1,237 @@
+"""Batches and the server (through the C ABI) against the CPU oracle and
+against the single-graph entry points.
+
+A batch peels its graphs as one disjoint union with a level per graph, so
+every graph's results must equal the oracle's, and the batch must take
+exactly as many peel rounds as its slowest graph takes alone.
+"""
+from __future__ import annotations
+
+import math
+import time
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import dsd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    dsd.load()
+
+
+def mixed_graphs(seed=0, count=24):
+    """Small graphs of the batch workload's family plus degenerate ones."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = i % 6
+        if kind == 0:
+            out.append(synth.er_planted(n=int(rng.integers(60, 400)), m=int(rng.integers(200, 2000)), plant=20,
+                                        p=0.6, seed=seed * 100 + i))
+        elif kind in (1, 2):
+            out.append(synth.chung_lu(n=int(rng.integers(200, 3000)), avg_deg=float(rng.uniform(4, 16)),
+                                      beta=float(rng.uniform(2.0, 3.0)), planted=1, plant_size=20, p=0.7,
+                                      seed=seed * 100 + i))
+        elif kind == 3:
+            out.append(synth.complete_graph(int(rng.integers(3, 25))))
+        elif kind == 4:
+            n = int(rng.integers(0, 3))                      # empty, single vertex, or one edge
+            s = np.array([0], np.int32) if n == 2 else np.zeros(0, np.int32)
+            d = np.array([1], np.int32) if n == 2 else np.zeros(0, np.int32)
+            out.append((n, s, d))
+        else:
+            n = int(rng.integers(10, 200))                   # a tree: no triangles
+            s = np.arange(1, n, dtype=np.int32)
+            d = (rng.integers(0, np.arange(1, n))).astype(np.int32)
+            out.append((n, s, d))
+    return out
+
+
+def build_all(graphs):
+    return [dsd.build_csr(n, s, d) for n, s, d in graphs]
+
+
+def density_of(og, h, member):
+    idx = np.nonzero(np.asarray(member))[0]
+    if idx.size == 0:
+        return Fraction(0)
+    off, adj = og.adjacency()
+    keep = np.zeros(og.n, dtype=bool)
+    keep[idx] = True
+    rows = np.repeat(np.arange(og.n), np.diff(off))
+    e = keep[rows] & keep[adj] & (rows < adj)
+    return Fraction(oracle.Graph(og.n, rows[e].astype(np.int32), adj[e].astype(np.int32)).clique_degrees(h)[1],
+                    idx.size)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_batch_core_and_degrees_match_oracle(seed):
+    graphs = mixed_graphs(seed)
+    hs = [2 + (i % 3) for i in range(len(graphs))]
+    handles = build_all(graphs)
+    degs = [np.zeros(max(n, 1), np.uint64) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, hs, "degrees", outs=degs)
+    for (n, s, d), h, r, out in zip(graphs, hs, res, degs):
+        og = oracle.Graph(n, s, d)
+        deg_o, mu_o = og.clique_degrees(h)
+        assert r["status"] == 0 and r["num_cliques"] == mu_o
+        np.testing.assert_array_equal(out[:n], deg_o)
+    cores = [np.zeros(max(n, 1), np.uint64) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, hs, "core", outs=cores)
+    for (n, s, d), h, r, out in zip(graphs, hs, res, cores):
+        core_o, km_o = oracle.Graph(n, s, d).core_decomposition(h)
+        assert r["status"] == 0 and r["kmax"] == km_o
+        np.testing.assert_array_equal(out[:n], core_o)
+
+
+def test_batch_rounds_are_those_of_the_slowest_graph():
+    graphs = mixed_graphs(3, count=12)
+    h = 3
+    alone = []
+    for n, s, d in graphs:
+        g = dsd.build_csr(n, s, d)
+        dsd.clique_core(g, h)
+        alone.append(g.stats()["peel_rounds"])
+    handles = build_all(graphs)
+    res = dsd.batch_run(handles, h, "core")
+    assert all(r["status"] == 0 for r in res)
+    assert max(r["peel_rounds"] for r in res) == max(alone)
+
+
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_batch_app_and_exact_match_oracle(h):
+    graphs = mixed_graphs(4, count=18)
+    handles = build_all(graphs)
+    mems = [np.zeros(max(n, 1), np.uint8) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, h, "app", outs=mems)
+    for (n, s, d), r, out in zip(graphs, res, mems):
+        mem_o, km_o, dens_o = oracle.Graph(n, s, d).inc_app(h)
+        assert r["status"] == 0 and r["kmax"] == km_o and r["density"] == dens_o
+        np.testing.assert_array_equal(out[:n].astype(bool), mem_o)
+        assert r["members"] == int(np.count_nonzero(mem_o))
+    handles = build_all(graphs)
+    mems = [np.zeros(max(n, 1), np.uint8) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, h, "exact", outs=mems)
+    for (n, s, d), r, out in zip(graphs, res, mems):
+        og = oracle.Graph(n, s, d)
+        _, rho_o, _ = og.exact(h, "core")
+        assert r["status"] == 0 and r["density"] == rho_o
+        assert density_of(og, h, out[:n]) == rho_o
+        assert r["members"] == int(np.count_nonzero(out[:n]))
+
+
+def test_batch_device_outputs_and_cached_decomposition():
+    torch = pytest.importorskip("torch")
+    graphs = mixed_graphs(5, count=10)
+    handles = build_all(graphs)
+    outs = [torch.zeros(max(n, 1), dtype=torch.uint64, device="cuda") for n, _, _ in graphs]
+    res = dsd.batch_run(handles, 3, "core", outs=outs)
+    assert all(r["status"] == 0 for r in res)
+    for (n, s, d), g, out in zip(graphs, handles, outs):
+        og = oracle.Graph(n, s, d)
+        core_o, _ = og.core_decomposition(3)
+        np.testing.assert_array_equal(out.cpu().numpy()[:n], core_o)
+        # the handle keeps the batch's decomposition: single-graph calls reuse it
+        core_g, _ = dsd.clique_core(g, 3)
+        np.testing.assert_array_equal(core_g, core_o)
+        mem, rho = dsd.core_exact(g, 3)
+        assert rho == og.exact(3, "core")[1]
+
+
+def test_batch_argument_errors():
+    graphs = mixed_graphs(6, count=3)
+    handles = build_all(graphs)
+    with pytest.raises(dsd.DsdError) as e:
+        dsd.batch_run([handles[0], handles[0]], 3, "core")
+    assert e.value.status == -1
+    with pytest.raises(dsd.DsdError) as e:
+        dsd.batch_run(handles, [3, 7, 3], "core")
+    assert e.value.status == -1
+    assert dsd.batch_run([], 3, "core") == []
+
+
+def test_batch_of_chung_lu_graphs_matches_single_calls():
+    # the batch workload's generator: n log-uniform, exponent and degree drawn per graph
+    specs = synth.batch_specs(count=40, seed=11)
+    graphs = [synth.batch_graph(sp) for sp in specs]
+    hs = [sp["h"] for sp in specs]
+    handles = build_all([(n, s, d) for n, s, d in graphs])
+    cores = [np.zeros(max(n, 1), np.uint64) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, hs, "core", outs=cores)
+    for (n, s, d), h, r, out in zip(graphs, hs, res, cores):
+        g = dsd.build_csr(n, s, d)
+        core1, km1 = dsd.clique_core(g, h)
+        assert r["status"] == 0 and r["kmax"] == km1
+        np.testing.assert_array_equal(out[:n], core1)
+
+
+# ------------------------------------------------------------------ server
+
+def test_server_results_match_single_calls():
+    graphs = mixed_graphs(7, count=16)
+    handles = build_all(graphs)
+    srv = dsd.Server(1 << 34, 64)
+    ops = ["degrees", "core", "app", "exact"]
+    tickets, outs = [], []
+    for i, g in enumerate(handles):
+        n = graphs[i][0]
+        op = ops[i % 4]
+        out = np.zeros(max(n, 1), np.uint64 if op in ("degrees", "core") else np.uint8)
+        outs.append(out)
+        tickets.append(srv.submit(g, 3, op, out))
+    for i, t in enumerate(tickets):
+        st, r = srv.wait(t)
+        assert st == 0 and r["status"] == 0
+        n, s, d = graphs[i]
+        og = oracle.Graph(n, s, d)
+        op = ops[i % 4]
+        if op == "degrees":
+            np.testing.assert_array_equal(outs[i][:n], og.clique_degrees(3)[0])
+        elif op == "core":
+            np.testing.assert_array_equal(outs[i][:n], og.core_decomposition(3)[0])
+        elif op == "app":
+            np.testing.assert_array_equal(outs[i][:n].astype(bool), og.inc_app(3)[0])
+        else:
+            assert r["density"] == og.exact(3, "core")[1]
+    with pytest.raises(dsd.DsdError):          # a completed ticket is released by its wait
+        srv.wait(tickets[0], 0)
+    srv.close()
+
+
+def test_server_admission_slots_timeout_and_cancel():
+    n, s, d = synth.chung_lu(n=200_000, avg_deg=16, beta=2.2, planted=2, plant_size=100, p=0.6, seed=3)
+    big = dsd.build_csr(n, s, d)
+    small = [dsd.build_csr(*synth.complete_graph(10)) for _ in range(3)]
+    # a request whose footprint exceeds the whole budget is refused
+    tiny = dsd.Server(1 << 20, 8)
+    with pytest.raises(dsd.DsdError) as e:
+        tiny.submit(big, 3, "core")
+    assert e.value.status == -2
+    tiny.close()
+    srv = dsd.Server(1 << 34, 2)
+    t0 = srv.submit(big, 3, "exact")          # runs for a while
+    t1 = srv.submit(small[0], 3, "core")
+    with pytest.raises(dsd.DsdError) as e:    # both slots are taken until t0 completes
+        srv.submit(small[1], 3, "core")
+    assert e.value.status == dsd.DSD_EBUSY
+    st, _ = srv.wait(t0, 0)
+    assert st in (0, dsd.DSD_ETIMEDOUT)
+    c = srv.cancel(t1)                         # queued behind t0, or already running
+    st1, r1 = srv.wait(t1)
+    if c == 0:
+        assert st1 == dsd.DSD_ECANCELED
+    else:
+        assert c == dsd.DSD_EBUSY and st1 == 0
+    if st == dsd.DSD_ETIMEDOUT:
+        st, r = srv.wait(t0)
+        assert st == 0 and r["status"] == 0
+    t2 = srv.submit(small[2], 3, "core")
+    st, r = srv.wait(t2)
+    assert st == 0 and r["kmax"] == math.comb(9, 2)
+    srv.close()
