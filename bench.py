@@ -90,6 +90,127 @@ def cpu_baseline(workload: str, seed: int):
             "sample": f"{workload} generator at n={n} (m={g.m}, mu={mu}); {stages}; {t:.2f} s, one thread"}
 
 
+def batch_leg(n_graphs: int, seed: int):
+    """Batched vs plain on a bounded sample of the batched mixture (n
+    log-uniform in [100, 50000], Chung-Lu exponent U[2, 3], average degree
+    U[4, 40], h in {2, 3, 4}): the first n_graphs graphs of the 8192-graph
+    mixture.  Op: the (k, Psi)-core decomposition.  Plain = one
+    dsd_clique_core call per graph; batched = one dsd_batch_run."""
+    import torch
+    from paper_1906_00341_amd import dsd, synth
+    specs = synth.batch_specs(count=8192, seed=seed)[:n_graphs]
+    graphs = [synth.batch_graph(sp) for sp in specs]
+    hs = [sp["h"] for sp in specs]
+    handles = []
+    for n, s, d in graphs:
+        handles.append(dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()))
+    torch.cuda.synchronize()
+    mu = 0
+    t0 = time.perf_counter()
+    for g, h in zip(handles, hs):
+        _, km = dsd.clique_core(g, h)
+        mu += g.stats()["num_cliques"]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = dsd.batch_run(handles, hs, "core")
+    t_batch = time.perf_counter() - t0
+    assert all(r["status"] == 0 for r in res)
+    assert sum(r["num_cliques"] for r in res) == mu
+    m = sum(g.info()[1] for g in handles)
+    for g in handles:
+        g.free()
+    return {"graphs": n_graphs, "of": 8192, "edges": m, "h_cliques": mu, "op": "core",
+            "plain_s": t_plain, "batched_s": t_batch,
+            "plain_graphs_per_s": n_graphs / t_plain, "batched_graphs_per_s": n_graphs / t_batch,
+            "plain_h_cliques_per_s": mu / t_plain, "batched_h_cliques_per_s": mu / t_batch,
+            "speedup": t_plain / t_batch,
+            "peel_rounds_batched": max(r["peel_rounds"] for r in res)}
+
+
+def serve_leg(n_requests: int, seed: int):
+    """The server under load: requests drawn 95 % from the batched mixture and
+    5 % from R-MAT scale 20 (a = 0.57, b = c = 0.19), h in {2, 3, 4}, ops 70 %
+    CoreApp, 20 % core decomposition, 10 % CoreExact (R-MAT requests: CoreApp
+    only, whose cost does not depend on the located core).  Pass 1 submits
+    everything at once (saturation throughput); pass 2 submits with Poisson
+    arrivals at half that rate and records each request's latency.  Plain =
+    the same requests as sequential single-graph calls."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    from paper_1906_00341_amd import dsd, synth
+    rng = np.random.default_rng(seed)
+    specs = synth.batch_specs(count=8192, seed=seed + 1)
+    n_rmat = max(1, n_requests // 20)
+    reqs = []
+    rn, rs, rd = synth.rmat(scale=20, edge_factor=16, seed=seed)
+    rmat_graph = (rn, rs, rd)
+    for i in range(n_requests):
+        if i < n_rmat:
+            reqs.append((rmat_graph, int(rng.integers(2, 5)), "app"))
+        else:
+            sp = specs[i]
+            u = rng.random()
+            op = "app" if u < 0.7 else ("core" if u < 0.9 else "exact")
+            reqs.append((synth.batch_graph(sp), sp["h"], op))
+    order = rng.permutation(n_requests)
+    reqs = [reqs[i] for i in order]
+
+    def build():
+        return [dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()) for (n, s, d), _, _ in reqs]
+
+    handles = build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, (_, h, op) in zip(handles, reqs):
+        {"app": dsd.core_app, "core": dsd.clique_core, "exact": dsd.core_exact}[op](g, h)
+    t_plain = time.perf_counter() - t0
+    for g in handles:
+        g.free()
+
+    srv = dsd.Server(64 << 30, 4 * n_requests)
+
+    def run(rate):
+        hs = build()
+        torch.cuda.synchronize()
+        lat = [0.0] * n_requests
+        with cf.ThreadPoolExecutor(max_workers=64) as pool:
+            futs = []
+            start = time.perf_counter()
+            t_next = start
+            for i, (g, (_, h, op)) in enumerate(zip(hs, reqs)):
+                if rate:
+                    t_next += rng.exponential(1.0 / rate)
+                    delay = t_next - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                t_sub = time.perf_counter()
+                tk = srv.submit(g, h, op)
+
+                def waiter(tk=tk, t_sub=t_sub, i=i):
+                    st, r = srv.wait(tk)
+                    lat[i] = time.perf_counter() - t_sub
+                    return st, r
+
+                futs.append(pool.submit(waiter))
+            outs = [f.result() for f in futs]
+            total = time.perf_counter() - start
+        assert all(st == 0 and r["status"] in (0, -5) for st, r in outs)
+        for g in hs:
+            g.free()
+        return total, lat
+
+    t_sat, _ = run(None)
+    qps_sat = n_requests / t_sat
+    t_half, lat = run(0.5 * qps_sat)
+    srv.close()
+    lat_ms = np.sort(np.asarray(lat)) * 1000.0
+    return {"requests": n_requests, "rmat20_requests": n_rmat, "mix": "70% app / 20% core / 10% exact",
+            "plain_qps": n_requests / t_plain, "served_qps_saturation": qps_sat,
+            "offered_qps": 0.5 * qps_sat, "served_qps_at_offered": n_requests / t_half,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +219,10 @@ def main() -> int:
     ap.add_argument("--workload", default="chung_lu_1e6", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=512,
+                    help="graphs of the batched mixture in the batched-vs-plain leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=192,
+                    help="requests in the serving leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is not sharded "
@@ -192,6 +317,10 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_call": bytes_call, "ms_per_call": t_ms, "launches_per_call": launches},
     }
+    if args.batch_graphs > 0:
+        out["batch"] = batch_leg(args.batch_graphs, 7)
+    if args.serve_requests > 0:
+        out["serve"] = serve_leg(args.serve_requests, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
     print(json.dumps(out), flush=True)

@@ -150,7 +150,9 @@ typedef enum {
 typedef struct {
     dsd_status status;       /* this graph's outcome */
     int32_t h, op;
-    uint64_t num_cliques;    /* mu(G, Psi) (Definition 4) */
+    uint64_t num_cliques;    /* mu(G, Psi) (Definition 4); 0 for DSD_OP_APP on a graph of
+                                2^20 edges or more, where CoreApp runs alone (Algorithm 6
+                                never counts the whole graph) */
     uint64_t kmax;           /* CORE, APP, EXACT: the largest clique-core number */
     dsd_rational density;    /* APP: density of the (k_max, Psi)-core; EXACT: rho_opt */
     uint64_t members;        /* APP, EXACT: size of the member set */
@@ -164,7 +166,9 @@ typedef struct {
  * so Definition 3 and the (k, Psi)-cores of Definition 6 hold graph by
  * graph, and the union needs as many peel rounds as its slowest graph
  * instead of their sum.  Every graph's decomposition is kept on its handle,
- * as a single-graph call would keep it.  DSD_OP_EXACT then runs the locate
+ * as a single-graph call would keep it.  DSD_OP_APP on a graph of 2^20
+ * edges or more runs CoreApp's own top-down search (Algorithm 6) alone
+ * instead, as dsd_core_app does.  DSD_OP_EXACT then runs the locate
  * steps and the host exact search of Algorithm 4 graph by graph, on up to 16
  * host threads.
  *   graphs: count distinct handles (a handle twice -> DSD_EINVAL).
@@ -183,10 +187,12 @@ dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, const int *h, i
 
 /* ------------------------------------------------------------------ serving
  *
- * A server owns one worker thread.  The worker takes the queued requests
- * that fit the device-memory budget, groups them (distinct graphs, one op
- * per group), runs every group through dsd_batch_run and completes their
- * tickets.  A request's footprint is estimated as 160 bytes per vertex plus
+ * A server owns two worker threads, one for requests on graphs below 2^20
+ * edges and one for larger graphs, so that small requests never queue
+ * behind a large one.  A worker takes, in arrival order, the queued requests
+ * of its class that fit the device-memory budget left by running work,
+ * groups them (distinct graphs, one op per group), runs every group through
+ * dsd_batch_run and completes their tickets.  A request's footprint is estimated as 160 bytes per vertex plus
  * 192 bytes per edge (the peel's buffers dominate); requests start only while
  * the running footprints fit in hbm_budget_bytes, and one that could never
  * fit is refused at submit with DSD_ENOMEM.  At most max_slots requests are

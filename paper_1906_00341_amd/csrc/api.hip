@@ -379,6 +379,83 @@ __global__ void k_count_top(const u64 *keys, int32_t n, int bits, int32_t *cnt) 
     if (lane() == 0 && c) atomicAdd(cnt, c);
 }
 
+}  // extern "C"
+
+namespace dsd {
+
+// CoreApp (Algorithm 6, in the corrected reading) on a handle: best (device,
+// rank space, length n) receives the (k_max, Psi)-core; returns k_max and
+// its density.
+u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
+    const int32_t n = G->g.n;
+    hipStream_t s = G->stream;
+    u64 kmax = 0, best_mu = 0, best_size = 0;
+    fill_u8(best, 0, n, s);
+    if (n > 0) {
+        // gamma(v) = C(x_v, h-1) from the classic core numbers x_v (Section 6.2)
+        u64 *d = G->sc.get_n<u64>(n), *x = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
+        u64 m = degrees_and_mu(G, 2, nullptr, d);
+        Timer tp(s);
+        PeelResult xr = peel(G->g, 2, nullptr, d, m, 0, x, s, G->sc);
+        G->stats.t_peel_ms += tp.stop();
+        u64 xsat = 0;
+        while (xsat <= (u64)n && binom_sat(xsat, h - 1) != ~0ull) xsat++;
+        const u64 keymax = std::min<u64>(xsat, (u64)n);
+        u64 *keys = G->sc.get_n<u64>(n), *tmp = G->sc.get_n<u64>(n);
+        k_gamma_keys<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(x, n, G->g.bits, keymax, keymax, h - 1, keys);
+        int kb = G->g.bits + 1;
+        while ((keymax >> (kb - G->g.bits)) != 0) kb++;
+        radix_sort_u64(keys, tmp, n, kb, s, G->sc);
+        int32_t *cnt = G->sc.get_n<int32_t>(1);
+        fill_i32(cnt, 0, 1, s);
+        k_count_top<<<grid_for(n, BLOCK, 2048), BLOCK, 0, s>>>(keys, n, G->g.bits, cnt);
+        int32_t ntop = 0;
+        DSD_HIP(hipMemcpyAsync(&ntop, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+        auto gamma_at = [&](int64_t i) -> u64 {
+            u64 k = 0;
+            DSD_HIP(hipMemcpyAsync(&k, keys + i, sizeof(u64), hipMemcpyDeviceToHost, s));
+            DSD_HIP(hipStreamSynchronize(s));
+            return binom_sat(keymax - (k >> G->g.bits), h - 1);
+        };
+        int64_t w = std::min<int64_t>(n, std::max<int64_t>(64, ntop));
+        uint8_t *inW = G->sc.get_n<uint8_t>(n);
+        u64 *mn = G->sc.get_n<u64>(1);
+        while (true) {
+            mask_from_order_prefix(keys, n, w, G->g.bits, inW, s);
+            Timer te(s);
+            u64 muW = degrees_and_mu(G, h, inW, d);
+            G->stats.t_enum_ms += te.stop();
+            masked_min_u64(d, inW, n, mn, s);
+            u64 kl = 0;
+            DSD_HIP(hipMemcpyAsync(&kl, mn, sizeof(u64), hipMemcpyDeviceToHost, s));
+            DSD_HIP(hipStreamSynchronize(s));
+            const u64 k0 = std::max(kl, kmax);
+            const u64 floor_k = k0 > 0 ? k0 - 1 : 0;
+            Timer tq(s);
+            PeelResult pr = peel(G->g, h, inW, d, muW, floor_k, core, s, G->sc);
+            G->stats.t_peel_ms += tq.stop();
+            G->stats.peel_rounds += pr.rounds;
+            G->stats.peel_levels += pr.levels;
+            if (pr.levels > 0 && pr.kmax > 0 && pr.kmax >= k0) {
+                kmax = pr.kmax;
+                best_mu = pr.level_mu.back();
+                best_size = pr.level_size.back();
+                mask_core_equal(core, n, kmax, best, s);
+            }
+            // stop once every vertex outside W has gamma < kmax (its clique-core number is smaller)
+            if (w >= n || gamma_at(w) < kmax) break;
+            w = std::min<int64_t>(n, 2 * w);
+        }
+    }
+    if (density) *density = kmax > 0 ? make_rational(best_mu, best_size) : dsd_rational{0, 1};
+    return kmax;
+}
+
+}  // namespace dsd
+
+extern "C" {
+
 dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64_t *kmax_out,
                         dsd_rational *density) {
     if (!G) return fail(DSD_EINVAL, "NULL graph");
@@ -388,71 +465,11 @@ dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
         begin_stats(G);
-        hipStream_t s = G->stream;
-        Timer tm(s);
-        u64 kmax = 0, best_mu = 0, best_size = 0;
+        Timer tm(G->stream);
         uint8_t *best = G->sc.get_n<uint8_t>(n);
-        fill_u8(best, 0, n, s);
-        if (n > 0) {
-            // gamma(v) = C(x_v, h-1) from the classic core numbers x_v (Section 6.2)
-            u64 *d = G->sc.get_n<u64>(n), *x = G->sc.get_n<u64>(n), *core = G->sc.get_n<u64>(n);
-            u64 m = degrees_and_mu(G, 2, nullptr, d);
-            Timer tp(s);
-            PeelResult xr = peel(G->g, 2, nullptr, d, m, 0, x, s, G->sc);
-            G->stats.t_peel_ms += tp.stop();
-            u64 xsat = 0;
-            while (xsat <= (u64)n && binom_sat(xsat, h - 1) != ~0ull) xsat++;
-            const u64 keymax = std::min<u64>(xsat, (u64)n);
-            u64 *keys = G->sc.get_n<u64>(n), *tmp = G->sc.get_n<u64>(n);
-            k_gamma_keys<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(x, n, G->g.bits, keymax, keymax, h - 1, keys);
-            int kb = G->g.bits + 1;
-            while ((keymax >> (kb - G->g.bits)) != 0) kb++;
-            radix_sort_u64(keys, tmp, n, kb, s, G->sc);
-            int32_t *cnt = G->sc.get_n<int32_t>(1);
-            fill_i32(cnt, 0, 1, s);
-            k_count_top<<<grid_for(n, BLOCK, 2048), BLOCK, 0, s>>>(keys, n, G->g.bits, cnt);
-            int32_t ntop = 0;
-            DSD_HIP(hipMemcpyAsync(&ntop, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            DSD_HIP(hipStreamSynchronize(s));
-            auto gamma_at = [&](int64_t i) -> u64 {
-                u64 k = 0;
-                DSD_HIP(hipMemcpyAsync(&k, keys + i, sizeof(u64), hipMemcpyDeviceToHost, s));
-                DSD_HIP(hipStreamSynchronize(s));
-                return binom_sat(keymax - (k >> G->g.bits), h - 1);
-            };
-            int64_t w = std::min<int64_t>(n, std::max<int64_t>(64, ntop));
-            uint8_t *inW = G->sc.get_n<uint8_t>(n);
-            u64 *mn = G->sc.get_n<u64>(1);
-            while (true) {
-                mask_from_order_prefix(keys, n, w, G->g.bits, inW, s);
-                Timer te(s);
-                u64 muW = degrees_and_mu(G, h, inW, d);
-                G->stats.t_enum_ms += te.stop();
-                masked_min_u64(d, inW, n, mn, s);
-                u64 kl = 0;
-                DSD_HIP(hipMemcpyAsync(&kl, mn, sizeof(u64), hipMemcpyDeviceToHost, s));
-                DSD_HIP(hipStreamSynchronize(s));
-                const u64 k0 = std::max(kl, kmax);
-                const u64 floor_k = k0 > 0 ? k0 - 1 : 0;
-                Timer tq(s);
-                PeelResult pr = peel(G->g, h, inW, d, muW, floor_k, core, s, G->sc);
-                G->stats.t_peel_ms += tq.stop();
-                G->stats.peel_rounds += pr.rounds;
-                G->stats.peel_levels += pr.levels;
-                if (pr.levels > 0 && pr.kmax > 0 && pr.kmax >= k0) {
-                    kmax = pr.kmax;
-                    best_mu = pr.level_mu.back();
-                    best_size = pr.level_size.back();
-                    mask_core_equal(core, n, kmax, best, s);
-                }
-                // stop once every vertex outside W has gamma < kmax (its clique-core number is smaller)
-                if (w >= n || gamma_at(w) < kmax) break;
-                w = std::min<int64_t>(n, 2 * w);
-            }
-        }
+        const u64 kmax = core_app_run(G, h, best, density);
         write_u8(G, best, member, out_mem);
         if (kmax_out) *kmax_out = kmax;
-        if (density) *density = kmax > 0 ? make_rational(best_mu, best_size) : dsd_rational{0, 1};
         G->stats.t_total_ms = tm.stop();
         return DSD_OK;
     })

@@ -24,6 +24,10 @@ namespace {
 constexpr int64_t BATCH_MAX_ARCS = (int64_t)1 << 27;
 constexpr int64_t BATCH_MAX_VERTICES = (int64_t)1 << 28;
 constexpr int EXACT_THREADS = 16;
+// CoreApp on a graph this large runs its own top-down search (Algorithm 6)
+// instead of joining the union's full decomposition, which would also hold
+// every small graph of the group for the large graph's many levels
+constexpr int64_t APP_ALONE_EDGES = (int64_t)1 << 20;
 
 struct UnionDesc {
     const int64_t *row_ptr;
@@ -267,6 +271,29 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
     for (int32_t i : idx) results[i].t_ms = ms;
 }
 
+// CoreApp for one large graph of the batch, alone
+void run_app_alone(dsd_graph_s *Gi, int h, int out_mem, void *out, dsd_result &r) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int32_t n = Gi->g.n;
+    Gi->sc.reset();
+    begin_stats(Gi);
+    uint8_t *best = Gi->sc.get_n<uint8_t>(n);
+    dsd_rational dens{0, 1};
+    const u64 kmax = core_app_run(Gi, h, best, &dens);
+    std::vector<uint8_t> hm(n);
+    if (n > 0) {
+        DSD_HIP(hipMemcpyAsync(hm.data(), best, n, hipMemcpyDeviceToHost, Gi->stream));
+        DSD_HIP(hipStreamSynchronize(Gi->stream));
+    }
+    if (out) write_u8(Gi, best, (uint8_t *)out, out_mem);
+    r.kmax = kmax;
+    r.density = dens;
+    r.members = (uint64_t)std::count(hm.begin(), hm.end(), (uint8_t)1);
+    r.num_cliques = 0;   // CoreApp does not count the whole graph's cliques
+    r.peel_rounds = Gi->stats.peel_rounds;
+    r.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // CoreExact for one graph of the batch (its decomposition is on its handle)
 void run_exact(dsd_graph_s *Gi, int h, int out_mem, void *out, dsd_result &r) {
     auto t0 = std::chrono::steady_clock::now();
@@ -337,6 +364,7 @@ extern "C" dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, cons
             };
             for (int32_t i = 0; i < count; i++) {
                 if (h[i] != hh) continue;
+                if (op == DSD_OP_APP && graphs[i]->g.m >= APP_ALONE_EDGES) continue;
                 const int64_t a = 2 * graphs[i]->g.m, v = graphs[i]->g.n;
                 if (!grp.empty() && (arcs + a > BATCH_MAX_ARCS || verts + v > BATCH_MAX_VERTICES)) flush();
                 grp.push_back(i);
@@ -345,15 +373,18 @@ extern "C" dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, cons
             }
             flush();
         }
-        if (op == DSD_OP_EXACT) {
+        const bool app_alone = op == DSD_OP_APP;
+        if (op == DSD_OP_EXACT || app_alone) {
             std::atomic<int32_t> next{0};
             auto worker = [&]() {
                 while (true) {
                     const int32_t i = next.fetch_add(1);
                     if (i >= count) return;
                     if (results[i].status != DSD_OK) continue;
+                    if (app_alone && graphs[i]->g.m < APP_ALONE_EDGES) continue;
                     try {
-                        run_exact(graphs[i], h[i], out_mem, outs ? outs[i] : nullptr, results[i]);
+                        if (app_alone) run_app_alone(graphs[i], h[i], out_mem, outs ? outs[i] : nullptr, results[i]);
+                        else run_exact(graphs[i], h[i], out_mem, outs ? outs[i] : nullptr, results[i]);
                     } catch (const Error &e) {
                         results[i].status = (dsd_status)e.status;
                         errs[i] = e.what();

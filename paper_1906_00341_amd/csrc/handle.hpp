@@ -91,6 +91,9 @@ void decomp_stats(dsd_graph_s *G, const Decomp &D);
 // rank-space device array -> caller ids, into host or device memory
 void write_u64(dsd_graph_s *G, const u64 *rank_space, uint64_t *out, int mem);
 void write_u8(dsd_graph_s *G, const uint8_t *rank_space, uint8_t *out, int mem);
+// CoreApp (Algorithm 6) on a handle: best (device, rank space, length n)
+// receives the (k_max, Psi)-core; returns k_max, *density its density
+u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density);
 // CoreExact on a handle: res (device, rank space, length n) receives the
 // members of one densest subgraph; returns rho_opt
 dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res);

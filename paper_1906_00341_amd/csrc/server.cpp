@@ -1,8 +1,9 @@
-// dsd_server_*: a request queue served by one worker thread through the
-// batch path.  The worker takes, in arrival order, the queued requests with
-// the first request's op whose graphs are distinct and whose estimated
-// device footprints fit the budget together, runs them as one batch and
-// completes their tickets.
+// dsd_server_*: a request queue served through the batch path by two worker
+// threads, one for graphs below LARGE_EDGES edges and one for larger ones.
+// A worker takes, in arrival order, queued requests of its class with the
+// first one's op whose graphs are distinct and whose estimated device
+// footprints fit what the budget leaves, runs them as one batch (a large
+// graph alone) and completes their tickets.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -20,6 +21,7 @@ namespace {
 constexpr size_t BYTES_PER_VERTEX = 160;
 constexpr size_t BYTES_PER_EDGE = 192;
 constexpr size_t MAX_GROUP = 4096;
+constexpr int64_t LARGE_EDGES = (int64_t)1 << 20;   // requests on larger graphs go to the second worker
 
 enum class St { QUEUED, RUNNING, DONE, CANCELED };
 
@@ -43,38 +45,63 @@ struct dsd_server_s {
     std::unordered_map<uint64_t, dsd_result> done;
     uint64_t next_ticket = 1;
     int in_flight = 0;     // queued + running
+    size_t running = 0;    // footprints of the groups being run
     bool stop = false;
-    std::thread worker;
+    std::thread workers[2];
 
-    void run() {
+    static bool large(const Req &r) { return r.g->g.m >= LARGE_EDGES; }
+
+    bool has_class(bool lg) const {
+        for (const Req &r : queue)
+            if (large(r) == lg) return true;
+        return false;
+    }
+
+    // the next group of class lg that fits the budget left (mu held); empty if none
+    std::vector<Req> take(bool lg) {
+        std::vector<Req> group;
+        int op = -1;
+        size_t used = 0;
+        std::set<dsd_graph> seen;
+        for (auto it = queue.begin(); it != queue.end() && group.size() < MAX_GROUP;) {
+            if (large(*it) != lg) {
+                ++it;
+                continue;
+            }
+            if (op < 0) op = it->op;
+            const bool fits = running + used + it->foot <= budget || (running == 0 && group.empty());
+            if (it->op == op && !seen.count(it->g) && fits) {
+                used += it->foot;
+                seen.insert(it->g);
+                state[it->ticket] = St::RUNNING;
+                group.push_back(*it);
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+            if (lg && !group.empty()) break;    // a large graph runs alone
+        }
+        return group;
+    }
+
+    void run(bool lg) {
         while (true) {
             std::vector<Req> group;
+            size_t foot = 0;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-                if (queue.empty()) return;          // stop requested and nothing queued
-                const int op = queue.front().op;
-                size_t used = 0;
-                std::set<dsd_graph> seen;
-                for (auto it = queue.begin(); it != queue.end() && group.size() < MAX_GROUP;) {
-                    if (it->op == op && !seen.count(it->g) && (group.empty() || used + it->foot <= budget)) {
-                        used += it->foot;
-                        seen.insert(it->g);
-                        state[it->ticket] = St::RUNNING;
-                        group.push_back(*it);
-                        it = queue.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
+                cv_work.wait(lk, [&] {
+                    if (stop && !has_class(lg)) return true;
+                    group = take(lg);
+                    return !group.empty();
+                });
+                if (group.empty()) return;          // stopping, nothing of this class queued
+                for (const Req &r : group) foot += r.foot;
+                running += foot;
             }
             const int32_t cnt = (int32_t)group.size();
-            std::vector<dsd_graph> gs(cnt);
-            std::vector<int> hs(cnt);
-            std::vector<void *> outs(cnt);
             std::vector<dsd_result> res(cnt);
-            // every request of a group shares the op; out_mem may differ, so
-            // requests with device outputs and host outputs go in two calls
+            // one op per group; requests with host and with device outputs go in two calls
             for (int pass = 0; pass < 2; pass++) {
                 const int mem = pass == 0 ? DSD_MEM_HOST : DSD_MEM_DEVICE;
                 std::vector<int32_t> sel;
@@ -99,6 +126,7 @@ struct dsd_server_s {
             }
             {
                 std::lock_guard<std::mutex> lk(mu);
+                running -= foot;
                 for (int32_t i = 0; i < cnt; i++) {
                     state[group[i].ticket] = St::DONE;
                     done[group[i].ticket] = res[i];
@@ -106,6 +134,7 @@ struct dsd_server_s {
                 }
             }
             cv_done.notify_all();
+            cv_work.notify_all();
         }
     }
 };
@@ -123,7 +152,8 @@ dsd_status dsd_server_create(size_t hbm_budget_bytes, int max_slots, dsd_server 
         dsd_server_s *s = new dsd_server_s();
         s->budget = hbm_budget_bytes;
         s->max_slots = max_slots;
-        s->worker = std::thread([s] { s->run(); });
+        s->workers[0] = std::thread([s] { s->run(false); });
+        s->workers[1] = std::thread([s] { s->run(true); });
         *out = s;
         return DSD_OK;
     })
@@ -144,7 +174,7 @@ dsd_status dsd_server_submit(dsd_server s, dsd_graph g, int h, int op, int out_m
     s->state[t] = St::QUEUED;
     s->in_flight++;
     *ticket = t;
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();    // two workers: wake the one of this request's class
     return DSD_OK;
 }
 
@@ -200,7 +230,8 @@ dsd_status dsd_server_destroy(dsd_server s) {
     }
     s->cv_work.notify_all();
     s->cv_done.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (std::thread &w : s->workers)
+        if (w.joinable()) w.join();
     delete s;
     return DSD_OK;
 }

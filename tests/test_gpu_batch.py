@@ -206,32 +206,43 @@ def test_server_results_match_single_calls():
 
 def test_server_admission_slots_timeout_and_cancel():
     n, s, d = synth.chung_lu(n=200_000, avg_deg=16, beta=2.2, planted=2, plant_size=100, p=0.6, seed=3)
-    big = dsd.build_csr(n, s, d)
+    big = [dsd.build_csr(n, s, d) for _ in range(2)]         # above 2^20 edges: the large-graph worker
+    assert big[0].info()[1] >= 1 << 20
     small = [dsd.build_csr(*synth.complete_graph(10)) for _ in range(3)]
     # a request whose footprint exceeds the whole budget is refused
     tiny = dsd.Server(1 << 20, 8)
     with pytest.raises(dsd.DsdError) as e:
-        tiny.submit(big, 3, "core")
+        tiny.submit(big[0], 3, "core")
     assert e.value.status == -2
     tiny.close()
-    srv = dsd.Server(1 << 34, 2)
-    t0 = srv.submit(big, 3, "exact")          # runs for a while
-    t1 = srv.submit(small[0], 3, "core")
-    with pytest.raises(dsd.DsdError) as e:    # both slots are taken until t0 completes
-        srv.submit(small[1], 3, "core")
+    # one slot: taken until the running request completes
+    srv = dsd.Server(1 << 34, 1)
+    t0 = srv.submit(big[0], 3, "exact")
+    with pytest.raises(dsd.DsdError) as e:
+        srv.submit(small[0], 3, "core")
     assert e.value.status == dsd.DSD_EBUSY
     st, _ = srv.wait(t0, 0)
     assert st in (0, dsd.DSD_ETIMEDOUT)
-    c = srv.cancel(t1)                         # queued behind t0, or already running
-    st1, r1 = srv.wait(t1)
-    if c == 0:
-        assert st1 == dsd.DSD_ECANCELED
-    else:
-        assert c == dsd.DSD_EBUSY and st1 == 0
     if st == dsd.DSD_ETIMEDOUT:
         st, r = srv.wait(t0)
         assert st == 0 and r["status"] == 0
-    t2 = srv.submit(small[2], 3, "core")
-    st, r = srv.wait(t2)
+    t1 = srv.submit(small[1], 3, "core")                     # the slot is free again
+    st, r = srv.wait(t1)
     assert st == 0 and r["kmax"] == math.comb(9, 2)
+    srv.close()
+    # large requests run one at a time: the second waits in the queue and can be cancelled
+    srv = dsd.Server(1 << 34, 8)
+    ta = srv.submit(big[0], 3, "exact")
+    tb = srv.submit(big[1], 3, "core")
+    tc = srv.submit(small[2], 3, "core")                     # the small-graph worker is not blocked
+    st, r = srv.wait(tc)
+    assert st == 0 and r["kmax"] == math.comb(9, 2)
+    c = srv.cancel(tb)
+    stb, _ = srv.wait(tb)
+    if c == 0:
+        assert stb == dsd.DSD_ECANCELED
+    else:
+        assert c == dsd.DSD_EBUSY and stb == 0
+    st, r = srv.wait(ta)
+    assert st == 0 and r["status"] == 0
     srv.close()
