@@ -60,6 +60,45 @@ def k4_bytes(st: dict, h: int) -> float:
     return 4.0 * st["s2"] + 24.0 * st["m"]
 
 
+MAIN_KERNEL = {2: "k_process_h2", 3: "k_h3_probe"}
+
+
+def main_kernel_bytes(st: dict, h: int) -> float:
+    """Algorithmic bytes of the peel's main kernel over one peel, from the
+    work it counted.  h = 3 (triangle probe): every probed out-list entry
+    costs 4 B, every expanded neighbour w its column entry and the two row
+    offsets of N+(w) (4 + 8 + 8 B).  h = 2 (edge pass): every walked
+    adjacency entry costs its column entry, the neighbour's stamp and an
+    8-byte read-modify-write of its degree (4 + 4 + 16 B), every frontier
+    vertex its two row offsets (16 B)."""
+    if h == 2:
+        return 24.0 * st["k4_main_pairs"] + 16.0 * st["k4_main_nbrs"]
+    return 4.0 * st["k4_main_pairs"] + 20.0 * st["k4_main_nbrs"]
+
+
+PEEL_SOURCE = os.path.join(ROOT, "paper_1906_00341_amd", "csrc", "peel.hip")
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of kernel on workload from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of
+    known size), or None when there is none or the peel's source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(PEEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(workload: str, seed: int):
     """The CPU oracle, single-threaded, on a bounded sample of the same
     workload.  Chung-Lu: the same generator at n = 600,000 (same degree law
@@ -274,13 +313,12 @@ def main() -> int:
     avg = lambda key, stage: sum(r[stage][key] for r in recs) / len(recs)
     k3_ms = avg("k3_ms", "core")
     k4_ms = avg("k4_ms", "core")
-    fam = {
-        "k3_clique_degree_engine": (k3_ms, max(core["k3_launches"], 1), k3_bytes(core)),
-        "k4_peel": (k4_ms, max(core["k4_launches"], 1), k4_bytes(core, h)),
-    }
-    dom = max(fam, key=lambda k: fam[k][0])
-    t_ms, launches, bytes_call = fam[dom]
-    achieved = bytes_call / (t_ms / 1e3) / 1e9 if t_ms > 0 else 0.0
+    # roofline of the peel's main kernel, every launch timed with HIP events on its stream
+    main_ms = avg("k4_main_ms", "core")
+    launches = max(core["k4_main_launches"], 1)
+    bytes_call = main_kernel_bytes(core, h) / launches
+    ms_call = main_ms / launches
+    achieved = bytes_call / (ms_call / 1e3) / 1e9 if ms_call > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": mu / (ms_per_step / 1e3),
@@ -313,9 +351,11 @@ def main() -> int:
             "enum_hbm_frac": k3_bytes(core) / (k3_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k3_ms else None,
             "peel_hbm_frac": k4_bytes(core, h) / (k4_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k4_ms else None,
         },
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_call": bytes_call, "ms_per_call": t_ms, "launches_per_call": launches},
+        "roofline": {"kernel": MAIN_KERNEL.get(h), "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(MAIN_KERNEL.get(h), args.workload),
+                     "bytes_per_launch": bytes_call, "ms_per_launch": ms_call, "launches_per_step": launches,
+                     "pairs_per_step": core["k4_main_pairs"], "nbrs_per_step": core["k4_main_nbrs"]},
     }
     if args.batch_graphs > 0:
         out["batch"] = batch_leg(args.batch_graphs, 7)

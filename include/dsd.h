@@ -76,6 +76,13 @@ typedef struct {
     uint64_t n, m, w2, s2;
     /* host exact step: network construction and maximum-flow time */
     double t_flow_build_ms, t_flow_ms;
+    /* the peel's main kernel (h = 3: the triangle probe; h = 2: the edge
+     * pass), every launch timed on its own with HIP events: total time,
+     * launches, out-list entries probed (h = 3) or adjacency entries walked
+     * (h = 2), and neighbours expanded (h = 3) or frontier vertices (h = 2);
+     * zero for h >= 4 */
+    double k4_main_ms;
+    uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
 } dsd_stats;
 
 /*

@@ -70,6 +70,10 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k3_ms = kt.k3_ms;
     G->stats.k4_ms = kt.k4_ms;
     G->stats.k3_launches = kt.k3_launches;
+    G->stats.k4_main_ms = kt.main_ms;
+    G->stats.k4_main_launches = kt.main_launches;
+    G->stats.k4_main_pairs = kt.main_pairs;
+    G->stats.k4_main_nbrs = kt.main_nbrs;
     G->stats.k4_launches = kt.k4_launches;
 }
 

@@ -31,6 +31,12 @@ struct DevGraph {
 struct KernelTimes {
     double k3_ms = 0, k4_ms = 0;
     u64 k3_launches = 0, k4_launches = 0;
+    // the peel's main kernel (h = 3: the triangle probe; h = 2: the edge
+    // pass), every launch timed on its own; pairs: out-list entries probed
+    // (h = 3) or adjacency entries walked (h = 2); nbrs: neighbours expanded
+    // (h = 3) or frontier vertices (h = 2)
+    double main_ms = 0;
+    u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----

@@ -21,6 +21,11 @@
 // neighbours plus one item per neighbour with a long out-list, so that even a
 // round that removes a single hub keeps thousands of waves busy; its
 // neighbourhood hash sits in global memory, shared by those items.
+#include <hip/hip_ext.h>
+
+#include <mutex>
+#include <vector>
+
 #include "engine.hpp"
 #include "graph.hpp"
 
@@ -38,6 +43,7 @@ struct PeelCtl {
     int32_t nitems[8]; // (v, w) work items per class (h >= 4)
     int64_t htop[2];   // slots handed out in the global neighbourhood hashes (h = 3)
     int64_t nW;        // wide (v, w) items of this round (h = 3)
+    u64 work[2];       // main kernel's pairs and neighbours over the whole peel (when counted)
 };
 
 // one graph of the batch (a single graph is a batch of one)
@@ -79,6 +85,7 @@ struct PeelBufs {
     int64_t wcap;
     int32_t n;
     int32_t h;
+    int32_t count_work;  // the main kernel adds up its pairs and neighbours
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
@@ -192,6 +199,27 @@ __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int
 // cliques destroyed through frontier vertex v
 __device__ __forceinline__ void add_destroyed(const PeelBufs &b, int32_t v, u64 t) {
     if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed, t);
+}
+
+// the main kernel's counted work: lane 0 of every wave holds its wave's
+// tally; one atomic per block.  All threads of the block call together.
+__device__ __forceinline__ void add_work(const PeelBufs &b, u64 pairs, u64 nbrs) {
+    __shared__ u64 sP[WAVES_PER_BLOCK], sN[WAVES_PER_BLOCK];
+    const int wv = threadIdx.x / WAVE;
+    if (lane() == 0) {
+        sP[wv] = pairs;
+        sN[wv] = nbrs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 p = 0, q = 0;
+        for (int i = 0; i < WAVES_PER_BLOCK; i++) {
+            p += sP[i];
+            q += sN[i];
+        }
+        if (p) atomicAdd(&b.ctl->work[0], p);
+        if (q) atomicAdd(&b.ctl->work[1], q);
+    }
 }
 
 // a clique through frontier vertex v may use x iff x was alive at the start
@@ -365,6 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     const int32_t r = c->round;
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE;
+    u64 wp = 0, wn = 0;   // counted work (lane 0's tally is the wave's)
     for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nF; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[i];
         u64 destroyed = 0;
@@ -380,7 +409,9 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
         }
         destroyed = wave_sum(destroyed);
         if (lane() == 0) add_destroyed(b, v, destroyed);
+        if (b.count_work) wp += (u64)(b.row_ptr[v + 1] - b.row_ptr[v]), wn += 1;
     }
+    if (b.count_work) add_work(b, wp, wn);
 }
 
 // ---------------------------------------------------------------- h = 3
@@ -448,7 +479,8 @@ __device__ __forceinline__ void hash_flush(const PeelBufs &b, const NbHash &hs, 
 // 64-entry LDS scratch.
 __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64_t lo, int64_t hi, int32_t r,
                                             const NbHash &hs, int32_t *sPre, int64_t *sSt, int32_t *sW,
-                                            uint32_t *sCnt, int32_t wide_out) {
+                                            uint32_t *sCnt, int32_t wide_out, u64 *pairs = nullptr,
+                                            u64 *nbrs = nullptr) {
     const int L = lane();
     u64 destroyed = 0;
     for (int64_t base = lo; base < hi; base += WAVE) {
@@ -469,6 +501,10 @@ __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64
         sW[L] = wslot;
         sCnt[L] = 0;
         const int32_t total = __shfl(inc, WAVE - 1, WAVE);
+        if (pairs) {
+            *pairs += (u64)total;
+            *nbrs += (u64)__popcll(__ballot(len > 0));
+        }
         __builtin_amdgcn_wave_barrier();
         for (int32_t pb = 0; pb < total; pb += WAVE) {
             int32_t p = pb + L;
@@ -585,6 +621,7 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
     const int64_t nW = c->nW;
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const int wv = threadIdx.x / WAVE;
+    u64 wp = 0, wn = 0;   // counted work (wave-uniform)
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB + nW; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         int32_t v;
         u64 destroyed;
@@ -596,7 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
             const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
             const int64_t lo = rv0 + (int64_t)ch * CHUNK, hi = min(rv1, lo + CHUNK);
             const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
-            destroyed = h3_wave_range(b, v, lo, hi, r, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv], WIDE_OUT);
+            destroyed = h3_wave_range(b, v, lo, hi, r, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv], WIDE_OUT, &wp, &wn);
             destroyed = wave_sum(destroyed);
         } else {
             // wide item (v, w): the lanes walk N+(w)
@@ -606,6 +643,8 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
             const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
             const NbHash hs = big_hash(b, cur, v, rv1 - rv0);
             uint32_t cw = 0;
+            wp += (u64)(b.row_ptr[w + 1] - b.dag_off[w]);
+            wn += 1;
             for (int64_t e = b.dag_off[w] + lane(); e < b.row_ptr[w + 1]; e += WAVE) {
                 const int slot = hs.find(b.col[e]);
                 if (slot >= 0) {                          // triangle {v, w, x}, owned by v
@@ -622,6 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
         }
         if (lane() == 0) add_destroyed(b, v, destroyed);
     }
+    if (b.count_work) add_work(b, wp, wn);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
@@ -846,6 +886,59 @@ __global__ void k_start_graphs(PeelBufs b) {
     if (g == 0) b.ctl->n_alive = b.ctl->nlist[0];
 }
 
+// Times every launch of one kernel: the launch carries a start and a stop
+// HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL), so the
+// pair spans the kernel and nothing else on the stream.  The events come
+// from a process-wide pool that only grows, so a call pays for event
+// creation only the first time it needs that many; a second peel running at
+// the same time (another thread) goes untimed.
+class LaunchTimer {
+public:
+    explicit LaunchTimer(bool want) : lk_(pool_mu(), std::try_to_lock) { on_ = want && lk_.owns_lock(); }
+    // launch kernel k on s, timed when the timer is on
+    template <typename... Args>
+    void launch(void (*k)(Args...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
+        if (!on_) {
+            hipLaunchKernelGGL(k, grid, block, 0, s, args...);
+            return;
+        }
+        std::vector<hipEvent_t> &ev = pool();
+        while (ev.size() < used_ + 2) {
+            hipEvent_t e;
+            DSD_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        hipExtLaunchKernelGGL(k, grid, block, 0, s, ev[used_], ev[used_ + 1], 0, args...);
+        used_ += 2;
+    }
+    // total milliseconds and launches (after the stream has drained)
+    double total_ms(u64 *launches) {
+        double t = 0;
+        std::vector<hipEvent_t> &ev = pool();
+        for (size_t i = 0; on_ && i < used_; i += 2) {
+            float ms = 0;
+            DSD_HIP(hipEventSynchronize(ev[i + 1]));
+            DSD_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            t += ms;
+        }
+        *launches = used_ / 2;
+        return t;
+    }
+
+private:
+    static std::mutex &pool_mu() {
+        static std::mutex m;
+        return m;
+    }
+    static std::vector<hipEvent_t> &pool() {
+        static std::vector<hipEvent_t> v;
+        return v;
+    }
+    std::unique_lock<std::mutex> lk_;
+    bool on_ = false;
+    size_t used_ = 0;
+};
+
 template <int R>
 static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t s, u64 *gS) {
     PeelCtx ctx{b, 0};
@@ -884,6 +977,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.row_ptr = g.row_ptr;
     b.col = g.col;
     b.dag_off = g.dag_off;
+    b.count_work = kt != nullptr && h <= 3;
     b.ctl = sc.get_n<PeelCtl>(1);
     b.gs = sc.get_n<GraphState>(G);
     b.stamp = sc.get_n<int32_t>(n);
@@ -944,6 +1038,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipEventRecord(e0, s));
     }
     const int gmin = 256, gbuild = 1024, gproc = 2048;
+    LaunchTimer main_timer(kt != nullptr && h <= 3);
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
     const bool compacting = h <= 3;
@@ -961,11 +1056,11 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             k_level_min<<<gmin, BLOCK, 0, s>>>(b);
             k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
             if (h == 2) {
-                k_process_h2<<<gproc, BLOCK, 0, s>>>(b);
+                main_timer.launch(k_process_h2, dim3(gproc), dim3(BLOCK), s, b);
             } else if (h == 3) {
                 k_process_h3_small<<<gproc, BLOCK, 0, s>>>(b);
                 k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
-                k_h3_probe<<<gproc, BLOCK, 0, s>>>(b);
+                main_timer.launch(k_h3_probe, dim3(gproc), dim3(BLOCK), s, b);
                 k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
@@ -1001,6 +1096,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipEventElapsedTime(&ms, e0, e1));
         kt->k4_ms += ms;
         kt->k4_launches += 1;
+        u64 launches = 0;
+        kt->main_ms += main_timer.total_ms(&launches);
+        kt->main_launches += launches;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
@@ -1010,6 +1108,10 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     DSD_HIP(hipMemcpyAsync(gst.data(), b.gs, G * sizeof(GraphState), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     if (fin.n_alive != 0) throw Error(-3, "peel ended with alive vertices");
+    if (kt && b.count_work) {
+        kt->main_pairs += fin.work[0];
+        kt->main_nbrs += fin.work[1];
+    }
     res.rounds = fin.round;
     res.graph_levels.resize(G);
     for (int32_t i = 0; i < G; i++) {
