@@ -28,7 +28,9 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <atomic>
 #include <numeric>
+#include <thread>
 
 #include "common.hpp"
 
@@ -40,41 +42,140 @@ static const int64_t CAP_LIMIT = (int64_t)1 << 62;
 // h-cliques of each component bounds every network (about h arcs per clique).
 static const uint64_t MAX_HOST_CLIQUES = 100000000ull;
 
+// ---------------------------------------------------------------- host threads
+
+static int host_threads() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
+// f(t, lo, hi) on T contiguous slices of [0, n) (uniform work per index)
+template <class F>
+static void parallel_slices(int64_t n, int T, F &&f) {
+    if (T <= 1 || n < 2 * (int64_t)T) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; t++) {
+        const int64_t lo = n * t / T, hi = n * (t + 1) / T;
+        th.emplace_back([&f, t, lo, hi] { f(t, lo, hi); });
+    }
+    for (std::thread &x : th) x.join();
+}
+
+// f(t, i) for every i in [0, n), handed out `grain` at a time (uneven work per index)
+template <class F>
+static void parallel_dynamic(int64_t n, int T, int64_t grain, F &&f) {
+    if (T <= 1 || n <= grain) {
+        for (int64_t i = 0; i < n; i++) f(0, i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; t++)
+        th.emplace_back([&, t] {
+            while (true) {
+                const int64_t lo = next.fetch_add(grain);
+                if (lo >= n) return;
+                const int64_t hi = std::min(n, lo + grain);
+                for (int64_t i = lo; i < hi; i++) f(t, i);
+            }
+        });
+    for (std::thread &x : th) x.join();
+}
+
+// an array that is never zero-filled: every entry is written before it is read
+template <typename T>
+struct RawArray {
+    std::unique_ptr<T[]> p;
+    int64_t n = 0;
+    void alloc(int64_t k) {
+        p.reset(new T[k > 0 ? k : 1]);
+        n = k;
+    }
+    T &operator[](int64_t i) { return p[i]; }
+    const T &operator[](int64_t i) const { return p[i]; }
+};
+
 // ---------------------------------------------------------------- push-relabel
 
 class PushRelabel {
 public:
     explicit PushRelabel(int n) : n_(n) {}
     void reserve(int64_t arcs) {
-        eu_.reserve(arcs);
-        ev_.reserve(arcs);
+        if (arcs <= cap_arcs_) return;
+        RawArray<int> nu, nv;
+        nu.alloc(arcs);
+        nv.alloc(arcs);
+        for (int64_t i = 0; i < E_; i++) {
+            nu[i] = eu_[i];
+            nv[i] = ev_[i];
+        }
+        eu_ = std::move(nu);
+        ev_ = std::move(nv);
+        cap_arcs_ = arcs;
     }
     int arc(int u, int v) {   // capacities are set per test
-        eu_.push_back(u);
-        ev_.push_back(v);
-        return (int)eu_.size() - 1;
+        if (E_ == cap_arcs_) reserve(std::max<int64_t>(1024, 2 * cap_arcs_));
+        eu_[E_] = u;
+        ev_[E_] = v;
+        return (int)E_++;
     }
+    // room for `more` arcs written in place by set_arc; returns the first index
+    int64_t grow(int64_t more) {
+        reserve(E_ + more);
+        const int64_t at = E_;
+        E_ += more;
+        return at;
+    }
+    void set_arc(int64_t i, int u, int v) {
+        eu_[i] = u;
+        ev_[i] = v;
+    }
+    // Residual CSR: every arc and its reverse.  Each thread takes a slice of
+    // the arcs; per-thread counts per node give every thread its own range in
+    // every node's list.
     void build() {
+        const int64_t E = E_;
+        const int T = E < (1 << 20) ? 1 : host_threads();
+        std::vector<std::vector<int>> cnt(T, std::vector<int>(n_, 0));
+        parallel_slices(E, T, [&](int t, int64_t lo, int64_t hi) {
+            int *c = cnt[t].data();
+            for (int64_t i = lo; i < hi; i++) {
+                c[eu_[i]]++;
+                c[ev_[i]]++;
+            }
+        });
         first_.assign(n_ + 1, 0);
-        for (size_t i = 0; i < eu_.size(); i++) {
-            first_[eu_[i] + 1]++;
-            first_[ev_[i] + 1]++;
+        {
+            int64_t run = 0;
+            for (int v = 0; v < n_; v++) {
+                first_[v] = (int)run;
+                for (int t = 0; t < T; t++) {
+                    const int c = cnt[t][v];
+                    cnt[t][v] = (int)run;        // thread t's next slot in v's list
+                    run += c;
+                }
+            }
+            first_[n_] = (int)run;
         }
-        for (int i = 0; i < n_; i++) first_[i + 1] += first_[i];
-        std::vector<int> fill(first_.begin(), first_.end() - 1);
-        const size_t A = 2 * eu_.size();
-        to_.assign(A, 0);
-        rev_.assign(A, 0);
-        fwd_.assign(eu_.size(), 0);
-        for (size_t i = 0; i < eu_.size(); i++) {
-            int pu = fill[eu_[i]]++, pv = fill[ev_[i]]++;
-            to_[pu] = ev_[i];
-            to_[pv] = eu_[i];
-            rev_[pu] = pv;
-            rev_[pv] = pu;
-            fwd_[i] = pu;
-        }
-        cap_.assign(A, 0);
+        const int64_t A = 2 * E;
+        to_.alloc(A);     // every slot is written once below
+        rev_.alloc(A);
+        fwd_.alloc(E);
+        cap_.alloc(A);    // every arc's capacity is set (set()) before each flow
+        parallel_slices(E, T, [&](int t, int64_t lo, int64_t hi) {
+            int *fill = cnt[t].data();
+            for (int64_t i = lo; i < hi; i++) {
+                const int pu = fill[eu_[i]]++, pv = fill[ev_[i]]++;
+                to_[pu] = ev_[i];
+                to_[pv] = eu_[i];
+                rev_[pu] = pv;
+                rev_[pv] = pu;
+                fwd_[i] = pu;
+            }
+        });
     }
     // capacity of arc i (forward) and of its reverse
     void set(int i, int64_t c, int64_t rc = 0) {
@@ -106,7 +207,7 @@ public:
             inq_[u] = 0;
             if (ht_[u] >= n_ || ex_[u] <= 0) continue;
             discharge(u, work);
-            if (work > 6 * (int64_t)n_ + (int64_t)to_.size() / 2) {
+            if (work > 6 * (int64_t)n_ + to_.n / 2) {
                 work = 0;
                 global_relabel();
             }
@@ -206,10 +307,12 @@ private:
     }
 
     int n_, s_ = 0, t_ = 1;
-    std::vector<int> eu_, ev_, fwd_;
-    std::vector<int> first_, to_, rev_, ht_, cnt_, cur_;
+    int64_t E_ = 0, cap_arcs_ = 0;
+    RawArray<int> eu_, ev_, fwd_, to_, rev_;
+    RawArray<int64_t> cap_;
+    std::vector<int> first_, ht_, cnt_, cur_;
     std::vector<char> inq_;
-    std::vector<int64_t> cap_, ex_;
+    std::vector<int64_t> ex_;
     std::deque<int> q_;
 };
 
@@ -397,18 +500,30 @@ public:
         }
         const int64_t base = 2 + nv;
         if (base + npsi > 0x7fffffff) throw Error(-5, "flow network too large");
-        // count triangles first so that the arc arrays are sized once
-        uint64_t tri = 0;
-        for (int i = 0; i < nv; i++)
-            for (int64_t a = fwd[i]; a < so[i + 1]; a++) {
-                int j = sa[a];
-                int64_t p = a + 1, q = fwd[j];
-                while (p < so[i + 1] && q < so[j + 1]) {
-                    if (sa[p] < sa[q]) p++;
-                    else if (sa[p] > sa[q]) q++;
-                    else { tri++; p++; q++; }
+        // triangles per vertex i (i the lowest of the three), so that every
+        // vertex's arcs go to a range of their own
+        const int T = host_threads();
+        std::vector<uint64_t> tri_of(nv + 1, 0);
+        auto merge = [&](int i, int64_t a, auto &&emit) {
+            const int j = sa[a];
+            int64_t p = a + 1, q = fwd[j];
+            while (p < so[i + 1] && q < so[j + 1]) {
+                if (sa[p] < sa[q]) p++;
+                else if (sa[p] > sa[q]) q++;
+                else {
+                    emit(j, p, q);
+                    p++;
+                    q++;
                 }
             }
+        };
+        parallel_dynamic(nv, T, 4, [&](int, int64_t i) {
+            uint64_t c = 0;
+            for (int64_t a = fwd[i]; a < so[i + 1]; a++) merge((int)i, a, [&](int, int64_t, int64_t) { c++; });
+            tri_of[i + 1] = c;
+        });
+        for (int i = 0; i < nv; i++) tri_of[i + 1] += tri_of[i];
+        const uint64_t tri = tri_of[nv];
         mu_ = tri;
         net_ = new PushRelabel((int)(base + npsi));
         net_->reserve(2 * (int64_t)nv + 2 * npsi + 3 * (int64_t)tri);
@@ -422,27 +537,31 @@ public:
                 inf_.push_back(net_->arc((int)(base + eid[a]), 2 + i));
                 inf_.push_back(net_->arc((int)(base + eid[a]), 2 + sa[a]));
             }
-        mid_.reserve(3 * tri);
-        for (int i = 0; i < nv; i++)
-            for (int64_t a = fwd[i]; a < so[i + 1]; a++) {
-                const int j = sa[a];
-                int64_t p = a + 1, q = fwd[j];
-                while (p < so[i + 1] && q < so[j + 1]) {
-                    if (sa[p] < sa[q]) p++;
-                    else if (sa[p] > sa[q]) q++;
-                    else {
+        const int64_t m0 = net_->grow(3 * (int64_t)tri);
+        mid_.resize(3 * tri);
+        std::vector<uint64_t> tdeg((size_t)T * nv, 0);   // per-thread triangle counts per vertex
+        parallel_dynamic(nv, T, 4, [&](int t, int64_t i) {
+            uint64_t *dg = tdeg.data() + (size_t)t * nv;
+            {
+                int64_t at = 3 * (int64_t)tri_of[i];
+                for (int64_t a = fwd[i]; a < so[i + 1]; a++)
+                    merge((int)i, a, [&](int j, int64_t p, int64_t q) {
                         const int k = sa[p];
-                        mid_.push_back(net_->arc(2 + i, (int)(base + eid[q])));   // i with edge (j, k)
-                        mid_.push_back(net_->arc(2 + j, (int)(base + eid[p])));   // j with edge (i, k)
-                        mid_.push_back(net_->arc(2 + k, (int)(base + eid[a])));   // k with edge (i, j)
-                        deg_[i]++;
-                        deg_[j]++;
-                        deg_[k]++;
-                        p++;
-                        q++;
-                    }
-                }
+                        net_->set_arc(m0 + at, 2 + (int)i, (int)(base + eid[q]));   // i with edge (j, k)
+                        net_->set_arc(m0 + at + 1, 2 + j, (int)(base + eid[p]));    // j with edge (i, k)
+                        net_->set_arc(m0 + at + 2, 2 + k, (int)(base + eid[a]));    // k with edge (i, j)
+                        mid_[at] = (int)(m0 + at);
+                        mid_[at + 1] = (int)(m0 + at + 1);
+                        mid_[at + 2] = (int)(m0 + at + 2);
+                        dg[i]++;
+                        dg[j]++;
+                        dg[k]++;
+                        at += 3;
+                    });
             }
+        });
+        for (int t = 0; t < T; t++)
+            for (int i = 0; i < nv; i++) deg_[i] += tdeg[(size_t)t * nv + i];
     }
 
     ~CompNet() { delete net_; }
@@ -466,7 +585,7 @@ public:
                 net_->set(snk_[i], (int64_t)ct);
                 srcsum += cs;
             }
-            for (int e : mid_) net_->set(e, (int64_t)b, (int64_t)b);
+            set_all(mid_, (int64_t)b, (int64_t)b);
         } else {
             for (int i = 0; i < nv; i++) {
                 i128 cs = (i128)b * (i128)deg_[i], ct = (i128)h_ * (i128)a;
@@ -477,8 +596,8 @@ public:
             }
             if (srcsum * 2 >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
             const int64_t inf = (int64_t)srcsum + 1;
-            for (int e : inf_) net_->set(e, inf);
-            for (int e : mid_) net_->set(e, (int64_t)b);
+            set_all(inf_, inf, 0);
+            set_all(mid_, (int64_t)b, 0);
         }
         if (srcsum >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
         int64_t f = net_->maxflow(0, 1);
@@ -492,6 +611,13 @@ public:
     }
 
 private:
+    void set_all(const std::vector<int> &arcs, int64_t c, int64_t rc) {
+        parallel_slices((int64_t)arcs.size(), arcs.size() < (1u << 20) ? 1 : host_threads(),
+                        [&](int, int64_t lo, int64_t hi) {
+                            for (int64_t i = lo; i < hi; i++) net_->set(arcs[i], c, rc);
+                        });
+    }
+
     const LocatedCore &lc_;
     int h_;
     std::vector<int32_t> verts_;
