@@ -318,66 +318,86 @@ private:
 
 // ---------------------------------------------------------------- host clique listing
 
-// Lists the cliques of size `size` inside `in` (membership over local ids) in
-// increasing id order; calls f(const int32_t *members).
-template <class F>
-static void list_cliques(const LocatedCore &lc, const std::vector<char> &in, int size, F &&f) {
-    const int32_t s = (int32_t)lc.rank.size();
-    std::vector<std::vector<int32_t>> cand(size + 1);
-    std::vector<int32_t> mem(size);
-    struct Rec {
-        const LocatedCore &lc;
-        int size;
-        std::vector<std::vector<int32_t>> &cand;
-        std::vector<int32_t> &mem;
-        F &f;
-        void go(int depth) {
-            const std::vector<int32_t> &c = cand[depth];
-            for (size_t i = 0; i < c.size(); i++) {
-                int32_t x = c[i];
-                mem[depth] = x;
-                if (depth + 1 == size) {
-                    f(mem.data());
-                    continue;
-                }
-                std::vector<int32_t> &nx = cand[depth + 1];
-                nx.clear();
-                const int32_t *a = lc.adj.data() + lc.off[x], *ae = lc.adj.data() + lc.off[x + 1];
-                size_t j = i + 1;
-                while (j < c.size() && a < ae) {
-                    if (c[j] < *a) j++;
-                    else if (c[j] > *a) a++;
-                    else { nx.push_back(c[j]); j++; a++; }
-                }
-                if (!nx.empty()) go(depth + 1);
+// Lists the cliques of size `size` inside `in` (membership over local ids)
+// whose smallest member is `root`, in increasing id order; calls
+// f(const int32_t *members).  One lister per thread.
+struct CliqueLister {
+    const LocatedCore &lc;
+    const std::vector<char> &in;
+    int size;
+    std::vector<std::vector<int32_t>> cand;
+    std::vector<int32_t> mem;
+    CliqueLister(const LocatedCore &l, const std::vector<char> &i, int sz)
+        : lc(l), in(i), size(sz), cand(sz + 1), mem(sz) {}
+
+    template <class F>
+    void go(int depth, F &f) {
+        const std::vector<int32_t> &c = cand[depth];
+        for (size_t i = 0; i < c.size(); i++) {
+            int32_t x = c[i];
+            mem[depth] = x;
+            if (depth + 1 == size) {
+                f(mem.data());
+                continue;
             }
+            std::vector<int32_t> &nx = cand[depth + 1];
+            nx.clear();
+            const int32_t *a = lc.adj.data() + lc.off[x], *ae = lc.adj.data() + lc.off[x + 1];
+            size_t j = i + 1;
+            while (j < c.size() && a < ae) {
+                if (c[j] < *a) j++;
+                else if (c[j] > *a) a++;
+                else { nx.push_back(c[j]); j++; a++; }
+            }
+            if (!nx.empty()) go(depth + 1, f);
         }
-    } rec{lc, size, cand, mem, f};
-    for (int32_t v = 0; v < s; v++) {
-        if (!in[v]) continue;
+    }
+
+    template <class F>
+    void root(int32_t v, F &&f) {
+        if (!in[v]) return;
         mem[0] = v;
-        if (size == 1) { f(mem.data()); continue; }
+        if (size == 1) {
+            f(mem.data());
+            return;
+        }
         cand[1].clear();
         for (int64_t e = lc.off[v]; e < lc.off[v + 1]; e++) {
             int32_t w = lc.adj[e];
             if (w > v && in[w]) cand[1].push_back(w);
         }
-        if (!cand[1].empty()) {
-            // reuse go() from depth 1 with the first member fixed
-            rec.go(1);
-        }
+        if (!cand[1].empty()) go(1, f);
     }
+};
+
+template <class F>
+static void list_cliques(const LocatedCore &lc, const std::vector<char> &in, int size, F &&f) {
+    CliqueLister L(lc, in, size);
+    for (int32_t v = 0; v < (int32_t)lc.rank.size(); v++) L.root(v, f);
 }
 
+// h-cliques inside verts, counted on all host threads (roots handed out
+// dynamically); throws once the count passes MAX_HOST_CLIQUES
 uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int32_t> &verts) {
     std::vector<char> in(lc.rank.size(), 0);
     for (int32_t v : verts) in[v] = 1;
-    uint64_t c = 0;
-    list_cliques(lc, in, h, [&](const int32_t *) {
-        if (++c > MAX_HOST_CLIQUES)
-            throw Error(-5, "a located component holds more than 1e8 h-cliques: its flow network is beyond "
-                            "the host exact step's limit");
+    const int T = host_threads();
+    std::vector<uint64_t> cnt(T, 0);
+    std::atomic<uint64_t> total{0};
+    std::atomic<bool> over{false};
+    std::vector<CliqueLister> lister;
+    for (int t = 0; t < T; t++) lister.emplace_back(lc, in, h);
+    parallel_dynamic((int64_t)verts.size(), T, 4, [&](int t, int64_t i) {
+        if (over.load(std::memory_order_relaxed)) return;
+        uint64_t c = 0;
+        lister[t].root(verts[i], [&](const int32_t *) { c++; });
+        cnt[t] += c;
+        if (total.fetch_add(c) + c > MAX_HOST_CLIQUES) over = true;
     });
+    if (over) throw Error(-5, "a located component holds more than 1e8 h-cliques: its flow network is beyond "
+                              "the host exact step's limit");
+    uint64_t c = 0;
+    for (uint64_t x : cnt) c += x;
     return c;
 }
 

@@ -528,41 +528,6 @@ __device__ __forceinline__ u64 h3_wave_range(const PeelBufs &b, int32_t v, int64
     return destroyed;
 }
 
-// small frontier vertices (degree <= SMALL_DEG): one wave each, per-wave LDS hash
-__global__ __launch_bounds__(BLOCK) void k_process_h3_small(PeelBufs b) {
-    __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
-    __shared__ uint32_t sVal[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
-    __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
-    __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
-    __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
-    __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
-    PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0) return;
-    const int32_t r = c->round;
-    const int32_t *F = b.F + (size_t)cur * b.n;
-    const int wv = threadIdx.x / WAVE, L = lane();
-    const NbHash hs{sKey[wv], sVal[wv], 1u << SMALL_HASH_BITS};
-    for (int i = L; i < (1 << SMALL_HASH_BITS); i += WAVE) {
-        hs.keys[i] = HASH_EMPTY;
-        hs.vals[i] = 0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int64_t fi = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; fi < nF; fi += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
-        const int32_t v = F[fi];
-        const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
-        if (rv1 - rv0 > SMALL_DEG) continue;                     // chunk items cover it
-        hash_fill(b, hs, v, rv0, rv1, r, L, WAVE);
-        __builtin_amdgcn_wave_barrier();
-        u64 destroyed = h3_wave_range(b, v, rv0, rv1, r, hs, sPre[wv], sSt[wv], sW[wv], sCnt[wv], 0x7fffffff);
-        __builtin_amdgcn_wave_barrier();
-        hash_flush(b, hs, r, 0, hs.size, L, WAVE);
-        __builtin_amdgcn_wave_barrier();
-        destroyed = wave_sum(destroyed);
-        if (L == 0) add_destroyed(b, v, destroyed);
-    }
-}
-
 // Larger frontier vertices (degree > SMALL_DEG) are cut into chunks of CHUNK
 // neighbours, one wave each, so that the pairs of a hub spread over the whole
 // chip.  Their neighbourhood hashes live in global memory (SLOTS_PER_CHUNK
@@ -609,23 +574,50 @@ __global__ __launch_bounds__(BLOCK) void k_h3_fill(PeelBufs b) {
     }
 }
 
+// The round's triangle work, one wave per item: chunk items and wide items
+// of the large frontier vertices (their hashes filled by k_h3_fill), then
+// every small frontier vertex (degree <= SMALL_DEG) whole, with a per-wave
+// LDS hash that the wave fills, probes and flushes itself.
 __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
+    __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
+    __shared__ uint32_t sVal[WAVES_PER_BLOCK][1 << SMALL_HASH_BITS];
     __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
     __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
     __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
     __shared__ uint32_t sCnt[WAVES_PER_BLOCK][WAVE];
     PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur;
-    if (c->nF[cur] == 0) return;
+    const int32_t cur = c->cur, nF = c->nF[cur];
+    if (nF == 0) return;
     const int32_t r = c->round, nB = c->nB[cur];
     const int64_t nW = c->nW;
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
-    const int wv = threadIdx.x / WAVE;
+    const int32_t *F = b.F + (size_t)cur * b.n;
+    const int wv = threadIdx.x / WAVE, L = lane();
+    const NbHash small{sKey[wv], sVal[wv], 1u << SMALL_HASH_BITS};
+    for (int i = L; i < (1 << SMALL_HASH_BITS); i += WAVE) {
+        small.keys[i] = HASH_EMPTY;
+        small.vals[i] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
     u64 wp = 0, wn = 0;   // counted work (wave-uniform)
-    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB + nW; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+    const int64_t total = (int64_t)nB + nW + nF;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < total; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         int32_t v;
         u64 destroyed;
-        if (it < nB) {
+        if (it >= (int64_t)nB + nW) {
+            // a small frontier vertex, whole
+            v = F[it - nB - nW];
+            const int64_t rv0 = b.row_ptr[v], rv1 = b.row_ptr[v + 1];
+            if (rv1 - rv0 > SMALL_DEG) continue;                 // its chunk items cover it
+            hash_fill(b, small, v, rv0, rv1, r, L, WAVE);
+            __builtin_amdgcn_wave_barrier();
+            destroyed = h3_wave_range(b, v, rv0, rv1, r, small, sPre[wv], sSt[wv], sW[wv], sCnt[wv], 0x7fffffff,
+                                      &wp, &wn);
+            __builtin_amdgcn_wave_barrier();
+            hash_flush(b, small, r, 0, small.size, L, WAVE);
+            __builtin_amdgcn_wave_barrier();
+            destroyed = wave_sum(destroyed);
+        } else if (it < nB) {
             // chunk item: the neighbours with short out-lists, their pairs flattened over the wave
             const int64_t item = Bc[it];
             v = (int32_t)(item >> 32);
@@ -1058,7 +1050,6 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             if (h == 2) {
                 main_timer.launch(k_process_h2, dim3(gproc), dim3(BLOCK), s, b);
             } else if (h == 3) {
-                k_process_h3_small<<<gproc, BLOCK, 0, s>>>(b);
                 k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
                 main_timer.launch(k_h3_probe, dim3(gproc), dim3(BLOCK), s, b);
                 k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
