@@ -83,6 +83,9 @@ typedef struct {
      * zero for h >= 4 */
     double k4_main_ms;
     uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
+    /* minimum cuts of the exact step computed on the GPU (the others ran on
+     * the host) */
+    uint64_t flow_gpu_calls;
 } dsd_stats;
 
 /*

@@ -230,6 +230,7 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
     G->stats.flow_nodes_max = es.max_nodes;
     G->stats.t_flow_build_ms = es.build_ms;
     G->stats.t_flow_ms = es.flow_ms;
+    G->stats.flow_gpu_calls = es.gpu_flow_calls;
     if (improved) {
         rho = dsd_rational{l.num, l.den};
         std::vector<uint8_t> hm(n, 0);

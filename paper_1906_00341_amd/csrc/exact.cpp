@@ -29,10 +29,12 @@
 #include <deque>
 #include <memory>
 #include <atomic>
+#include <cstdlib>
 #include <numeric>
 #include <thread>
 
 #include "common.hpp"
+#include "flow.hpp"
 
 namespace dsd {
 
@@ -41,6 +43,15 @@ static const int64_t CAP_LIMIT = (int64_t)1 << 62;
 // Every network is built over a subset of one component, so bounding the
 // h-cliques of each component bounds every network (about h arcs per clique).
 static const uint64_t MAX_HOST_CLIQUES = 100000000ull;
+// Networks with at least this many residual arcs get their minimum cut on the
+// GPU (DSD_FLOW_GPU_MIN_ARCS overrides; a negative value keeps every cut on
+// the host).  A device run that has not converged after GPU_FLOW_MAX_PASSES
+// push/relabel passes is redone by the host push-relabel.
+static const int64_t GPU_FLOW_MAX_PASSES = 200000;
+static int64_t gpu_flow_min_arcs() {
+    const char *e = getenv("DSD_FLOW_GPU_MIN_ARCS");
+    return e ? (int64_t)atoll(e) : (int64_t)1 << 21;
+}
 
 // ---------------------------------------------------------------- host threads
 
@@ -183,6 +194,12 @@ public:
         cap_[rev_[fwd_[i]]] = rc;
     }
     int nodes() const { return n_; }
+    // the residual CSR (valid after build) and the capacities set for a test
+    int64_t residual_arcs() const { return 2 * E_; }
+    const int *first_data() const { return first_.data(); }
+    const int *to_data() const { return to_.p.get(); }
+    const int *rev_data() const { return rev_.p.get(); }
+    const int64_t *cap_data() const { return cap_.p.get(); }
 
     int64_t maxflow(int s, int t) {
         ex_.assign(n_, 0);
@@ -590,6 +607,7 @@ public:
 
     uint64_t mu() const { return mu_; }
     int nodes() const { return net_->nodes(); }
+    int64_t gpu_calls() const { return gpu_calls_; }
 
     // Strict test at alpha = a/b.  Returns true and the found set (local ids)
     // when some subgraph of this vertex set is denser than alpha.
@@ -620,10 +638,21 @@ public:
             set_all(mid_, (int64_t)b, 0);
         }
         if (srcsum >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
-        int64_t f = net_->maxflow(0, 1);
-        if ((i128)f >= srcsum) return false;
+        int64_t f = 0;
         std::vector<char> reach;
-        net_->reach_sink(1, reach);
+        bool done = false;
+        const int64_t A = net_->residual_arcs();
+        if (gpu_flow_min_arcs() >= 0 && A >= gpu_flow_min_arcs()) {
+            // the network goes to the device once; capacities per test
+            if (!gpu_) gpu_.reset(new GpuFlow(net_->nodes(), A, net_->first_data(), net_->to_data(), net_->rev_data()));
+            f = gpu_->maxflow(net_->cap_data(), 0, 1, reach, GPU_FLOW_MAX_PASSES, &done);
+            if (done) gpu_calls_++;
+        }
+        if (!done) {
+            f = net_->maxflow(0, 1);
+            if ((i128)f < srcsum) net_->reach_sink(1, reach);
+        }
+        if ((i128)f >= srcsum) return false;
         found.clear();
         for (int i = 0; i < nv; i++)
             if (!reach[2 + i]) found.push_back(verts_[i]);
@@ -648,6 +677,8 @@ private:
     std::vector<uint32_t> psi_first_;
     uint64_t mu_ = 0, m_ = 0;
     PushRelabel *net_ = nullptr;
+    std::unique_ptr<GpuFlow> gpu_;
+    int64_t gpu_calls_ = 0;
 };
 
 bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::vector<int32_t> &best,
@@ -695,7 +726,9 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             auto t1 = std::chrono::steady_clock::now();
             st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
             st.flow_calls++;
+            const int64_t g0 = net->gpu_calls();
             bool denser = net->denser_than(lc_l.num, lc_l.den, found);
+            st.gpu_flow_calls += net->gpu_calls() - g0;
             auto t2 = std::chrono::steady_clock::now();
             st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
             st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();

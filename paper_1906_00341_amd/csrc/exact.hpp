@@ -23,6 +23,7 @@ struct Rational {
 struct ExactStats {
     int64_t flow_calls = 0;
     int64_t max_nodes = 0;
+    int64_t gpu_flow_calls = 0;          // minimum cuts computed on the GPU
     double build_ms = 0, flow_ms = 0;   // network construction / maximum flow
 };
 

@@ -1,0 +1,310 @@
+// Maximum preflow and minimum cut on the GPU for the exact step's networks
+// (Algorithm 1's network, Goldberg's network for h = 2).
+//
+// Synchronous push-relabel.  A pass is two kernels: every active node (excess
+// > 0, height < n) pushes along all of its admissible arcs (residual > 0,
+// one level lower) with heights fixed for the whole kernel, then every node
+// still active with no admissible arc left is relabelled to one above its
+// lowest residual neighbour.  With heights fixed, an arc and its reverse are
+// never both admissible, so a push writes its arc pair without races; only
+// the receivers' excess needs atomics.  Relabels only raise heights, so a
+// neighbour relabelled concurrently leaves the new label valid.  Global
+// relabelling (breadth-first search from t over residual arcs, level by
+// level) sets exact distances, and marks the nodes that cannot reach t: they
+// hold the source side of the maximal minimum cut.  Only the maximum preflow
+// is computed: its value is the maximum flow value.
+//
+// One wave per node: the lanes scan the node's arcs 64 at a time, and a
+// node's excess is spread over its admissible arcs by a prefix sum.
+#include <vector>
+
+#include "common.hpp"
+#include "flow.hpp"
+#include "primitives.hpp"
+
+namespace dsd {
+
+namespace {
+
+// inclusive prefix sum of non-negative values, saturating at SAT (saturating
+// addition of non-negative numbers is associative, so the scan is exact
+// below SAT)
+constexpr int64_t SAT = (int64_t)1 << 62;
+__device__ __forceinline__ int64_t wave_incl_scan_sat(int64_t v) {
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int64_t t = __shfl_up(v, o, WAVE);
+        if (lane() >= o) v = (v > SAT - t) ? SAT : v + t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        int t = __shfl_xor(v, o, WAVE);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+struct FlowBufs {
+    int n, s, t;
+    const int *first, *to, *rev;
+    int64_t *cf, *ex;
+    int *ht;
+    int *front[2];
+    int *nfront;   // [2] frontier sizes
+    int *active;   // active node count
+};
+
+__global__ void k_flow_init(FlowBufs b, const int64_t *cap, int64_t A) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A; i += (int64_t)gridDim.x * blockDim.x)
+        b.cf[i] = cap[i];
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < b.n; v += (int64_t)gridDim.x * blockDim.x)
+        b.ex[v] = 0;
+}
+
+// saturate every arc out of s (one wave)
+__global__ void k_flow_saturate(FlowBufs b) {
+    int64_t sent = 0;
+    for (int a = b.first[b.s] + lane(); a < b.first[b.s + 1]; a += WAVE) {
+        const int64_t c = b.cf[a];
+        if (c <= 0) continue;
+        b.cf[a] = 0;
+        b.cf[b.rev[a]] += c;
+        atomicAdd((unsigned long long *)&b.ex[b.to[a]], (unsigned long long)c);
+        sent += c;
+    }
+    sent = wave_sum(sent);
+    if (lane() == 0) atomicAdd((unsigned long long *)&b.ex[b.s], (unsigned long long)(-sent));
+}
+
+// breadth-first search from t over residual arcs (u -> v with residual > 0
+// means u reaches v): start
+__global__ void k_bfs_start(FlowBufs b) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < b.n; v += gridDim.x * blockDim.x)
+        b.ht[v] = v == b.t ? 0 : b.n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.front[0][0] = b.t;
+        b.nfront[0] = 1;
+        b.nfront[1] = 0;
+    }
+}
+
+// one level: every node of front[cur] (height `level`) labels its unlabelled
+// in-neighbours (u with a residual arc u -> v) level + 1
+__global__ __launch_bounds__(BLOCK) void k_bfs_level(FlowBufs b, int cur, int level) {
+    const int nf = b.nfront[cur];
+    const int *F = b.front[cur];
+    int *N = b.front[cur ^ 1];
+    const int wv = threadIdx.x / WAVE;
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + wv; i < nf; i += gridDim.x * WAVES_PER_BLOCK) {
+        const int v = F[i];
+        for (int a0 = b.first[v]; a0 < b.first[v + 1]; a0 += WAVE) {
+            const int a = a0 + lane();
+            bool take = false;
+            int u = -1;
+            if (a < b.first[v + 1]) {
+                u = b.to[a];
+                // the arc u -> v is rev[a]
+                if (u != b.s && b.cf[b.rev[a]] > 0 && b.ht[u] == b.n)
+                    take = atomicCAS(&b.ht[u], b.n, level + 1) == b.n;
+            }
+            const u64 m = __ballot(take);
+            if (m) {
+                const int leader = __builtin_ctzll(m);
+                int base = 0;
+                if (lane() == leader) base = atomicAdd(&b.nfront[cur ^ 1], __popcll(m));
+                base = __shfl(base, leader, WAVE);
+                if (take) N[base + __popcll(m & lanemask_lt())] = u;
+            }
+        }
+    }
+}
+
+__global__ void k_bfs_reset(FlowBufs b, int cur) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.nfront[cur] = 0;
+}
+
+// push phase: heights are read-only here
+__global__ __launch_bounds__(BLOCK) void k_flow_push(FlowBufs b) {
+    const int wv = threadIdx.x / WAVE;
+    for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
+        if (u == b.s || u == b.t) continue;
+        const int hu = __shfl(b.ht[u], 0, WAVE);
+        int64_t rem = __shfl(b.ex[u], 0, WAVE);   // one snapshot for the whole wave
+        if (rem <= 0 || hu >= b.n) continue;
+        const int64_t start = rem;
+        for (int a0 = b.first[u]; a0 < b.first[u + 1] && rem > 0; a0 += WAVE) {
+            const int a = a0 + lane();
+            int64_t c = 0;
+            int v = -1;
+            if (a < b.first[u + 1]) {
+                v = b.to[a];
+                const int64_t r = b.cf[a];
+                if (r > 0 && b.ht[v] == hu - 1) c = r < rem ? r : rem;
+            }
+            const int64_t inc = wave_incl_scan_sat(c);
+            const int64_t before = inc - c;
+            int64_t d = rem - before;
+            d = d < 0 ? 0 : (d > c ? c : d);
+            if (d > 0) {
+                b.cf[a] -= d;
+                b.cf[b.rev[a]] += d;
+                atomicAdd((unsigned long long *)&b.ex[v], (unsigned long long)d);
+            }
+            const int64_t total = __shfl(inc, WAVE - 1, WAVE);
+            rem -= total < rem ? total : rem;
+        }
+        if (lane() == 0 && rem != start)
+            atomicAdd((unsigned long long *)&b.ex[u], (unsigned long long)(rem - start));
+    }
+}
+
+// relabel phase: an active node without admissible arcs rises to one above
+// its lowest residual neighbour (n when it has none: it cannot reach t)
+__global__ __launch_bounds__(BLOCK) void k_flow_relabel(FlowBufs b) {
+    const int wv = threadIdx.x / WAVE;
+    int act = 0;
+    for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
+        if (u == b.s || u == b.t) continue;
+        const int hu = __shfl(b.ht[u], 0, WAVE);
+        const int64_t eu = __shfl(b.ex[u], 0, WAVE);
+        if (eu <= 0 || hu >= b.n) continue;
+        int hmin = 0x7fffffff;
+        for (int a0 = b.first[u]; a0 < b.first[u + 1]; a0 += WAVE) {
+            const int a = a0 + lane();
+            if (a < b.first[u + 1] && b.cf[a] > 0) {
+                const int hv = b.ht[b.to[a]];
+                hmin = hv < hmin ? hv : hmin;
+            }
+        }
+        hmin = wave_min_i32(hmin);
+        if (hmin >= hu) {
+            const int nh = hmin >= b.n - 1 ? b.n : hmin + 1;
+            if (lane() == 0) b.ht[u] = nh;
+            if (nh < b.n) act++;
+        } else {
+            act++;
+        }
+    }
+    if (lane() == 0 && act) atomicAdd(b.active, act);
+}
+
+__global__ void k_zero_i32(int *p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_reach(FlowBufs b, uint8_t *out) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < b.n; v += gridDim.x * blockDim.x)
+        out[v] = b.ht[v] < b.n ? 1 : 0;
+}
+
+}  // namespace
+
+struct GpuFlow::Impl {
+    hipStream_t s = nullptr;
+    Scratch sc;
+    FlowBufs b{};
+    int64_t A = 0;
+    int64_t *cap = nullptr;
+    int *pinned = nullptr;
+    ~Impl() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (pinned) (void)hipHostFree(pinned);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    int global_relabel();
+};
+
+GpuFlow::GpuFlow(int n, int64_t A, const int *first, const int *to, const int *rev) : p_(new Impl) {
+    Impl &I = *p_;
+    DSD_HIP(hipStreamCreateWithFlags(&I.s, hipStreamNonBlocking));
+    I.A = A;
+    FlowBufs &b = I.b;
+    b.n = n;
+    int *d_first = I.sc.get_n<int>(n + 1);
+    int *d_to = I.sc.get_n<int>(A), *d_rev = I.sc.get_n<int>(A);
+    DSD_HIP(hipMemcpyAsync(d_first, first, (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(d_to, to, (size_t)A * sizeof(int), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(d_rev, rev, (size_t)A * sizeof(int), hipMemcpyHostToDevice, I.s));
+    b.first = d_first;
+    b.to = d_to;
+    b.rev = d_rev;
+    b.cf = I.sc.get_n<int64_t>(A);
+    I.cap = I.sc.get_n<int64_t>(A);
+    b.ex = I.sc.get_n<int64_t>(n);
+    b.ht = I.sc.get_n<int>(n);
+    b.front[0] = I.sc.get_n<int>(n);
+    b.front[1] = I.sc.get_n<int>(n);
+    b.nfront = I.sc.get_n<int>(2);
+    b.active = I.sc.get_n<int>(1);
+    DSD_HIP(hipHostMalloc((void **)&I.pinned, 4 * sizeof(int), hipHostMallocDefault));
+    DSD_HIP(hipStreamSynchronize(I.s));
+}
+
+GpuFlow::~GpuFlow() = default;
+
+// global relabel (the scratch stays allocated until the Impl goes); returns
+// the number of levels
+int GpuFlow::Impl::global_relabel() {
+    k_bfs_start<<<grid_for(b.n, BLOCK, 4096), BLOCK, 0, s>>>(b);
+    int cur = 0, level = 0;
+    while (true) {
+        k_bfs_level<<<grid_for(b.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cur, level);
+        k_bfs_reset<<<1, 1, 0, s>>>(b, cur);
+        DSD_HIP(hipMemcpyAsync(pinned, b.nfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+        cur ^= 1;
+        level++;
+        if (pinned[0] == 0 || level > b.n) break;
+    }
+    return level;
+}
+
+int64_t GpuFlow::maxflow(const int64_t *cap, int s, int t, std::vector<char> &reach_t, int64_t max_passes,
+                         bool *converged) {
+    Impl &I = *p_;
+    FlowBufs &b = I.b;
+    b.s = s;
+    b.t = t;
+    DSD_HIP(hipMemcpyAsync(I.cap, cap, (size_t)I.A * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
+    k_flow_init<<<grid_for(I.A, BLOCK, 16384), BLOCK, 0, I.s>>>(b, I.cap, I.A);
+    k_flow_saturate<<<1, WAVE, 0, I.s>>>(b);
+    I.global_relabel();
+    const int gpass = grid_for(b.n, WAVES_PER_BLOCK, 16384);
+    int64_t passes = 0;
+    *converged = false;
+    int since_relabel = 0;
+    while (passes < max_passes) {
+        for (int i = 0; i < 8; i++) {
+            k_zero_i32<<<1, 1, 0, I.s>>>(b.active);
+            k_flow_push<<<gpass, BLOCK, 0, I.s>>>(b);
+            k_flow_relabel<<<gpass, BLOCK, 0, I.s>>>(b);
+        }
+        passes += 8;
+        since_relabel += 8;
+        DSD_HIP(hipMemcpyAsync(I.pinned, b.active, sizeof(int), hipMemcpyDeviceToHost, I.s));
+        DSD_HIP(hipStreamSynchronize(I.s));
+        if (I.pinned[0] == 0) {
+            *converged = true;
+            break;
+        }
+        if (since_relabel >= 32) {
+            I.global_relabel();
+            since_relabel = 0;
+        }
+    }
+    int64_t flow = 0;
+    DSD_HIP(hipMemcpyAsync(&flow, b.ex + t, sizeof(int64_t), hipMemcpyDeviceToHost, I.s));
+    // the final search marks the nodes that still reach t
+    I.global_relabel();
+    uint8_t *r = I.sc.get_n<uint8_t>(b.n);
+    k_reach<<<grid_for(b.n, BLOCK, 4096), BLOCK, 0, I.s>>>(b, r);
+    std::vector<uint8_t> hr(b.n);
+    DSD_HIP(hipMemcpyAsync(hr.data(), r, b.n, hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
+    reach_t.assign(hr.begin(), hr.end());
+    return flow;
+}
+
+}  // namespace dsd

@@ -220,6 +220,34 @@ def test_union_of_complete_graphs(h):
     assert dens == Fraction(math.comb(1281, h), 1281)
 
 
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_exact_with_every_min_cut_on_the_gpu(fixtures, monkeypatch, h):
+    # every network of the exact step goes to the device push-relabel
+    monkeypatch.setenv("DSD_FLOW_GPU_MIN_ARCS", "0")
+    cases = []
+    for name in ("F1", "F4"):
+        e = np.asarray(fixtures[name]["edges"], np.int32)
+        cases.append((int(fixtures[name]["n"]), e[:, 0], e[:, 1]))
+    for seed in range(4):
+        cases.append(synth.er_planted(n=300, m=1500, plant=25, p=0.6, seed=40 + seed))
+    cases.append(synth.er_planted(seed=2))
+    gpu_cuts = 0
+    for n, s, d in cases:
+        og = oracle.Graph(n, s, d)
+        gg = dsd.build_csr(n, np.ascontiguousarray(s, np.int32), np.ascontiguousarray(d, np.int32))
+        _, rho_o, _ = og.exact(h, "core")
+        mem_g, rho_g = dsd.core_exact(gg, h)
+        st = gg.stats()
+        assert st["flow_gpu_calls"] == st["flow_calls"]
+        gpu_cuts += st["flow_gpu_calls"]
+        assert rho_g == rho_o
+        if rho_o > 0:
+            assert density_of(og, h, mem_g) == rho_o
+            core_o, _ = og.core_decomposition(h)
+            assert (core_o[mem_g.astype(bool)] >= math.ceil(rho_o)).all()
+    assert gpu_cuts > 0
+
+
 def test_bad_arguments():
     g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     for h in (0, 1, 7):
