@@ -14,7 +14,8 @@
 // hold the source side of the maximal minimum cut.  Only the maximum preflow
 // is computed: its value is the maximum flow value.
 //
-// One wave per node: the lanes scan the node's arcs 64 at a time, and a
+// One wave per node (its lanes scan the arcs 64 at a time), except nodes with
+// more than BIG_ARCS residual arcs, which take a 1024-thread block each; a
 // node's excess is spread over its admissible arcs by a prefix sum.
 #include <vector>
 
@@ -46,8 +47,14 @@ __device__ __forceinline__ int wave_min_i32(int v) {
     return v;
 }
 
+constexpr int BIG_ARCS = 4096;
+constexpr int BIG_BLOCK = 1024;
+constexpr int BIG_WAVES = BIG_BLOCK / WAVE;
+
 struct FlowBufs {
     int n, s, t;
+    const int *big;   // nodes with more than BIG_ARCS arcs
+    int nbig;
     const int *first, *to, *rev;
     int64_t *cf, *ex;
     int *ht;
@@ -125,11 +132,11 @@ __global__ void k_bfs_reset(FlowBufs b, int cur) {
     if (blockIdx.x == 0 && threadIdx.x == 0) b.nfront[cur] = 0;
 }
 
-// push phase: heights are read-only here
+// push phase: heights are read-only here (nodes up to BIG_ARCS arcs)
 __global__ __launch_bounds__(BLOCK) void k_flow_push(FlowBufs b) {
     const int wv = threadIdx.x / WAVE;
     for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
-        if (u == b.s || u == b.t) continue;
+        if (u == b.s || u == b.t || b.first[u + 1] - b.first[u] > BIG_ARCS) continue;
         const int hu = __shfl(b.ht[u], 0, WAVE);
         int64_t rem = __shfl(b.ex[u], 0, WAVE);   // one snapshot for the whole wave
         if (rem <= 0 || hu >= b.n) continue;
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_flow_relabel(FlowBufs b) {
     const int wv = threadIdx.x / WAVE;
     int act = 0;
     for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
-        if (u == b.s || u == b.t) continue;
+        if (u == b.s || u == b.t || b.first[u + 1] - b.first[u] > BIG_ARCS) continue;
         const int hu = __shfl(b.ht[u], 0, WAVE);
         const int64_t eu = __shfl(b.ex[u], 0, WAVE);
         if (eu <= 0 || hu >= b.n) continue;
@@ -188,6 +195,120 @@ __global__ __launch_bounds__(BLOCK) void k_flow_relabel(FlowBufs b) {
         }
     }
     if (lane() == 0 && act) atomicAdd(b.active, act);
+}
+
+// block-wide inclusive saturating scan of one value per thread; sW: BIG_WAVES entries
+__device__ __forceinline__ int64_t block_scan_sat(int64_t c, int64_t *sW, int64_t *total) {
+    const int wv = threadIdx.x / WAVE;
+    int64_t inc = wave_incl_scan_sat(c);
+    if (lane() == WAVE - 1) sW[wv] = inc;
+    __syncthreads();
+    int64_t before = 0;
+    for (int w = 0; w < wv; w++) before = (before > SAT - sW[w]) ? SAT : before + sW[w];
+    int64_t all = 0;
+    for (int w = 0; w < BIG_WAVES; w++) all = (all > SAT - sW[w]) ? SAT : all + sW[w];
+    __syncthreads();
+    *total = all;
+    return (inc > SAT - before) ? SAT : inc + before;
+}
+
+// push phase for the nodes with more than BIG_ARCS arcs: one block each
+__global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
+    __shared__ int64_t sW[BIG_WAVES];
+    __shared__ int64_t sEx;
+    __shared__ int sHt;
+    for (int i = blockIdx.x; i < b.nbig; i += gridDim.x) {
+        const int u = b.big[i];
+        if (u == b.s || u == b.t) continue;
+        // one snapshot of the node for the whole block (others add to its
+        // excess concurrently), so every thread takes the same path
+        if (threadIdx.x == 0) {
+            sHt = b.ht[u];
+            sEx = b.ex[u];
+        }
+        __syncthreads();
+        const int hu = sHt;
+        int64_t rem = sEx;
+        __syncthreads();
+        if (rem <= 0 || hu >= b.n) continue;
+        const int64_t start = rem;
+        for (int a0 = b.first[u]; a0 < b.first[u + 1] && rem > 0; a0 += BIG_BLOCK) {
+            const int a = a0 + threadIdx.x;
+            int64_t c = 0;
+            int v = -1;
+            if (a < b.first[u + 1]) {
+                v = b.to[a];
+                const int64_t r = b.cf[a];
+                if (r > 0 && b.ht[v] == hu - 1) c = r < rem ? r : rem;
+            }
+            int64_t total;
+            const int64_t inc = block_scan_sat(c, sW, &total);
+            const int64_t before = inc - c;
+            int64_t d = rem - before;
+            d = d < 0 ? 0 : (d > c ? c : d);
+            if (d > 0) {
+                b.cf[a] -= d;
+                b.cf[b.rev[a]] += d;
+                atomicAdd((unsigned long long *)&b.ex[v], (unsigned long long)d);
+            }
+            rem -= total < rem ? total : rem;
+        }
+        if (threadIdx.x == 0 && rem != start)
+            atomicAdd((unsigned long long *)&b.ex[u], (unsigned long long)(rem - start));
+    }
+}
+
+// relabel phase for the nodes with more than BIG_ARCS arcs: one block each;
+// the scan stops once an admissible arc shows there is nothing to relabel
+__global__ __launch_bounds__(BIG_BLOCK) void k_flow_relabel_big(FlowBufs b) {
+    __shared__ int sMin[BIG_WAVES];
+    __shared__ int sAdm;
+    int act = 0;
+    __shared__ int64_t sEx;
+    __shared__ int sHt;
+    for (int i = blockIdx.x; i < b.nbig; i += gridDim.x) {
+        const int u = b.big[i];
+        if (u == b.s || u == b.t) continue;
+        if (threadIdx.x == 0) {
+            sHt = b.ht[u];
+            sEx = b.ex[u];
+            sAdm = 0;
+        }
+        __syncthreads();
+        const int hu = sHt;
+        const int64_t eu = sEx;
+        __syncthreads();
+        if (eu <= 0 || hu >= b.n) continue;
+        int hmin = 0x7fffffff;
+        for (int a0 = b.first[u]; a0 < b.first[u + 1]; a0 += BIG_BLOCK) {
+            const int a = a0 + threadIdx.x;
+            if (a < b.first[u + 1] && b.cf[a] > 0) {
+                const int hv = b.ht[b.to[a]];
+                hmin = hv < hmin ? hv : hmin;
+                if (hv < hu) sAdm = 1;
+            }
+            __syncthreads();
+            const bool stop = sAdm != 0;        // the same value for every thread
+            __syncthreads();                    // no thread writes sAdm before all have read it
+            if (stop) break;
+        }
+        hmin = wave_min_i32(hmin);
+        if (lane() == 0) sMin[threadIdx.x / WAVE] = hmin;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int m = 0x7fffffff;
+            for (int w = 0; w < BIG_WAVES; w++) m = sMin[w] < m ? sMin[w] : m;
+            if (!sAdm && m >= hu) {
+                const int nh = m >= b.n - 1 ? b.n : m + 1;
+                b.ht[u] = nh;
+                if (nh < b.n) act++;
+            } else {
+                act++;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && act) atomicAdd(b.active, act);
 }
 
 __global__ void k_zero_i32(int *p) {
@@ -238,6 +359,14 @@ GpuFlow::GpuFlow(int n, int64_t A, const int *first, const int *to, const int *r
     b.front[1] = I.sc.get_n<int>(n);
     b.nfront = I.sc.get_n<int>(2);
     b.active = I.sc.get_n<int>(1);
+    std::vector<int> big;
+    for (int v = 0; v < n; v++)
+        if (first[v + 1] - first[v] > BIG_ARCS) big.push_back(v);
+    b.nbig = (int)big.size();
+    int *d_big = I.sc.get_n<int>(b.nbig > 0 ? b.nbig : 1);
+    if (b.nbig > 0)
+        DSD_HIP(hipMemcpyAsync(d_big, big.data(), big.size() * sizeof(int), hipMemcpyHostToDevice, I.s));
+    b.big = d_big;
     DSD_HIP(hipHostMalloc((void **)&I.pinned, 4 * sizeof(int), hipHostMallocDefault));
     DSD_HIP(hipStreamSynchronize(I.s));
 }
@@ -279,7 +408,9 @@ int64_t GpuFlow::maxflow(const int64_t *cap, int s, int t, std::vector<char> &re
         for (int i = 0; i < 8; i++) {
             k_zero_i32<<<1, 1, 0, I.s>>>(b.active);
             k_flow_push<<<gpass, BLOCK, 0, I.s>>>(b);
+            if (b.nbig > 0) k_flow_push_big<<<b.nbig < 4096 ? b.nbig : 4096, BIG_BLOCK, 0, I.s>>>(b);
             k_flow_relabel<<<gpass, BLOCK, 0, I.s>>>(b);
+            if (b.nbig > 0) k_flow_relabel_big<<<b.nbig < 4096 ? b.nbig : 4096, BIG_BLOCK, 0, I.s>>>(b);
         }
         passes += 8;
         since_relabel += 8;

@@ -231,6 +231,11 @@ def test_exact_with_every_min_cut_on_the_gpu(fixtures, monkeypatch, h):
     for seed in range(4):
         cases.append(synth.er_planted(n=300, m=1500, plant=25, p=0.6, seed=40 + seed))
     cases.append(synth.er_planted(seed=2))
+    if h == 3:
+        # nodes with more than 4096 residual arcs take the block-per-node kernels
+        n, s, d = synth.complete_graph(110)
+        keep = np.random.default_rng(3).random(len(s)) < 0.97
+        cases.append((n, s[keep], d[keep]))
     gpu_cuts = 0
     for n, s, d in cases:
         og = oracle.Graph(n, s, d)
