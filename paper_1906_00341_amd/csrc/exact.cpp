@@ -194,12 +194,15 @@ public:
         cap_[rev_[fwd_[i]]] = rc;
     }
     int nodes() const { return n_; }
-    // the residual CSR (valid after build) and the capacities set for a test
+    int64_t arcs() const { return E_; }
     int64_t residual_arcs() const { return 2 * E_; }
-    const int *first_data() const { return first_.data(); }
-    const int *to_data() const { return to_.p.get(); }
-    const int *rev_data() const { return rev_.p.get(); }
-    const int64_t *cap_data() const { return cap_.p.get(); }
+    const int *eu_data() const { return eu_.p.get(); }
+    const int *ev_data() const { return ev_.p.get(); }
+    // the residual CSR is built on first use by the host maximum flow
+    void ensure_built() {
+        if (!built_) build();
+        built_ = true;
+    }
 
     int64_t maxflow(int s, int t) {
         ex_.assign(n_, 0);
@@ -324,6 +327,7 @@ private:
     }
 
     int n_, s_ = 0, t_ = 1;
+    bool built_ = false;
     int64_t E_ = 0, cap_arcs_ = 0;
     RawArray<int> eu_, ev_, fwd_, to_, rev_;
     RawArray<int64_t> cap_;
@@ -510,7 +514,6 @@ public:
                     mid_.push_back(net_->arc(2 + idx_[K[drop]], (int)(base + psi_of[c * h + drop])));
             }
         }
-        net_->build();
     }
     // h = 3: psi ranges over the edges of the vertex set (an edge is the
     // 2-clique left when one vertex of a triangle is taken away).  Triangles
@@ -613,42 +616,59 @@ public:
     // when some subgraph of this vertex set is denser than alpha.
     bool denser_than(uint64_t a, uint64_t b, std::vector<int32_t> &found) {
         const int nv = (int)verts_.size();
+        // every capacity must fit in 63 bits, and the infinite arcs above the total
         i128 srcsum = 0;
-        if (h_ == 2) {
-            const i128 bm = (i128)b * (i128)m_;
-            for (int i = 0; i < nv; i++) {
-                i128 cs = bm, ct = bm + 2 * (i128)a - (i128)b * (i128)deg_[i];
-                if (cs >= CAP_LIMIT || ct >= CAP_LIMIT || ct < 0) throw Error(-4, "scaled capacity overflow");
-                net_->set(src_[i], (int64_t)cs);
-                net_->set(snk_[i], (int64_t)ct);
-                srcsum += cs;
+        for (int i = 0; i < nv; i++) {
+            i128 cs, ct;
+            if (h_ == 2) {
+                cs = (i128)b * (i128)m_;
+                ct = cs + 2 * (i128)a - (i128)b * (i128)deg_[i];
+            } else {
+                cs = (i128)b * (i128)deg_[i];
+                ct = (i128)h_ * (i128)a;
             }
-            set_all(mid_, (int64_t)b, (int64_t)b);
-        } else {
-            for (int i = 0; i < nv; i++) {
-                i128 cs = (i128)b * (i128)deg_[i], ct = (i128)h_ * (i128)a;
-                if (cs >= CAP_LIMIT || ct >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
-                net_->set(src_[i], (int64_t)cs);
-                net_->set(snk_[i], (int64_t)ct);
-                srcsum += cs;
-            }
-            if (srcsum * 2 >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
-            const int64_t inf = (int64_t)srcsum + 1;
-            set_all(inf_, inf, 0);
-            set_all(mid_, (int64_t)b, 0);
+            if (cs >= CAP_LIMIT || ct >= CAP_LIMIT || ct < 0) throw Error(-4, "scaled capacity overflow");
+            srcsum += cs;
         }
-        if (srcsum >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+        if (srcsum * 2 >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+        const FlowTest test{h_, (int64_t)a, (int64_t)b, (int64_t)m_, (int64_t)srcsum + 1};
         int64_t f = 0;
         std::vector<char> reach;
         bool done = false;
-        const int64_t A = net_->residual_arcs();
-        if (gpu_flow_min_arcs() >= 0 && A >= gpu_flow_min_arcs()) {
-            // the network goes to the device once; capacities per test
-            if (!gpu_) gpu_.reset(new GpuFlow(net_->nodes(), A, net_->first_data(), net_->to_data(), net_->rev_data()));
-            f = gpu_->maxflow(net_->cap_data(), 0, 1, reach, GPU_FLOW_MAX_PASSES, &done);
+        if (gpu_flow_min_arcs() >= 0 && net_->residual_arcs() >= gpu_flow_min_arcs()) {
+            // the arcs go to the device once; the device sets each test's capacities
+            if (!gpu_) {
+                std::vector<uint8_t> cls(net_->arcs());
+                for (int e : src_) cls[e] = ARC_SRC;
+                for (int e : snk_) cls[e] = ARC_SNK;
+                for (int e : inf_) cls[e] = ARC_INF;
+                parallel_slices((int64_t)mid_.size(), host_threads(), [&](int, int64_t lo, int64_t hi) {
+                    for (int64_t i = lo; i < hi; i++) cls[mid_[i]] = ARC_MID;
+                });
+                gpu_.reset(new GpuFlow(net_->nodes(), net_->arcs(), net_->eu_data(), net_->ev_data(), cls.data(), nv,
+                                       deg_.data()));
+            }
+            f = gpu_->maxflow(test, reach, GPU_FLOW_MAX_PASSES, &done);
             if (done) gpu_calls_++;
         }
         if (!done) {
+            net_->ensure_built();
+            for (int i = 0; i < nv; i++) {
+                if (h_ == 2) {
+                    const int64_t cs = test.b * test.m;
+                    net_->set(src_[i], cs);
+                    net_->set(snk_[i], cs + 2 * test.a - test.b * (int64_t)deg_[i]);
+                } else {
+                    net_->set(src_[i], test.b * (int64_t)deg_[i]);
+                    net_->set(snk_[i], (int64_t)h_ * test.a);
+                }
+            }
+            if (h_ == 2) {
+                set_all(mid_, test.b, test.b);
+            } else {
+                set_all(inf_, test.inf, 0);
+                set_all(mid_, test.b, 0);
+            }
             f = net_->maxflow(0, 1);
             if ((i128)f < srcsum) net_->reach_sink(1, reach);
         }

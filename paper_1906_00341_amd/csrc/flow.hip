@@ -63,9 +63,47 @@ struct FlowBufs {
     int *active;   // active node count
 };
 
-__global__ void k_flow_init(FlowBufs b, const int64_t *cap, int64_t A) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A; i += (int64_t)gridDim.x * blockDim.x)
-        b.cf[i] = cap[i];
+// residual CSR from the arc list: degrees, then every arc and its reverse
+__global__ void k_csr_count(const int *eu, const int *ev, int64_t E, uint32_t *cnt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+        atomicAdd(&cnt[eu[i]], 1u);
+        atomicAdd(&cnt[ev[i]], 1u);
+    }
+}
+
+__global__ void k_csr_last(const uint32_t *cnt, int n, int *first) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) first[n] = first[n - 1] + (int)cnt[n - 1];
+}
+
+__global__ void k_csr_fill(const int *eu, const int *ev, int64_t E, uint32_t *fill, int *to, int *rev, int *fwd) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+        const int u = eu[i], v = ev[i];
+        const int pu = (int)atomicAdd(&fill[u], 1u), pv = (int)atomicAdd(&fill[v], 1u);
+        to[pu] = v;
+        to[pv] = u;
+        rev[pu] = pv;
+        rev[pv] = pu;
+        fwd[i] = pu;
+    }
+}
+
+// capacities of one test (see FlowTest), and zero excess
+__global__ void k_flow_caps(FlowBufs b, const int *eu, const int *ev, const uint8_t *cls, const int *fwd,
+                            const int64_t *deg, int64_t E, FlowTest t) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0, rc = 0;
+        switch (cls[i]) {
+            case ARC_SRC: c = t.h == 2 ? t.b * t.m : t.b * deg[ev[i] - 2]; break;
+            case ARC_SNK: c = t.h == 2 ? t.b * t.m + 2 * t.a - t.b * deg[eu[i] - 2] : (int64_t)t.h * t.a; break;
+            case ARC_INF: c = t.inf; break;
+            default:
+                c = t.b;
+                rc = t.h == 2 ? t.b : 0;
+        }
+        const int p = fwd[i];
+        b.cf[p] = c;
+        b.cf[b.rev[p]] = rc;
+    }
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < b.n; v += (int64_t)gridDim.x * blockDim.x)
         b.ex[v] = 0;
 }
@@ -326,8 +364,10 @@ struct GpuFlow::Impl {
     hipStream_t s = nullptr;
     Scratch sc;
     FlowBufs b{};
-    int64_t A = 0;
-    int64_t *cap = nullptr;
+    int64_t E = 0;
+    int *eu = nullptr, *ev = nullptr, *fwd = nullptr;
+    uint8_t *cls = nullptr;
+    int64_t *deg = nullptr;
     int *pinned = nullptr;
     ~Impl() {
         if (s) (void)hipStreamSynchronize(s);
@@ -337,31 +377,51 @@ struct GpuFlow::Impl {
     int global_relabel();
 };
 
-GpuFlow::GpuFlow(int n, int64_t A, const int *first, const int *to, const int *rev) : p_(new Impl) {
+GpuFlow::GpuFlow(int n, int64_t E, const int *eu, const int *ev, const uint8_t *cls, int nv,
+                 const uint64_t *deg)
+    : p_(new Impl) {
     Impl &I = *p_;
     DSD_HIP(hipStreamCreateWithFlags(&I.s, hipStreamNonBlocking));
-    I.A = A;
+    I.E = E;
+    const int64_t A = 2 * E;
     FlowBufs &b = I.b;
     b.n = n;
-    int *d_first = I.sc.get_n<int>(n + 1);
-    int *d_to = I.sc.get_n<int>(A), *d_rev = I.sc.get_n<int>(A);
-    DSD_HIP(hipMemcpyAsync(d_first, first, (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice, I.s));
-    DSD_HIP(hipMemcpyAsync(d_to, to, (size_t)A * sizeof(int), hipMemcpyHostToDevice, I.s));
-    DSD_HIP(hipMemcpyAsync(d_rev, rev, (size_t)A * sizeof(int), hipMemcpyHostToDevice, I.s));
-    b.first = d_first;
-    b.to = d_to;
-    b.rev = d_rev;
+    I.eu = I.sc.get_n<int>(E);
+    I.ev = I.sc.get_n<int>(E);
+    I.cls = I.sc.get_n<uint8_t>(E);
+    I.deg = I.sc.get_n<int64_t>(nv);
+    DSD_HIP(hipMemcpyAsync(I.eu, eu, (size_t)E * sizeof(int), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(I.ev, ev, (size_t)E * sizeof(int), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(I.cls, cls, (size_t)E, hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(I.deg, deg, (size_t)nv * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
+    // residual CSR: count, scan, fill
+    uint32_t *cnt = I.sc.get_n<uint32_t>(n), *fill = I.sc.get_n<uint32_t>(n);
+    int *first = I.sc.get_n<int>(n + 1);
+    int *to = I.sc.get_n<int>(A), *rev = I.sc.get_n<int>(A);
+    I.fwd = I.sc.get_n<int>(E);
+    fill_i32((int32_t *)cnt, 0, n, I.s);
+    k_csr_count<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, cnt);
+    scan_exclusive_u32(cnt, (uint32_t *)first, n, I.s, I.sc);
+    k_csr_last<<<1, 1, 0, I.s>>>(cnt, n, first);
+    DSD_HIP(hipMemcpyAsync(fill, first, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, I.s));
+    k_csr_fill<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, fill, to, rev, I.fwd);
+    b.first = first;
+    b.to = to;
+    b.rev = rev;
     b.cf = I.sc.get_n<int64_t>(A);
-    I.cap = I.sc.get_n<int64_t>(A);
     b.ex = I.sc.get_n<int64_t>(n);
     b.ht = I.sc.get_n<int>(n);
     b.front[0] = I.sc.get_n<int>(n);
     b.front[1] = I.sc.get_n<int>(n);
     b.nfront = I.sc.get_n<int>(2);
     b.active = I.sc.get_n<int>(1);
+    // nodes with more than BIG_ARCS residual arcs
+    std::vector<int> hfirst(n + 1);
+    DSD_HIP(hipMemcpyAsync(hfirst.data(), first, (size_t)(n + 1) * sizeof(int), hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
     std::vector<int> big;
     for (int v = 0; v < n; v++)
-        if (first[v + 1] - first[v] > BIG_ARCS) big.push_back(v);
+        if (hfirst[v + 1] - hfirst[v] > BIG_ARCS) big.push_back(v);
     b.nbig = (int)big.size();
     int *d_big = I.sc.get_n<int>(b.nbig > 0 ? b.nbig : 1);
     if (b.nbig > 0)
@@ -390,14 +450,13 @@ int GpuFlow::Impl::global_relabel() {
     return level;
 }
 
-int64_t GpuFlow::maxflow(const int64_t *cap, int s, int t, std::vector<char> &reach_t, int64_t max_passes,
-                         bool *converged) {
+int64_t GpuFlow::maxflow(const FlowTest &test, std::vector<char> &reach_t, int64_t max_passes, bool *converged) {
     Impl &I = *p_;
     FlowBufs &b = I.b;
-    b.s = s;
+    const int t = 1;
+    b.s = 0;
     b.t = t;
-    DSD_HIP(hipMemcpyAsync(I.cap, cap, (size_t)I.A * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
-    k_flow_init<<<grid_for(I.A, BLOCK, 16384), BLOCK, 0, I.s>>>(b, I.cap, I.A);
+    k_flow_caps<<<grid_for(I.E, BLOCK, 16384), BLOCK, 0, I.s>>>(b, I.eu, I.ev, I.cls, I.fwd, I.deg, I.E, test);
     k_flow_saturate<<<1, WAVE, 0, I.s>>>(b);
     I.global_relabel();
     const int gpass = grid_for(b.n, WAVES_PER_BLOCK, 16384);

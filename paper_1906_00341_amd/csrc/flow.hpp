@@ -7,22 +7,35 @@
 
 namespace dsd {
 
-// A residual network (CSR of every arc and its reverse, as the host
-// push-relabel builds it) resident on the device; its capacities change per
-// test.  Owns a stream of its own.
+// Arc classes of the exact step's networks (Algorithm 1; Goldberg's network
+// for h = 2): capacities follow from the class, the test density alpha = a/b
+// and the arc's vertex.
+enum FlowArc : uint8_t { ARC_SRC = 0, ARC_SNK = 1, ARC_INF = 2, ARC_MID = 3 };
+
+// Capacities of one test.  h >= 3: s->v b*deg(v), v->t h*a, psi->v inf,
+// v->psi b.  h = 2: s->v b*m, v->t b*m + 2a - b*deg(v), u<->v b both ways.
+// Every value has been checked to fit by the caller.
+struct FlowTest {
+    int h;
+    int64_t a, b, m, inf;
+};
+
+// A network resident on the device: its arcs (node 0 = s, node 1 = t, node
+// 2 + i = vertex i of the component) are uploaded once and the residual CSR
+// (every arc and its reverse) is built there; capacities are set per test by
+// a kernel.  Owns a stream of its own.
 class GpuFlow {
 public:
-    // first: n + 1 row offsets; to, rev: A entries (head of every residual
-    // arc, index of its reverse)
-    GpuFlow(int n, int64_t A, const int *first, const int *to, const int *rev);
+    // E arcs eu[i] -> ev[i] of class cls[i]; deg: clique-degree of each of
+    // the nv component vertices
+    GpuFlow(int n, int64_t E, const int *eu, const int *ev, const uint8_t *cls, int nv, const uint64_t *deg);
     ~GpuFlow();
     GpuFlow(const GpuFlow &) = delete;
     GpuFlow &operator=(const GpuFlow &) = delete;
-    // Maximum s-t flow value for the A residual capacities cap (host
-    // memory); reach_t[v] = 1 iff v reaches t in the final residual network.
-    // Gives up after max_passes push/relabel passes (*converged = false).
-    int64_t maxflow(const int64_t *cap, int s, int t, std::vector<char> &reach_t, int64_t max_passes,
-                    bool *converged);
+    // Maximum s-t flow value at the test's capacities; reach_t[v] = 1 iff v
+    // reaches t in the final residual network.  Gives up after max_passes
+    // push/relabel passes (*converged = false).
+    int64_t maxflow(const FlowTest &test, std::vector<char> &reach_t, int64_t max_passes, bool *converged);
     struct Impl;
 
 private:
