@@ -144,6 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_level(FlowBufs b, int cur, int le
     const int wv = threadIdx.x / WAVE;
     for (int i = blockIdx.x * WAVES_PER_BLOCK + wv; i < nf; i += gridDim.x * WAVES_PER_BLOCK) {
         const int v = F[i];
+        if (b.first[v + 1] - b.first[v] > BIG_ARCS) continue;     // k_bfs_level_big
         for (int a0 = b.first[v]; a0 < b.first[v + 1]; a0 += WAVE) {
             const int a = a0 + lane();
             bool take = false;
@@ -162,6 +163,34 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_level(FlowBufs b, int cur, int le
                 base = __shfl(base, leader, WAVE);
                 if (take) N[base + __popcll(m & lanemask_lt())] = u;
             }
+        }
+    }
+}
+
+// the same for frontier nodes with more than BIG_ARCS arcs: one block each
+__global__ __launch_bounds__(BIG_BLOCK) void k_bfs_level_big(FlowBufs b, int cur, int level) {
+    __shared__ int sBase[BIG_WAVES];
+    const int nf = b.nfront[cur];
+    const int *F = b.front[cur];
+    int *N = b.front[cur ^ 1];
+    const int wv = threadIdx.x / WAVE;
+    for (int i = blockIdx.x; i < nf; i += gridDim.x) {
+        const int v = F[i];
+        if (b.first[v + 1] - b.first[v] <= BIG_ARCS) continue;    // block-uniform
+        for (int a0 = b.first[v]; a0 < b.first[v + 1]; a0 += BIG_BLOCK) {
+            const int a = a0 + threadIdx.x;
+            bool take = false;
+            int u = -1;
+            if (a < b.first[v + 1]) {
+                u = b.to[a];
+                if (u != b.s && b.cf[b.rev[a]] > 0 && b.ht[u] == b.n)
+                    take = atomicCAS(&b.ht[u], b.n, level + 1) == b.n;
+            }
+            const u64 m = __ballot(take);
+            if (lane() == 0) sBase[wv] = m ? atomicAdd(&b.nfront[cur ^ 1], __popcll(m)) : 0;
+            __builtin_amdgcn_wave_barrier();
+            if (take) N[sBase[wv] + __popcll(m & lanemask_lt())] = u;
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -440,6 +469,7 @@ int GpuFlow::Impl::global_relabel() {
     int cur = 0, level = 0;
     while (true) {
         k_bfs_level<<<grid_for(b.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cur, level);
+        if (b.nbig > 0) k_bfs_level_big<<<1024, BIG_BLOCK, 0, s>>>(b, cur, level);
         k_bfs_reset<<<1, 1, 0, s>>>(b, cur);
         DSD_HIP(hipMemcpyAsync(pinned, b.nfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
         DSD_HIP(hipStreamSynchronize(s));

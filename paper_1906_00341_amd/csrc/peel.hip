@@ -1029,7 +1029,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipEventCreate(&e1));
         DSD_HIP(hipEventRecord(e0, s));
     }
-    const int gmin = 256, gbuild = 1024, gproc = 2048;
+    const int gmin = 256, gbuild = 1024, gproc = 2048, gprobe = 1024;
     LaunchTimer main_timer(kt != nullptr && h <= 3);
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
@@ -1051,7 +1051,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                 main_timer.launch(k_process_h2, dim3(gproc), dim3(BLOCK), s, b);
             } else if (h == 3) {
                 k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
-                main_timer.launch(k_h3_probe, dim3(gproc), dim3(BLOCK), s, b);
+                main_timer.launch(k_h3_probe, dim3(gprobe), dim3(BLOCK), s, b);
                 k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
