@@ -53,11 +53,12 @@ def _load():
     lib.orc_level_table.argtypes = [P, C.c_int, u64p, u64p, u64p, u64p, i64]
     lib.orc_inc_app.argtypes = [P, C.c_int, u8p, u64, u64, u64]
     lib.orc_core_app.argtypes = [P, C.c_int, C.c_int, C.c_int64, u8p, u64, u64, u64, i64]
+    lib.orc_peel_app.argtypes = [P, C.c_int, C.c_int, u8p, u64, u64, i64, i64]
     lib.orc_locate.argtypes = [P, C.c_int, u64p, u64, u64, u64, u64, u64, u64, i32p, i64]
     lib.orc_exact.argtypes = [P, C.c_int, C.c_int, u8p, u64, u64, i64]
     lib.orc_denser_than.argtypes = [P, C.c_int, C.c_uint64, C.c_uint64, u8p]
     for f in ("orc_clique_degrees", "orc_clique_degree_of", "orc_core_decomposition",
-              "orc_level_table", "orc_inc_app", "orc_core_app", "orc_locate",
+              "orc_level_table", "orc_inc_app", "orc_core_app", "orc_peel_app", "orc_locate",
               "orc_exact", "orc_denser_than"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -148,6 +149,19 @@ class Graph:
                                  C.byref(a), C.byref(b), C.byref(it)), "core_app")
         return (mem[: self.n].astype(bool), int(kmax.value),
                 Fraction(int(a.value), int(b.value)), int(it.value))
+
+    # -- Alg. 2 ---------------------------------------------------------
+    def peel_app(self, h: int, rounds: bool = True):
+        """PeelApp.  rounds=True: every minimum-degree vertex leaves in the
+        same step; False: one vertex (smallest id) per step.  Returns
+        (member, density, steps, best_step)."""
+        mem = np.zeros(max(1, self.n), dtype=np.uint8)
+        a, b = C.c_uint64(), C.c_uint64()
+        st, bs = C.c_int64(), C.c_int64()
+        _check(_lib.orc_peel_app(self._p, h, int(bool(rounds)), mem, C.byref(a), C.byref(b),
+                                 C.byref(st), C.byref(bs)), "peel_app")
+        return (mem[: self.n].astype(bool), Fraction(int(a.value), int(b.value)),
+                int(st.value), int(bs.value))
 
     # -- Pruning1/2 -----------------------------------------------------
     def locate(self, h: int, core):

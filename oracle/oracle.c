@@ -671,6 +671,85 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* Alg. 2 (PeelApp)                                                      */
+/* S starts as G; a step removes vertices of minimum clique-degree in S   */
+/* and every h-clique through them.  The answer is the densest of the     */
+/* residual graphs seen before each step (G included), the first one      */
+/* when several tie.  rounds = 0: one vertex per step, the smallest id     */
+/* among the minima (Alg. 2 as printed).  rounds = 1: every vertex at the  */
+/* minimum leaves in the same step.                                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct { uint64_t *deg; uint64_t destroyed; int32_t v; } papctx;
+
+static void emit_remove(void *c, const int32_t *mem, int size) {
+    papctx *p = (papctx *)c;
+    for (int i = 0; i < size; i++)
+        if (mem[i] != p->v) p->deg[mem[i]]--;
+    p->destroyed++;
+}
+
+int orc_peel_app(const orc_graph *g, int h, int rounds, uint8_t *member,
+                 uint64_t *num, uint64_t *den, int64_t *steps, int64_t *best_step) {
+    if (h < 2 || h > ORC_HMAX) return ORC_EINVAL;
+    int32_t n = g->n;
+    memset(member, 0, (size_t)n);
+    *num = 0; *den = 1; *steps = 0; *best_step = -1;
+    uint64_t *deg = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+    uint8_t *alive = (uint8_t *)malloc((size_t)n + 1);
+    int64_t *gone = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t *F = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!deg || !alive || !gone || !F) { free(deg); free(alive); free(gone); free(F); return ORC_ENOMEM; }
+    uint64_t mu;
+    int rc = orc_clique_degrees(g, h, deg, &mu);
+    if (rc) { free(deg); free(alive); free(gone); free(F); return rc; }
+    papctx pc = {deg, 0, -1};
+    lister L;
+    if (lister_init(&L, g, h, emit_remove, &pc)) {
+        lister_free(&L); free(deg); free(alive); free(gone); free(F); return ORC_ENOMEM;
+    }
+    for (int32_t v = 0; v < n; v++) { alive[v] = 1; gone[v] = -1; }
+    uint64_t size = (uint64_t)n, bn = 0, bd = 1;
+    int64_t t = 0;
+    while (size > 0) {
+        /* the residual graph S before this step: |S| = size, mu(S) = mu */
+        if (frac_gt(mu, size, bn, bd)) { bn = mu; bd = size; *best_step = t; }
+        uint64_t mn = UINT64_MAX;
+        for (int32_t v = 0; v < n; v++)
+            if (alive[v] && deg[v] < mn) mn = deg[v];
+        int32_t nf = 0;
+        for (int32_t v = 0; v < n; v++)
+            if (alive[v] && deg[v] == mn) {
+                F[nf++] = v;
+                if (!rounds) break;
+            }
+        /* remove F one vertex after another: a clique with several members
+         * in F is listed (and destroyed) once, from the first of them */
+        for (int32_t i = 0; i < nf; i++) {
+            pc.v = F[i];
+            pc.destroyed = 0;
+            list_containing(&L, F[i], alive);
+            alive[F[i]] = 0;
+            gone[F[i]] = t;
+            mu -= pc.destroyed;
+            size--;
+        }
+        t++;
+    }
+    lister_free(&L);
+    *steps = t;
+    if (*best_step >= 0 && bn > 0) {
+        for (int32_t v = 0; v < n; v++) member[v] = gone[v] >= *best_step ? 1 : 0;
+        *num = bn; *den = bd;
+        reduce(num, den);
+    } else {
+        *best_step = -1;
+    }
+    free(deg); free(alive); free(gone); free(F);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Pruning1 / Pruning2 (Section 6.1)                                     */
 /* ------------------------------------------------------------------ */
 

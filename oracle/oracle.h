@@ -22,7 +22,9 @@
  *     the minimal minimum cut (vertices reachable from s in the residual
  *     network), which is what Lemma 14 characterises;
  *   - alpha lives on an integer grid p/Q so that capacities are integers;
- *   - CoreApp (Alg. 6): see orc_core_app.
+ *   - CoreApp (Alg. 6): see orc_core_app;
+ *   - PeelApp (Alg. 2) compares the residual graph before every step, G
+ *     included, and keeps the first of equally dense ones: see orc_peel_app.
  */
 #ifndef DSD_ORACLE_H
 #define DSD_ORACLE_H
@@ -80,6 +82,15 @@ int orc_inc_app(const orc_graph *g, int h, uint8_t *member, uint64_t *kmax,
 int orc_core_app(const orc_graph *g, int h, int literal, int64_t w0,
                  uint8_t *member, uint64_t *kmax, uint64_t *num, uint64_t *den,
                  int64_t *iterations);
+
+/* Alg. 2 (PeelApp).  A step removes vertices of minimum clique-degree from
+ * the residual graph S (rounds = 0: the one of smallest id, as printed;
+ * rounds = 1: all of them at once).  member marks the densest residual graph
+ * seen before a step (G included; the first one on ties), num/den its
+ * density; steps = number of steps, best_step = the step before which it was
+ * seen (-1 and an empty member set when no residual graph holds a clique). */
+int orc_peel_app(const orc_graph *g, int h, int rounds, uint8_t *member,
+                 uint64_t *num, uint64_t *den, int64_t *steps, int64_t *best_step);
 
 /* Pruning1/2 (Section 6.1): rho' = max level density, k' = ceil(rho');
  * components of R_{k'}; rho'' = max component density; k'' = max(k', ceil(rho'')).

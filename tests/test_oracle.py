@@ -408,3 +408,99 @@ def test_core_app_literal_keeps_stale_core():
     ml, kl, _, _ = g.core_app(2, literal=True, w0=5)
     assert kc == kl == 4
     assert members(mc) == list(range(10)) and members(ml) != list(range(10))
+
+
+# ---------------------------------------------------------- Algorithm 2 PeelApp
+
+def _peel_replay(n, edges, h, rounds):
+    """Algorithm 2 replayed from scratch: the clique-degrees of every residual
+    graph are recounted by brute force (Definition 3), never decremented."""
+    alive = set(range(n))
+    best, best_step, gone, t = Fraction(0), -1, {}, 0
+    while alive:
+        deg, mu = brute.clique_degrees(n, edges, h, alive)
+        if Fraction(mu, len(alive)) > best:
+            best, best_step = Fraction(mu, len(alive)), t
+        mn = min(deg[v] for v in alive)
+        drop = sorted(v for v in alive if deg[v] == mn)
+        if not rounds:
+            drop = drop[:1]
+        for v in drop:
+            gone[v] = t
+        alive -= set(drop)
+        t += 1
+    mem = [v for v in range(n) if best_step >= 0 and gone[v] >= best_step]
+    return mem, best, t, best_step
+
+
+def test_peel_app_fig6_trace(fixtures):
+    # Figure 6 graph, Psi an edge.  Every minimum-degree vertex leaving at once:
+    # residual densities 26/14, 25/12 (after H', H'' = the pendant edge),
+    # 19/10, 13/8, 10/5 (the K5) -- the best is the 3-core with 25/12, which
+    # Example 5 gives as rho'.  One vertex per step reaches the same set two
+    # steps in (both pendant vertices leave first).
+    f = fixtures["F4"]
+    g = G(f["n"], f["edges"])
+    mem, rho, steps, best = g.peel_app(2, rounds=True)
+    assert (rho, steps, best) == (Fraction(25, 12), 5, 1)
+    assert members(mem) == list(range(12))
+    assert rho == Fraction(*f["expect"]["rho1"])
+    mem, rho, steps, best = g.peel_app(2, rounds=False)
+    assert (rho, steps, best) == (Fraction(25, 12), 14, 2)
+    assert members(mem) == list(range(12))
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("h", [2, 3, 4])
+@pytest.mark.parametrize("rounds", [True, False])
+def test_peel_app_matches_replay(seed, h, rounds):
+    n = 11
+    edges = brute.random_graph(n, 0.55, 900 + seed)
+    g = G(n, edges)
+    mem, rho, steps, best = g.peel_app(h, rounds=rounds)
+    emem, erho, esteps, ebest = _peel_replay(n, edges, h, rounds)
+    assert (rho, steps, best) == (erho, esteps, ebest)
+    assert members(mem) == emem
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_peel_app_bounds(seed, h):
+    # Lemma 10: h * rho(S*) >= rho_opt.  Every (k, Psi)-core is one of the
+    # residual graphs (a vertex of R_k never has the minimum degree while a
+    # vertex outside R_k is left), so rho(S*) >= rho' as well.
+    n = 13
+    edges = brute.random_graph(n, 0.45, 500 + seed)
+    g = G(n, edges)
+    opt, _ = brute.densest(n, edges, h)
+    core, _ = g.core_decomposition(h)
+    lv, rs, rm = g.level_table(h, core)
+    rho1 = max([Fraction(int(m), int(s)) for m, s in zip(rm, rs) if s] + [Fraction(0)])
+    for rounds in (True, False):
+        mem, rho, _, best = g.peel_app(h, rounds=rounds)
+        assert rho <= opt and h * rho >= opt and rho >= rho1
+        if rho > 0:
+            _, mu = brute.clique_degrees(n, edges, h, members(mem))
+            assert Fraction(mu, len(members(mem))) == rho
+
+
+@pytest.mark.parametrize("n", [3, 6, 10])
+@pytest.mark.parametrize("h", [2, 3, 5])
+def test_peel_app_complete_graph(n, h):
+    g = G(n, list(itertools.combinations(range(n), 2)))
+    for rounds, esteps in ((True, 1), (False, n)):
+        mem, rho, steps, best = g.peel_app(h, rounds=rounds)
+        if n < h:
+            assert rho == 0 and best == -1 and not mem.any()
+        else:
+            assert rho == Fraction(math.comb(n, h), n) and best == 0 and mem.all()
+        assert steps == esteps
+
+
+def test_peel_app_without_cliques():
+    # a path holds no triangle: no residual graph has positive density
+    g = G(6, [(i, i + 1) for i in range(5)])
+    mem, rho, steps, best = g.peel_app(3)
+    assert rho == 0 and best == -1 and not mem.any() and steps == 1
+    g = oracle.Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert g.peel_app(2)[1:] == (Fraction(0), 0, -1)
