@@ -132,6 +132,26 @@ dsd_status dsd_core_app(dsd_graph g, int h, int out_mem, uint8_t *member, uint64
                         dsd_rational *density);
 
 /*
+ * PeelApp (Algorithm 2): the densest residual graph of a peel by
+ * clique-degree, a 1/h-approximation of the densest subgraph (Lemma 10).  A
+ * round removes every vertex whose clique-degree in the residual graph S is
+ * the smallest in S, with every h-clique through them (the 1/h argument
+ * holds unchanged: the round that takes the first vertex of a densest
+ * subgraph starts from an S whose minimum degree is at least rho_opt).  The
+ * residual graph before every round, G itself included, is a candidate; of
+ * equally dense ones the first (largest) is kept.
+ *   member:     length n bytes, residency out_mem: 1 for the vertices of the
+ *               answer (none when G holds no h-clique).
+ *   density:    mu(S)/|S| of the answer, reduced; 0/1 when G has no h-clique.
+ *   rounds:     rounds until S is empty.
+ *   best_round: the round before which the answer was the residual graph
+ *               (-1 when G has no h-clique).
+ * density, rounds and best_round may be NULL.
+ */
+dsd_status dsd_peel_app(dsd_graph g, int h, int out_mem, uint8_t *member, dsd_rational *density,
+                        int64_t *rounds, int64_t *best_round);
+
+/*
  * CoreExact (Algorithm 4): the clique-densest subgraph (Problem 1).  The GPU
  * decomposes the graph, locates the densest subgraph with Pruning1 and
  * Pruning2 and labels the components of the located core; the binary search

@@ -457,6 +457,48 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
     return kmax;
 }
 
+// PeelApp (Algorithm 2) on a handle, every minimum-degree vertex per round:
+// the peel's min-degree mode records |S| and mu(S) before every round and
+// each vertex's removal round; the answer is the first densest of those
+// residual graphs, i.e. the vertices removed in its round or later.
+dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds, int64_t *best_round) {
+    const int32_t n = G->g.n;
+    hipStream_t s = G->stream;
+    fill_u8(best, 0, n, s);
+    *rounds = 0;
+    *best_round = -1;
+    if (n == 0) return dsd_rational{0, 1};
+    KernelTimes kt;
+    Timer te(s);
+    u64 *d = G->sc.get_n<u64>(n);
+    const u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);
+    G->stats.t_enum_ms = te.stop();
+    G->stats.num_cliques = mu;
+    if (mu == 0) {                 // every vertex is at the minimum, 0: one round empties S
+        end_stats(G, kt);
+        *rounds = 1;
+        return dsd_rational{0, 1};
+    }
+    u64 *round = G->sc.get_n<u64>(n);
+    Timer tp(s);
+    PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, round, s, G->sc, &kt, nullptr, true);
+    G->stats.t_peel_ms = tp.stop();
+    G->stats.peel_rounds = pr.rounds;
+    G->stats.peel_levels = pr.levels;
+    end_stats(G, kt);
+    u64 a = 0, b = 1;
+    for (int64_t j = 0; j < (int64_t)pr.level_size.size(); j++)
+        if (pr.level_size[j] > 0 && rat_gt(pr.level_mu[j], pr.level_size[j], a, b)) {
+            a = pr.level_mu[j];
+            b = pr.level_size[j];
+            *best_round = j;
+        }
+    *rounds = pr.rounds;
+    if (*best_round < 0) return dsd_rational{0, 1};
+    mask_core_at_least(round, n, (u64)*best_round, best, s);
+    return make_rational(a, b);
+}
+
 }  // namespace dsd
 
 extern "C" {
@@ -475,6 +517,28 @@ dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64
         const u64 kmax = core_app_run(G, h, best, density);
         write_u8(G, best, member, out_mem);
         if (kmax_out) *kmax_out = kmax;
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_peel_app(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_rational *density, int64_t *rounds,
+                        int64_t *best_round) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    DSD_TRY({
+        check_h(h);
+        const int32_t n = G->g.n;
+        if (n > 0) check_out(member, out_mem);
+        G->sc.reset();
+        begin_stats(G);
+        Timer tm(G->stream);
+        uint8_t *best = G->sc.get_n<uint8_t>(n);
+        int64_t r = 0, br = -1;
+        const dsd_rational rho = peel_app_run(G, h, best, &r, &br);
+        write_u8(G, best, member, out_mem);
+        if (density) *density = rho;
+        if (rounds) *rounds = r;
+        if (best_round) *best_round = br;
         G->stats.t_total_ms = tm.stop();
         return DSD_OK;
     })

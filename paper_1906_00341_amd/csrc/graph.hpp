@@ -77,8 +77,14 @@ struct PeelResult {
 // (single graph; grp->mu for a batch).  k_floor: every vertex of degree <=
 // k_floor goes in the first level (CoreApp starts its peel there); 0 for a
 // full decomposition.  core: rank space.
+// min_degree: PeelApp's order instead (Algorithm 2, all minimum-degree
+// vertices of a graph per round; k_floor must be 0): core[] receives the
+// round that removed each vertex, and the level table one entry per round of
+// each graph: the smallest degree, |S| and mu(S) of the residual graph S
+// before that round (entry j of a graph is round j).
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr, const PeelGroups *grp = nullptr);
+                hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr, const PeelGroups *grp = nullptr,
+                bool min_degree = false);
 
 // ---- K5: connected components of the subgraph induced by mask ----
 // label[r] = smallest rank of r's component for r in mask, -1 outside.

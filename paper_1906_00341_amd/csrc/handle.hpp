@@ -94,6 +94,10 @@ void write_u8(dsd_graph_s *G, const uint8_t *rank_space, uint8_t *out, int mem);
 // CoreApp (Algorithm 6) on a handle: best (device, rank space, length n)
 // receives the (k_max, Psi)-core; returns k_max, *density its density
 u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density);
+// PeelApp (Algorithm 2, all minimum-degree vertices per round) on a handle:
+// best (device, rank space, length n) receives the densest residual graph;
+// returns its density; *rounds / *best_round as dsd_peel_app reports them
+dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds, int64_t *best_round);
 // CoreExact on a handle: res (device, rank space, length n) receives the
 // members of one densest subgraph; returns rho_opt
 dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res);

@@ -10,6 +10,12 @@
 // When no frontier is left, k jumps to the smallest alive degree (a new
 // level; no level in between can remove anything).
 //
+// In the min-degree mode (PeelApp, Algorithm 2) every round is a level of
+// its own: the frontier is the alive vertices at the graph's smallest
+// clique-degree, survivors only lose degree (they never join the next
+// frontier), core[] receives each vertex's removal round, and the level
+// table holds |S| and mu(S) of the residual graph before every round.
+//
 // A batch of graphs is peeled as one disjoint union in which every graph
 // keeps its own level k (GraphState): cliques never cross graphs, so each
 // graph's peel is exactly its own, and one round advances all of them.
@@ -86,6 +92,7 @@ struct PeelBufs {
     int32_t n;
     int32_t h;
     int32_t count_work;  // the main kernel adds up its pairs and neighbours
+    int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
@@ -102,6 +109,7 @@ __device__ __forceinline__ int32_t graph_of(const PeelBufs &b, int32_t v) { retu
 __device__ __forceinline__ u64 level_of(const PeelBufs &b, int32_t g) {
     const GraphState &s = b.gs[g];
     if (!s.sel) return s.k;
+    if (b.minpeel) return s.kcand;
     return s.k > s.kcand ? s.k : s.kcand;
 }
 
@@ -181,6 +189,10 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
 // a survivor x loses c cliques; if that takes it to the level of its graph it
 // joins the next frontier with that core number
 __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int32_t r) {
+    if (b.minpeel) {                      // the next round takes the new minimum itself
+        atomic_sub_u64(&b.deg[x], c);
+        return;
+    }
     const int32_t g = graph_of(b, x);
     const u64 k = level_of(b, g);
     u64 old = atomic_sub_u64(&b.deg[x], c);
@@ -310,7 +322,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
                     take = b.deg[v] <= k;
                     if (take) {
                         b.stamp[v] = r;
-                        b.core[v] = k;
+                        b.core[v] = b.minpeel ? (u64)r : k;
                         push_chunks(b, v, cur);
                     }
                 }
@@ -956,7 +968,7 @@ static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t 
 }
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp) {
+                hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp, bool min_degree) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
@@ -970,6 +982,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.col = g.col;
     b.dag_off = g.dag_off;
     b.count_work = kt != nullptr && h <= 3;
+    b.minpeel = min_degree ? 1 : 0;
     b.ctl = sc.get_n<PeelCtl>(1);
     b.gs = sc.get_n<GraphState>(G);
     b.stamp = sc.get_n<int32_t>(n);

@@ -31,7 +31,7 @@ OP_DEGREES, OP_CORE, OP_APP, OP_EXACT = 0, 1, 2, 3
 OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT}
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
-           "dsd_clique_core", "dsd_core_app", "dsd_core_exact", "dsd_last_stats",
+           "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_last_stats",
            "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
            "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
 
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.dsd_clique_degrees.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_clique_core.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
+    lib.dsd_peel_app.argtypes = [P, I, I, P, C.POINTER(Rational), C.POINTER(I64), C.POINTER(I64)]
     lib.dsd_core_exact.argtypes = [P, I, I, P, C.POINTER(Rational)]
     lib.dsd_last_stats.argtypes = [P, C.POINTER(Stats)]
     lib.dsd_batch_run.argtypes = [I32, C.POINTER(P), C.POINTER(I), I, I, C.POINTER(P), C.POINTER(Result)]
@@ -228,6 +229,15 @@ def core_app(g: Graph, h: int, out=None):
     km, r = C.c_uint64(), Rational()
     _check(_lib.dsd_core_app(g.handle, int(h), mem, p, C.byref(km), C.byref(r)))
     return (out[:n] if isinstance(out, np.ndarray) else out), int(km.value), Fraction(r.num, r.den)
+
+
+def peel_app(g: Graph, h: int, out=None):
+    """dsd_peel_app -> (member[n] uint8, density Fraction, rounds, best_round)."""
+    out, p, mem, n = _out_u8(g, out)
+    r, rounds, best = Rational(), C.c_int64(), C.c_int64()
+    _check(_lib.dsd_peel_app(g.handle, int(h), mem, p, C.byref(r), C.byref(rounds), C.byref(best)))
+    return ((out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den),
+            int(rounds.value), int(best.value))
 
 
 def core_exact(g: Graph, h: int, out=None):

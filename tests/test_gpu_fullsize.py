@@ -7,7 +7,11 @@ graph.  The oracle's exact step (Dinic on 128-bit capacities) would take many
 minutes here, so CoreExact's answer is checked by properties that hold for
 every densest subgraph: its density is the returned rho_opt (counted by the
 oracle), it lies in the ceil(rho_opt)-core (Lemma 7), and rho_opt lies between
-the density of the k_max-core and k_max (Lemma 8 and Theorem 1).
+the density of the k_max-core and k_max (Lemma 8 and Theorem 1).  PeelApp (every
+minimum-degree vertex per round) is compared with the oracle exactly: member
+set, density, rounds and the round of the answer; its density is also at least
+rho' (every level set R_k is one of its residual graphs) and within Lemma 10's
+factor h of rho_opt.
 """
 from __future__ import annotations
 
@@ -44,7 +48,9 @@ def test_chung_lu_1e6_triangles_whole_graph():
     core_g, km_g = dsd.clique_core(g, h)
     mem_app, km_app, dens_app = dsd.core_app(g, h)
     mem_x, rho = dsd.core_exact(g, h)
-    print(f"gpu: mu={mu_g} kmax={km_g} rho_app={dens_app} rho_opt={rho}", flush=True)
+    mem_p, rho_p, rounds_p, best_p = dsd.peel_app(g, h)
+    print(f"gpu: mu={mu_g} kmax={km_g} rho_app={dens_app} rho_opt={rho} "
+          f"peel_app={rho_p} rounds={rounds_p} best_round={best_p}", flush=True)
 
     og = oracle.Graph(n, s, d)
     deg_o, mu_o = og.clique_degrees(h)
@@ -64,3 +70,10 @@ def test_chung_lu_1e6_triangles_whole_graph():
     assert Fraction(induced_mu(og, h, sel), int(sel.sum())) == rho
     assert (core_o[sel] >= math.ceil(rho)).all()
     assert dens_app <= rho <= km_o
+
+    mem_po, rho_po, steps_po, best_po = og.peel_app(h, rounds=True)
+    assert (rho_p, rounds_p, best_p) == (rho_po, steps_po, best_po)
+    np.testing.assert_array_equal(mem_p.astype(bool), mem_po)
+    lv, rs, rm = og.level_table(h, core_o)
+    rho1 = max(Fraction(int(m), int(z)) for m, z in zip(rm, rs) if z)
+    assert rho1 <= rho_p <= rho <= h * rho_p
