@@ -173,7 +173,8 @@ typedef enum {
     DSD_OP_DEGREES = 0,   /* dsd_clique_degrees */
     DSD_OP_CORE = 1,      /* dsd_clique_core */
     DSD_OP_APP = 2,       /* dsd_core_app */
-    DSD_OP_EXACT = 3      /* dsd_core_exact */
+    DSD_OP_EXACT = 3,     /* dsd_core_exact */
+    DSD_OP_PEEL = 4       /* dsd_peel_app */
 } dsd_op;
 
 /* Scalar outcome for one graph of a batch or one served request. */
@@ -184,9 +185,11 @@ typedef struct {
                                 2^20 edges or more, where CoreApp runs alone (Algorithm 6
                                 never counts the whole graph) */
     uint64_t kmax;           /* CORE, APP, EXACT: the largest clique-core number */
-    dsd_rational density;    /* APP: density of the (k_max, Psi)-core; EXACT: rho_opt */
-    uint64_t members;        /* APP, EXACT: size of the member set */
-    uint64_t peel_rounds;    /* rounds of the peel this graph took part in */
+    dsd_rational density;    /* APP: density of the (k_max, Psi)-core; EXACT: rho_opt;
+                                PEEL: density of the densest residual graph */
+    uint64_t members;        /* APP, EXACT, PEEL: size of the member set */
+    uint64_t peel_rounds;    /* rounds of the peel this graph took part in (PEEL: the
+                                graph's own rounds, as dsd_peel_app reports them) */
     double t_ms;             /* wall time of the batch group that computed it */
 } dsd_result;
 
@@ -198,14 +201,16 @@ typedef struct {
  * instead of their sum.  Every graph's decomposition is kept on its handle,
  * as a single-graph call would keep it.  DSD_OP_APP on a graph of 2^20
  * edges or more runs CoreApp's own top-down search (Algorithm 6) alone
- * instead, as dsd_core_app does.  DSD_OP_EXACT then runs the locate
+ * instead, as dsd_core_app does.  DSD_OP_PEEL peels the union in
+ * PeelApp's order (each graph removes its own minimum-degree vertices every
+ * round) and keeps no decomposition.  DSD_OP_EXACT then runs the locate
  * steps and the host exact search of Algorithm 4 graph by graph, on up to 16
  * host threads.
  *   graphs: count distinct handles (a handle twice -> DSD_EINVAL).
  *   h:      count values in [2, 6].
  *   outs:   NULL, or count pointers, each NULL or an array of n_i entries:
  *           uint64_t for DEGREES (clique-degrees) and CORE (core numbers),
- *           uint8_t member flags for APP and EXACT; residency out_mem.
+ *           uint8_t member flags for APP, EXACT and PEEL; residency out_mem.
  *   results: count entries, written for every graph.
  * Argument errors (DSD_EINVAL) are reported before any work.  Otherwise the
  * call returns DSD_OK when every graph succeeded, else the status of the

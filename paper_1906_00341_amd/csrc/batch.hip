@@ -103,6 +103,15 @@ __global__ void k_member_kmax(const u64 *core, const int32_t *gid, const u64 *km
     }
 }
 
+// member flags of every graph's densest residual graph in PeelApp's order:
+// the vertices removed in its best round or later (none when best < 0)
+__global__ void k_member_round(const u64 *round, const int32_t *gid, const int64_t *best, int64_t N, uint8_t *mem) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < N; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = best[gid[v]];
+        mem[v] = (b >= 0 && round[v] >= (u64)b) ? 1 : 0;
+    }
+}
+
 int bits_for_n(int64_t n) {
     int b = 1;
     while (((int64_t)1 << b) <= n) b++;
@@ -207,6 +216,46 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
 
     if (op == DSD_OP_DEGREES) {
         deliver(deg, sizeof(u64), gather64);
+    } else if (op == DSD_OP_PEEL) {
+        // PeelApp's order: every graph's level table holds |S| and mu(S) before each of its rounds
+        u64 *round = sc.get_n<u64>(N);
+        PeelGroups grp;
+        grp.G = G;
+        grp.gid = gid;
+        grp.mu = mu;
+        grp.lv_base = d_lvb;
+        grp.lv_total = N + G;
+        PeelResult pr;
+        {
+            Timer tp(s);
+            if (N > 0) pr = peel(U, h, nullptr, deg, 0, 0, round, s, sc, &kt, &grp, true);
+            t_peel = tp.stop();
+        }
+        std::vector<int64_t> best(G, -1);
+        for (int32_t j = 0; j < G; j++) {
+            const int32_t L = N > 0 ? pr.graph_levels[j] : 0;
+            u64 a = 0, b = 1;
+            for (int32_t i = 0; i < L; i++) {
+                const u64 sz = pr.level_size[lvb[j] + i], m = pr.level_mu[lvb[j] + i];
+                if (sz > 0 && rat_gt(m, sz, a, b)) {
+                    a = m;
+                    b = sz;
+                    best[j] = i;
+                }
+            }
+            dsd_result &r = results[idx[j]];
+            r.peel_rounds = (uint64_t)L;
+            if (best[j] >= 0) {
+                r.density = make_rational(a, b);
+                r.members = b;
+            }
+        }
+        int64_t *dbest = sc.get_n<int64_t>(G);
+        DSD_HIP(hipMemcpyAsync(dbest, best.data(), G * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        uint8_t *mem = sc.get_n<uint8_t>(N);
+        if (N > 0) k_member_round<<<grid_for(N, BLOCK, 8192), BLOCK, 0, s>>>(round, gid, dbest, N, mem);
+        deliver(mem, 1, gather8);
+        DSD_HIP(hipStreamSynchronize(s));
     } else {
         // the peel: every graph keeps its own level
         u64 *core = sc.get_n<u64>(N);
@@ -325,7 +374,7 @@ extern "C" dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, cons
     if (count < 0) return fail(DSD_EINVAL, "negative batch size");
     if (count == 0) return DSD_OK;
     if (!graphs || !h || !results) return fail(DSD_EINVAL, "NULL batch array");
-    if (op < DSD_OP_DEGREES || op > DSD_OP_EXACT) return fail(DSD_EINVAL, "unknown batch operation");
+    if (op < DSD_OP_DEGREES || op > DSD_OP_PEEL) return fail(DSD_EINVAL, "unknown batch operation");
     if (outs && out_mem != DSD_MEM_HOST && out_mem != DSD_MEM_DEVICE) return fail(DSD_EINVAL, "bad memory flag");
     std::vector<dsd_graph> sorted(graphs, graphs + count);
     for (int32_t i = 0; i < count; i++) {

@@ -162,7 +162,7 @@ dsd_status dsd_server_create(size_t hbm_budget_bytes, int max_slots, dsd_server 
 dsd_status dsd_server_submit(dsd_server s, dsd_graph g, int h, int op, int out_mem, void *out, uint64_t *ticket) {
     if (!s || !g || !ticket) return fail(DSD_EINVAL, "NULL argument");
     if (h < 2 || h > 6) return fail(DSD_EINVAL, "h must be in [2, 6]");
-    if (op < DSD_OP_DEGREES || op > DSD_OP_EXACT) return fail(DSD_EINVAL, "unknown operation");
+    if (op < DSD_OP_DEGREES || op > DSD_OP_PEEL) return fail(DSD_EINVAL, "unknown operation");
     if (out && out_mem != DSD_MEM_HOST && out_mem != DSD_MEM_DEVICE) return fail(DSD_EINVAL, "bad memory flag");
     const size_t foot = BYTES_PER_VERTEX * (size_t)g->g.n + BYTES_PER_EDGE * (size_t)g->g.m;
     std::lock_guard<std::mutex> lk(s->mu);

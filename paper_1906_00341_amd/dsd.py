@@ -27,8 +27,8 @@ STATUS = {0: "DSD_OK", -1: "DSD_EINVAL", -2: "DSD_ENOMEM", -3: "DSD_EDEVICE",
           -8: "DSD_ECANCELED"}
 DSD_EBUSY, DSD_ETIMEDOUT, DSD_ECANCELED = -6, -7, -8
 
-OP_DEGREES, OP_CORE, OP_APP, OP_EXACT = 0, 1, 2, 3
-OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT}
+OP_DEGREES, OP_CORE, OP_APP, OP_EXACT, OP_PEEL = 0, 1, 2, 3, 4
+OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT, "peel": OP_PEEL}
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_last_stats",
@@ -259,7 +259,7 @@ def _op(op) -> int:
 def batch_run(graphs, hs, op, outs=None, out_mem=None):
     """dsd_batch_run -> list of result dicts (one per graph, each with its own
     ``status``).  outs: None or a list (entries None, numpy arrays or torch
-    tensors of n_i entries: uint64 for degrees/core, uint8 for app/exact; all
+    tensors of n_i entries: uint64 for degrees/core, uint8 for app/exact/peel; all
     in the same memory).  Raises DsdError for argument errors."""
     lib = load()
     cnt = len(graphs)

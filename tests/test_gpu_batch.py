@@ -126,6 +126,21 @@ def test_batch_app_and_exact_match_oracle(h):
         assert r["members"] == int(np.count_nonzero(out[:n]))
 
 
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_batch_peel_app_matches_oracle(h):
+    # every graph of the union removes its own minimum-degree vertices each
+    # round; its answer, member set and round count are those of a graph alone
+    graphs = mixed_graphs(5, count=24)
+    handles = build_all(graphs)
+    mems = [np.full(max(n, 1), 9, np.uint8) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, h, "peel", outs=mems)
+    for (n, s, d), r, out in zip(graphs, res, mems):
+        mem_o, rho_o, steps_o, _ = oracle.Graph(n, s, d).peel_app(h, rounds=True)
+        assert r["status"] == 0 and r["density"] == rho_o and r["peel_rounds"] == steps_o
+        np.testing.assert_array_equal(out[:n].astype(bool), mem_o)
+        assert r["members"] == int(np.count_nonzero(mem_o))
+
+
 def test_batch_device_outputs_and_cached_decomposition():
     torch = pytest.importorskip("torch")
     graphs = mixed_graphs(5, count=10)
@@ -177,11 +192,11 @@ def test_server_results_match_single_calls():
     graphs = mixed_graphs(7, count=16)
     handles = build_all(graphs)
     srv = dsd.Server(1 << 34, 64)
-    ops = ["degrees", "core", "app", "exact"]
+    ops = ["degrees", "core", "app", "exact", "peel"]
     tickets, outs = [], []
     for i, g in enumerate(handles):
         n = graphs[i][0]
-        op = ops[i % 4]
+        op = ops[i % len(ops)]
         out = np.zeros(max(n, 1), np.uint64 if op in ("degrees", "core") else np.uint8)
         outs.append(out)
         tickets.append(srv.submit(g, 3, op, out))
@@ -190,13 +205,17 @@ def test_server_results_match_single_calls():
         assert st == 0 and r["status"] == 0
         n, s, d = graphs[i]
         og = oracle.Graph(n, s, d)
-        op = ops[i % 4]
+        op = ops[i % len(ops)]
         if op == "degrees":
             np.testing.assert_array_equal(outs[i][:n], og.clique_degrees(3)[0])
         elif op == "core":
             np.testing.assert_array_equal(outs[i][:n], og.core_decomposition(3)[0])
         elif op == "app":
             np.testing.assert_array_equal(outs[i][:n].astype(bool), og.inc_app(3)[0])
+        elif op == "peel":
+            mem_o, rho_o, _, _ = og.peel_app(3)
+            assert r["density"] == rho_o
+            np.testing.assert_array_equal(outs[i][:n].astype(bool), mem_o)
         else:
             assert r["density"] == og.exact(3, "core")[1]
     with pytest.raises(dsd.DsdError):          # a completed ticket is released by its wait
