@@ -60,19 +60,26 @@ def k4_bytes(st: dict, h: int) -> float:
     return 4.0 * st["s2"] + 24.0 * st["m"]
 
 
-MAIN_KERNEL = {2: "k_process_h2", 3: "k_h3_probe"}
+# the peel's main kernel by the kind the library reports
+MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process"}
 
 
-def main_kernel_bytes(st: dict, h: int) -> float:
+def main_kernel_bytes(st: dict) -> float:
     """Algorithmic bytes of the peel's main kernel over one peel, from the
-    work it counted.  h = 3 (triangle probe): every probed out-list entry
-    costs 4 B, every expanded neighbour w its column entry and the two row
-    offsets of N+(w) (4 + 8 + 8 B).  h = 2 (edge pass): every walked
+    work it counted.  Triangle lists (k_tl_process): every walked entry b
+    costs itself and b's stamp (4 + 4 B), every examined arc (v, a) its
+    column entry, a's stamp and the two list offsets (4 + 4 + 16 B).
+    Triangle probe (k_h3_probe): every probed out-list entry costs 4 B,
+    every expanded neighbour w its column entry and the two row offsets of
+    N+(w) (4 + 8 + 8 B).  Edge pass (k_process_h2, h = 2): every walked
     adjacency entry costs its column entry, the neighbour's stamp and an
     8-byte read-modify-write of its degree (4 + 4 + 16 B), every frontier
     vertex its two row offsets (16 B)."""
-    if h == 2:
+    kind = st["k4_main_kind"]
+    if kind == 1:
         return 24.0 * st["k4_main_pairs"] + 16.0 * st["k4_main_nbrs"]
+    if kind == 3:
+        return 8.0 * st["k4_main_pairs"] + 24.0 * st["k4_main_nbrs"]
     return 4.0 * st["k4_main_pairs"] + 20.0 * st["k4_main_nbrs"]
 
 
@@ -316,7 +323,7 @@ def main() -> int:
     # roofline of the peel's main kernel, every launch timed with HIP events on its stream
     main_ms = avg("k4_main_ms", "core")
     launches = max(core["k4_main_launches"], 1)
-    bytes_call = main_kernel_bytes(core, h) / launches
+    bytes_call = main_kernel_bytes(core) / launches
     ms_call = main_ms / launches
     achieved = bytes_call / (ms_call / 1e3) / 1e9 if ms_call > 0 else 0.0
     out = {
@@ -351,9 +358,9 @@ def main() -> int:
             "enum_hbm_frac": k3_bytes(core) / (k3_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k3_ms else None,
             "peel_hbm_frac": k4_bytes(core, h) / (k4_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k4_ms else None,
         },
-        "roofline": {"kernel": MAIN_KERNEL.get(h), "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": MAIN_KERNEL.get(core["k4_main_kind"]), "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(MAIN_KERNEL.get(h), args.workload),
+                     "traffic": measured_traffic(MAIN_KERNEL.get(core["k4_main_kind"]), args.workload),
                      "bytes_per_launch": bytes_call, "ms_per_launch": ms_call, "launches_per_step": launches,
                      "pairs_per_step": core["k4_main_pairs"], "nbrs_per_step": core["k4_main_nbrs"]},
     }

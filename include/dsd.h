@@ -76,16 +76,19 @@ typedef struct {
     uint64_t n, m, w2, s2;
     /* host exact step: network construction and maximum-flow time */
     double t_flow_build_ms, t_flow_ms;
-    /* the peel's main kernel (h = 3: the triangle probe; h = 2: the edge
-     * pass), every launch timed on its own with HIP events: total time,
-     * launches, out-list entries probed (h = 3) or adjacency entries walked
-     * (h = 2), and neighbours expanded (h = 3) or frontier vertices (h = 2);
-     * zero for h >= 4 */
+    /* the peel's main kernel, every launch timed on its own with HIP events:
+     * total time, launches and the work it counted (pairs, nbrs); which
+     * kernel it was is k4_main_kind:
+     *   1  h = 2 edge pass: adjacency entries walked, frontier vertices;
+     *   2  h = 3 triangle probe: out-list entries probed, neighbours expanded;
+     *   3  h = 3 triangle lists: list entries walked, arcs examined;
+     *   0  none timed (h >= 4) */
     double k4_main_ms;
     uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
     /* minimum cuts of the exact step computed on the GPU (the others ran on
      * the host) */
     uint64_t flow_gpu_calls;
+    uint64_t k4_main_kind;
 } dsd_stats;
 
 /*

@@ -75,6 +75,7 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k4_main_pairs = kt.main_pairs;
     G->stats.k4_main_nbrs = kt.main_nbrs;
     G->stats.k4_launches = kt.k4_launches;
+    G->stats.k4_main_kind = (uint64_t)kt.main_kind;
 }
 
 // clique-degrees (rank space) and mu; throws on overflow
@@ -92,6 +93,21 @@ u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelT
     return hs[0] / (u64)h;
 }
 
+const TriList *tri_lists(dsd_graph_s *G, const u64 *deg, u64 mu) {
+    if (!G->tl.pairs && !G->tl_tried) {
+        G->tl_tried = true;
+        if (tri_list_wanted(G->g, mu)) {
+            try {
+                build_tri_list(G->g, deg, mu, G->tl, G->stream, G->sc);
+            } catch (const Error &e) {
+                if (e.status != DSD_ENOMEM) throw;     // no room: the peel intersects neighbourhoods instead
+            }
+        }
+    }
+    if (!G->tl.pairs || G->tl.mu != mu) return nullptr;
+    return &G->tl;
+}
+
 // The decomposition for h, computed once per handle (Algorithm 3 via the
 // round-synchronous peel).
 const Decomp &decompose(dsd_graph_s *G, int h) {
@@ -107,11 +123,12 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
     Timer te(s);
     u64 *d = G->sc.get_n<u64>(n);
     D.mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &D.kt) : 0;
+    const TriList *tl = h == 3 && D.mu > 0 ? tri_lists(G, d, D.mu) : nullptr;
     D.t_enum_ms = te.stop();
     Timer tp(s);
     D.levels = PeelResult();
     if (n > 0) {
-        if (D.mu > 0) D.levels = peel(G->g, h, nullptr, d, D.mu, 0, D.core, s, G->sc, &D.kt);
+        if (D.mu > 0) D.levels = peel(G->g, h, nullptr, d, D.mu, 0, D.core, s, G->sc, &D.kt, nullptr, false, tl);
         else fill_u64(D.core, 0, n, s);
     }
     D.t_peel_ms = tp.stop();
@@ -429,6 +446,8 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
         while (true) {
             mask_from_order_prefix(keys, n, w, G->g.bits, inW, s);
             Timer te(s);
+            // (no triangle lists here: their rows hold every triangle of the whole graph, and a
+            // hub's row in G[W] is mostly triangles that leave W)
             u64 muW = degrees_and_mu(G, h, inW, d);
             G->stats.t_enum_ms += te.stop();
             masked_min_u64(d, inW, n, mn, s);
@@ -472,6 +491,7 @@ dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds,
     Timer te(s);
     u64 *d = G->sc.get_n<u64>(n);
     const u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);
+    const TriList *tl = h == 3 && mu > 0 ? tri_lists(G, d, mu) : nullptr;
     G->stats.t_enum_ms = te.stop();
     G->stats.num_cliques = mu;
     if (mu == 0) {                 // every vertex is at the minimum, 0: one round empties S
@@ -481,7 +501,7 @@ dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds,
     }
     u64 *round = G->sc.get_n<u64>(n);
     Timer tp(s);
-    PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, round, s, G->sc, &kt, nullptr, true);
+    PeelResult pr = peel(G->g, h, nullptr, d, mu, 0, round, s, G->sc, &kt, nullptr, true, tl);
     G->stats.t_peel_ms = tp.stop();
     G->stats.peel_rounds = pr.rounds;
     G->stats.peel_levels = pr.levels;

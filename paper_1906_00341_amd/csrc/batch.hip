@@ -178,9 +178,27 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
     std::vector<u64> hmu(G);
     DSD_HIP(hipMemcpyAsync(hmu.data(), mu, G * sizeof(u64), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
+    u64 mu_all = 0;
     for (int32_t j = 0; j < G; j++) {
         dsd_result &r = results[idx[j]];
         r.num_cliques = hmu[j];
+        mu_all += hmu[j];
+    }
+    // h = 3: the union's triangle lists for the peel, freed with the group
+    struct ListHolder {
+        TriList tl;
+        ~ListHolder() { free_tri_list(tl); }
+    } lists;
+    const TriList *tl = nullptr;
+    if (h == 3 && op != DSD_OP_DEGREES && N > 0 && tri_list_wanted(U, mu_all)) {
+        try {
+            Timer tb(s);
+            build_tri_list(U, deg, mu_all, lists.tl, s, sc);
+            t_enum += tb.stop();
+            tl = &lists.tl;
+        } catch (const Error &e) {
+            if (e.status != DSD_ENOMEM) throw;   // no room: the peel intersects neighbourhoods instead
+        }
     }
 
     // host staging for host outputs: one copy for the whole group
@@ -228,7 +246,7 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
         PeelResult pr;
         {
             Timer tp(s);
-            if (N > 0) pr = peel(U, h, nullptr, deg, 0, 0, round, s, sc, &kt, &grp, true);
+            if (N > 0) pr = peel(U, h, nullptr, deg, 0, 0, round, s, sc, &kt, &grp, true, tl);
             t_peel = tp.stop();
         }
         std::vector<int64_t> best(G, -1);
@@ -268,7 +286,7 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
         PeelResult pr;
         {
             Timer tp(s);
-            if (N > 0) pr = peel(U, h, nullptr, deg, 0, 0, core, s, sc, &kt, &grp);
+            if (N > 0) pr = peel(U, h, nullptr, deg, 0, 0, core, s, sc, &kt, &grp, false, tl);
             t_peel = tp.stop();
         }
         // keep every graph's decomposition on its handle

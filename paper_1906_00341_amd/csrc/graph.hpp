@@ -37,6 +37,7 @@ struct KernelTimes {
     // (h = 3) or frontier vertices (h = 2)
     double main_ms = 0;
     u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
+    int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----
@@ -52,6 +53,24 @@ void free_graph(DevGraph &g);
 // overwritten.  Returns false if the counts could overflow 64 bits.
 bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
                     KernelTimes *kt = nullptr);
+
+// ---- triangle lists (h = 3) ----
+// Row v is pairs[2 voff[v] .. 2 voff[v+1]): a pair (a, b) for every triangle
+// {v, a, b}, twice (as (a, b) and (b, a)), grouped by a: 6 mu pairs in all.
+struct TriList {
+    int64_t *voff = nullptr;   // [n + 1]
+    int32_t *pairs = nullptr;  // [2 * entries]
+    int64_t entries = 0;
+    u64 mu = 0;
+};
+// whether the lists of a graph with mu triangles fit (positions in int32,
+// out-degree within the listing kernels, at most a quarter of free device
+// memory); the environment variable DSD_TRI_LIST=0 turns them off
+bool tri_list_wanted(const DevGraph &g, u64 mu);
+// list every triangle of the graph (mu of them); deg is unused.  Allocates
+// tl's arrays (released by free_tri_list).
+void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc);
+void free_tri_list(TriList &tl);
 
 // ---- K4: round-synchronous peel ----
 // A batch of graphs is peeled as one disjoint union in which every graph
@@ -82,9 +101,11 @@ struct PeelResult {
 // round that removed each vertex, and the level table one entry per round of
 // each graph: the smallest degree, |S| and mu(S) of the residual graph S
 // before that round (entry j of a graph is round j).
+// tl (h = 3, nullable): the graph's triangle lists; the rounds then walk the
+// removed vertices' rows of triangles instead of intersecting neighbourhoods.
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
                 hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr, const PeelGroups *grp = nullptr,
-                bool min_degree = false);
+                bool min_degree = false, const TriList *tl = nullptr);
 
 // ---- K5: connected components of the subgraph induced by mask ----
 // label[r] = smallest rank of r's component for r in mask, -1 outside.

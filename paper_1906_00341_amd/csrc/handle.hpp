@@ -31,8 +31,11 @@ struct dsd_graph_s {
     dsd::Scratch sc;
     dsd_stats stats{};
     dsd::Decomp dec[7];             // by h
+    dsd::TriList tl;                // triangle lists, built by the first h = 3 decomposition that wants them
+    bool tl_tried = false;
     ~dsd_graph_s() {
         for (dsd::Decomp &d : dec) (void)hipFree(d.core);
+        dsd::free_tri_list(tl);
         dsd::free_graph(g);
     }
 };
@@ -85,6 +88,9 @@ void begin_stats(dsd_graph_s *G);
 void end_stats(dsd_graph_s *G, const KernelTimes &kt);
 // clique-degrees (rank space) inside mask and their total mu; throws on overflow
 u64 degrees_and_mu(dsd_graph_s *G, int h, const uint8_t *mask, u64 *deg, KernelTimes *kt = nullptr);
+// the handle's triangle lists, built on first use (deg: whole-graph triangle
+// degrees, mu triangles) if they fit; nullptr if not
+const TriList *tri_lists(dsd_graph_s *G, const u64 *deg, u64 mu);
 // the cached decomposition for h, computed on first use
 const Decomp &decompose(dsd_graph_s *G, int h);
 void decomp_stats(dsd_graph_s *G, const Decomp &D);

@@ -16,6 +16,12 @@
 // frontier), core[] receives each vertex's removal round, and the level
 // table holds |S| and mu(S) of the residual graph before every round.
 //
+// With triangle lists (h = 3) a round walks the stored triangles {v, a, b}
+// of every frontier vertex v instead of intersecting neighbourhoods; the
+// owner rule picks the same destroyer, and each neighbour's losses are summed
+// over its run of pairs before they reach its degree.  A row is cut into
+// items of TL_CHUNK pairs, so a hub's triangles spread over many waves.
+//
 // A batch of graphs is peeled as one disjoint union in which every graph
 // keeps its own level k (GraphState): cliques never cross graphs, so each
 // graph's peel is exactly its own, and one round advances all of them.
@@ -49,6 +55,8 @@ struct PeelCtl {
     int32_t nitems[8]; // (v, w) work items per class (h >= 4)
     int64_t htop[2];   // slots handed out in the global neighbourhood hashes (h = 3)
     int64_t nW;        // wide (v, w) items of this round (h = 3)
+    int32_t nT[2];     // row items of the frontier (triangle lists)
+    int32_t pending;   // tail mode: a round has been started and not yet finished
     u64 work[2];       // main kernel's pairs and neighbours over the whole peel (when counted)
 };
 
@@ -91,6 +99,10 @@ struct PeelBufs {
     int64_t wcap;
     int32_t n;
     int32_t h;
+    const int64_t *tvoff; // triangle lists (nullptr: none): row starts, (a, b) pairs
+    const int32_t *tpairs;
+    int64_t *T;          // [2][tcap] row items (v << 32 | chunk) of frontier vertices
+    int64_t tcap;
     int32_t count_work;  // the main kernel adds up its pairs and neighbours
     int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
 };
@@ -100,6 +112,7 @@ constexpr int CHUNK = 32;               // neighbours per chunk item (one wave)
 constexpr int SLOTS_PER_CHUNK = 64;     // global hash slots per chunk (load factor <= 1/2)
 constexpr int WIDE_OUT = 32;            // neighbours w with |N+(w)| >= this get a wave of their own
 constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
+constexpr int TL_CHUNK = 128;           // pairs per row item (two per lane), triangle lists
 
 __device__ __forceinline__ int32_t graph_of(const PeelBufs &b, int32_t v) { return b.gid ? b.gid[v] : 0; }
 
@@ -186,6 +199,22 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
     for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
 }
 
+// row items of a frontier vertex (triangle lists)
+__device__ __forceinline__ void push_items(const PeelBufs &b, int32_t x, int which) {
+    const int64_t len = b.tvoff[x + 1] - b.tvoff[x];
+    if (len == 0) return;
+    const int32_t nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
+    const int32_t base = atomicAdd(&b.ctl->nT[which], nc);
+    int64_t *Tw = b.T + (size_t)which * b.tcap;
+    for (int32_t c = 0; c < nc; c++) Tw[base + c] = ((int64_t)x << 32) | c;
+}
+
+// a frontier vertex's work items for the round's process kernels
+__device__ __forceinline__ void push_work(const PeelBufs &b, int32_t x, int which) {
+    if (b.tpairs) push_items(b, x, which);
+    else push_chunks(b, x, which);
+}
+
 // a survivor x loses c cliques; if that takes it to the level of its graph it
 // joins the next frontier with that core number
 __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int32_t r) {
@@ -204,7 +233,7 @@ __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int
         atomicAdd(&b.gs[g].nF[nx], 1);
         b.stamp[x] = r + 1;
         b.core[x] = k;
-        push_chunks(b, x, nx);
+        push_work(b, x, nx);
     }
 }
 
@@ -323,7 +352,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
                     if (take) {
                         b.stamp[v] = r;
                         b.core[v] = b.minpeel ? (u64)r : k;
-                        push_chunks(b, v, cur);
+                        push_work(b, v, cur);
                     }
                 }
             }
@@ -373,11 +402,108 @@ __device__ __forceinline__ void finish_global(PeelCtl *c) {
     c->nsel[cur] = 0;
     c->nF[cur] = 0;
     c->nB[cur] = 0;
+    c->nT[cur] = 0;
     c->htop[cur] = 0;
     c->nW = 0;
     for (int i = 0; i < 8; i++) c->nitems[i] = 0;
     c->cur = cur ^ 1;
     c->round += 1;
+}
+
+// ---------------------------------------------------------------- tail mode
+//
+// Once few vertices are left, the round's control work fits one workgroup:
+// k_tail_level ends the previous round (what k_finish_* do), then selects
+// the level and builds the frontier (what k_level_min and k_level_build do),
+// so a round is this kernel plus the process kernels.  k_tail_finish ends
+// the last round before the host reads the alive count.
+
+constexpr int TAIL_BLOCK = 1024;
+constexpr int TAIL_WAVES = TAIL_BLOCK / WAVE;
+
+// end of the pending round; all threads of the (single) block call it
+__device__ __forceinline__ void tail_finish_block(const PeelBufs &b) {
+    PeelCtl *c = b.ctl;
+    if (c->pending) {
+        for (int32_t g = threadIdx.x; g < b.G; g += blockDim.x) finish_graph(b, g);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            finish_global(c);
+            c->pending = 0;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(TAIL_BLOCK) void k_tail_finish(PeelBufs b) { tail_finish_block(b); }
+
+__global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
+    __shared__ u64 sMin[TAIL_WAVES];
+    PeelCtl *c = b.ctl;
+    tail_finish_block(b);
+    const int32_t cur = c->cur;
+    if (c->nsel[cur] > 0) {
+        const int32_t lc = c->lcur, cnt = c->nlist[lc], r = c->round;
+        const int32_t *in = b.lists + (size_t)lc * b.n;
+        // smallest alive degree of every graph that opens a level
+        if (b.G == 1) {
+            u64 m = ~0ull;
+            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_BLOCK) {
+                const int32_t v = in[i];
+                if (b.stamp[v] == ALIVE) {
+                    const u64 d = b.deg[v];
+                    m = d < m ? d : m;
+                }
+            }
+            m = wave_min(m);
+            if (lane() == 0) sMin[threadIdx.x / WAVE] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int i = 1; i < TAIL_WAVES; i++) m = sMin[i] < m ? sMin[i] : m;
+                if (m < b.gs[0].kcand) b.gs[0].kcand = m;
+            }
+        } else {
+            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_BLOCK) {
+                const int32_t v = in[i];
+                if (b.stamp[v] == ALIVE) {
+                    const int32_t g = b.gid[v];
+                    if (b.gs[g].sel) atomicMin(&b.gs[g].kcand, b.deg[v]);
+                }
+            }
+        }
+        __syncthreads();
+        // the level's frontier: alive vertices of degree <= k
+        int32_t *out = b.lists + (size_t)(lc ^ 1) * b.n;
+        int32_t *F = b.F + (size_t)cur * b.n;
+        const bool compact = list_compacts(c);
+        constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
+        for (int32_t base = 0; base < cnt; base += TAIL_BLOCK) {
+            const int32_t i = base + threadIdx.x;
+            int32_t v = -1, g = 0;
+            bool alive = false, take = false;
+            if (i < cnt) {
+                v = in[i];
+                alive = b.stamp[v] == ALIVE;
+                if (alive) {
+                    g = graph_of(b, v);
+                    if (b.gs[g].sel) {
+                        const u64 k = level_of(b, g);
+                        take = b.deg[v] <= k;
+                        if (take) {
+                            b.stamp[v] = r;
+                            b.core[v] = b.minpeel ? (u64)r : k;
+                            push_work(b, v, cur);
+                        }
+                    }
+                }
+            }
+            wave_push(take, v, F, &c->nF[cur]);
+            wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
+            if (compact) wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) c->pending = 1;
 }
 
 __global__ void k_finish_one(PeelBufs b) {
@@ -685,6 +811,64 @@ __global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
     }
 }
 
+// ---------------------------------------------------------------- h = 3, triangle lists
+
+// One wave per row item: TL_CHUNK pairs (a, b) of a frontier vertex v, each
+// a triangle {v, a, b}.  v destroys the triangle iff a and b may share a
+// clique with v this round (alive, or frontier vertices of larger rank: the
+// owner rule makes v the triangle's frontier member of smallest rank).  The
+// pairs of one neighbour a are contiguous, so its losses are summed over its
+// run of lanes and applied once.  Each triangle sits twice in v's row, as
+// (a, b) and (b, a), and is counted once.  Counted work: pairs walked (pairs)
+// and items (nbrs).
+__global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0) return;
+    const int32_t r = c->round, nT = c->nT[cur];
+    const int64_t *Tc = b.T + (size_t)cur * b.tcap;
+    const int wv = threadIdx.x / WAVE, L = lane();
+    u64 wp = 0, wn = 0;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nT; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int64_t item = Tc[it];
+        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+        const int64_t lo = b.tvoff[v] + (int64_t)ch * TL_CHUNK;
+        const int64_t hi = min(b.tvoff[v + 1], lo + TL_CHUNK);
+        u64 destroyed = 0;
+        for (int64_t base = lo; base < hi; base += WAVE) {
+            const int64_t e = base + L;
+            const bool valid = e < hi;
+            int32_t a = -1, x = -1, sa = -1;
+            bool ok = false;
+            if (valid) {
+                a = b.tpairs[2 * e];
+                x = b.tpairs[2 * e + 1];
+                sa = b.stamp[a];
+                const int32_t sx = b.stamp[x];
+                ok = allowed(sa, r, a, v) && allowed(sx, r, x, v);
+            }
+            destroyed += (ok && a < x) ? 1 : 0;
+            // runs of equal a over the valid lanes
+            const int32_t pa = __shfl_up(a, 1, WAVE);
+            const bool head = valid && (L == 0 || pa != a);
+            const u64 hm = __ballot(head), om = __ballot(ok);
+            const u64 le = lanemask_lt() | (1ull << L);
+            const u64 nxt = hm & ~le;
+            const int end = nxt ? __builtin_ctzll(nxt) : WAVE;
+            const u64 upto = end == WAVE ? ~0ull : ((1ull << end) - 1);
+            if (head) {
+                const uint32_t cnt = (uint32_t)__popcll(om & upto & ~lanemask_lt());
+                if (cnt && sa > r) dec_deg(b, a, cnt, r);
+            }
+        }
+        destroyed = wave_sum(destroyed);
+        if (L == 0) add_destroyed(b, v, destroyed);
+        wp += (u64)(hi - lo);
+        wn += 1;
+    }
+    if (b.count_work) add_work(b, wp, wn);
+}
+
 // ---------------------------------------------------------------- h >= 4
 
 // Items (v, w): v in the frontier, w an allowed neighbour of v.  The engine
@@ -968,7 +1152,8 @@ static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t 
 }
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
-                hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp, bool min_degree) {
+                hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp, bool min_degree,
+                const TriList *tl) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
@@ -994,7 +1179,14 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.lv_k = sc.get_n<u64>(lv_total);
     b.lv_size = sc.get_n<u64>(lv_total);
     b.lv_mu = sc.get_n<u64>(lv_total);
-    if (h == 3) {
+    const bool listed = h == 3 && tl != nullptr && tl->pairs != nullptr;
+    if (listed) {
+        b.tvoff = tl->voff;
+        b.tpairs = tl->pairs;
+        // a vertex joins at most one frontier; its items number <= 1 + pairs / TL_CHUNK
+        b.tcap = (int64_t)n + tl->entries / TL_CHUNK + 1;
+        b.T = sc.get_n<int64_t>(2 * b.tcap);
+    } else if (h == 3) {
         // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK
         b.bcap = (int64_t)n + 2 * g.m / CHUNK + 1;
         b.B = sc.get_n<int64_t>(2 * b.bcap);
@@ -1042,11 +1234,15 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipEventCreate(&e1));
         DSD_HIP(hipEventRecord(e0, s));
     }
-    const int gmin = 256, gbuild = 1024, gproc = 2048, gprobe = 1024;
+    const int gmin = 256, gbuild = 1024, gproc = 2048, gprobe = 1024, gtail = 256;
+    // tail mode from this many alive vertices on (the count only falls)
+    constexpr int64_t TAIL_ALIVE = 16384;
+    bool tail = false;
     LaunchTimer main_timer(kt != nullptr && h <= 3);
+    // the lists need no adjacency: dead entries are skipped by their bit
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
-    const bool compacting = h <= 3;
+    const bool compacting = h <= 3 && !listed;
     int64_t compacted_at = n;
     if (compacting && n_alive > 0 && n_alive < n / 2) {
         compact_adjacency(b, s, sc);
@@ -1057,15 +1253,23 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;
         }
+        if (n_alive <= TAIL_ALIVE) tail = true;
+        const int gp = tail ? gtail : gprobe, gq = tail ? gtail : gproc, gf = tail ? gtail : gbuild;
         for (int64_t i = 0; i < chunk; i++) {
-            k_level_min<<<gmin, BLOCK, 0, s>>>(b);
-            k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
+            if (tail) {
+                k_tail_level<<<1, TAIL_BLOCK, 0, s>>>(b);
+            } else {
+                k_level_min<<<gmin, BLOCK, 0, s>>>(b);
+                k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
+            }
             if (h == 2) {
-                main_timer.launch(k_process_h2, dim3(gproc), dim3(BLOCK), s, b);
+                main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), s, b);
+            } else if (listed) {
+                main_timer.launch(k_tl_process, dim3(gp), dim3(BLOCK), s, b);
             } else if (h == 3) {
-                k_h3_fill<<<gbuild, BLOCK, 0, s>>>(b);
-                main_timer.launch(k_h3_probe, dim3(gprobe), dim3(BLOCK), s, b);
-                k_h3_flush<<<gbuild, BLOCK, 0, s>>>(b);
+                k_h3_fill<<<gf, BLOCK, 0, s>>>(b);
+                main_timer.launch(k_h3_probe, dim3(gp), dim3(BLOCK), s, b);
+                k_h3_flush<<<gf, BLOCK, 0, s>>>(b);
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
@@ -1075,13 +1279,16 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                     default: throw Error(-1, "h outside [2, 6]");
                 }
             }
-            if (G == 1) {
+            if (tail) {
+                // the next k_tail_level ends this round
+            } else if (G == 1) {
                 k_finish_one<<<1, 1, 0, s>>>(b);
             } else {
                 k_finish_graphs<<<grid_for(G, 256), 256, 0, s>>>(b);
                 k_finish_global<<<1, 1, 0, s>>>(b);
             }
         }
+        if (tail) k_tail_finish<<<1, TAIL_BLOCK, 0, s>>>(b);
         steps += chunk;
         DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         DSD_HIP(hipStreamSynchronize(s));
@@ -1103,6 +1310,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         u64 launches = 0;
         kt->main_ms += main_timer.total_ms(&launches);
         kt->main_launches += launches;
+        if (h == 2) kt->main_kind = 1;
+        else if (h == 3) kt->main_kind = listed ? 3 : 2;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }

@@ -265,3 +265,23 @@ def test_server_admission_slots_timeout_and_cancel():
     st, r = srv.wait(ta)
     assert st == 0 and r["status"] == 0
     srv.close()
+
+
+def test_batch_triangles_without_lists(monkeypatch):
+    # DSD_TRI_LIST=0: the union's h = 3 peel intersects neighbourhoods instead
+    # of walking triangle lists; same results
+    monkeypatch.setenv("DSD_TRI_LIST", "0")
+    graphs = mixed_graphs(6, count=18)
+    handles = build_all(graphs)
+    cores = [np.zeros(max(n, 1), np.uint64) for n, _, _ in graphs]
+    res = dsd.batch_run(handles, 3, "core", outs=cores)
+    for (n, s, d), r, out in zip(graphs, res, cores):
+        core_o, km_o = oracle.Graph(n, s, d).core_decomposition(3)
+        assert r["status"] == 0 and r["kmax"] == km_o
+        np.testing.assert_array_equal(out[:n], core_o)
+    mems = [np.zeros(max(n, 1), np.uint8) for n, _, _ in graphs]
+    res = dsd.batch_run(build_all(graphs), 3, "peel", outs=mems)
+    for (n, s, d), r, out in zip(graphs, res, mems):
+        mem_o, rho_o, steps_o, _ = oracle.Graph(n, s, d).peel_app(3)
+        assert r["status"] == 0 and r["density"] == rho_o and r["peel_rounds"] == steps_o
+        np.testing.assert_array_equal(out[:n].astype(bool), mem_o)

@@ -316,3 +316,28 @@ def test_repeat_calls_are_identical():
     for _ in range(3):
         np.testing.assert_array_equal(dsd.clique_degrees(g, 3)[0], ref[0])
         np.testing.assert_array_equal(dsd.clique_core(g, 3)[0], ref[1])
+
+
+# ------------------------------------------------------------------ h = 3 without triangle lists
+
+@pytest.mark.parametrize("case", ["er", "chung_lu", "multipartite", "random"])
+def test_triangle_peel_without_lists(monkeypatch, case):
+    # DSD_TRI_LIST=0: the h = 3 peel intersects neighbourhoods (hashes, chunk
+    # and wide items) instead of walking triangle lists; same results
+    monkeypatch.setenv("DSD_TRI_LIST", "0")
+    if case == "er":
+        n, s, d = synth.er_planted(seed=2)
+    elif case == "chung_lu":
+        n, s, d = synth.chung_lu(n=30000, avg_deg=12, beta=2.1, planted=2, plant_size=60, p=0.7, seed=3)
+    elif case == "multipartite":
+        n, s, d, _ = synth.complete_multipartite([40, 30, 25, 20, 10], seed=1)
+    else:
+        rng = np.random.default_rng(77)
+        e = np.asarray([(u, v) for u in range(60) for v in range(u + 1, 60) if rng.random() < 0.3], np.int32)
+        n, s, d = 60, e[:, 0].copy(), e[:, 1].copy()
+    gg = check_all(n, s, d, 3, exact=(case != "chung_lu"))
+    og = oracle.Graph(n, s, d)
+    mem_o, rho_o, steps_o, best_o = og.peel_app(3)
+    mem_g, rho_g, rounds_g, best_g = dsd.peel_app(gg, 3)
+    assert (rho_g, rounds_g, best_g) == (rho_o, steps_o, best_o)
+    np.testing.assert_array_equal(mem_g.astype(bool), mem_o)
