@@ -66,9 +66,9 @@ MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process"}
 
 def main_kernel_bytes(st: dict) -> float:
     """Algorithmic bytes of the peel's main kernel over one peel, from the
-    work it counted.  Triangle lists (k_tl_process): every walked entry b
-    costs itself and b's stamp (4 + 4 B), every examined arc (v, a) its
-    column entry, a's stamp and the two list offsets (4 + 4 + 16 B).
+    work it counted.  Triangle lists (k_tl_process): every walked pair
+    (a, b) costs itself and the removal stamps of a and b (8 + 4 + 4 B),
+    every row item its descriptor and the row's two offsets (8 + 16 B).
     Triangle probe (k_h3_probe): every probed out-list entry costs 4 B,
     every expanded neighbour w its column entry and the two row offsets of
     N+(w) (4 + 8 + 8 B).  Edge pass (k_process_h2, h = 2): every walked
@@ -79,7 +79,7 @@ def main_kernel_bytes(st: dict) -> float:
     if kind == 1:
         return 24.0 * st["k4_main_pairs"] + 16.0 * st["k4_main_nbrs"]
     if kind == 3:
-        return 8.0 * st["k4_main_pairs"] + 24.0 * st["k4_main_nbrs"]
+        return 16.0 * st["k4_main_pairs"] + 24.0 * st["k4_main_nbrs"]
     return 4.0 * st["k4_main_pairs"] + 20.0 * st["k4_main_nbrs"]
 
 

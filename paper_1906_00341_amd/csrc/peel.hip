@@ -199,20 +199,34 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
     for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
 }
 
-// row items of a frontier vertex (triangle lists)
-__device__ __forceinline__ void push_items(const PeelBufs &b, int32_t x, int which) {
-    const int64_t len = b.tvoff[x + 1] - b.tvoff[x];
-    if (len == 0) return;
-    const int32_t nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
-    const int32_t base = atomicAdd(&b.ctl->nT[which], nc);
-    int64_t *Tw = b.T + (size_t)which * b.tcap;
-    for (int32_t c = 0; c < nc; c++) Tw[base + c] = ((int64_t)x << 32) | c;
+// Row items of the round's frontier (triangle lists): waves wave0, wave0 +
+// nwaves, ... each take a frontier vertex and write its items together.  A
+// hub's row holds thousands of items, too many for one lane.
+__device__ __forceinline__ void tl_items(const PeelBufs &b, int64_t wave0, int64_t nwaves) {
+    const int32_t cur = b.ctl->cur, nF = b.ctl->nF[cur];
+    const int32_t *F = b.F + (size_t)cur * b.n;
+    int64_t *Tc = b.T + (size_t)cur * b.tcap;
+    for (int64_t i = wave0; i < nF; i += nwaves) {
+        const int32_t v = F[i];
+        const int64_t len = b.tvoff[v + 1] - b.tvoff[v];
+        const int32_t nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
+        if (nc == 0) continue;
+        int32_t base = 0;
+        if (lane() == 0) base = atomicAdd(&b.ctl->nT[cur], nc);
+        base = __shfl(base, 0, WAVE);
+        for (int32_t c = lane(); c < nc; c += WAVE) Tc[base + c] = ((int64_t)v << 32) | c;
+    }
 }
 
-// a frontier vertex's work items for the round's process kernels
+__global__ __launch_bounds__(BLOCK) void k_tl_items(PeelBufs b) {
+    tl_items(b, (int64_t)blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE, (int64_t)gridDim.x * WAVES_PER_BLOCK);
+}
+
+// a frontier vertex's work items for the round's process kernels (with
+// triangle lists they are written for the whole frontier at once, by
+// tl_items, before the process kernel)
 __device__ __forceinline__ void push_work(const PeelBufs &b, int32_t x, int which) {
-    if (b.tpairs) push_items(b, x, which);
-    else push_chunks(b, x, which);
+    if (!b.tpairs) push_chunks(b, x, which);
 }
 
 // a survivor x loses c cliques; if that takes it to the level of its graph it
@@ -437,7 +451,26 @@ __device__ __forceinline__ void tail_finish_block(const PeelBufs &b) {
 
 __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_finish(PeelBufs b) { tail_finish_block(b); }
 
+// the frontier decision for one alive-list entry (v, its stamp and degree)
+__device__ __forceinline__ bool tail_take(const PeelBufs &b, int32_t v, int32_t st, u64 d, int32_t r, int32_t cur,
+                                          int32_t *g_out) {
+    *g_out = 0;
+    if (st != ALIVE) return false;
+    const int32_t g = graph_of(b, v);
+    *g_out = g;
+    if (!b.gs[g].sel) return false;
+    const u64 k = level_of(b, g);
+    if (d > k) return false;
+    b.stamp[v] = r;
+    b.core[v] = b.minpeel ? (u64)r : k;
+    push_work(b, v, cur);
+    return true;
+}
+
 __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
+    // each thread keeps its first TAIL_REG alive-list entries in registers, so
+    // the level's minimum and its frontier need one round of loads
+    constexpr int TAIL_REG = 16;
     __shared__ u64 sMin[TAIL_WAVES];
     PeelCtl *c = b.ctl;
     tail_finish_block(b);
@@ -445,10 +478,25 @@ __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
     if (c->nsel[cur] > 0) {
         const int32_t lc = c->lcur, cnt = c->nlist[lc], r = c->round;
         const int32_t *in = b.lists + (size_t)lc * b.n;
+        int32_t rv[TAIL_REG], rs[TAIL_REG];
+        u64 rd[TAIL_REG];
+#pragma unroll
+        for (int j = 0; j < TAIL_REG; j++) {
+            const int32_t i = j * TAIL_BLOCK + threadIdx.x;
+            rv[j] = i < cnt ? in[i] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < TAIL_REG; j++) {
+            rs[j] = rv[j] >= 0 ? b.stamp[rv[j]] : -1;
+            rd[j] = rv[j] >= 0 ? b.deg[rv[j]] : ~0ull;
+        }
         // smallest alive degree of every graph that opens a level
         if (b.G == 1) {
             u64 m = ~0ull;
-            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_BLOCK) {
+#pragma unroll
+            for (int j = 0; j < TAIL_REG; j++)
+                if (rs[j] == ALIVE && rd[j] < m) m = rd[j];
+            for (int32_t i = TAIL_REG * TAIL_BLOCK + threadIdx.x; i < cnt; i += TAIL_BLOCK) {
                 const int32_t v = in[i];
                 if (b.stamp[v] == ALIVE) {
                     const u64 d = b.deg[v];
@@ -463,7 +511,10 @@ __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
                 if (m < b.gs[0].kcand) b.gs[0].kcand = m;
             }
         } else {
-            for (int32_t i = threadIdx.x; i < cnt; i += TAIL_BLOCK) {
+#pragma unroll
+            for (int j = 0; j < TAIL_REG; j++)
+                if (rs[j] == ALIVE && b.gs[b.gid[rv[j]]].sel) atomicMin(&b.gs[b.gid[rv[j]]].kcand, rd[j]);
+            for (int32_t i = TAIL_REG * TAIL_BLOCK + threadIdx.x; i < cnt; i += TAIL_BLOCK) {
                 const int32_t v = in[i];
                 if (b.stamp[v] == ALIVE) {
                     const int32_t g = b.gid[v];
@@ -477,32 +528,30 @@ __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
         int32_t *F = b.F + (size_t)cur * b.n;
         const bool compact = list_compacts(c);
         constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
-        for (int32_t base = 0; base < cnt; base += TAIL_BLOCK) {
+#pragma unroll
+        for (int j = 0; j < TAIL_REG; j++) {
+            int32_t g = 0;
+            const bool take = rv[j] >= 0 && tail_take(b, rv[j], rs[j], rd[j], r, cur, &g);
+            wave_push(take, rv[j], F, &c->nF[cur]);
+            wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
+            if (compact) wave_push(rs[j] == ALIVE && !take, rv[j], out, &c->nlist[lc ^ 1]);
+        }
+        for (int32_t base = TAIL_REG * TAIL_BLOCK; base < cnt; base += TAIL_BLOCK) {
             const int32_t i = base + threadIdx.x;
-            int32_t v = -1, g = 0;
-            bool alive = false, take = false;
+            int32_t v = -1, st = -1, g = 0;
+            bool take = false;
             if (i < cnt) {
                 v = in[i];
-                alive = b.stamp[v] == ALIVE;
-                if (alive) {
-                    g = graph_of(b, v);
-                    if (b.gs[g].sel) {
-                        const u64 k = level_of(b, g);
-                        take = b.deg[v] <= k;
-                        if (take) {
-                            b.stamp[v] = r;
-                            b.core[v] = b.minpeel ? (u64)r : k;
-                            push_work(b, v, cur);
-                        }
-                    }
-                }
+                st = b.stamp[v];
+                take = tail_take(b, v, st, b.deg[v], r, cur, &g);
             }
             wave_push(take, v, F, &c->nF[cur]);
             wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
-            if (compact) wave_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
+            if (compact) wave_push(st == ALIVE && !take, v, out, &c->nlist[lc ^ 1]);
         }
     }
     __syncthreads();
+    if (b.tpairs) tl_items(b, threadIdx.x / WAVE, TAIL_WAVES);
     if (threadIdx.x == 0) c->pending = 1;
 }
 
@@ -1261,6 +1310,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             } else {
                 k_level_min<<<gmin, BLOCK, 0, s>>>(b);
                 k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
+                if (listed) k_tl_items<<<gbuild, BLOCK, 0, s>>>(b);
             }
             if (h == 2) {
                 main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), s, b);
