@@ -77,3 +77,84 @@ def test_chung_lu_1e6_triangles_whole_graph():
     lv, rs, rm = og.level_table(h, core_o)
     rho1 = max(Fraction(int(m), int(z)) for m, z in zip(rm, rs) if z)
     assert rho1 <= rho_p <= rho <= h * rho_p
+
+
+# ------------------------------------------------------------------ R-MAT scale 22, h = 4 and 5
+
+RMAT_22 = dict(scale=22, edge_factor=16, seed=1)
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    torch = pytest.importorskip("torch")
+    n, s, d = synth.rmat(**RMAT_22)
+    og = oracle.Graph(n, s, d)
+    g = dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    return n, og, g
+
+
+def induced(og, mask):
+    """Edges of the subgraph induced by mask, relabelled 0 .. |mask| - 1."""
+    off, adj = og.adjacency()
+    rows = np.repeat(np.arange(og.n, dtype=np.int32), np.diff(off))
+    e = mask[rows] & mask[adj] & (rows < adj)
+    idx = np.nonzero(mask)[0]
+    new = np.full(og.n, -1, dtype=np.int64)
+    new[idx] = np.arange(idx.size)
+    return idx, new[rows[e]].astype(np.int32), new[adj[e]].astype(np.int32)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("h", [4, 5])
+def test_rmat22_higher_order_cliques(rmat22, h):
+    """R-MAT scale 22 (n = 4,194,304, 67,108,864 edge draws): the oracle
+    cannot list its 10^11 - 10^13 cliques, so the decomposition is checked by
+    what pins it at any size: clique-degrees of sampled vertices against the
+    oracle, sum of degrees = h mu, core <= degree, every sampled level set
+    R_c = {core >= c} has least clique-degree exactly c inside itself
+    (counted by a separate enumeration of its induced subgraph), and the
+    vertex of least
+    clique-degree in each such R_c, which certifies it, has the same count in
+    the oracle.  At h = 4 CoreApp must return exactly the k_max-core, with
+    the density the separate count gives it."""
+    n, og, g = rmat22
+    deg_g, mu_g = dsd.clique_degrees(g, h)
+    core_g, km = dsd.clique_core(g, h)
+    print(f"rmat22 h={h}: mu={mu_g} kmax={km} levels={np.unique(core_g).size}", flush=True)
+    assert int(deg_g.sum()) == h * mu_g
+    assert (core_g <= deg_g).all()
+    assert int(core_g.max()) == km
+
+    off, _ = og.adjacency()
+    deg = np.diff(off)
+    rng = np.random.default_rng(100 + h)
+    sample = rng.choice(np.nonzero((deg >= 1) & (deg <= 1500))[0], 48, replace=False)
+    for v in sample:
+        assert og.clique_degree_of(h, int(v)) == int(deg_g[v]), int(v)
+
+    if h == 4:
+        mem_app, km_app, dens_app = dsd.core_app(g, h)
+        np.testing.assert_array_equal(mem_app.astype(bool), core_g == km)
+        assert km_app == km
+
+    # sampled level sets, top first: each must be a c-core; the vertex of
+    # least clique-degree inside it (the one that certifies that) is recounted
+    # by the oracle on the induced subgraph
+    levels = np.unique(core_g)
+    checked = 0
+    for c in levels[np.linspace(1, levels.size - 1, 4).astype(int)][::-1]:
+        mask = core_g >= c
+        idx, s2, d2 = induced(og, mask)
+        sub = dsd.build_csr(idx.size, s2, d2)
+        d_in, mu_in = dsd.clique_degrees(sub, h)
+        j = int(np.argmin(d_in))
+        print(f"  R_{int(c)}: {idx.size} vertices, {mu_in} cliques, least degree {int(d_in[j])}", flush=True)
+        # R_c is a c-core, and c is the smallest degree when its level opens
+        assert int(d_in[j]) == int(c), int(c)
+        if h == 4 and c == km:
+            assert dens_app == Fraction(mu_in, idx.size)
+        if int(d_in[j]) <= 200_000_000:
+            assert oracle.Graph(idx.size, s2, d2).clique_degree_of(h, j) == int(d_in[j])
+            checked += 1
+        sub.free()
+    assert checked >= 2
