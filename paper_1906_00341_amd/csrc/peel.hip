@@ -1177,25 +1177,26 @@ private:
 };
 
 template <int R>
-static void launch_peel_items(const DevGraph &g, const PeelBufs &b, hipStream_t s, u64 *gS) {
+// the engines read the peel's current (possibly compacted) adjacency
+static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
     PeelCtx ctx{b, 0};
     const int32_t *ni = &b.ctl->nitems[0];
-    k_engine_wave<R, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off, 0, ni + 0);
+    k_engine_wave<R, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off, 0, ni + 0);
     if constexpr (R <= 2) {
         ctx.cls = 1;
-        k_engine_block<R, 2048, 12, 1, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off,
+        k_engine_block<R, 2048, 12, 1, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
                                                                                 0, ni + 1, nullptr);
         ctx.cls = 2;
-        k_engine_huge_r2<PeelCtx><<<256, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off, 0, ni + 2);
+        k_engine_huge_r2<PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off, 0, ni + 2);
     } else {
         ctx.cls = 1;
-        k_engine_block<R, 256, 9, 4, false, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off,
+        k_engine_block<R, 256, 9, 4, false, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
                                                                                0, ni + 1, nullptr);
         ctx.cls = 2;
-        k_engine_block<R, 768, 11, 12, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off,
+        k_engine_block<R, 768, 11, 12, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
                                                                                 0, ni + 2, nullptr);
         ctx.cls = 3;
-        k_engine_block<R, 1280, 12, 20, true, PeelCtx><<<256, BLOCK, 0, s>>>(ctx, g.row_ptr, g.col, g.dag_off,
+        k_engine_block<R, 1280, 12, 20, true, PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
                                                                                 0, ni + 3, gS);
     }
 }
@@ -1291,7 +1292,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     // the lists need no adjacency: dead entries are skipped by their bit
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
-    const bool compacting = h <= 3 && !listed;
+    const bool compacting = !listed;
     int64_t compacted_at = n;
     if (compacting && n_alive > 0 && n_alive < n / 2) {
         compact_adjacency(b, s, sc);
@@ -1323,9 +1324,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
-                    case 2: launch_peel_items<2>(g, b, s, gS); break;
-                    case 3: launch_peel_items<3>(g, b, s, gS); break;
-                    case 4: launch_peel_items<4>(g, b, s, gS); break;
+                    case 2: launch_peel_items<2>(b, s, gS); break;
+                    case 3: launch_peel_items<3>(b, s, gS); break;
+                    case 4: launch_peel_items<4>(b, s, gS); break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
             }
