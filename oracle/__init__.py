@@ -57,9 +57,10 @@ def _load():
     lib.orc_locate.argtypes = [P, C.c_int, u64p, u64, u64, u64, u64, u64, u64, i32p, i64]
     lib.orc_exact.argtypes = [P, C.c_int, C.c_int, u8p, u64, u64, i64]
     lib.orc_denser_than.argtypes = [P, C.c_int, C.c_uint64, C.c_uint64, u8p]
+    lib.orc_exact_query.argtypes = [P, C.c_int, C.c_int32, i32p, u8p, u64, u64, i64]
     for f in ("orc_clique_degrees", "orc_clique_degree_of", "orc_core_decomposition",
               "orc_level_table", "orc_inc_app", "orc_core_app", "orc_peel_app", "orc_locate",
-              "orc_exact", "orc_denser_than"):
+              "orc_exact", "orc_denser_than", "orc_exact_query"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -184,6 +185,16 @@ class Graph:
         calls = C.c_int64()
         r = {"whole": 0, "core": 1}[route]
         _check(_lib.orc_exact(self._p, h, r, mem, C.byref(a), C.byref(b), C.byref(calls)), "exact")
+        return mem[: self.n].astype(bool), Fraction(int(a.value), int(b.value)), int(calls.value)
+
+    def exact_query(self, h: int, q):
+        """Densest subgraph containing every vertex of q -> (member, density, flow calls)."""
+        q = np.ascontiguousarray(np.atleast_1d(q), dtype=np.int32)
+        mem = np.zeros(max(1, self.n), dtype=np.uint8)
+        a, b = C.c_uint64(), C.c_uint64()
+        calls = C.c_int64()
+        _check(_lib.orc_exact_query(self._p, h, int(q.size), q, mem, C.byref(a), C.byref(b), C.byref(calls)),
+               "exact_query")
         return mem[: self.n].astype(bool), Fraction(int(a.value), int(b.value)), int(calls.value)
 
     def denser_than(self, h: int, alpha: Fraction):

@@ -989,8 +989,12 @@ static void emit_net(void *c, const int32_t *mem, int size) {
 
 /* Strict test on graph s for alpha = a/b: is there a subgraph of density
  * > alpha?  Alg. 1's network scaled by b (h >= 3), or Goldberg's network
- * scaled by b (h = 2).  side_v[v] = 1 for v on the source side. */
-static int denser_than(const orc_graph *s, int h, uint64_t a, uint64_t b, uint8_t *side_v, int *found) {
+ * scaled by b (h = 2).  side_v[v] = 1 for v on the source side.  forced
+ * (may be NULL): vertices whose source arc is infinite, so that every cut of
+ * finite capacity keeps them on the source side (then *found only says the
+ * side is non-empty; the caller compares densities). */
+static int denser_than_forced(const orc_graph *s, int h, uint64_t a, uint64_t b, const uint8_t *forced,
+                              uint8_t *side_v, int *found) {
     int32_t n = s->n;
     *found = 0;
     for (int32_t v = 0; v < n; v++) side_v[v] = 0;
@@ -1004,9 +1008,13 @@ static int denser_than(const orc_graph *s, int h, uint64_t a, uint64_t b, uint8_
         rc = fn_init(&F, nodes, 2 * (int64_t)n + 2 * s->off[n] + 8);
         if (rc) { fn_free(&F); return rc; }
         i128 M = (i128)s->m;
+        /* infinity: more than the sum of every finite capacity */
+        i128 inf = 1;
+        for (int32_t v = 0; v < n; v++)
+            inf += 2 * (i128)b * M + 2 * (i128)a + (i128)b * (i128)(s->off[v + 1] - s->off[v]);
         for (int32_t v = 0; v < n; v++) {
             i128 dv = (i128)(s->off[v + 1] - s->off[v]);
-            rc |= fn_arc(&F, 0, 2 + v, (i128)b * M);
+            rc |= fn_arc(&F, 0, 2 + v, forced && forced[v] ? inf : (i128)b * M);
             rc |= fn_arc(&F, 2 + v, 1, (i128)b * M + 2 * (i128)a - (i128)b * dv);
             for (int64_t e = s->off[v]; e < s->off[v + 1]; e++)
                 rc |= fn_arc(&F, 2 + v, 2 + s->adj[e], (i128)b);
@@ -1032,7 +1040,7 @@ static int denser_than(const orc_graph *s, int h, uint64_t a, uint64_t b, uint8_
         if (fin >= ((u128)1) << 118) { fn_free(&F); free(deg); free(lam.tuples); return ORC_EOVERFLOW; }
         i128 inf = (i128)fin + 1;
         for (int32_t v = 0; v < n; v++) {
-            rc |= fn_arc(&F, 0, 2 + v, (i128)b * (i128)deg[v]);
+            rc |= fn_arc(&F, 0, 2 + v, forced && forced[v] ? inf : (i128)b * (i128)deg[v]);
             rc |= fn_arc(&F, 2 + v, 1, (i128)h * (i128)a);
         }
         for (int64_t i = 0; i < lam.n; i++)
@@ -1061,6 +1069,10 @@ static int denser_than(const orc_graph *s, int h, uint64_t a, uint64_t b, uint8_
     free(lam.tuples);
     fn_free(&F);
     return rc;
+}
+
+static int denser_than(const orc_graph *s, int h, uint64_t a, uint64_t b, uint8_t *side_v, int *found) {
+    return denser_than_forced(s, h, a, b, NULL, side_v, found);
 }
 
 int orc_denser_than(const orc_graph *g, int h, uint64_t a, uint64_t b, uint8_t *member) {
@@ -1103,6 +1115,45 @@ static int density_of(const orc_graph *g, int h, const uint8_t *mask, uint64_t *
     *den = size;
     reduce(num, den);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Densest subgraph containing a query set Q (Section 6.3, the variant of  */
+/* the problem).  Start from Q itself; while the minimum cut of the network */
+/* with Q forced to the source side yields a set of density > l (its       */
+/* source side maximises mu(S) - l|S| over S containing Q), move to it.    */
+/* Densities strictly increase, so this ends, at the largest density of a  */
+/* set containing Q.                                                       */
+/* ------------------------------------------------------------------ */
+
+int orc_exact_query(const orc_graph *g, int h, int32_t nq, const int32_t *q, uint8_t *member,
+                    uint64_t *num, uint64_t *den, int64_t *flow_calls) {
+    if (h < 2 || h > ORC_HMAX || nq < 1) return ORC_EINVAL;
+    int32_t n = g->n;
+    for (int32_t i = 0; i < nq; i++)
+        if (q[i] < 0 || q[i] >= n) return ORC_EINVAL;
+    uint8_t *forced = (uint8_t *)calloc((size_t)n + 1, 1);
+    uint8_t *side = (uint8_t *)malloc((size_t)n + 1);
+    if (!forced || !side) { free(forced); free(side); return ORC_ENOMEM; }
+    for (int32_t i = 0; i < nq; i++) forced[q[i]] = 1;
+    memcpy(member, forced, (size_t)n);
+    int rc = density_of(g, h, member, num, den);
+    *flow_calls = 0;
+    while (!rc) {
+        int found;
+        rc = denser_than_forced(g, h, *num, *den, forced, side, &found);
+        (*flow_calls)++;
+        if (rc) break;
+        uint64_t sn, sd;
+        rc = density_of(g, h, side, &sn, &sd);
+        if (rc || !frac_gt(sn, sd, *num, *den)) break;
+        memcpy(member, side, (size_t)n);
+        *num = sn;
+        *den = sd;
+    }
+    free(forced);
+    free(side);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

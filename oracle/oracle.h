@@ -108,6 +108,13 @@ int orc_locate(const orc_graph *g, int h, const uint64_t *core,
 int orc_exact(const orc_graph *g, int h, int route, uint8_t *member,
               uint64_t *num, uint64_t *den, int64_t *flow_calls);
 
+/* Densest subgraph that contains every vertex of q (nq >= 1 ids, repeats
+ * allowed): member marks it, num/den its density (0/1 when no set containing
+ * q holds a clique).  Minimum cuts of Alg. 1's network (Goldberg's for h = 2)
+ * with q forced to the source side.  Returns 0, -1 on bad arguments. */
+int orc_exact_query(const orc_graph *g, int h, int32_t nq, const int32_t *q, uint8_t *member,
+                    uint64_t *num, uint64_t *den, int64_t *flow_calls);
+
 /* Min-cut helper exposed for tests: strict test "is there a subgraph with
  * density > a/b", returns 1 and marks member if so, else 0. */
 int orc_denser_than(const orc_graph *g, int h, uint64_t a, uint64_t b, uint8_t *member);

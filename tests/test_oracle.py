@@ -504,3 +504,56 @@ def test_peel_app_without_cliques():
     assert rho == 0 and best == -1 and not mem.any() and steps == 1
     g = oracle.Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32))
     assert g.peel_app(2)[1:] == (Fraction(0), 0, -1)
+
+
+# ---------------------------------------------- Section 6.3, query-constrained densest subgraph
+
+def _densest_containing(n, edges, h, q):
+    """max over S containing q of mu(S)/|S|, by trying every superset of q."""
+    cl = brute.cliques(n, edges, h)
+    rest = [v for v in range(n) if v not in set(q)]
+    best = Fraction(0)
+    for r in range(len(rest) + 1):
+        for extra in itertools.combinations(rest, r):
+            S = set(q) | set(extra)
+            mu = sum(1 for c in cl if set(c) <= S)
+            best = max(best, Fraction(mu, len(S)))
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_query_exact_against_exhaustive_search(seed, h):
+    n = 11
+    edges = brute.random_graph(n, 0.5, 1300 + seed)
+    g = G(n, edges)
+    rng = np.random.default_rng(seed)
+    for nq in (1, 2, 3):
+        q = rng.choice(n, nq, replace=False).tolist()
+        mem, rho, _ = g.exact_query(h, q)
+        assert rho == _densest_containing(n, edges, h, q), q
+        assert all(mem[v] for v in q)
+        _, mu = brute.clique_degrees(n, edges, h, members(mem))
+        assert Fraction(mu, len(members(mem))) == rho
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_query_special_cases(fixtures, h):
+    # Figure 6 graph: a query vertex inside an unconstrained densest subgraph
+    # gives rho_opt; the whole vertex set as the query gives the graph's
+    # density; adding query vertices never raises the optimum
+    f = fixtures["F4"]
+    g = G(f["n"], f["edges"])
+    dmem, opt, _ = g.exact(h, "whole")
+    v = members(dmem)[0]
+    assert g.exact_query(h, [v])[1] == opt
+    mu = g.clique_degrees(h)[1]
+    assert g.exact_query(h, list(range(f["n"])))[1] == Fraction(mu, f["n"])
+    assert g.exact_query(h, [12, 13])[1] <= g.exact_query(h, [12])[1] <= opt
+
+
+def test_query_without_cliques():
+    # a path holds no triangle: the query set itself, at density 0
+    g = G(6, [(i, i + 1) for i in range(5)])
+    mem, rho, _ = g.exact_query(3, [2, 4])
+    assert rho == 0 and members(mem) == [2, 4]
