@@ -168,6 +168,25 @@ dsd_status dsd_peel_app(dsd_graph g, int h, int out_mem, uint8_t *member, dsd_ra
 dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
                           dsd_rational *rho_opt);
 
+/*
+ * The densest subgraph that contains every vertex of a query set Q
+ * (Section 6.3, the variant of the problem, here for h-cliques).  With x the
+ * smallest clique-core number over Q, the (x, Psi)-core contains Q and has
+ * density l >= x/h (Theorem 1); every densest set containing Q lies in the
+ * (min(x, ceil(l)), Psi)-core, which the GPU locates; the host searches it
+ * with minimum cuts of Algorithm 1's network (Goldberg's for h = 2) in which
+ * Q is forced to the source side.
+ *   q:      nq >= 1 caller ids in [0, n), host memory (repeats allowed).
+ *   member: length n bytes, residency out_mem: 1 for the vertices of one
+ *           densest set containing Q (Q itself, at density 0/1, when no set
+ *           containing Q holds an h-clique).
+ *   rho:    its density (may be NULL).
+ * DSD_EINVAL for an empty query or an id outside [0, n); otherwise as
+ * dsd_core_exact.
+ */
+dsd_status dsd_core_exact_query(dsd_graph g, int h, int32_t nq, const int32_t *q, int out_mem, uint8_t *member,
+                                dsd_rational *rho);
+
 /* ------------------------------------------------------------------ batches
  *
  * dsd_batch_run runs one operation on many graphs at once and gives every

@@ -258,6 +258,95 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
     return rho;
 }
 
+// rank and clique-core number of every query vertex
+__global__ void k_query_core(const int32_t *rank_of, const u64 *core, const int32_t *q, int32_t nq, int32_t *rank,
+                             u64 *qcore) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
+        const int32_t r = rank_of[q[i]];
+        rank[i] = r;
+        qcore[i] = core[r];
+    }
+}
+
+__global__ void k_mark(uint8_t *mask, const int32_t *ids, int32_t nq) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) mask[ids[i]] = 1;
+}
+
+// The densest subgraph containing every query vertex (Section 6.3, for
+// h-cliques).  With x the least clique-core number over Q, the (x, Psi)-core
+// contains Q and has density l >= x/h (Theorem 1); any densest set D
+// containing Q has every vertex outside Q at clique-degree >= rho(D) >= l
+// inside D, so D together with the (x, Psi)-core has least degree >=
+// min(x, ceil(l)): D lies in that core.  The GPU locates it; the host
+// searches it with Q forced to the source side of every cut.
+dsd_rational core_exact_query_run(dsd_graph_s *G, int h, const std::vector<int32_t> &q, uint8_t *res) {
+    const int32_t n = G->g.n, nq = (int32_t)q.size();
+    hipStream_t s = G->stream;
+    const Decomp &D = decompose(G, h);
+    decomp_stats(G, D);
+    fill_u8(res, 0, n, s);
+    int32_t *dq = G->sc.get_n<int32_t>(nq), *dr = G->sc.get_n<int32_t>(nq);
+    u64 *dc = G->sc.get_n<u64>(nq);
+    DSD_HIP(hipMemcpyAsync(dq, q.data(), (size_t)nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    k_query_core<<<grid_for(nq, 256, 1024), 256, 0, s>>>(G->g.rank_of, D.core, dq, nq, dr, dc);
+    std::vector<int32_t> qr(nq);
+    std::vector<u64> qc(nq);
+    DSD_HIP(hipMemcpyAsync(qr.data(), dr, (size_t)nq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(qc.data(), dc, (size_t)nq * sizeof(u64), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (D.mu == 0) {                  // no clique anywhere: Q itself, at density 0
+        k_mark<<<grid_for(nq, 256, 1024), 256, 0, s>>>(res, dr, nq);
+        DSD_HIP(hipStreamSynchronize(s));
+        return dsd_rational{0, 1};
+    }
+    const u64 x = *std::min_element(qc.begin(), qc.end());
+    // the (x, Psi)-core: Q's first candidate, its density from the level table
+    const PeelResult &pr = D.levels;
+    int64_t li = -1;
+    for (int64_t i = 0; i < (int64_t)pr.level_k.size(); i++)
+        if (pr.level_k[i] == x) li = i;
+    if (li < 0) throw Error(DSD_EDEVICE, "query vertex core number missing from the level table");
+    Rational l{pr.level_mu[li], pr.level_size[li]};
+    {
+        const dsd_rational r = make_rational(l.num, l.den);
+        l = Rational{r.num, r.den};
+    }
+    const u64 kstar = std::min<u64>(x, ceil_div_u(l.num, l.den));
+    Timer tl(s);
+    uint8_t *m = G->sc.get_n<uint8_t>(n);
+    int32_t *lab = G->sc.get_n<int32_t>(n);
+    mask_core_at_least(D.core, n, kstar, m, s);
+    components(G->g, m, lab, s, G->sc);
+    LocatedCore lc;
+    extract_induced(G->g, m, lab, D.core, lc, s, G->sc);
+    G->stats.located_vertices = lc.rank.size();
+    G->stats.t_locate_ms = tl.stop();
+    std::vector<int32_t> local(n, -1);
+    for (size_t i = 0; i < lc.rank.size(); i++) local[lc.rank[i]] = (int32_t)i;
+    std::vector<int32_t> ql;
+    for (int32_t r : qr)
+        if (local[r] >= 0) ql.push_back(local[r]);
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<int32_t> bestset;
+    ExactStats es;
+    const bool improved = exact_search_query(lc, h, x, ql, l, bestset, es);
+    G->stats.t_exact_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    G->stats.flow_calls = es.flow_calls;
+    G->stats.flow_nodes_max = es.max_nodes;
+    G->stats.t_flow_build_ms = es.build_ms;
+    G->stats.t_flow_ms = es.flow_ms;
+    G->stats.flow_gpu_calls = es.gpu_flow_calls;
+    if (improved) {
+        std::vector<uint8_t> hm(n, 0);
+        for (int32_t v : bestset) hm[lc.rank[v]] = 1;
+        DSD_HIP(hipMemcpyAsync(res, hm.data(), n, hipMemcpyHostToDevice, s));
+        DSD_HIP(hipStreamSynchronize(s));
+    } else {
+        mask_core_at_least(D.core, n, x, res, s);
+    }
+    return dsd_rational{l.num, l.den};
+}
+
 }  // namespace dsd
 
 extern "C" {
@@ -559,6 +648,28 @@ dsd_status dsd_peel_app(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_ra
         if (density) *density = rho;
         if (rounds) *rounds = r;
         if (best_round) *best_round = br;
+        G->stats.t_total_ms = tm.stop();
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_core_exact_query(dsd_graph G, int h, int32_t nq, const int32_t *q, int out_mem, uint8_t *member,
+                                dsd_rational *rho) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    if (nq < 1 || !q) return fail(DSD_EINVAL, "the query needs at least one vertex");
+    for (int32_t i = 0; i < nq; i++)
+        if (q[i] < 0 || q[i] >= G->g.n) return fail(DSD_EINVAL, "query vertex outside [0, n)");
+    DSD_TRY({
+        check_h(h);
+        const int32_t n = G->g.n;
+        check_out(member, out_mem);
+        G->sc.reset();
+        begin_stats(G);
+        Timer tm(G->stream);
+        uint8_t *res = G->sc.get_n<uint8_t>(n);
+        const dsd_rational r = core_exact_query_run(G, h, std::vector<int32_t>(q, q + nq), res);
+        write_u8(G, res, member, out_mem);
+        if (rho) *rho = r;
         G->stats.t_total_ms = tm.stop();
         return DSD_OK;
     })

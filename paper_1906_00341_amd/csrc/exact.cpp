@@ -612,6 +612,15 @@ public:
     int nodes() const { return net_->nodes(); }
     int64_t gpu_calls() const { return gpu_calls_; }
 
+    // Vertices (local ids of the located core, members of this network) that
+    // every cut must keep on the source side: their source arcs become
+    // infinite.  Call before the first test.
+    void force(const std::vector<int32_t> &q) {
+        forced_.assign(verts_.size(), 0);
+        for (int32_t v : q)
+            if (idx_[v] >= 0) forced_[idx_[v]] = 1;
+    }
+
     // Strict test at alpha = a/b.  Returns true and the found set (local ids)
     // when some subgraph of this vertex set is denser than alpha.
     bool denser_than(uint64_t a, uint64_t b, std::vector<int32_t> &found) {
@@ -631,7 +640,20 @@ public:
             srcsum += cs;
         }
         if (srcsum * 2 >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
-        const FlowTest test{h_, (int64_t)a, (int64_t)b, (int64_t)m_, (int64_t)srcsum + 1};
+        // infinity: above every finite cut.  Without forced vertices the cut
+        // {s} bounds the minimum by the source total; with them the minimum
+        // can exceed it, so infinity must exceed every finite capacity.
+        i128 inf = srcsum + 1;
+        if (!forced_.empty()) {
+            i128 fin = srcsum;
+            for (int i = 0; i < nv; i++)
+                fin += h_ == 2 ? (i128)b * (i128)m_ + 2 * (i128)a : (i128)h_ * (i128)a;
+            fin += (i128)b * (i128)mid_.size();
+            if (h_ == 2) fin += (i128)b * (i128)mid_.size();
+            inf = fin + 1;
+            if (inf >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
+        }
+        const FlowTest test{h_, (int64_t)a, (int64_t)b, (int64_t)m_, (int64_t)inf};
         int64_t f = 0;
         std::vector<char> reach;
         bool done = false;
@@ -640,6 +662,8 @@ public:
             if (!gpu_) {
                 std::vector<uint8_t> cls(net_->arcs());
                 for (int e : src_) cls[e] = ARC_SRC;
+                for (size_t i = 0; i < forced_.size(); i++)
+                    if (forced_[i]) cls[src_[i]] = ARC_INF;
                 for (int e : snk_) cls[e] = ARC_SNK;
                 for (int e : inf_) cls[e] = ARC_INF;
                 parallel_slices((int64_t)mid_.size(), host_threads(), [&](int, int64_t lo, int64_t hi) {
@@ -654,12 +678,13 @@ public:
         if (!done) {
             net_->ensure_built();
             for (int i = 0; i < nv; i++) {
+                const bool fv = !forced_.empty() && forced_[i];
                 if (h_ == 2) {
                     const int64_t cs = test.b * test.m;
-                    net_->set(src_[i], cs);
+                    net_->set(src_[i], fv ? test.inf : cs);
                     net_->set(snk_[i], cs + 2 * test.a - test.b * (int64_t)deg_[i]);
                 } else {
-                    net_->set(src_[i], test.b * (int64_t)deg_[i]);
+                    net_->set(src_[i], fv ? test.inf : test.b * (int64_t)deg_[i]);
                     net_->set(snk_[i], (int64_t)h_ * test.a);
                 }
             }
@@ -694,6 +719,7 @@ private:
     std::vector<int32_t> idx_;
     std::vector<uint64_t> deg_;
     std::vector<int> src_, snk_, mid_, inf_;
+    std::vector<char> forced_;
     std::vector<uint32_t> psi_first_;
     uint64_t mu_ = 0, m_ = 0;
     PushRelabel *net_ = nullptr;
@@ -761,6 +787,43 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             best = U;
             improved = true;
         }
+    }
+    return improved;
+}
+
+bool exact_search_query(const LocatedCore &lc, int h, uint64_t x, const std::vector<int32_t> &q, Rational &l,
+                        std::vector<int32_t> &best, ExactStats &st) {
+    const int32_t S = (int32_t)lc.rank.size();
+    bool improved = false;
+    std::vector<int32_t> cur, built, found;
+    std::unique_ptr<CompNet> net;
+    while (true) {
+        // the densest set containing q lies in R_k for k = min(x, ceil(l))
+        const uint64_t floor_k = std::min<uint64_t>(x, ceil_div_u(l.num, l.den));
+        cur.clear();
+        for (int32_t v = 0; v < S; v++)
+            if (lc.core[v] >= floor_k) cur.push_back(v);
+        auto t0 = std::chrono::steady_clock::now();
+        if (!net || cur != built) {
+            net.reset(new CompNet(lc, h, cur));
+            net->force(q);
+            built = cur;
+        }
+        auto t1 = std::chrono::steady_clock::now();
+        st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
+        st.flow_calls++;
+        const int64_t g0 = net->gpu_calls();
+        const bool denser = net->denser_than(l.num, l.den, found);
+        st.gpu_flow_calls += net->gpu_calls() - g0;
+        auto t2 = std::chrono::steady_clock::now();
+        st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+        if (!denser) break;
+        const Rational d = reduced(count_cliques_host(lc, h, found), found.size());
+        if (!frac_less(l, d)) break;
+        l = d;
+        best = found;
+        improved = true;
     }
     return improved;
 }

@@ -37,6 +37,15 @@ struct ExactStats {
 bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::vector<int32_t> &best,
                   ExactStats &st);
 
+// The densest subgraph of the located core that contains every vertex of q
+// (local ids).  x = the smallest clique-core number over q; l enters as the
+// density of a set containing q (the caller's (x, Psi)-core) and the search
+// runs over R_k, k = min(x, ceil(l)), which holds every such set at least
+// that dense.  Returns true and overwrites best (local ids) / l when a denser
+// set containing q exists.
+bool exact_search_query(const LocatedCore &lc, int h, uint64_t x, const std::vector<int32_t> &q, Rational &l,
+                        std::vector<int32_t> &best, ExactStats &st);
+
 // h-cliques of the subgraph of lc induced by `verts` (local ids)
 uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int32_t> &verts);
 

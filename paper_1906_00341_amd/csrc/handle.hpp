@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/dsd.h"
 #include "exact.hpp"
@@ -104,6 +105,10 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density);
 // best (device, rank space, length n) receives the densest residual graph;
 // returns its density; *rounds / *best_round as dsd_peel_app reports them
 dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds, int64_t *best_round);
+// densest subgraph containing the query vertices q (caller ids, at least
+// one) on a handle: res (device, rank space, length n) receives it; returns
+// its density
+dsd_rational core_exact_query_run(dsd_graph_s *G, int h, const std::vector<int32_t> &q, uint8_t *res);
 // CoreExact on a handle: res (device, rank space, length n) receives the
 // members of one densest subgraph; returns rho_opt
 dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res);

@@ -31,7 +31,8 @@ OP_DEGREES, OP_CORE, OP_APP, OP_EXACT, OP_PEEL = 0, 1, 2, 3, 4
 OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT, "peel": OP_PEEL}
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
-           "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_last_stats",
+           "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
+           "dsd_last_stats",
            "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
            "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
 
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
     lib.dsd_peel_app.argtypes = [P, I, I, P, C.POINTER(Rational), C.POINTER(I64), C.POINTER(I64)]
     lib.dsd_core_exact.argtypes = [P, I, I, P, C.POINTER(Rational)]
+    lib.dsd_core_exact_query.argtypes = [P, I, I32, P, I, P, C.POINTER(Rational)]
     lib.dsd_last_stats.argtypes = [P, C.POINTER(Stats)]
     lib.dsd_batch_run.argtypes = [I32, C.POINTER(P), C.POINTER(I), I, I, C.POINTER(P), C.POINTER(Result)]
     lib.dsd_server_create.argtypes = [C.c_size_t, I, C.POINTER(P)]
@@ -245,6 +247,17 @@ def core_exact(g: Graph, h: int, out=None):
     out, p, mem, n = _out_u8(g, out)
     r = Rational()
     _check(_lib.dsd_core_exact(g.handle, int(h), mem, p, C.byref(r)))
+    return (out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den)
+
+
+def core_exact_query(g: Graph, h: int, q, out=None):
+    """dsd_core_exact_query -> (member[n] uint8, density Fraction): the densest
+    subgraph containing every vertex of q."""
+    q = np.ascontiguousarray(np.atleast_1d(q), dtype=np.int32)
+    out, p, mem, n = _out_u8(g, out)
+    r = Rational()
+    _check(_lib.dsd_core_exact_query(g.handle, int(h), int(q.size), q.ctypes.data_as(C.c_void_p), mem, p,
+                                     C.byref(r)))
     return (out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den)
 
 

@@ -1,0 +1,134 @@
+"""GPU parity of the query-constrained densest subgraph (Section 6.3): the
+densest subgraph that contains every vertex of a query set Q, through the C
+ABI, against the oracle's search with Q forced to the source side.
+
+Densities are compared as exact rationals; densest sets need not be unique,
+so the returned set must contain Q and attain the density (counted by the
+oracle on its vertices).
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import dsd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    dsd.load()          # fails loudly when the library is missing
+
+
+def density_of(og, h, member):
+    idx = np.nonzero(np.asarray(member))[0]
+    if idx.size == 0:
+        return Fraction(0)
+    off, adj = og.adjacency()
+    keep = np.zeros(og.n, dtype=bool)
+    keep[idx] = True
+    rows = np.repeat(np.arange(og.n), np.diff(off))
+    e = keep[rows] & keep[adj] & (rows < adj)
+    sub = oracle.Graph(og.n, rows[e].astype(np.int32), adj[e].astype(np.int32))
+    return Fraction(sub.clique_degrees(h)[1], idx.size)
+
+
+def check(og, gg, h, q):
+    _, rho_o, _ = og.exact_query(h, q)
+    mem, rho = dsd.core_exact_query(gg, h, q)
+    assert rho == rho_o, (h, q)
+    sel = mem.astype(bool)
+    assert sel[np.asarray(q)].all()
+    assert density_of(og, h, sel) == rho
+    return rho, sel
+
+
+def both(n, s, d):
+    s = np.ascontiguousarray(s, np.int32)
+    d = np.ascontiguousarray(d, np.int32)
+    return oracle.Graph(n, s, d), dsd.build_csr(n, s, d)
+
+
+@pytest.mark.parametrize("name", ["F1", "F2", "F4"])
+@pytest.mark.parametrize("h", [2, 3])
+def test_paper_examples(fixtures, name, h):
+    f = fixtures[name]
+    e = np.asarray(f["edges"], np.int32)
+    og, gg = both(f["n"], e[:, 0], e[:, 1])
+    for v in range(f["n"]):
+        check(og, gg, h, [v])
+    check(og, gg, h, [0, f["n"] - 1])
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_random_small(seed, h):
+    rng = np.random.default_rng(400 + seed)
+    n = 40
+    pairs = [(u, v) for u, v in itertools.combinations(range(n), 2) if rng.random() < 0.3]
+    e = np.asarray(pairs, np.int32)
+    og, gg = both(n, e[:, 0], e[:, 1])
+    for nq in (1, 2, 4):
+        check(og, gg, h, rng.choice(n, nq, replace=False).tolist())
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_er_planted_config(seed):
+    n, s, d = synth.er_planted(seed=seed)
+    og, gg = both(n, s, d)
+    rng = np.random.default_rng(seed)
+    for h in (2, 3):
+        for nq in (1, 3):
+            check(og, gg, h, rng.choice(n, nq, replace=False).tolist())
+
+
+def test_every_min_cut_on_the_gpu(fixtures, monkeypatch):
+    # the forced query vertices take infinite source arcs in the GPU cut too
+    monkeypatch.setenv("DSD_FLOW_GPU_MIN_ARCS", "0")
+    n, s, d = synth.er_planted(seed=3)
+    og, gg = both(n, s, d)
+    rng = np.random.default_rng(9)
+    for h in (2, 3):
+        check(og, gg, h, rng.choice(n, 2, replace=False).tolist())
+    f = fixtures["F4"]
+    e = np.asarray(f["edges"], np.int32)
+    og, gg = both(f["n"], e[:, 0], e[:, 1])
+    for v in (0, 7, 12):
+        check(og, gg, 2, [v])
+
+
+def test_chung_lu_properties():
+    # too large for the oracle's whole-graph search: the answer contains Q,
+    # attains its density, lies between the density of the (x, Psi)-core and
+    # rho_opt, and a query inside a densest subgraph gives rho_opt
+    h = 3
+    n, s, d = synth.chung_lu(n=30000, avg_deg=12, beta=2.1, planted=2, plant_size=60, p=0.7, seed=5)
+    og, gg = both(n, s, d)
+    core, _ = dsd.clique_core(gg, h)
+    opt_mem, opt = dsd.core_exact(gg, h)
+    rng = np.random.default_rng(3)
+    for q in ([int(np.nonzero(opt_mem)[0][0])], rng.choice(n, 2, replace=False).tolist()):
+        mem, rho = dsd.core_exact_query(gg, h, q)
+        sel = mem.astype(bool)
+        assert sel[np.asarray(q)].all() and density_of(og, h, sel) == rho
+        x = int(core[np.asarray(q)].min())
+        rx = core >= x
+        assert density_of(og, h, rx) <= rho <= opt
+    assert dsd.core_exact_query(gg, h, [int(np.nonzero(opt_mem)[0][0])])[1] == opt
+
+
+def test_without_cliques_and_bad_arguments():
+    n = 30
+    s = np.arange(n - 1, dtype=np.int32)
+    g = dsd.build_csr(n, s, s + 1)
+    mem, rho = dsd.core_exact_query(g, 3, [4, 9])
+    assert rho == 0 and np.nonzero(mem)[0].tolist() == [4, 9]
+    for bad in ([], [n], [-1]):
+        with pytest.raises(dsd.DsdError) as e:
+            dsd.core_exact_query(g, 3, bad)
+        assert e.value.status == -1
