@@ -57,10 +57,12 @@ def _load():
     lib.orc_locate.argtypes = [P, C.c_int, u64p, u64, u64, u64, u64, u64, u64, i32p, i64]
     lib.orc_exact.argtypes = [P, C.c_int, C.c_int, u8p, u64, u64, i64]
     lib.orc_denser_than.argtypes = [P, C.c_int, C.c_uint64, C.c_uint64, u8p]
+    lib.orc_pattern_degrees.argtypes = [P, C.c_int, C.c_int, u64p, u64]
+    lib.orc_pattern_core.argtypes = [P, C.c_int, C.c_int, u64p, u64]
     lib.orc_exact_query.argtypes = [P, C.c_int, C.c_int32, i32p, u8p, u64, u64, i64]
     for f in ("orc_clique_degrees", "orc_clique_degree_of", "orc_core_decomposition",
               "orc_level_table", "orc_inc_app", "orc_core_app", "orc_peel_app", "orc_locate",
-              "orc_exact", "orc_denser_than", "orc_exact_query"):
+              "orc_exact", "orc_denser_than", "orc_exact_query", "orc_pattern_degrees", "orc_pattern_core"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -163,6 +165,19 @@ class Graph:
                                  C.byref(st), C.byref(bs)), "peel_app")
         return (mem[: self.n].astype(bool), Fraction(int(a.value), int(b.value)),
                 int(st.value), int(bs.value))
+
+    # -- special patterns (1 = x-star, 2 = 4-loop) -------------------------
+    def pattern_degrees(self, pattern: int, x: int = 0):
+        deg = np.zeros(max(1, self.n), dtype=np.uint64)
+        cnt = C.c_uint64()
+        _check(_lib.orc_pattern_degrees(self._p, int(pattern), int(x), deg, C.byref(cnt)), "pattern_degrees")
+        return deg[: self.n], int(cnt.value)
+
+    def pattern_core(self, pattern: int, x: int = 0):
+        core = np.zeros(max(1, self.n), dtype=np.uint64)
+        km = C.c_uint64()
+        _check(_lib.orc_pattern_core(self._p, int(pattern), int(x), core, C.byref(km)), "pattern_core")
+        return core[: self.n], int(km.value)
 
     # -- Pruning1/2 -----------------------------------------------------
     def locate(self, h: int, core):

@@ -750,6 +750,167 @@ int orc_peel_app(const orc_graph *g, int h, int rounds, uint8_t *member,
 }
 
 /* ------------------------------------------------------------------ */
+/* Special patterns (the appendix on core decomposition for special        */
+/* patterns).  An x-star (x >= 2) is a centre joined to x tails; a 4-loop  */
+/* is a cycle on four vertices (the appendix's "diamond": two 2-paths from */
+/* a vertex to the same 2-hop neighbour).  Instances are subgraphs, not    */
+/* necessarily induced.  Degrees and cores come from listing instances.    */
+/* ------------------------------------------------------------------ */
+
+#define ORC_STAR 1
+#define ORC_LOOP4 2
+
+typedef void (*pemit_fn)(void *ctx, const int32_t *mem, int size);
+
+/* every k-subset of cand[0..nc) after buf[0..np), emitted as buf[0..np+k) */
+static void subsets_rec(const int32_t *cand, int nc, int k, int start, int32_t *buf, int np, int depth,
+                        pemit_fn emit, void *ctx) {
+    if (depth == k) { emit(ctx, buf, np + k); return; }
+    for (int i = start; i <= nc - (k - depth); i++) {
+        buf[np + depth] = cand[i];
+        subsets_rec(cand, nc, k, i + 1, buf, np, depth + 1, emit, ctx);
+    }
+}
+
+static int is_alive(const uint8_t *alive, int32_t v) { return !alive || alive[v]; }
+
+/* x-stars containing v among alive vertices: v as the centre, or v as a
+ * tail of an alive neighbour c; each instance once (its centre is unique) */
+static void star_containing(const orc_graph *g, int x, int32_t v, const uint8_t *alive, int32_t *cand,
+                            int32_t *buf, pemit_fn emit, void *ctx) {
+    int nc = 0;
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++)
+        if (is_alive(alive, g->adj[e])) cand[nc++] = g->adj[e];
+    buf[0] = v;
+    subsets_rec(cand, nc, x, 0, buf, 1, 0, emit, ctx);
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+        int32_t c = g->adj[e];
+        if (!is_alive(alive, c)) continue;
+        int n2 = 0;
+        for (int64_t f = g->off[c]; f < g->off[c + 1]; f++)
+            if (g->adj[f] != v && is_alive(alive, g->adj[f])) cand[n2++] = g->adj[f];
+        buf[0] = c;
+        buf[1] = v;
+        subsets_rec(cand, n2, x - 1, 0, buf, 2, 0, emit, ctx);
+    }
+}
+
+/* 4-loops containing v among alive vertices: v's two loop neighbours a < b
+ * and the vertex w opposite v (a common neighbour of a and b); each once */
+static void loop4_containing(const orc_graph *g, int32_t v, const uint8_t *alive, int32_t *cand, int32_t *tmp,
+                             pemit_fn emit, void *ctx) {
+    int nc = 0;
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++)
+        if (is_alive(alive, g->adj[e])) cand[nc++] = g->adj[e];
+    for (int i = 0; i < nc; i++)
+        for (int j = i + 1; j < nc; j++) {
+            int32_t a = cand[i], b = cand[j];
+            int64_t k = intersect(g->adj + g->off[a], g->off[a + 1] - g->off[a], g->adj + g->off[b],
+                                  g->off[b + 1] - g->off[b], tmp);
+            for (int64_t t = 0; t < k; t++) {
+                int32_t w = tmp[t];
+                if (w == v || !is_alive(alive, w)) continue;
+                int32_t mem[4] = {v, a, w, b};
+                emit(ctx, mem, 4);
+            }
+        }
+}
+
+/* every instance of the pattern in g, each once */
+static void pattern_all(const orc_graph *g, int pattern, int x, int32_t *cand, int32_t *tmp, int32_t *buf,
+                        pemit_fn emit, void *ctx) {
+    for (int32_t v = 0; v < g->n; v++) {
+        if (pattern == ORC_STAR) {
+            int nc = 0;
+            for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) cand[nc++] = g->adj[e];
+            buf[0] = v;
+            subsets_rec(cand, nc, x, 0, buf, 1, 0, emit, ctx);      /* v as the centre */
+        } else {
+            /* loops whose smallest vertex is v: neighbours a < b above v, w above v */
+            int nc = 0;
+            for (int64_t e = g->off[v]; e < g->off[v + 1]; e++)
+                if (g->adj[e] > v) cand[nc++] = g->adj[e];
+            for (int i = 0; i < nc; i++)
+                for (int j = i + 1; j < nc; j++) {
+                    int32_t a = cand[i], b = cand[j];
+                    int64_t k = intersect(g->adj + g->off[a], g->off[a + 1] - g->off[a], g->adj + g->off[b],
+                                          g->off[b + 1] - g->off[b], tmp);
+                    for (int64_t t = 0; t < k; t++)
+                        if (tmp[t] > v) {
+                            int32_t mem[4] = {v, a, tmp[t], b};
+                            emit(ctx, mem, 4);
+                        }
+                }
+        }
+    }
+}
+
+static int pattern_args(const orc_graph *g, int pattern, int x) {
+    if (pattern == ORC_STAR) return (x >= 2 && x <= 8) ? ORC_OK : ORC_EINVAL;
+    if (pattern == ORC_LOOP4) return g ? ORC_OK : ORC_EINVAL;
+    return ORC_EINVAL;
+}
+
+typedef struct { int32_t *cand, *tmp, *buf; } pbufs;
+
+static int pbufs_init(pbufs *B, const orc_graph *g) {
+    int32_t d = max_degree(g) + 2;
+    B->cand = (int32_t *)malloc((size_t)d * sizeof(int32_t));
+    B->tmp = (int32_t *)malloc((size_t)d * sizeof(int32_t));
+    B->buf = (int32_t *)malloc((size_t)(ORC_HMAX + 2) * sizeof(int32_t));
+    return (B->cand && B->tmp && B->buf) ? ORC_OK : ORC_ENOMEM;
+}
+static void pbufs_free(pbufs *B) { free(B->cand); free(B->tmp); free(B->buf); }
+
+int orc_pattern_degrees(const orc_graph *g, int pattern, int x, uint64_t *deg, uint64_t *count) {
+    int rc = pattern_args(g, pattern, x);
+    if (rc) return rc;
+    for (int32_t v = 0; v < g->n; v++) deg[v] = 0;
+    degctx d = {deg, 0, 0};
+    pbufs B;
+    if (pbufs_init(&B, g)) { pbufs_free(&B); return ORC_ENOMEM; }
+    pattern_all(g, pattern, x, B.cand, B.tmp, B.buf, emit_degree, &d);
+    pbufs_free(&B);
+    if (d.overflow || d.mu > (u128)UINT64_MAX) return ORC_EOVERFLOW;
+    *count = (uint64_t)d.mu;
+    return ORC_OK;
+}
+
+/* Alg. 3 with pattern instances in place of cliques: pop the vertex of
+ * least pattern-degree, record it, and take one unit from every other
+ * member (of larger degree) of every instance through it among the
+ * remaining vertices. */
+int orc_pattern_core(const orc_graph *g, int pattern, int x, uint64_t *core, uint64_t *kmax) {
+    int32_t n = g->n;
+    uint64_t cnt;
+    uint64_t *deg = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+    uint8_t *alive = (uint8_t *)malloc((size_t)n + 1);
+    int32_t *hp = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *pos = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    pbufs B;
+    int rc = (deg && alive && hp && pos) ? pbufs_init(&B, g) : ORC_ENOMEM;
+    if (!rc) rc = orc_pattern_degrees(g, pattern, x, deg, &cnt);
+    if (rc) { free(deg); free(alive); free(hp); free(pos); pbufs_free(&B); return rc; }
+    iheap H = {deg, hp, pos, n};
+    for (int32_t v = 0; v < n; v++) { hp[v] = v; pos[v] = v; alive[v] = 1; }
+    for (int32_t i = n / 2 - 1; i >= 0; i--) hdown(&H, i);
+    peelctx pc = {deg, &H, -1};
+    uint64_t km = 0;
+    while (H.size > 0) {
+        int32_t v = hpop(&H);
+        core[v] = deg[v];
+        if (deg[v] > km) km = deg[v];
+        pc.v = v;
+        if (pattern == ORC_STAR) star_containing(g, x, v, alive, B.cand, B.buf, emit_peel, &pc);
+        else loop4_containing(g, v, alive, B.cand, B.tmp, emit_peel, &pc);
+        alive[v] = 0;
+    }
+    *kmax = km;
+    free(deg); free(alive); free(hp); free(pos); pbufs_free(&B);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Pruning1 / Pruning2 (Section 6.1)                                     */
 /* ------------------------------------------------------------------ */
 

@@ -92,6 +92,16 @@ int orc_core_app(const orc_graph *g, int h, int literal, int64_t w0,
 int orc_peel_app(const orc_graph *g, int h, int rounds, uint8_t *member,
                  uint64_t *num, uint64_t *den, int64_t *steps, int64_t *best_step);
 
+/* Special patterns (the appendix on core decomposition for special
+ * patterns): pattern 1 = x-star (a centre with x >= 2 tails, x <= 8),
+ * pattern 2 = 4-loop (a cycle on four vertices, the appendix's diamond;
+ * x ignored).  Instances are subgraphs, not necessarily induced.
+ * orc_pattern_degrees: deg[v] = instances containing v, *count = instances.
+ * orc_pattern_core: Alg. 3 over pattern instances; core[v], *kmax.
+ * Returns 0, -1 on bad arguments, -4 on overflow. */
+int orc_pattern_degrees(const orc_graph *g, int pattern, int x, uint64_t *deg, uint64_t *count);
+int orc_pattern_core(const orc_graph *g, int pattern, int x, uint64_t *core, uint64_t *kmax);
+
 /* Pruning1/2 (Section 6.1): rho' = max level density, k' = ceil(rho');
  * components of R_{k'}; rho'' = max component density; k'' = max(k', ceil(rho'')).
  * label[v] = component id (>= 0) for v in R_{k'}, -1 otherwise. */

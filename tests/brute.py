@@ -121,3 +121,54 @@ def multipartite_closed_form(parts, h):
             core[i] = k
             alive.remove(i)
     return deg, core
+
+
+def pattern_instances(n, edges, pattern, x=0, vertices=None):
+    """Instances of a special pattern as (members) tuples, by testing vertex
+    subsets: an x-star (pattern 1) is a centre adjacent to x other chosen
+    vertices; a 4-loop (pattern 2) is one of the three cyclic orders of a
+    4-set whose four edges all exist.  Subgraphs, not necessarily induced."""
+    adj = adjacency_sets(n, edges)
+    vs = sorted(range(n) if vertices is None else vertices)
+    out = []
+    if pattern == 1:
+        for S in itertools.combinations(vs, x + 1):
+            for c in S:
+                if all(u in adj[c] for u in S if u != c):
+                    out.append(S)
+    else:
+        for a, b, c, d in itertools.combinations(vs, 4):
+            for p, q, r, s in ((a, b, c, d), (a, b, d, c), (a, c, b, d)):
+                if q in adj[p] and r in adj[q] and s in adj[r] and p in adj[s]:
+                    out.append((a, b, c, d))
+    return out
+
+
+def pattern_degrees(n, edges, pattern, x=0, vertices=None):
+    deg = [0] * n
+    inst = pattern_instances(n, edges, pattern, x, vertices)
+    for S in inst:
+        for v in S:
+            deg[v] += 1
+    return deg, len(inst)
+
+
+def pattern_core_fixpoint(n, edges, pattern, x=0):
+    """core(v) = max k with v in the largest set whose every vertex lies in
+    >= k pattern instances inside it (recounted from scratch each pass)."""
+    core = [0] * n
+    k = 0
+    while True:
+        alive = set(range(n))
+        while True:
+            deg, _ = pattern_degrees(n, edges, pattern, x, alive)
+            drop = {v for v in alive if deg[v] < k}
+            if not drop:
+                break
+            alive -= drop
+        if not alive:
+            break
+        for v in alive:
+            core[v] = k
+        k += 1
+    return core

@@ -557,3 +557,68 @@ def test_query_without_cliques():
     g = G(6, [(i, i + 1) for i in range(5)])
     mem, rho, _ = g.exact_query(3, [2, 4])
     assert rho == 0 and members(mem) == [2, 4]
+
+
+# ------------------------------------------- special patterns: x-stars and 4-loops
+
+STAR, LOOP4 = 1, 2
+
+
+def _star_closed_form(n, edges, x):
+    """The appendix's star pattern-degree: C(y, x) for v as the centre plus
+    C(z_u - 1, x - 1) over its neighbours u as centres (y, z: degrees)."""
+    adj = brute.adjacency_sets(n, edges)
+    return [math.comb(len(adj[v]), x) + sum(math.comb(len(adj[u]) - 1, x - 1) for u in adj[v]) for v in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("pattern,x", [(STAR, 2), (STAR, 3), (STAR, 4), (LOOP4, 0)])
+def test_pattern_degrees_brute_force(seed, pattern, x):
+    n = 9
+    edges = brute.random_graph(n, 0.45, 1700 + seed)
+    deg, cnt = G(n, edges).pattern_degrees(pattern, x)
+    bdeg, bcnt = brute.pattern_degrees(n, edges, pattern, x)
+    assert deg.tolist() == bdeg and cnt == bcnt
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("x", [2, 3, 5])
+def test_star_degrees_closed_form(seed, x):
+    n, s, d = synth.chung_lu(n=400, avg_deg=8, beta=2.3, planted=1, plant_size=12, p=0.7, seed=seed)
+    g = oracle.Graph(n, s, d)
+    off, adj = g.adjacency()
+    edges = [(u, int(adj[e])) for u in range(n) for e in range(off[u], off[u + 1]) if u < adj[e]]
+    deg, cnt = g.pattern_degrees(STAR, x)
+    assert deg.tolist() == _star_closed_form(n, edges, x)
+    assert cnt * (x + 1) == int(deg.sum())
+
+
+@pytest.mark.parametrize("n", [4, 7, 10])
+def test_patterns_on_complete_and_bipartite_graphs(n):
+    kn = list(itertools.combinations(range(n), 2))
+    g = G(n, kn)
+    for x in (2, 3):
+        deg, _ = g.pattern_degrees(STAR, x)
+        assert (deg == math.comb(n - 1, x) + (n - 1) * math.comb(n - 2, x - 1)).all()
+        core, _ = g.pattern_core(STAR, x)
+        assert (core == deg).all()
+    deg, cnt = g.pattern_degrees(LOOP4)
+    assert cnt == 3 * math.comb(n, 4) and (deg == 3 * math.comb(n - 1, 3)).all()
+    # K_{a,b}: a vertex on the side of size a lies in (a - 1) C(b, 2) 4-loops
+    a, b = n, n + 2
+    kab = [(i, a + j) for i in range(a) for j in range(b)]
+    deg, cnt = G(a + b, kab).pattern_degrees(LOOP4)
+    assert cnt == math.comb(a, 2) * math.comb(b, 2)
+    assert (deg[:a] == (a - 1) * math.comb(b, 2)).all() and (deg[a:] == (b - 1) * math.comb(a, 2)).all()
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("pattern,x", [(STAR, 2), (STAR, 3), (LOOP4, 0)])
+def test_pattern_cores_match_fixpoint_definition(seed, pattern, x):
+    n = 9
+    edges = brute.random_graph(n, 0.5, 1900 + seed)
+    g = G(n, edges)
+    core, kmax = g.pattern_core(pattern, x)
+    assert core.tolist() == brute.pattern_core_fixpoint(n, edges, pattern, x)
+    deg, _ = g.pattern_degrees(pattern, x)
+    assert (core <= deg).all() and kmax == int(core.max())
