@@ -61,7 +61,7 @@ def k4_bytes(st: dict, h: int) -> float:
 
 
 # the peel's main kernel by the kind the library reports
-MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process"}
+MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process", 4: "k_star_front"}
 
 
 def main_kernel_bytes(st: dict) -> float:

@@ -81,7 +81,8 @@ typedef struct {
      * kernel it was is k4_main_kind:
      *   1  h = 2 edge pass: adjacency entries walked, frontier vertices;
      *   2  h = 3 triangle probe: out-list entries probed, neighbours expanded;
-     *   3  h = 3 triangle lists: list entries walked, arcs examined;
+     *   3  h = 3 triangle lists: pairs walked, row items;
+ *   4  x-star pattern frontier pass: adjacency entries walked, frontier vertices;
      *   0  none timed (h >= 4) */
     double k4_main_ms;
     uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
@@ -186,6 +187,32 @@ dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
  */
 dsd_status dsd_core_exact_query(dsd_graph g, int h, int32_t nq, const int32_t *q, int out_mem, uint8_t *member,
                                 dsd_rational *rho);
+
+/* ------------------------------------------------------------------ special patterns
+ *
+ * Pattern-degrees and (k, Psi)-cores for special patterns (the appendix on
+ * core decomposition for special patterns; the (k, Psi)-core of a pattern is
+ * the largest subgraph whose every vertex lies in >= k of its instances).
+ * Instances are subgraphs, not necessarily induced. */
+typedef enum {
+    DSD_PATTERN_STAR = 1   /* x-star: a centre joined to x tails, 2 <= x <= 8 */
+} dsd_pattern;
+
+/*
+ * deg[v] = x-star instances containing v (a pass over v's row:
+ * C(y, x) + sum over neighbours u of C(z_u - 1, x - 1), y and z_u degrees);
+ * *count = instances.  deg: length n, residency out_mem; count may be NULL.
+ * DSD_EINVAL for an unknown pattern or x outside [2, 8]; DSD_EOVERFLOW when a
+ * value could exceed 64 bits.
+ */
+dsd_status dsd_pattern_degrees(dsd_graph g, int pattern, int x, int out_mem, uint64_t *deg, uint64_t *count);
+
+/*
+ * core[v] = the pattern-core number of v (round-synchronous peel over the
+ * same closed form); *kmax = the largest.  core: length n, residency
+ * out_mem; kmax may be NULL.  Errors as dsd_pattern_degrees.
+ */
+dsd_status dsd_pattern_core(dsd_graph g, int pattern, int x, int out_mem, uint64_t *core, uint64_t *kmax);
 
 /* ------------------------------------------------------------------ batches
  *

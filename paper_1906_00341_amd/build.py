@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdsd.so")
-SOURCES = ["primitives.hip", "csr.hip", "enum.hip", "tlist.hip", "peel.hip", "cc.hip", "api.hip", "batch.hip", "flow.hip", "exact.cpp",
+SOURCES = ["primitives.hip", "csr.hip", "enum.hip", "tlist.hip", "peel.hip", "cc.hip", "api.hip", "pattern.hip", "batch.hip", "flow.hip", "exact.cpp",
            "server.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Werror=infinite-recursion", "-Werror=return-type",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -22,6 +22,15 @@
 // over its run of pairs before they reach its degree.  A row is cut into
 // items of TL_CHUNK pairs, so a hub's triangles spread over many waves.
 //
+// For an x-star pattern (the appendix on special patterns) a round works from
+// the closed form deg(w) = C(y_w, x) + sum over neighbours u of C(y_u - 1,
+// x - 1), y the residual degrees: after the frontier F leaves, a survivor w
+// loses C(y_w, x) - C(y'_w, x), C(y_f - 1, x - 1) for every neighbour f in
+// F, and C(y_u - 1, x - 1) - C(y'_u - 1, x - 1) for every surviving
+// neighbour u whose degree fell (primes: after the round).  k_star_front
+// walks the frontier's edges (degree drops, the middle term), k_star_touch
+// the rows of the survivors whose degree fell (the other two).
+//
 // A batch of graphs is peeled as one disjoint union in which every graph
 // keeps its own level k (GraphState): cliques never cross graphs, so each
 // graph's peel is exactly its own, and one round advances all of them.
@@ -57,6 +66,7 @@ struct PeelCtl {
     int64_t nW;        // wide (v, w) items of this round (h = 3)
     int32_t nT[2];     // row items of the frontier (triangle lists)
     int32_t pending;   // tail mode: a round has been started and not yet finished
+    int32_t nTouch;    // x-star pattern: survivors whose degree fell this round
     u64 work[2];       // main kernel's pairs and neighbours over the whole peel (when counted)
 };
 
@@ -103,6 +113,12 @@ struct PeelBufs {
     const int32_t *tpairs;
     int64_t *T;          // [2][tcap] row items (v << 32 | chunk) of frontier vertices
     int64_t tcap;
+    int32_t pattern;     // 0: cliques; 1: x-stars with px tails
+    int32_t px;
+    int32_t *ydeg;       // x-star: residual degree, now and at the start of the round
+    int32_t *yold;
+    int32_t *tround;     // x-star: round in which the vertex's degree last fell
+    int32_t *touch;      // x-star: this round's survivors whose degree fell
     int32_t count_work;  // the main kernel adds up its pairs and neighbours
     int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
 };
@@ -417,6 +433,7 @@ __device__ __forceinline__ void finish_global(PeelCtl *c) {
     c->nF[cur] = 0;
     c->nB[cur] = 0;
     c->nT[cur] = 0;
+    c->nTouch = 0;
     c->htop[cur] = 0;
     c->nW = 0;
     for (int i = 0; i < 8; i++) c->nitems[i] = 0;
@@ -918,6 +935,66 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
     if (b.count_work) add_work(b, wp, wn);
 }
 
+// ---------------------------------------------------------------- x-star pattern
+
+// C(n, k) for k <= 8 (the terms of a residual graph never exceed the
+// degrees the enumeration accepted without overflow)
+__device__ __forceinline__ u64 binom_small(int64_t n, int k) {
+    if (n < k || n < 0) return 0;
+    unsigned __int128 acc = 1;
+    for (int i = 1; i <= k; i++) acc = acc * (unsigned __int128)(n - k + i) / (unsigned __int128)i;
+    return (u64)acc;
+}
+
+// one wave per frontier vertex f: its surviving neighbours lose a unit of
+// degree and the stars centred at f that use them as tails
+__global__ __launch_bounds__(BLOCK) void k_star_front(PeelBufs b) {
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur, nF = c->nF[cur];
+    if (nF == 0) return;
+    const int32_t r = c->round;
+    const int32_t *F = b.F + (size_t)cur * b.n;
+    const int wv = threadIdx.x / WAVE;
+    u64 wp = 0, wn = 0;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nF; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t f = F[i];
+        const u64 tail = binom_small((int64_t)b.yold[f] - 1, b.px - 1);
+        for (int64_t e = b.row_ptr[f] + lane(); e < b.row_ptr[f + 1]; e += WAVE) {
+            const int32_t u = b.col[e];
+            if (b.stamp[u] <= r) continue;
+            atomicSub(&b.ydeg[u], 1);
+            if (atomicExch(&b.tround[u], r) != r) b.touch[atomicAdd(&c->nTouch, 1)] = u;
+            if (tail) dec_deg(b, u, tail, r);
+        }
+        wp += (u64)(b.row_ptr[f + 1] - b.row_ptr[f]);
+        wn += 1;
+    }
+    if (b.count_work) add_work(b, wp, wn);
+}
+
+// one wave per survivor u whose degree fell: its own centre term, and the
+// stars centred at u whose other tails remain
+__global__ __launch_bounds__(BLOCK) void k_star_touch(PeelBufs b) {
+    PeelCtl *c = b.ctl;
+    const int32_t nt = c->nTouch;
+    const int32_t r = c->round;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nt; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t u = b.touch[i];
+        const int32_t yo = b.yold[u], yn = b.ydeg[u];
+        const u64 own = binom_small(yo, b.px) - binom_small(yn, b.px);
+        const u64 two = binom_small((int64_t)yo - 1, b.px - 1) - binom_small((int64_t)yn - 1, b.px - 1);
+        if (lane() == 0 && own) dec_deg(b, u, own, r);
+        if (two)
+            for (int64_t e = b.row_ptr[u] + lane(); e < b.row_ptr[u + 1]; e += WAVE) {
+                const int32_t w = b.col[e];
+                if (b.stamp[w] > r) dec_deg(b, w, two, r);
+            }
+        __builtin_amdgcn_wave_barrier();
+        if (lane() == 0) b.yold[u] = yn;
+    }
+}
+
 // ---------------------------------------------------------------- h >= 4
 
 // Items (v, w): v in the frontier, w an allowed neighbour of v.  The engine
@@ -1086,6 +1163,16 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
 
 // ---------------------------------------------------------------- host driver
 
+// x-star pattern: residual degrees start as the degrees
+__global__ void k_star_init(PeelBufs b) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < b.n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = (int32_t)(b.row_ptr[v + 1] - b.row_ptr[v]);
+        b.ydeg[v] = d;
+        b.yold[v] = d;
+        b.tround[v] = -1;
+    }
+}
+
 __global__ void k_init_graphs(PeelBufs b, const u64 *mu, const int64_t *lv_base, u64 k_floor) {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= b.G) return;
@@ -1203,7 +1290,7 @@ static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
                 hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp, bool min_degree,
-                const TriList *tl) {
+                const TriList *tl, int star_x) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
@@ -1216,8 +1303,21 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.row_ptr = g.row_ptr;
     b.col = g.col;
     b.dag_off = g.dag_off;
-    b.count_work = kt != nullptr && h <= 3;
     b.minpeel = min_degree ? 1 : 0;
+    if (star_x > 0) {
+        // x-star pattern: no clique machinery (h is only the pattern's size)
+        b.pattern = 1;
+        b.px = star_x;
+        b.h = 0;
+        h = 2;
+        tl = nullptr;
+        b.ydeg = sc.get_n<int32_t>(n);
+        b.yold = sc.get_n<int32_t>(n);
+        b.tround = sc.get_n<int32_t>(n);
+        b.touch = sc.get_n<int32_t>(n);
+        k_star_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b);
+    }
+    b.count_work = kt != nullptr && h <= 3;
     b.ctl = sc.get_n<PeelCtl>(1);
     b.gs = sc.get_n<GraphState>(G);
     b.stamp = sc.get_n<int32_t>(n);
@@ -1313,7 +1413,10 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                 k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
                 if (listed) k_tl_items<<<gbuild, BLOCK, 0, s>>>(b);
             }
-            if (h == 2) {
+            if (b.pattern == 1) {
+                main_timer.launch(k_star_front, dim3(gq), dim3(BLOCK), s, b);
+                k_star_touch<<<gq, BLOCK, 0, s>>>(b);
+            } else if (h == 2) {
                 main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), s, b);
             } else if (listed) {
                 main_timer.launch(k_tl_process, dim3(gp), dim3(BLOCK), s, b);
@@ -1361,7 +1464,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         u64 launches = 0;
         kt->main_ms += main_timer.total_ms(&launches);
         kt->main_launches += launches;
-        if (h == 2) kt->main_kind = 1;
+        if (b.pattern == 1) kt->main_kind = 4;
+        else if (h == 2) kt->main_kind = 1;
         else if (h == 3) kt->main_kind = listed ? 3 : 2;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -32,6 +32,7 @@ OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT,
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
+           "dsd_pattern_degrees", "dsd_pattern_core",
            "dsd_last_stats",
            "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
            "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
@@ -105,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.dsd_peel_app.argtypes = [P, I, I, P, C.POINTER(Rational), C.POINTER(I64), C.POINTER(I64)]
     lib.dsd_core_exact.argtypes = [P, I, I, P, C.POINTER(Rational)]
     lib.dsd_core_exact_query.argtypes = [P, I, I32, P, I, P, C.POINTER(Rational)]
+    lib.dsd_pattern_degrees.argtypes = [P, I, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_pattern_core.argtypes = [P, I, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_last_stats.argtypes = [P, C.POINTER(Stats)]
     lib.dsd_batch_run.argtypes = [I32, C.POINTER(P), C.POINTER(I), I, I, C.POINTER(P), C.POINTER(Result)]
     lib.dsd_server_create.argtypes = [C.c_size_t, I, C.POINTER(P)]
@@ -259,6 +262,27 @@ def core_exact_query(g: Graph, h: int, q, out=None):
     _check(_lib.dsd_core_exact_query(g.handle, int(h), int(q.size), q.ctypes.data_as(C.c_void_p), mem, p,
                                      C.byref(r)))
     return (out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den)
+
+
+PATTERN_STAR = 1
+
+
+def pattern_degrees(g: Graph, pattern: int, x: int, out=None):
+    """dsd_pattern_degrees -> (deg[n], instances)."""
+    out, p, mem = _out_u64(g, out)
+    cnt = C.c_uint64()
+    _check(_lib.dsd_pattern_degrees(g.handle, int(pattern), int(x), mem, p, C.byref(cnt)))
+    n, _ = g.info()
+    return out[:n] if isinstance(out, np.ndarray) else out, int(cnt.value)
+
+
+def pattern_core(g: Graph, pattern: int, x: int, out=None):
+    """dsd_pattern_core -> (core[n], kmax)."""
+    out, p, mem = _out_u64(g, out)
+    km = C.c_uint64()
+    _check(_lib.dsd_pattern_core(g.handle, int(pattern), int(x), mem, p, C.byref(km)))
+    n, _ = g.info()
+    return out[:n] if isinstance(out, np.ndarray) else out, int(km.value)
 
 
 def status_str(s: int) -> str:

@@ -1,0 +1,96 @@
+"""GPU parity of the special-pattern cores (x-stars, the appendix on core
+decomposition for special patterns) through the C ABI against the oracle,
+which lists every star instance.  Pattern-degrees, core numbers and k_max
+must match exactly."""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_00341_amd import dsd, synth
+
+pytestmark = pytest.mark.gpu
+STAR = 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    dsd.load()          # fails loudly when the library is missing
+
+
+def check(n, s, d, xs):
+    s = np.ascontiguousarray(s, np.int32)
+    d = np.ascontiguousarray(d, np.int32)
+    og, gg = oracle.Graph(n, s, d), dsd.build_csr(n, s, d)
+    for x in xs:
+        deg_o, cnt_o = og.pattern_degrees(STAR, x)
+        deg_g, cnt_g = dsd.pattern_degrees(gg, STAR, x)
+        assert cnt_g == cnt_o
+        np.testing.assert_array_equal(deg_g, deg_o)
+        core_o, km_o = og.pattern_core(STAR, x)
+        core_g, km_g = dsd.pattern_core(gg, STAR, x)
+        assert km_g == km_o
+        np.testing.assert_array_equal(core_g, core_o)
+    return gg
+
+
+@pytest.mark.parametrize("name", ["F1", "F2", "F4"])
+def test_paper_examples(fixtures, name):
+    f = fixtures[name]
+    e = np.asarray(f["edges"], np.int32)
+    check(f["n"], e[:, 0], e[:, 1], (2, 3, 4))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_small(seed):
+    rng = np.random.default_rng(2100 + seed)
+    n = 60
+    pairs = [(u, v) for u, v in itertools.combinations(range(n), 2) if rng.random() < 0.15]
+    e = np.asarray(pairs, np.int32)
+    check(n, e[:, 0], e[:, 1], (2, 3, 5))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 12])
+def test_complete_and_tiny(n):
+    e = np.asarray(list(itertools.combinations(range(n), 2)) or np.zeros((0, 2)), np.int32).reshape(-1, 2)
+    check(n, e[:, 0], e[:, 1], (2, 3))
+
+
+def test_complete_bipartite():
+    a, b = 30, 45
+    e = np.asarray([(i, a + j) for i in range(a) for j in range(b)], np.int32)
+    gg = check(a + b, e[:, 0], e[:, 1], (2, 3, 4))
+    deg, _ = dsd.pattern_degrees(gg, STAR, 3)
+    assert (deg[:a] == math.comb(b, 3) + b * math.comb(a - 1, 2)).all()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_er_planted_config(seed):
+    n, s, d = synth.er_planted(seed=seed)
+    check(n, s, d, (2, 3, 4))
+
+
+def test_chung_lu_hubs():
+    # hubs of degree ~600: many survivors lose stars through a 2-hop neighbour
+    n, s, d = synth.chung_lu(n=30000, avg_deg=12, beta=2.1, planted=2, plant_size=60, p=0.7, seed=1)
+    check(n, s, d, (2,))
+    n, s, d = synth.chung_lu(n=5000, avg_deg=10, beta=2.4, planted=1, plant_size=40, p=0.7, seed=2)
+    check(n, s, d, (3,))
+
+
+def test_device_buffers_and_bad_arguments():
+    torch = pytest.importorskip("torch")
+    n, s, d = synth.er_planted(seed=4)
+    og = oracle.Graph(n, s, d)
+    g = dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    out = torch.zeros(n, dtype=torch.uint64, device="cuda")
+    dsd.pattern_core(g, STAR, 2, out=out)
+    np.testing.assert_array_equal(out.cpu().numpy(), og.pattern_core(STAR, 2)[0])
+    for pattern, x in ((STAR, 1), (STAR, 9), (7, 2)):
+        with pytest.raises(dsd.DsdError) as e:
+            dsd.pattern_degrees(g, pattern, x)
+        assert e.value.status == -1
