@@ -195,15 +195,20 @@ dsd_status dsd_core_exact_query(dsd_graph g, int h, int32_t nq, const int32_t *q
  * the largest subgraph whose every vertex lies in >= k of its instances).
  * Instances are subgraphs, not necessarily induced. */
 typedef enum {
-    DSD_PATTERN_STAR = 1   /* x-star: a centre joined to x tails, 2 <= x <= 8 */
+    DSD_PATTERN_STAR = 1,  /* x-star: a centre joined to x tails, 2 <= x <= 8 */
+    DSD_PATTERN_LOOP4 = 2  /* 4-loop: a cycle on four vertices (the appendix's
+                              diamond: two 2-paths from a vertex to one other); x ignored */
 } dsd_pattern;
 
 /*
- * deg[v] = x-star instances containing v (a pass over v's row:
- * C(y, x) + sum over neighbours u of C(z_u - 1, x - 1), y and z_u degrees);
- * *count = instances.  deg: length n, residency out_mem; count may be NULL.
- * DSD_EINVAL for an unknown pattern or x outside [2, 8]; DSD_EOVERFLOW when a
- * value could exceed 64 bits.
+ * deg[v] = pattern instances containing v; *count = instances.  x-stars: a
+ * pass over v's row, C(y, x) + sum over neighbours u of C(z_u - 1, x - 1)
+ * (y, z_u degrees).  4-loops: sum over the vertices w two steps away of
+ * C(c, 2), c the 2-paths from v to w, grouped in a table of v's 2-hop
+ * neighbours.  deg: length n, residency out_mem; count may be NULL.
+ * DSD_EINVAL for an unknown pattern or x outside [2, 8] (x-stars);
+ * DSD_EOVERFLOW when a value could exceed 64 bits; DSD_EUNSUPPORTED when a
+ * vertex's neighbours' degrees sum past 2^25 (4-loop tables).
  */
 dsd_status dsd_pattern_degrees(dsd_graph g, int pattern, int x, int out_mem, uint64_t *deg, uint64_t *count);
 

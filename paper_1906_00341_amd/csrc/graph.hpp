@@ -37,7 +37,7 @@ struct KernelTimes {
     // (h = 3) or frontier vertices (h = 2)
     double main_ms = 0;
     u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
-    int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass
+    int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----
@@ -103,16 +103,21 @@ struct PeelResult {
 // before that round (entry j of a graph is round j).
 // tl (h = 3, nullable): the graph's triangle lists; the rounds then walk the
 // removed vertices' rows of triangles instead of intersecting neighbourhoods.
-// star_x > 0: peel x-star pattern-degrees instead (deg: the pattern-degrees
-// of the whole graph; alive0 must be nullptr; h, tl and min_degree unused).
+// pattern 1 (x-stars with px tails) or 2 (4-loops): peel pattern-degrees
+// instead (deg: the pattern-degrees of the whole graph; alive0 must be
+// nullptr; h, tl and min_degree unused).  Throws Error(-5) when a 2-hop
+// neighbourhood is too large for the 4-loop tables.
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
                 hipStream_t s, Scratch &sc, KernelTimes *kt = nullptr, const PeelGroups *grp = nullptr,
-                bool min_degree = false, const TriList *tl = nullptr, int star_x = 0);
+                bool min_degree = false, const TriList *tl = nullptr, int pattern = 0, int px = 0);
 
 // ---- special patterns ----
 // deg[r] = x-star pattern-degree of r (closed form of the appendix on special
 // patterns); false if a value could exceed 64 bits
 bool star_degrees(const DevGraph &g, int x, u64 *deg, hipStream_t s, Scratch &sc);
+// deg[r] = 4-loops through r (one workgroup per vertex with a table of its
+// 2-hop neighbours); throws Error(-5) when a table would be too large
+void loop4_degrees(const DevGraph &g, u64 *deg, hipStream_t s, Scratch &sc);
 
 // ---- K5: connected components of the subgraph induced by mask ----
 // label[r] = smallest rank of r's component for r in mask, -1 outside.

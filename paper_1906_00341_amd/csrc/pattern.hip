@@ -1,11 +1,17 @@
 // Special patterns (the appendix on core decomposition for special
-// patterns): pattern-degrees and (k, Psi)-cores for x-stars.
+// patterns): pattern-degrees and (k, Psi)-cores for x-stars and 4-loops.
 //
 // An x-star is a centre joined to x tails (x >= 2).  A vertex v with y
 // neighbours is the centre of C(y, x) of them and a tail of C(z_u - 1, x - 1)
 // stars centred at each neighbour u of degree z_u, so its pattern-degree is a
 // pass over its row: no instance is ever listed.  The peel removes the
 // frontier and updates the same closed form (peel.hip).
+//
+// A 4-loop (the appendix's diamond) through v consists of two 2-paths from v
+// to one vertex w: v lies in C(c, 2) loops opposite w when c of its
+// neighbours are also w's.  Its pattern-degree and its peel group the 2-paths
+// of a vertex by their end w in a table of the vertex's workgroup
+// (peel.hip).
 #include "handle.hpp"
 
 namespace dsd {
@@ -68,8 +74,12 @@ bool star_degrees(const DevGraph &g, int x, u64 *deg, hipStream_t s, Scratch &sc
 // pattern-degrees of the whole graph and their instance count
 static u64 pattern_degrees_run(dsd_graph_s *G, int pattern, int x, u64 *d) {
     hipStream_t s = G->stream;
-    if (pattern != DSD_PATTERN_STAR) throw Error(DSD_EUNSUPPORTED, "pattern not supported");
-    if (!star_degrees(G->g, x, d, s, G->sc)) throw Error(DSD_EOVERFLOW, "pattern-degrees could exceed 64 bits");
+    if (pattern == DSD_PATTERN_STAR) {
+        if (!star_degrees(G->g, x, d, s, G->sc)) throw Error(DSD_EOVERFLOW, "pattern-degrees could exceed 64 bits");
+    } else {
+        loop4_degrees(G->g, d, s, G->sc);
+        x = 3;                           // four vertices per instance
+    }
     u64 *sum = G->sc.get_n<u64>(2);
     sum_u64_128(d, G->g.n, sum, s, G->sc);
     u64 hs[2];
@@ -85,6 +95,7 @@ static void check_pattern(int pattern, int x) {
         if (x < 2 || x > 8) throw Error(DSD_EINVAL, "an x-star needs 2 <= x <= 8 tails");
         return;
     }
+    if (pattern == DSD_PATTERN_LOOP4) return;
     throw Error(DSD_EINVAL, "unknown pattern");
 }
 
@@ -134,7 +145,9 @@ dsd_status dsd_pattern_core(dsd_graph G, int pattern, int x, int out_mem, uint64
             G->stats.num_cliques = mu;
             Timer tp(s);
             if (mu > 0) {
-                PeelResult pr = peel(G->g, x + 1, nullptr, d, mu, 0, c, s, G->sc, &kt, nullptr, false, nullptr, x);
+                const int size = pattern == DSD_PATTERN_STAR ? x + 1 : 4;
+                PeelResult pr = peel(G->g, size, nullptr, d, mu, 0, c, s, G->sc, &kt, nullptr, false, nullptr,
+                                     pattern, x);
                 G->stats.peel_rounds = pr.rounds;
                 G->stats.peel_levels = pr.levels;
                 km = pr.kmax;

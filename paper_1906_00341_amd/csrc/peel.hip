@@ -31,6 +31,13 @@
 // walks the frontier's edges (degree drops, the middle term), k_star_touch
 // the rows of the survivors whose degree fell (the other two).
 //
+// For the 4-loop pattern (a cycle on four vertices; the appendix's diamond,
+// two 2-paths from a vertex to the same vertex) a round takes one workgroup
+// per frontier vertex v: its 2-hop neighbours w are counted in a hash of
+// the workgroup's own (the common neighbours through which v reaches w),
+// each group of c 2-paths holds C(c, 2) loops, and under the owner rule v
+// destroys them: w loses C(c, 2), every middle vertex c - 1.
+//
 // A batch of graphs is peeled as one disjoint union in which every graph
 // keeps its own level k (GraphState): cliques never cross graphs, so each
 // graph's peel is exactly its own, and one round advances all of them.
@@ -113,12 +120,15 @@ struct PeelBufs {
     const int32_t *tpairs;
     int64_t *T;          // [2][tcap] row items (v << 32 | chunk) of frontier vertices
     int64_t tcap;
-    int32_t pattern;     // 0: cliques; 1: x-stars with px tails
+    int32_t pattern;     // 0: cliques; 1: x-stars with px tails; 2: 4-loops
     int32_t px;
     int32_t *ydeg;       // x-star: residual degree, now and at the start of the round
     int32_t *yold;
     int32_t *tround;     // x-star: round in which the vertex's degree last fell
     int32_t *touch;      // x-star: this round's survivors whose degree fell
+    int32_t *lkey;       // 4-loop: [blocks][lsize] hash of a frontier vertex's 2-hop neighbours
+    uint32_t *lval;
+    int64_t lsize;
     int32_t count_work;  // the main kernel adds up its pairs and neighbours
     int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
 };
@@ -995,6 +1005,217 @@ __global__ __launch_bounds__(BLOCK) void k_star_touch(PeelBufs b) {
     }
 }
 
+// ---------------------------------------------------------------- 4-loop pattern
+
+constexpr int LOOP_EMPTY = -1;
+
+__device__ __forceinline__ uint32_t loop_slot(int32_t w, uint32_t mask) {
+    return (uint32_t)(((u64)((uint32_t)w * 2654435761u) * (mask + 1ull)) >> 32) & mask;
+}
+
+// add one 2-path to w's count (the table is never more than half full)
+__device__ __forceinline__ void loop_add(int32_t *keys, uint32_t *vals, uint32_t mask, int32_t w) {
+    uint32_t slot = loop_slot(w, mask);
+    while (true) {
+        const int32_t k = keys[slot];
+        if (k == w) break;
+        if (k == LOOP_EMPTY) {
+            const int32_t prev = atomicCAS(&keys[slot], LOOP_EMPTY, w);
+            if (prev == LOOP_EMPTY || prev == w) break;
+            continue;          // another thread took the slot: look at it again
+        }
+        slot = (slot + 1) & mask;
+    }
+    atomicAdd(&vals[slot], 1u);
+}
+
+__device__ __forceinline__ uint32_t loop_get(const int32_t *keys, const uint32_t *vals, uint32_t mask, int32_t w) {
+    uint32_t slot = loop_slot(w, mask);
+    while (true) {
+        const int32_t k = keys[slot];
+        if (k == w) return vals[slot];
+        if (k == LOOP_EMPTY) return 0;
+        slot = (slot + 1) & mask;
+    }
+}
+
+// The 2-paths v - a - w of one workgroup, flattened over its threads 256
+// middles a at a time: fn(i, a, w) for every neighbour a of v (i its index in
+// the chunk, from sA) with keep_a(a), and every neighbour w != v of a with
+// keep_w(w).  after_chunk(n) runs once the chunk's pairs are done (all
+// threads, n middles in sA).
+template <class KA, class KW, class FN, class AC>
+__device__ __forceinline__ void loop_two_paths(const int64_t *row_ptr, const int32_t *col, int32_t v, KA keep_a,
+                                               KW keep_w, FN fn, AC after_chunk, int32_t *sA, int64_t *sSt,
+                                               int32_t *sPre, int32_t *wtmp) {
+    const int64_t r0 = row_ptr[v], r1 = row_ptr[v + 1];
+    for (int64_t base = r0; base < r1; base += BLOCK) {
+        const int64_t e = base + threadIdx.x;
+        int32_t a = -1, len = 0;
+        int64_t st0 = 0;
+        if (e < r1) {
+            a = col[e];
+            if (keep_a(a)) {
+                st0 = row_ptr[a];
+                len = (int32_t)(row_ptr[a + 1] - st0);
+            }
+        }
+        sA[threadIdx.x] = a;
+        sSt[threadIdx.x] = st0;
+        sPre[threadIdx.x] = len;
+        __syncthreads();
+        const int cnt = (int)min((int64_t)BLOCK, r1 - base);
+        const int32_t total = block_incl_scan_lds(sPre, cnt, wtmp);
+        for (int32_t p = threadIdx.x; p < total; p += BLOCK) {
+            const int i = upper_bound_i32(sPre, cnt, p);
+            const int32_t o = p - (i ? sPre[i - 1] : 0);
+            const int32_t w = col[sSt[i] + o];
+            if (w != v && keep_w(w)) fn(i, sA[i], w);
+        }
+        __syncthreads();
+        after_chunk(cnt);
+        __syncthreads();
+    }
+}
+
+// bound on a vertex's 2-hop table: the degrees of its neighbours
+__global__ void k_loop_bound(const int64_t *row_ptr, const int32_t *col, int32_t n, unsigned long long *mx) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        u64 sum = 0;
+        for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) {
+            const int32_t a = col[e];
+            sum += (u64)(row_ptr[a + 1] - row_ptr[a]);
+        }
+        sum = wave_sum(sum);
+        if (lane() == 0 && sum) atomicMax(mx, (unsigned long long)sum);
+    }
+}
+
+// the table of a workgroup for vertex v: the smallest power of two >= 2 *
+// (bound), cleared
+__device__ __forceinline__ uint32_t loop_table(const int64_t *row_ptr, const int32_t *col, int32_t v,
+                                               int32_t *keys, uint32_t *vals, int64_t lsize, u64 *sRed) {
+    u64 sum = 0;
+    for (int64_t e = row_ptr[v] + threadIdx.x; e < row_ptr[v + 1]; e += BLOCK) {
+        const int32_t a = col[e];
+        sum += (u64)(row_ptr[a + 1] - row_ptr[a]);
+    }
+    sum = wave_sum(sum);
+    if (lane() == 0) sRed[threadIdx.x / WAVE] = sum;
+    __syncthreads();
+    u64 tot = 0;
+    for (int i = 0; i < WAVES_PER_BLOCK; i++) tot += sRed[i];
+    int64_t size = 2;
+    while (size < 2 * (int64_t)tot) size <<= 1;
+    if (size > lsize) size = lsize;                  // never: lsize covers the graph's largest bound
+    for (int64_t i = threadIdx.x; i < size; i += BLOCK) {
+        keys[i] = LOOP_EMPTY;
+        vals[i] = 0;
+    }
+    __syncthreads();
+    return (uint32_t)(size - 1);
+}
+
+// 4-loop pattern-degrees: deg(v) = sum over w of C(2-paths v - . - w, 2);
+// one workgroup per vertex, the table in its slice of keys/vals
+__global__ __launch_bounds__(BLOCK) void k_loop_degrees(const int64_t *row_ptr, const int32_t *col, int32_t n,
+                                                         int32_t *lkey, uint32_t *lval, int64_t lsize, u64 *deg) {
+    __shared__ int32_t sA[BLOCK];
+    __shared__ int64_t sSt[BLOCK];
+    __shared__ int32_t sPre[BLOCK];
+    __shared__ int32_t wtmp[WAVES_PER_BLOCK];
+    __shared__ u64 sRed[WAVES_PER_BLOCK];
+    int32_t *keys = lkey + (size_t)blockIdx.x * lsize;
+    uint32_t *vals = lval + (size_t)blockIdx.x * lsize;
+    for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+        const uint32_t mask = loop_table(row_ptr, col, (int32_t)v, keys, vals, lsize, sRed);
+        loop_two_paths(
+            row_ptr, col, (int32_t)v, [](int32_t) { return true; }, [](int32_t) { return true; },
+            [&](int, int32_t, int32_t w) { loop_add(keys, vals, mask, w); }, [](int) {}, sA, sSt, sPre, wtmp);
+        u64 c = 0;
+        for (uint32_t i = threadIdx.x; i <= mask; i += BLOCK) {
+            const u64 y = vals[i];
+            c += y * (y - (y ? 1 : 0)) / 2;
+        }
+        c = wave_sum(c);
+        __syncthreads();
+        if (lane() == 0) sRed[threadIdx.x / WAVE] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 t = 0;
+            for (int i = 0; i < WAVES_PER_BLOCK; i++) t += sRed[i];
+            deg[v] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per frontier vertex v: the loops v - a - w - b whose other
+// members may share a clique with v this round (the owner rule) are
+// destroyed; w loses C(c, 2) and each middle a loses c - 1 per group of c
+// 2-paths to w.
+__global__ __launch_bounds__(BLOCK) void k_loop_process(PeelBufs b) {
+    __shared__ int32_t sA[BLOCK];
+    __shared__ int64_t sSt[BLOCK];
+    __shared__ int32_t sPre[BLOCK];
+    __shared__ int32_t wtmp[WAVES_PER_BLOCK];
+    __shared__ u64 sRed[WAVES_PER_BLOCK];
+    __shared__ u64 sLoss[BLOCK];
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur, nF = c->nF[cur];
+    if (nF == 0) return;
+    const int32_t r = c->round;
+    const int32_t *F = b.F + (size_t)cur * b.n;
+    int32_t *keys = b.lkey + (size_t)blockIdx.x * b.lsize;
+    uint32_t *vals = b.lval + (size_t)blockIdx.x * b.lsize;
+    for (int64_t fi = blockIdx.x; fi < nF; fi += gridDim.x) {
+        const int32_t v = F[fi];
+        const uint32_t mask = loop_table(b.row_ptr, b.col, v, keys, vals, b.lsize, sRed);
+        auto ok = [&](int32_t x) { return allowed(b.stamp[x], r, x, v); };
+        loop_two_paths(
+            b.row_ptr, b.col, v, ok, ok, [&](int, int32_t, int32_t w) { loop_add(keys, vals, mask, w); },
+            [](int) {}, sA, sSt, sPre, wtmp);
+        // opposite vertices
+        u64 destroyed = 0;
+        for (uint32_t i = threadIdx.x; i <= mask; i += BLOCK) {
+            const int32_t w = keys[i];
+            const u64 y = vals[i];
+            if (w == LOOP_EMPTY || y < 2) continue;
+            const u64 t = y * (y - 1) / 2;
+            destroyed += t;
+            if (b.stamp[w] > r) dec_deg(b, w, t, r);
+        }
+        // middle vertices: c - 1 per 2-path, summed per middle over its chunk
+        for (int i = threadIdx.x; i < BLOCK; i += BLOCK) sLoss[i] = 0;
+        __syncthreads();
+        loop_two_paths(
+            b.row_ptr, b.col, v, ok, ok,
+            [&](int i, int32_t, int32_t w) {
+                const u64 y = loop_get(keys, vals, mask, w);
+                if (y > 1) atomicAdd(&sLoss[i], y - 1);
+            },
+            [&](int cnt) {
+                for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+                    const u64 l = sLoss[i];
+                    const int32_t a = sA[i];
+                    if (l && b.stamp[a] > r) dec_deg(b, a, l, r);
+                    sLoss[i] = 0;
+                }
+            },
+            sA, sSt, sPre, wtmp);
+        destroyed = wave_sum(destroyed);
+        if (lane() == 0) sRed[threadIdx.x / WAVE] = destroyed;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 t = 0;
+            for (int i = 0; i < WAVES_PER_BLOCK; i++) t += sRed[i];
+            add_destroyed(b, v, t);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- h >= 4
 
 // Items (v, w): v in the frontier, w an allowed neighbour of v.  The engine
@@ -1163,6 +1384,36 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
 
 // ---------------------------------------------------------------- host driver
 
+// 4-loop tables: slots per workgroup (a power of two, twice the largest
+// 2-hop bound of the graph) and the number of workgroups that fit in
+// LOOP_TABLE_SLOTS slots in all
+constexpr int64_t LOOP_TABLE_SLOTS = (int64_t)1 << 28;   // 2 GiB of keys and counts
+constexpr int64_t LOOP_MAX_SLOTS = (int64_t)1 << 26;
+
+static int64_t loop_tables(const DevGraph &g, int *groups, hipStream_t s, Scratch &sc) {
+    unsigned long long *mx = sc.get_n<unsigned long long>(1);
+    fill_u64((u64 *)mx, 0, 1, s);
+    if (g.n > 0) k_loop_bound<<<grid_for(g.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, g.n, mx);
+    unsigned long long bound = 0;
+    DSD_HIP(hipMemcpyAsync(&bound, mx, sizeof(bound), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    int64_t size = 2;
+    while (size < 2 * (int64_t)bound) size <<= 1;
+    if (size > LOOP_MAX_SLOTS)
+        throw Error(-5, "a 2-hop neighbourhood is too large for the 4-loop tables");
+    *groups = (int)std::min<int64_t>(512, std::max<int64_t>(1, LOOP_TABLE_SLOTS / size));
+    return size;
+}
+
+void loop4_degrees(const DevGraph &g, u64 *deg, hipStream_t s, Scratch &sc) {
+    if (g.n == 0) return;
+    int groups = 0;
+    const int64_t size = loop_tables(g, &groups, s, sc);
+    int32_t *keys = sc.get_n<int32_t>((int64_t)groups * size);
+    uint32_t *vals = sc.get_n<uint32_t>((int64_t)groups * size);
+    k_loop_degrees<<<groups, BLOCK, 0, s>>>(g.row_ptr, g.col, g.n, keys, vals, size, deg);
+}
+
 // x-star pattern: residual degrees start as the degrees
 __global__ void k_star_init(PeelBufs b) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < b.n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -1290,7 +1541,7 @@ static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
                 hipStream_t s, Scratch &sc, KernelTimes *kt, const PeelGroups *grp, bool min_degree,
-                const TriList *tl, int star_x) {
+                const TriList *tl, int pattern, int px) {
     PeelResult res;
     const int32_t n = g.n;
     if (n == 0) return res;
@@ -1304,18 +1555,25 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     b.col = g.col;
     b.dag_off = g.dag_off;
     b.minpeel = min_degree ? 1 : 0;
-    if (star_x > 0) {
-        // x-star pattern: no clique machinery (h is only the pattern's size)
-        b.pattern = 1;
-        b.px = star_x;
+    int gloop = 0;
+    if (pattern != 0) {
+        // special patterns: no clique machinery (h is only the pattern's size)
+        b.pattern = pattern;
+        b.px = px;
         b.h = 0;
         h = 2;
         tl = nullptr;
-        b.ydeg = sc.get_n<int32_t>(n);
-        b.yold = sc.get_n<int32_t>(n);
-        b.tround = sc.get_n<int32_t>(n);
-        b.touch = sc.get_n<int32_t>(n);
-        k_star_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b);
+        if (pattern == 1) {
+            b.ydeg = sc.get_n<int32_t>(n);
+            b.yold = sc.get_n<int32_t>(n);
+            b.tround = sc.get_n<int32_t>(n);
+            b.touch = sc.get_n<int32_t>(n);
+            k_star_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b);
+        } else {
+            b.lsize = loop_tables(g, &gloop, s, sc);
+            b.lkey = sc.get_n<int32_t>((int64_t)gloop * b.lsize);
+            b.lval = sc.get_n<uint32_t>((int64_t)gloop * b.lsize);
+        }
     }
     b.count_work = kt != nullptr && h <= 3;
     b.ctl = sc.get_n<PeelCtl>(1);
@@ -1416,6 +1674,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             if (b.pattern == 1) {
                 main_timer.launch(k_star_front, dim3(gq), dim3(BLOCK), s, b);
                 k_star_touch<<<gq, BLOCK, 0, s>>>(b);
+            } else if (b.pattern == 2) {
+                main_timer.launch(k_loop_process, dim3(gloop), dim3(BLOCK), s, b);
             } else if (h == 2) {
                 main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), s, b);
             } else if (listed) {
@@ -1465,6 +1725,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         kt->main_ms += main_timer.total_ms(&launches);
         kt->main_launches += launches;
         if (b.pattern == 1) kt->main_kind = 4;
+        else if (b.pattern == 2) kt->main_kind = 5;
         else if (h == 2) kt->main_kind = 1;
         else if (h == 3) kt->main_kind = listed ? 3 : 2;
         (void)hipEventDestroy(e0);

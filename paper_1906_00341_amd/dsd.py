@@ -264,7 +264,7 @@ def core_exact_query(g: Graph, h: int, q, out=None):
     return (out[:n] if isinstance(out, np.ndarray) else out), Fraction(r.num, r.den)
 
 
-PATTERN_STAR = 1
+PATTERN_STAR, PATTERN_LOOP4 = 1, 2
 
 
 def pattern_degrees(g: Graph, pattern: int, x: int, out=None):

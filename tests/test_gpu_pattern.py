@@ -94,3 +94,66 @@ def test_device_buffers_and_bad_arguments():
         with pytest.raises(dsd.DsdError) as e:
             dsd.pattern_degrees(g, pattern, x)
         assert e.value.status == -1
+
+
+# ------------------------------------------------------------------ 4-loops
+
+LOOP4 = 2
+
+
+def check_loop(n, s, d):
+    s = np.ascontiguousarray(s, np.int32)
+    d = np.ascontiguousarray(d, np.int32)
+    og, gg = oracle.Graph(n, s, d), dsd.build_csr(n, s, d)
+    deg_o, cnt_o = og.pattern_degrees(LOOP4)
+    deg_g, cnt_g = dsd.pattern_degrees(gg, LOOP4, 0)
+    assert cnt_g == cnt_o
+    np.testing.assert_array_equal(deg_g, deg_o)
+    core_o, km_o = og.pattern_core(LOOP4)
+    core_g, km_g = dsd.pattern_core(gg, LOOP4, 0)
+    assert km_g == km_o
+    np.testing.assert_array_equal(core_g, core_o)
+    return gg
+
+
+@pytest.mark.parametrize("name", ["F1", "F2", "F4"])
+def test_loop_paper_examples(fixtures, name):
+    f = fixtures[name]
+    e = np.asarray(f["edges"], np.int32)
+    check_loop(f["n"], e[:, 0], e[:, 1])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_loop_random_small(seed):
+    rng = np.random.default_rng(2300 + seed)
+    n = 50
+    pairs = [(u, v) for u, v in itertools.combinations(range(n), 2) if rng.random() < 0.2]
+    e = np.asarray(pairs, np.int32)
+    check_loop(n, e[:, 0], e[:, 1])
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 9])
+def test_loop_complete_and_tiny(n):
+    e = np.asarray(list(itertools.combinations(range(n), 2)) or np.zeros((0, 2)), np.int32).reshape(-1, 2)
+    gg = check_loop(n, e[:, 0], e[:, 1])
+    if n >= 4:
+        assert (dsd.pattern_degrees(gg, LOOP4, 0)[0] == 3 * math.comb(n - 1, 3)).all()
+
+
+def test_loop_complete_bipartite():
+    a, b = 25, 40
+    e = np.asarray([(i, a + j) for i in range(a) for j in range(b)], np.int32)
+    gg = check_loop(a + b, e[:, 0], e[:, 1])
+    deg, cnt = dsd.pattern_degrees(gg, LOOP4, 0)
+    assert cnt == math.comb(a, 2) * math.comb(b, 2) and (deg[:a] == (a - 1) * math.comb(b, 2)).all()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_loop_er_planted_config(seed):
+    n, s, d = synth.er_planted(seed=seed)
+    check_loop(n, s, d)
+
+
+def test_loop_chung_lu_hubs():
+    n, s, d = synth.chung_lu(n=20000, avg_deg=10, beta=2.2, planted=1, plant_size=40, p=0.7, seed=2)
+    check_loop(n, s, d)
