@@ -349,6 +349,7 @@ def main() -> int:
             "core_exact_locate_gpu": avg("t_locate_ms", "exact"),
             "core_exact_host_network": avg("t_flow_build_ms", "exact"),
             "core_exact_host_maxflow": avg("t_flow_ms", "exact"),
+            "core_exact_flow_setup": avg("t_flow_setup_ms", "exact"),
             "core_exact_total": avg("t_total_ms", "exact"),
         },
         "kernel_rates": {

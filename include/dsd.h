@@ -90,6 +90,8 @@ typedef struct {
      * the host) */
     uint64_t flow_gpu_calls;
     uint64_t k4_main_kind;
+    /* part of t_flow_ms: moving networks to the device (arcs up, residual CSR built there) */
+    double t_flow_setup_ms;
 } dsd_stats;
 
 /*

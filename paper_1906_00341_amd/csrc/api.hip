@@ -247,6 +247,7 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
     G->stats.flow_nodes_max = es.max_nodes;
     G->stats.t_flow_build_ms = es.build_ms;
     G->stats.t_flow_ms = es.flow_ms;
+    G->stats.t_flow_setup_ms = es.setup_ms;
     G->stats.flow_gpu_calls = es.gpu_flow_calls;
     if (improved) {
         rho = dsd_rational{l.num, l.den};
@@ -335,6 +336,7 @@ dsd_rational core_exact_query_run(dsd_graph_s *G, int h, const std::vector<int32
     G->stats.flow_nodes_max = es.max_nodes;
     G->stats.t_flow_build_ms = es.build_ms;
     G->stats.t_flow_ms = es.flow_ms;
+    G->stats.t_flow_setup_ms = es.setup_ms;
     G->stats.flow_gpu_calls = es.gpu_flow_calls;
     if (improved) {
         std::vector<uint8_t> hm(n, 0);

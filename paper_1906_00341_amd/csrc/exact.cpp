@@ -611,6 +611,7 @@ public:
     uint64_t mu() const { return mu_; }
     int nodes() const { return net_->nodes(); }
     int64_t gpu_calls() const { return gpu_calls_; }
+    double setup_ms() const { return setup_ms_; }
 
     // Vertices (local ids of the located core, members of this network) that
     // every cut must keep on the source side: their source arcs become
@@ -669,8 +670,10 @@ public:
                 parallel_slices((int64_t)mid_.size(), host_threads(), [&](int, int64_t lo, int64_t hi) {
                     for (int64_t i = lo; i < hi; i++) cls[mid_[i]] = ARC_MID;
                 });
+                const auto t0 = std::chrono::steady_clock::now();
                 gpu_.reset(new GpuFlow(net_->nodes(), net_->arcs(), net_->eu_data(), net_->ev_data(), cls.data(), nv,
                                        deg_.data()));
+                setup_ms_ += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             }
             f = gpu_->maxflow(test, reach, GPU_FLOW_MAX_PASSES, &done);
             if (done) gpu_calls_++;
@@ -725,6 +728,7 @@ private:
     PushRelabel *net_ = nullptr;
     std::unique_ptr<GpuFlow> gpu_;
     int64_t gpu_calls_ = 0;
+    double setup_ms_ = 0;
 };
 
 bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::vector<int32_t> &best,
@@ -773,8 +777,10 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
             st.flow_calls++;
             const int64_t g0 = net->gpu_calls();
+            const double s0 = net->setup_ms();
             bool denser = net->denser_than(lc_l.num, lc_l.den, found);
             st.gpu_flow_calls += net->gpu_calls() - g0;
+            st.setup_ms += net->setup_ms() - s0;
             auto t2 = std::chrono::steady_clock::now();
             st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
             st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -813,8 +819,10 @@ bool exact_search_query(const LocatedCore &lc, int h, uint64_t x, const std::vec
         st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
         st.flow_calls++;
         const int64_t g0 = net->gpu_calls();
+        const double s0 = net->setup_ms();
         const bool denser = net->denser_than(l.num, l.den, found);
         st.gpu_flow_calls += net->gpu_calls() - g0;
+        st.setup_ms += net->setup_ms() - s0;
         auto t2 = std::chrono::steady_clock::now();
         st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
         st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();

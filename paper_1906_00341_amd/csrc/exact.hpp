@@ -25,6 +25,7 @@ struct ExactStats {
     int64_t max_nodes = 0;
     int64_t gpu_flow_calls = 0;          // minimum cuts computed on the GPU
     double build_ms = 0, flow_ms = 0;   // network construction / maximum flow
+    double setup_ms = 0;                // part of flow_ms: moving a network to the device (arcs, residual CSR)
 };
 
 // Searches every component for a subgraph denser than `l` (the density of

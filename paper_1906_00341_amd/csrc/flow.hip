@@ -71,6 +71,66 @@ __global__ void k_csr_count(const int *eu, const int *ev, int64_t E, uint32_t *c
     }
 }
 
+// The same two passes with the arcs of the hot nodes (s, t and the vertex
+// nodes, ids < hot: they hold almost every arc) counted in LDS per
+// workgroup, so that a global atomic is paid once per hot node per
+// workgroup; every workgroup walks one contiguous range of arcs.
+constexpr int CSR_HOT = 8192;
+
+__device__ __forceinline__ void csr_range(int64_t E, int64_t *lo, int64_t *hi) {
+    const int64_t per = (E + gridDim.x - 1) / gridDim.x;
+    *lo = min(E, (int64_t)blockIdx.x * per);
+    *hi = min(E, *lo + per);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_csr_count_hot(const int *eu, const int *ev, int64_t E, int hot,
+                                                          uint32_t *cnt) {
+    __shared__ uint32_t sc[CSR_HOT];
+    for (int i = threadIdx.x; i < hot; i += BLOCK) sc[i] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    csr_range(E, &lo, &hi);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) {
+        const int u = eu[i], v = ev[i];
+        if (u < hot) atomicAdd(&sc[u], 1u);
+        else atomicAdd(&cnt[u], 1u);
+        if (v < hot) atomicAdd(&sc[v], 1u);
+        else atomicAdd(&cnt[v], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < hot; i += BLOCK)
+        if (sc[i]) atomicAdd(&cnt[i], sc[i]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_csr_fill_hot(const int *eu, const int *ev, int64_t E, int hot,
+                                                         uint32_t *fill, int *to, int *rev, int *fwd) {
+    __shared__ uint32_t sc[CSR_HOT];
+    for (int i = threadIdx.x; i < hot; i += BLOCK) sc[i] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    csr_range(E, &lo, &hi);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) {
+        const int u = eu[i], v = ev[i];
+        if (u < hot) atomicAdd(&sc[u], 1u);
+        if (v < hot) atomicAdd(&sc[v], 1u);
+    }
+    __syncthreads();
+    // this workgroup's range of each hot node's row
+    for (int i = threadIdx.x; i < hot; i += BLOCK)
+        if (sc[i]) sc[i] = atomicAdd(&fill[i], sc[i]);
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) {
+        const int u = eu[i], v = ev[i];
+        const int pu = (int)(u < hot ? atomicAdd(&sc[u], 1u) : atomicAdd(&fill[u], 1u));
+        const int pv = (int)(v < hot ? atomicAdd(&sc[v], 1u) : atomicAdd(&fill[v], 1u));
+        to[pu] = v;
+        to[pv] = u;
+        rev[pu] = pv;
+        rev[pv] = pu;
+        fwd[i] = pu;
+    }
+}
+
 __global__ void k_csr_last(const uint32_t *cnt, int n, int *first) {
     if (blockIdx.x == 0 && threadIdx.x == 0) first[n] = first[n - 1] + (int)cnt[n - 1];
 }
@@ -429,11 +489,16 @@ GpuFlow::GpuFlow(int n, int64_t E, const int *eu, const int *ev, const uint8_t *
     int *to = I.sc.get_n<int>(A), *rev = I.sc.get_n<int>(A);
     I.fwd = I.sc.get_n<int>(E);
     fill_i32((int32_t *)cnt, 0, n, I.s);
-    k_csr_count<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, cnt);
+    // s, t and the vertex nodes take LDS counters when they fit
+    const int hot = 2 + nv <= CSR_HOT ? 2 + nv : 0;
+    const int gcsr = (int)std::min<int64_t>(1024, std::max<int64_t>(1, E / 4096));
+    if (hot) k_csr_count_hot<<<gcsr, BLOCK, 0, I.s>>>(I.eu, I.ev, E, hot, cnt);
+    else k_csr_count<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, cnt);
     scan_exclusive_u32(cnt, (uint32_t *)first, n, I.s, I.sc);
     k_csr_last<<<1, 1, 0, I.s>>>(cnt, n, first);
     DSD_HIP(hipMemcpyAsync(fill, first, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, I.s));
-    k_csr_fill<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, fill, to, rev, I.fwd);
+    if (hot) k_csr_fill_hot<<<gcsr, BLOCK, 0, I.s>>>(I.eu, I.ev, E, hot, fill, to, rev, I.fwd);
+    else k_csr_fill<<<grid_for(E, BLOCK, 16384), BLOCK, 0, I.s>>>(I.eu, I.ev, E, fill, to, rev, I.fwd);
     b.first = first;
     b.to = to;
     b.rev = rev;
