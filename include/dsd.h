@@ -92,6 +92,9 @@ typedef struct {
     uint64_t k4_main_kind;
     /* part of t_flow_ms: moving networks to the device (arcs up, residual CSR built there) */
     double t_flow_setup_ms;
+    /* networks of the exact step built on the device (h = 3 components with
+     * enough edges); the others were built on the host */
+    uint64_t flow_gpu_networks;
 } dsd_stats;
 
 /*

@@ -249,6 +249,7 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
     G->stats.t_flow_ms = es.flow_ms;
     G->stats.t_flow_setup_ms = es.setup_ms;
     G->stats.flow_gpu_calls = es.gpu_flow_calls;
+    G->stats.flow_gpu_networks = es.gpu_networks;
     if (improved) {
         rho = dsd_rational{l.num, l.den};
         std::vector<uint8_t> hm(n, 0);
@@ -338,6 +339,7 @@ dsd_rational core_exact_query_run(dsd_graph_s *G, int h, const std::vector<int32
     G->stats.t_flow_ms = es.flow_ms;
     G->stats.t_flow_setup_ms = es.setup_ms;
     G->stats.flow_gpu_calls = es.gpu_flow_calls;
+    G->stats.flow_gpu_networks = es.gpu_networks;
     if (improved) {
         std::vector<uint8_t> hm(n, 0);
         for (int32_t v : bestset) hm[lc.rank[v]] = 1;

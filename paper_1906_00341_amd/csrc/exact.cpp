@@ -52,6 +52,13 @@ static int64_t gpu_flow_min_arcs() {
     const char *e = getenv("DSD_FLOW_GPU_MIN_ARCS");
     return e ? (int64_t)atoll(e) : (int64_t)1 << 21;
 }
+// h = 3 networks of components with at least this many edges (and at most
+// TRI_NET_MAX_NV vertices) are built on the device; the environment variable
+// DSD_NET_GPU_MIN_EDGES overrides it (negative: always on the host)
+static int64_t gpu_net_min_edges() {
+    const char *e = getenv("DSD_NET_GPU_MIN_EDGES");
+    return e ? (int64_t)atoll(e) : (int64_t)8192;
+}
 
 // ---------------------------------------------------------------- host threads
 
@@ -196,6 +203,13 @@ public:
     int nodes() const { return n_; }
     int64_t arcs() const { return E_; }
     int64_t residual_arcs() const { return 2 * E_; }
+    // all arcs at once: f(eu, ev) fills arrays of `arcs` entries
+    template <class F>
+    void load(int64_t arcs, F &&f) {
+        reserve(arcs);
+        E_ = arcs;
+        f(eu_.p.get(), ev_.p.get());
+    }
     const int *eu_data() const { return eu_.p.get(); }
     const int *ev_data() const { return ev_.p.get(); }
     // the residual CSR is built on first use by the host maximum flow
@@ -530,14 +544,23 @@ public:
             so[i + 1] = (int64_t)sa.size();
         }
         std::vector<int64_t> fwd(nv);
-        std::vector<int32_t> eid(sa.size(), -1);
-        int64_t npsi = 0;
         for (int i = 0; i < nv; i++) {
             int64_t a = so[i];
             while (a < so[i + 1] && sa[a] < i) a++;
             fwd[i] = a;
-            for (int64_t e = a; e < so[i + 1]; e++) eid[e] = (int32_t)npsi++;
         }
+        const int64_t edges = (int64_t)sa.size() / 2;
+        if (gpu_net_min_edges() >= 0 && edges >= std::max<int64_t>(1, gpu_net_min_edges()) && nv <= TRI_NET_MAX_NV) {
+            // the same network, node and arc numbering built on the device
+            gpu_ = GpuFlow::triangles(nv, so.data(), sa.data(), fwd.data(), deg_, &mu_);
+            dev_ = true;
+            np_ = edges;
+            return;
+        }
+        std::vector<int32_t> eid(sa.size(), -1);
+        int64_t npsi = 0;
+        for (int i = 0; i < nv; i++)
+            for (int64_t e = fwd[i]; e < so[i + 1]; e++) eid[e] = (int32_t)npsi++;
         const int64_t base = 2 + nv;
         if (base + npsi > 0x7fffffff) throw Error(-5, "flow network too large");
         // triangles per vertex i (i the lowest of the three), so that every
@@ -609,7 +632,8 @@ public:
     CompNet &operator=(const CompNet &) = delete;
 
     uint64_t mu() const { return mu_; }
-    int nodes() const { return net_->nodes(); }
+    bool built_on_device() const { return dev_; }
+    int nodes() const { return net_ ? net_->nodes() : gpu_->nodes(); }
     int64_t gpu_calls() const { return gpu_calls_; }
     double setup_ms() const { return setup_ms_; }
 
@@ -620,6 +644,7 @@ public:
         forced_.assign(verts_.size(), 0);
         for (int32_t v : q)
             if (idx_[v] >= 0) forced_[idx_[v]] = 1;
+        if (dev_ && gpu_) gpu_->force_sources(forced_);
     }
 
     // Strict test at alpha = a/b.  Returns true and the found set (local ids)
@@ -649,8 +674,8 @@ public:
             i128 fin = srcsum;
             for (int i = 0; i < nv; i++)
                 fin += h_ == 2 ? (i128)b * (i128)m_ + 2 * (i128)a : (i128)h_ * (i128)a;
-            fin += (i128)b * (i128)mid_.size();
-            if (h_ == 2) fin += (i128)b * (i128)mid_.size();
+            fin += (i128)b * (i128)mids();
+            if (h_ == 2) fin += (i128)b * (i128)mids();
             inf = fin + 1;
             if (inf >= CAP_LIMIT) throw Error(-4, "scaled capacity overflow");
         }
@@ -658,7 +683,9 @@ public:
         int64_t f = 0;
         std::vector<char> reach;
         bool done = false;
-        if (gpu_flow_min_arcs() >= 0 && net_->residual_arcs() >= gpu_flow_min_arcs()) {
+        const int64_t res_arcs = net_ ? net_->residual_arcs() : 2 * gpu_->arcs();
+        const bool use_gpu = gpu_flow_min_arcs() >= 0 && res_arcs >= gpu_flow_min_arcs();
+        if (use_gpu) {
             // the arcs go to the device once; the device sets each test's capacities
             if (!gpu_) {
                 std::vector<uint8_t> cls(net_->arcs());
@@ -679,6 +706,10 @@ public:
             if (done) gpu_calls_++;
         }
         if (!done) {
+            if (!net_) {
+                adopt_device_net();
+                if (!use_gpu) gpu_.reset();
+            }
             net_->ensure_built();
             for (int i = 0; i < nv; i++) {
                 const bool fv = !forced_.empty() && forced_[i];
@@ -708,6 +739,26 @@ public:
     }
 
 private:
+    int64_t mids() const { return dev_ && !net_ ? 3 * (int64_t)mu_ : (int64_t)mid_.size(); }
+
+    // a device-built network copied to the host maximum flow, in the arc
+    // order the device built it (source, sink, infinite, then triangle arcs)
+    void adopt_device_net() {
+        const int nv = (int)verts_.size();
+        net_ = new PushRelabel(gpu_->nodes());
+        net_->load(gpu_->arcs(), [&](int *eu, int *ev) { gpu_->download_arcs(eu, ev); });
+        src_.resize(nv);
+        snk_.resize(nv);
+        for (int i = 0; i < nv; i++) {
+            src_[i] = i;
+            snk_[i] = nv + i;
+        }
+        inf_.resize(2 * np_);
+        std::iota(inf_.begin(), inf_.end(), 2 * nv);
+        mid_.resize(3 * mu_);
+        std::iota(mid_.begin(), mid_.end(), (int)(2 * nv + 2 * np_));
+    }
+
     void set_all(const std::vector<int> &arcs, int64_t c, int64_t rc) {
         parallel_slices((int64_t)arcs.size(), arcs.size() < (1u << 20) ? 1 : host_threads(),
                         [&](int, int64_t lo, int64_t hi) {
@@ -727,6 +778,8 @@ private:
     uint64_t mu_ = 0, m_ = 0;
     PushRelabel *net_ = nullptr;
     std::unique_ptr<GpuFlow> gpu_;
+    bool dev_ = false;   // built on the device (h = 3): gpu_ holds the network until the host needs it
+    int64_t np_ = 0;     // edge nodes of a device-built network
     int64_t gpu_calls_ = 0;
     double setup_ms_ = 0;
 };
@@ -772,6 +825,7 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             if (!net || cur != built) {
                 net.reset(new CompNet(lc, h, cur));
                 built = cur;
+                st.gpu_networks += net->built_on_device();
             }
             auto t1 = std::chrono::steady_clock::now();
             st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());
@@ -814,6 +868,7 @@ bool exact_search_query(const LocatedCore &lc, int h, uint64_t x, const std::vec
             net.reset(new CompNet(lc, h, cur));
             net->force(q);
             built = cur;
+            st.gpu_networks += net->built_on_device();
         }
         auto t1 = std::chrono::steady_clock::now();
         st.max_nodes = std::max<int64_t>(st.max_nodes, net->nodes());

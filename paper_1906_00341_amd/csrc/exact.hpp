@@ -24,6 +24,7 @@ struct ExactStats {
     int64_t flow_calls = 0;
     int64_t max_nodes = 0;
     int64_t gpu_flow_calls = 0;          // minimum cuts computed on the GPU
+    int64_t gpu_networks = 0;            // networks built on the device
     double build_ms = 0, flow_ms = 0;   // network construction / maximum flow
     double setup_ms = 0;                // part of flow_ms: moving a network to the device (arcs, residual CSR)
 };

@@ -147,6 +147,135 @@ __global__ void k_csr_fill(const int *eu, const int *ev, int64_t E, uint32_t *fi
     }
 }
 
+// ---- Algorithm 1's network for h = 3, built on the device ----
+// Nodes: s = 0, t = 1, vertex i -> 2 + i, edge e -> 2 + nv + e.  Edges are
+// numbered row by row: the edges (i, j), j > i, of row i (its forward part,
+// from fwd[i] on) take ebase[i] .. ebase[i+1].  Arcs:
+//   [0, nv)             s -> i
+//   [nv, 2 nv)          i -> t
+//   [2 nv, 2 nv + 2 np) edge (i, j) -> i and edge (i, j) -> j (infinite)
+//   then for every edge (i, j) in edge order and every triangle {i, j, k},
+//   k > j, in ascending k: i -> (j, k), j -> (i, k), k -> (i, j).
+
+// the source, sink and infinite arcs (one wave per vertex)
+__global__ __launch_bounds__(BLOCK) void k_tn_fixed(const int64_t *so, const int32_t *sa, const int64_t *fwd,
+                                                     const int64_t *ebase, int nv, int *eu, int *ev, uint8_t *cls) {
+    const int nw = gridDim.x * WAVES_PER_BLOCK;
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE; i < nv; i += nw) {
+        if (lane() == 0) {
+            eu[i] = 0;
+            ev[i] = 2 + i;
+            cls[i] = ARC_SRC;
+            eu[nv + i] = 2 + i;
+            ev[nv + i] = 1;
+            cls[nv + i] = ARC_SNK;
+        }
+        const int64_t f0 = fwd[i], f1 = so[i + 1];
+        for (int64_t a = f0 + lane(); a < f1; a += WAVE) {
+            const int64_t e = ebase[i] + (a - f0);
+            const int node = 2 + nv + (int)e;
+            const int64_t at = 2 * (int64_t)nv + 2 * e;
+            eu[at] = node;
+            ev[at] = 2 + i;
+            cls[at] = ARC_INF;
+            eu[at + 1] = node;
+            ev[at + 1] = 2 + sa[a];
+            cls[at + 1] = ARC_INF;
+        }
+    }
+}
+
+// Triangles by their lowest vertex i: one workgroup per i keeps a bitmap of
+// i's forward part in LDS (W words, and with EMIT the number of its bits
+// before every word, so that the rank of k in the forward part is one
+// lookup); each wave takes an edge (i, j) of the forward part and tests j's
+// forward part against the bitmap 64 entries at a time.  Count pass: the
+// triangles of every edge into tcnt.  Emit pass: with toff the exclusive
+// scan of those counts, the three arcs of every triangle from arc m0 on.
+template <bool EMIT>
+__global__ __launch_bounds__(BLOCK) void k_tn_tri(const int64_t *so, const int32_t *sa, const int64_t *fwd,
+                                                   const int64_t *ebase, int nv, int W, int64_t *tcnt,
+                                                   const int64_t *toff, int64_t m0, int *eu, int *ev,
+                                                   uint8_t *cls) {
+    extern __shared__ uint32_t tn_lds[];
+    __shared__ uint32_t wsum[WAVES_PER_BLOCK];
+    uint32_t *bm = tn_lds, *pre = tn_lds + W;
+    const int wid = threadIdx.x / WAVE;
+    for (int i = blockIdx.x; i < nv; i += gridDim.x) {
+        const int64_t f0 = fwd[i], f1 = so[i + 1];
+        if (f1 - f0 < 2) {   // no triangle has i as its lowest vertex
+            if (!EMIT)
+                for (int64_t a = f0 + threadIdx.x; a < f1; a += BLOCK) tcnt[ebase[i] + (a - f0)] = 0;
+            continue;
+        }
+        for (int w = threadIdx.x; w < W; w += BLOCK) bm[w] = 0;
+        __syncthreads();
+        for (int64_t a = f0 + threadIdx.x; a < f1; a += BLOCK) {
+            const int k = sa[a];
+            atomicOr(&bm[k >> 5], 1u << (k & 31));
+        }
+        __syncthreads();
+        if (EMIT) {
+            // pre[w] = bits set in words before w: each thread sums a run of
+            // words, then a block scan of the run totals
+            const int per = (W + BLOCK - 1) / BLOCK;
+            const int w0 = min(W, (int)threadIdx.x * per), w1 = min(W, w0 + per);
+            uint32_t own = 0;
+            for (int w = w0; w < w1; w++) own += __popc(bm[w]);
+            const uint32_t inc = wave_incl_scan(own);
+            if (lane() == WAVE - 1) wsum[wid] = inc;
+            __syncthreads();
+            uint32_t run = inc - own;
+            for (int x = 0; x < wid; x++) run += wsum[x];
+            for (int w = w0; w < w1; w++) {
+                pre[w] = run;
+                run += __popc(bm[w]);
+            }
+            __syncthreads();
+        }
+        for (int64_t a = f0 + wid; a < f1; a += WAVES_PER_BLOCK) {
+            const int j = sa[a];
+            const int64_t e = ebase[i] + (a - f0);
+            const int64_t g0 = fwd[j], g1 = so[j + 1];
+            int64_t pos = EMIT ? toff[e] : 0;
+            for (int64_t q0 = g0; q0 < g1; q0 += WAVE) {
+                const int64_t q = q0 + lane();
+                int k = 0;
+                bool hit = false;
+                if (q < g1) {
+                    k = sa[q];
+                    hit = (bm[k >> 5] >> (k & 31)) & 1u;
+                }
+                const u64 m = __ballot(hit);
+                if (EMIT && hit) {
+                    const int64_t at = m0 + 3 * (pos + __popcll(m & lanemask_lt()));
+                    const uint32_t below = bm[k >> 5] & ((1u << (k & 31)) - 1u);
+                    const int64_t p = (int64_t)pre[k >> 5] + __popc(below);   // rank of k in i's forward part
+                    eu[at] = 2 + i;
+                    ev[at] = 2 + nv + (int)(ebase[j] + (q - g0));
+                    eu[at + 1] = 2 + j;
+                    ev[at + 1] = 2 + nv + (int)(ebase[i] + p);
+                    eu[at + 2] = 2 + k;
+                    ev[at + 2] = 2 + nv + (int)e;
+                    cls[at] = ARC_MID;
+                    cls[at + 1] = ARC_MID;
+                    cls[at + 2] = ARC_MID;
+                }
+                pos += __popcll(m);
+            }
+            if (!EMIT && lane() == 0) tcnt[e] = pos;
+        }
+        __syncthreads();   // the next vertex rewrites the bitmap
+    }
+}
+
+// triangles through vertex i: its residual row holds the reverse of s -> i,
+// i -> t, one infinite arc per edge at i and one arc per triangle at i
+__global__ void k_tn_deg(const int *first, const int64_t *so, int nv, int64_t *deg) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x)
+        deg[i] = (int64_t)(first[3 + i] - first[2 + i]) - 2 - (so[i + 1] - so[i]);
+}
+
 // capacities of one test (see FlowTest), and zero excess
 __global__ void k_flow_caps(FlowBufs b, const int *eu, const int *ev, const uint8_t *cls, const int *fwd,
                             const int64_t *deg, int64_t E, FlowTest t) {
@@ -458,23 +587,24 @@ struct GpuFlow::Impl {
     uint8_t *cls = nullptr;
     int64_t *deg = nullptr;
     int *pinned = nullptr;
+    int nv = 0;
     ~Impl() {
         if (s) (void)hipStreamSynchronize(s);
         if (pinned) (void)hipHostFree(pinned);
         if (s) (void)hipStreamDestroy(s);
     }
     int global_relabel();
+    void residual(int n);
 };
+
+GpuFlow::GpuFlow() : p_(new Impl) { DSD_HIP(hipStreamCreateWithFlags(&p_->s, hipStreamNonBlocking)); }
 
 GpuFlow::GpuFlow(int n, int64_t E, const int *eu, const int *ev, const uint8_t *cls, int nv,
                  const uint64_t *deg)
-    : p_(new Impl) {
+    : GpuFlow() {
     Impl &I = *p_;
-    DSD_HIP(hipStreamCreateWithFlags(&I.s, hipStreamNonBlocking));
     I.E = E;
-    const int64_t A = 2 * E;
-    FlowBufs &b = I.b;
-    b.n = n;
+    I.nv = nv;
     I.eu = I.sc.get_n<int>(E);
     I.ev = I.sc.get_n<int>(E);
     I.cls = I.sc.get_n<uint8_t>(E);
@@ -483,7 +613,83 @@ GpuFlow::GpuFlow(int n, int64_t E, const int *eu, const int *ev, const uint8_t *
     DSD_HIP(hipMemcpyAsync(I.ev, ev, (size_t)E * sizeof(int), hipMemcpyHostToDevice, I.s));
     DSD_HIP(hipMemcpyAsync(I.cls, cls, (size_t)E, hipMemcpyHostToDevice, I.s));
     DSD_HIP(hipMemcpyAsync(I.deg, deg, (size_t)nv * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
-    // residual CSR: count, scan, fill
+    I.residual(n);
+}
+
+std::unique_ptr<GpuFlow> GpuFlow::triangles(int nv, const int64_t *so, const int32_t *sa, const int64_t *fwd,
+                                            std::vector<uint64_t> &deg, uint64_t *tri) {
+    if (nv < 1 || nv > TRI_NET_MAX_NV) throw Error(-5, "triangle network: vertex count out of range");
+    std::unique_ptr<GpuFlow> g(new GpuFlow());
+    Impl &I = *g->p_;
+    I.nv = nv;
+    const int64_t ns = so[nv];
+    std::vector<int64_t> ebase(nv + 1, 0);
+    for (int i = 0; i < nv; i++) ebase[i + 1] = ebase[i] + (so[i + 1] - fwd[i]);
+    const int64_t np = ebase[nv];
+    if (2 + (int64_t)nv + np > 0x7fffffff) throw Error(-5, "flow network too large");
+    int64_t *d_so = I.sc.get_n<int64_t>(nv + 1), *d_fwd = I.sc.get_n<int64_t>(nv);
+    int64_t *d_eb = I.sc.get_n<int64_t>(nv + 1), *tcnt = I.sc.get_n<int64_t>(np + 1);
+    int32_t *d_sa = I.sc.get_n<int32_t>(ns);
+    DSD_HIP(hipMemcpyAsync(d_so, so, (size_t)(nv + 1) * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(d_fwd, fwd, (size_t)nv * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipMemcpyAsync(d_eb, ebase.data(), (size_t)(nv + 1) * sizeof(int64_t), hipMemcpyHostToDevice, I.s));
+    if (ns > 0) DSD_HIP(hipMemcpyAsync(d_sa, sa, (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice, I.s));
+    const int W = (nv + 31) / 32;
+    const size_t lds = (size_t)2 * W * sizeof(uint32_t);
+    // triangles per edge, then their offsets (tcnt[np] = total)
+    k_tn_tri<false><<<nv, BLOCK, lds, I.s>>>(d_so, d_sa, d_fwd, d_eb, nv, W, tcnt, nullptr, 0, nullptr, nullptr,
+                                             nullptr);
+    fill_i32((int32_t *)(tcnt + np), 0, 2, I.s);
+    scan_exclusive_i64(tcnt, tcnt, np + 1, I.s, I.sc);
+    int64_t total = 0;
+    DSD_HIP(hipMemcpyAsync(&total, tcnt + np, sizeof(int64_t), hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
+    const int64_t m0 = 2 * (int64_t)nv + 2 * np;
+    if (m0 > 0x7fffffff / 2 || total > (0x7fffffff / 2 - m0) / 3) throw Error(-5, "flow network too large");
+    const int64_t E = m0 + 3 * total;
+    I.E = E;
+    I.eu = I.sc.get_n<int>(E);
+    I.ev = I.sc.get_n<int>(E);
+    I.cls = I.sc.get_n<uint8_t>(E);
+    I.deg = I.sc.get_n<int64_t>(nv);
+    k_tn_fixed<<<grid_for(nv, WAVES_PER_BLOCK, 16384), BLOCK, 0, I.s>>>(d_so, d_sa, d_fwd, d_eb, nv, I.eu, I.ev,
+                                                                        I.cls);
+    if (total > 0)
+        k_tn_tri<true><<<nv, BLOCK, lds, I.s>>>(d_so, d_sa, d_fwd, d_eb, nv, W, nullptr, tcnt, m0, I.eu, I.ev,
+                                                I.cls);
+    I.residual((int)(2 + nv + np));
+    k_tn_deg<<<grid_for(nv, BLOCK, 4096), BLOCK, 0, I.s>>>(I.b.first, d_so, nv, I.deg);
+    deg.resize(nv);
+    DSD_HIP(hipMemcpyAsync(deg.data(), I.deg, (size_t)nv * sizeof(int64_t), hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
+    *tri = (uint64_t)total;
+    return g;
+}
+
+int GpuFlow::nodes() const { return p_->b.n; }
+int64_t GpuFlow::arcs() const { return p_->E; }
+
+void GpuFlow::download_arcs(int *eu, int *ev) const {
+    Impl &I = *p_;
+    DSD_HIP(hipMemcpyAsync(eu, I.eu, (size_t)I.E * sizeof(int), hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipMemcpyAsync(ev, I.ev, (size_t)I.E * sizeof(int), hipMemcpyDeviceToHost, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
+}
+
+void GpuFlow::force_sources(const std::vector<char> &forced) {
+    Impl &I = *p_;
+    if ((int)forced.size() != I.nv) throw Error(-5, "force_sources: one flag per vertex expected");
+    std::vector<uint8_t> c(I.nv);
+    for (int i = 0; i < I.nv; i++) c[i] = forced[i] ? ARC_INF : ARC_SRC;
+    DSD_HIP(hipMemcpyAsync(I.cls, c.data(), (size_t)I.nv, hipMemcpyHostToDevice, I.s));
+    DSD_HIP(hipStreamSynchronize(I.s));
+}
+
+// residual CSR of the E arcs in eu/ev: count, scan, fill
+void GpuFlow::Impl::residual(int n) {
+    Impl &I = *this;
+    const int64_t A = 2 * E;
+    b.n = n;
     uint32_t *cnt = I.sc.get_n<uint32_t>(n), *fill = I.sc.get_n<uint32_t>(n);
     int *first = I.sc.get_n<int>(n + 1);
     int *to = I.sc.get_n<int>(A), *rev = I.sc.get_n<int>(A);

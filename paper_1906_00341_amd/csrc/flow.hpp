@@ -32,6 +32,24 @@ public:
     ~GpuFlow();
     GpuFlow(const GpuFlow &) = delete;
     GpuFlow &operator=(const GpuFlow &) = delete;
+    // Algorithm 1's network for h = 3 over a component of nv vertices (at
+    // most TRI_NET_MAX_NV), built on the device.  so/sa (host): the
+    // component's adjacency in local ids, rows sorted ascending; fwd[i]: the
+    // first entry of row i above i.  Nodes: s = 0, t = 1, vertex i -> 2 + i,
+    // then one node per edge, numbered row by row over the rows' parts from
+    // fwd on.  Arcs: the nv source arcs first, the nv sink arcs next, then
+    // two infinite arcs per edge, then three arcs per triangle.  deg receives
+    // the triangles through each vertex, *tri their number.  Throws
+    // Error(-5) when the arcs would not fit int indices.
+    static std::unique_ptr<GpuFlow> triangles(int nv, const int64_t *so, const int32_t *sa, const int64_t *fwd,
+                                              std::vector<uint64_t> &deg, uint64_t *tri);
+    int nodes() const;
+    int64_t arcs() const;
+    // the arcs' ends as built (arrays of arcs() entries, host)
+    void download_arcs(int *eu, int *ev) const;
+    // networks from triangles(): the source arcs of the vertices flagged in
+    // forced (one flag per vertex) become infinite, the others finite again
+    void force_sources(const std::vector<char> &forced);
     // Maximum s-t flow value at the test's capacities; reach_t[v] = 1 iff v
     // reaches t in the final residual network.  Gives up after max_passes
     // push/relabel passes (*converged = false).
@@ -39,7 +57,11 @@ public:
     struct Impl;
 
 private:
+    GpuFlow();
     std::unique_ptr<Impl> p_;
 };
+
+// largest component triangles() takes (its LDS bitmap has one bit per vertex)
+constexpr int TRI_NET_MAX_NV = 1 << 17;
 
 }  // namespace dsd

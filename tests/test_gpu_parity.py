@@ -253,6 +253,44 @@ def test_exact_with_every_min_cut_on_the_gpu(fixtures, monkeypatch, h):
     assert gpu_cuts > 0
 
 
+def _exact_cases(fixtures, extra_dense):
+    cases = []
+    for name in ("F1", "F4"):
+        e = np.asarray(fixtures[name]["edges"], np.int32)
+        cases.append((int(fixtures[name]["n"]), e[:, 0], e[:, 1]))
+    for seed in range(4):
+        cases.append(synth.er_planted(n=300, m=1500, plant=25, p=0.6, seed=40 + seed))
+    cases.append(synth.er_planted(seed=2))
+    if extra_dense:
+        n, s, d = synth.complete_graph(110)
+        keep = np.random.default_rng(3).random(len(s)) < 0.97
+        cases.append((n, s[keep], d[keep]))
+    return cases
+
+
+@pytest.mark.parametrize("cut", ["gpu", "host"])
+def test_triangle_networks_built_on_the_device(fixtures, monkeypatch, cut):
+    # every h = 3 network of the exact step is built on the device (bitmap
+    # triangle listing, residual CSR there); its minimum cuts run on the
+    # device, or on the host from the arcs copied back
+    monkeypatch.setenv("DSD_NET_GPU_MIN_EDGES", "0")
+    monkeypatch.setenv("DSD_FLOW_GPU_MIN_ARCS", "0" if cut == "gpu" else "-1")
+    h = 3
+    nets = 0
+    for n, s, d in _exact_cases(fixtures, True):
+        og = oracle.Graph(n, s, d)
+        gg = dsd.build_csr(n, np.ascontiguousarray(s, np.int32), np.ascontiguousarray(d, np.int32))
+        _, rho_o, _ = og.exact(h, "core")
+        mem_g, rho_g = dsd.core_exact(gg, h)
+        st = gg.stats()
+        nets += st["flow_gpu_networks"]
+        assert st["flow_gpu_calls"] == (st["flow_calls"] if cut == "gpu" else 0)
+        assert rho_g == rho_o
+        if rho_o > 0:
+            assert density_of(og, h, mem_g) == rho_o
+    assert nets > 0
+
+
 def test_bad_arguments():
     g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     for h in (0, 1, 7):

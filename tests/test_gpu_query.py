@@ -102,6 +102,23 @@ def test_every_min_cut_on_the_gpu(fixtures, monkeypatch):
         check(og, gg, 2, [v])
 
 
+@pytest.mark.parametrize("cut", ["gpu", "host"])
+def test_query_networks_built_on_the_device(monkeypatch, cut):
+    # h = 3 networks built on the device take the query vertices' infinite
+    # source arcs there; the cuts run on the device or on the host
+    monkeypatch.setenv("DSD_NET_GPU_MIN_EDGES", "0")
+    monkeypatch.setenv("DSD_FLOW_GPU_MIN_ARCS", "0" if cut == "gpu" else "-1")
+    rng = np.random.default_rng(11)
+    nets = 0
+    for seed in (3, 4):
+        n, s, d = synth.er_planted(seed=seed)
+        og, gg = both(n, s, d)
+        for nq in (1, 2):
+            check(og, gg, 3, rng.choice(n, nq, replace=False).tolist())
+            nets += gg.stats()["flow_gpu_networks"]
+    assert nets > 0
+
+
 def test_chung_lu_properties():
     # too large for the oracle's whole-graph search: the answer contains Q,
     # attains its density, lies between the density of the (x, Psi)-core and
