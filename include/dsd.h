@@ -76,14 +76,16 @@ typedef struct {
     uint64_t n, m, w2, s2;
     /* host exact step: network construction and maximum-flow time */
     double t_flow_build_ms, t_flow_ms;
-    /* the peel's main kernel, every launch timed on its own with HIP events:
-     * total time, launches and the work it counted (pairs, nbrs); which
-     * kernel it was is k4_main_kind:
+    /* the peel's main kernel: with dsd_set_kernel_timing on, every launch
+     * timed on its own with HIP events (total time, launches; else 0); the
+     * work it counted (pairs, nbrs) always.  Which kernel it was is
+     * k4_main_kind:
      *   1  h = 2 edge pass: adjacency entries walked, frontier vertices;
      *   2  h = 3 triangle probe: out-list entries probed, neighbours expanded;
      *   3  h = 3 triangle lists: pairs walked, row items;
- *   4  x-star pattern frontier pass: adjacency entries walked, frontier vertices;
-     *   0  none timed (h >= 4) */
+     *   4  x-star pattern frontier pass: adjacency entries walked, frontier vertices;
+     *   5  4-loop pattern pass;
+     *   0  none (h >= 4) */
     double k4_main_ms;
     uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
     /* minimum cuts of the exact step computed on the GPU (the others ran on
@@ -319,6 +321,16 @@ dsd_status dsd_server_destroy(dsd_server s);
  * dsd_core_exact reuse it (their enumeration and peel figures then repeat
  * those of the call that computed it). */
 dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out);
+
+/* With on != 0, later calls on g bracket every launch of the peel's main
+ * kernel (the kernel named by k4_main_kind) with a pair of HIP events on the
+ * graph's stream, and report their sum and count in k4_main_ms and
+ * k4_main_launches; with on == 0 (the default) both stay 0.  A bracketed
+ * launch costs the host some 20 microseconds, more than the round loop of
+ * the peel spends on a round otherwise, so leave it off outside
+ * measurements.  A decomposition already cached on g is not recomputed.
+ * DSD_EINVAL: g is NULL. */
+dsd_status dsd_set_kernel_timing(dsd_graph g, int on);
 
 /* Human-readable name of a status; never NULL. */
 const char *dsd_status_str(dsd_status s);

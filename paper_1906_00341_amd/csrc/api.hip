@@ -120,6 +120,7 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
             throw Error(DSD_ENOMEM, "device allocation of core numbers failed");
     }
     D.kt = KernelTimes();
+    D.kt.time_main = G->time_main;
     Timer te(s);
     u64 *d = G->sc.get_n<u64>(n);
     D.mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &D.kt) : 0;
@@ -428,6 +429,12 @@ dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out) {
     return DSD_OK;
 }
 
+dsd_status dsd_set_kernel_timing(dsd_graph g, int on) {
+    if (!g) return fail(DSD_EINVAL, "NULL graph");
+    g->time_main = on != 0;
+    return DSD_OK;
+}
+
 dsd_status dsd_clique_degrees(dsd_graph G, int h, int out_mem, uint64_t *deg, uint64_t *num_cliques) {
     if (!G) return fail(DSD_EINVAL, "NULL graph");
     DSD_TRY({
@@ -581,6 +588,7 @@ dsd_rational peel_app_run(dsd_graph_s *G, int h, uint8_t *best, int64_t *rounds,
     *best_round = -1;
     if (n == 0) return dsd_rational{0, 1};
     KernelTimes kt;
+    kt.time_main = G->time_main;
     Timer te(s);
     u64 *d = G->sc.get_n<u64>(n);
     const u64 mu = degrees_and_mu(G, h, nullptr, d, &kt);

@@ -38,6 +38,7 @@ struct KernelTimes {
     double main_ms = 0;
     u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
     int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass
+    bool time_main = false;   // bracket every main-kernel launch with HIP events (main_ms)
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----

@@ -34,6 +34,7 @@ struct dsd_graph_s {
     dsd::Decomp dec[7];             // by h
     dsd::TriList tl;                // triangle lists, built by the first h = 3 decomposition that wants them
     bool tl_tried = false;
+    bool time_main = false;         // dsd_set_kernel_timing
     ~dsd_graph_s() {
         for (dsd::Decomp &d : dec) (void)hipFree(d.core);
         dsd::free_tri_list(tl);

@@ -139,6 +139,7 @@ dsd_status dsd_pattern_core(dsd_graph G, int pattern, int x, int out_mem, uint64
         u64 km = 0;
         if (n > 0) {
             KernelTimes kt;
+            kt.time_main = G->time_main;
             Timer te(s);
             const u64 mu = pattern_degrees_run(G, pattern, x, d);
             G->stats.t_enum_ms = te.stop();

@@ -264,13 +264,14 @@ __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int
     }
     const int32_t g = graph_of(b, x);
     const u64 k = level_of(b, g);
-    u64 old = atomic_sub_u64(&b.deg[x], c);
-    if (old > k && old - c <= k) {
-        const int nx = b.ctl->cur ^ 1;
-        int32_t *Fn = b.F + (size_t)nx * b.n;
-        int32_t pos = atomicAdd(&b.ctl->nF[nx], 1);
-        Fn[pos] = x;
-        atomicAdd(&b.gs[g].nF[nx], 1);
+    const u64 old = atomic_sub_u64(&b.deg[x], c);
+    const bool cross = old > k && old - c <= k;
+    // the lanes that cross together take their frontier slots with one atomic
+    const int nx = b.ctl->cur ^ 1;
+    constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
+    wave_push(cross, x, b.F + (size_t)nx * b.n, &b.ctl->nF[nx]);
+    wave_add_by_graph<int32_t>(cross ? g : -1, &b.gs[0].nF[nx], GS_STRIDE);
+    if (cross) {
         b.stamp[x] = r + 1;
         b.core[x] = k;
         push_work(b, x, nx);
@@ -281,6 +282,27 @@ __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int
 __device__ __forceinline__ void add_destroyed(const PeelBufs &b, int32_t v, u64 t) {
     if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed, t);
 }
+
+// Cliques destroyed, summed by one lane over the frontier vertices or items
+// it handles in a row: one atomic per run of one graph's vertices instead of
+// one per vertex (a large round's frontier would otherwise queue on the one
+// counter of its graph).
+struct DestroyedTally {
+    int32_t g = -1;
+    u64 t = 0;
+    __device__ __forceinline__ void add(const PeelBufs &b, int32_t v, u64 c) {
+        const int32_t gv = graph_of(b, v);
+        if (gv != g) {
+            flush(b);
+            g = gv;
+        }
+        t += c;
+    }
+    __device__ __forceinline__ void flush(const PeelBufs &b) {
+        if (t) atomicAdd(&b.gs[g].destroyed, t);
+        t = 0;
+    }
+};
 
 // the main kernel's counted work: lane 0 of every wave holds its wave's
 // tally; one atomic per block.  All threads of the block call together.
@@ -608,6 +630,7 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE;
     u64 wp = 0, wn = 0;   // counted work (lane 0's tally is the wave's)
+    DestroyedTally tally;
     for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nF; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int32_t v = F[i];
         u64 destroyed = 0;
@@ -622,9 +645,10 @@ __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
             }
         }
         destroyed = wave_sum(destroyed);
-        if (lane() == 0) add_destroyed(b, v, destroyed);
+        if (lane() == 0) tally.add(b, v, destroyed);
         if (b.count_work) wp += (u64)(b.row_ptr[v + 1] - b.row_ptr[v]), wn += 1;
     }
+    if (lane() == 0) tally.flush(b);
     if (b.count_work) add_work(b, wp, wn);
 }
 
@@ -814,6 +838,7 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
     }
     __builtin_amdgcn_wave_barrier();
     u64 wp = 0, wn = 0;   // counted work (wave-uniform)
+    DestroyedTally tally;
     const int64_t total = (int64_t)nB + nW + nF;
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < total; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         int32_t v;
@@ -865,8 +890,9 @@ __global__ __launch_bounds__(BLOCK) void k_h3_probe(PeelBufs b) {
             }
             destroyed = cw;
         }
-        if (lane() == 0) add_destroyed(b, v, destroyed);
+        if (lane() == 0) tally.add(b, v, destroyed);
     }
+    if (lane() == 0) tally.flush(b);
     if (b.count_work) add_work(b, wp, wn);
 }
 
@@ -905,6 +931,7 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
     const int64_t *Tc = b.T + (size_t)cur * b.tcap;
     const int wv = threadIdx.x / WAVE, L = lane();
     u64 wp = 0, wn = 0;
+    DestroyedTally tally;
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nT; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         const int64_t item = Tc[it];
         const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
@@ -938,10 +965,11 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
             }
         }
         destroyed = wave_sum(destroyed);
-        if (L == 0) add_destroyed(b, v, destroyed);
+        if (L == 0) tally.add(b, v, destroyed);
         wp += (u64)(hi - lo);
         wn += 1;
     }
+    if (L == 0) tally.flush(b);
     if (b.count_work) add_work(b, wp, wn);
 }
 
@@ -1646,7 +1674,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     // tail mode from this many alive vertices on (the count only falls)
     constexpr int64_t TAIL_ALIVE = 16384;
     bool tail = false;
-    LaunchTimer main_timer(kt != nullptr && h <= 3);
+    LaunchTimer main_timer(kt != nullptr && kt->time_main && h <= 3);
     // the lists need no adjacency: dead entries are skipped by their bit
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;

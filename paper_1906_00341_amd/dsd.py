@@ -33,7 +33,7 @@ OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT,
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
            "dsd_pattern_degrees", "dsd_pattern_core",
-           "dsd_last_stats",
+           "dsd_last_stats", "dsd_set_kernel_timing",
            "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
            "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
 
@@ -174,6 +174,10 @@ class Graph:
         s = Stats()
         _check(_lib.dsd_last_stats(self._h, C.byref(s)))
         return s.as_dict()
+
+    def set_kernel_timing(self, on: bool):
+        """dsd_set_kernel_timing: HIP events around every launch of the peel's main kernel."""
+        _check(_lib.dsd_set_kernel_timing(self._h, 1 if on else 0))
 
 
 def build_csr(n: int, src, dst, stream=None) -> Graph:
