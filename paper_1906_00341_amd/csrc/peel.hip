@@ -51,6 +51,8 @@
 // neighbourhood hash sits in global memory, shared by those items.
 #include <hip/hip_ext.h>
 
+#include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -1489,6 +1491,387 @@ __global__ void k_start_graphs(PeelBufs b) {
     if (g == 0) b.ctl->n_alive = b.ctl->nlist[0];
 }
 
+// ---------------------------------------------------------------- tail engine (h = 3, triangle lists)
+//
+// Once at most TE_MAX vertices are alive, the rest of a single graph's peel
+// runs in one launch of one workgroup.  First every CU helps to rewrite the
+// tail vertices' triangle rows: only pairs whose two vertices are still in
+// the tail stay, renumbered to local ids that follow the rank order (so the
+// owner rule compares local ids), packed two to a 32-bit word, each row
+// padded to a multiple of four words.  The workgroup then keeps the degrees
+// and the states of the tail vertices in LDS and takes round after round,
+// with only workgroup barriers between them: the level (the rule of the
+// round-synchronous peel: the alive vertices of degree <= k, else a new
+// level at the smallest alive degree), the frontier, and the frontier's rows
+// streamed from HBM.  Each lane takes TE_PL consecutive pairs of a row with
+// vector loads, looks up all of their states before it waits, and applies
+// each run of one first vertex with a single LDS atomic.
+
+constexpr int TE_MAX = 16384;                 // tail vertices: local ids fit 16 bits
+constexpr int TE_BLOCK = 1024;
+constexpr int TE_WAVES = TE_BLOCK / WAVE;
+constexpr int TE_PER = TE_MAX / TE_BLOCK;     // local ids per thread in the frontier scans
+constexpr int TE_PL = 8;                      // consecutive pairs per lane
+constexpr int TE_ITEM = WAVE * TE_PL;         // pairs per work item of a round
+constexpr int TE_FB = 2048;                   // frontier vertices per batch of items
+constexpr int TE_CH = 4096;                   // pairs per item of the row rewrite
+constexpr uint32_t TE_NONE = 0xffffffffu;     // padding (local ids are below 2^14)
+constexpr uint8_t TE_DEAD = 0, TE_CUR = 1, TE_ALIVE = 2;
+
+// tail membership: alive, or in the pending frontier of the next round
+__global__ void k_te_flags(const int32_t *stamp, int32_t n, const PeelCtl *c, uint32_t *flag) {
+    const int32_t r = c->round;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = stamp[v] >= r ? 1u : 0u;
+}
+
+// local id -> vertex, and each tail vertex's rewrite items
+__global__ void k_te_glob(const uint32_t *flag, const uint32_t *loc, int32_t n, const int64_t *tvoff, int32_t *glob,
+                          int64_t *ib, int32_t *count) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[v]) continue;
+        const uint32_t l = loc[v];
+        glob[l] = (int32_t)v;
+        ib[l] = (tvoff[v + 1] - tvoff[v] + TE_CH - 1) / TE_CH;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (int32_t)(loc[n - 1] + flag[n - 1]);
+}
+
+// The pairs of one rewrite item that stay inside the tail, each triangle
+// once (a row holds every triangle as (a, x) and as (x, a): the one with
+// a < x stays): counted (FILL false, into kc[it]) or written from kc[it] on
+// (FILL true), in row order, so every row stays grouped by its first vertex.
+template <bool FILL>
+__global__ __launch_bounds__(BLOCK) void k_te_pairs(const int64_t *tvoff, const int32_t *tpairs, const uint32_t *flag,
+                                                     const uint32_t *loc, const int32_t *glob, const int64_t *ib,
+                                                     int32_t A, int64_t NI, int64_t *kc, uint32_t *lp) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < NI; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        int32_t lo = 0, hi = A - 1;   // the item's vertex: the largest l with ib[l] <= it
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (ib[mid] <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t v = glob[lo];
+        const int64_t e0 = tvoff[v] + (it - ib[lo]) * TE_CH, e1 = min(tvoff[v + 1], e0 + TE_CH);
+        int64_t pos = FILL ? kc[it] : 0;
+        for (int64_t base = e0; base < e1; base += WAVE) {
+            const int64_t e = base + lane();
+            bool keep = false;
+            uint32_t val = 0;
+            if (e < e1) {
+                const int32_t a = tpairs[2 * e], x = tpairs[2 * e + 1];
+                keep = a < x && flag[a] && flag[x];   // rank order is local-id order
+                if (FILL && keep) val = (loc[a] << 16) | loc[x];
+            }
+            const u64 m = __ballot(keep);
+            if (FILL && keep) lp[pos + __popcll(m & lanemask_lt())] = val;
+            pos += __popcll(m);
+        }
+        if (!FILL && lane() == 0) kc[it] = pos;
+    }
+}
+
+// kept pairs of every tail vertex (vcnt) and its row length padded to four (rl)
+__global__ void k_te_vsum(const int64_t *ib, const int64_t *kc, int32_t A, int64_t *vcnt, int64_t *rl) {
+    for (int32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < A; l += gridDim.x * blockDim.x) {
+        int64_t s = 0;
+        for (int64_t it = ib[l]; it < ib[l + 1]; it++) s += kc[it];
+        vcnt[l] = s;
+        rl[l] = (s + 3) & ~(int64_t)3;
+    }
+}
+
+// where every rewrite item starts writing: its row's start plus the kept
+// pairs of the row's earlier items (kc: counts in, starts out)
+__global__ void k_te_ioff(const int64_t *ib, const int64_t *lrow, int32_t A, int64_t *kc) {
+    for (int32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < A; l += gridDim.x * blockDim.x) {
+        int64_t run = lrow[l];
+        for (int64_t it = ib[l]; it < ib[l + 1]; it++) {
+            const int64_t c = kc[it];
+            kc[it] = run;
+            run += c;
+        }
+    }
+}
+
+__global__ void k_te_pad(const int64_t *lrow, const int64_t *vcnt, int32_t A, uint32_t *lp) {
+    for (int32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < A; l += gridDim.x * blockDim.x)
+        for (int64_t e = lrow[l] + vcnt[l]; e < lrow[l + 1]; e++) lp[e] = TE_NONE;
+}
+
+// workgroup barrier that orders LDS only: a wave's global stores stay in
+// flight across it (nothing in the engine reads them back)
+__device__ __forceinline__ void te_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ bool te_allowed(uint32_t st, uint32_t x, uint32_t v) {
+    return st == TE_ALIVE || (st == TE_CUR && x > v);
+}
+
+// exclusive prefix of v over the workgroup; *total: the sum.  Every thread
+// calls it; buf (TE_WAVES entries) is free again on return.
+template <typename T>
+__device__ __forceinline__ T te_scan(T v, T *buf, T *total) {
+    const int wv = threadIdx.x / WAVE;
+    const T inc = wave_incl_scan(v);
+    if (lane() == WAVE - 1) buf[wv] = inc;
+    te_sync();
+    T before = 0, tot = 0;
+    for (int i = 0; i < TE_WAVES; i++) {
+        const T s = buf[i];
+        if (i < wv) before += s;
+        tot += s;
+    }
+    *total = tot;
+    te_sync();
+    return before + inc - v;
+}
+
+__device__ __forceinline__ u64 te_min(u64 v, u64 *buf) {
+    v = wave_min(v);
+    if (lane() == 0) buf[threadIdx.x / WAVE] = v;
+    te_sync();
+    u64 m = ~0ull;
+    for (int i = 0; i < TE_WAVES; i++) m = buf[i] < m ? buf[i] : m;
+    te_sync();
+    return m;
+}
+
+// this thread's TE_PER local ids: their degrees and states
+__device__ __forceinline__ void te_load(const uint32_t *sDeg, const uint8_t *sSt, int l0, uint32_t *d,
+                                        uint32_t *st) {
+    const uint4 s4 = *(const uint4 *)(sSt + l0);
+    const uint32_t sw[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint4 d4 = *(const uint4 *)(sDeg + l0 + 4 * q);
+        d[4 * q] = d4.x;
+        d[4 * q + 1] = d4.y;
+        d[4 * q + 2] = d4.z;
+        d[4 * q + 3] = d4.w;
+#pragma unroll
+        for (int j = 0; j < 4; j++) st[4 * q + j] = (sw[q] >> (8 * j)) & 0xffu;
+    }
+}
+
+__global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int32_t *glob, const int64_t *lrow,
+                                                          const uint32_t *lp, int32_t A, int32_t *err) {
+    __shared__ __align__(16) uint32_t sDeg[TE_MAX];
+    __shared__ __align__(16) uint8_t sSt[TE_MAX];
+    __shared__ uint16_t sF[TE_MAX];
+    __shared__ uint32_t sIpre[TE_FB + 1];
+    __shared__ int64_t sRow[TE_FB];
+    __shared__ uint32_t sLen[TE_FB];
+    __shared__ uint32_t sBuf32[TE_WAVES];
+    __shared__ u64 sBuf64[TE_WAVES];
+    PeelCtl *c = b.ctl;
+    GraphState *gs = b.gs;
+    const int t = threadIdx.x, wv = t / WAVE, L = lane();
+    for (int l = t; l < TE_MAX; l += TE_BLOCK) {
+        sDeg[l] = l < A ? (uint32_t)b.deg[glob[l]] : 0u;
+        sSt[l] = l < A ? TE_ALIVE : TE_DEAD;
+    }
+    int32_t r = c->round;
+    u64 k = gs[0].k, mu_alive = gs[0].mu_alive;
+    int64_t n_alive = gs[0].n_alive;
+    int32_t nlevels = gs[0].nlevels;
+    const int64_t lv_base = gs[0].lv_base;
+    bool open = gs[0].sel != 0;
+    __syncthreads();
+    const int l0 = t * TE_PER;
+    int64_t guard = 0;
+    while (n_alive > 0) {
+        if (++guard > (int64_t)A + 1) {   // every round removes at least one vertex
+            if (t == 0) *err = 1;
+            break;
+        }
+        // the frontier: alive vertices of degree <= k; none left means a new
+        // level at the smallest alive degree
+        uint32_t d[TE_PER], st[TE_PER];
+        te_load(sDeg, sSt, l0, d, st);
+        uint32_t mask = 0, nF = 0, at = 0;
+        if (!open) {
+#pragma unroll
+            for (int j = 0; j < TE_PER; j++) mask |= (st[j] == TE_ALIVE && d[j] <= k) ? 1u << j : 0u;
+            at = te_scan<uint32_t>(__popc(mask), sBuf32, &nF);
+            open = nF == 0;
+        }
+        if (open) {
+            u64 m = ~0ull;
+#pragma unroll
+            for (int j = 0; j < TE_PER; j++)
+                if (st[j] == TE_ALIVE && d[j] < m) m = d[j];
+            m = te_min(m, sBuf64);
+            k = k > m ? k : m;
+            mask = 0;
+#pragma unroll
+            for (int j = 0; j < TE_PER; j++) mask |= (st[j] == TE_ALIVE && d[j] <= k) ? 1u << j : 0u;
+            at = te_scan<uint32_t>(__popc(mask), sBuf32, &nF);
+        }
+        if (nF == 0) {   // cannot happen while vertices are alive
+            if (t == 0) *err = 2;
+            break;
+        }
+        // a removed vertex's degree slot keeps its core number (written out at
+        // the end); the first batch's rows are located here
+        for (uint32_t mm = mask; mm; mm &= mm - 1) {
+            const int l = l0 + __builtin_ctz(mm);
+            if (at < TE_FB) {
+                const int64_t r0 = lrow[l], r1 = lrow[l + 1];
+                sRow[at] = r0;
+                sLen[at] = (uint32_t)(r1 - r0);
+            }
+            sF[at++] = (uint16_t)l;
+            sSt[l] = TE_CUR;
+            sDeg[l] = (uint32_t)k;
+        }
+        te_sync();
+        // the frontier's rows, TE_FB vertices at a time
+        u64 destroyed = 0;
+        for (uint32_t f0 = 0; f0 < nF; f0 += TE_FB) {
+            const int nb = (int)min((uint32_t)TE_FB, nF - f0);
+            constexpr int PT = TE_FB / TE_BLOCK;
+            uint32_t cnt[PT], own = 0;
+#pragma unroll
+            for (int j = 0; j < PT; j++) {
+                const int q = t * PT + j;
+                cnt[j] = 0;
+                if (q < nb) {
+                    if (f0 > 0) {
+                        const int32_t l = sF[f0 + q];
+                        const int64_t r0 = lrow[l], r1 = lrow[l + 1];
+                        sRow[q] = r0;
+                        sLen[q] = (uint32_t)(r1 - r0);
+                    }
+                    cnt[j] = (sLen[q] + TE_ITEM - 1) / TE_ITEM;
+                }
+                own += cnt[j];
+            }
+            uint32_t items = 0;
+            uint32_t run = te_scan<uint32_t>(own, sBuf32, &items);
+#pragma unroll
+            for (int j = 0; j < PT; j++) {
+                const int q = t * PT + j;
+                if (q < nb) sIpre[q] = run;
+                run += cnt[j];
+            }
+            te_sync();
+            // each wave takes items wv, wv + TE_WAVES, ...; the next one's
+            // pairs are loaded while the current one is processed
+            auto locate = [&](uint32_t it, uint32_t *v, int64_t *p0, int64_t *p1) {
+                int lo = 0, hi = nb - 1;   // the item's frontier vertex: the largest q with sIpre[q] <= it
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sIpre[mid] <= it) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t ofs = (it - sIpre[lo]) * TE_ITEM;
+                *v = sF[f0 + lo];
+                *p0 = sRow[lo] + ofs;
+                *p1 = sRow[lo] + min(sLen[lo], ofs + TE_ITEM);
+            };
+            auto fetch = [&](int64_t p0, int64_t p1, uint32_t *pv) {
+                const int64_t q0 = p0 + (int64_t)L * TE_PL;
+#pragma unroll
+                for (int cq = 0; cq < TE_PL / 4; cq++) {
+                    uint4 w = make_uint4(TE_NONE, TE_NONE, TE_NONE, TE_NONE);
+                    if (q0 + 4 * cq < p1) w = *(const uint4 *)(lp + q0 + 4 * cq);
+                    pv[4 * cq] = w.x;
+                    pv[4 * cq + 1] = w.y;
+                    pv[4 * cq + 2] = w.z;
+                    pv[4 * cq + 3] = w.w;
+                }
+            };
+            uint32_t v = 0, pv[TE_PL];
+            int64_t p0 = 0, p1 = 0;
+            if ((uint32_t)wv < items) {
+                locate(wv, &v, &p0, &p1);
+                fetch(p0, p1, pv);
+            }
+            for (uint32_t it = wv; it < items; it += TE_WAVES) {
+                uint32_t vn = 0, pn[TE_PL];
+#pragma unroll
+                for (int j = 0; j < TE_PL; j++) pn[j] = TE_NONE;
+                if (it + TE_WAVES < items) {
+                    locate(it + TE_WAVES, &vn, &p0, &p1);
+                    fetch(p0, p1, pn);
+                }
+                uint32_t s2[TE_PL];   // states of a (low byte) and x (next byte)
+#pragma unroll
+                for (int j = 0; j < TE_PL; j++) {
+                    const uint32_t q = pv[j] == TE_NONE ? 0u : pv[j];
+                    s2[j] = (uint32_t)sSt[q >> 16] | ((uint32_t)sSt[q & 0xffffu] << 8);
+                }
+                uint32_t prev = TE_NONE, n1 = 0;
+                bool prev_alive = false;
+#pragma unroll
+                for (int j = 0; j < TE_PL; j++) {
+                    const uint32_t q = pv[j];
+                    const bool valid = q != TE_NONE;
+                    const uint32_t a = q >> 16, x = q & 0xffffu;
+                    const uint32_t sa = s2[j] & 0xffu, sx = s2[j] >> 8;
+                    const bool ok = valid && te_allowed(sa, a, v) && te_allowed(sx, x, v);
+                    destroyed += ok ? 1 : 0;
+                    // triangle {v, a, x} costs a and x a clique each; a's over
+                    // its run in one atomic
+                    if (ok && sx == TE_ALIVE) atomicSub(&sDeg[x], 1u);
+                    if (valid && a != prev) {
+                        if (n1 && prev_alive) atomicSub(&sDeg[prev], n1);
+                        prev = a;
+                        n1 = 0;
+                        prev_alive = sa == TE_ALIVE;
+                    }
+                    n1 += ok ? 1u : 0u;
+                }
+                if (n1 && prev_alive) atomicSub(&sDeg[prev], n1);
+                v = vn;
+#pragma unroll
+                for (int j = 0; j < TE_PL; j++) pv[j] = pn[j];
+            }
+            te_sync();   // the next batch rewrites sIpre, sRow and sLen
+        }
+        // end of the round: the level table entry of a new level holds the
+        // level, |R_k| and mu(R_k) as the round began
+        u64 gone = 0;
+        (void)te_scan<u64>(wave_sum(destroyed) * (L == 0 ? 1 : 0), sBuf64, &gone);
+        if (open && t == 0) {
+            const int64_t at_l = lv_base + nlevels;
+            b.lv_k[at_l] = k;
+            b.lv_size[at_l] = (u64)n_alive;
+            b.lv_mu[at_l] = mu_alive;
+        }
+        if (open) nlevels += 1;
+        mu_alive -= gone;
+        n_alive -= nF;
+        r += 1;
+        open = false;
+        for (uint32_t mm = mask; mm; mm &= mm - 1) sSt[l0 + __builtin_ctz(mm)] = TE_DEAD;
+        te_sync();
+    }
+    for (int l = t; l < A; l += TE_BLOCK) b.core[glob[l]] = sDeg[l];
+    if (t == 0) {
+        GraphState &g0 = gs[0];
+        g0.k = k;
+        g0.kcand = ~0ull;
+        g0.mu_alive = mu_alive;
+        g0.destroyed = 0;
+        g0.n_alive = n_alive;
+        g0.nF[0] = g0.nF[1] = 0;
+        g0.nlevels = nlevels;
+        g0.sel = 0;
+        c->n_alive = n_alive;
+        c->round = r;
+        c->nF[0] = c->nF[1] = 0;
+        c->nsel[0] = c->nsel[1] = 0;
+        c->pending = 0;
+    }
+}
+
 // Times every launch of one kernel: the launch carries a start and a stop
 // HIP event recorded by the dispatch itself (hipExtLaunchKernelGGL), so the
 // pair spans the kernel and nothing else on the stream.  The events come
@@ -1565,6 +1948,66 @@ static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
         k_engine_block<R, 1280, 12, 20, true, PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
                                                                                 0, ni + 3, gS);
     }
+}
+
+// The rest of a single graph's h = 3 peel by the tail engine, once at most
+// TE_MAX vertices are alive (the state is between two rounds).  Returns
+// false, having changed nothing, when the degrees could exceed 32 bits or
+// the rewritten rows would not fit; the environment variable
+// DSD_TAIL_ENGINE=0 turns it off.
+static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream_t s, Scratch &sc) {
+    const char *env = std::getenv("DSD_TAIL_ENGINE");
+    if (env && std::strcmp(env, "0") == 0) return false;
+    if (n_alive < 1 || n_alive > TE_MAX) return false;
+    GraphState g0;
+    DSD_HIP(hipMemcpyAsync(&g0, b.gs, sizeof(GraphState), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (g0.mu_alive >= ((u64)1 << 32) || g0.n_alive != n_alive) return false;   // degrees <= mu_alive
+    // every clique of the tail sits in 3 pairs of the rows, 4 bytes each
+    const int64_t bytes = 12 * (int64_t)g0.mu_alive + 8 * (int64_t)n + 64 * n_alive;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || bytes > (int64_t)(free_b / 4)) return false;
+    const int32_t A = (int32_t)n_alive;
+    uint32_t *flag = sc.get_n<uint32_t>(n), *loc = sc.get_n<uint32_t>(n);
+    int32_t *glob = sc.get_n<int32_t>(A), *cnt = sc.get_n<int32_t>(2);
+    int64_t *ib = sc.get_n<int64_t>(A + 1);
+    k_te_flags<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b.stamp, n, b.ctl, flag);
+    scan_exclusive_u32(flag, loc, n, s, sc);
+    fill_i32((int32_t *)(ib + A), 0, 2, s);
+    k_te_glob<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(flag, loc, n, b.tvoff, glob, ib, cnt);
+    scan_exclusive_i64(ib, ib, A + 1, s, sc);
+    int64_t hv[2] = {0, 0};
+    DSD_HIP(hipMemcpyAsync(&hv[0], ib + A, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(&hv[1], cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    const int64_t NI = hv[0];
+    if ((int32_t)hv[1] != A) throw Error(-3, "tail engine: the tail's vertex count disagrees with the alive count");
+    int64_t *kc = sc.get_n<int64_t>(NI + 1);
+    const int gp = grid_for(NI, WAVES_PER_BLOCK, 8192), gA = grid_for(A, BLOCK, 64);
+    if (NI > 0)
+        k_te_pairs<false><<<gp, BLOCK, 0, s>>>(b.tvoff, b.tpairs, flag, loc, glob, ib, A, NI, kc, nullptr);
+    // rows padded to four pairs, so that lanes load them four at a time
+    int64_t *vcnt = sc.get_n<int64_t>(A), *lrow = sc.get_n<int64_t>(A + 1);
+    fill_i32((int32_t *)(lrow + A), 0, 2, s);
+    k_te_vsum<<<gA, BLOCK, 0, s>>>(ib, kc, A, vcnt, lrow);
+    scan_exclusive_i64(lrow, lrow, A + 1, s, sc);
+    int64_t total = 0;
+    DSD_HIP(hipMemcpyAsync(&total, lrow + A, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (total > 3 * (int64_t)g0.mu_alive + 3 * (int64_t)A)
+        throw Error(-3, "tail engine: more pairs than the tail's cliques allow");
+    k_te_ioff<<<gA, BLOCK, 0, s>>>(ib, lrow, A, kc);
+    uint32_t *lp = sc.get_n<uint32_t>(total);
+    if (NI > 0) k_te_pairs<true><<<gp, BLOCK, 0, s>>>(b.tvoff, b.tpairs, flag, loc, glob, ib, A, NI, kc, lp);
+    k_te_pad<<<gA, BLOCK, 0, s>>>(lrow, vcnt, A, lp);
+    fill_i32(cnt, 0, 1, s);
+    k_tail_engine<<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
+    DSD_HIP(hipGetLastError());
+    int32_t err = 0;
+    DSD_HIP(hipMemcpyAsync(&err, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (err) throw Error(-3, "tail engine: a round removed no vertex");
+    return true;
 }
 
 PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 mu, u64 k_floor, u64 *core,
@@ -1684,7 +2127,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         compact_adjacency(b, s, sc);
         compacted_at = n_alive;
     }
+    const bool engine = listed && G == 1 && !min_degree && pattern == 0;
     while (n_alive > 0) {
+        if (engine && n_alive <= TE_MAX && tail_engine(b, n, n_alive, s, sc)) break;
         if (compacting && n_alive < compacted_at / 2) {
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;

@@ -291,6 +291,33 @@ def test_triangle_networks_built_on_the_device(fixtures, monkeypatch, cut):
     assert nets > 0
 
 
+@pytest.mark.parametrize("case", ["chung_lu", "er_planted", "rmat", "multipartite"])
+def test_tail_engine_matches_round_kernels(monkeypatch, case):
+    # the single-workgroup tail engine (the last alive vertices of an h = 3
+    # peel over triangle lists) against the per-round kernels: the same core
+    # numbers, rounds, levels, and the same exact answer from the level table
+    if case == "chung_lu":
+        n, s, d = synth.chung_lu(n=60000, avg_deg=14, beta=2.1, planted=2, plant_size=80, p=0.6, seed=5)
+    elif case == "er_planted":
+        n, s, d = synth.er_planted(seed=2)
+    elif case == "rmat":
+        n, s, d = synth.rmat(scale=15, seed=3)
+    else:
+        n, s, d, _ = synth.complete_multipartite([30, 40, 50, 60, 70], seed=4)
+    s = np.ascontiguousarray(s, np.int32)
+    d = np.ascontiguousarray(d, np.int32)
+    res = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("DSD_TAIL_ENGINE", flag)
+        g = dsd.build_csr(n, s, d)
+        core, km = dsd.clique_core(g, 3)
+        st = g.stats()
+        mem, rho = dsd.core_exact(g, 3)
+        res[flag] = (core, km, st["peel_rounds"], st["peel_levels"], rho)
+    np.testing.assert_array_equal(res["0"][0], res["1"][0])
+    assert res["0"][1:] == res["1"][1:]
+
+
 def test_bad_arguments():
     g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     for h in (0, 1, 7):
