@@ -97,6 +97,13 @@ typedef struct {
     /* networks of the exact step built on the device (h = 3 components with
      * enough edges); the others were built on the host */
     uint64_t flow_gpu_networks;
+    /* the h = 3 peel's tail engine (one workgroup takes every round once at
+     * most 16384 vertices are alive): its time (HIP events, with
+     * dsd_set_kernel_timing on; else 0), launches, the row pairs it walked
+     * (each triangle among the tail vertices once per row) and the vertices
+     * it peeled */
+    double k4_tail_ms;
+    uint64_t k4_tail_launches, k4_tail_pairs, k4_tail_vertices;
 } dsd_stats;
 
 /*

@@ -76,6 +76,10 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k4_main_nbrs = kt.main_nbrs;
     G->stats.k4_launches = kt.k4_launches;
     G->stats.k4_main_kind = (uint64_t)kt.main_kind;
+    G->stats.k4_tail_ms = kt.tail_ms;
+    G->stats.k4_tail_launches = kt.tail_launches;
+    G->stats.k4_tail_pairs = kt.tail_pairs;
+    G->stats.k4_tail_vertices = kt.tail_vertices;
 }
 
 // clique-degrees (rank space) and mu; throws on overflow

@@ -1613,33 +1613,42 @@ __device__ __forceinline__ bool te_allowed(uint32_t st, uint32_t x, uint32_t v) 
     return st == TE_ALIVE || (st == TE_CUR && x > v);
 }
 
-// exclusive prefix of v over the workgroup; *total: the sum.  Every thread
-// calls it; buf (TE_WAVES entries) is free again on return.
-template <typename T>
-__device__ __forceinline__ T te_scan(T v, T *buf, T *total) {
-    const int wv = threadIdx.x / WAVE;
-    const T inc = wave_incl_scan(v);
-    if (lane() == WAVE - 1) buf[wv] = inc;
-    te_sync();
-    T before = 0, tot = 0;
-    for (int i = 0; i < TE_WAVES; i++) {
-        const T s = buf[i];
-        if (i < wv) before += s;
-        tot += s;
-    }
-    *total = tot;
-    te_sync();
-    return before + inc - v;
-}
+// Workgroup reductions, double-buffered so that one barrier suffices: a
+// call writes one half and reads it after the barrier; the next call uses
+// the other half, and the call after that is behind the next call's barrier.
+struct TeRed {
+    uint32_t cnt[2][TE_WAVES];
+    u64 mn[2][TE_WAVES];
+    u64 sum[2][TE_WAVES];
+};
 
-__device__ __forceinline__ u64 te_min(u64 v, u64 *buf) {
-    v = wave_min(v);
-    if (lane() == 0) buf[threadIdx.x / WAVE] = v;
+// exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall) and
+// sum of s (*sall) over the workgroup; every thread calls it with the same par
+__device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, u64 m, u64 s, uint32_t *ctot,
+                                              u64 *mall, u64 *sall) {
+    const int wv = threadIdx.x / WAVE;
+    const uint32_t inc = wave_incl_scan(c);
+    const u64 wm = wave_min(m), ws = wave_sum(s);
+    if (lane() == WAVE - 1) R.cnt[par][wv] = inc;
+    if (lane() == 0) {
+        R.mn[par][wv] = wm;
+        R.sum[par][wv] = ws;
+    }
     te_sync();
-    u64 m = ~0ull;
-    for (int i = 0; i < TE_WAVES; i++) m = buf[i] < m ? buf[i] : m;
-    te_sync();
-    return m;
+    uint32_t before = 0, tot = 0;
+    u64 mm = ~0ull, ss = 0;
+    for (int i = 0; i < TE_WAVES; i++) {
+        const uint32_t x = R.cnt[par][i];
+        if (i < wv) before += x;
+        tot += x;
+        mm = R.mn[par][i] < mm ? R.mn[par][i] : mm;
+        ss += R.sum[par][i];
+    }
+    par ^= 1;
+    *ctot = tot;
+    *mall = mm;
+    *sall = ss;
+    return before + inc - c;
 }
 
 // this thread's TE_PER local ids: their degrees and states
@@ -1659,16 +1668,23 @@ __device__ __forceinline__ void te_load(const uint32_t *sDeg, const uint8_t *sSt
     }
 }
 
+// the frontier flags of this thread's ids at level k
+__device__ __forceinline__ uint32_t te_mask(const uint32_t *d, const uint32_t *st, u64 k) {
+    uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < TE_PER; j++) mask |= (st[j] == TE_ALIVE && d[j] <= k) ? 1u << j : 0u;
+    return mask;
+}
+
+// lrow (A + 1 entries) below 2^32: the row starts live in LDS
 __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int32_t *glob, const int64_t *lrow,
                                                           const uint32_t *lp, int32_t A, int32_t *err) {
     __shared__ __align__(16) uint32_t sDeg[TE_MAX];
     __shared__ __align__(16) uint8_t sSt[TE_MAX];
-    __shared__ uint16_t sF[TE_MAX];
-    __shared__ uint32_t sIpre[TE_FB + 1];
-    __shared__ int64_t sRow[TE_FB];
-    __shared__ uint32_t sLen[TE_FB];
-    __shared__ uint32_t sBuf32[TE_WAVES];
-    __shared__ u64 sBuf64[TE_WAVES];
+    __shared__ uint32_t sRs[TE_MAX + 1];
+    __shared__ uint16_t sF[TE_FB];
+    __shared__ uint32_t sIpre[TE_FB];
+    __shared__ TeRed R;
     PeelCtl *c = b.ctl;
     GraphState *gs = b.gs;
     const int t = threadIdx.x, wv = t / WAVE, L = lane();
@@ -1676,12 +1692,15 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         sDeg[l] = l < A ? (uint32_t)b.deg[glob[l]] : 0u;
         sSt[l] = l < A ? TE_ALIVE : TE_DEAD;
     }
+    for (int l = t; l <= A; l += TE_BLOCK) sRs[l] = (uint32_t)lrow[l];
     int32_t r = c->round;
     u64 k = gs[0].k, mu_alive = gs[0].mu_alive;
     int64_t n_alive = gs[0].n_alive;
     int32_t nlevels = gs[0].nlevels;
     const int64_t lv_base = gs[0].lv_base;
     bool open = gs[0].sel != 0;
+    int par = 0;
+    u64 destroyed = 0;   // this thread's share of the current round (summed at the next round's start)
     __syncthreads();
     const int l0 = t * TE_PER;
     int64_t guard = 0;
@@ -1691,92 +1710,95 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             break;
         }
         // the frontier: alive vertices of degree <= k; none left means a new
-        // level at the smallest alive degree
-        uint32_t d[TE_PER], st[TE_PER];
-        te_load(sDeg, sSt, l0, d, st);
-        uint32_t mask = 0, nF = 0, at = 0;
-        if (!open) {
-#pragma unroll
-            for (int j = 0; j < TE_PER; j++) mask |= (st[j] == TE_ALIVE && d[j] <= k) ? 1u << j : 0u;
-            at = te_scan<uint32_t>(__popc(mask), sBuf32, &nF);
-            open = nF == 0;
-        }
-        if (open) {
-            u64 m = ~0ull;
+        // level at the smallest alive degree.  The same reduction ends the
+        // previous round (its destroyed cliques).
+        uint32_t mask = 0, nF = 0;
+        u64 mn = ~0ull;
+        {
+            uint32_t d[TE_PER], st[TE_PER];
+            te_load(sDeg, sSt, l0, d, st);
+            mask = te_mask(d, st, k);
 #pragma unroll
             for (int j = 0; j < TE_PER; j++)
-                if (st[j] == TE_ALIVE && d[j] < m) m = d[j];
-            m = te_min(m, sBuf64);
-            k = k > m ? k : m;
-            mask = 0;
-#pragma unroll
-            for (int j = 0; j < TE_PER; j++) mask |= (st[j] == TE_ALIVE && d[j] <= k) ? 1u << j : 0u;
-            at = te_scan<uint32_t>(__popc(mask), sBuf32, &nF);
+                if (st[j] == TE_ALIVE && d[j] < mn) mn = d[j];
+        }
+        u64 mall = 0, gone = 0;
+        uint32_t at = te_reduce(R, par, __popc(mask), mn, destroyed, &nF, &mall, &gone);
+        destroyed = 0;
+        mu_alive -= gone;
+        if (nF == 0) open = true;
+        if (open) {
+            k = k > mall ? k : mall;
+            uint32_t d[TE_PER], st[TE_PER];
+            te_load(sDeg, sSt, l0, d, st);   // unchanged since the reduction read them
+            mask = te_mask(d, st, k);
+            u64 u1, u2;
+            at = te_reduce(R, par, __popc(mask), ~0ull, 0, &nF, &u1, &u2);
         }
         if (nF == 0) {   // cannot happen while vertices are alive
             if (t == 0) *err = 2;
             break;
         }
-        // a removed vertex's degree slot keeps its core number (written out at
-        // the end); the first batch's rows are located here
+        // the level table entry of a new level: the level, |R_k| and mu(R_k)
+        // as its first round begins
+        if (open && t == 0) {
+            const int64_t at_l = lv_base + nlevels;
+            b.lv_k[at_l] = k;
+            b.lv_size[at_l] = (u64)n_alive;
+            b.lv_mu[at_l] = mu_alive;
+        }
+        // frontier vertices leave: a removed vertex's degree slot keeps its
+        // core number (written out at the end)
         for (uint32_t mm = mask; mm; mm &= mm - 1) {
             const int l = l0 + __builtin_ctz(mm);
-            if (at < TE_FB) {
-                const int64_t r0 = lrow[l], r1 = lrow[l + 1];
-                sRow[at] = r0;
-                sLen[at] = (uint32_t)(r1 - r0);
-            }
-            sF[at++] = (uint16_t)l;
             sSt[l] = TE_CUR;
             sDeg[l] = (uint32_t)k;
         }
-        te_sync();
         // the frontier's rows, TE_FB vertices at a time
-        u64 destroyed = 0;
         for (uint32_t f0 = 0; f0 < nF; f0 += TE_FB) {
             const int nb = (int)min((uint32_t)TE_FB, nF - f0);
+            uint32_t q = at;
+            for (uint32_t mm = mask; mm; mm &= mm - 1, q++)
+                if (q >= f0 && q < f0 + TE_FB) sF[q - f0] = (uint16_t)(l0 + __builtin_ctz(mm));
+            te_sync();
             constexpr int PT = TE_FB / TE_BLOCK;
             uint32_t cnt[PT], own = 0;
 #pragma unroll
             for (int j = 0; j < PT; j++) {
-                const int q = t * PT + j;
+                const int qq = t * PT + j;
                 cnt[j] = 0;
-                if (q < nb) {
-                    if (f0 > 0) {
-                        const int32_t l = sF[f0 + q];
-                        const int64_t r0 = lrow[l], r1 = lrow[l + 1];
-                        sRow[q] = r0;
-                        sLen[q] = (uint32_t)(r1 - r0);
-                    }
-                    cnt[j] = (sLen[q] + TE_ITEM - 1) / TE_ITEM;
+                if (qq < nb) {
+                    const uint32_t l = sF[qq];
+                    cnt[j] = (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
                 }
                 own += cnt[j];
             }
             uint32_t items = 0;
-            uint32_t run = te_scan<uint32_t>(own, sBuf32, &items);
+            u64 u1, u2;
+            uint32_t run = te_reduce(R, par, own, ~0ull, 0, &items, &u1, &u2);
 #pragma unroll
             for (int j = 0; j < PT; j++) {
-                const int q = t * PT + j;
-                if (q < nb) sIpre[q] = run;
+                const int qq = t * PT + j;
+                if (qq < nb) sIpre[qq] = run;
                 run += cnt[j];
             }
             te_sync();
             // each wave takes items wv, wv + TE_WAVES, ...; the next one's
             // pairs are loaded while the current one is processed
-            auto locate = [&](uint32_t it, uint32_t *v, int64_t *p0, int64_t *p1) {
+            auto locate = [&](uint32_t it, uint32_t *v, uint32_t *p0, uint32_t *p1) {
                 int lo = 0, hi = nb - 1;   // the item's frontier vertex: the largest q with sIpre[q] <= it
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (sIpre[mid] <= it) lo = mid;
                     else hi = mid - 1;
                 }
-                const uint32_t ofs = (it - sIpre[lo]) * TE_ITEM;
-                *v = sF[f0 + lo];
-                *p0 = sRow[lo] + ofs;
-                *p1 = sRow[lo] + min(sLen[lo], ofs + TE_ITEM);
+                const uint32_t l = sF[lo], ofs = (it - sIpre[lo]) * TE_ITEM;
+                *v = l;
+                *p0 = sRs[l] + ofs;
+                *p1 = min(sRs[l + 1], *p0 + TE_ITEM);
             };
-            auto fetch = [&](int64_t p0, int64_t p1, uint32_t *pv) {
-                const int64_t q0 = p0 + (int64_t)L * TE_PL;
+            auto fetch = [&](uint32_t p0, uint32_t p1, uint32_t *pv) {
+                const uint32_t q0 = p0 + (uint32_t)L * TE_PL;
 #pragma unroll
                 for (int cq = 0; cq < TE_PL / 4; cq++) {
                     uint4 w = make_uint4(TE_NONE, TE_NONE, TE_NONE, TE_NONE);
@@ -1787,8 +1809,7 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                     pv[4 * cq + 3] = w.w;
                 }
             };
-            uint32_t v = 0, pv[TE_PL];
-            int64_t p0 = 0, p1 = 0;
+            uint32_t v = 0, pv[TE_PL], p0 = 0, p1 = 0;
             if ((uint32_t)wv < items) {
                 locate(wv, &v, &p0, &p1);
                 fetch(p0, p1, pv);
@@ -1804,16 +1825,16 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                 uint32_t s2[TE_PL];   // states of a (low byte) and x (next byte)
 #pragma unroll
                 for (int j = 0; j < TE_PL; j++) {
-                    const uint32_t q = pv[j] == TE_NONE ? 0u : pv[j];
-                    s2[j] = (uint32_t)sSt[q >> 16] | ((uint32_t)sSt[q & 0xffffu] << 8);
+                    const uint32_t qv = pv[j] == TE_NONE ? 0u : pv[j];
+                    s2[j] = (uint32_t)sSt[qv >> 16] | ((uint32_t)sSt[qv & 0xffffu] << 8);
                 }
                 uint32_t prev = TE_NONE, n1 = 0;
                 bool prev_alive = false;
 #pragma unroll
                 for (int j = 0; j < TE_PL; j++) {
-                    const uint32_t q = pv[j];
-                    const bool valid = q != TE_NONE;
-                    const uint32_t a = q >> 16, x = q & 0xffffu;
+                    const uint32_t qv = pv[j];
+                    const bool valid = qv != TE_NONE;
+                    const uint32_t a = qv >> 16, x = qv & 0xffffu;
                     const uint32_t sa = s2[j] & 0xffu, sx = s2[j] >> 8;
                     const bool ok = valid && te_allowed(sa, a, v) && te_allowed(sx, x, v);
                     destroyed += ok ? 1 : 0;
@@ -1833,25 +1854,22 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
 #pragma unroll
                 for (int j = 0; j < TE_PL; j++) pv[j] = pn[j];
             }
-            te_sync();   // the next batch rewrites sIpre, sRow and sLen
+            te_sync();   // the next batch rewrites sF and sIpre; the next round reads the degrees
         }
-        // end of the round: the level table entry of a new level holds the
-        // level, |R_k| and mu(R_k) as the round began
-        u64 gone = 0;
-        (void)te_scan<u64>(wave_sum(destroyed) * (L == 0 ? 1 : 0), sBuf64, &gone);
-        if (open && t == 0) {
-            const int64_t at_l = lv_base + nlevels;
-            b.lv_k[at_l] = k;
-            b.lv_size[at_l] = (u64)n_alive;
-            b.lv_mu[at_l] = mu_alive;
-        }
+        // end of the round; each thread retires its own frontier entries (the
+        // next round's reduction orders this before any other thread's reads)
         if (open) nlevels += 1;
-        mu_alive -= gone;
         n_alive -= nF;
         r += 1;
         open = false;
         for (uint32_t mm = mask; mm; mm &= mm - 1) sSt[l0 + __builtin_ctz(mm)] = TE_DEAD;
-        te_sync();
+    }
+    {
+        u64 u1;
+        uint32_t u0;
+        u64 gone = 0;
+        (void)te_reduce(R, par, 0, ~0ull, destroyed, &u0, &u1, &gone);
+        mu_alive -= gone;
     }
     for (int l = t; l < A; l += TE_BLOCK) b.core[glob[l]] = sDeg[l];
     if (t == 0) {
@@ -1955,7 +1973,8 @@ static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
 // false, having changed nothing, when the degrees could exceed 32 bits or
 // the rewritten rows would not fit; the environment variable
 // DSD_TAIL_ENGINE=0 turns it off.
-static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream_t s, Scratch &sc) {
+static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream_t s, Scratch &sc,
+                        KernelTimes *kt) {
     const char *env = std::getenv("DSD_TAIL_ENGINE");
     if (env && std::strcmp(env, "0") == 0) return false;
     if (n_alive < 1 || n_alive > TE_MAX) return false;
@@ -1996,16 +2015,42 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     DSD_HIP(hipStreamSynchronize(s));
     if (total > 3 * (int64_t)g0.mu_alive + 3 * (int64_t)A)
         throw Error(-3, "tail engine: more pairs than the tail's cliques allow");
+    if (total >= ((int64_t)1 << 32)) return false;   // row starts are kept in 32 bits
+    u64 walked = 0;   // pairs the engine walks: every kept pair once
+    if (kt) {
+        u64 *s2 = sc.get_n<u64>(2);
+        sum_u64_128((const u64 *)kc, NI, s2, s, sc);
+        DSD_HIP(hipMemcpyAsync(&walked, s2, sizeof(u64), hipMemcpyDeviceToHost, s));
+    }
     k_te_ioff<<<gA, BLOCK, 0, s>>>(ib, lrow, A, kc);
     uint32_t *lp = sc.get_n<uint32_t>(total);
     if (NI > 0) k_te_pairs<true><<<gp, BLOCK, 0, s>>>(b.tvoff, b.tpairs, flag, loc, glob, ib, A, NI, kc, lp);
     k_te_pad<<<gA, BLOCK, 0, s>>>(lrow, vcnt, A, lp);
     fill_i32(cnt, 0, 1, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt && kt->time_main) {
+        DSD_HIP(hipEventCreate(&e0));
+        DSD_HIP(hipEventCreate(&e1));
+        DSD_HIP(hipEventRecord(e0, s));
+    }
     k_tail_engine<<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
     DSD_HIP(hipGetLastError());
+    if (e1) DSD_HIP(hipEventRecord(e1, s));
     int32_t err = 0;
     DSD_HIP(hipMemcpyAsync(&err, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
+    if (kt) {
+        if (e1) {
+            float ms = 0;
+            DSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+            kt->tail_ms += ms;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        kt->tail_launches += 1;
+        kt->tail_pairs += walked;
+        kt->tail_vertices += (u64)A;
+    }
     if (err) throw Error(-3, "tail engine: a round removed no vertex");
     return true;
 }
@@ -2129,7 +2174,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     }
     const bool engine = listed && G == 1 && !min_degree && pattern == 0;
     while (n_alive > 0) {
-        if (engine && n_alive <= TE_MAX && tail_engine(b, n, n_alive, s, sc)) break;
+        if (engine && n_alive <= TE_MAX && tail_engine(b, n, n_alive, s, sc, kt)) break;
         if (compacting && n_alive < compacted_at / 2) {
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;
