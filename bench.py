@@ -383,6 +383,7 @@ def main() -> int:
             "core_exact_host_network": avg("t_flow_build_ms", "exact"),
             "core_exact_host_maxflow": avg("t_flow_ms", "exact"),
             "core_exact_flow_setup": avg("t_flow_setup_ms", "exact"),
+            "core_exact_search": avg("t_exact_ms", "exact"),
             "core_exact_total": avg("t_total_ms", "exact"),
         },
         "kernel_rates": {

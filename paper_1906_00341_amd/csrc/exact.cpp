@@ -436,6 +436,34 @@ uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int3
     return c;
 }
 
+// h-cliques inside verts: the triangles of a large set on the device (the
+// listing that builds the h = 3 networks), everything else on the host
+static uint64_t count_cliques(const LocatedCore &lc, int h, const std::vector<int32_t> &verts) {
+    if (h == 3 && gpu_net_min_edges() >= 0 && verts.size() >= 2 && verts.size() <= (size_t)TRI_NET_MAX_NV) {
+        std::vector<int32_t> sorted(verts);
+        std::sort(sorted.begin(), sorted.end());
+        std::vector<int32_t> idx(lc.rank.size(), -1);
+        for (size_t i = 0; i < sorted.size(); i++) idx[sorted[i]] = (int32_t)i;
+        const int nv = (int)sorted.size();
+        std::vector<int64_t> so(nv + 1, 0), fwd(nv);
+        std::vector<int32_t> sa;
+        for (int i = 0; i < nv; i++) {
+            const int32_t v = sorted[i];
+            for (int64_t e = lc.off[v]; e < lc.off[v + 1]; e++)
+                if (idx[lc.adj[e]] >= 0) sa.push_back(idx[lc.adj[e]]);   // idx is increasing: rows stay sorted
+            so[i + 1] = (int64_t)sa.size();
+        }
+        for (int i = 0; i < nv; i++) {
+            int64_t a = so[i];
+            while (a < so[i + 1] && sa[a] < i) a++;
+            fwd[i] = a;
+        }
+        if ((int64_t)sa.size() / 2 >= std::max<int64_t>(1, gpu_net_min_edges()))
+            return count_triangles_device(nv, so.data(), sa.data(), fwd.data());
+    }
+    return count_cliques_host(lc, h, verts);
+}
+
 // ---------------------------------------------------------------- one component
 
 static uint64_t ceil_div_u(uint64_t a, uint64_t b) { return a / b + (a % b != 0); }
@@ -804,10 +832,14 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
         while (j < S && lc.label[order[j]] == lc.label[order[i]]) c.v.push_back(order[j++]);
         i = j;
         if (c.v.size() < 2) continue;
-        c.dens = reduced(count_cliques_host(lc, h, c.v), c.v.size());
         comps.push_back(std::move(c));
     }
-    std::stable_sort(comps.begin(), comps.end(), [](const Comp &a, const Comp &b) { return frac_less(b.dens, a.dens); });
+    // densest components first (one component needs no order)
+    if (comps.size() > 1) {
+        for (Comp &c : comps) c.dens = reduced(count_cliques(lc, h, c.v), c.v.size());
+        std::stable_sort(comps.begin(), comps.end(),
+                         [](const Comp &a, const Comp &b) { return frac_less(b.dens, a.dens); });
+    }
     bool improved = false;
     std::vector<int32_t> found, cur, built;
     for (const Comp &c : comps) {
@@ -840,7 +872,7 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
             st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
             if (!denser) break;
             U = found;
-            lc_l = reduced(count_cliques_host(lc, h, U), U.size());
+            lc_l = reduced(count_cliques(lc, h, U), U.size());
         }
         if (!U.empty() && frac_less(l, lc_l)) {
             l = lc_l;
@@ -882,7 +914,7 @@ bool exact_search_query(const LocatedCore &lc, int h, uint64_t x, const std::vec
         st.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
         st.flow_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
         if (!denser) break;
-        const Rational d = reduced(count_cliques_host(lc, h, found), found.size());
+        const Rational d = reduced(count_cliques(lc, h, found), found.size());
         if (!frac_less(l, d)) break;
         l = d;
         best = found;

@@ -666,6 +666,39 @@ std::unique_ptr<GpuFlow> GpuFlow::triangles(int nv, const int64_t *so, const int
     return g;
 }
 
+uint64_t count_triangles_device(int nv, const int64_t *so, const int32_t *sa, const int64_t *fwd) {
+    if (nv < 1 || nv > TRI_NET_MAX_NV) throw Error(-5, "triangle count: vertex count out of range");
+    std::vector<int64_t> ebase(nv + 1, 0);
+    for (int i = 0; i < nv; i++) ebase[i + 1] = ebase[i] + (so[i + 1] - fwd[i]);
+    const int64_t np = ebase[nv], ns = so[nv];
+    if (np == 0) return 0;
+    hipStream_t s = nullptr;
+    DSD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    uint64_t total[2] = {0, 0};
+    try {
+        Scratch sc;
+        int64_t *d_so = sc.get_n<int64_t>(nv + 1), *d_fwd = sc.get_n<int64_t>(nv);
+        int64_t *d_eb = sc.get_n<int64_t>(nv + 1), *tcnt = sc.get_n<int64_t>(np);
+        int32_t *d_sa = sc.get_n<int32_t>(ns);
+        u64 *d_tot = sc.get_n<u64>(2);
+        DSD_HIP(hipMemcpyAsync(d_so, so, (size_t)(nv + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DSD_HIP(hipMemcpyAsync(d_fwd, fwd, (size_t)nv * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DSD_HIP(hipMemcpyAsync(d_eb, ebase.data(), (size_t)(nv + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DSD_HIP(hipMemcpyAsync(d_sa, sa, (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        const int W = (nv + 31) / 32;
+        k_tn_tri<false><<<nv, BLOCK, (size_t)2 * W * sizeof(uint32_t), s>>>(d_so, d_sa, d_fwd, d_eb, nv, W, tcnt,
+                                                                            nullptr, 0, nullptr, nullptr, nullptr);
+        sum_u64_128((const u64 *)tcnt, np, d_tot, s, sc);
+        DSD_HIP(hipMemcpyAsync(total, d_tot, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    DSD_HIP(hipStreamDestroy(s));
+    return total[0];
+}
+
 int GpuFlow::nodes() const { return p_->b.n; }
 int64_t GpuFlow::arcs() const { return p_->E; }
 

@@ -64,4 +64,8 @@ private:
 // largest component triangles() takes (its LDS bitmap has one bit per vertex)
 constexpr int TRI_NET_MAX_NV = 1 << 17;
 
+// Triangles of a vertex set given as for GpuFlow::triangles (nv <=
+// TRI_NET_MAX_NV), counted on the device with the same listing.
+uint64_t count_triangles_device(int nv, const int64_t *so, const int32_t *sa, const int64_t *fwd);
+
 }  // namespace dsd

@@ -1613,42 +1613,72 @@ __device__ __forceinline__ bool te_allowed(uint32_t st, uint32_t x, uint32_t v) 
     return st == TE_ALIVE || (st == TE_CUR && x > v);
 }
 
+// Wave reductions in VALU cross-lane operations (DPP: quad permutations and
+// row mirrors reduce every 16-lane row, row broadcasts join the rows; lane
+// 63 ends with the total, which readlane hands to every lane).  id: the
+// operation's identity, taken by lanes a row mask leaves out.
+template <bool MIN>
+__device__ __forceinline__ uint32_t te_dpp_op(uint32_t a, uint32_t b) {
+    return MIN ? (a < b ? a : b) : a + b;
+}
+template <bool MIN>
+__device__ __forceinline__ uint32_t te_wave_reduce(uint32_t v) {
+    const int id = MIN ? -1 : 0;
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0xb1, 0xf, 0xf, false));   // quad [1,0,3,2]
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x4e, 0xf, 0xf, false));   // quad [2,3,0,1]
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xf, 0xf, false));  // half-row mirror
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xf, 0xf, false));  // row mirror
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xa, 0xf, false));  // row 15 -> rows 1, 3
+    v = te_dpp_op<MIN>(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xc, 0xf, false));  // lane 31 -> rows 2, 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// exclusive prefix of v over the wave's lanes, from one ballot per bit in use
+__device__ __forceinline__ uint32_t te_wave_prefix(uint32_t v, uint32_t *total) {
+    uint32_t pre = 0, tot = 0;
+    const u64 lt = lanemask_lt();
+    for (int bit = 0; bit < 32; bit++) {
+        if (__ballot((v >> bit) != 0) == 0) break;
+        const u64 m = __ballot((v >> bit) & 1u);
+        pre += (uint32_t)__popcll(m & lt) << bit;
+        tot += (uint32_t)__popcll(m) << bit;
+    }
+    *total = tot;
+    return pre;
+}
+
 // Workgroup reductions, double-buffered so that one barrier suffices: a
 // call writes one half and reads it after the barrier; the next call uses
 // the other half, and the call after that is behind the next call's barrier.
 struct TeRed {
     uint32_t cnt[2][TE_WAVES];
-    u64 mn[2][TE_WAVES];
-    u64 sum[2][TE_WAVES];
+    uint32_t mn[2][TE_WAVES];
+    uint32_t sum[2][TE_WAVES];
 };
 
 // exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall) and
 // sum of s (*sall) over the workgroup; every thread calls it with the same par
-__device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, u64 m, u64 s, uint32_t *ctot,
-                                              u64 *mall, u64 *sall) {
-    const int wv = threadIdx.x / WAVE;
-    const uint32_t inc = wave_incl_scan(c);
-    const u64 wm = wave_min(m), ws = wave_sum(s);
-    if (lane() == WAVE - 1) R.cnt[par][wv] = inc;
-    if (lane() == 0) {
-        R.mn[par][wv] = wm;
-        R.sum[par][wv] = ws;
+__device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, uint32_t m, uint32_t s, uint32_t *ctot,
+                                              uint32_t *mall, uint32_t *sall) {
+    const int wv = threadIdx.x / WAVE, L = lane();
+    uint32_t wtot = 0;
+    const uint32_t pre = te_wave_prefix(c, &wtot);
+    const uint32_t wmin = te_wave_reduce<true>(m), wsum = te_wave_reduce<false>(s);
+    if (L == 0) {
+        R.cnt[par][wv] = wtot;
+        R.mn[par][wv] = wmin;
+        R.sum[par][wv] = wsum;
     }
     te_sync();
-    uint32_t before = 0, tot = 0;
-    u64 mm = ~0ull, ss = 0;
-    for (int i = 0; i < TE_WAVES; i++) {
-        const uint32_t x = R.cnt[par][i];
-        if (i < wv) before += x;
-        tot += x;
-        mm = R.mn[par][i] < mm ? R.mn[par][i] : mm;
-        ss += R.sum[par][i];
-    }
+    const uint32_t ci = L < TE_WAVES ? R.cnt[par][L] : 0u;
+    const uint32_t mi = L < TE_WAVES ? R.mn[par][L] : 0xffffffffu;
+    const uint32_t si = L < TE_WAVES ? R.sum[par][L] : 0u;
+    const uint32_t before = te_wave_reduce<false>(L < wv ? ci : 0u);
+    *ctot = te_wave_reduce<false>(ci);
+    *mall = te_wave_reduce<true>(mi);
+    *sall = te_wave_reduce<false>(si);
     par ^= 1;
-    *ctot = tot;
-    *mall = mm;
-    *sall = ss;
-    return before + inc - c;
+    return before + pre;
 }
 
 // this thread's TE_PER local ids: their degrees and states
@@ -1700,7 +1730,8 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
     const int64_t lv_base = gs[0].lv_base;
     bool open = gs[0].sel != 0;
     int par = 0;
-    u64 destroyed = 0;   // this thread's share of the current round (summed at the next round's start)
+    uint32_t destroyed = 0;   // this thread's share of the current round (summed at the next round's start;
+                              // a round destroys at most mu_alive < 2^32 cliques)
     __syncthreads();
     const int l0 = t * TE_PER;
     int64_t guard = 0;
@@ -1712,8 +1743,7 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         // the frontier: alive vertices of degree <= k; none left means a new
         // level at the smallest alive degree.  The same reduction ends the
         // previous round (its destroyed cliques).
-        uint32_t mask = 0, nF = 0;
-        u64 mn = ~0ull;
+        uint32_t mask = 0, nF = 0, mn = 0xffffffffu;
         {
             uint32_t d[TE_PER], st[TE_PER];
             te_load(sDeg, sSt, l0, d, st);
@@ -1722,18 +1752,18 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             for (int j = 0; j < TE_PER; j++)
                 if (st[j] == TE_ALIVE && d[j] < mn) mn = d[j];
         }
-        u64 mall = 0, gone = 0;
+        uint32_t mall = 0, gone = 0;
         uint32_t at = te_reduce(R, par, __popc(mask), mn, destroyed, &nF, &mall, &gone);
         destroyed = 0;
         mu_alive -= gone;
         if (nF == 0) open = true;
         if (open) {
-            k = k > mall ? k : mall;
+            k = k > (u64)mall ? k : (u64)mall;
             uint32_t d[TE_PER], st[TE_PER];
             te_load(sDeg, sSt, l0, d, st);   // unchanged since the reduction read them
             mask = te_mask(d, st, k);
-            u64 u1, u2;
-            at = te_reduce(R, par, __popc(mask), ~0ull, 0, &nF, &u1, &u2);
+            uint32_t u1, u2;
+            at = te_reduce(R, par, __popc(mask), 0xffffffffu, 0u, &nF, &u1, &u2);
         }
         if (nF == 0) {   // cannot happen while vertices are alive
             if (t == 0) *err = 2;
@@ -1773,9 +1803,8 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                 }
                 own += cnt[j];
             }
-            uint32_t items = 0;
-            u64 u1, u2;
-            uint32_t run = te_reduce(R, par, own, ~0ull, 0, &items, &u1, &u2);
+            uint32_t items = 0, u1, u2;
+            uint32_t run = te_reduce(R, par, own, 0xffffffffu, 0u, &items, &u1, &u2);
 #pragma unroll
             for (int j = 0; j < PT; j++) {
                 const int qq = t * PT + j;
@@ -1828,28 +1857,25 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                     const uint32_t qv = pv[j] == TE_NONE ? 0u : pv[j];
                     s2[j] = (uint32_t)sSt[qv >> 16] | ((uint32_t)sSt[qv & 0xffffu] << 8);
                 }
-                uint32_t prev = TE_NONE, n1 = 0;
-                bool prev_alive = false;
+                // triangle {v, a, x} costs a and x a clique each: x's loss goes
+                // at once (0 for a removed vertex; a padding word touches slot
+                // 0 with 0), a's are summed over the lane's run of equal a
+                uint32_t acc = 0;
 #pragma unroll
                 for (int j = 0; j < TE_PL; j++) {
-                    const uint32_t qv = pv[j];
-                    const bool valid = qv != TE_NONE;
+                    const uint32_t qv = pv[j] == TE_NONE ? 0u : pv[j];
                     const uint32_t a = qv >> 16, x = qv & 0xffffu;
                     const uint32_t sa = s2[j] & 0xffu, sx = s2[j] >> 8;
-                    const bool ok = valid && te_allowed(sa, a, v) && te_allowed(sx, x, v);
-                    destroyed += ok ? 1 : 0;
-                    // triangle {v, a, x} costs a and x a clique each; a's over
-                    // its run in one atomic
-                    if (ok && sx == TE_ALIVE) atomicSub(&sDeg[x], 1u);
-                    if (valid && a != prev) {
-                        if (n1 && prev_alive) atomicSub(&sDeg[prev], n1);
-                        prev = a;
-                        n1 = 0;
-                        prev_alive = sa == TE_ALIVE;
+                    const bool ok = pv[j] != TE_NONE && te_allowed(sa, a, v) && te_allowed(sx, x, v);
+                    destroyed += ok ? 1u : 0u;
+                    atomicSub(&sDeg[x], (ok && sx == TE_ALIVE) ? 1u : 0u);
+                    acc += (ok && sa == TE_ALIVE) ? 1u : 0u;
+                    const bool last = j == TE_PL - 1 || (pv[j + (j < TE_PL - 1)] >> 16) != a;
+                    if (last && acc) {
+                        atomicSub(&sDeg[a], acc);
+                        acc = 0;
                     }
-                    n1 += ok ? 1u : 0u;
                 }
-                if (n1 && prev_alive) atomicSub(&sDeg[prev], n1);
                 v = vn;
 #pragma unroll
                 for (int j = 0; j < TE_PL; j++) pv[j] = pn[j];
@@ -1865,10 +1891,8 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         for (uint32_t mm = mask; mm; mm &= mm - 1) sSt[l0 + __builtin_ctz(mm)] = TE_DEAD;
     }
     {
-        u64 u1;
-        uint32_t u0;
-        u64 gone = 0;
-        (void)te_reduce(R, par, 0, ~0ull, destroyed, &u0, &u1, &gone);
+        uint32_t u0, u1, gone = 0;
+        (void)te_reduce(R, par, 0u, 0xffffffffu, destroyed, &u0, &u1, &gone);
         mu_alive -= gone;
     }
     for (int l = t; l < A; l += TE_BLOCK) b.core[glob[l]] = sDeg[l];
