@@ -1491,14 +1491,14 @@ __global__ void k_start_graphs(PeelBufs b) {
     if (g == 0) b.ctl->n_alive = b.ctl->nlist[0];
 }
 
-// ---------------------------------------------------------------- tail engine (h = 3, triangle lists)
+// ---------------------------------------------------------------- tail engine (h = 3 with triangle lists, h = 2)
 //
 // Once at most TE_MAX vertices are alive, the rest of a single graph's peel
 // runs in one launch of one workgroup.  First every CU helps to rewrite the
-// tail vertices' triangle rows: only pairs whose two vertices are still in
-// the tail stay, renumbered to local ids that follow the rank order (so the
-// owner rule compares local ids), packed two to a 32-bit word, each row
-// padded to a multiple of four words.  The workgroup then keeps the degrees
+// tail vertices' rows (h = 3: triangle rows; h = 2: adjacency rows): only
+// pairs whose two vertices are still in the tail stay, renumbered to local
+// ids that follow the rank order (so the owner rule compares local ids),
+// packed two to a 32-bit word, each row padded to a multiple of four words.  The workgroup then keeps the degrees
 // and the states of the tail vertices in LDS and takes round after round,
 // with only workgroup barriers between them: the level (the rule of the
 // round-synchronous peel: the alive vertices of degree <= k, else a new
@@ -1525,14 +1525,15 @@ __global__ void k_te_flags(const int32_t *stamp, int32_t n, const PeelCtl *c, ui
         flag[v] = stamp[v] >= r ? 1u : 0u;
 }
 
-// local id -> vertex, and each tail vertex's rewrite items
-__global__ void k_te_glob(const uint32_t *flag, const uint32_t *loc, int32_t n, const int64_t *tvoff, int32_t *glob,
+// local id -> vertex, and each tail vertex's rewrite items (roff: the
+// triangle rows' offsets for h = 3, the adjacency's for h = 2)
+__global__ void k_te_glob(const uint32_t *flag, const uint32_t *loc, int32_t n, const int64_t *roff, int32_t *glob,
                           int64_t *ib, int32_t *count) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         if (!flag[v]) continue;
         const uint32_t l = loc[v];
         glob[l] = (int32_t)v;
-        ib[l] = (tvoff[v + 1] - tvoff[v] + TE_CH - 1) / TE_CH;
+        ib[l] = (roff[v + 1] - roff[v] + TE_CH - 1) / TE_CH;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *count = (int32_t)(loc[n - 1] + flag[n - 1]);
 }
@@ -1541,7 +1542,9 @@ __global__ void k_te_glob(const uint32_t *flag, const uint32_t *loc, int32_t n, 
 // once (a row holds every triangle as (a, x) and as (x, a): the one with
 // a < x stays): counted (FILL false, into kc[it]) or written from kc[it] on
 // (FILL true), in row order, so every row stays grouped by its first vertex.
-template <bool FILL>
+// H = 2: the rows are adjacency rows (tpairs: the column array), and each
+// neighbour x in the tail becomes the word (x, x).
+template <bool FILL, int H>
 __global__ __launch_bounds__(BLOCK) void k_te_pairs(const int64_t *tvoff, const int32_t *tpairs, const uint32_t *flag,
                                                      const uint32_t *loc, const int32_t *glob, const int64_t *ib,
                                                      int32_t A, int64_t NI, int64_t *kc, uint32_t *lp) {
@@ -1561,9 +1564,15 @@ __global__ __launch_bounds__(BLOCK) void k_te_pairs(const int64_t *tvoff, const 
             bool keep = false;
             uint32_t val = 0;
             if (e < e1) {
-                const int32_t a = tpairs[2 * e], x = tpairs[2 * e + 1];
-                keep = a < x && flag[a] && flag[x];   // rank order is local-id order
-                if (FILL && keep) val = (loc[a] << 16) | loc[x];
+                if (H == 3) {
+                    const int32_t a = tpairs[2 * e], x = tpairs[2 * e + 1];
+                    keep = a < x && flag[a] && flag[x];   // rank order is local-id order
+                    if (FILL && keep) val = (loc[a] << 16) | loc[x];
+                } else {
+                    const int32_t x = tpairs[e];
+                    keep = flag[x] != 0;
+                    if (FILL && keep) val = (loc[x] << 16) | loc[x];
+                }
             }
             const u64 m = __ballot(keep);
             if (FILL && keep) lp[pos + __popcll(m & lanemask_lt())] = val;
@@ -1706,7 +1715,9 @@ __device__ __forceinline__ uint32_t te_mask(const uint32_t *d, const uint32_t *s
     return mask;
 }
 
-// lrow (A + 1 entries) below 2^32: the row starts live in LDS
+// lrow (A + 1 entries) below 2^32: the row starts live in LDS.  H = 2: a
+// removed vertex costs each alive neighbour x (the word (x, x)) one edge.
+template <int H>
 __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int32_t *glob, const int64_t *lrow,
                                                           const uint32_t *lp, int32_t A, int32_t *err) {
     __shared__ __align__(16) uint32_t sDeg[TE_MAX];
@@ -1868,7 +1879,7 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                     const uint32_t sa = s2[j] & 0xffu, sx = s2[j] >> 8;
                     const bool ok = pv[j] != TE_NONE && te_allowed(sa, a, v) && te_allowed(sx, x, v);
                     destroyed += ok ? 1u : 0u;
-                    atomicSub(&sDeg[x], (ok && sx == TE_ALIVE) ? 1u : 0u);
+                    if (H == 3) atomicSub(&sDeg[x], (ok && sx == TE_ALIVE) ? 1u : 0u);
                     acc += (ok && sa == TE_ALIVE) ? 1u : 0u;
                     const bool last = j == TE_PL - 1 || (pv[j + (j < TE_PL - 1)] >> 16) != a;
                     if (last && acc) {
@@ -1997,7 +2008,7 @@ static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
 // false, having changed nothing, when the degrees could exceed 32 bits or
 // the rewritten rows would not fit; the environment variable
 // DSD_TAIL_ENGINE=0 turns it off.
-static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream_t s, Scratch &sc,
+static bool tail_engine(const PeelBufs &b, int h, int32_t n, int64_t n_alive, hipStream_t s, Scratch &sc,
                         KernelTimes *kt) {
     const char *env = std::getenv("DSD_TAIL_ENGINE");
     if (env && std::strcmp(env, "0") == 0) return false;
@@ -2006,8 +2017,12 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     DSD_HIP(hipMemcpyAsync(&g0, b.gs, sizeof(GraphState), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     if (g0.mu_alive >= ((u64)1 << 32) || g0.n_alive != n_alive) return false;   // degrees <= mu_alive
-    // every clique of the tail sits in 3 pairs of the rows, 4 bytes each
-    const int64_t bytes = 12 * (int64_t)g0.mu_alive + 8 * (int64_t)n + 64 * n_alive;
+    // every clique of the tail sits in ppc words of the rows (a triangle in
+    // its three members' rows, an edge in its two ends'), 4 bytes each
+    const int64_t ppc = h == 3 ? 3 : 2;
+    const int64_t bytes = 4 * ppc * (int64_t)g0.mu_alive + 8 * (int64_t)n + 64 * n_alive;
+    const int64_t *roff = h == 3 ? b.tvoff : b.row_ptr;
+    const int32_t *rdat = h == 3 ? b.tpairs : b.col;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || bytes > (int64_t)(free_b / 4)) return false;
     const int32_t A = (int32_t)n_alive;
@@ -2017,7 +2032,7 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     k_te_flags<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b.stamp, n, b.ctl, flag);
     scan_exclusive_u32(flag, loc, n, s, sc);
     fill_i32((int32_t *)(ib + A), 0, 2, s);
-    k_te_glob<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(flag, loc, n, b.tvoff, glob, ib, cnt);
+    k_te_glob<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(flag, loc, n, roff, glob, ib, cnt);
     scan_exclusive_i64(ib, ib, A + 1, s, sc);
     int64_t hv[2] = {0, 0};
     DSD_HIP(hipMemcpyAsync(&hv[0], ib + A, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -2027,8 +2042,10 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     if ((int32_t)hv[1] != A) throw Error(-3, "tail engine: the tail's vertex count disagrees with the alive count");
     int64_t *kc = sc.get_n<int64_t>(NI + 1);
     const int gp = grid_for(NI, WAVES_PER_BLOCK, 8192), gA = grid_for(A, BLOCK, 64);
-    if (NI > 0)
-        k_te_pairs<false><<<gp, BLOCK, 0, s>>>(b.tvoff, b.tpairs, flag, loc, glob, ib, A, NI, kc, nullptr);
+    if (NI > 0) {
+        if (h == 3) k_te_pairs<false, 3><<<gp, BLOCK, 0, s>>>(roff, rdat, flag, loc, glob, ib, A, NI, kc, nullptr);
+        else k_te_pairs<false, 2><<<gp, BLOCK, 0, s>>>(roff, rdat, flag, loc, glob, ib, A, NI, kc, nullptr);
+    }
     // rows padded to four pairs, so that lanes load them four at a time
     int64_t *vcnt = sc.get_n<int64_t>(A), *lrow = sc.get_n<int64_t>(A + 1);
     fill_i32((int32_t *)(lrow + A), 0, 2, s);
@@ -2037,7 +2054,7 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     int64_t total = 0;
     DSD_HIP(hipMemcpyAsync(&total, lrow + A, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
-    if (total > 3 * (int64_t)g0.mu_alive + 3 * (int64_t)A)
+    if (total > ppc * (int64_t)g0.mu_alive + 3 * (int64_t)A)
         throw Error(-3, "tail engine: more pairs than the tail's cliques allow");
     if (total >= ((int64_t)1 << 32)) return false;   // row starts are kept in 32 bits
     u64 walked = 0;   // pairs the engine walks: every kept pair once
@@ -2048,7 +2065,10 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
     }
     k_te_ioff<<<gA, BLOCK, 0, s>>>(ib, lrow, A, kc);
     uint32_t *lp = sc.get_n<uint32_t>(total);
-    if (NI > 0) k_te_pairs<true><<<gp, BLOCK, 0, s>>>(b.tvoff, b.tpairs, flag, loc, glob, ib, A, NI, kc, lp);
+    if (NI > 0) {
+        if (h == 3) k_te_pairs<true, 3><<<gp, BLOCK, 0, s>>>(roff, rdat, flag, loc, glob, ib, A, NI, kc, lp);
+        else k_te_pairs<true, 2><<<gp, BLOCK, 0, s>>>(roff, rdat, flag, loc, glob, ib, A, NI, kc, lp);
+    }
     k_te_pad<<<gA, BLOCK, 0, s>>>(lrow, vcnt, A, lp);
     fill_i32(cnt, 0, 1, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2057,7 +2077,8 @@ static bool tail_engine(const PeelBufs &b, int32_t n, int64_t n_alive, hipStream
         DSD_HIP(hipEventCreate(&e1));
         DSD_HIP(hipEventRecord(e0, s));
     }
-    k_tail_engine<<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
+    if (h == 3) k_tail_engine<3><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
+    else k_tail_engine<2><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
     DSD_HIP(hipGetLastError());
     if (e1) DSD_HIP(hipEventRecord(e1, s));
     int32_t err = 0;
@@ -2196,9 +2217,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         compact_adjacency(b, s, sc);
         compacted_at = n_alive;
     }
-    const bool engine = listed && G == 1 && !min_degree && pattern == 0;
+    const bool engine = (listed || h == 2) && G == 1 && !min_degree && pattern == 0;
     while (n_alive > 0) {
-        if (engine && n_alive <= TE_MAX && tail_engine(b, n, n_alive, s, sc, kt)) break;
+        if (engine && n_alive <= TE_MAX && tail_engine(b, h, n, n_alive, s, sc, kt)) break;
         if (compacting && n_alive < compacted_at / 2) {
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;

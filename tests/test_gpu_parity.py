@@ -291,11 +291,13 @@ def test_triangle_networks_built_on_the_device(fixtures, monkeypatch, cut):
     assert nets > 0
 
 
+@pytest.mark.parametrize("h", [2, 3])
 @pytest.mark.parametrize("case", ["chung_lu", "er_planted", "rmat", "multipartite"])
-def test_tail_engine_matches_round_kernels(monkeypatch, case):
+def test_tail_engine_matches_round_kernels(monkeypatch, case, h):
     # the single-workgroup tail engine (the last alive vertices of an h = 3
-    # peel over triangle lists) against the per-round kernels: the same core
-    # numbers, rounds, levels, and the same exact answer from the level table
+    # peel over triangle lists, or of an h = 2 peel over the adjacency)
+    # against the per-round kernels: the same core numbers, rounds, levels,
+    # and the same exact answer from the level table
     if case == "chung_lu":
         n, s, d = synth.chung_lu(n=60000, avg_deg=14, beta=2.1, planted=2, plant_size=80, p=0.6, seed=5)
     elif case == "er_planted":
@@ -310,10 +312,11 @@ def test_tail_engine_matches_round_kernels(monkeypatch, case):
     for flag in ("0", "1"):
         monkeypatch.setenv("DSD_TAIL_ENGINE", flag)
         g = dsd.build_csr(n, s, d)
-        core, km = dsd.clique_core(g, 3)
+        core, km = dsd.clique_core(g, h)
         st = g.stats()
-        mem, rho = dsd.core_exact(g, 3)
-        res[flag] = (core, km, st["peel_rounds"], st["peel_levels"], rho)
+        mem, rho = dsd.core_exact(g, h)
+        _, km_app, dens_app = dsd.core_app(g, h)
+        res[flag] = (core, km, st["peel_rounds"], st["peel_levels"], rho, km_app, dens_app)
     np.testing.assert_array_equal(res["0"][0], res["1"][0])
     assert res["0"][1:] == res["1"][1:]
 
