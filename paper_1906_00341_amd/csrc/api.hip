@@ -550,8 +550,6 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
         while (true) {
             mask_from_order_prefix(keys, n, w, G->g.bits, inW, s);
             Timer te(s);
-            // (no triangle lists here: their rows hold every triangle of the whole graph, and a
-            // hub's row in G[W] is mostly triangles that leave W)
             u64 muW = degrees_and_mu(G, h, inW, d);
             G->stats.t_enum_ms += te.stop();
             masked_min_u64(d, inW, n, mn, s);
@@ -561,6 +559,9 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
             const u64 k0 = std::max(kl, kmax);
             const u64 floor_k = k0 > 0 ? k0 - 1 : 0;
             Timer tq(s);
+            // (no triangle lists here: their rows hold every triangle of the whole graph, and a
+            // hub's row in G[W] is mostly triangles that leave W; rewriting them for the tail
+            // engine at every W costs more than the peel of G[W])
             PeelResult pr = peel(G->g, h, inW, d, muW, floor_k, core, s, G->sc);
             G->stats.t_peel_ms += tq.stop();
             G->stats.peel_rounds += pr.rounds;

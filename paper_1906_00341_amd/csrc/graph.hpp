@@ -79,6 +79,11 @@ void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipS
 void free_tri_list(TriList &tl);
 
 // ---- K4: round-synchronous peel ----
+// Once at most this many vertices of a single graph are alive (h = 2, or
+// h = 3 with triangle lists), one workgroup finishes the peel in one launch
+// (the tail engine); a peel that starts at or below it never launches a
+// round kernel.
+constexpr int64_t TAIL_ENGINE_VERTICES = 16384;
 // A batch of graphs is peeled as one disjoint union in which every graph
 // keeps its own level: a round moves every graph on by one step, so the
 // batch takes as many rounds as its slowest graph.

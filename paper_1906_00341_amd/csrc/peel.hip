@@ -1507,7 +1507,7 @@ __global__ void k_start_graphs(PeelBufs b) {
 // vector loads, looks up all of their states before it waits, and applies
 // each run of one first vertex with a single LDS atomic.
 
-constexpr int TE_MAX = 16384;                 // tail vertices: local ids fit 16 bits
+constexpr int TE_MAX = (int)TAIL_ENGINE_VERTICES;   // tail vertices: local ids fit 16 bits
 constexpr int TE_BLOCK = 1024;
 constexpr int TE_WAVES = TE_BLOCK / WAVE;
 constexpr int TE_PER = TE_MAX / TE_BLOCK;     // local ids per thread in the frontier scans
