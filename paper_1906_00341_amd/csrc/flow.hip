@@ -61,6 +61,8 @@ struct FlowBufs {
     int *front[2];
     int *nfront;   // [2] frontier sizes
     int *active;   // active node count
+    int *act_s, *act_b;   // this pass's active nodes (up to / more than BIG_ARCS arcs)
+    int *nact;            // [2] their numbers
 };
 
 // residual CSR from the arc list: degrees, then every arc and its reverse
@@ -388,11 +390,48 @@ __global__ void k_bfs_reset(FlowBufs b, int cur) {
     if (blockIdx.x == 0 && threadIdx.x == 0) b.nfront[cur] = 0;
 }
 
-// push phase: heights are read-only here (nodes up to BIG_ARCS arcs)
+// The active nodes of a pass (excess > 0, height < n, not s or t), listed
+// once so that the pass's kernels walk the list rather than every node: a
+// few hundred nodes stay active for most of the passes.  nact (two
+// counters) must be zero on entry.
+__device__ __forceinline__ void flow_list_push(bool pred, int u, int *list, int *count) {
+    const u64 m = __ballot(pred);
+    if (!m) return;
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane() == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (pred) list[base + __popcll(m & lanemask_lt())] = u;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_flow_active(FlowBufs b) {
+    const int stride = gridDim.x * BLOCK;
+    const int lim = (b.n + WAVE - 1) / WAVE * WAVE;   // whole waves take part in the ballots
+    for (int u = blockIdx.x * BLOCK + threadIdx.x; u - lane() < lim; u += stride) {
+        bool act = false, big = false;
+        if (u < b.n && u != b.s && u != b.t) {
+            act = b.ex[u] > 0 && b.ht[u] < b.n;
+            big = b.first[u + 1] - b.first[u] > BIG_ARCS;
+        }
+        flow_list_push(act && !big, u, b.act_s, &b.nact[0]);
+        flow_list_push(act && big, u, b.act_b, &b.nact[1]);
+    }
+}
+
+__global__ void k_zero_act(FlowBufs b) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.nact[0] = 0;
+        b.nact[1] = 0;
+    }
+}
+
+// push phase: heights are read-only here (nodes up to BIG_ARCS arcs, from
+// the pass's active list)
 __global__ __launch_bounds__(BLOCK) void k_flow_push(FlowBufs b) {
     const int wv = threadIdx.x / WAVE;
-    for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
-        if (u == b.s || u == b.t || b.first[u + 1] - b.first[u] > BIG_ARCS) continue;
+    const int na = b.nact[0];
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + wv; i < na; i += gridDim.x * WAVES_PER_BLOCK) {
+        const int u = b.act_s[i];
         const int hu = __shfl(b.ht[u], 0, WAVE);
         int64_t rem = __shfl(b.ex[u], 0, WAVE);   // one snapshot for the whole wave
         if (rem <= 0 || hu >= b.n) continue;
@@ -428,8 +467,9 @@ __global__ __launch_bounds__(BLOCK) void k_flow_push(FlowBufs b) {
 __global__ __launch_bounds__(BLOCK) void k_flow_relabel(FlowBufs b) {
     const int wv = threadIdx.x / WAVE;
     int act = 0;
-    for (int u = blockIdx.x * WAVES_PER_BLOCK + wv; u < b.n; u += gridDim.x * WAVES_PER_BLOCK) {
-        if (u == b.s || u == b.t || b.first[u + 1] - b.first[u] > BIG_ARCS) continue;
+    const int na = b.nact[0];
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + wv; i < na; i += gridDim.x * WAVES_PER_BLOCK) {
+        const int u = b.act_s[i];
         const int hu = __shfl(b.ht[u], 0, WAVE);
         const int64_t eu = __shfl(b.ex[u], 0, WAVE);
         if (eu <= 0 || hu >= b.n) continue;
@@ -470,11 +510,13 @@ __device__ __forceinline__ int64_t block_scan_sat(int64_t c, int64_t *sW, int64_
 
 // push phase for the nodes with more than BIG_ARCS arcs: one block each
 __global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
+    constexpr int K = 4;   // arcs per thread per step: their loads go out together
     __shared__ int64_t sW[BIG_WAVES];
     __shared__ int64_t sEx;
     __shared__ int sHt;
-    for (int i = blockIdx.x; i < b.nbig; i += gridDim.x) {
-        const int u = b.big[i];
+    const int na = b.nact[1];
+    for (int i = blockIdx.x; i < na; i += gridDim.x) {
+        const int u = b.act_b[i];
         if (u == b.s || u == b.t) continue;
         // one snapshot of the node for the whole block (others add to its
         // excess concurrently), so every thread takes the same path
@@ -488,24 +530,38 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
         __syncthreads();
         if (rem <= 0 || hu >= b.n) continue;
         const int64_t start = rem;
-        for (int a0 = b.first[u]; a0 < b.first[u + 1] && rem > 0; a0 += BIG_BLOCK) {
-            const int a = a0 + threadIdx.x;
-            int64_t c = 0;
-            int v = -1;
-            if (a < b.first[u + 1]) {
-                v = b.to[a];
-                const int64_t r = b.cf[a];
-                if (r > 0 && b.ht[v] == hu - 1) c = r < rem ? r : rem;
+        const int end = b.first[u + 1];
+        for (int a0 = b.first[u]; a0 < end && rem > 0; a0 += BIG_BLOCK * K) {
+            int64_t c[K];
+            int v[K];
+            int64_t own = 0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int a = a0 + k * BIG_BLOCK + threadIdx.x;
+                c[k] = 0;
+                v[k] = -1;
+                if (a < end) {
+                    v[k] = b.to[a];
+                    const int64_t r = b.cf[a];
+                    if (r > 0 && b.ht[v[k]] == hu - 1) c[k] = r < rem ? r : rem;
+                }
+                own = (own > SAT - c[k]) ? SAT : own + c[k];
             }
+            if (!__syncthreads_or(own > 0)) continue;   // no admissible arc in this step
             int64_t total;
-            const int64_t inc = block_scan_sat(c, sW, &total);
-            const int64_t before = inc - c;
-            int64_t d = rem - before;
-            d = d < 0 ? 0 : (d > c ? c : d);
-            if (d > 0) {
-                b.cf[a] -= d;
-                b.cf[b.rev[a]] += d;
-                atomicAdd((unsigned long long *)&b.ex[v], (unsigned long long)d);
+            const int64_t inc = block_scan_sat(own, sW, &total);
+            int64_t before = inc - own;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                int64_t d = rem - before;
+                d = d < 0 ? 0 : (d > c[k] ? c[k] : d);
+                if (d > 0) {
+                    const int a = a0 + k * BIG_BLOCK + threadIdx.x;
+                    b.cf[a] -= d;
+                    b.cf[b.rev[a]] += d;
+                    atomicAdd((unsigned long long *)&b.ex[v[k]], (unsigned long long)d);
+                }
+                before = (before > SAT - c[k]) ? SAT : before + c[k];
             }
             rem -= total < rem ? total : rem;
         }
@@ -522,8 +578,9 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_relabel_big(FlowBufs b) {
     int act = 0;
     __shared__ int64_t sEx;
     __shared__ int sHt;
-    for (int i = blockIdx.x; i < b.nbig; i += gridDim.x) {
-        const int u = b.big[i];
+    const int na = b.nact[1];
+    for (int i = blockIdx.x; i < na; i += gridDim.x) {
+        const int u = b.act_b[i];
         if (u == b.s || u == b.t) continue;
         if (threadIdx.x == 0) {
             sHt = b.ht[u];
@@ -536,17 +593,23 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_relabel_big(FlowBufs b) {
         __syncthreads();
         if (eu <= 0 || hu >= b.n) continue;
         int hmin = 0x7fffffff;
-        for (int a0 = b.first[u]; a0 < b.first[u + 1]; a0 += BIG_BLOCK) {
-            const int a = a0 + threadIdx.x;
-            if (a < b.first[u + 1] && b.cf[a] > 0) {
-                const int hv = b.ht[b.to[a]];
-                hmin = hv < hmin ? hv : hmin;
-                if (hv < hu) sAdm = 1;
+        constexpr int K = 4;   // arcs per thread per step: their loads go out together
+        const int end = b.first[u + 1];
+        for (int a0 = b.first[u]; a0 < end; a0 += BIG_BLOCK * K) {
+            bool adm = false;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int a = a0 + k * BIG_BLOCK + threadIdx.x;
+                if (a < end && b.cf[a] > 0) {
+                    const int hv = b.ht[b.to[a]];
+                    hmin = hv < hmin ? hv : hmin;
+                    adm = adm || hv < hu;
+                }
             }
-            __syncthreads();
-            const bool stop = sAdm != 0;        // the same value for every thread
-            __syncthreads();                    // no thread writes sAdm before all have read it
-            if (stop) break;
+            if (__syncthreads_or(adm)) {   // the same value for every thread
+                if (threadIdx.x == 0) sAdm = 1;
+                break;
+            }
         }
         hmin = wave_min_i32(hmin);
         if (lane() == 0) sMin[threadIdx.x / WAVE] = hmin;
@@ -748,6 +811,9 @@ void GpuFlow::Impl::residual(int n) {
     b.front[1] = I.sc.get_n<int>(n);
     b.nfront = I.sc.get_n<int>(2);
     b.active = I.sc.get_n<int>(1);
+    b.act_s = I.sc.get_n<int>(n);
+    b.act_b = I.sc.get_n<int>(n);
+    b.nact = I.sc.get_n<int>(2);
     // nodes with more than BIG_ARCS residual arcs
     std::vector<int> hfirst(n + 1);
     DSD_HIP(hipMemcpyAsync(hfirst.data(), first, (size_t)(n + 1) * sizeof(int), hipMemcpyDeviceToHost, I.s));
@@ -793,29 +859,42 @@ int64_t GpuFlow::maxflow(const FlowTest &test, std::vector<char> &reach_t, int64
     k_flow_caps<<<grid_for(I.E, BLOCK, 16384), BLOCK, 0, I.s>>>(b, I.eu, I.ev, I.cls, I.fwd, I.deg, I.E, test);
     k_flow_saturate<<<1, WAVE, 0, I.s>>>(b);
     I.global_relabel();
-    const int gpass = grid_for(b.n, WAVES_PER_BLOCK, 16384);
+    // a pass: list the active nodes, push, relabel; the passes' kernels
+    // walk the lists with grids sized for the busy first passes
+    const int gpass = grid_for(b.n, WAVES_PER_BLOCK, 2048), gact = grid_for(b.n, BLOCK, 1024);
+    const int gbig = b.nbig < 4096 ? b.nbig : 4096;
     int64_t passes = 0;
     *converged = false;
     int since_relabel = 0;
+    // The list made after a pass's pushes serves its relabels and the next
+    // pass's pushes (relabelling adds no excess; a node raised to n is
+    // skipped by the push).
+    auto list_active = [&]() {
+        k_zero_act<<<1, 1, 0, I.s>>>(b);
+        k_flow_active<<<gact, BLOCK, 0, I.s>>>(b);
+    };
+    list_active();
     while (passes < max_passes) {
         for (int i = 0; i < 8; i++) {
-            k_zero_i32<<<1, 1, 0, I.s>>>(b.active);
             k_flow_push<<<gpass, BLOCK, 0, I.s>>>(b);
-            if (b.nbig > 0) k_flow_push_big<<<b.nbig < 4096 ? b.nbig : 4096, BIG_BLOCK, 0, I.s>>>(b);
+            if (b.nbig > 0) k_flow_push_big<<<gbig, BIG_BLOCK, 0, I.s>>>(b);
+            list_active();
             k_flow_relabel<<<gpass, BLOCK, 0, I.s>>>(b);
-            if (b.nbig > 0) k_flow_relabel_big<<<b.nbig < 4096 ? b.nbig : 4096, BIG_BLOCK, 0, I.s>>>(b);
+            if (b.nbig > 0) k_flow_relabel_big<<<gbig, BIG_BLOCK, 0, I.s>>>(b);
         }
         passes += 8;
         since_relabel += 8;
-        DSD_HIP(hipMemcpyAsync(I.pinned, b.active, sizeof(int), hipMemcpyDeviceToHost, I.s));
+        // converged when no node was active after the last pass's pushes
+        DSD_HIP(hipMemcpyAsync(I.pinned, b.nact, 2 * sizeof(int), hipMemcpyDeviceToHost, I.s));
         DSD_HIP(hipStreamSynchronize(I.s));
-        if (I.pinned[0] == 0) {
+        if (I.pinned[0] + I.pinned[1] == 0) {
             *converged = true;
             break;
         }
         if (since_relabel >= 32) {
             I.global_relabel();
             since_relabel = 0;
+            list_active();   // heights changed: nodes that cannot reach t leave the list
         }
     }
     int64_t flow = 0;
