@@ -127,8 +127,33 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
     D.kt.time_main = G->time_main;
     Timer te(s);
     u64 *d = G->sc.get_n<u64>(n);
-    D.mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &D.kt) : 0;
-    const TriList *tl = h == 3 && D.mu > 0 ? tri_lists(G, d, D.mu) : nullptr;
+    const TriList *tl = nullptr;
+    if (h == 3 && n > 0 && G->tl.pairs) {
+        // lists from an earlier call: the clique-degrees are their row lengths
+        tri_list_degrees(G->tl, n, d, s);
+        D.mu = G->tl.mu;
+        tl = &G->tl;
+    } else if (h == 3 && n > 0 && !G->tl_tried && tri_supports_possible(G->g)) {
+        // the lists' first pass gives the clique-degrees; its supports then
+        // serve the second pass
+        TlCounts w;
+        Timer tk(s);
+        D.mu = tri_supports(G->g, d, w, s, G->sc);
+        D.kt.k3_ms += tk.stop();
+        D.kt.k3_launches += 1;
+        G->tl_tried = true;
+        if (D.mu > 0 && tri_list_wanted(G->g, D.mu)) {
+            try {
+                build_tri_list(G->g, w, G->tl, s, G->sc);
+            } catch (const Error &e) {
+                if (e.status != DSD_ENOMEM) throw;     // no room: the peel intersects neighbourhoods instead
+            }
+        }
+        if (G->tl.pairs && G->tl.mu == D.mu) tl = &G->tl;
+    } else {
+        D.mu = n > 0 ? degrees_and_mu(G, h, nullptr, d, &D.kt) : 0;
+        tl = h == 3 && D.mu > 0 ? tri_lists(G, d, D.mu) : nullptr;
+    }
     D.t_enum_ms = te.stop();
     Timer tp(s);
     D.levels = PeelResult();

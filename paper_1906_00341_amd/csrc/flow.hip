@@ -365,23 +365,33 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_bfs_level_big(FlowBufs b, int cur
     const int *F = b.front[cur];
     int *N = b.front[cur ^ 1];
     const int wv = threadIdx.x / WAVE;
+    constexpr int K = 4;   // arcs per thread per step: their loads go out together
     for (int i = blockIdx.x; i < nf; i += gridDim.x) {
         const int v = F[i];
         if (b.first[v + 1] - b.first[v] <= BIG_ARCS) continue;    // block-uniform
-        for (int a0 = b.first[v]; a0 < b.first[v + 1]; a0 += BIG_BLOCK) {
-            const int a = a0 + threadIdx.x;
-            bool take = false;
-            int u = -1;
-            if (a < b.first[v + 1]) {
-                u = b.to[a];
-                if (u != b.s && b.cf[b.rev[a]] > 0 && b.ht[u] == b.n)
-                    take = atomicCAS(&b.ht[u], b.n, level + 1) == b.n;
+        const int end = b.first[v + 1];
+        for (int a0 = b.first[v]; a0 < end; a0 += BIG_BLOCK * K) {
+            int u[K];
+            bool cand[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int a = a0 + k * BIG_BLOCK + threadIdx.x;
+                u[k] = -1;
+                cand[k] = false;
+                if (a < end) {
+                    u[k] = b.to[a];
+                    cand[k] = u[k] != b.s && b.cf[b.rev[a]] > 0 && b.ht[u[k]] == b.n;
+                }
             }
-            const u64 m = __ballot(take);
-            if (lane() == 0) sBase[wv] = m ? atomicAdd(&b.nfront[cur ^ 1], __popcll(m)) : 0;
-            __builtin_amdgcn_wave_barrier();
-            if (take) N[sBase[wv] + __popcll(m & lanemask_lt())] = u;
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const bool take = cand[k] && atomicCAS(&b.ht[u[k]], b.n, level + 1) == b.n;
+                const u64 m = __ballot(take);
+                if (lane() == 0) sBase[wv] = m ? atomicAdd(&b.nfront[cur ^ 1], __popcll(m)) : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (take) N[sBase[wv] + __popcll(m & lanemask_lt())] = u[k];
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
 }

@@ -73,9 +73,28 @@ struct TriList {
 // out-degree within the listing kernels, at most a quarter of free device
 // memory); the environment variable DSD_TRI_LIST=0 turns them off
 bool tri_list_wanted(const DevGraph &g, u64 mu);
-// list every triangle of the graph (mu of them); deg is unused.  Allocates
-// tl's arrays (released by free_tri_list).
+// The first pass of the listing alone: every arc's support (triangles on its
+// edge), and from them the clique-degrees (half the supports of a vertex's
+// arcs) and mu.  The arrays live in the scratch until its next reset.
+struct TlCounts {
+    int64_t *rev = nullptr;   // [2m] reverse arc of every arc
+    u64 *cnt = nullptr;       // [2m] supports
+    int32_t *big = nullptr, *nbig = nullptr;
+    u64 mu = 0;
+};
+// whether the supports can be counted (out-degrees within the listing
+// kernels, room on the device; DSD_TRI_LIST=0 turns them off)
+bool tri_supports_possible(const DevGraph &g);
+// deg (length n) = clique-degrees (h = 3); returns mu
+u64 tri_supports(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc);
+// the second pass: every triangle written out through per-arc cursors into
+// the segments the supports give.  Allocates tl's arrays (released by
+// free_tri_list).
+void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc);
+// both passes for a graph with mu triangles (deg unused)
 void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc);
+// clique-degrees read off finished lists (two pairs per triangle at a vertex)
+void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s);
 void free_tri_list(TriList &tl);
 
 // ---- K4: round-synchronous peel ----

@@ -258,6 +258,24 @@ __global__ void k_tl_offsets_tail(int64_t *woff, const u64 *cnt, int64_t arcs) {
     if (blockIdx.x == 0 && threadIdx.x == 0) woff[arcs] = woff[arcs - 1] + (int64_t)cnt[arcs - 1];
 }
 
+// clique-degrees from the supports: every triangle at v is counted on two of
+// v's arcs (one wave per vertex)
+__global__ void k_tl_degrees(const int64_t *row_ptr, const u64 *cnt, int32_t n, u64 *deg) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        u64 sum = 0;
+        for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) sum += cnt[e];
+        sum = wave_sum(sum);
+        if (lane() == 0) deg[v] = sum / 2;
+    }
+}
+
+// clique-degrees from finished lists: row v holds two pairs per triangle at v
+__global__ void k_tl_row_degrees(const int64_t *voff, int32_t n, u64 *deg) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        deg[v] = (u64)(voff[v + 1] - voff[v]) / 2;
+}
+
 // row starts: voff[v] = start of v's first arc segment
 __global__ void k_tl_rows(const int64_t *row_ptr, const int64_t *woff, int32_t n, int64_t *voff) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x)
@@ -279,13 +297,61 @@ bool tri_list_wanted(const DevGraph &g, u64 mu) {
     return bytes <= TL_MAX_BYTES && bytes <= (int64_t)(free_b / 4);
 }
 
-void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc) {
-    (void)deg;
+bool tri_supports_possible(const DevGraph &g) {
+    const char *e = std::getenv("DSD_TRI_LIST");
+    if (e && std::strcmp(e, "0") == 0) return false;
+    if (g.n == 0 || g.m == 0 || g.maxdout > TL_MAX_OUT) return false;
+    // reverse arcs, supports and segment starts: 24 B per arc
+    const int64_t bytes = 24 * 2 * g.m + 8 * ((int64_t)g.n + 1);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+    return bytes <= (int64_t)(free_b / 4);
+}
+
+u64 tri_supports(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc) {
+    const int32_t n = g.n;
+    const int64_t arcs = 2 * g.m;
+    w.rev = sc.get_n<int64_t>(arcs);
+    w.cnt = sc.get_n<u64>(arcs);
+    w.big = sc.get_n<int32_t>(n);
+    w.nbig = sc.get_n<int32_t>(2);
+    fill_i32(w.nbig, 0, 2, s);
+    fill_u64(w.cnt, 0, arcs, s);
+    TlBuild b{};
+    b.row_ptr = g.row_ptr;
+    b.col = g.col;
+    b.dag_off = g.dag_off;
+    b.rev = w.rev;
+    b.cnt = w.cnt;
+    b.big = w.big;
+    b.nbig = w.nbig;
+    b.err = w.nbig + 1;
+    b.n = n;
+    k_tl_rev<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, g.dag_off, n, w.rev);
+    b.pass = 0;
+    k_tl_small<<<grid_for(n, WAVES_PER_BLOCK, 4096), BLOCK, 0, s>>>(b);
+    k_tl_big<<<1024, BLOCK, 0, s>>>(b);
+    k_tl_mirror<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.dag_off, w.rev, n, w.cnt, b.err);
+    k_tl_degrees<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, w.cnt, n, deg);
+    u64 *sum = sc.get_n<u64>(2);
+    sum_u64_128(deg, n, sum, s, sc);
+    u64 hs[2];
+    int32_t err = 0;
+    DSD_HIP(hipMemcpyAsync(hs, sum, sizeof(hs), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(&err, b.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipStreamSynchronize(s));
+    if (err) throw Error(-3, "triangle supports: a reverse arc is missing");
+    if (hs[1] != 0 || hs[0] % 3 != 0) throw Error(-3, "triangle supports: clique-degree sum not a multiple of 3");
+    w.mu = hs[0] / 3;
+    return w.mu;
+}
+
+void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc) {
     free_tri_list(tl);
     const int32_t n = g.n;
     const int64_t arcs = 2 * g.m;
-    tl.mu = mu;
-    tl.entries = 6 * (int64_t)mu;
+    tl.mu = w.mu;
+    tl.entries = 6 * (int64_t)w.mu;
     if (hipMalloc(&tl.voff, (size_t)(n + 1) * sizeof(int64_t)) != hipSuccess ||
         hipMalloc(&tl.pairs, (size_t)(tl.entries > 0 ? tl.entries : 1) * 2 * sizeof(int32_t)) != hipSuccess) {
         free_tri_list(tl);
@@ -295,25 +361,17 @@ void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipS
     b.row_ptr = g.row_ptr;
     b.col = g.col;
     b.dag_off = g.dag_off;
-    int64_t *rev = sc.get_n<int64_t>(arcs);
-    b.rev = rev;
-    b.cnt = sc.get_n<u64>(arcs);
+    b.rev = w.rev;
+    b.cnt = w.cnt;
     int64_t *woff = sc.get_n<int64_t>(arcs + 1);
     b.woff = woff;
     b.pairs = tl.pairs;
-    b.big = sc.get_n<int32_t>(n);
-    b.nbig = sc.get_n<int32_t>(2);
-    b.err = b.nbig + 1;
+    b.big = w.big;
+    b.nbig = w.nbig;
+    b.err = w.nbig + 1;
     b.n = n;
-    fill_i32(b.nbig, 0, 2, s);
-    fill_u64(b.cnt, 0, arcs, s);
-    k_tl_rev<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, g.dag_off, n, rev);
-    b.pass = 0;
-    k_tl_small<<<grid_for(n, WAVES_PER_BLOCK, 4096), BLOCK, 0, s>>>(b);
-    k_tl_big<<<1024, BLOCK, 0, s>>>(b);
-    k_tl_mirror<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.dag_off, rev, n, b.cnt, b.err);
-    scan_exclusive_i64((const int64_t *)b.cnt, woff, arcs, s, sc);
-    k_tl_offsets_tail<<<1, 1, 0, s>>>(woff, b.cnt, arcs);
+    scan_exclusive_i64((const int64_t *)w.cnt, woff, arcs, s, sc);
+    k_tl_offsets_tail<<<1, 1, 0, s>>>(woff, w.cnt, arcs);
     int32_t err = 0;
     int64_t total = 0;
     DSD_HIP(hipMemcpyAsync(&err, b.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -321,7 +379,7 @@ void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipS
     DSD_HIP(hipStreamSynchronize(s));
     if (err || total != tl.entries) {      // every reverse arc found, supports summing to 6 mu
         free_tri_list(tl);
-        throw Error(-3, "triangle lists do not match the clique-degrees");
+        throw Error(-3, "triangle lists do not match the supports");
     }
     DSD_HIP(hipMemcpyAsync(b.cnt, woff, (size_t)arcs * sizeof(u64), hipMemcpyDeviceToDevice, s));
     k_tl_rows<<<grid_for((int64_t)n + 1, BLOCK, 4096), BLOCK, 0, s>>>(g.row_ptr, woff, n, tl.voff);
@@ -333,8 +391,20 @@ void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipS
     DSD_HIP(hipStreamSynchronize(s));
     if (err) {
         free_tri_list(tl);
-        throw Error(-3, "triangle lists do not match the clique-degrees");
+        throw Error(-3, "triangle lists do not match the supports");
     }
+}
+
+void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc) {
+    (void)deg;
+    TlCounts w;
+    u64 *d = sc.get_n<u64>(g.n);
+    if (tri_supports(g, d, w, s, sc) != mu) throw Error(-3, "triangle lists do not match the clique-degrees");
+    build_tri_list(g, w, tl, s, sc);
+}
+
+void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s) {
+    k_tl_row_degrees<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(tl.voff, n, deg);
 }
 
 void free_tri_list(TriList &tl) {
