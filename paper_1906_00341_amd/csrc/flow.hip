@@ -60,6 +60,8 @@ struct FlowBufs {
     int *ht;
     int *front[2];
     int *nfront;   // [2] frontier sizes
+    int *bfront[2];   // the frontier's nodes with more than BIG_ARCS arcs
+    int *nbfront;     // [2] their numbers
     int *active;   // active node count
     int *act_s, *act_b;   // this pass's active nodes (up to / more than BIG_ARCS arcs)
     int *nact;            // [2] their numbers
@@ -320,22 +322,39 @@ __global__ void k_bfs_start(FlowBufs b) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < b.n; v += gridDim.x * blockDim.x)
         b.ht[v] = v == b.t ? 0 : b.n;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        b.front[0][0] = b.t;
-        b.nfront[0] = 1;
+        const bool big = b.first[b.t + 1] - b.first[b.t] > BIG_ARCS;
+        (big ? b.bfront : b.front)[0][0] = b.t;
+        b.nfront[0] = big ? 0 : 1;
+        b.nbfront[0] = big ? 1 : 0;
         b.nfront[1] = 0;
+        b.nbfront[1] = 0;
     }
 }
 
-// one level: every node of front[cur] (height `level`) labels its unlabelled
+// a newly labelled node u joins the next frontier of its kind (all lanes
+// of the wave call this together)
+__device__ __forceinline__ void bfs_push(const FlowBufs &b, bool take, int u, int nx) {
+    const bool big = take && b.first[u + 1] - b.first[u] > BIG_ARCS;
+    const u64 ms = __ballot(take && !big), mb = __ballot(big);
+    const int leader_s = ms ? __builtin_ctzll(ms) : 0, leader_b = mb ? __builtin_ctzll(mb) : 0;
+    int base_s = 0, base_b = 0;
+    if (ms && lane() == leader_s) base_s = atomicAdd(&b.nfront[nx], __popcll(ms));
+    if (mb && lane() == leader_b) base_b = atomicAdd(&b.nbfront[nx], __popcll(mb));
+    base_s = __shfl(base_s, leader_s, WAVE);
+    base_b = __shfl(base_b, leader_b, WAVE);
+    if (take && !big) b.front[nx][base_s + __popcll(ms & lanemask_lt())] = u;
+    if (big) b.bfront[nx][base_b + __popcll(mb & lanemask_lt())] = u;
+}
+
+// one level: every node of front[cur] (height `level`; the frontier nodes
+// with at most BIG_ARCS arcs) labels its unlabelled
 // in-neighbours (u with a residual arc u -> v) level + 1
 __global__ __launch_bounds__(BLOCK) void k_bfs_level(FlowBufs b, int cur, int level) {
     const int nf = b.nfront[cur];
     const int *F = b.front[cur];
-    int *N = b.front[cur ^ 1];
     const int wv = threadIdx.x / WAVE;
     for (int i = blockIdx.x * WAVES_PER_BLOCK + wv; i < nf; i += gridDim.x * WAVES_PER_BLOCK) {
         const int v = F[i];
-        if (b.first[v + 1] - b.first[v] > BIG_ARCS) continue;     // k_bfs_level_big
         for (int a0 = b.first[v]; a0 < b.first[v + 1]; a0 += WAVE) {
             const int a = a0 + lane();
             bool take = false;
@@ -346,29 +365,18 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_level(FlowBufs b, int cur, int le
                 if (u != b.s && b.cf[b.rev[a]] > 0 && b.ht[u] == b.n)
                     take = atomicCAS(&b.ht[u], b.n, level + 1) == b.n;
             }
-            const u64 m = __ballot(take);
-            if (m) {
-                const int leader = __builtin_ctzll(m);
-                int base = 0;
-                if (lane() == leader) base = atomicAdd(&b.nfront[cur ^ 1], __popcll(m));
-                base = __shfl(base, leader, WAVE);
-                if (take) N[base + __popcll(m & lanemask_lt())] = u;
-            }
+            if (__ballot(take)) bfs_push(b, take, u, cur ^ 1);
         }
     }
 }
 
 // the same for frontier nodes with more than BIG_ARCS arcs: one block each
 __global__ __launch_bounds__(BIG_BLOCK) void k_bfs_level_big(FlowBufs b, int cur, int level) {
-    __shared__ int sBase[BIG_WAVES];
-    const int nf = b.nfront[cur];
-    const int *F = b.front[cur];
-    int *N = b.front[cur ^ 1];
-    const int wv = threadIdx.x / WAVE;
+    const int nf = b.nbfront[cur];
+    const int *F = b.bfront[cur];
     constexpr int K = 4;   // arcs per thread per step: their loads go out together
     for (int i = blockIdx.x; i < nf; i += gridDim.x) {
         const int v = F[i];
-        if (b.first[v + 1] - b.first[v] <= BIG_ARCS) continue;    // block-uniform
         const int end = b.first[v + 1];
         for (int a0 = b.first[v]; a0 < end; a0 += BIG_BLOCK * K) {
             int u[K];
@@ -386,18 +394,17 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_bfs_level_big(FlowBufs b, int cur
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 const bool take = cand[k] && atomicCAS(&b.ht[u[k]], b.n, level + 1) == b.n;
-                const u64 m = __ballot(take);
-                if (lane() == 0) sBase[wv] = m ? atomicAdd(&b.nfront[cur ^ 1], __popcll(m)) : 0;
-                __builtin_amdgcn_wave_barrier();
-                if (take) N[sBase[wv] + __popcll(m & lanemask_lt())] = u[k];
-                __builtin_amdgcn_wave_barrier();
+                if (__ballot(take)) bfs_push(b, take, u[k], cur ^ 1);
             }
         }
     }
 }
 
 __global__ void k_bfs_reset(FlowBufs b, int cur) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.nfront[cur] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.nfront[cur] = 0;
+        b.nbfront[cur] = 0;
+    }
 }
 
 // The active nodes of a pass (excess > 0, height < n, not s or t), listed
@@ -820,6 +827,9 @@ void GpuFlow::Impl::residual(int n) {
     b.front[0] = I.sc.get_n<int>(n);
     b.front[1] = I.sc.get_n<int>(n);
     b.nfront = I.sc.get_n<int>(2);
+    b.bfront[0] = I.sc.get_n<int>(n);
+    b.bfront[1] = I.sc.get_n<int>(n);
+    b.nbfront = I.sc.get_n<int>(2);
     b.active = I.sc.get_n<int>(1);
     b.act_s = I.sc.get_n<int>(n);
     b.act_b = I.sc.get_n<int>(n);
@@ -849,13 +859,14 @@ int GpuFlow::Impl::global_relabel() {
     int cur = 0, level = 0;
     while (true) {
         k_bfs_level<<<grid_for(b.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cur, level);
-        if (b.nbig > 0) k_bfs_level_big<<<1024, BIG_BLOCK, 0, s>>>(b, cur, level);
+        if (b.nbig > 0) k_bfs_level_big<<<b.nbig < 1024 ? b.nbig : 1024, BIG_BLOCK, 0, s>>>(b, cur, level);
         k_bfs_reset<<<1, 1, 0, s>>>(b, cur);
         DSD_HIP(hipMemcpyAsync(pinned, b.nfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipMemcpyAsync(pinned + 1, b.nbfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
         DSD_HIP(hipStreamSynchronize(s));
         cur ^= 1;
         level++;
-        if (pinned[0] == 0 || level > b.n) break;
+        if ((pinned[0] == 0 && pinned[1] == 0) || level > b.n) break;
     }
     return level;
 }
