@@ -230,19 +230,31 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
 // Row items of the round's frontier (triangle lists): waves wave0, wave0 +
 // nwaves, ... each take a frontier vertex and write its items together.  A
 // hub's row holds thousands of items, too many for one lane.
+// Every lane of a wave takes one frontier vertex; one scan over the lanes and
+// one atomic give the 64 vertices their ranges of items, which the wave
+// then writes vertex by vertex.
 __device__ __forceinline__ void tl_items(const PeelBufs &b, int64_t wave0, int64_t nwaves) {
     const int32_t cur = b.ctl->cur, nF = b.ctl->nF[cur];
     const int32_t *F = b.F + (size_t)cur * b.n;
     int64_t *Tc = b.T + (size_t)cur * b.tcap;
-    for (int64_t i = wave0; i < nF; i += nwaves) {
-        const int32_t v = F[i];
-        const int64_t len = b.tvoff[v + 1] - b.tvoff[v];
-        const int32_t nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
-        if (nc == 0) continue;
+    for (int64_t i0 = wave0 * WAVE; i0 < nF; i0 += nwaves * WAVE) {
+        const int64_t i = i0 + lane();
+        int32_t v = 0, nc = 0;
+        if (i < nF) {
+            v = F[i];
+            const int64_t len = b.tvoff[v + 1] - b.tvoff[v];
+            nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
+        }
+        const int32_t inc = wave_incl_scan(nc);
+        const int32_t tot = __shfl(inc, WAVE - 1, WAVE);
+        if (tot == 0) continue;
         int32_t base = 0;
-        if (lane() == 0) base = atomicAdd(&b.ctl->nT[cur], nc);
-        base = __shfl(base, 0, WAVE);
-        for (int32_t c = lane(); c < nc; c += WAVE) Tc[base + c] = ((int64_t)v << 32) | c;
+        if (lane() == 0) base = atomicAdd(&b.ctl->nT[cur], tot);
+        base = __shfl(base, 0, WAVE) + inc - nc;
+        for (int j = 0; j < WAVE; j++) {
+            const int32_t vj = __shfl(v, j, WAVE), ncj = __shfl(nc, j, WAVE), bj = __shfl(base, j, WAVE);
+            for (int32_t c = lane(); c < ncj; c += WAVE) Tc[bj + c] = ((int64_t)vj << 32) | c;
+        }
     }
 }
 
