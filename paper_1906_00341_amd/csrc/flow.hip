@@ -853,19 +853,23 @@ void GpuFlow::Impl::residual(int n) {
 GpuFlow::~GpuFlow() = default;
 
 // global relabel (the scratch stays allocated until the Impl goes); returns
-// the number of levels
+// the number of levels launched (a multiple of eight)
 int GpuFlow::Impl::global_relabel() {
     k_bfs_start<<<grid_for(b.n, BLOCK, 4096), BLOCK, 0, s>>>(b);
+    // levels go out eight at a time (a level whose frontier is empty does
+    // nothing), and the host looks at the frontier after each batch
     int cur = 0, level = 0;
     while (true) {
-        k_bfs_level<<<grid_for(b.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cur, level);
-        if (b.nbig > 0) k_bfs_level_big<<<b.nbig < 1024 ? b.nbig : 1024, BIG_BLOCK, 0, s>>>(b, cur, level);
-        k_bfs_reset<<<1, 1, 0, s>>>(b, cur);
-        DSD_HIP(hipMemcpyAsync(pinned, b.nfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
-        DSD_HIP(hipMemcpyAsync(pinned + 1, b.nbfront + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, s));
+        for (int j = 0; j < 8; j++) {
+            k_bfs_level<<<grid_for(b.n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cur, level);
+            if (b.nbig > 0) k_bfs_level_big<<<b.nbig < 1024 ? b.nbig : 1024, BIG_BLOCK, 0, s>>>(b, cur, level);
+            k_bfs_reset<<<1, 1, 0, s>>>(b, cur);
+            cur ^= 1;
+            level++;
+        }
+        DSD_HIP(hipMemcpyAsync(pinned, b.nfront + cur, sizeof(int), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipMemcpyAsync(pinned + 1, b.nbfront + cur, sizeof(int), hipMemcpyDeviceToHost, s));
         DSD_HIP(hipStreamSynchronize(s));
-        cur ^= 1;
-        level++;
         if ((pinned[0] == 0 && pinned[1] == 0) || level > b.n) break;
     }
     return level;
