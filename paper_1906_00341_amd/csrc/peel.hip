@@ -636,11 +636,59 @@ __global__ void k_finish_global(PeelBufs b) {
 
 // ---------------------------------------------------------------- h = 2
 
+// A large h = 2 round from the other side: every alive vertex x counts its
+// frontier neighbours and takes them off its own degree (one writer per
+// degree, no atomics); a frontier vertex counts its frontier neighbours of
+// larger rank, so every removed edge is counted once.  Worth it once the
+// frontier is a sizeable share of the alive vertices, whose rows (the
+// compacted adjacency) are then read in place of the frontier's.
+constexpr int64_t H2_PULL_MIN = 16384, H2_PULL_SHARE = 16;
+
+__device__ __forceinline__ void process_h2_pull(const PeelBufs &b, int32_t r) {
+    PeelCtl *c = b.ctl;
+    const int32_t lc = c->lcur, cnt = c->nlist[lc];
+    const int32_t *list = b.lists + (size_t)lc * b.n;
+    const int nx = c->cur ^ 1;
+    const u64 k = level_of(b, 0);
+    const int wv = threadIdx.x / WAVE;
+    constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
+    DestroyedTally tally;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < cnt; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t x = list[i];
+        const int32_t sx = b.stamp[x];
+        if (sx < r) continue;   // removed in an earlier round (or not taking part)
+        uint32_t n_in = 0;
+        for (int64_t e = b.row_ptr[x] + lane(); e < b.row_ptr[x + 1]; e += WAVE) {
+            const int32_t y = b.col[e];
+            if (b.stamp[y] == r && (sx != r || y > x)) n_in++;
+        }
+        n_in = wave_sum(n_in);
+        if (lane() == 0) tally.add(b, x, n_in);
+        bool cross = false;
+        if (sx > r && n_in && lane() == 0) {
+            const u64 old = b.deg[x];
+            b.deg[x] = old - n_in;
+            cross = old > k && old - n_in <= k;
+        }
+        wave_push(cross, x, b.F + (size_t)nx * b.n, &c->nF[nx]);
+        wave_add_by_graph<int32_t>(cross ? 0 : -1, &b.gs[0].nF[nx], GS_STRIDE);
+        if (cross) {
+            b.stamp[x] = r + 1;
+            b.core[x] = k;
+        }
+    }
+    if (lane() == 0) tally.flush(b);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_process_h2(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur, nF = c->nF[cur];
     if (nF == 0) return;
     const int32_t r = c->round;
+    if (b.G == 1 && !b.minpeel && b.pattern == 0 && nF >= H2_PULL_MIN && (int64_t)nF * H2_PULL_SHARE >= c->n_alive) {
+        process_h2_pull(b, r);
+        return;
+    }
     const int32_t *F = b.F + (size_t)cur * b.n;
     const int wv = threadIdx.x / WAVE;
     u64 wp = 0, wn = 0;   // counted work (lane 0's tally is the wave's)

@@ -321,6 +321,24 @@ def test_tail_engine_matches_round_kernels(monkeypatch, case, h):
     assert res["0"][1:] == res["1"][1:]
 
 
+def test_h2_large_rounds_match_oracle():
+    # the first rounds of this classic core decomposition remove more than
+    # 16,384 vertices and a sixteenth of the alive ones each, so the peel
+    # counts them from the alive side; core numbers, k_max and the level
+    # count against the oracle's bucket-queue peel
+    n, s, d = synth.chung_lu(n=200000, avg_deg=10, beta=2.3, planted=2, plant_size=50, p=0.6, seed=11)
+    s = np.ascontiguousarray(s, np.int32)
+    d = np.ascontiguousarray(d, np.int32)
+    og = oracle.Graph(n, s, d)
+    core_o, km_o = og.core_decomposition(2)
+    g = dsd.build_csr(n, s, d)
+    core_g, km_g = dsd.clique_core(g, 2)
+    assert km_g == km_o
+    np.testing.assert_array_equal(core_g, core_o)
+    _, km_app, _ = dsd.core_app(g, 2)
+    assert km_app == km_o
+
+
 def test_bad_arguments():
     g = dsd.build_csr(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     for h in (0, 1, 7):
