@@ -133,12 +133,12 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
         tri_list_degrees(G->tl, n, d, s);
         D.mu = G->tl.mu;
         tl = &G->tl;
-    } else if (h == 3 && n > 0 && !G->tl_tried && tri_supports_possible(G->g)) {
-        // the lists' first pass gives the clique-degrees; its supports then
-        // serve the second pass
+    } else if (h == 3 && n > 0 && !G->tl_tried && tri_counts_possible(G->g)) {
+        // the lists' first pass gives the clique-degrees; its segment sizes
+        // then serve the second pass
         TlCounts w;
         Timer tk(s);
-        D.mu = tri_supports(G->g, d, w, s, G->sc);
+        D.mu = tri_counts(G->g, d, w, s, G->sc);
         D.kt.k3_ms += tk.stop();
         D.kt.k3_launches += 1;
         G->tl_tried = true;

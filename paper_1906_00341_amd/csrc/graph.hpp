@@ -62,7 +62,7 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
 
 // ---- triangle lists (h = 3) ----
 // Row v is pairs[2 voff[v] .. 2 voff[v+1]): a pair (a, b) for every triangle
-// {v, a, b}, twice (as (a, b) and (b, a)), grouped by a: 6 mu pairs in all.
+// {v, a, b}, once, with a ranked below b, grouped by a: 3 mu pairs in all.
 struct TriList {
     int64_t *voff = nullptr;   // [n + 1]
     int32_t *pairs = nullptr;  // [2 * entries]
@@ -73,27 +73,30 @@ struct TriList {
 // out-degree within the listing kernels, at most a quarter of free device
 // memory); the environment variable DSD_TRI_LIST=0 turns them off
 bool tri_list_wanted(const DevGraph &g, u64 mu);
-// The first pass of the listing alone: every arc's support (triangles on its
-// edge), and from them the clique-degrees (half the supports of a vertex's
-// arcs) and mu.  The arrays live in the scratch until its next reset.
+// The first pass of the listing alone: the size of every arc's segment (the
+// triangles it will hold), and from them the clique-degrees (the sum over a
+// vertex's segments) and mu.  The arrays live in the scratch until its next
+// reset.
 struct TlCounts {
     int64_t *rev = nullptr;   // [2m] reverse arc of every arc
-    u64 *cnt = nullptr;       // [2m] supports
+    uint32_t *cnt = nullptr;  // [2m] segment sizes
+    uint32_t *top = nullptr;  // [2m] triangles with the arc's head on top (forward arcs)
     int32_t *big = nullptr, *nbig = nullptr;
+    int64_t *mid = nullptr;
     u64 mu = 0;
 };
-// whether the supports can be counted (out-degrees within the listing
+// whether the segment sizes can be counted (out-degrees within the listing
 // kernels, room on the device; DSD_TRI_LIST=0 turns them off)
-bool tri_supports_possible(const DevGraph &g);
+bool tri_counts_possible(const DevGraph &g);
 // deg (length n) = clique-degrees (h = 3); returns mu
-u64 tri_supports(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc);
+u64 tri_counts(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc);
 // the second pass: every triangle written out through per-arc cursors into
-// the segments the supports give.  Allocates tl's arrays (released by
+// the segments the counts give.  Allocates tl's arrays (released by
 // free_tri_list).
 void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc);
 // both passes for a graph with mu triangles (deg unused)
 void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc);
-// clique-degrees read off finished lists (two pairs per triangle at a vertex)
+// clique-degrees read off finished lists (one pair per triangle at a vertex)
 void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s);
 void free_tri_list(TriList &tl);
 

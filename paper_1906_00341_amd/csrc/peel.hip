@@ -982,9 +982,9 @@ __global__ __launch_bounds__(BLOCK) void k_h3_flush(PeelBufs b) {
 // clique with v this round (alive, or frontier vertices of larger rank: the
 // owner rule makes v the triangle's frontier member of smallest rank).  The
 // pairs of one neighbour a are contiguous, so its losses are summed over its
-// run of lanes and applied once.  Each triangle sits twice in v's row, as
-// (a, b) and (b, a), and is counted once.  Counted work: pairs walked (pairs)
-// and items (nbrs).
+// run of lanes and applied once; b loses each triangle on its own.  Each
+// triangle sits once in v's row.  Counted work: pairs walked (pairs) and
+// items (nbrs).
 __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
@@ -1003,16 +1003,17 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
         for (int64_t base = lo; base < hi; base += WAVE) {
             const int64_t e = base + L;
             const bool valid = e < hi;
-            int32_t a = -1, x = -1, sa = -1;
+            int32_t a = -1, x = -1, sa = -1, sx = -1;
             bool ok = false;
             if (valid) {
-                a = b.tpairs[2 * e];
-                x = b.tpairs[2 * e + 1];
+                const int2 pr = *(const int2 *)&b.tpairs[2 * e];
+                a = pr.x;
+                x = pr.y;
                 sa = b.stamp[a];
-                const int32_t sx = b.stamp[x];
+                sx = b.stamp[x];
                 ok = allowed(sa, r, a, v) && allowed(sx, r, x, v);
             }
-            destroyed += (ok && a < x) ? 1 : 0;
+            destroyed += ok ? 1 : 0;
             // runs of equal a over the valid lanes
             const int32_t pa = __shfl_up(a, 1, WAVE);
             const bool head = valid && (L == 0 || pa != a);
@@ -1025,6 +1026,7 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
                 const uint32_t cnt = (uint32_t)__popcll(om & upto & ~lanemask_lt());
                 if (cnt && sa > r) dec_deg(b, a, cnt, r);
             }
+            if (ok && sx > r) dec_deg(b, x, 1, r);
         }
         destroyed = wave_sum(destroyed);
         if (L == 0) tally.add(b, v, destroyed);
@@ -1598,10 +1600,10 @@ __global__ void k_te_glob(const uint32_t *flag, const uint32_t *loc, int32_t n, 
     if (blockIdx.x == 0 && threadIdx.x == 0) *count = (int32_t)(loc[n - 1] + flag[n - 1]);
 }
 
-// The pairs of one rewrite item that stay inside the tail, each triangle
-// once (a row holds every triangle as (a, x) and as (x, a): the one with
-// a < x stays): counted (FILL false, into kc[it]) or written from kc[it] on
-// (FILL true), in row order, so every row stays grouped by its first vertex.
+// The pairs of one rewrite item that stay inside the tail (a row holds every
+// triangle once, as (a, x) with a ranked below x): counted (FILL false, into
+// kc[it]) or written from kc[it] on (FILL true), in row order, so every row
+// stays grouped by its first vertex.
 // H = 2: the rows are adjacency rows (tpairs: the column array), and each
 // neighbour x in the tail becomes the word (x, x).
 template <bool FILL, int H>
@@ -1626,7 +1628,7 @@ __global__ __launch_bounds__(BLOCK) void k_te_pairs(const int64_t *tvoff, const 
             if (e < e1) {
                 if (H == 3) {
                     const int32_t a = tpairs[2 * e], x = tpairs[2 * e + 1];
-                    keep = a < x && flag[a] && flag[x];   // rank order is local-id order
+                    keep = flag[a] && flag[x];
                     if (FILL && keep) val = (loc[a] << 16) | loc[x];
                 } else {
                     const int32_t x = tpairs[e];

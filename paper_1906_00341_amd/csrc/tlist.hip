@@ -1,18 +1,30 @@
 // Triangle lists (h = 3): row v holds a pair (a, b) for every triangle
-// {v, a, b}, twice (as (a, b) and as (b, a)), grouped by a in the order of
-// v's CSR row; the rows hold 6 mu pairs in all.
+// {v, a, b}, once, with a ranked below b, in the segment of arc (v, a); the
+// segments follow v's CSR row, so a row is grouped by a, and the rows hold
+// 3 mu pairs in all.
 //
 // The peel destroys the triangles of a removed vertex by walking its row in
 // fixed-size runs of pairs, so that even a hub's row spreads over thousands
-// of waves; each neighbour's losses are summed over its run of pairs before
-// they reach its degree.
+// of waves; the losses of a are summed over its run of pairs before they
+// reach its degree, b loses its triangle on its own.
 //
 // Listing: every triangle {u, w, x} with rank u < w < x is found once from
 // its root u, as w in N+(u) and x in N+(w) ∩ N+(u); N+(u) is hashed in LDS
-// with each member's position in row u (one wave per root of out-degree <=
-// 64, one workgroup per larger root).  A first pass counts the triangles on
-// every edge (its support, for both arcs), a second writes the six pairs
-// through per-arc cursors into the segment of each arc.
+// with each member's position in row u.  A root of out-degree <= 64 takes
+// one wave; one of out-degree <= 256 is cut into chunks of 64 out-neighbours
+// w, each chunk an item for one wave that hashes N+(u) itself (the hashing
+// costs d+(u)/64 steps against the chunk's sum of d+(w) probes, and every
+// wave of the chip stays busy); larger roots take a workgroup.  The triangle
+// goes to the segments of (u, w) as (w, x), of (w, u) as (u, x) and of
+// (x, u) as (u, w), so every segment is written only by the root of its
+// triangles, the lower end of its arc.  A first pass counts, on u's own
+// forward arcs (u, a), the triangles with a in the middle (r1, summed over a
+// run of lanes) and with a on top (r2); segment (u, a) then holds r1 pairs
+// and segment (a, u) r1 + r2.  A second pass writes the three pairs through
+// per-arc cursors.  Counts and cursors are 32-bit (a count is below n, a
+// position below 3 mu < 2^31); a write is bounded by the size of the lists,
+// and a final check that every cursor stopped exactly at its segment's end
+// catches any miscount.
 #include <cstdlib>
 #include <cstring>
 
@@ -25,6 +37,8 @@ namespace {
 
 constexpr int TL_SMALL = 64;          // roots with |N+| <= this take one wave
 constexpr int TL_SMALL_BITS = 7;      // their hash: 128 slots
+constexpr int TL_MID = 256;           // roots with |N+| <= this are cut into per-wave chunks of 64
+constexpr int TL_MID_BITS = 9;        // their hash: <= 512 slots
 constexpr int TL_MAX_OUT = 2048;      // larger roots take a workgroup, hash of <= 4096 slots
 constexpr int TL_BIG_BITS = 12;
 constexpr int TL_EMPTY = -1;
@@ -35,23 +49,26 @@ struct TlBuild {
     const int32_t *col;
     const int64_t *dag_off;
     const int64_t *rev;   // [2m] reverse arc: rev[e] for e = (v, a) is the position of v in row a
-    u64 *cnt;             // [2m] pass 0: supports of forward arcs; pass 1: write cursors
-    const int64_t *woff;  // [2m + 1] arc segment starts (pass 1)
-    int32_t *pairs;       // [2 * 6 mu] (a, b) (pass 1)
-    int32_t *big;         // roots with more than TL_SMALL out-neighbours
-    int32_t *nbig;
-    int32_t *err;         // set if a list would overflow (never, when the supports are right)
+    uint32_t *cnt;        // [2m] pass 0: r1 of forward arcs; pass 1: write cursors
+    uint32_t *top;        // [2m] pass 0: r2 of forward arcs
+    int64_t entries;      // 3 mu: the pairs' capacity (pass 1)
+    int32_t *pairs;       // [2 * 3 mu] (a, b) (pass 1)
+    int32_t *big;         // roots with more than TL_MID out-neighbours
+    int32_t *nbig;        // [0] their count, [1] the error flags, [2] the count of mid items
+    int64_t *mid;         // items (root, chunk): root | chunk << 32 for roots of TL_SMALL+1 .. TL_MID
+    int32_t *err;         // set if a list would overflow (never, when the counts are right)
     int32_t n;
     int32_t pass;         // 0: count, 1: fill
 };
 
-__device__ __forceinline__ void tl_insert(int32_t *keys, int32_t *pos, int bits, int32_t x, int32_t p) {
+template <class P>
+__device__ __forceinline__ void tl_insert(int32_t *keys, P *pos, int bits, int32_t x, int32_t p) {
     const uint32_t mask = (1u << bits) - 1;
     uint32_t slot = hash_slot(x, bits);
     while (true) {
         const int32_t prev = atomicCAS(&keys[slot], TL_EMPTY, x);
         if (prev == TL_EMPTY) {
-            pos[slot] = p;
+            pos[slot] = (P)p;
             return;
         }
         if (prev == x) return;
@@ -60,34 +77,39 @@ __device__ __forceinline__ void tl_insert(int32_t *keys, int32_t *pos, int bits,
 }
 
 // position (offset in N+(u)) of x, or -1
-__device__ __forceinline__ int32_t tl_find(const int32_t *keys, const int32_t *pos, int bits, int32_t x) {
+template <class P>
+__device__ __forceinline__ int32_t tl_find(const int32_t *keys, const P *pos, int bits, int32_t x) {
     const uint32_t mask = (1u << bits) - 1;
     uint32_t slot = hash_slot(x, bits);
     while (true) {
         const int32_t k = keys[slot];
-        if (k == x) return pos[slot];
+        if (k == x) return (int32_t)pos[slot];
         if (k == TL_EMPTY) return -1;
         slot = (slot + 1) & mask;
     }
 }
 
-// pair (a, y) into the segment of arc e = (v, a) through its cursor
-__device__ __forceinline__ void tl_put(const TlBuild &b, int64_t e, int32_t a, int32_t y) {
-    const int64_t p = (int64_t)atomicAdd(&b.cnt[e], (u64)1);
-    if (p >= b.woff[e + 1]) {
+// pair (a, y) at position p of the lists (p from an arc's cursor)
+__device__ __forceinline__ void tl_store(const TlBuild &b, int64_t p, int32_t a, int32_t y) {
+    if (p >= b.entries) {
         atomicOr(b.err, 1);
         return;
     }
-    b.pairs[2 * p] = a;
-    b.pairs[2 * p + 1] = y;
+    *(int2 *)&b.pairs[2 * p] = make_int2(a, y);
+}
+
+// pair (a, y) into the segment of arc e = (v, a) through its cursor
+__device__ __forceinline__ void tl_put(const TlBuild &b, int64_t e, int32_t a, int32_t y) {
+    tl_store(b, (int64_t)atomicAdd(&b.cnt[e], 1u), a, y);
 }
 
 // One wave: the triangles {u, w, x} for the out-neighbours w of u at row
 // positions [lo, hi) (hi - lo <= 64; u's out-list starts at ulo), x in N+(w)
 // found in the hash of N+(u).  The (w, x) pairs are flattened over the
 // lanes.  sPre/sSt/sW: this wave's 64-entry LDS scratch.
+template <class P>
 __device__ __forceinline__ void tl_range(const TlBuild &b, int32_t u, int64_t ulo, const int32_t *keys,
-                                         const int32_t *pos, int bits, int64_t lo, int64_t hi, int32_t *sPre,
+                                         const P *pos, int bits, int64_t lo, int64_t hi, int32_t *sPre,
                                          int64_t *sSt, int32_t *sW) {
     const int L = lane();
     int32_t w = -1, len = 0;
@@ -103,18 +125,31 @@ __device__ __forceinline__ void tl_range(const TlBuild &b, int32_t u, int64_t ul
     sW[L] = w;
     const int32_t total = __shfl(inc, WAVE - 1, WAVE);
     __builtin_amdgcn_wave_barrier();
+    // a lane's step p lies in the row of w number i = the first with
+    // sPre[i] > p; the next step's i (a search from the current one, which
+    // mostly ends at its first test) and neighbour are fetched while this
+    // step's are probed
+    int i_n = 0;
+    int64_t e_n = 0;
+    int32_t x_n = -1;
+    if (L < total) {
+        i_n = upper_bound_i32(sPre, WAVE, L);
+        e_n = sSt[i_n] + (L - (i_n ? sPre[i_n - 1] : 0));
+        x_n = b.col[e_n];
+    }
     for (int32_t pb = 0; pb < total; pb += WAVE) {
         const int32_t p = pb + L;
-        int i = 0;
-        int32_t x = -1, px = -1;
-        int64_t e_wx = 0;
-        if (p < total) {
-            i = upper_bound_i32(sPre, WAVE, p);
-            const int32_t o = p - (i ? sPre[i - 1] : 0);
-            e_wx = sSt[i] + o;
-            x = b.col[e_wx];
-            px = tl_find(keys, pos, bits, x);
+        const int i = i_n;
+        const int64_t e_wx = e_n;
+        const int32_t x = x_n;
+        if (p + WAVE < total) {
+            const int32_t q = p + WAVE;     // sPre[WAVE - 1] = total > q bounds both searches
+            if (sPre[i_n] <= q) i_n += 1 + upper_bound_i32(sPre + i_n + 1, WAVE - 1 - i_n, q);
+            e_n = sSt[i_n] + (q - (i_n ? sPre[i_n - 1] : 0));
+            x_n = b.col[e_n];
         }
+        int32_t px = -1;
+        if (p < total) px = tl_find(keys, pos, bits, x);
         const bool found = px >= 0;
         const u64 fm = __ballot(found);
         if (!fm) continue;
@@ -130,40 +165,23 @@ __device__ __forceinline__ void tl_range(const TlBuild &b, int32_t u, int64_t ul
         const int32_t c = __popcll(fm & run);
         const int64_t e_uw = lo + i, e_ux = ulo + px;
         if (b.pass == 0) {
-            if (L == start && c > 0) atomicAdd(&b.cnt[e_uw], (u64)c);
-            if (found) {
-                atomicAdd(&b.cnt[e_ux], (u64)1);
-                atomicAdd(&b.cnt[e_wx], (u64)1);
-            }
+            if (L == start && c > 0) atomicAdd(&b.cnt[e_uw], (uint32_t)c);
+            if (found) atomicAdd(&b.top[e_ux], 1u);
         } else {
-            // the two lists of edge (u, w) take one cursor step per run
-            u64 b1 = 0, b2 = 0;
+            // segments (u, w) and (w, u) take one cursor step per run
+            uint32_t b1 = 0, b2 = 0;
             if (L == start && c > 0) {
-                b1 = atomicAdd(&b.cnt[e_uw], (u64)c);
-                b2 = atomicAdd(&b.cnt[b.rev[e_uw]], (u64)c);
+                b1 = atomicAdd(&b.cnt[e_uw], (uint32_t)c);
+                b2 = atomicAdd(&b.cnt[b.rev[e_uw]], (uint32_t)c);
             }
             b1 = __shfl(b1, start, WAVE);
             b2 = __shfl(b2, start, WAVE);
             if (found) {
                 const int32_t k = __popcll(fm & run & lanemask_lt());
                 const int32_t wv = sW[i];
-                const int64_t q1 = (int64_t)b1 + k, q2 = (int64_t)b2 + k;
-                if (q1 < b.woff[e_uw + 1]) {
-                    b.pairs[2 * q1] = wv;
-                    b.pairs[2 * q1 + 1] = x;
-                } else {
-                    atomicOr(b.err, 1);
-                }
-                if (q2 < b.woff[b.rev[e_uw] + 1]) {
-                    b.pairs[2 * q2] = u;
-                    b.pairs[2 * q2 + 1] = x;
-                } else {
-                    atomicOr(b.err, 1);
-                }
-                tl_put(b, e_ux, x, wv);
+                tl_store(b, (int64_t)b1 + k, wv, x);
+                tl_store(b, (int64_t)b2 + k, u, x);
                 tl_put(b, b.rev[e_ux], u, wv);
-                tl_put(b, e_wx, x, u);
-                tl_put(b, b.rev[e_wx], wv, u);
             }
         }
     }
@@ -183,7 +201,15 @@ __global__ __launch_bounds__(BLOCK) void k_tl_small(TlBuild b) {
         const int64_t d = hi - lo;
         if (d < 2) continue;
         if (d > TL_SMALL) {
-            if (b.pass == 0 && L == 0) b.big[atomicAdd(b.nbig, 1)] = (int32_t)u;
+            if (b.pass == 0 && L == 0) {
+                if (d > TL_MID) {
+                    b.big[atomicAdd(b.nbig, 1)] = (int32_t)u;
+                } else {
+                    const int32_t k = (int32_t)((d + WAVE - 1) / WAVE);
+                    const int32_t q = atomicAdd(b.nbig + 2, k);
+                    for (int32_t c = 0; c < k; c++) b.mid[q + c] = u | ((int64_t)c << 32);
+                }
+            }
             continue;
         }
         for (int i = L; i < (1 << TL_SMALL_BITS); i += WAVE) sKey[wv][i] = TL_EMPTY;
@@ -194,7 +220,34 @@ __global__ __launch_bounds__(BLOCK) void k_tl_small(TlBuild b) {
     }
 }
 
-// queued roots (out-degree TL_SMALL+1 .. TL_MAX_OUT), one workgroup each
+// chunks of 64 out-neighbours of the queued roots of out-degree
+// TL_SMALL+1 .. TL_MID, one wave each; the wave hashes N+(u) first
+__global__ __launch_bounds__(BLOCK) void k_tl_mid(TlBuild b) {
+    __shared__ int32_t sKey[WAVES_PER_BLOCK][1 << TL_MID_BITS];
+    __shared__ int16_t sPos[WAVES_PER_BLOCK][1 << TL_MID_BITS];
+    __shared__ int32_t sPre[WAVES_PER_BLOCK][WAVE];
+    __shared__ int64_t sSt[WAVES_PER_BLOCK][WAVE];
+    __shared__ int32_t sW[WAVES_PER_BLOCK][WAVE];
+    const int wv = threadIdx.x / WAVE, L = lane();
+    const int32_t ni = b.nbig[2];
+    for (int32_t it = blockIdx.x * WAVES_PER_BLOCK + wv; it < ni; it += gridDim.x * WAVES_PER_BLOCK) {
+        const int64_t item = b.mid[it];
+        const int32_t u = (int32_t)(item & 0xffffffff);
+        const int64_t c = item >> 32;
+        const int64_t lo = b.dag_off[u], hi = b.row_ptr[u + 1];
+        const int32_t d = (int32_t)(hi - lo);
+        int bits = TL_SMALL_BITS;
+        while ((1 << bits) < 2 * d) bits++;             // load <= 1/2; d <= TL_MID keeps bits <= TL_MID_BITS
+        for (int i = L; i < (1 << bits); i += WAVE) sKey[wv][i] = TL_EMPTY;
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t j = L; j < d; j += WAVE) tl_insert(sKey[wv], sPos[wv], bits, b.col[lo + j], j);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t a = lo + c * WAVE;
+        tl_range(b, u, lo, sKey[wv], sPos[wv], bits, a, a + WAVE < hi ? a + WAVE : hi, sPre[wv], sSt[wv], sW[wv]);
+    }
+}
+
+// queued roots (out-degree TL_MID+1 .. TL_MAX_OUT), one workgroup each
 __global__ __launch_bounds__(BLOCK) void k_tl_big(TlBuild b) {
     __shared__ int32_t sKey[1 << TL_BIG_BITS];
     __shared__ int32_t sPos[1 << TL_BIG_BITS];
@@ -234,52 +287,52 @@ __global__ void k_tl_rev(const int64_t *row_ptr, const int32_t *col, const int64
     }
 }
 
-// supports of reverse arcs from their forward arcs; -1 in rev means a
-// broken CSR (never)
-__global__ void k_tl_mirror(const int64_t *row_ptr, const int64_t *dag_off, const int64_t *rev, int32_t n, u64 *cnt,
-                            int32_t *err) {
+// segment sizes of reverse arcs: (a, v) for the forward arc (v, a) holds
+// r1 + r2 of (v, a); -1 in rev means a broken CSR (never)
+__global__ void k_tl_mirror(const int64_t *row_ptr, const int64_t *dag_off, const int64_t *rev, int32_t n, uint32_t *cnt,
+                            const uint32_t *top, int32_t *err) {
     const int wv = threadIdx.x / WAVE;
     for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         for (int64_t e = dag_off[v] + lane(); e < row_ptr[v + 1]; e += WAVE) {
             const int64_t f = rev[e];
             if (f < 0) atomicOr(err, 4);
-            else cnt[f] = cnt[e];
+            else cnt[f] = cnt[e] + top[e];
         }
     }
 }
 
 // every list must be exactly full
-__global__ void k_tl_check(const u64 *cur, const int64_t *woff, int64_t arcs, int32_t *err) {
+__global__ void k_tl_check(const uint32_t *cur, const uint32_t *woff, int64_t arcs, int32_t *err) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < arcs; e += (int64_t)gridDim.x * blockDim.x)
-        if ((int64_t)cur[e] != woff[e + 1]) atomicOr(err, 2);
+        if (cur[e] != woff[e + 1]) atomicOr(err, 2);
 }
 
-__global__ void k_tl_offsets_tail(int64_t *woff, const u64 *cnt, int64_t arcs) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) woff[arcs] = woff[arcs - 1] + (int64_t)cnt[arcs - 1];
+__global__ void k_tl_offsets_tail(uint32_t *woff, const uint32_t *cnt, int64_t arcs) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) woff[arcs] = woff[arcs - 1] + cnt[arcs - 1];
 }
 
-// clique-degrees from the supports: every triangle at v is counted on two of
-// v's arcs (one wave per vertex)
-__global__ void k_tl_degrees(const int64_t *row_ptr, const u64 *cnt, int32_t n, u64 *deg) {
+// clique-degrees from the segment sizes: every triangle at v lies in one of
+// v's segments (one wave per vertex)
+__global__ void k_tl_degrees(const int64_t *row_ptr, const uint32_t *cnt, int32_t n, u64 *deg) {
     const int wv = threadIdx.x / WAVE;
     for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         u64 sum = 0;
         for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) sum += cnt[e];
         sum = wave_sum(sum);
-        if (lane() == 0) deg[v] = sum / 2;
+        if (lane() == 0) deg[v] = sum;
     }
 }
 
-// clique-degrees from finished lists: row v holds two pairs per triangle at v
+// clique-degrees from finished lists: row v holds one pair per triangle at v
 __global__ void k_tl_row_degrees(const int64_t *voff, int32_t n, u64 *deg) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        deg[v] = (u64)(voff[v + 1] - voff[v]) / 2;
+        deg[v] = (u64)(voff[v + 1] - voff[v]);
 }
 
 // row starts: voff[v] = start of v's first arc segment
-__global__ void k_tl_rows(const int64_t *row_ptr, const int64_t *woff, int32_t n, int64_t *voff) {
+__global__ void k_tl_rows(const int64_t *row_ptr, const uint32_t *woff, int32_t n, int64_t *voff) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x)
-        voff[v] = woff[row_ptr[v]];
+        voff[v] = (int64_t)woff[row_ptr[v]];
 }
 
 }  // namespace
@@ -288,8 +341,8 @@ bool tri_list_wanted(const DevGraph &g, u64 mu) {
     const char *e = std::getenv("DSD_TRI_LIST");
     if (e && std::strcmp(e, "0") == 0) return false;
     if (g.n == 0 || mu == 0 || g.maxdout > TL_MAX_OUT) return false;
-    if (mu > (u64)0x7fffffff / 6) return false;             // entries are counted in int32 positions
-    const int64_t entries = 6 * (int64_t)mu, arcs = 2 * g.m;
+    if (mu > (u64)0x7fffffff / 3) return false;             // entries are counted in int32 positions
+    const int64_t entries = 3 * (int64_t)mu, arcs = 2 * g.m;
     // pairs and row starts, and the build's segment starts, cursors and reverse arcs
     const int64_t bytes = 8 * entries + 8 * ((int64_t)g.n + 1) + 24 * arcs + 8;
     size_t free_b = 0, total_b = 0;
@@ -297,41 +350,47 @@ bool tri_list_wanted(const DevGraph &g, u64 mu) {
     return bytes <= TL_MAX_BYTES && bytes <= (int64_t)(free_b / 4);
 }
 
-bool tri_supports_possible(const DevGraph &g) {
+bool tri_counts_possible(const DevGraph &g) {
     const char *e = std::getenv("DSD_TRI_LIST");
     if (e && std::strcmp(e, "0") == 0) return false;
     if (g.n == 0 || g.m == 0 || g.maxdout > TL_MAX_OUT) return false;
-    // reverse arcs, supports and segment starts: 24 B per arc
+    // reverse arcs, counts and segment starts: at most 24 B per arc
     const int64_t bytes = 24 * 2 * g.m + 8 * ((int64_t)g.n + 1);
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
     return bytes <= (int64_t)(free_b / 4);
 }
 
-u64 tri_supports(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc) {
+u64 tri_counts(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch &sc) {
     const int32_t n = g.n;
     const int64_t arcs = 2 * g.m;
     w.rev = sc.get_n<int64_t>(arcs);
-    w.cnt = sc.get_n<u64>(arcs);
+    w.cnt = sc.get_n<uint32_t>(arcs);
+    w.top = sc.get_n<uint32_t>(arcs);
     w.big = sc.get_n<int32_t>(n);
-    w.nbig = sc.get_n<int32_t>(2);
-    fill_i32(w.nbig, 0, 2, s);
-    fill_u64(w.cnt, 0, arcs, s);
+    w.nbig = sc.get_n<int32_t>(3);
+    w.mid = sc.get_n<int64_t>(g.m / 32 + 2);     // sum of ceil(d/64) over roots with d > 64 is below m/32 + 1
+    fill_i32(w.nbig, 0, 3, s);
+    fill_i32((int32_t *)w.cnt, 0, arcs, s);
+    fill_i32((int32_t *)w.top, 0, arcs, s);
     TlBuild b{};
     b.row_ptr = g.row_ptr;
     b.col = g.col;
     b.dag_off = g.dag_off;
     b.rev = w.rev;
     b.cnt = w.cnt;
+    b.top = w.top;
     b.big = w.big;
     b.nbig = w.nbig;
+    b.mid = w.mid;
     b.err = w.nbig + 1;
     b.n = n;
     k_tl_rev<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, g.dag_off, n, w.rev);
     b.pass = 0;
     k_tl_small<<<grid_for(n, WAVES_PER_BLOCK, 4096), BLOCK, 0, s>>>(b);
+    k_tl_mid<<<4096, BLOCK, 0, s>>>(b);
     k_tl_big<<<1024, BLOCK, 0, s>>>(b);
-    k_tl_mirror<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.dag_off, w.rev, n, w.cnt, b.err);
+    k_tl_mirror<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.dag_off, w.rev, n, w.cnt, w.top, b.err);
     k_tl_degrees<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, w.cnt, n, deg);
     u64 *sum = sc.get_n<u64>(2);
     sum_u64_128(deg, n, sum, s, sc);
@@ -340,8 +399,8 @@ u64 tri_supports(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratc
     DSD_HIP(hipMemcpyAsync(hs, sum, sizeof(hs), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipMemcpyAsync(&err, b.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
-    if (err) throw Error(-3, "triangle supports: a reverse arc is missing");
-    if (hs[1] != 0 || hs[0] % 3 != 0) throw Error(-3, "triangle supports: clique-degree sum not a multiple of 3");
+    if (err) throw Error(-3, "triangle lists: a reverse arc is missing");
+    if (hs[1] != 0 || hs[0] % 3 != 0) throw Error(-3, "triangle lists: clique-degree sum not a multiple of 3");
     w.mu = hs[0] / 3;
     return w.mu;
 }
@@ -351,7 +410,8 @@ void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, 
     const int32_t n = g.n;
     const int64_t arcs = 2 * g.m;
     tl.mu = w.mu;
-    tl.entries = 6 * (int64_t)w.mu;
+    tl.entries = 3 * (int64_t)w.mu;
+    if (tl.entries > 0x7fffffff) throw Error(-3, "triangle lists: positions exceed 31 bits");
     if (hipMalloc(&tl.voff, (size_t)(n + 1) * sizeof(int64_t)) != hipSuccess ||
         hipMalloc(&tl.pairs, (size_t)(tl.entries > 0 ? tl.entries : 1) * 2 * sizeof(int32_t)) != hipSuccess) {
         free_tri_list(tl);
@@ -363,35 +423,37 @@ void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, 
     b.dag_off = g.dag_off;
     b.rev = w.rev;
     b.cnt = w.cnt;
-    int64_t *woff = sc.get_n<int64_t>(arcs + 1);
-    b.woff = woff;
+    uint32_t *woff = sc.get_n<uint32_t>(arcs + 1);
+    b.entries = tl.entries;
     b.pairs = tl.pairs;
     b.big = w.big;
     b.nbig = w.nbig;
+    b.mid = w.mid;
     b.err = w.nbig + 1;
     b.n = n;
-    scan_exclusive_i64((const int64_t *)w.cnt, woff, arcs, s, sc);
+    scan_exclusive_u32(w.cnt, woff, arcs, s, sc);
     k_tl_offsets_tail<<<1, 1, 0, s>>>(woff, w.cnt, arcs);
     int32_t err = 0;
-    int64_t total = 0;
+    uint32_t total = 0;
     DSD_HIP(hipMemcpyAsync(&err, b.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    DSD_HIP(hipMemcpyAsync(&total, woff + arcs, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DSD_HIP(hipMemcpyAsync(&total, woff + arcs, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
-    if (err || total != tl.entries) {      // every reverse arc found, supports summing to 6 mu
+    if (err || (int64_t)total != tl.entries) {      // every reverse arc found, segments summing to 3 mu
         free_tri_list(tl);
-        throw Error(-3, "triangle lists do not match the supports");
+        throw Error(-3, "triangle lists do not match their counts");
     }
-    DSD_HIP(hipMemcpyAsync(b.cnt, woff, (size_t)arcs * sizeof(u64), hipMemcpyDeviceToDevice, s));
+    DSD_HIP(hipMemcpyAsync(b.cnt, woff, (size_t)arcs * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     k_tl_rows<<<grid_for((int64_t)n + 1, BLOCK, 4096), BLOCK, 0, s>>>(g.row_ptr, woff, n, tl.voff);
     b.pass = 1;
     k_tl_small<<<grid_for(n, WAVES_PER_BLOCK, 4096), BLOCK, 0, s>>>(b);
+    k_tl_mid<<<4096, BLOCK, 0, s>>>(b);
     k_tl_big<<<1024, BLOCK, 0, s>>>(b);
     k_tl_check<<<grid_for(arcs, BLOCK, 4096), BLOCK, 0, s>>>(b.cnt, woff, arcs, b.err);
     DSD_HIP(hipMemcpyAsync(&err, b.err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     if (err) {
         free_tri_list(tl);
-        throw Error(-3, "triangle lists do not match the supports");
+        throw Error(-3, "triangle lists do not match their counts");
     }
 }
 
@@ -399,7 +461,7 @@ void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipS
     (void)deg;
     TlCounts w;
     u64 *d = sc.get_n<u64>(g.n);
-    if (tri_supports(g, d, w, s, sc) != mu) throw Error(-3, "triangle lists do not match the clique-degrees");
+    if (tri_counts(g, d, w, s, sc) != mu) throw Error(-3, "triangle lists do not match the clique-degrees");
     build_tri_list(g, w, tl, s, sc);
 }
 
