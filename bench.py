@@ -87,12 +87,14 @@ TAIL_KERNEL = "k_tail_engine"
 
 
 def tail_kernel_bytes(st: dict) -> float:
-    """Algorithmic bytes of the h = 3 tail engine over one peel: every walked
-    pair is one 4-byte word of the rewritten rows; every tail vertex costs its
+    """Algorithmic bytes of the h = 3 tail engine over one peel: every pair it
+    walks is one 4-byte word of the rewritten rows; every tail vertex costs its
     degree and id in (8 + 4 B), its two row offsets (16 B), its id again and
-    its core number out (4 + 8 B).  The degrees and states themselves stay in
-    LDS for the whole launch."""
-    return 4.0 * st["k4_tail_pairs"] + 40.0 * st["k4_tail_vertices"]
+    its core number out (4 + 8 B); every round handed to the grid costs each
+    tail vertex its degree and state out (5 B) and back in with its row start
+    (13 B).  The degrees and states stay in LDS while the engine runs."""
+    return (4.0 * st["k4_tail_pairs"] + 40.0 * st["k4_tail_vertices"]
+            + 18.0 * st["k4_tail_vertices"] * st["k4_tail_grid_rounds"])
 
 
 PEEL_SOURCE = os.path.join(ROOT, "paper_1906_00341_amd", "csrc", "peel.hip")
@@ -354,7 +356,9 @@ def main() -> int:
                      main_kernel_bytes(inst))
     main_roof.update({"pairs_per_step": inst["k4_main_pairs"], "nbrs_per_step": inst["k4_main_nbrs"]})
     tail_roof = roof(TAIL_KERNEL, inst["k4_tail_ms"], inst["k4_tail_launches"], tail_kernel_bytes(inst))
-    tail_roof.update({"pairs_per_step": inst["k4_tail_pairs"], "tail_vertices": inst["k4_tail_vertices"]})
+    tail_roof.update({"pairs_per_step": inst["k4_tail_pairs"], "tail_vertices": inst["k4_tail_vertices"],
+                      "grid_rounds": inst["k4_tail_grid_rounds"], "grid_pairs": inst["k4_tail_grid_pairs"],
+                      "grid_ms": inst["k4_tail_grid_ms"]})
     if inst["k4_tail_ms"] > inst["k4_main_ms"]:
         dominant, other = tail_roof, main_roof
     else:

@@ -97,13 +97,19 @@ typedef struct {
     /* networks of the exact step built on the device (h = 3 components with
      * enough edges); the others were built on the host */
     uint64_t flow_gpu_networks;
-    /* the h = 3 peel's tail engine (one workgroup takes every round once at
-     * most 16384 vertices are alive): its time (HIP events, with
-     * dsd_set_kernel_timing on; else 0), launches, the row pairs it walked
-     * (each triangle among the tail vertices once per row) and the vertices
-     * it peeled */
+    /* the peel's tail engine (h = 3 with triangle lists, and h = 2: one
+     * workgroup takes every round once at most 16384 vertices are alive):
+     * its time (HIP events around every launch, with dsd_set_kernel_timing
+     * on; else 0), launches (one per peel that reaches it, one more after
+     * every grid round), the row pairs it walked (each clique among the tail
+     * vertices once per row) and the vertices it peeled */
     double k4_tail_ms;
     uint64_t k4_tail_launches, k4_tail_pairs, k4_tail_vertices;
+    /* the tail's rounds whose frontier rows hold more than 2^18 pairs, which
+     * the engine hands to a kernel on every CU: their time (HIP events, with
+     * dsd_set_kernel_timing on; else 0), count and pairs */
+    double k4_tail_grid_ms;
+    uint64_t k4_tail_grid_rounds, k4_tail_grid_pairs;
 } dsd_stats;
 
 /*

@@ -80,6 +80,9 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k4_tail_launches = kt.tail_launches;
     G->stats.k4_tail_pairs = kt.tail_pairs;
     G->stats.k4_tail_vertices = kt.tail_vertices;
+    G->stats.k4_tail_grid_ms = kt.tail_grid_ms;
+    G->stats.k4_tail_grid_rounds = kt.tail_grid_rounds;
+    G->stats.k4_tail_grid_pairs = kt.tail_grid_pairs;
 }
 
 // clique-degrees (rank space) and mu; throws on overflow

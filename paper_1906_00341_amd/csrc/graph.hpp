@@ -39,11 +39,15 @@ struct KernelTimes {
     u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
     int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass
     bool time_main = false;   // bracket every main-kernel launch with HIP events (main_ms)
-    // the h = 3 tail engine (one launch per peel that reaches it): its time
-    // (HIP events, with time_main), launches, the row pairs it walked and the
-    // tail vertices it peeled
+    // the tail engine (h = 3 with triangle lists, h = 2): its time (HIP
+    // events around every launch, with time_main), launches (one per peel
+    // that reaches it, plus one per grid round), the row pairs it walked and
+    // the tail vertices it peeled; and the rounds it handed to the grid, their
+    // time (with time_main) and pairs
     double tail_ms = 0;
     u64 tail_launches = 0, tail_pairs = 0, tail_vertices = 0;
+    double tail_grid_ms = 0;
+    u64 tail_grid_rounds = 0, tail_grid_pairs = 0;
 };
 
 // ---- K1 + K2: CSR build and degree-ordered orientation ----

@@ -292,6 +292,39 @@ __device__ __forceinline__ void dec_deg(const PeelBufs &b, int32_t x, u64 c, int
     }
 }
 
+// two survivors per lane lose cliques (c = 0: none): both atomics are in
+// flight before either result is needed, and the whole wave calls this
+__device__ __forceinline__ void dec_deg2(const PeelBufs &b, int32_t x1, u64 c1, int32_t x2, u64 c2, int32_t r) {
+    if (b.minpeel) {
+        if (c1) atomic_sub_u64(&b.deg[x1], c1);
+        if (c2) atomic_sub_u64(&b.deg[x2], c2);
+        return;
+    }
+    const int32_t g1 = c1 ? graph_of(b, x1) : -1, g2 = c2 ? graph_of(b, x2) : -1;
+    const u64 k1 = c1 ? level_of(b, g1) : 0, k2 = c2 ? level_of(b, g2) : 0;
+    u64 o1 = 0, o2 = 0;
+    if (c1) o1 = atomic_sub_u64(&b.deg[x1], c1);
+    if (c2) o2 = atomic_sub_u64(&b.deg[x2], c2);
+    const bool cr1 = c1 && o1 > k1 && o1 - c1 <= k1;
+    const bool cr2 = c2 && o2 > k2 && o2 - c2 <= k2;
+    const int nx = b.ctl->cur ^ 1;
+    constexpr size_t GS_STRIDE = sizeof(GraphState) / sizeof(int32_t);
+    wave_push(cr1, x1, b.F + (size_t)nx * b.n, &b.ctl->nF[nx]);
+    wave_add_by_graph<int32_t>(cr1 ? g1 : -1, &b.gs[0].nF[nx], GS_STRIDE);
+    wave_push(cr2, x2, b.F + (size_t)nx * b.n, &b.ctl->nF[nx]);
+    wave_add_by_graph<int32_t>(cr2 ? g2 : -1, &b.gs[0].nF[nx], GS_STRIDE);
+    if (cr1) {
+        b.stamp[x1] = r + 1;
+        b.core[x1] = k1;
+        push_work(b, x1, nx);
+    }
+    if (cr2) {
+        b.stamp[x2] = r + 1;
+        b.core[x2] = k2;
+        push_work(b, x2, nx);
+    }
+}
+
 // cliques destroyed through frontier vertex v
 __device__ __forceinline__ void add_destroyed(const PeelBufs &b, int32_t v, u64 t) {
     if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed, t);
@@ -1022,11 +1055,8 @@ __global__ __launch_bounds__(BLOCK) void k_tl_process(PeelBufs b) {
             const u64 nxt = hm & ~le;
             const int end = nxt ? __builtin_ctzll(nxt) : WAVE;
             const u64 upto = end == WAVE ? ~0ull : ((1ull << end) - 1);
-            if (head) {
-                const uint32_t cnt = (uint32_t)__popcll(om & upto & ~lanemask_lt());
-                if (cnt && sa > r) dec_deg(b, a, cnt, r);
-            }
-            if (ok && sx > r) dec_deg(b, x, 1, r);
+            const uint32_t cnt = head ? (uint32_t)__popcll(om & upto & ~lanemask_lt()) : 0u;
+            dec_deg2(b, a, sa > r ? cnt : 0u, x, (ok && sx > r) ? 1u : 0u, r);
         }
         destroyed = wave_sum(destroyed);
         if (L == 0) tally.add(b, v, destroyed);
@@ -1579,6 +1609,31 @@ constexpr int TE_FB = 2048;                   // frontier vertices per batch of 
 constexpr int TE_CH = 4096;                   // pairs per item of the row rewrite
 constexpr uint32_t TE_NONE = 0xffffffffu;     // padding (local ids are below 2^14)
 constexpr uint8_t TE_DEAD = 0, TE_CUR = 1, TE_ALIVE = 2;
+constexpr uint32_t TE_HEAVY = 1u << 18;       // a round whose frontier rows hold more pairs goes to the grid
+                                              // (DSD_TE_GRID_PAIRS overrides it)
+constexpr int TE_HBLOCK = 1024;               // threads per workgroup of the grid round
+
+// The engine's state across a round handed to the grid: the engine stops
+// with its frontier marked (TE_CUR) and its rows' items listed, k_te_heavy
+// processes those items on every CU, and the engine starts again where the
+// round ends.  On a single CU a round of the dense innermost levels (hundreds
+// of vertices whose rows hold tens of millions of pairs) takes milliseconds;
+// the grid takes tens of microseconds.
+struct TeState {
+    uint32_t *deg;        // [A] degrees (a removed vertex's slot: its core number)
+    uint8_t *st;          // [A] TE_DEAD / TE_CUR / TE_ALIVE
+    uint32_t *F;          // [nF] the round's frontier (local ids)
+    uint32_t *ipre;       // [nF + 1] each frontier vertex's first item; ipre[nF] = items
+    uint32_t *imap;       // [items] item -> frontier position
+    int32_t heavy;        // set when the engine stopped for a grid round
+    int32_t r, nlevels, open;
+    uint32_t nF, items;
+    u64 k, mu_alive;
+    int64_t n_alive;
+    u64 destroyed;        // cliques the grid round destroyed
+    u64 pairs;            // pairs of all grid rounds
+    u64 rounds;           // grid rounds
+};
 
 // tail membership: alive, or in the pending frontier of the next round
 __global__ void k_te_flags(const int32_t *stamp, int32_t n, const PeelCtl *c, uint32_t *flag) {
@@ -1725,20 +1780,25 @@ struct TeRed {
     uint32_t cnt[2][TE_WAVES];
     uint32_t mn[2][TE_WAVES];
     uint32_t sum[2][TE_WAVES];
+    uint32_t sum2[2][TE_WAVES];
 };
 
-// exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall) and
-// sum of s (*sall) over the workgroup; every thread calls it with the same par
+// exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall),
+// sum of s (*sall) and, with S2, sum of s2 (*s2all) over the workgroup;
+// every thread calls it with the same par
+template <bool S2 = false>
 __device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, uint32_t m, uint32_t s, uint32_t *ctot,
-                                              uint32_t *mall, uint32_t *sall) {
+                                              uint32_t *mall, uint32_t *sall, uint32_t s2 = 0, uint32_t *s2all = nullptr) {
     const int wv = threadIdx.x / WAVE, L = lane();
     uint32_t wtot = 0;
     const uint32_t pre = te_wave_prefix(c, &wtot);
     const uint32_t wmin = te_wave_reduce<true>(m), wsum = te_wave_reduce<false>(s);
+    const uint32_t wsum2 = S2 ? te_wave_reduce<false>(s2) : 0u;
     if (L == 0) {
         R.cnt[par][wv] = wtot;
         R.mn[par][wv] = wmin;
         R.sum[par][wv] = wsum;
+        if (S2) R.sum2[par][wv] = wsum2;
     }
     te_sync();
     const uint32_t ci = L < TE_WAVES ? R.cnt[par][L] : 0u;
@@ -1748,6 +1808,7 @@ __device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, ui
     *ctot = te_wave_reduce<false>(ci);
     *mall = te_wave_reduce<true>(mi);
     *sall = te_wave_reduce<false>(si);
+    if (S2) *s2all = te_wave_reduce<false>(L < TE_WAVES ? R.sum2[par][L] : 0u);
     par ^= 1;
     return before + pre;
 }
@@ -1777,11 +1838,25 @@ __device__ __forceinline__ uint32_t te_mask(const uint32_t *d, const uint32_t *s
     return mask;
 }
 
+// pairs in the rows of this thread's frontier ids
+__device__ __forceinline__ uint32_t te_front_pairs(uint32_t mask, int l0, const uint32_t *sRs) {
+    uint32_t p = 0;
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
+        const int l = l0 + __builtin_ctz(mm);
+        p += sRs[l + 1] - sRs[l];
+    }
+    return p;
+}
+
 // lrow (A + 1 entries) below 2^32: the row starts live in LDS.  H = 2: a
 // removed vertex costs each alive neighbour x (the word (x, x)) one edge.
+// resume: the state comes from ts, where the engine left it for a grid
+// round, and that round ends first.  A round whose frontier rows hold more
+// than heavy pairs is left to the grid.
 template <int H>
 __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int32_t *glob, const int64_t *lrow,
-                                                          const uint32_t *lp, int32_t A, int32_t *err) {
+                                                          const uint32_t *lp, int32_t A, int32_t *err, TeState *ts,
+                                                          int resume, uint32_t heavy) {
     __shared__ __align__(16) uint32_t sDeg[TE_MAX];
     __shared__ __align__(16) uint8_t sSt[TE_MAX];
     __shared__ uint32_t sRs[TE_MAX + 1];
@@ -1791,22 +1866,52 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
     PeelCtl *c = b.ctl;
     GraphState *gs = b.gs;
     const int t = threadIdx.x, wv = t / WAVE, L = lane();
-    for (int l = t; l < TE_MAX; l += TE_BLOCK) {
-        sDeg[l] = l < A ? (uint32_t)b.deg[glob[l]] : 0u;
-        sSt[l] = l < A ? TE_ALIVE : TE_DEAD;
-    }
-    for (int l = t; l <= A; l += TE_BLOCK) sRs[l] = (uint32_t)lrow[l];
-    int32_t r = c->round;
-    u64 k = gs[0].k, mu_alive = gs[0].mu_alive;
-    int64_t n_alive = gs[0].n_alive;
-    int32_t nlevels = gs[0].nlevels;
-    const int64_t lv_base = gs[0].lv_base;
-    bool open = gs[0].sel != 0;
-    int par = 0;
+    int32_t r, nlevels;
+    u64 k, mu_alive;
+    int64_t n_alive;
+    bool open;
     uint32_t destroyed = 0;   // this thread's share of the current round (summed at the next round's start;
                               // a round destroys at most mu_alive < 2^32 cliques)
+    if (!resume) {
+        for (int l = t; l < TE_MAX; l += TE_BLOCK) {
+            sDeg[l] = l < A ? (uint32_t)b.deg[glob[l]] : 0u;
+            sSt[l] = l < A ? TE_ALIVE : TE_DEAD;
+        }
+        r = c->round;
+        k = gs[0].k;
+        mu_alive = gs[0].mu_alive;
+        n_alive = gs[0].n_alive;
+        nlevels = gs[0].nlevels;
+        open = gs[0].sel != 0;
+    } else {
+        for (int l = t; l < TE_MAX; l += TE_BLOCK) {
+            sDeg[l] = l < A ? ts->deg[l] : 0u;
+            sSt[l] = l < A ? ts->st[l] : TE_DEAD;
+        }
+        r = ts->r;
+        k = ts->k;
+        mu_alive = ts->mu_alive;
+        n_alive = ts->n_alive;
+        nlevels = ts->nlevels;
+        open = ts->open != 0;
+        if (t == 0) destroyed = (uint32_t)ts->destroyed;
+    }
+    for (int l = t; l <= A; l += TE_BLOCK) sRs[l] = (uint32_t)lrow[l];
+    const int64_t lv_base = gs[0].lv_base;
+    int par = 0;
     __syncthreads();
+    if (t == 0) ts->heavy = 0;
     const int l0 = t * TE_PER;
+    if (resume) {
+        // the end of the round the grid processed
+        if (open) nlevels += 1;
+        n_alive -= ts->nF;
+        r += 1;
+        open = false;
+#pragma unroll
+        for (int j = 0; j < TE_PER; j++)
+            if (sSt[l0 + j] == TE_CUR) sSt[l0 + j] = TE_DEAD;
+    }
     int64_t guard = 0;
     while (n_alive > 0) {
         if (++guard > (int64_t)A + 1) {   // every round removes at least one vertex
@@ -1825,8 +1930,9 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             for (int j = 0; j < TE_PER; j++)
                 if (st[j] == TE_ALIVE && d[j] < mn) mn = d[j];
         }
-        uint32_t mall = 0, gone = 0;
-        uint32_t at = te_reduce(R, par, __popc(mask), mn, destroyed, &nF, &mall, &gone);
+        uint32_t mall = 0, gone = 0, fpairs = 0;
+        uint32_t at = te_reduce<true>(R, par, __popc(mask), mn, destroyed, &nF, &mall, &gone,
+                                      te_front_pairs(mask, l0, sRs), &fpairs);
         destroyed = 0;
         mu_alive -= gone;
         if (nF == 0) open = true;
@@ -1836,7 +1942,8 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             te_load(sDeg, sSt, l0, d, st);   // unchanged since the reduction read them
             mask = te_mask(d, st, k);
             uint32_t u1, u2;
-            at = te_reduce(R, par, __popc(mask), 0xffffffffu, 0u, &nF, &u1, &u2);
+            at = te_reduce<true>(R, par, __popc(mask), 0xffffffffu, 0u, &nF, &u1, &u2, te_front_pairs(mask, l0, sRs),
+                                 &fpairs);
         }
         if (nF == 0) {   // cannot happen while vertices are alive
             if (t == 0) *err = 2;
@@ -1856,6 +1963,44 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             const int l = l0 + __builtin_ctz(mm);
             sSt[l] = TE_CUR;
             sDeg[l] = (uint32_t)k;
+        }
+        if (fpairs > heavy) {
+            // a heavy round goes to the grid: the frontier with its items'
+            // starts, and the whole state, to ts; then the engine stops
+            uint32_t own = 0;
+            for (uint32_t mm = mask; mm; mm &= mm - 1) {
+                const int l = l0 + __builtin_ctz(mm);
+                own += (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
+            }
+            uint32_t items = 0, u1, u2;
+            uint32_t run = te_reduce(R, par, own, 0xffffffffu, 0u, &items, &u1, &u2);   // its barrier orders the marks
+            uint32_t q = at;
+            for (uint32_t mm = mask; mm; mm &= mm - 1, q++) {
+                const int l = l0 + __builtin_ctz(mm);
+                ts->F[q] = (uint32_t)l;
+                ts->ipre[q] = run;
+                run += (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
+            }
+            for (int l = t; l < A; l += TE_BLOCK) {
+                ts->deg[l] = sDeg[l];
+                ts->st[l] = sSt[l];
+            }
+            if (t == 0) {
+                ts->ipre[nF] = items;
+                ts->nF = nF;
+                ts->items = items;
+                ts->r = r;
+                ts->k = k;
+                ts->mu_alive = mu_alive;
+                ts->n_alive = n_alive;
+                ts->nlevels = nlevels;
+                ts->open = open ? 1 : 0;
+                ts->destroyed = 0;
+                ts->pairs += fpairs;
+                ts->rounds += 1;
+                ts->heavy = 1;
+            }
+            return;
         }
         // the frontier's rows, TE_FB vertices at a time
         for (uint32_t f0 = 0; f0 < nF; f0 += TE_FB) {
@@ -1985,6 +2130,74 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         c->nsel[0] = c->nsel[1] = 0;
         c->pending = 0;
     }
+}
+
+// item -> frontier position for a grid round (one wave per frontier vertex)
+__global__ void k_te_expand(const TeState *ts) {
+    const uint32_t nF = ts->nF;
+    const int wv = threadIdx.x / WAVE;
+    for (uint32_t q = blockIdx.x * WAVES_PER_BLOCK + wv; q < nF; q += gridDim.x * WAVES_PER_BLOCK)
+        for (uint32_t i = ts->ipre[q] + lane(); i < ts->ipre[q + 1]; i += WAVE) ts->imap[i] = q;
+}
+
+// One round of the engine on every CU: a wave per item (TE_ITEM pairs of a
+// frontier vertex's row, TE_PL consecutive pairs per lane), the same owner
+// rule and losses as the engine.  Each workgroup holds the states and its own
+// loss counters in LDS and adds the counters to the degrees at its end, so
+// the degrees of the few survivors of a dense level see one atomic per
+// workgroup instead of one per pair.
+template <int H>
+__global__ __launch_bounds__(TE_HBLOCK) void k_te_heavy(TeState *ts, const int64_t *lrow, const uint32_t *lp,
+                                                         int32_t A) {
+    __shared__ uint8_t sSt[TE_MAX];          // 80 KB in all: two workgroups per CU
+    __shared__ uint32_t sLoss[TE_MAX];
+    for (int l = threadIdx.x; l < A; l += TE_HBLOCK) {
+        sSt[l] = ts->st[l];
+        sLoss[l] = 0;
+    }
+    __syncthreads();
+    const uint32_t items = ts->items;
+    const int wv = threadIdx.x / WAVE, L = lane();
+    uint32_t destroyed = 0;
+    for (uint32_t it = blockIdx.x * (TE_HBLOCK / WAVE) + wv; it < items; it += gridDim.x * (TE_HBLOCK / WAVE)) {
+        const uint32_t q = ts->imap[it];
+        const uint32_t v = ts->F[q];
+        const int64_t p0 = lrow[v] + (int64_t)(it - ts->ipre[q]) * TE_ITEM;
+        const int64_t p1 = min(lrow[v + 1], p0 + TE_ITEM);
+        const int64_t q0 = p0 + (int64_t)L * TE_PL;
+        uint32_t pv[TE_PL];
+#pragma unroll
+        for (int cq = 0; cq < TE_PL / 4; cq++) {
+            uint4 w = make_uint4(TE_NONE, TE_NONE, TE_NONE, TE_NONE);
+            if (q0 + 4 * cq < p1) w = *(const uint4 *)(lp + q0 + 4 * cq);
+            pv[4 * cq] = w.x;
+            pv[4 * cq + 1] = w.y;
+            pv[4 * cq + 2] = w.z;
+            pv[4 * cq + 3] = w.w;
+        }
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < TE_PL; j++) {
+            const bool real = pv[j] != TE_NONE;
+            const uint32_t qv = real ? pv[j] : 0u;
+            const uint32_t a = qv >> 16, x = qv & 0xffffu;
+            const uint32_t sa = sSt[a], sx = sSt[x];
+            const bool ok = real && te_allowed(sa, a, v) && te_allowed(sx, x, v);
+            destroyed += ok ? 1u : 0u;
+            if (H == 3 && ok && sx == TE_ALIVE) atomicAdd(&sLoss[x], 1u);
+            acc += (ok && sa == TE_ALIVE) ? 1u : 0u;
+            const bool last = j == TE_PL - 1 || (pv[j + (j < TE_PL - 1)] >> 16) != a;
+            if (last && acc) {
+                atomicAdd(&sLoss[a], acc);
+                acc = 0;
+            }
+        }
+    }
+    const uint32_t wd = te_wave_reduce<false>(destroyed);
+    if (L == 0 && wd) atomicAdd((unsigned long long *)&ts->destroyed, (unsigned long long)wd);
+    __syncthreads();
+    for (int l = threadIdx.x; l < A; l += TE_HBLOCK)
+        if (sLoss[l]) atomicSub(&ts->deg[l], sLoss[l]);
 }
 
 // Times every launch of one kernel: the launch carries a start and a stop
@@ -2133,32 +2346,72 @@ static bool tail_engine(const PeelBufs &b, int h, int32_t n, int64_t n_alive, hi
     }
     k_te_pad<<<gA, BLOCK, 0, s>>>(lrow, vcnt, A, lp);
     fill_i32(cnt, 0, 1, s);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (kt && kt->time_main) {
-        DSD_HIP(hipEventCreate(&e0));
-        DSD_HIP(hipEventCreate(&e1));
-        DSD_HIP(hipEventRecord(e0, s));
-    }
-    if (h == 3) k_tail_engine<3><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
-    else k_tail_engine<2><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt);
-    DSD_HIP(hipGetLastError());
-    if (e1) DSD_HIP(hipEventRecord(e1, s));
-    int32_t err = 0;
-    DSD_HIP(hipMemcpyAsync(&err, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    DSD_HIP(hipStreamSynchronize(s));
-    if (kt) {
-        if (e1) {
+    // the state for grid rounds
+    TeState *ts = sc.get_n<TeState>(1);
+    TeState hts{};
+    hts.deg = sc.get_n<uint32_t>(A);
+    hts.st = sc.get_n<uint8_t>(A);
+    hts.F = sc.get_n<uint32_t>(A);
+    hts.ipre = sc.get_n<uint32_t>(A + 1);
+    hts.imap = sc.get_n<uint32_t>(total / TE_ITEM + A + 1);   // items of one round: sum of ceil(row / TE_ITEM)
+    DSD_HIP(hipMemcpyAsync(ts, &hts, sizeof(TeState), hipMemcpyHostToDevice, s));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (kt && kt->time_main)
+        for (auto &e : ev) DSD_HIP(hipEventCreate(&e));
+    double engine_ms = 0, grid_ms = 0;
+    u64 launches = 0;
+    int resume = 0;
+    uint32_t heavy = TE_HEAVY;
+    if (const char *hp = std::getenv("DSD_TE_GRID_PAIRS")) heavy = (uint32_t)std::strtoul(hp, nullptr, 10);
+    while (true) {
+        if (ev[0]) DSD_HIP(hipEventRecord(ev[0], s));
+        if (h == 3) k_tail_engine<3><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt, ts, resume, heavy);
+        else k_tail_engine<2><<<1, TE_BLOCK, 0, s>>>(b, glob, lrow, lp, A, cnt, ts, resume, heavy);
+        DSD_HIP(hipGetLastError());
+        if (ev[1]) DSD_HIP(hipEventRecord(ev[1], s));
+        launches += 1;
+        int32_t err = 0;
+        DSD_HIP(hipMemcpyAsync(&hts, ts, sizeof(TeState), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipMemcpyAsync(&err, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DSD_HIP(hipStreamSynchronize(s));
+        if (ev[0]) {
             float ms = 0;
-            DSD_HIP(hipEventElapsedTime(&ms, e0, e1));
-            kt->tail_ms += ms;
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+            DSD_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            engine_ms += ms;
         }
-        kt->tail_launches += 1;
-        kt->tail_pairs += walked;
-        kt->tail_vertices += (u64)A;
+        if (err) {
+            for (auto &e : ev)
+                if (e) (void)hipEventDestroy(e);
+            throw Error(-3, "tail engine: a round removed no vertex");
+        }
+        if (!hts.heavy) break;
+        // the round the engine stopped at, on every CU; then the engine resumes
+        if (ev[2]) DSD_HIP(hipEventRecord(ev[2], s));
+        k_te_expand<<<grid_for(hts.nF, WAVES_PER_BLOCK, 1024), BLOCK, 0, s>>>(ts);
+        const int gh = (int)std::min<u64>(512, ((u64)hts.items + TE_HBLOCK / WAVE - 1) / (TE_HBLOCK / WAVE));
+        if (h == 3) k_te_heavy<3><<<gh, TE_HBLOCK, 0, s>>>(ts, lrow, lp, A);
+        else k_te_heavy<2><<<gh, TE_HBLOCK, 0, s>>>(ts, lrow, lp, A);
+        DSD_HIP(hipGetLastError());
+        if (ev[3]) {
+            DSD_HIP(hipEventRecord(ev[3], s));
+            DSD_HIP(hipEventSynchronize(ev[3]));
+            float ms = 0;
+            DSD_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+            grid_ms += ms;
+        }
+        resume = 1;
     }
-    if (err) throw Error(-3, "tail engine: a round removed no vertex");
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (kt) {
+        kt->tail_ms += engine_ms;
+        kt->tail_launches += launches;
+        kt->tail_pairs += walked - hts.pairs;
+        kt->tail_vertices += (u64)A;
+        kt->tail_grid_ms += grid_ms;
+        kt->tail_grid_rounds += hts.rounds;
+        kt->tail_grid_pairs += hts.pairs;
+    }
     return true;
 }
 

@@ -63,7 +63,8 @@ class Stats(C.Structure):
                 ("flow_gpu_calls", C.c_uint64), ("k4_main_kind", C.c_uint64),
                 ("t_flow_setup_ms", C.c_double), ("flow_gpu_networks", C.c_uint64),
                 ("k4_tail_ms", C.c_double), ("k4_tail_launches", C.c_uint64), ("k4_tail_pairs", C.c_uint64),
-                ("k4_tail_vertices", C.c_uint64)]
+                ("k4_tail_vertices", C.c_uint64), ("k4_tail_grid_ms", C.c_double),
+                ("k4_tail_grid_rounds", C.c_uint64), ("k4_tail_grid_pairs", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

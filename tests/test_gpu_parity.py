@@ -297,7 +297,10 @@ def test_tail_engine_matches_round_kernels(monkeypatch, case, h):
     # the single-workgroup tail engine (the last alive vertices of an h = 3
     # peel over triangle lists, or of an h = 2 peel over the adjacency)
     # against the per-round kernels: the same core numbers, rounds, levels,
-    # and the same exact answer from the level table
+    # and the same exact answer from the level table; the third run hands
+    # every round with a pair to the grid kernel (the engine stops and
+    # resumes around each), the default hands over rounds of more than 2^18
+    # pairs (the multipartite graph's last level)
     if case == "chung_lu":
         n, s, d = synth.chung_lu(n=60000, avg_deg=14, beta=2.1, planted=2, plant_size=80, p=0.6, seed=5)
     elif case == "er_planted":
@@ -308,17 +311,28 @@ def test_tail_engine_matches_round_kernels(monkeypatch, case, h):
         n, s, d, _ = synth.complete_multipartite([30, 40, 50, 60, 70], seed=4)
     s = np.ascontiguousarray(s, np.int32)
     d = np.ascontiguousarray(d, np.int32)
-    res = {}
-    for flag in ("0", "1"):
+    res, grid = {}, {}
+    for mode, flag, heavy in (("rounds", "0", None), ("engine", "1", None), ("grid", "1", "0")):
         monkeypatch.setenv("DSD_TAIL_ENGINE", flag)
+        if heavy is None:
+            monkeypatch.delenv("DSD_TE_GRID_PAIRS", raising=False)
+        else:
+            monkeypatch.setenv("DSD_TE_GRID_PAIRS", heavy)
         g = dsd.build_csr(n, s, d)
         core, km = dsd.clique_core(g, h)
         st = g.stats()
+        grid[mode] = (st["k4_tail_launches"], st["k4_tail_grid_rounds"])
         mem, rho = dsd.core_exact(g, h)
         _, km_app, dens_app = dsd.core_app(g, h)
-        res[flag] = (core, km, st["peel_rounds"], st["peel_levels"], rho, km_app, dens_app)
-    np.testing.assert_array_equal(res["0"][0], res["1"][0])
-    assert res["0"][1:] == res["1"][1:]
+        res[mode] = (core, km, st["peel_rounds"], st["peel_levels"], rho, km_app, dens_app)
+    for mode in ("engine", "grid"):
+        np.testing.assert_array_equal(res["rounds"][0], res[mode][0])
+        assert res["rounds"][1:] == res[mode][1:]
+    assert grid["rounds"] == (0, 0)
+    launches, rounds = grid["grid"]
+    assert launches == rounds + 1 and rounds > 0
+    if case == "multipartite" and h == 3:
+        assert grid["engine"][1] > 0
 
 
 def test_h2_large_rounds_match_oracle():
