@@ -1780,25 +1780,20 @@ struct TeRed {
     uint32_t cnt[2][TE_WAVES];
     uint32_t mn[2][TE_WAVES];
     uint32_t sum[2][TE_WAVES];
-    uint32_t sum2[2][TE_WAVES];
 };
 
-// exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall),
-// sum of s (*sall) and, with S2, sum of s2 (*s2all) over the workgroup;
-// every thread calls it with the same par
-template <bool S2 = false>
+// exclusive prefix (return) and total (*ctot) of c, minimum of m (*mall) and
+// sum of s (*sall) over the workgroup; every thread calls it with the same par
 __device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, uint32_t m, uint32_t s, uint32_t *ctot,
-                                              uint32_t *mall, uint32_t *sall, uint32_t s2 = 0, uint32_t *s2all = nullptr) {
+                                              uint32_t *mall, uint32_t *sall) {
     const int wv = threadIdx.x / WAVE, L = lane();
     uint32_t wtot = 0;
     const uint32_t pre = te_wave_prefix(c, &wtot);
     const uint32_t wmin = te_wave_reduce<true>(m), wsum = te_wave_reduce<false>(s);
-    const uint32_t wsum2 = S2 ? te_wave_reduce<false>(s2) : 0u;
     if (L == 0) {
         R.cnt[par][wv] = wtot;
         R.mn[par][wv] = wmin;
         R.sum[par][wv] = wsum;
-        if (S2) R.sum2[par][wv] = wsum2;
     }
     te_sync();
     const uint32_t ci = L < TE_WAVES ? R.cnt[par][L] : 0u;
@@ -1808,7 +1803,6 @@ __device__ __forceinline__ uint32_t te_reduce(TeRed &R, int &par, uint32_t c, ui
     *ctot = te_wave_reduce<false>(ci);
     *mall = te_wave_reduce<true>(mi);
     *sall = te_wave_reduce<false>(si);
-    if (S2) *s2all = te_wave_reduce<false>(L < TE_WAVES ? R.sum2[par][L] : 0u);
     par ^= 1;
     return before + pre;
 }
@@ -1838,14 +1832,95 @@ __device__ __forceinline__ uint32_t te_mask(const uint32_t *d, const uint32_t *s
     return mask;
 }
 
-// pairs in the rows of this thread's frontier ids
-__device__ __forceinline__ uint32_t te_front_pairs(uint32_t mask, int l0, const uint32_t *sRs) {
-    uint32_t p = 0;
+// pairs and items (TE_ITEM pairs each) in the rows of this thread's ids in mask
+__device__ __forceinline__ void te_front_work(uint32_t mask, int l0, const uint32_t *sRs, uint32_t *pairs,
+                                              uint32_t *items) {
+    uint32_t p = 0, it = 0;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         const int l = l0 + __builtin_ctz(mm);
-        p += sRs[l + 1] - sRs[l];
+        const uint32_t len = sRs[l + 1] - sRs[l];
+        p += len;
+        it += (len + TE_ITEM - 1) / TE_ITEM;
     }
-    return p;
+    *pairs = p;
+    *items = it;
+}
+
+// A round's frontier from one exchange between the waves.  Each wave offers
+// two candidates: its alive ids of degree <= k, and its alive ids at the
+// wave's smallest degree; with their counts, item counts and pairs, and the
+// previous round's destroyed cliques.  Once the exchange is read, either some
+// ids are at degree <= k (the level goes on with them) or none is, and the
+// new level opens at the smallest alive degree with the ids of the waves
+// whose own minimum it is.  The frontier position (at) and first item (iat)
+// of this thread's ids are exclusive prefixes in id order.
+struct TeSel {
+    uint32_t v[2][8][TE_WAVES];   // [parity][field][wave]
+};
+constexpr int TS_CK = 0, TS_CM = 1, TS_MIN = 2, TS_DEST = 3, TS_PK = 4, TS_PM = 5, TS_IK = 6, TS_IM = 7;
+struct TeRound {
+    uint32_t mask, nF, at, iat, items, fpairs, gone, gmin;
+    bool fresh;   // a new level at gmin
+};
+__device__ __forceinline__ TeRound te_select(TeSel &S, int &par, const uint32_t *d, const uint32_t *st, u64 k, int l0,
+                                             const uint32_t *sRs, uint32_t destroyed) {
+    const int wv = threadIdx.x / WAVE, L = lane();
+    const uint32_t mk = te_mask(d, st, k);
+    uint32_t mn = 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < TE_PER; j++)
+        if (st[j] == TE_ALIVE && d[j] < mn) mn = d[j];
+    const uint32_t wmin = te_wave_reduce<true>(mn);
+    uint32_t mm = 0;
+#pragma unroll
+    for (int j = 0; j < TE_PER; j++) mm |= (st[j] == TE_ALIVE && d[j] == wmin) ? 1u << j : 0u;
+    uint32_t pk, ik, pm, im;
+    te_front_work(mk, l0, sRs, &pk, &ik);
+    te_front_work(mm, l0, sRs, &pm, &im);
+    uint32_t ckw, cmw, ikw, imw;
+    const uint32_t prek = te_wave_prefix(__popc(mk), &ckw), prem = te_wave_prefix(__popc(mm), &cmw);
+    const uint32_t preik = te_wave_prefix(ik, &ikw), preim = te_wave_prefix(im, &imw);
+    const uint32_t dw = te_wave_reduce<false>(destroyed), pkw = te_wave_reduce<false>(pk),
+                   pmw = te_wave_reduce<false>(pm);
+    if (L == 0) {
+        S.v[par][TS_CK][wv] = ckw;
+        S.v[par][TS_CM][wv] = cmw;
+        S.v[par][TS_MIN][wv] = wmin;
+        S.v[par][TS_DEST][wv] = dw;
+        S.v[par][TS_PK][wv] = pkw;
+        S.v[par][TS_PM][wv] = pmw;
+        S.v[par][TS_IK][wv] = ikw;
+        S.v[par][TS_IM][wv] = imw;
+    }
+    te_sync();
+    const bool in = L < TE_WAVES;
+    const uint32_t ck = in ? S.v[par][TS_CK][L] : 0u, wm = in ? S.v[par][TS_MIN][L] : 0xffffffffu;
+    TeRound o;
+    o.gone = te_wave_reduce<false>(in ? S.v[par][TS_DEST][L] : 0u);
+    o.gmin = te_wave_reduce<true>(wm);
+    const uint32_t nfk = te_wave_reduce<false>(ck);
+    if (nfk > 0) {
+        const uint32_t ic = in ? S.v[par][TS_IK][L] : 0u;
+        o.fresh = false;
+        o.mask = mk;
+        o.nF = nfk;
+        o.at = prek + te_wave_reduce<false>(L < wv ? ck : 0u);
+        o.iat = preik + te_wave_reduce<false>(L < wv ? ic : 0u);
+        o.items = te_wave_reduce<false>(ic);
+        o.fpairs = te_wave_reduce<false>(in ? S.v[par][TS_PK][L] : 0u);
+    } else {
+        const bool eq = in && wm == o.gmin;
+        const uint32_t cm = eq ? S.v[par][TS_CM][L] : 0u, ic = eq ? S.v[par][TS_IM][L] : 0u;
+        o.fresh = true;
+        o.mask = wmin == o.gmin ? mm : 0u;
+        o.nF = te_wave_reduce<false>(cm);
+        o.at = prem + te_wave_reduce<false>(L < wv ? cm : 0u);
+        o.iat = preim + te_wave_reduce<false>(L < wv ? ic : 0u);
+        o.items = te_wave_reduce<false>(ic);
+        o.fpairs = te_wave_reduce<false>(eq ? S.v[par][TS_PM][L] : 0u);
+    }
+    par ^= 1;
+    return o;
 }
 
 // lrow (A + 1 entries) below 2^32: the row starts live in LDS.  H = 2: a
@@ -1863,6 +1938,7 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
     __shared__ uint16_t sF[TE_FB];
     __shared__ uint32_t sIpre[TE_FB];
     __shared__ TeRed R;
+    __shared__ TeSel S;
     PeelCtl *c = b.ctl;
     GraphState *gs = b.gs;
     const int t = threadIdx.x, wv = t / WAVE, L = lane();
@@ -1898,7 +1974,7 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
     }
     for (int l = t; l <= A; l += TE_BLOCK) sRs[l] = (uint32_t)lrow[l];
     const int64_t lv_base = gs[0].lv_base;
-    int par = 0;
+    int par = 0, spar = 0;
     __syncthreads();
     if (t == 0) ts->heavy = 0;
     const int l0 = t * TE_PER;
@@ -1921,30 +1997,19 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         // the frontier: alive vertices of degree <= k; none left means a new
         // level at the smallest alive degree.  The same reduction ends the
         // previous round (its destroyed cliques).
-        uint32_t mask = 0, nF = 0, mn = 0xffffffffu;
+        TeRound rd;
         {
             uint32_t d[TE_PER], st[TE_PER];
             te_load(sDeg, sSt, l0, d, st);
-            mask = te_mask(d, st, k);
-#pragma unroll
-            for (int j = 0; j < TE_PER; j++)
-                if (st[j] == TE_ALIVE && d[j] < mn) mn = d[j];
+            rd = te_select(S, spar, d, st, k, l0, sRs, destroyed);
         }
-        uint32_t mall = 0, gone = 0, fpairs = 0;
-        uint32_t at = te_reduce<true>(R, par, __popc(mask), mn, destroyed, &nF, &mall, &gone,
-                                      te_front_pairs(mask, l0, sRs), &fpairs);
         destroyed = 0;
-        mu_alive -= gone;
-        if (nF == 0) open = true;
-        if (open) {
-            k = k > (u64)mall ? k : (u64)mall;
-            uint32_t d[TE_PER], st[TE_PER];
-            te_load(sDeg, sSt, l0, d, st);   // unchanged since the reduction read them
-            mask = te_mask(d, st, k);
-            uint32_t u1, u2;
-            at = te_reduce<true>(R, par, __popc(mask), 0xffffffffu, 0u, &nF, &u1, &u2, te_front_pairs(mask, l0, sRs),
-                                 &fpairs);
+        mu_alive -= rd.gone;
+        if (rd.fresh) {
+            open = true;
+            k = k > (u64)rd.gmin ? k : (u64)rd.gmin;
         }
+        const uint32_t mask = rd.mask, nF = rd.nF, at = rd.at, fpairs = rd.fpairs;
         if (nF == 0) {   // cannot happen while vertices are alive
             if (t == 0) *err = 2;
             break;
@@ -1967,13 +2032,9 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
         if (fpairs > heavy) {
             // a heavy round goes to the grid: the frontier with its items'
             // starts, and the whole state, to ts; then the engine stops
-            uint32_t own = 0;
-            for (uint32_t mm = mask; mm; mm &= mm - 1) {
-                const int l = l0 + __builtin_ctz(mm);
-                own += (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
-            }
-            uint32_t items = 0, u1, u2;
-            uint32_t run = te_reduce(R, par, own, 0xffffffffu, 0u, &items, &u1, &u2);   // its barrier orders the marks
+            const uint32_t items = rd.items;
+            uint32_t run = rd.iat;
+            te_sync();   // orders the frontier marks before the state is copied
             uint32_t q = at;
             for (uint32_t mm = mask; mm; mm &= mm - 1, q++) {
                 const int l = l0 + __builtin_ctz(mm);
@@ -2002,34 +2063,9 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
             }
             return;
         }
-        // the frontier's rows, TE_FB vertices at a time
-        for (uint32_t f0 = 0; f0 < nF; f0 += TE_FB) {
-            const int nb = (int)min((uint32_t)TE_FB, nF - f0);
-            uint32_t q = at;
-            for (uint32_t mm = mask; mm; mm &= mm - 1, q++)
-                if (q >= f0 && q < f0 + TE_FB) sF[q - f0] = (uint16_t)(l0 + __builtin_ctz(mm));
-            te_sync();
-            constexpr int PT = TE_FB / TE_BLOCK;
-            uint32_t cnt[PT], own = 0;
-#pragma unroll
-            for (int j = 0; j < PT; j++) {
-                const int qq = t * PT + j;
-                cnt[j] = 0;
-                if (qq < nb) {
-                    const uint32_t l = sF[qq];
-                    cnt[j] = (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
-                }
-                own += cnt[j];
-            }
-            uint32_t items = 0, u1, u2;
-            uint32_t run = te_reduce(R, par, own, 0xffffffffu, 0u, &items, &u1, &u2);
-#pragma unroll
-            for (int j = 0; j < PT; j++) {
-                const int qq = t * PT + j;
-                if (qq < nb) sIpre[qq] = run;
-                run += cnt[j];
-            }
-            te_sync();
+        // the frontier's rows: the nb vertices listed in sF, their items'
+        // starts in sIpre
+        auto run_items = [&](int nb, uint32_t items) {
             // each wave takes items wv, wv + TE_WAVES, ...; the next one's
             // pairs are loaded while the current one is processed
             auto locate = [&](uint32_t it, uint32_t *v, uint32_t *p0, uint32_t *p1) {
@@ -2099,6 +2135,49 @@ __global__ __launch_bounds__(TE_BLOCK) void k_tail_engine(PeelBufs b, const int3
                 for (int j = 0; j < TE_PL; j++) pv[j] = pn[j];
             }
             te_sync();   // the next batch rewrites sF and sIpre; the next round reads the degrees
+        };
+        if (nF <= TE_FB) {
+            // one batch: the list and the item starts come from the selection
+            uint32_t q = at, ip = rd.iat;
+            for (uint32_t mm = mask; mm; mm &= mm - 1, q++) {
+                const int l = l0 + __builtin_ctz(mm);
+                sF[q] = (uint16_t)l;
+                sIpre[q] = ip;
+                ip += (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
+            }
+            te_sync();
+            run_items((int)nF, rd.items);
+        } else {
+            // TE_FB vertices at a time
+            for (uint32_t f0 = 0; f0 < nF; f0 += TE_FB) {
+                const int nb = (int)min((uint32_t)TE_FB, nF - f0);
+                uint32_t q = at;
+                for (uint32_t mm = mask; mm; mm &= mm - 1, q++)
+                    if (q >= f0 && q < f0 + TE_FB) sF[q - f0] = (uint16_t)(l0 + __builtin_ctz(mm));
+                te_sync();
+                constexpr int PT = TE_FB / TE_BLOCK;
+                uint32_t cnt[PT], own = 0;
+#pragma unroll
+                for (int j = 0; j < PT; j++) {
+                    const int qq = t * PT + j;
+                    cnt[j] = 0;
+                    if (qq < nb) {
+                        const uint32_t l = sF[qq];
+                        cnt[j] = (sRs[l + 1] - sRs[l] + TE_ITEM - 1) / TE_ITEM;
+                    }
+                    own += cnt[j];
+                }
+                uint32_t items = 0, u1, u2;
+                uint32_t run = te_reduce(R, par, own, 0xffffffffu, 0u, &items, &u1, &u2);
+#pragma unroll
+                for (int j = 0; j < PT; j++) {
+                    const int qq = t * PT + j;
+                    if (qq < nb) sIpre[qq] = run;
+                    run += cnt[j];
+                }
+                te_sync();
+                run_items(nb, items);
+            }
         }
         // end of the round; each thread retires its own frontier entries (the
         // next round's reduction orders this before any other thread's reads)
