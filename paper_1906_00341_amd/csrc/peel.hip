@@ -227,44 +227,33 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
     for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
 }
 
-// Row items of the round's frontier (triangle lists): waves wave0, wave0 +
-// nwaves, ... each take a frontier vertex and write its items together.  A
-// hub's row holds thousands of items, too many for one lane.
-// Every lane of a wave takes one frontier vertex; one scan over the lanes and
-// one atomic give the 64 vertices their ranges of items, which the wave
-// then writes vertex by vertex.
-__device__ __forceinline__ void tl_items(const PeelBufs &b, int64_t wave0, int64_t nwaves) {
-    const int32_t cur = b.ctl->cur, nF = b.ctl->nF[cur];
-    const int32_t *F = b.F + (size_t)cur * b.n;
-    int64_t *Tc = b.T + (size_t)cur * b.tcap;
-    for (int64_t i0 = wave0 * WAVE; i0 < nF; i0 += nwaves * WAVE) {
-        const int64_t i = i0 + lane();
-        int32_t v = 0, nc = 0;
-        if (i < nF) {
-            v = F[i];
-            const int64_t len = b.tvoff[v + 1] - b.tvoff[v];
-            nc = (int32_t)((len + TL_CHUNK - 1) / TL_CHUNK);
-        }
-        const int32_t inc = wave_incl_scan(nc);
-        const int32_t tot = __shfl(inc, WAVE - 1, WAVE);
-        if (tot == 0) continue;
-        int32_t base = 0;
-        if (lane() == 0) base = atomicAdd(&b.ctl->nT[cur], tot);
-        base = __shfl(base, 0, WAVE) + inc - nc;
-        for (int j = 0; j < WAVE; j++) {
-            const int32_t vj = __shfl(v, j, WAVE), ncj = __shfl(nc, j, WAVE), bj = __shfl(base, j, WAVE);
-            for (int32_t c = lane(); c < ncj; c += WAVE) Tc[bj + c] = ((int64_t)vj << 32) | c;
-        }
+// Row items (triangle lists) of the vertices that join frontier `which`
+// (pred), written where they join it: TL_CHUNK pairs of a row each, since a
+// hub's row holds thousands of them.  The whole wave calls this; one scan
+// over the lanes and one atomic give the joining vertices their ranges of
+// items, which the wave then writes vertex by vertex.
+__device__ __forceinline__ void wave_push_items(const PeelBufs &b, bool pred, int32_t v, int which) {
+    const u64 m = __ballot(pred);
+    if (!m) return;
+    int32_t nc = 0;
+    if (pred) nc = (int32_t)((b.tvoff[v + 1] - b.tvoff[v] + TL_CHUNK - 1) / TL_CHUNK);
+    const int32_t inc = wave_incl_scan(nc);
+    const int32_t tot = __shfl(inc, WAVE - 1, WAVE);
+    if (tot == 0) return;
+    int32_t base = 0;
+    if (lane() == 0) base = atomicAdd(&b.ctl->nT[which], tot);
+    base = __shfl(base, 0, WAVE) + inc - nc;
+    int64_t *Tw = b.T + (size_t)which * b.tcap;
+    for (u64 mm = m; mm; mm &= mm - 1) {
+        const int j = __builtin_ctzll(mm);
+        const int32_t vj = __shfl(v, j, WAVE), ncj = __shfl(nc, j, WAVE), bj = __shfl(base, j, WAVE);
+        for (int32_t c = lane(); c < ncj; c += WAVE) Tw[bj + c] = ((int64_t)vj << 32) | c;
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_tl_items(PeelBufs b) {
-    tl_items(b, (int64_t)blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE, (int64_t)gridDim.x * WAVES_PER_BLOCK);
-}
-
 // a frontier vertex's work items for the round's process kernels (with
-// triangle lists they are written for the whole frontier at once, by
-// tl_items, before the process kernel)
+// triangle lists they are written by wave_push_items where the vertex joins
+// the frontier)
 __device__ __forceinline__ void push_work(const PeelBufs &b, int32_t x, int which) {
     if (!b.tpairs) push_chunks(b, x, which);
 }
@@ -313,6 +302,10 @@ __device__ __forceinline__ void dec_deg2(const PeelBufs &b, int32_t x1, u64 c1, 
     wave_add_by_graph<int32_t>(cr1 ? g1 : -1, &b.gs[0].nF[nx], GS_STRIDE);
     wave_push(cr2, x2, b.F + (size_t)nx * b.n, &b.ctl->nF[nx]);
     wave_add_by_graph<int32_t>(cr2 ? g2 : -1, &b.gs[0].nF[nx], GS_STRIDE);
+    if (b.tpairs) {
+        wave_push_items(b, cr1, x1, nx);
+        wave_push_items(b, cr2, x2, nx);
+    }
     if (cr1) {
         b.stamp[x1] = r + 1;
         b.core[x1] = k1;
@@ -468,6 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_build(PeelBufs b) {
         }
         wave_push(take, v, F, &c->nF[cur]);
         wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
+        if (b.tpairs) wave_push_items(b, take, v, cur);
         if (compact) block_push(alive && !take, v, out, &c->nlist[lc ^ 1]);
     }
 }
@@ -630,6 +624,7 @@ __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
             const bool take = rv[j] >= 0 && tail_take(b, rv[j], rs[j], rd[j], r, cur, &g);
             wave_push(take, rv[j], F, &c->nF[cur]);
             wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
+            if (b.tpairs) wave_push_items(b, take, rv[j], cur);
             if (compact) wave_push(rs[j] == ALIVE && !take, rv[j], out, &c->nlist[lc ^ 1]);
         }
         for (int32_t base = TAIL_REG * TAIL_BLOCK; base < cnt; base += TAIL_BLOCK) {
@@ -643,11 +638,10 @@ __global__ __launch_bounds__(TAIL_BLOCK) void k_tail_level(PeelBufs b) {
             }
             wave_push(take, v, F, &c->nF[cur]);
             wave_add_by_graph<int32_t>(take ? g : -1, &b.gs[0].nF[cur], GS_STRIDE);
+            if (b.tpairs) wave_push_items(b, take, v, cur);
             if (compact) wave_push(st == ALIVE && !take, v, out, &c->nlist[lc ^ 1]);
         }
     }
-    __syncthreads();
-    if (b.tpairs) tl_items(b, threadIdx.x / WAVE, TAIL_WAVES);
     if (threadIdx.x == 0) c->pending = 1;
 }
 
@@ -2626,7 +2620,6 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             } else {
                 k_level_min<<<gmin, BLOCK, 0, s>>>(b);
                 k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
-                if (listed) k_tl_items<<<gbuild, BLOCK, 0, s>>>(b);
             }
             if (b.pattern == 1) {
                 main_timer.launch(k_star_front, dim3(gq), dim3(BLOCK), s, b);
