@@ -65,6 +65,14 @@ struct FlowBufs {
     int *active;   // active node count
     int *act_s, *act_b;   // this pass's active nodes (up to / more than BIG_ARCS arcs)
     int *nact;            // [2] their numbers
+    // A big node whose push scan saw every arc with excess left over (so it
+    // saturated every admissible arc) records the lowest height behind the
+    // arcs still residual after its pushes (rlm, with the pass in rlp); the
+    // only residual arcs it did not see are those that nodes pushing into it
+    // opened, whose heights are its own plus one (pin: the last pass that
+    // pushed into the node).  Its relabel then needs no second scan.
+    int *rlp, *rlm, *pin;
+    int pass;
 };
 
 // residual CSR from the arc list: degrees, then every arc and its reverse
@@ -470,6 +478,7 @@ __global__ __launch_bounds__(BLOCK) void k_flow_push(FlowBufs b) {
                 b.cf[a] -= d;
                 b.cf[b.rev[a]] += d;
                 atomicAdd((unsigned long long *)&b.ex[v], (unsigned long long)d);
+                b.pin[v] = b.pass;
             }
             const int64_t total = __shfl(inc, WAVE - 1, WAVE);
             rem -= total < rem ? total : rem;
@@ -529,6 +538,7 @@ __device__ __forceinline__ int64_t block_scan_sat(int64_t c, int64_t *sW, int64_
 __global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
     constexpr int K = 4;   // arcs per thread per step: their loads go out together
     __shared__ int64_t sW[BIG_WAVES];
+    __shared__ int sMn[BIG_WAVES];
     __shared__ int64_t sEx;
     __shared__ int sHt;
     const int na = b.nact[1];
@@ -548,23 +558,34 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
         if (rem <= 0 || hu >= b.n) continue;
         const int64_t start = rem;
         const int end = b.first[u + 1];
+        int hmin = 0x7fffffff;   // heights behind this thread's arcs still residual after the pushes
         for (int a0 = b.first[u]; a0 < end && rem > 0; a0 += BIG_BLOCK * K) {
-            int64_t c[K];
-            int v[K];
+            int64_t c[K], r[K];
+            int v[K], hv[K];
             int64_t own = 0;
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 const int a = a0 + k * BIG_BLOCK + threadIdx.x;
                 c[k] = 0;
+                r[k] = 0;
                 v[k] = -1;
+                hv[k] = 0x7fffffff;
                 if (a < end) {
                     v[k] = b.to[a];
-                    const int64_t r = b.cf[a];
-                    if (r > 0 && b.ht[v[k]] == hu - 1) c[k] = r < rem ? r : rem;
+                    r[k] = b.cf[a];
+                    if (r[k] > 0) {
+                        hv[k] = b.ht[v[k]];
+                        if (hv[k] == hu - 1) c[k] = r[k] < rem ? r[k] : rem;
+                    }
                 }
                 own = (own > SAT - c[k]) ? SAT : own + c[k];
             }
-            if (!__syncthreads_or(own > 0)) continue;   // no admissible arc in this step
+            if (!__syncthreads_or(own > 0)) {   // no admissible arc in this step
+#pragma unroll
+                for (int k = 0; k < K; k++)
+                    if (r[k] > 0 && hv[k] < hmin) hmin = hv[k];
+                continue;
+            }
             int64_t total;
             const int64_t inc = block_scan_sat(own, sW, &total);
             int64_t before = inc - own;
@@ -577,13 +598,26 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_push_big(FlowBufs b) {
                     b.cf[a] -= d;
                     b.cf[b.rev[a]] += d;
                     atomicAdd((unsigned long long *)&b.ex[v[k]], (unsigned long long)d);
+                    b.pin[v[k]] = b.pass;
                 }
+                if (r[k] - d > 0 && hv[k] < hmin) hmin = hv[k];
                 before = (before > SAT - c[k]) ? SAT : before + c[k];
             }
             rem -= total < rem ? total : rem;
         }
         if (threadIdx.x == 0 && rem != start)
             atomicAdd((unsigned long long *)&b.ex[u], (unsigned long long)(rem - start));
+        if (rem > 0) {   // (the same for every thread) every arc seen, every admissible one saturated
+            hmin = wave_min_i32(hmin);
+            if (lane() == 0) sMn[threadIdx.x / WAVE] = hmin;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int m = 0x7fffffff;
+                for (int w = 0; w < BIG_WAVES; w++) m = sMn[w] < m ? sMn[w] : m;
+                b.rlm[u] = m;
+                b.rlp[u] = b.pass;
+            }
+        }
     }
 }
 
@@ -594,7 +628,7 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_relabel_big(FlowBufs b) {
     __shared__ int sAdm;
     int act = 0;
     __shared__ int64_t sEx;
-    __shared__ int sHt;
+    __shared__ int sHt, sFast, sPin;
     const int na = b.nact[1];
     for (int i = blockIdx.x; i < na; i += gridDim.x) {
         const int u = b.act_b[i];
@@ -603,12 +637,31 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_flow_relabel_big(FlowBufs b) {
             sHt = b.ht[u];
             sEx = b.ex[u];
             sAdm = 0;
+            sFast = b.rlp[u] == b.pass ? 1 : 0;
+            sPin = b.pin[u] == b.pass ? 1 : 0;
         }
         __syncthreads();
         const int hu = sHt;
         const int64_t eu = sEx;
+        const bool fast = sFast != 0, pin = sPin != 0;
         __syncthreads();
         if (eu <= 0 || hu >= b.n) continue;
+        if (fast) {
+            // the push scan saw every arc: the lowest residual neighbour is
+            // the one it recorded, or one that pushed into the node
+            if (threadIdx.x == 0) {
+                int m = b.rlm[u];
+                if (pin && hu + 1 < m) m = hu + 1;
+                if (m >= hu) {
+                    const int nh = m >= b.n - 1 ? b.n : m + 1;
+                    b.ht[u] = nh;
+                    if (nh < b.n) act++;
+                } else {
+                    act++;
+                }
+            }
+            continue;
+        }
         int hmin = 0x7fffffff;
         constexpr int K = 4;   // arcs per thread per step: their loads go out together
         const int end = b.first[u + 1];
@@ -834,6 +887,9 @@ void GpuFlow::Impl::residual(int n) {
     b.act_s = I.sc.get_n<int>(n);
     b.act_b = I.sc.get_n<int>(n);
     b.nact = I.sc.get_n<int>(2);
+    b.rlp = I.sc.get_n<int>(n);
+    b.rlm = I.sc.get_n<int>(n);
+    b.pin = I.sc.get_n<int>(n);
     // nodes with more than BIG_ARCS residual arcs
     std::vector<int> hfirst(n + 1);
     DSD_HIP(hipMemcpyAsync(hfirst.data(), first, (size_t)(n + 1) * sizeof(int), hipMemcpyDeviceToHost, I.s));
@@ -883,6 +939,8 @@ int64_t GpuFlow::maxflow(const FlowTest &test, std::vector<char> &reach_t, int64
     b.t = t;
     k_flow_caps<<<grid_for(I.E, BLOCK, 16384), BLOCK, 0, I.s>>>(b, I.eu, I.ev, I.cls, I.fwd, I.deg, I.E, test);
     k_flow_saturate<<<1, WAVE, 0, I.s>>>(b);
+    fill_i32(b.rlp, -1, b.n, I.s);
+    fill_i32(b.pin, -1, b.n, I.s);
     I.global_relabel();
     // a pass: list the active nodes, push, relabel; the passes' kernels
     // walk the lists with grids sized for the busy first passes
@@ -901,6 +959,7 @@ int64_t GpuFlow::maxflow(const FlowTest &test, std::vector<char> &reach_t, int64
     list_active();
     while (passes < max_passes) {
         for (int i = 0; i < 8; i++) {
+            b.pass = (int)(passes + i);
             k_flow_push<<<gpass, BLOCK, 0, I.s>>>(b);
             if (b.nbig > 0) k_flow_push_big<<<gbig, BIG_BLOCK, 0, I.s>>>(b);
             list_active();
