@@ -552,8 +552,14 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
         Timer tp(s);
         PeelResult xr = peel(G->g, 2, nullptr, d, m, 0, x, s, G->sc);
         G->stats.t_peel_ms += tp.stop();
-        u64 xsat = 0;
-        while (xsat <= (u64)n && binom_sat(xsat, h - 1) != ~0ull) xsat++;
+        // the smallest core number whose C(x, h-1) saturates 64 bits (n + 1
+        // if none up to n does); C(x, h-1) only grows with x
+        u64 xlo = 0, xsat = (u64)n + 1;
+        while (xlo < xsat) {
+            const u64 mid = xlo + (xsat - xlo) / 2;
+            if (binom_sat(mid, h - 1) == ~0ull) xsat = mid;
+            else xlo = mid + 1;
+        }
         const u64 keymax = std::min<u64>(xsat, (u64)n);
         u64 *keys = G->sc.get_n<u64>(n), *tmp = G->sc.get_n<u64>(n);
         k_gamma_keys<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(x, n, G->g.bits, keymax, keymax, h - 1, keys);
@@ -585,7 +591,12 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
             DSD_HIP(hipMemcpyAsync(&kl, mn, sizeof(u64), hipMemcpyDeviceToHost, s));
             DSD_HIP(hipStreamSynchronize(s));
             const u64 k0 = std::max(kl, kmax);
-            const u64 floor_k = k0 > 0 ? k0 - 1 : 0;
+            // G[W]'s k_max is at least its density mu(W)/|W| (its densest
+            // subgraph lies in the ceil(rho)-core, Lemma 7), so the levels
+            // below that need not be peeled one by one
+            const u64 dens_ceil = (muW + (u64)w - 1) / (u64)w;
+            const u64 kf = std::max(k0, dens_ceil);
+            const u64 floor_k = kf > 0 ? kf - 1 : 0;
             Timer tq(s);
             // (no triangle lists here: their rows hold every triangle of the whole graph, and a
             // hub's row in G[W] is mostly triangles that leave W; rewriting them for the tail

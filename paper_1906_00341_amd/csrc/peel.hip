@@ -1410,19 +1410,25 @@ __global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, int R) {
 // the tail of row v.  Vertex ids do not change.
 
 // one wave per vertex: kept neighbours, and kept out-neighbours
+// The compaction walks the alive list (alive vertices and the pending
+// frontier, which were alive when the list was last rebuilt; removed ones are
+// skipped): a masked peel of a small vertex set then costs its own rows, not
+// a pass over every vertex.  cnt and cnt_out are zero on entry.
 __global__ __launch_bounds__(BLOCK) void k_compact_count(PeelBufs b, int64_t *cnt, int32_t *cnt_out) {
-    const int32_t r = b.ctl->round;
+    const PeelCtl *pc = b.ctl;
+    const int32_t r = pc->round, lc = pc->lcur, nl = pc->nlist[lc];
+    const int32_t *lst = b.lists + (size_t)lc * b.n;
     const int wv = threadIdx.x / WAVE;
-    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < b.n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nl; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = lst[i];
+        if (b.stamp[v] < r) continue;
         int64_t c = 0;
         int32_t co = 0;
-        if (b.stamp[v] >= r) {
-            for (int64_t e = b.row_ptr[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
-                int32_t w = b.col[e];
-                bool keep = b.stamp[w] >= r;
-                c += keep ? 1 : 0;
-                co += (keep && w > (int32_t)v) ? 1 : 0;
-            }
+        for (int64_t e = b.row_ptr[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
+            int32_t w = b.col[e];
+            bool keep = b.stamp[w] >= r;
+            c += keep ? 1 : 0;
+            co += (keep && w > v) ? 1 : 0;
         }
         c = wave_sum(c);
         co = wave_sum(co);
@@ -1433,14 +1439,21 @@ __global__ __launch_bounds__(BLOCK) void k_compact_count(PeelBufs b, int64_t *cn
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_compact_fill(PeelBufs b, const int64_t *nrow, const int32_t *cnt_out,
-                                                         int32_t *ncol, int64_t *ndag) {
-    const int32_t r = b.ctl->round;
+// DAG offsets of the compacted rows (a removed vertex's row is empty)
+__global__ void k_compact_dag(const int64_t *nrow, const int32_t *cnt_out, int32_t n, int64_t *ndag) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        ndag[v] = nrow[v + 1] - cnt_out[v];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_compact_fill(PeelBufs b, const int64_t *nrow, int32_t *ncol) {
+    const PeelCtl *pc = b.ctl;
+    const int32_t r = pc->round, lc = pc->lcur, nl = pc->nlist[lc];
+    const int32_t *lst = b.lists + (size_t)lc * b.n;
     const int wv = threadIdx.x / WAVE;
-    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < b.n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
-        int64_t o = nrow[v];
-        if (lane() == 0) ndag[v] = nrow[v + 1] - cnt_out[v];
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < nl; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = lst[i];
         if (b.stamp[v] < r) continue;
+        int64_t o = nrow[v];
         const int64_t e1 = b.row_ptr[v + 1];
         for (int64_t e = b.row_ptr[v]; e < e1; e += WAVE) {
             int32_t w = -1;
@@ -1480,6 +1493,8 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
     int64_t *cnt = sc.get_n<int64_t>(n);
     int32_t *cnt_out = sc.get_n<int32_t>(n);
     int64_t *nrow = sc.get_n<int64_t>((int64_t)n + 1);
+    fill_u64((u64 *)cnt, 0, n, s);
+    fill_i32(cnt_out, 0, n, s);
     k_compact_count<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, cnt, cnt_out);
     scan_exclusive_i64(cnt, nrow, n, s, sc);
     k_last_row<<<1, 1, 0, s>>>(nrow, cnt, n);
@@ -1488,7 +1503,8 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
     DSD_HIP(hipStreamSynchronize(s));
     int32_t *ncol = sc.get_n<int32_t>(total);
     int64_t *ndag = sc.get_n<int64_t>(n);
-    k_compact_fill<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, nrow, cnt_out, ncol, ndag);
+    k_compact_dag<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(nrow, cnt_out, n, ndag);
+    k_compact_fill<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, nrow, ncol);
     b.row_ptr = nrow;
     b.col = ncol;
     b.dag_off = ndag;
