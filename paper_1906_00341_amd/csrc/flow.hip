@@ -723,6 +723,7 @@ struct GpuFlow::Impl {
     int nv = 0;
     ~Impl() {
         if (s) (void)hipStreamSynchronize(s);
+        sc.recycle();
         if (pinned) (void)hipHostFree(pinned);
         if (s) (void)hipStreamDestroy(s);
     }

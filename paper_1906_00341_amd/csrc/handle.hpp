@@ -36,9 +36,11 @@ struct dsd_graph_s {
     bool tl_tried = false;
     bool time_main = false;         // dsd_set_kernel_timing
     ~dsd_graph_s() {
+        (void)hipStreamSynchronize(stream);
         for (dsd::Decomp &d : dec) (void)hipFree(d.core);
         dsd::free_tri_list(tl);
         dsd::free_graph(g);
+        sc.recycle();   // the stream is idle: the next handle reuses the chunks
     }
 };
 

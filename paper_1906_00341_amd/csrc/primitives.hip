@@ -1,12 +1,49 @@
 // Scans, reductions and a stable LSD radix sort of 64-bit keys for gfx950.
+#include <map>
+#include <mutex>
+
 #include "primitives.hpp"
 
 namespace dsd {
 
 // ---------------------------------------------------------------- Scratch
 
+namespace {
+
+// recycled scratch chunks, by device and size
+struct ChunkPool {
+    std::mutex mu;
+    std::multimap<std::pair<int, size_t>, char *> free;
+    size_t bytes = 0;
+};
+ChunkPool &chunk_pool() {
+    static ChunkPool *p = new ChunkPool();   // never destroyed: handles may outlive static destruction
+    return *p;
+}
+constexpr size_t POOL_MAX = (size_t)16 << 30;
+
+}  // namespace
+
 Scratch::~Scratch() {
     for (auto &c : chunks_) (void)hipFree(c.first);
+}
+
+void Scratch::recycle() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    ChunkPool &P = chunk_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto &c : chunks_) {
+        if (dev >= 0 && P.bytes + c.second <= POOL_MAX) {
+            P.free.emplace(std::make_pair(dev, c.second), c.first);
+            P.bytes += c.second;
+        } else {
+            (void)hipFree(c.first);
+        }
+    }
+    chunks_.clear();
+    cur_ = 0;
+    off_ = 0;
 }
 
 size_t Scratch::capacity() const {
@@ -28,7 +65,20 @@ void *Scratch::get(size_t bytes) {
     }
     size_t sz = bytes > ((size_t)64 << 20) ? bytes : ((size_t)64 << 20);
     char *p = nullptr;
-    if (hipMalloc(&p, sz) != hipSuccess) throw Error(-2, "device allocation of scratch failed");
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        // the smallest recycled chunk of this device that is large enough
+        ChunkPool &P = chunk_pool();
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.free.lower_bound(std::make_pair(dev, sz));
+        if (it != P.free.end() && it->first.first == dev) {
+            p = it->second;
+            sz = it->first.second;
+            P.bytes -= sz;
+            P.free.erase(it);
+        }
+    }
+    if (!p && hipMalloc(&p, sz) != hipSuccess) throw Error(-2, "device allocation of scratch failed");
     chunks_.push_back({p, sz});
     cur_ = chunks_.size() - 1;
     off_ = bytes;

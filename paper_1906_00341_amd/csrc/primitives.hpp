@@ -8,10 +8,16 @@
 namespace dsd {
 
 // Bump allocator over device chunks; reset() recycles everything (stream-ordered reuse).
+// Device scratch: a bump allocator over chunks of at least 64 MiB.  A new
+// chunk comes from a process-wide pool of recycled chunks (per device, at
+// most 16 GiB kept) before hipMalloc is asked; recycle() hands the chunks to
+// that pool, and the caller promises that no work still uses them (its
+// stream is idle).  Chunks not recycled are freed with the scratch.
 class Scratch {
 public:
     ~Scratch();
     void *get(size_t bytes);
+    void recycle();
     template <typename T> T *get_n(int64_t n) { return (T *)get((size_t)(n > 0 ? n : 1) * sizeof(T)); }
     void reset() { cur_ = 0; off_ = 0; }
     size_t capacity() const;
