@@ -105,7 +105,7 @@ const TriList *tri_lists(dsd_graph_s *G, const u64 *deg, u64 mu) {
         G->tl_tried = true;
         if (tri_list_wanted(G->g, mu)) {
             try {
-                build_tri_list(G->g, deg, mu, G->tl, G->stream, G->sc);
+                build_tri_list(G->g, deg, mu, G->tl, G->stream, G->sc, &G->keep);
             } catch (const Error &e) {
                 if (e.status != DSD_ENOMEM) throw;     // no room: the peel intersects neighbourhoods instead
             }
@@ -123,8 +123,7 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
     hipStream_t s = G->stream;
     const int32_t n = G->g.n;
     if (!D.core) {
-        if (hipMalloc(&D.core, (size_t)(n > 0 ? n : 1) * sizeof(u64)) != hipSuccess)
-            throw Error(DSD_ENOMEM, "device allocation of core numbers failed");
+        D.core = G->keep.get_n<u64>(n);
     }
     D.kt = KernelTimes();
     D.kt.time_main = G->time_main;
@@ -147,7 +146,7 @@ const Decomp &decompose(dsd_graph_s *G, int h) {
         G->tl_tried = true;
         if (D.mu > 0 && tri_list_wanted(G->g, D.mu)) {
             try {
-                build_tri_list(G->g, w, G->tl, s, G->sc);
+                build_tri_list(G->g, w, G->tl, s, G->sc, &G->keep);
             } catch (const Error &e) {
                 if (e.status != DSD_ENOMEM) throw;     // no room: the peel intersects neighbourhoods instead
             }
@@ -429,7 +428,7 @@ dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const
         }
         float t = 0;
         Timer tm(s);
-        build_graph(n, num_pairs, ds, dd, G->g, s, G->sc, &t);
+        build_graph(n, num_pairs, ds, dd, G->g, s, G->sc, &t, &G->keep);
         begin_stats(G);
         G->stats.t_total_ms = tm.stop();
         G->stats.t_orient_ms = t;

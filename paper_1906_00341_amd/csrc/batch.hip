@@ -295,8 +295,7 @@ void run_group(const std::vector<int32_t> &idx, int h, int op, const dsd_graph *
             dsd_graph_s *Gi = graphs[idx[j]];
             const int32_t n = Gi->g.n;
             Decomp &D = Gi->dec[h];
-            if (!D.core && hipMalloc(&D.core, (size_t)(n > 0 ? n : 1) * sizeof(u64)) != hipSuccess)
-                throw Error(DSD_ENOMEM, "device allocation of core numbers failed");
+            if (!D.core) D.core = Gi->keep.get_n<u64>(n);
             if (n > 0)
                 DSD_HIP(hipMemcpyAsync(D.core, core + voff[j], (size_t)n * sizeof(u64), hipMemcpyDeviceToDevice, s));
             const int32_t L = N > 0 ? pr.graph_levels[j] : 0;

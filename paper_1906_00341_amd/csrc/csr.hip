@@ -134,7 +134,7 @@ __global__ void k_wedges(const int64_t *row_ptr, const int64_t *dag_off, int32_t
 }
 
 void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, DevGraph &g, hipStream_t s,
-                 Scratch &sc, float *t_orient_ms) {
+                 Scratch &sc, float *t_orient_ms, Scratch *keep) {
     g.n = n;
     g.bits = bits_for(n > 0 ? n : 1);
     const int bits = g.bits;
@@ -172,11 +172,21 @@ void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, D
     DSD_HIP(hipEventRecord(e0, s));
     // degrees in caller ids -> rank order
     int32_t *deg = sc.get_n<int32_t>(n);
-    DSD_HIP(hipMalloc(&g.row_ptr, ((size_t)n + 1) * sizeof(int64_t)));
-    DSD_HIP(hipMalloc(&g.col, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
-    DSD_HIP(hipMalloc(&g.dag_off, (size_t)(n > 0 ? n : 1) * sizeof(int64_t)));
-    DSD_HIP(hipMalloc(&g.orig_of, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
-    DSD_HIP(hipMalloc(&g.rank_of, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
+    if (keep) {
+        g.owned = false;
+        g.row_ptr = keep->get_n<int64_t>((int64_t)n + 1);
+        g.col = keep->get_n<int32_t>(E);
+        g.dag_off = keep->get_n<int64_t>(n);
+        g.orig_of = keep->get_n<int32_t>(n);
+        g.rank_of = keep->get_n<int32_t>(n);
+    } else {
+        g.owned = true;
+        DSD_HIP(hipMalloc(&g.row_ptr, ((size_t)n + 1) * sizeof(int64_t)));
+        DSD_HIP(hipMalloc(&g.col, (size_t)(E > 0 ? E : 1) * sizeof(int32_t)));
+        DSD_HIP(hipMalloc(&g.dag_off, (size_t)(n > 0 ? n : 1) * sizeof(int64_t)));
+        DSD_HIP(hipMalloc(&g.orig_of, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
+        DSD_HIP(hipMalloc(&g.rank_of, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
+    }
     int32_t *maxes = d_bad + 2;
     if (n > 0) {
         fill_i32(deg, 0, n, s);
@@ -214,11 +224,13 @@ void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, D
 }
 
 void free_graph(DevGraph &g) {
-    (void)hipFree(g.row_ptr);
-    (void)hipFree(g.col);
-    (void)hipFree(g.dag_off);
-    (void)hipFree(g.orig_of);
-    (void)hipFree(g.rank_of);
+    if (g.owned) {
+        (void)hipFree(g.row_ptr);
+        (void)hipFree(g.col);
+        (void)hipFree(g.dag_off);
+        (void)hipFree(g.orig_of);
+        (void)hipFree(g.rank_of);
+    }
     g = DevGraph();
 }
 

@@ -719,12 +719,11 @@ struct GpuFlow::Impl {
     int *eu = nullptr, *ev = nullptr, *fwd = nullptr;
     uint8_t *cls = nullptr;
     int64_t *deg = nullptr;
-    int *pinned = nullptr;
+    int *pinned = nullptr;   // the thread's pinned buffer
     int nv = 0;
     ~Impl() {
         if (s) (void)hipStreamSynchronize(s);
         sc.recycle();
-        if (pinned) (void)hipHostFree(pinned);
         if (s) (void)hipStreamDestroy(s);
     }
     int global_relabel();
@@ -903,7 +902,7 @@ void GpuFlow::Impl::residual(int n) {
     if (b.nbig > 0)
         DSD_HIP(hipMemcpyAsync(d_big, big.data(), big.size() * sizeof(int), hipMemcpyHostToDevice, I.s));
     b.big = d_big;
-    DSD_HIP(hipHostMalloc((void **)&I.pinned, 4 * sizeof(int), hipHostMallocDefault));
+    I.pinned = (int *)thread_pinned();
     DSD_HIP(hipStreamSynchronize(I.s));
 }
 

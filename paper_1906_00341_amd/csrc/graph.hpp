@@ -25,6 +25,7 @@ struct DevGraph {
     int32_t maxdeg = 0, maxdout = 0;
     u64 w2 = 0;   // sum_v d-(v) d+(v): directed 2-paths of the DAG (pairs the enumeration probes)
     u64 s2 = 0;   // sum_v deg(v) d+(v): out-list entries the peel probes over all removed vertices
+    bool owned = true;   // the arrays were hipMalloc'd (else they live in a handle's scratch)
 };
 
 // HIP-event timing of the two kernel families, accumulated per call
@@ -53,8 +54,9 @@ struct KernelTimes {
 // ---- K1 + K2: CSR build and degree-ordered orientation ----
 // src/dst: device arrays of num_pairs raw pairs.  Throws Error(EINVAL) on an
 // id outside [0, n).  t_orient receives the time of the orientation part.
+// keep: where the graph's arrays live (nullptr: hipMalloc, freed by free_graph)
 void build_graph(int32_t n, int64_t num_pairs, const int32_t *src, const int32_t *dst, DevGraph &g,
-                 hipStream_t s, Scratch &sc, float *t_orient_ms);
+                 hipStream_t s, Scratch &sc, float *t_orient_ms, Scratch *keep = nullptr);
 void free_graph(DevGraph &g);
 
 // ---- K3: clique-degrees ----
@@ -72,6 +74,7 @@ struct TriList {
     int32_t *pairs = nullptr;  // [2 * entries]
     int64_t entries = 0;
     u64 mu = 0;
+    bool owned = true;         // hipMalloc'd (else in a handle's scratch)
 };
 // whether the lists of a graph with mu triangles fit (positions in int32,
 // out-degree within the listing kernels, at most a quarter of free device
@@ -97,9 +100,12 @@ u64 tri_counts(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch 
 // the second pass: every triangle written out through per-arc cursors into
 // the segments the counts give.  Allocates tl's arrays (released by
 // free_tri_list).
-void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc);
+// keep: where the lists live (nullptr: hipMalloc, freed by free_tri_list).
+void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc,
+                    Scratch *keep = nullptr);
 // both passes for a graph with mu triangles (deg unused)
-void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc);
+void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc,
+                    Scratch *keep = nullptr);
 // clique-degrees read off finished lists (one pair per triangle at a vertex)
 void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s);
 void free_tri_list(TriList &tl);

@@ -30,6 +30,7 @@ struct dsd_graph_s {
     dsd::DevGraph g;
     hipStream_t stream = nullptr;
     dsd::Scratch sc;
+    dsd::Scratch keep{(size_t)1 << 20};   // the handle's own arrays: CSR, triangle lists, core numbers
     dsd_stats stats{};
     dsd::Decomp dec[7];             // by h
     dsd::TriList tl;                // triangle lists, built by the first h = 3 decomposition that wants them
@@ -37,10 +38,12 @@ struct dsd_graph_s {
     bool time_main = false;         // dsd_set_kernel_timing
     ~dsd_graph_s() {
         (void)hipStreamSynchronize(stream);
-        for (dsd::Decomp &d : dec) (void)hipFree(d.core);
         dsd::free_tri_list(tl);
         dsd::free_graph(g);
-        sc.recycle();   // the stream is idle: the next handle reuses the chunks
+        // the stream is idle: the next handle reuses the chunks (the core
+        // numbers, lists and CSR live in keep)
+        sc.recycle();
+        keep.recycle();
     }
 };
 

@@ -2596,8 +2596,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     k_init_graphs<<<grid_for(G, 256), 256, 0, s>>>(b, mu_dev, grp ? grp->lv_base : nullptr, k_floor);
     k_peel_init<<<grid_for(n, BLOCK, 4096), BLOCK, 0, s>>>(b, alive0, b.lists, &b.ctl->nlist[0]);
     k_start_graphs<<<grid_for(G, 256), 256, 0, s>>>(b);
-    int64_t *pinned = nullptr;
-    DSD_HIP(hipHostMalloc((void **)&pinned, 2 * sizeof(int64_t), hipHostMallocDefault));
+    int64_t *pinned = (int64_t *)thread_pinned();
     DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     int64_t n_alive = pinned[0];
@@ -2673,13 +2672,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         DSD_HIP(hipStreamSynchronize(s));
         n_alive = pinned[0];
-        if (steps > max_steps) {
-            (void)hipHostFree(pinned);
-            throw Error(-3, "peel did not converge");
-        }
+        if (steps > max_steps) throw Error(-3, "peel did not converge");
         if (chunk < 32) chunk *= 2;
     }
-    (void)hipHostFree(pinned);
     if (kt) {
         DSD_HIP(hipEventRecord(e1, s));
         DSD_HIP(hipEventSynchronize(e1));

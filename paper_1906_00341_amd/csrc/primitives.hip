@@ -28,6 +28,15 @@ Scratch::~Scratch() {
     for (auto &c : chunks_) (void)hipFree(c.first);
 }
 
+void *thread_pinned() {
+    thread_local void *p = nullptr;
+    if (!p && hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) {
+        p = nullptr;
+        throw Error(-2, "pinned host allocation failed");
+    }
+    return p;
+}
+
 void Scratch::recycle() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = -1;
@@ -63,7 +72,7 @@ void *Scratch::get(size_t bytes) {
         cur_++;
         off_ = 0;
     }
-    size_t sz = bytes > ((size_t)64 << 20) ? bytes : ((size_t)64 << 20);
+    size_t sz = bytes > min_chunk_ ? bytes : min_chunk_;
     char *p = nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {

@@ -8,13 +8,15 @@
 namespace dsd {
 
 // Bump allocator over device chunks; reset() recycles everything (stream-ordered reuse).
-// Device scratch: a bump allocator over chunks of at least 64 MiB.  A new
+// Device scratch: a bump allocator over chunks of at least min_chunk bytes
+// (64 MiB unless given).  A new
 // chunk comes from a process-wide pool of recycled chunks (per device, at
 // most 16 GiB kept) before hipMalloc is asked; recycle() hands the chunks to
 // that pool, and the caller promises that no work still uses them (its
 // stream is idle).  Chunks not recycled are freed with the scratch.
 class Scratch {
 public:
+    explicit Scratch(size_t min_chunk = (size_t)64 << 20) : min_chunk_(min_chunk) {}
     ~Scratch();
     void *get(size_t bytes);
     void recycle();
@@ -25,6 +27,7 @@ public:
 private:
     std::vector<std::pair<char *, size_t>> chunks_;
     size_t cur_ = 0, off_ = 0;
+    size_t min_chunk_;
 };
 
 // out[i] = sum_{j<i} in[j]; returns nothing, total = out[n-1] + in[n-1].  in == out allowed.
@@ -37,6 +40,10 @@ void radix_sort_u64(u64 *keys, u64 *tmp, int64_t n, int bits, hipStream_t s, Scr
 
 // sum of a u64 array as a 128-bit (lo, hi) pair written to out[0], out[1] (device)
 void sum_u64_128(const u64 *in, int64_t n, u64 *out2, hipStream_t s, Scratch &sc);
+
+// a 64-byte pinned host buffer of the calling thread, for reading counters
+// back; allocated on first use and kept until the process ends
+void *thread_pinned();
 
 // fill helpers (kernels, usable under stream capture)
 void fill_u64(u64 *p, u64 v, int64_t n, hipStream_t s);

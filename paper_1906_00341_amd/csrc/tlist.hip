@@ -405,15 +405,19 @@ u64 tri_counts(const DevGraph &g, u64 *deg, TlCounts &w, hipStream_t s, Scratch 
     return w.mu;
 }
 
-void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc) {
+void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, Scratch &sc, Scratch *keep) {
     free_tri_list(tl);
     const int32_t n = g.n;
     const int64_t arcs = 2 * g.m;
     tl.mu = w.mu;
     tl.entries = 3 * (int64_t)w.mu;
     if (tl.entries > 0x7fffffff) throw Error(-3, "triangle lists: positions exceed 31 bits");
-    if (hipMalloc(&tl.voff, (size_t)(n + 1) * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc(&tl.pairs, (size_t)(tl.entries > 0 ? tl.entries : 1) * 2 * sizeof(int32_t)) != hipSuccess) {
+    if (keep) {
+        tl.owned = false;
+        tl.voff = keep->get_n<int64_t>((int64_t)n + 1);
+        tl.pairs = keep->get_n<int32_t>(2 * tl.entries);
+    } else if (hipMalloc(&tl.voff, (size_t)(n + 1) * sizeof(int64_t)) != hipSuccess ||
+               hipMalloc(&tl.pairs, (size_t)(tl.entries > 0 ? tl.entries : 1) * 2 * sizeof(int32_t)) != hipSuccess) {
         free_tri_list(tl);
         throw Error(-2, "device allocation of the triangle lists failed");
     }
@@ -457,12 +461,13 @@ void build_tri_list(const DevGraph &g, TlCounts &w, TriList &tl, hipStream_t s, 
     }
 }
 
-void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc) {
+void build_tri_list(const DevGraph &g, const u64 *deg, u64 mu, TriList &tl, hipStream_t s, Scratch &sc,
+                    Scratch *keep) {
     (void)deg;
     TlCounts w;
     u64 *d = sc.get_n<u64>(g.n);
     if (tri_counts(g, d, w, s, sc) != mu) throw Error(-3, "triangle lists do not match the clique-degrees");
-    build_tri_list(g, w, tl, s, sc);
+    build_tri_list(g, w, tl, s, sc, keep);
 }
 
 void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s) {
@@ -470,8 +475,10 @@ void tri_list_degrees(const TriList &tl, int32_t n, u64 *deg, hipStream_t s) {
 }
 
 void free_tri_list(TriList &tl) {
-    (void)hipFree(tl.voff);
-    (void)hipFree(tl.pairs);
+    if (tl.owned) {
+        (void)hipFree(tl.voff);
+        (void)hipFree(tl.pairs);
+    }
     tl = TriList();
 }
 
