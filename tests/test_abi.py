@@ -62,3 +62,35 @@ def test_batch_and_server_arguments_are_rejected_without_touching_a_gpu():
     assert lib.dsd_server_wait(None, 1, 0, None) == -1
     assert lib.dsd_server_cancel(None, 1) == -1
     assert lib.dsd_server_destroy(None) == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's ctypes structures against the header, compiled by the C
+    # compiler: every field at the same offset, the same total size
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    structs = {"dsd_stats": dsd.Stats, "dsd_result": dsd.Result, "dsd_rational": dsd.Rational}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
