@@ -127,8 +127,15 @@ dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const
 /* n and the number of undirected edges after de-duplication. */
 dsd_status dsd_graph_info(dsd_graph g, int32_t *n, int64_t *m);
 
-/* Release the handle and its device memory.  NULL is accepted. */
+/* Release the handle.  Its device memory goes to a process-wide cache of
+ * chunks per device (at most 16 GiB), from which later handles draw before
+ * they allocate; dsd_release_cache hands the cache back to the device.
+ * NULL is accepted. */
 dsd_status dsd_graph_free(dsd_graph g);
+
+/* Free every cached chunk (memory of freed handles, kept for reuse) of every
+ * device.  Handles still alive keep their own memory.  Always DSD_OK. */
+dsd_status dsd_release_cache(void);
 
 /*
  * Clique-degree (Definition 3): deg[v] = number of h-clique instances that

@@ -460,6 +460,11 @@ dsd_status dsd_last_stats(dsd_graph g, dsd_stats *out) {
     return DSD_OK;
 }
 
+dsd_status dsd_release_cache(void) {
+    dsd::release_chunk_pool();
+    return DSD_OK;
+}
+
 dsd_status dsd_set_kernel_timing(dsd_graph g, int on) {
     if (!g) return fail(DSD_EINVAL, "NULL graph");
     g->time_main = on != 0;

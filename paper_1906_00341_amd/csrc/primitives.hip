@@ -28,6 +28,20 @@ Scratch::~Scratch() {
     for (auto &c : chunks_) (void)hipFree(c.first);
 }
 
+void release_chunk_pool() {
+    ChunkPool &P = chunk_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto &e : P.free) {
+        if (have) (void)hipSetDevice(e.first.first);
+        (void)hipFree(e.second);
+    }
+    if (have) (void)hipSetDevice(cur);
+    P.free.clear();
+    P.bytes = 0;
+}
+
 void *thread_pinned() {
     thread_local void *p = nullptr;
     if (!p && hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) {

@@ -41,6 +41,9 @@ void radix_sort_u64(u64 *keys, u64 *tmp, int64_t n, int bits, hipStream_t s, Scr
 // sum of a u64 array as a 128-bit (lo, hi) pair written to out[0], out[1] (device)
 void sum_u64_128(const u64 *in, int64_t n, u64 *out2, hipStream_t s, Scratch &sc);
 
+// free every recycled chunk of every device
+void release_chunk_pool();
+
 // a 64-byte pinned host buffer of the calling thread, for reading counters
 // back; allocated on first use and kept until the process ends
 void *thread_pinned();

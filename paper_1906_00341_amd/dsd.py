@@ -33,7 +33,7 @@ OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT,
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
            "dsd_pattern_degrees", "dsd_pattern_core",
-           "dsd_last_stats", "dsd_set_kernel_timing",
+           "dsd_last_stats", "dsd_set_kernel_timing", "dsd_release_cache",
            "dsd_batch_run", "dsd_server_create", "dsd_server_submit", "dsd_server_wait",
            "dsd_server_cancel", "dsd_server_destroy", "dsd_status_str", "dsd_last_error"]
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.dsd_build_csr.argtypes = [I32, I64, P, P, I, P, C.POINTER(P)]
     lib.dsd_graph_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64)]
     lib.dsd_graph_free.argtypes = [P]
+    lib.dsd_release_cache.argtypes = []
     lib.dsd_clique_degrees.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_clique_core.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
@@ -217,6 +218,11 @@ def clique_degrees(g: Graph, h: int, out=None):
     _check(_lib.dsd_clique_degrees(g.handle, int(h), mem, p, C.byref(mu)))
     n, _ = g.info()
     return out[:n] if isinstance(out, np.ndarray) else out, int(mu.value)
+
+
+def release_cache():
+    """dsd_release_cache: free the device memory that freed handles left for reuse."""
+    _check(_lib.dsd_release_cache())
 
 
 def clique_core(g: Graph, h: int, out=None):
