@@ -158,24 +158,39 @@ __global__ void k_compact_verts(const uint8_t *mask, const int64_t *pos, int32_t
         if (mask[v]) verts[pos[v]] = (int32_t)v;
 }
 
-__global__ void k_local_deg(const int32_t *verts, int64_t cnt, const int64_t *row_ptr, const int32_t *col,
-                            const uint8_t *mask, int64_t *ldeg) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v = verts[i];
+// One wave per located vertex (they are the graph's hubs, with the longest
+// rows): its neighbours inside the mask, counted, then written in row order.
+__global__ __launch_bounds__(BLOCK) void k_local_deg(const int32_t *verts, int64_t cnt, const int64_t *row_ptr,
+                                                      const int32_t *col, const uint8_t *mask, int64_t *ldeg) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < cnt; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = verts[i];
         int64_t c = 0;
-        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) c += mask[col[e]] ? 1 : 0;
-        ldeg[i] = c;
+        for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) c += mask[col[e]] ? 1 : 0;
+        c = wave_sum(c);
+        if (lane() == 0) ldeg[i] = c;
     }
 }
 
-__global__ void k_local_fill(const int32_t *verts, int64_t cnt, const int64_t *row_ptr, const int32_t *col,
-                             const uint8_t *mask, const int64_t *pos, const int64_t *loff, int32_t *ladj) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v = verts[i];
+__global__ __launch_bounds__(BLOCK) void k_local_fill(const int32_t *verts, int64_t cnt, const int64_t *row_ptr,
+                                                       const int32_t *col, const uint8_t *mask, const int64_t *pos,
+                                                       const int64_t *loff, int32_t *ladj) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < cnt; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = verts[i];
         int64_t o = loff[i];
-        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
-            int32_t w = col[e];
-            if (mask[w]) ladj[o++] = (int32_t)pos[w];
+        const int64_t e1 = row_ptr[v + 1];
+        for (int64_t e0 = row_ptr[v]; e0 < e1; e0 += WAVE) {
+            const int64_t e = e0 + lane();
+            int32_t w = -1;
+            bool keep = false;
+            if (e < e1) {
+                w = col[e];
+                keep = mask[w] != 0;
+            }
+            const u64 m = __ballot(keep);
+            if (keep) ladj[o + __popcll(m & lanemask_lt())] = (int32_t)pos[w];
+            o += __popcll(m);
         }
     }
 }
@@ -207,7 +222,7 @@ void extract_induced(const DevGraph &g, const uint8_t *mask, const int32_t *labe
     int32_t *verts = sc.get_n<int32_t>(cnt);
     int64_t *loff = sc.get_n<int64_t>(cnt);
     k_compact_verts<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(mask, pos, n, verts);
-    k_local_deg<<<grid_for(cnt, BLOCK, 8192), BLOCK, 0, s>>>(verts, cnt, g.row_ptr, g.col, mask, loff);
+    k_local_deg<<<grid_for(cnt, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(verts, cnt, g.row_ptr, g.col, mask, loff);
     int64_t lastdeg = 0;
     DSD_HIP(hipMemcpyAsync(&lastdeg, loff + cnt - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     scan_exclusive_i64(loff, loff, cnt, s, sc);
@@ -218,7 +233,8 @@ void extract_induced(const DevGraph &g, const uint8_t *mask, const int32_t *labe
     int32_t *ladj = sc.get_n<int32_t>(tot);
     u64 *ocore = sc.get_n<u64>(cnt);
     int32_t *olabel = sc.get_n<int32_t>(cnt);
-    k_local_fill<<<grid_for(cnt, BLOCK, 8192), BLOCK, 0, s>>>(verts, cnt, g.row_ptr, g.col, mask, pos, loff, ladj);
+    k_local_fill<<<grid_for(cnt, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(verts, cnt, g.row_ptr, g.col, mask, pos, loff,
+                                                                        ladj);
     k_gather_located<<<grid_for(cnt, BLOCK, 8192), BLOCK, 0, s>>>(verts, cnt, core, label, ocore, olabel);
     out.rank.resize(cnt);
     out.off.resize(cnt + 1);
