@@ -20,17 +20,22 @@ struct EnumCtx {
     __device__ __forceinline__ void add_prefix(int64_t it, u64 t) const { atomic_add_u64(&deg[roots[it]], t); }
 };
 
-// h = 2: the clique-degree is the degree inside the mask
-__global__ void k_deg_h2(const int64_t *row_ptr, const int32_t *col, const uint8_t *mask, int32_t n, u64 *deg) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        if (!mask) {
-            deg[v] = (u64)(row_ptr[v + 1] - row_ptr[v]);
-            continue;
-        }
+// h = 2: the clique-degree is the degree (inside the mask: one wave per
+// vertex, since a hub's row is long)
+__global__ void k_deg_h2(const int64_t *row_ptr, int32_t n, u64 *deg) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        deg[v] = (u64)(row_ptr[v + 1] - row_ptr[v]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_deg_h2_masked(const int64_t *row_ptr, const int32_t *col,
+                                                          const uint8_t *mask, int32_t n, u64 *deg) {
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; v < n; v += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
         u64 c = 0;
         if (mask[v])
-            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) c += mask[col[e]] ? 1 : 0;
-        deg[v] = c;
+            for (int64_t e = row_ptr[v] + lane(); e < row_ptr[v + 1]; e += WAVE) c += mask[col[e]] ? 1 : 0;
+        c = wave_sum(c);
+        if (lane() == 0) deg[v] = c;
     }
 }
 
@@ -143,7 +148,8 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
     const int32_t n = g.n;
     if (n == 0) return true;
     if (h == 2) {
-        k_deg_h2<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, mask, n, deg);
+        if (mask) k_deg_h2_masked<<<grid_for(n, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, g.col, mask, n, deg);
+        else k_deg_h2<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(g.row_ptr, n, deg);
         return true;
     }
     const int R = h - 1;
