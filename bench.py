@@ -286,7 +286,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is not sharded "
-              f"across GPUs in this build", file=sys.stderr)
+              f"across GPUs", file=sys.stderr)
         return 2
     import numpy as np
     import torch

@@ -343,7 +343,7 @@ bool tri_list_wanted(const DevGraph &g, u64 mu) {
     if (g.n == 0 || mu == 0 || g.maxdout > TL_MAX_OUT) return false;
     if (mu > (u64)0x7fffffff / 3) return false;             // entries are counted in int32 positions
     const int64_t entries = 3 * (int64_t)mu, arcs = 2 * g.m;
-    // pairs and row starts, and the build's segment starts, cursors and reverse arcs
+    // pairs and row starts, and the listing's segment starts, cursors and reverse arcs
     const int64_t bytes = 8 * entries + 8 * ((int64_t)g.n + 1) + 24 * arcs + 8;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
