@@ -110,6 +110,15 @@ typedef struct {
      * dsd_set_kernel_timing on; else 0), count and pairs */
     double k4_tail_grid_ms;
     uint64_t k4_tail_grid_rounds, k4_tail_grid_pairs;
+    /* CoreExact's locate step (Section 6.1, Pruning1 and Pruning2), filled by
+     * dsd_core_exact (else 0): rho' = the largest density mu(R_k)/|R_k| over
+     * the level sets, k' = ceil(rho'); rho'' = the largest density of a
+     * connected component of R_{k'}, of which there are locate_components;
+     * k'' = max(k', ceil(rho'')); located_vertices above is |R_{k''}|, the
+     * vertices handed to the exact search.  Densities as reduced num/den. */
+    uint64_t locate_rho1_num, locate_rho1_den, locate_k1;
+    uint64_t locate_rho2_num, locate_rho2_den, locate_k2;
+    uint64_t locate_components;
 } dsd_stats;
 
 /*
@@ -144,6 +153,7 @@ dsd_status dsd_release_cache(void);
  */
 dsd_status dsd_clique_degrees(dsd_graph g, int h, int out_mem, uint64_t *deg,
                               uint64_t *num_cliques);
+
 
 /*
  * (k, Psi)-core decomposition (Definition 6, Algorithm 3): core[v] = the
@@ -303,16 +313,23 @@ dsd_status dsd_batch_run(int32_t count, const dsd_graph *graphs, const int *h, i
 
 /* ------------------------------------------------------------------ serving
  *
- * A server owns two worker threads, one for requests on graphs below 2^20
- * edges and one for larger graphs, so that small requests never queue
- * behind a large one.  A worker takes, in arrival order, the queued requests
- * of its class that fit the device-memory budget left by running work,
- * groups them (distinct graphs, one op per group), runs every group through
- * dsd_batch_run and completes their tickets.  A request's footprint is estimated as 160 bytes per vertex plus
- * 192 bytes per edge (the peel's buffers dominate); requests start only while
- * the running footprints fit in hbm_budget_bytes, and one that could never
- * fit is refused at submit with DSD_ENOMEM.  At most max_slots requests are
- * queued or running at once (DSD_EBUSY beyond). */
+ * Continuous batching.  A server owns worker threads (4, or
+ * DSD_SERVER_WORKERS in [2, 16]), each with a non-blocking HIP stream of its
+ * own.  A free worker takes the oldest queued request that fits the
+ * device-memory budget left by running work and, when that request is on a
+ * graph below 2^20 edges, every other queued small request with the same op
+ * and h on a distinct graph that still fits; it runs that group through
+ * dsd_batch_run on its stream (the group's handles are switched to it for
+ * the run) and completes their tickets.  Requests that arrive while others
+ * run therefore start as soon as a worker and budget are free, and the
+ * groups of different workers overlap on the device.  A request on a larger
+ * graph runs alone, and at most all workers but one hold such requests, so
+ * small requests never wait behind large ones alone.  A request's footprint
+ * is estimated as 160 bytes per vertex plus 192 bytes per edge (the peel's
+ * buffers dominate); one that could never fit hbm_budget_bytes is refused at
+ * submit with DSD_ENOMEM.  At most max_slots requests are queued or running
+ * at once (DSD_EBUSY beyond).  A queued request may be overtaken by later
+ * ones that fit while it does not. */
 typedef struct dsd_server_s *dsd_server;
 
 dsd_status dsd_server_create(size_t hbm_budget_bytes, int max_slots, dsd_server *out);

@@ -247,6 +247,18 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
         }
     dsd_rational r2 = make_rational(rn, rd);
     const u64 k2 = std::max(k1, ceil_div_u(r2.num, r2.den));
+    {
+        const dsd_rational r1 = make_rational(a, b);
+        G->stats.locate_rho1_num = r1.num;
+        G->stats.locate_rho1_den = r1.den;
+        G->stats.locate_k1 = k1;
+        G->stats.locate_rho2_num = r2.num;
+        G->stats.locate_rho2_den = r2.den;
+        G->stats.locate_k2 = k2;
+        u64 nc = 0;
+        for (const CompInfo &c : c1) nc += c.size > 0 ? 1 : 0;
+        G->stats.locate_components = nc;
+    }
     // D starts as the better of the level set attaining rho' and the
     // component attaining rho''; both densities are lower bounds on rho_opt
     if (rat_gt(a, b, r2.num, r2.den) && best_level >= 0) {
@@ -268,6 +280,35 @@ dsd_rational core_exact_run(dsd_graph_s *G, int h, uint8_t *res) {
     LocatedCore lc;
     extract_induced(G->g, m2, lab2, core, lc, s, G->sc);
     G->stats.located_vertices = lc.rank.size();
+    // h-cliques of every located component, counted here so that the exact
+    // search can refuse a component whose network would be too large before
+    // it lists anything: one component is R_{k''} itself, whose cliques the
+    // level table holds (mu(R_k) of the first level k >= k''); otherwise the
+    // components of R_{k'} (k'' = k') or a masked enumeration of R_{k''}
+    {
+        std::vector<int32_t> labs(lc.label);
+        std::sort(labs.begin(), labs.end());
+        labs.erase(std::unique(labs.begin(), labs.end()), labs.end());
+        if (labs.size() == 1) {
+            for (size_t i = 0; i < pr.level_k.size(); i++)
+                if (pr.level_k[i] >= k2) {
+                    lc.comp_mu.push_back({labs[0], pr.level_mu[i]});
+                    break;
+                }
+        } else if (labs.size() > 1) {
+            std::vector<CompInfo> c2;
+            if (k2 == k1) {
+                c2 = c1;
+            } else {
+                u64 *d2 = G->sc.get_n<u64>(n), *sz2 = G->sc.get_n<u64>(n), *ds2 = G->sc.get_n<u64>(n);
+                degrees_and_mu(G, h, m2, d2);
+                component_sums(lab2, d2, n, sz2, ds2, s);
+                collect_components(lab2, sz2, ds2, n, c2, s, G->sc);
+            }
+            for (const CompInfo &c : c2) lc.comp_mu.push_back({c.root, c.dsum / (u64)h});
+            std::sort(lc.comp_mu.begin(), lc.comp_mu.end());
+        }
+    }
     G->stats.t_locate_ms = tl.stop();
     auto t0 = std::chrono::steady_clock::now();
     Rational l{rho.num, rho.den};

@@ -268,7 +268,7 @@ void collect_components(const int32_t *label, const u64 *size, const u64 *dsum, 
     int32_t *cnt = sc.get_n<int32_t>(1);
     int32_t *root = sc.get_n<int32_t>(n);
     u64 *osize = sc.get_n<u64>(n), *odsum = sc.get_n<u64>(n);
-    DSD_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+    fill_i32(cnt, 0, 1, s);
     k_collect_roots<<<grid_for(n, BLOCK, 8192), BLOCK, 0, s>>>(label, size, dsum, n, cnt, root, osize, odsum);
     int32_t hc = 0;
     DSD_HIP(hipMemcpyAsync(&hc, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -141,7 +141,7 @@ void build_graph(int32_t n, int64_t P, const int32_t *src, const int32_t *dst, D
     const u64 invalid = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1ull);
     int64_t m = 0;
     int32_t *d_bad = sc.get_n<int32_t>(4);
-    DSD_HIP(hipMemsetAsync(d_bad, 0, 4 * sizeof(int32_t), s));
+    fill_i32(d_bad, 0, 4, s);
     u64 *edges = nullptr;
     if (P > 0) {
         u64 *keys = sc.get_n<u64>(P), *tmp = sc.get_n<u64>(P);

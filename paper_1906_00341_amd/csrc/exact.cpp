@@ -40,9 +40,18 @@ namespace dsd {
 
 typedef __int128 i128;
 static const int64_t CAP_LIMIT = (int64_t)1 << 62;
-// Every network is built over a subset of one component, so bounding the
-// h-cliques of each component bounds every network (about h arcs per clique).
-static const uint64_t MAX_HOST_CLIQUES = 100000000ull;
+// Every network is bounded before it is built: at most this many h-cliques
+// (about h arcs each); the environment variable DSD_EXACT_MAX_CLIQUES lowers
+// or raises it (read at every call).
+static const uint64_t MAX_HOST_CLIQUES_DEFAULT = 100000000ull;
+static uint64_t max_host_cliques() {
+    const char *e = getenv("DSD_EXACT_MAX_CLIQUES");
+    return e ? (uint64_t)strtoull(e, nullptr, 10) : MAX_HOST_CLIQUES_DEFAULT;
+}
+static void too_many_cliques() {
+    throw Error(-5, "a flow network of the exact step would hold more h-cliques than its limit (1e8 unless "
+                    "DSD_EXACT_MAX_CLIQUES says otherwise)");
+}
 // Networks with at least this many residual arcs get their minimum cut on the
 // GPU (DSD_FLOW_GPU_MIN_ARCS overrides; a negative value keeps every cut on
 // the host).  A device run that has not converged after GPU_FLOW_MAX_PASSES
@@ -156,6 +165,8 @@ public:
     // every node's list.
     void build() {
         const int64_t E = E_;
+        if (2 * E > (int64_t)0x7fffffff)
+            throw Error(-5, "flow network has more than 2^31 residual arcs (limit of the host solver)");
         const int T = E < (1 << 20) ? 1 : host_threads();
         std::vector<std::vector<int>> cnt(T, std::vector<int>(n_, 0));
         parallel_slices(E, T, [&](int t, int64_t lo, int64_t hi) {
@@ -422,15 +433,15 @@ uint64_t count_cliques_host(const LocatedCore &lc, int h, const std::vector<int3
     std::atomic<bool> over{false};
     std::vector<CliqueLister> lister;
     for (int t = 0; t < T; t++) lister.emplace_back(lc, in, h);
+    const uint64_t limit = max_host_cliques();
     parallel_dynamic((int64_t)verts.size(), T, 4, [&](int t, int64_t i) {
         if (over.load(std::memory_order_relaxed)) return;
         uint64_t c = 0;
         lister[t].root(verts[i], [&](const int32_t *) { c++; });
         cnt[t] += c;
-        if (total.fetch_add(c) + c > MAX_HOST_CLIQUES) over = true;
+        if (total.fetch_add(c) + c > limit) over = true;
     });
-    if (over) throw Error(-5, "a located component holds more than 1e8 h-cliques: its flow network is beyond "
-                              "the host exact step's limit");
+    if (over) too_many_cliques();
     uint64_t c = 0;
     for (uint64_t x : cnt) c += x;
     return c;
@@ -509,6 +520,8 @@ public:
         } else if (h == 3) {
             build_triangle_net(verts);
         } else {
+            // bounded first: the listing below holds every clique in memory
+            (void)count_cliques_host(lc, h, verts);
             // h-cliques, and the (h-1)-cliques they contain, as sorted tuples
             const int r = h - 1;
             std::vector<int32_t> cl;
@@ -524,15 +537,18 @@ public:
                         if (i != drop) tup.push_back(K[i]);
             }
             const uint64_t T = mu_ * h;
+            if (T > 0xffffffffull) too_many_cliques();   // tuple ids are 32-bit
             std::vector<uint32_t> ord(T);
             std::iota(ord.begin(), ord.end(), 0u);
             std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
-                return std::lexicographical_compare(&tup[a * r], &tup[a * r] + r, &tup[b * r], &tup[b * r] + r);
+                const int32_t *ta = &tup[(size_t)a * r], *tb = &tup[(size_t)b * r];
+                return std::lexicographical_compare(ta, ta + r, tb, tb + r);
             });
             std::vector<int32_t> psi_of(T);
             int64_t npsi = 0;
             for (uint64_t i = 0; i < T; i++) {
-                if (i > 0 && std::equal(&tup[ord[i] * r], &tup[ord[i] * r] + r, &tup[ord[i - 1] * r])) {
+                if (i > 0 && std::equal(&tup[(size_t)ord[i] * r], &tup[(size_t)ord[i] * r] + r,
+                                        &tup[(size_t)ord[i - 1] * r])) {
                     psi_of[ord[i]] = psi_of[ord[i - 1]];
                 } else {
                     psi_of[ord[i]] = (int32_t)npsi;
@@ -549,7 +565,7 @@ public:
             }
             for (int64_t p = 0; p < npsi; p++)
                 for (int i = 0; i < r; i++)
-                    inf_.push_back(net_->arc((int)(base + p), 2 + idx_[tup[psi_first_[p] * r + i]]));
+                    inf_.push_back(net_->arc((int)(base + p), 2 + idx_[tup[(size_t)psi_first_[p] * r + i]]));
             for (uint64_t c = 0; c < mu_; c++) {
                 const int32_t *K = &cl[c * h];
                 for (int drop = 0; drop < h; drop++)
@@ -615,6 +631,7 @@ public:
         });
         for (int i = 0; i < nv; i++) tri_of[i + 1] += tri_of[i];
         const uint64_t tri = tri_of[nv];
+        if (tri > max_host_cliques()) too_many_cliques();
         mu_ = tri;
         net_ = new PushRelabel((int)(base + npsi));
         net_->reserve(2 * (int64_t)nv + 2 * npsi + 3 * (int64_t)tri);
@@ -834,12 +851,27 @@ bool exact_search(const LocatedCore &lc, int h, uint64_t kpp, Rational &l, std::
         if (c.v.size() < 2) continue;
         comps.push_back(std::move(c));
     }
-    // densest components first (one component needs no order)
-    if (comps.size() > 1) {
-        for (Comp &c : comps) c.dens = reduced(count_cliques(lc, h, c.v), c.v.size());
+    // every component's h-cliques, from the GPU's counts when the caller has
+    // them: a component whose network would pass the limit is refused before
+    // anything is built, and the components are searched densest first
+    auto gpu_mu = [&](int32_t label, uint64_t *mu) {
+        auto it = std::lower_bound(lc.comp_mu.begin(), lc.comp_mu.end(), std::make_pair(label, (uint64_t)0));
+        if (it == lc.comp_mu.end() || it->first != label) return false;
+        *mu = it->second;
+        return true;
+    };
+    for (Comp &c : comps) {
+        uint64_t mu = 0;
+        if (!gpu_mu(lc.label[c.v[0]], &mu)) {
+            if (comps.size() == 1) continue;   // one component needs no order
+            mu = count_cliques(lc, h, c.v);
+        }
+        if (h >= 4 && mu > max_host_cliques()) too_many_cliques();
+        c.dens = reduced(mu, c.v.size());
+    }
+    if (comps.size() > 1)
         std::stable_sort(comps.begin(), comps.end(),
                          [](const Comp &a, const Comp &b) { return frac_less(b.dens, a.dens); });
-    }
     bool improved = false;
     std::vector<int32_t> found, cur, built;
     for (const Comp &c : comps) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 namespace dsd {
@@ -14,6 +15,9 @@ struct LocatedCore {
     std::vector<int32_t> adj;
     std::vector<uint64_t> core;     // clique-core number
     std::vector<int32_t> label;     // component label (any id, equal within a component)
+    // (label, h-cliques) of every component, counted on the GPU, sorted by
+    // label; empty when the caller did not count them
+    std::vector<std::pair<int32_t, uint64_t>> comp_mu;
 };
 
 struct Rational {

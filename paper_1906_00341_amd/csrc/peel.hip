@@ -133,6 +133,8 @@ struct PeelBufs {
     int64_t lsize;
     int32_t count_work;  // the main kernel adds up its pairs and neighbours
     int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
+    const u64 *eset;     // h >= 4: open-addressing set of the edges among the peel's vertices
+    int32_t eset_bits;   // (2^eset_bits slots, keys (lo << 32 | hi) in rank space)
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
@@ -141,6 +143,24 @@ constexpr int SLOTS_PER_CHUNK = 64;     // global hash slots per chunk (load fac
 constexpr int WIDE_OUT = 32;            // neighbours w with |N+(w)| >= this get a wave of their own
 constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
 constexpr int TL_CHUNK = 128;           // pairs per row item (two per lane), triangle lists
+constexpr int CHUNK4 = 64;              // h >= 4: neighbours per chunk item of a frontier vertex (one wave)
+constexpr u64 ESET_EMPTY = ~0ull;
+
+// Edge membership for the h >= 4 peel: one probe sequence in a table of
+// 64-bit keys instead of a binary search in a (possibly long) row.
+__device__ __forceinline__ u64 eset_key(int32_t a, int32_t b) {
+    const uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+    return ((u64)lo << 32) | hi;
+}
+__device__ __forceinline__ u64 eset_slot(u64 key, int bits) { return (key * 0x9E3779B97F4A7C15ull) >> (64 - bits); }
+__device__ __forceinline__ bool eset_has(const u64 *t, int bits, int32_t a, int32_t b) {
+    const u64 key = eset_key(a, b), mask = (1ull << bits) - 1ull;
+    for (u64 i = eset_slot(key, bits);; i = (i + 1) & mask) {
+        const u64 k = t[i];
+        if (k == key) return true;
+        if (k == ESET_EMPTY) return false;
+    }
+}
 
 __device__ __forceinline__ int32_t graph_of(const PeelBufs &b, int32_t v) { return b.gid ? b.gid[v] : 0; }
 
@@ -216,6 +236,16 @@ __device__ __forceinline__ void wave_add_by_graph(int32_t g, T *base, size_t str
 // chunk items of a large frontier vertex, and the slots of its neighbourhood
 // hash (h = 3)
 __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int which) {
+    if (b.h >= 4) {
+        // h >= 4: one item per CHUNK4 neighbours; k_peel_items expands them
+        const int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
+        if (d == 0) return;
+        const int32_t nc = (int32_t)((d + CHUNK4 - 1) / CHUNK4);
+        const int32_t base = atomicAdd(&b.ctl->nB[which], nc);
+        int64_t *Bw = b.B + (size_t)which * b.bcap;
+        for (int32_t c = 0; c < nc; c++) Bw[base + c] = ((int64_t)x << 32) | c;
+        return;
+    }
     if (b.h != 3) return;
     int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
     if (d <= SMALL_DEG) return;
@@ -1343,7 +1373,7 @@ struct PeelCtx {
     __device__ __forceinline__ bool accept(int64_t it, int32_t x) const {
         const int32_t v = b.item_v[cls * b.item_cap + it];
         if (!allowed(b.stamp[x], b.ctl->round, x, v)) return false;
-        return bsearch_i32(b.col, b.row_ptr[v], b.row_ptr[v + 1], x) >= 0;
+        return eset_has(b.eset, b.eset_bits, v, x);
     }
     __device__ __forceinline__ void add(int32_t x, u64 cnt) const {
         const int32_t r = b.ctl->round;
@@ -1367,35 +1397,63 @@ __device__ __forceinline__ int item_class(int d, int R) {
     return 4;
 }
 
+// One wave per chunk item (v, c): the neighbours N(v)[c * CHUNK4, ...) of
+// frontier vertex v.  A vertex in no alive clique at the start of the round
+// (degree 0) destroys nothing, and a neighbour w of degree 0 shares no clique
+// with v: neither makes items.  The degrees do not change during this kernel
+// (the engines run after it).
 __global__ __launch_bounds__(BLOCK) void k_peel_items(PeelBufs b, int R) {
     PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur, nF = c->nF[cur];
-    if (nF == 0) return;
+    const int32_t cur = c->cur, nB = c->nB[cur];
+    if (c->nF[cur] == 0 || nB == 0) return;
     const int32_t r = c->round;
-    const int32_t *F = b.F + (size_t)cur * b.n;
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const int wv = threadIdx.x / WAVE;
-    for (int64_t fi = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; fi < nF; fi += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
-        const int32_t v = F[fi];
-        const int64_t e1 = b.row_ptr[v + 1];
-        for (int64_t e = b.row_ptr[v]; e < e1; e += WAVE) {
-            int cls = -1;
-            int32_t w = -1;
-            if (e + lane() < e1) {
-                w = b.col[e + lane()];
-                if (allowed(b.stamp[w], r, w, v)) cls = item_class((int)(b.row_ptr[w + 1] - b.dag_off[w]), R);
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nB; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int64_t item = Bc[it];
+        const int32_t v = (int32_t)(item >> 32), ch = (int32_t)(item & 0xffffffff);
+        if (b.deg[v] == 0) continue;                          // wave-uniform
+        const int64_t e = b.row_ptr[v] + (int64_t)ch * CHUNK4 + lane();
+        int cls = -1;
+        int32_t w = -1;
+        if (e < b.row_ptr[v + 1]) {
+            w = b.col[e];
+            if (allowed(b.stamp[w], r, w, v) && b.deg[w] != 0)
+                cls = item_class((int)(b.row_ptr[w + 1] - b.dag_off[w]), R);
+        }
+        for (int q = 0; q < 5; q++) {
+            u64 m = __ballot(cls == q);
+            if (!m) continue;
+            int leader = __builtin_ctzll(m);
+            int32_t base = 0;
+            if (lane() == leader) base = atomicAdd(&c->nitems[q], __popcll(m));
+            base = __shfl(base, leader, WAVE);
+            if (cls == q) {
+                int64_t pos = (int64_t)q * b.item_cap + base + __popcll(m & lanemask_lt());
+                b.item_v[pos] = v;
+                b.item_w[pos] = w;
             }
-            for (int q = 0; q < 5; q++) {
-                u64 m = __ballot(cls == q);
-                if (!m) continue;
-                int leader = __builtin_ctzll(m);
-                int32_t base = 0;
-                if (lane() == leader) base = atomicAdd(&c->nitems[q], __popcll(m));
-                base = __shfl(base, leader, WAVE);
-                if (cls == q) {
-                    int64_t pos = (int64_t)q * b.item_cap + base + __popcll(m & lanemask_lt());
-                    b.item_v[pos] = v;
-                    b.item_w[pos] = w;
-                }
+        }
+    }
+}
+
+// The edge set of the h >= 4 peel: every DAG arc (v, x) with both ends in the
+// peel's starting vertex set (one wave per listed vertex, its out-row).
+__global__ __launch_bounds__(BLOCK) void k_eset_fill(PeelBufs b, const int32_t *list, const int32_t *count,
+                                                     u64 *t) {
+    const int32_t cnt = *count;
+    const u64 mask = (1ull << b.eset_bits) - 1ull;
+    const int wv = threadIdx.x / WAVE;
+    for (int64_t i = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; i < cnt; i += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = list[i];
+        for (int64_t e = b.dag_off[v] + lane(); e < b.row_ptr[v + 1]; e += WAVE) {
+            const int32_t x = b.col[e];
+            if (b.stamp[x] != ALIVE) continue;
+            const u64 key = eset_key(v, x);
+            for (u64 j = eset_slot(key, b.eset_bits);; j = (j + 1) & mask) {
+                const u64 prev = atomicCAS((unsigned long long *)&t[j], (unsigned long long)ESET_EMPTY,
+                                           (unsigned long long)key);
+                if (prev == ESET_EMPTY || prev == key) break;
             }
         }
     }
@@ -1508,7 +1566,7 @@ static void compact_adjacency(PeelBufs &b, hipStream_t s, Scratch &sc) {
     b.row_ptr = nrow;
     b.col = ncol;
     b.dag_off = ndag;
-    if (b.h == 3) {
+    if (b.h >= 3) {
         k_reset_chunks<<<1, 1, 0, s>>>(b);
         k_rechunk<<<256, BLOCK, 0, s>>>(b);
     }
@@ -2343,27 +2401,34 @@ private:
 };
 
 template <int R>
-// the engines read the peel's current (possibly compacted) adjacency
-static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS) {
+// the engines read the peel's current (possibly compacted) adjacency; a
+// class whose out-degree range lies above the graph's largest out-degree
+// (maxdout) never has items and is not launched
+static void launch_peel_items(const PeelBufs &b, hipStream_t s, u64 *gS, int32_t maxdout) {
     PeelCtx ctx{b, 0};
     const int32_t *ni = &b.ctl->nitems[0];
     k_engine_wave<R, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off, 0, ni + 0);
     if constexpr (R <= 2) {
         ctx.cls = 1;
-        k_engine_block<R, 2048, 12, 1, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
-                                                                                0, ni + 1, nullptr);
+        if (maxdout > 64)
+            k_engine_block<R, 2048, 12, 1, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
+                                                                                    0, ni + 1, nullptr);
         ctx.cls = 2;
-        k_engine_huge_r2<PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off, 0, ni + 2);
+        if (maxdout > 2048)
+            k_engine_huge_r2<PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off, 0, ni + 2);
     } else {
         ctx.cls = 1;
-        k_engine_block<R, 256, 9, 4, false, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
-                                                                               0, ni + 1, nullptr);
+        if (maxdout > 64)
+            k_engine_block<R, 256, 9, 4, false, PeelCtx><<<1024, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
+                                                                                   0, ni + 1, nullptr);
         ctx.cls = 2;
-        k_engine_block<R, 768, 11, 12, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
-                                                                                0, ni + 2, nullptr);
+        if (maxdout > 256)
+            k_engine_block<R, 768, 11, 12, false, PeelCtx><<<512, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
+                                                                                    0, ni + 2, nullptr);
         ctx.cls = 3;
-        k_engine_block<R, 1280, 12, 20, true, PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
-                                                                                0, ni + 3, gS);
+        if (maxdout > 768)
+            k_engine_block<R, 1280, 12, 20, true, PeelCtx><<<256, BLOCK, 0, s>>>(ctx, b.row_ptr, b.col, b.dag_off,
+                                                                                    0, ni + 3, gS);
     }
 }
 
@@ -2578,6 +2643,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     const int R = h - 2;
     u64 *gS = nullptr;
     if (h >= 4) {
+        // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK4
+        b.bcap = (int64_t)n + 2 * g.m / CHUNK4 + 1;
+        b.B = sc.get_n<int64_t>(2 * b.bcap);
         // every (v, w) item is an arc of the frontier's adjacency; a round holds at most 2m of them
         b.item_cap = 2 * g.m + 1;
         b.item_v = sc.get_n<int32_t>(5 * b.item_cap);
@@ -2600,6 +2668,18 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     int64_t n_alive = pinned[0];
+    if (h >= 4 && n_alive > 0) {
+        // the edges among the starting vertices, at most half the slots filled
+        const int64_t pairs = n_alive * (n_alive - 1) / 2;
+        const int64_t edges = std::max<int64_t>(1, std::min<int64_t>(g.m, pairs));
+        int bits = 10;
+        while (((int64_t)1 << bits) < 2 * edges) bits++;
+        u64 *t = sc.get_n<u64>((int64_t)1 << bits);
+        fill_u64(t, ESET_EMPTY, (int64_t)1 << bits, s);
+        b.eset = t;
+        b.eset_bits = bits;
+        k_eset_fill<<<grid_for(n_alive, WAVES_PER_BLOCK, 8192), BLOCK, 0, s>>>(b, b.lists, &b.ctl->nlist[0], t);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (kt) {
         DSD_HIP(hipEventCreate(&e0));
@@ -2652,9 +2732,9 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
-                    case 2: launch_peel_items<2>(b, s, gS); break;
-                    case 3: launch_peel_items<3>(b, s, gS); break;
-                    case 4: launch_peel_items<4>(b, s, gS); break;
+                    case 2: launch_peel_items<2>(b, s, gS, g.maxdout); break;
+                    case 3: launch_peel_items<3>(b, s, gS, g.maxdout); break;
+                    case 4: launch_peel_items<4>(b, s, gS, g.maxdout); break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
             }

@@ -1,13 +1,23 @@
-// dsd_server_*: a request queue served through the batch path by two worker
-// threads, one for graphs below LARGE_EDGES edges and one for larger ones.
-// A worker takes, in arrival order, queued requests of its class with the
-// first one's op whose graphs are distinct and whose estimated device
-// footprints fit what the budget leaves, runs them as one batch (a large
-// graph alone) and completes their tickets.
+// dsd_server_*: continuous batching of densest-subgraph queries.
+//
+// A server owns WORKERS worker threads, each with a non-blocking HIP stream
+// of its own (default priority).  A worker that is free takes the next work
+// from the queue at once: the oldest queued request, and with it, when that
+// request is on a small graph, every other queued small request with the same
+// op and h on a distinct graph whose device footprint still fits the budget
+// (at most MAX_GROUP); a request on a large graph runs alone.  The group runs
+// through the batch path on the worker's stream: every handle of the group is
+// switched to that stream for the run and switched back afterwards.  So
+// requests that arrive while others are on the GPU start as soon as a worker
+// and enough of the budget are free, and the groups of different workers
+// overlap on the device.  At most WORKERS - 1 workers hold large requests at
+// a time, so small requests never wait behind large ones alone.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <thread>
@@ -21,7 +31,8 @@ namespace {
 constexpr size_t BYTES_PER_VERTEX = 160;
 constexpr size_t BYTES_PER_EDGE = 192;
 constexpr size_t MAX_GROUP = 4096;
-constexpr int64_t LARGE_EDGES = (int64_t)1 << 20;   // requests on larger graphs go to the second worker
+constexpr int64_t LARGE_EDGES = (int64_t)1 << 20;   // a request on a larger graph runs alone
+constexpr int WORKERS_DEFAULT = 4;
 
 enum class St { QUEUED, RUNNING, DONE, CANCELED };
 
@@ -32,6 +43,12 @@ struct Req {
     void *out;
     size_t foot;
 };
+
+int workers_wanted() {
+    const char *e = std::getenv("DSD_SERVER_WORKERS");
+    const int w = e ? std::atoi(e) : WORKERS_DEFAULT;
+    return std::max(2, std::min(16, w));
+}
 
 }  // namespace
 
@@ -46,31 +63,40 @@ struct dsd_server_s {
     uint64_t next_ticket = 1;
     int in_flight = 0;     // queued + running
     size_t running = 0;    // footprints of the groups being run
+    int large_running = 0; // workers holding a large request
     bool stop = false;
-    std::thread workers[2];
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
 
     static bool large(const Req &r) { return r.g->g.m >= LARGE_EDGES; }
 
-    bool has_class(bool lg) const {
-        for (const Req &r : queue)
-            if (large(r) == lg) return true;
-        return false;
-    }
-
-    // the next group of class lg that fits the budget left (mu held); empty if none
-    std::vector<Req> take(bool lg) {
+    // the next group a free worker can run (mu held); empty if none
+    std::vector<Req> take() {
         std::vector<Req> group;
-        int op = -1;
+        const int nw = (int)workers.size();
         size_t used = 0;
         std::set<dsd_graph> seen;
+        int op = -1, h = -1;
         for (auto it = queue.begin(); it != queue.end() && group.size() < MAX_GROUP;) {
-            if (large(*it) != lg) {
-                ++it;
+            const bool lg = large(*it);
+            if (group.empty()) {
+                // the oldest request that may start now leads the group
+                const bool fits = running + it->foot <= budget || running == 0;
+                if (!fits || (lg && large_running >= nw - 1)) {
+                    ++it;
+                    continue;
+                }
+                op = it->op;
+                h = it->h;
+                used = it->foot;
+                seen.insert(it->g);
+                state[it->ticket] = St::RUNNING;
+                group.push_back(*it);
+                it = queue.erase(it);
+                if (lg) break;                      // a large graph runs alone
                 continue;
             }
-            if (op < 0) op = it->op;
-            const bool fits = running + used + it->foot <= budget || (running == 0 && group.empty());
-            if (it->op == op && !seen.count(it->g) && fits) {
+            if (!lg && it->op == op && it->h == h && !seen.count(it->g) && running + used + it->foot <= budget) {
                 used += it->foot;
                 seen.insert(it->g);
                 state[it->ticket] = St::RUNNING;
@@ -79,29 +105,39 @@ struct dsd_server_s {
             } else {
                 ++it;
             }
-            if (lg && !group.empty()) break;    // a large graph runs alone
         }
         return group;
     }
 
-    void run(bool lg) {
+    void run(int w) {
+        hipStream_t ws = streams[w];
         while (true) {
             std::vector<Req> group;
             size_t foot = 0;
+            bool lg = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
-                    if (stop && !has_class(lg)) return true;
-                    group = take(lg);
+                    if (stop && queue.empty()) return true;
+                    group = take();
                     return !group.empty();
                 });
-                if (group.empty()) return;          // stopping, nothing of this class queued
+                if (group.empty()) return;          // stopping, nothing queued
                 for (const Req &r : group) foot += r.foot;
+                lg = large(group[0]);
                 running += foot;
+                large_running += lg ? 1 : 0;
             }
             const int32_t cnt = (int32_t)group.size();
             std::vector<dsd_result> res(cnt);
-            // one op per group; requests with host and with device outputs go in two calls
+            // the group runs on this worker's stream
+            std::vector<hipStream_t> own(cnt);
+            for (int32_t i = 0; i < cnt; i++) {
+                own[i] = group[i].g->stream;
+                (void)hipStreamSynchronize(own[i]);
+                group[i].g->stream = ws;
+            }
+            // requests with host and with device outputs go in two calls
             for (int pass = 0; pass < 2; pass++) {
                 const int mem = pass == 0 ? DSD_MEM_HOST : DSD_MEM_DEVICE;
                 std::vector<int32_t> sel;
@@ -117,16 +153,19 @@ struct dsd_server_s {
                     h2.push_back(group[i].h);
                     o2.push_back(group[i].out);
                 }
-                dsd_status st = dsd_batch_run((int32_t)sel.size(), g2.data(), h2.data(), group[0].op, mem, o2.data(),
-                                              r2.data());
+                const dsd_status st = dsd_batch_run((int32_t)sel.size(), g2.data(), h2.data(), group[0].op, mem,
+                                                    o2.data(), r2.data());
                 for (size_t j = 0; j < sel.size(); j++) {
                     res[sel[j]] = r2[j];
                     if (st == DSD_EINVAL) res[sel[j]].status = DSD_EINVAL;
                 }
             }
+            (void)hipStreamSynchronize(ws);
+            for (int32_t i = 0; i < cnt; i++) group[i].g->stream = own[i];
             {
                 std::lock_guard<std::mutex> lk(mu);
                 running -= foot;
+                large_running -= lg ? 1 : 0;
                 for (int32_t i = 0; i < cnt; i++) {
                     state[group[i].ticket] = St::DONE;
                     done[group[i].ticket] = res[i];
@@ -149,12 +188,22 @@ dsd_status dsd_server_create(size_t hbm_budget_bytes, int max_slots, dsd_server 
     if (hbm_budget_bytes == 0 || max_slots <= 0) return fail(DSD_EINVAL, "budget and slots must be positive");
     DSD_TRY({
         check_device();
-        dsd_server_s *s = new dsd_server_s();
+        std::unique_ptr<dsd_server_s> s(new dsd_server_s());
         s->budget = hbm_budget_bytes;
         s->max_slots = max_slots;
-        s->workers[0] = std::thread([s] { s->run(false); });
-        s->workers[1] = std::thread([s] { s->run(true); });
-        *out = s;
+        const int nw = workers_wanted();
+        for (int w = 0; w < nw; w++) {
+            hipStream_t st = nullptr;
+            const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+                throw Error(DSD_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+            }
+            s->streams.push_back(st);
+        }
+        dsd_server_s *p = s.release();
+        for (int w = 0; w < nw; w++) p->workers.emplace_back([p, w] { p->run(w); });
+        *out = p;
         return DSD_OK;
     })
 }
@@ -174,7 +223,7 @@ dsd_status dsd_server_submit(dsd_server s, dsd_graph g, int h, int op, int out_m
     s->state[t] = St::QUEUED;
     s->in_flight++;
     *ticket = t;
-    s->cv_work.notify_all();    // two workers: wake the one of this request's class
+    s->cv_work.notify_one();
     return DSD_OK;
 }
 
@@ -232,6 +281,7 @@ dsd_status dsd_server_destroy(dsd_server s) {
     s->cv_done.notify_all();
     for (std::thread &w : s->workers)
         if (w.joinable()) w.join();
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return DSD_OK;
 }

@@ -64,7 +64,10 @@ class Stats(C.Structure):
                 ("t_flow_setup_ms", C.c_double), ("flow_gpu_networks", C.c_uint64),
                 ("k4_tail_ms", C.c_double), ("k4_tail_launches", C.c_uint64), ("k4_tail_pairs", C.c_uint64),
                 ("k4_tail_vertices", C.c_uint64), ("k4_tail_grid_ms", C.c_double),
-                ("k4_tail_grid_rounds", C.c_uint64), ("k4_tail_grid_pairs", C.c_uint64)]
+                ("k4_tail_grid_rounds", C.c_uint64), ("k4_tail_grid_pairs", C.c_uint64),
+                ("locate_rho1_num", C.c_uint64), ("locate_rho1_den", C.c_uint64), ("locate_k1", C.c_uint64),
+                ("locate_rho2_num", C.c_uint64), ("locate_rho2_den", C.c_uint64), ("locate_k2", C.c_uint64),
+                ("locate_components", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -285,3 +285,82 @@ def test_batch_triangles_without_lists(monkeypatch):
         mem_o, rho_o, steps_o, _ = oracle.Graph(n, s, d).peel_app(3)
         assert r["status"] == 0 and r["density"] == rho_o and r["peel_rounds"] == steps_o
         np.testing.assert_array_equal(out[:n].astype(bool), mem_o)
+
+
+def test_server_staggered_arrivals_match_single_calls_and_oracle():
+    """Continuous batching: requests of mixed h (2, 3, 4), op and size arrive
+    one by one while earlier ones run on the server's workers (each with its
+    own stream).  Every result must be the one the request's single-graph
+    entry point gives alone, and the oracle's."""
+    import threading
+    rng = np.random.default_rng(11)
+    graphs = mixed_graphs(5, count=30)
+    # two graphs above 2^20 edges: they run alone, beside the small groups
+    for k in range(2):
+        graphs.append(synth.chung_lu(n=150_000, avg_deg=16, beta=2.3, planted=1, plant_size=60, p=0.7, seed=40 + k))
+    ops = ["core", "app", "exact", "degrees", "peel"]
+    reqs = []
+    for i, (n, s, d) in enumerate(graphs):
+        h = int(rng.integers(2, 5))
+        op = ops[i % len(ops)]
+        if n >= 100_000 and op in ("exact", "peel", "degrees"):
+            op = "core"
+        reqs.append((i, h, op))
+    handles = build_all(graphs)
+    outs = [np.zeros(max(graphs[i][0], 1), np.uint64 if op in ("degrees", "core") else np.uint8)
+            for i, h, op in reqs]
+    srv = dsd.Server(1 << 36, 64)
+    tickets = [None] * len(reqs)
+
+    def submitter():
+        for j, (i, h, op) in enumerate(reqs):
+            tickets[j] = srv.submit(handles[i], h, op, outs[j])
+            time.sleep(float(rng.uniform(0.0, 0.01)))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = [None] * len(reqs)
+    for j in range(len(reqs)):
+        while tickets[j] is None:
+            time.sleep(0.001)
+        st, r = srv.wait(tickets[j])
+        assert st == 0 and r["status"] == 0, (j, reqs[j], r)
+        results[j] = r
+    th.join()
+    srv.close()
+    for j, (i, h, op) in enumerate(reqs):
+        n, s, d = graphs[i]
+        g1 = dsd.build_csr(n, s, d)                 # the single call, alone, on a fresh handle
+        r = results[j]
+        if op == "degrees":
+            deg1, mu1 = dsd.clique_degrees(g1, h)
+            np.testing.assert_array_equal(outs[j][:n], deg1[:n])
+            assert r["num_cliques"] == mu1
+        elif op == "core":
+            core1, km1 = dsd.clique_core(g1, h)
+            np.testing.assert_array_equal(outs[j][:n], core1[:n])
+            assert r["kmax"] == km1
+        elif op == "app":
+            mem1, km1, dens1 = dsd.core_app(g1, h)
+            np.testing.assert_array_equal(outs[j][:n], mem1[:n])
+            assert (r["kmax"], r["density"]) == (km1, dens1)
+        elif op == "peel":
+            mem1, rho1, rounds1, _ = dsd.peel_app(g1, h)
+            np.testing.assert_array_equal(outs[j][:n], mem1[:n])
+            assert r["density"] == rho1
+        else:
+            _, rho1 = dsd.core_exact(g1, h)
+            assert r["density"] == rho1
+        if n >= 100_000:
+            continue                                  # the oracle below: small graphs only
+        og = oracle.Graph(n, s, d)
+        if op == "degrees":
+            np.testing.assert_array_equal(outs[j][:n], og.clique_degrees(h)[0])
+        elif op == "core":
+            np.testing.assert_array_equal(outs[j][:n], og.core_decomposition(h)[0])
+        elif op == "app":
+            np.testing.assert_array_equal(outs[j][:n].astype(bool), og.inc_app(h)[0])
+        elif op == "peel":
+            assert r["density"] == og.peel_app(h)[1]
+        else:
+            assert r["density"] == og.exact(h, "core")[1]

@@ -37,13 +37,23 @@ def induced_mu(og, h, mask):
     return sub.clique_degrees(h)[1]
 
 
-@pytest.mark.timeout(600)
-def test_chung_lu_1e6_triangles_whole_graph():
+@pytest.fixture(scope="module")
+def chung_lu_1e6():
+    """The benchmark's Chung-Lu graph on the GPU (edge list read from device
+    memory, as the benchmark does) and in the oracle, with the oracle's core
+    numbers at h = 3 (computed once for the tests below)."""
     torch = pytest.importorskip("torch")
-    h = 3
     n, s, d = synth.chung_lu(seed=1, **CHUNG_LU_1E6)
-    # the library reads the edge list from device memory, as the benchmark does
     g = dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    og = oracle.Graph(n, s, d)
+    core_o, km_o = og.core_decomposition(3)
+    return n, g, og, core_o, km_o
+
+
+@pytest.mark.timeout(600)
+def test_chung_lu_1e6_triangles_whole_graph(chung_lu_1e6):
+    h = 3
+    n, g, og, core_o, km_o = chung_lu_1e6
     deg_g, mu_g = dsd.clique_degrees(g, h)
     core_g, km_g = dsd.clique_core(g, h)
     mem_app, km_app, dens_app = dsd.core_app(g, h)
@@ -52,11 +62,9 @@ def test_chung_lu_1e6_triangles_whole_graph():
     print(f"gpu: mu={mu_g} kmax={km_g} rho_app={dens_app} rho_opt={rho} "
           f"peel_app={rho_p} rounds={rounds_p} best_round={best_p}", flush=True)
 
-    og = oracle.Graph(n, s, d)
     deg_o, mu_o = og.clique_degrees(h)
     assert mu_g == mu_o
     np.testing.assert_array_equal(deg_g, deg_o)
-    core_o, km_o = og.core_decomposition(h)
     assert km_g == km_o
     np.testing.assert_array_equal(core_g, core_o)
 
@@ -77,6 +85,45 @@ def test_chung_lu_1e6_triangles_whole_graph():
     lv, rs, rm = og.level_table(h, core_o)
     rho1 = max(Fraction(int(m), int(z)) for m, z in zip(rm, rs) if z)
     assert rho1 <= rho_p <= rho <= h * rho_p
+
+
+@pytest.mark.timeout(900)
+def test_chung_lu_1e6_core_exact_certified(chung_lu_1e6):
+    """CoreExact's rho_opt on the benchmark graph, pinned exactly.
+
+    The locate step's figures (Pruning1/2, Section 6.1: rho', k', rho'',
+    k'', the number of components of R_{k'}) must equal the oracle's locate
+    on the oracle's core numbers.  Then one strict test of the oracle
+    (Algorithm 1's network, Lemma 14) on G[R_c], c = ceil(rho), at alpha =
+    rho must find nothing denser: by Lemma 7 every subgraph denser than rho
+    would have its densest subgraph inside R_{ceil(rho_opt)}, which lies in
+    R_c.  With the returned set attaining rho, rho = rho_opt."""
+    h = 3
+    n, g, og, core_o, km_o = chung_lu_1e6
+    mem_x, rho = dsd.core_exact(g, h)
+    st = g.stats()
+    loc = og.locate(h, core_o)
+    print(f"gpu locate: rho'={st['locate_rho1_num']}/{st['locate_rho1_den']} k'={st['locate_k1']} "
+          f"rho''={st['locate_rho2_num']}/{st['locate_rho2_den']} k''={st['locate_k2']} "
+          f"components={st['locate_components']} located={st['located_vertices']}; oracle {loc['rho1']} "
+          f"{loc['k1']} {loc['rho2']} {loc['k2']} {loc['ncomp']}", flush=True)
+    assert Fraction(st["locate_rho1_num"], st["locate_rho1_den"]) == loc["rho1"]
+    assert st["locate_k1"] == loc["k1"]
+    assert Fraction(st["locate_rho2_num"], st["locate_rho2_den"]) == loc["rho2"]
+    assert st["locate_k2"] == loc["k2"]
+    assert st["locate_components"] == loc["ncomp"]
+    assert st["located_vertices"] == int((core_o >= loc["k2"]).sum())
+
+    sel = mem_x.astype(bool)
+    assert Fraction(induced_mu(og, h, sel), int(sel.sum())) == rho
+    c = math.ceil(rho)
+    mask = core_o >= c
+    assert not (sel & ~mask).any()
+    idx, s2, d2 = induced(og, mask)
+    sub = oracle.Graph(idx.size, s2, d2)
+    found, _ = sub.denser_than(h, rho)
+    print(f"certificate: G[R_{c}] has {idx.size} vertices, {sub.m} edges; denser than {rho}: {found}", flush=True)
+    assert not found
 
 
 # ------------------------------------------------------------------ R-MAT scale 22, h = 4 and 5
