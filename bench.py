@@ -4,11 +4,21 @@
 One step = one pass of every stage over one synthetic graph whose edge list
 is already resident in HBM: CSR build and degree-ordered orientation, clique
 enumeration (clique-degrees), the (k, Psi)-core peel, CoreApp, and CoreExact
-(locating on the GPU, exact minimum cuts on the host).  CoreExact reuses the
-decomposition the handle already holds from the clique-core call.  The workload is a
-Chung-Lu power-law graph, n = 1,000,000, average degree 20, exponent 2.1,
-with 5 planted 200-vertex blocks at pair probability 0.7, and the triangle
-(h = 3) as the clique.
+(locating on the GPU, then the exact search with minimum cuts).  CoreExact
+reuses the decomposition the handle already holds from the clique-core call.
+
+The headline workload is the largest single-GPU configuration: an R-MAT graph
+of scale 22 (4,194,304 vertices, 67,108,864 edge draws, (a, b, c, d) =
+(0.57, 0.19, 0.19, 0.05), duplicates and self-loops removed) with the
+4-clique as the pattern.  Its located core holds about 3.4e10 4-cliques, so
+the exact step's flow network (about four arcs per clique) cannot be built
+in device memory; the library refuses it with DSD_EUNSUPPORTED after the
+locate step, and the step records that refusal.
+
+Further legs: the same graph at h = 5, the Chung-Lu graph (n = 10^6, h = 3,
+where CoreExact runs to the end), the batched mixture (8,192 graphs, batched
+vs a plain per-graph loop), the server under load, and the CPU oracle on a
+bounded sample of the headline family.
 
 Prints one JSON line.  ``value`` is whole-pass throughput in h-cliques/s
 (mu(G, Psi) divided by the time of one step).
@@ -28,11 +38,24 @@ METRIC = "h-cliques/s + peel edges/s on 1 GPU, %HBM peak; batched & served vs pl
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    # the configuration the metric is quoted on
+    # the largest single-GPU configuration: the headline
+    "rmat22_h4": dict(gen="rmat", h=4, kw=dict(scale=22, edge_factor=16)),
+    "rmat22_h5": dict(gen="rmat", h=5, kw=dict(scale=22, edge_factor=16)),
+    # triangle density on a power-law graph
     "chung_lu_1e6": dict(gen="chung_lu", h=3, kw=dict(n=1_000_000, avg_deg=20.0, beta=2.1, planted=5,
                                                      plant_size=200, p=0.7)),
     # the small configuration (quick runs)
     "er_2000": dict(gen="er_planted", h=2, kw=dict(n=2000, m=10000, plant=60, p=0.4)),
+}
+
+# the paper's own figures, quoted with the hardware it states (context only:
+# other machine, other graphs; the paper prints no absolute time for h >= 3)
+PAPER_FIGURES = {
+    "hardware": "Java; Intel Xeon 3.40 GHz, 16 cores, 125 GB RAM (section 8, setup)",
+    "core_app_h2_s": {"DBLP": 0.077, "Cit-Patents": 1.021, "Friendster": 2.986, "Enwiki-2017": 8.139,
+                      "UK-2002": 5.825},
+    "core_app_vs_peel_app_triangle": {"SSCA n=1e5": 20, "R-MAT n=1e5": 201},
+    "note": "CoreApp wall times at h = 2 from the paper's EMcore comparison table; speed-ups from section 8",
 }
 
 
@@ -43,25 +66,17 @@ def make_graph(name: str, seed: int):
 
 
 def k3_bytes(st: dict) -> float:
-    """Algorithmic bytes of one whole-graph clique-degree pass (h = 3): every
+    """Algorithmic bytes of one whole-graph clique-degree pass: every
     directed 2-path r -> v -> x reads one out-list entry (4 B), plus per edge
     the row pointers / staged out-list / flushed counters (24 B) and 8 B of
-    output per vertex."""
+    output per vertex.  The same bytes hold for h >= 4: the deeper levels run
+    in LDS bitmaps built from those reads."""
     return 4.0 * st["w2"] + 24.0 * st["m"] + 8.0 * st["n"]
 
 
-def k4_bytes(st: dict, h: int) -> float:
-    """Algorithmic bytes of one full peel: h = 3 reads the out-list of every
-    neighbour of every removed vertex (4 B per entry of sum_v deg(v) d+(v)),
-    stages N(v) (8 B per edge) and decrements survivors (16 B per edge);
-    h = 2 touches every edge from both ends (32 B per edge)."""
-    if h == 2:
-        return 32.0 * st["m"]
-    return 4.0 * st["s2"] + 24.0 * st["m"]
-
-
 # the peel's main kernel by the kind the library reports
-MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process", 4: "k_star_front"}
+MAIN_KERNEL = {1: "k_process_h2", 2: "k_h3_probe", 3: "k_tl_process", 4: "k_star_front", 6: "k_root_edges"}
+MAIN2_KERNEL = {6: "k_root_count"}
 
 
 def main_kernel_bytes(st: dict) -> float:
@@ -74,25 +89,50 @@ def main_kernel_bytes(st: dict) -> float:
     N+(w) (4 + 8 + 8 B).  Edge pass (k_process_h2, h = 2): every walked
     adjacency entry costs its column entry, the neighbour's stamp and an
     8-byte read-modify-write of its degree (4 + 4 + 16 B), every frontier
-    vertex its two row offsets (16 B)."""
+    vertex its two row offsets (16 B).  Arc discovery of h >= 4
+    (k_root_edges): every row entry of a removed vertex its column entry and
+    the neighbour's stamp (4 + 4 B), every member of a candidate set C_v its
+    two row offsets (16 B), every probed out-list entry 4 B."""
     kind = st["k4_main_kind"]
     if kind == 1:
         return 24.0 * st["k4_main_pairs"] + 16.0 * st["k4_main_nbrs"]
     if kind == 3:
         return 16.0 * st["k4_main_pairs"] + 24.0 * st["k4_main_nbrs"]
+    if kind == 6:
+        return 8.0 * st["k4_main_entries"] + 16.0 * st["k4_main_nbrs"] + 4.0 * st["k4_main_pairs"]
     return 4.0 * st["k4_main_pairs"] + 20.0 * st["k4_main_nbrs"]
+
+
+def main2_kernel_bytes(st: dict) -> float:
+    """Counting of h >= 4 (k_root_count): every member of a candidate set C_v
+    its stamp, and an 8-byte read-modify-write of its degree when it loses
+    cliques (4 + 16 B).  Its bitmap rows are scratch that stays in L2."""
+    return 20.0 * st["k4_main_nbrs"]
+
+
+def k4_bytes(st: dict, h: int) -> float:
+    """Algorithmic bytes of one full peel (the stage rate): h = 2 touches
+    every edge from both ends (32 B per edge); h = 3 reads the out-list of
+    every neighbour of every removed vertex (4 B per entry of
+    sum_v deg(v) d+(v)) and decrements survivors (24 B per edge); h >= 4
+    the bytes of its two kernels above."""
+    if h == 2:
+        return 32.0 * st["m"]
+    if h >= 4 and st["k4_main_kind"] == 6:
+        return main_kernel_bytes(st) + main2_kernel_bytes(st)
+    return 4.0 * st["s2"] + 24.0 * st["m"]
 
 
 TAIL_KERNEL = "k_tail_engine"
 
 
 def tail_kernel_bytes(st: dict) -> float:
-    """Algorithmic bytes of the h = 3 tail engine over one peel: every pair it
-    walks is one 4-byte word of the rewritten rows; every tail vertex costs its
-    degree and id in (8 + 4 B), its two row offsets (16 B), its id again and
-    its core number out (4 + 8 B); every round handed to the grid costs each
-    tail vertex its degree and state out (5 B) and back in with its row start
-    (13 B).  The degrees and states stay in LDS while the engine runs."""
+    """Algorithmic bytes of the tail engine (h = 2, 3) over one peel: every
+    pair it walks is one 4-byte word of the rewritten rows; every tail vertex
+    costs its degree and id in (8 + 4 B), its two row offsets (16 B), its id
+    again and its core number out (4 + 8 B); every round handed to the grid
+    costs each tail vertex its degree and state out (5 B) and back in with
+    its row start (13 B)."""
     return (4.0 * st["k4_tail_pairs"] + 40.0 * st["k4_tail_vertices"]
             + 18.0 * st["k4_tail_vertices"] * st["k4_tail_grid_rounds"])
 
@@ -120,13 +160,139 @@ def measured_traffic(kernel: str, workload: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def roof(kernel, workload, total_ms, launches, total_bytes):
+    launches = max(launches, 1)
+    bytes_call = total_bytes / launches
+    ms_call = total_ms / launches
+    achieved = bytes_call / (ms_call / 1e3) / 1e9 if ms_call > 0 else 0.0
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel, workload),
+            "bytes_per_launch": bytes_call, "ms_per_launch": ms_call, "launches_per_step": launches,
+            "ms_per_step": total_ms,
+            "timing": "HIP events around every launch of one extra step after the timed ones"}
+
+
+def run_workload(name: str, seed: int, steps: int, warmup: int):
+    """Timed steps of one workload; returns the record of the bench line."""
+    import numpy as np
+    import torch
+
+    from paper_1906_00341_amd import dsd
+
+    (n, src, dst), h = make_graph(name, seed)
+    dev = torch.device("cuda:0")
+    ts = torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev)
+    td = torch.from_numpy(np.ascontiguousarray(dst, np.int32)).to(dev)
+    del src, dst
+    core_t = torch.zeros(n, dtype=torch.uint64, device=dev)
+    app_t = torch.zeros(n, dtype=torch.uint8, device=dev)
+    exact_t = torch.zeros(n, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step(time_kernels=False):
+        rec = {}
+        g = dsd.build_csr(n, ts, td)
+        rec["build"] = g.stats()
+        g.set_kernel_timing(time_kernels)
+        _, km = dsd.clique_core(g, h, out=core_t)
+        rec["core"] = g.stats()
+        rec["kmax"] = km
+        _, km2, dens = dsd.core_app(g, h, out=app_t)
+        rec["app"] = g.stats()
+        rec["app_density"] = dens
+        try:
+            _, rho = dsd.core_exact(g, h, out=exact_t)
+            rec["rho"] = str(rho)
+        except dsd.DsdError as e:
+            if e.status != -5:
+                raise
+            rec["rho"] = None
+        rec["exact"] = g.stats()
+        rec["m"] = g.info()[1]
+        g.free()
+        return rec
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / steps
+    # one more step, right after the timed ones, with every launch of the
+    # peel's main kernels bracketed by HIP events on the graph's stream (each
+    # bracketed launch costs the host ~20 us, so the timed steps run without)
+    inst = step(time_kernels=True)["core"]
+
+    core = recs[-1]["core"]
+    ex = recs[-1]["exact"]
+    mu = core["num_cliques"]
+    avg = lambda key, stage: sum(r[stage][key] for r in recs) / len(recs)
+    k3_ms = avg("k3_ms", "core")
+    k4_ms = avg("k4_ms", "core")
+    kind = inst["k4_main_kind"]
+    cands = [roof(MAIN_KERNEL.get(kind), name, inst["k4_main_ms"], inst["k4_main_launches"],
+                  main_kernel_bytes(inst))]
+    cands[0].update({"pairs_per_step": inst["k4_main_pairs"], "members_per_step": inst["k4_main_nbrs"],
+                     "row_entries_per_step": inst["k4_main_entries"]})
+    if kind in MAIN2_KERNEL:
+        r2 = roof(MAIN2_KERNEL[kind], name, inst["k4_main2_ms"], inst["k4_main2_launches"],
+                  main2_kernel_bytes(inst))
+        r2.update({"members_per_step": inst["k4_main_nbrs"]})
+        cands.append(r2)
+    if inst["k4_tail_launches"]:
+        t = roof(TAIL_KERNEL, name, inst["k4_tail_ms"], inst["k4_tail_launches"], tail_kernel_bytes(inst))
+        t.update({"pairs_per_step": inst["k4_tail_pairs"], "tail_vertices": inst["k4_tail_vertices"],
+                  "grid_rounds": inst["k4_tail_grid_rounds"], "grid_pairs": inst["k4_tail_grid_pairs"],
+                  "grid_ms": inst["k4_tail_grid_ms"]})
+        cands.append(t)
+    cands.sort(key=lambda r: -r["ms_per_step"])
+    located = {"vertices": ex["located_vertices"],
+               "rho1": f"{ex['locate_rho1_num']}/{ex['locate_rho1_den']}", "k1": ex["locate_k1"],
+               "rho2": f"{ex['locate_rho2_num']}/{ex['locate_rho2_den']}", "k2": ex["locate_k2"],
+               "components": ex["locate_components"]}
+    return {
+        "value": mu / (ms_per_step / 1e3),
+        "ms_per_step": ms_per_step,
+        "config": {"workload": name, "h": h, "n": n, "m": recs[-1]["m"], "seed": seed, "num_cliques": mu,
+                   "kmax": recs[-1]["kmax"], "rho_app": str(recs[-1]["app_density"]),
+                   "rho_opt": recs[-1]["rho"] if recs[-1]["rho"] is not None else
+                   "refused: the located core's flow network does not fit (DSD_EUNSUPPORTED)",
+                   "located": located},
+        "stages_ms": {
+            "build_orient": avg("t_total_ms", "build"),
+            "clique_degrees": avg("t_enum_ms", "core"),
+            "peel": avg("t_peel_ms", "core"),
+            "core_app": avg("t_total_ms", "app"),
+            "core_exact_locate_gpu": avg("t_locate_ms", "exact"),
+            "core_exact_network": avg("t_flow_build_ms", "exact"),
+            "core_exact_maxflow": avg("t_flow_ms", "exact"),
+            "core_exact_flow_setup": avg("t_flow_setup_ms", "exact"),
+            "core_exact_search": avg("t_exact_ms", "exact"),
+            "core_exact_total": avg("t_total_ms", "exact"),
+        },
+        "kernel_rates": {
+            "enum_h_cliques_per_s": mu / (k3_ms / 1e3) if k3_ms else None,
+            "peel_edges_per_s": recs[-1]["m"] / (k4_ms / 1e3) if k4_ms else None,
+            "peel_cliques_per_s": mu / (k4_ms / 1e3) if k4_ms else None,
+            "peel_rounds": core["peel_rounds"], "peel_levels": core["peel_levels"],
+            "enum_hbm_frac": k3_bytes(core) / (k3_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k3_ms else None,
+            "peel_hbm_frac": k4_bytes(inst, h) / (k4_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k4_ms else None,
+        },
+        "roofline": cands[0],
+        "roofline_other": cands[1:],
+    }
+
+
 def cpu_baseline(workload: str, seed: int):
-    """The CPU oracle, single-threaded, on a bounded sample of the same
-    workload.  Chung-Lu: the same generator at n = 600,000 (same degree law
-    and planted blocks), clique-degrees + core decomposition + CoreApp; the
-    oracle's exact step (Dinic on 128-bit capacities over the whole located
-    core) alone runs for many minutes on this graph family, so it is left out
-    of the sample.  ER: the whole 2,000-vertex graph and the whole path."""
+    """The CPU oracle, single-threaded, on a bounded sample of the workload's
+    family.  R-MAT: the same generator at scale 14 (16,384 vertices),
+    clique-degrees + core decomposition + CoreApp at the workload's h.
+    Chung-Lu: the same generator at n = 600,000, the same stages.  ER: the
+    whole 2,000-vertex graph and the whole path."""
     import oracle
     from paper_1906_00341_amd import synth
     w = WORKLOADS[workload]
@@ -134,9 +300,11 @@ def cpu_baseline(workload: str, seed: int):
     if workload == "er_2000":
         n, s, d = synth.er_planted(seed=seed, **w["kw"])
         stages = "clique-degrees + core decomposition + CoreApp + CoreExact"
+    elif w["gen"] == "rmat":
+        n, s, d = synth.rmat(seed=seed, **dict(w["kw"], scale=14))
+        stages = "clique-degrees + core decomposition + CoreApp"
     else:
-        kw = dict(w["kw"], n=600_000)
-        n, s, d = synth.chung_lu(seed=seed, **kw)
+        n, s, d = synth.chung_lu(seed=seed, **dict(w["kw"], n=600_000))
         stages = "clique-degrees + core decomposition + CoreApp"
     g = oracle.Graph(n, s, d)
     t0 = time.perf_counter()
@@ -147,30 +315,51 @@ def cpu_baseline(workload: str, seed: int):
         g.exact(h, "core")
     t = time.perf_counter() - t0
     return {"value": mu / t, "unit": "h-cliques/s", "cores": 1, "kind": "oracle",
-            "sample": f"{workload} generator at n={n} (m={g.m}, mu={mu}); {stages}; {t:.2f} s, one thread"}
+            "sample": f"{w['gen']} generator of {workload} at n={n} (m={g.m}, h={h}, mu={mu}); {stages}; "
+                      f"{t:.2f} s, one thread"}
+
+
+def _batch_graphs(specs, threads=16):
+    import concurrent.futures as cf
+    from paper_1906_00341_amd import synth
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(synth.batch_graph, specs))
 
 
 def batch_leg(n_graphs: int, seed: int):
-    """Batched vs plain on a bounded sample of the batched mixture (n
-    log-uniform in [100, 50000], Chung-Lu exponent U[2, 3], average degree
-    U[4, 40], h in {2, 3, 4}): the first n_graphs graphs of the 8192-graph
-    mixture.  Op: the (k, Psi)-core decomposition.  Plain = one
-    dsd_clique_core call per graph; batched = one dsd_batch_run."""
+    """Batched vs plain on the batched mixture (n log-uniform in [100,
+    50000], Chung-Lu exponent U[2, 3], average degree U[4, 40], h in {2, 3,
+    4}): the first n_graphs graphs of the 8192-graph mixture.  Op: the (k,
+    Psi)-core decomposition.  Plain = one dsd_clique_core call per graph;
+    batched = one dsd_batch_run over all of them."""
     import torch
     from paper_1906_00341_amd import dsd, synth
     specs = synth.batch_specs(count=8192, seed=seed)[:n_graphs]
-    graphs = [synth.batch_graph(sp) for sp in specs]
     hs = [sp["h"] for sp in specs]
+    t0 = time.perf_counter()
+    graphs = _batch_graphs(specs)
+    t_gen = time.perf_counter() - t0
     handles = []
     for n, s, d in graphs:
         handles.append(dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()))
+    del graphs
     torch.cuda.synchronize()
     mu = 0
     t0 = time.perf_counter()
     for g, h in zip(handles, hs):
-        _, km = dsd.clique_core(g, h)
+        dsd.clique_core(g, h)
         mu += g.stats()["num_cliques"]
     t_plain = time.perf_counter() - t0
+    # every graph again, from scratch: the batch must not reuse the plain
+    # loop's cached decompositions
+    for g in handles:
+        g.free()
+    handles = []
+    graphs = _batch_graphs(specs)
+    for n, s, d in graphs:
+        handles.append(dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()))
+    del graphs
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = dsd.batch_run(handles, hs, "core")
     t_batch = time.perf_counter() - t0
@@ -183,18 +372,19 @@ def batch_leg(n_graphs: int, seed: int):
             "plain_s": t_plain, "batched_s": t_batch,
             "plain_graphs_per_s": n_graphs / t_plain, "batched_graphs_per_s": n_graphs / t_batch,
             "plain_h_cliques_per_s": mu / t_plain, "batched_h_cliques_per_s": mu / t_batch,
-            "speedup": t_plain / t_batch,
-            "peel_rounds_batched": max(r["peel_rounds"] for r in res)}
+            "batched_edges_per_s": m / t_batch, "speedup": t_plain / t_batch,
+            "peel_rounds_batched": max(r["peel_rounds"] for r in res), "generation_s": t_gen}
 
 
 def serve_leg(n_requests: int, seed: int):
     """The server under load: requests drawn 95 % from the batched mixture and
     5 % from R-MAT scale 20 (a = 0.57, b = c = 0.19), h in {2, 3, 4}, ops 70 %
-    CoreApp, 20 % core decomposition, 10 % CoreExact (R-MAT requests: CoreApp
-    only, whose cost does not depend on the located core).  Pass 1 submits
-    everything at once (saturation throughput); pass 2 submits with Poisson
-    arrivals at half that rate and records each request's latency.  Plain =
-    the same requests as sequential single-graph calls."""
+    CoreApp, 20 % core decomposition, 10 % CoreExact, on every graph kind.
+    Pass 1 submits everything at once (saturation throughput); pass 2 submits
+    with Poisson arrivals at half that rate and records each request's
+    latency.  Plain = the same requests as sequential single-graph calls.  A
+    request the library refuses (an exact step whose network would not fit)
+    is counted apart, not as served."""
     import concurrent.futures as cf
     import numpy as np
     import torch
@@ -202,28 +392,34 @@ def serve_leg(n_requests: int, seed: int):
     rng = np.random.default_rng(seed)
     specs = synth.batch_specs(count=8192, seed=seed + 1)
     n_rmat = max(1, n_requests // 20)
+    rmat_graph = synth.rmat(scale=20, edge_factor=16, seed=seed)
+    small = _batch_graphs([specs[i] for i in range(n_requests)])
     reqs = []
-    rn, rs, rd = synth.rmat(scale=20, edge_factor=16, seed=seed)
-    rmat_graph = (rn, rs, rd)
     for i in range(n_requests):
+        u = rng.random()
+        op = "app" if u < 0.7 else ("core" if u < 0.9 else "exact")
         if i < n_rmat:
-            reqs.append((rmat_graph, int(rng.integers(2, 5)), "app"))
+            reqs.append((rmat_graph, int(rng.integers(2, 5)), op))
         else:
-            sp = specs[i]
-            u = rng.random()
-            op = "app" if u < 0.7 else ("core" if u < 0.9 else "exact")
-            reqs.append((synth.batch_graph(sp), sp["h"], op))
+            reqs.append((small[i], specs[i]["h"], op))
     order = rng.permutation(n_requests)
     reqs = [reqs[i] for i in order]
+    calls = {"app": dsd.core_app, "core": dsd.clique_core, "exact": dsd.core_exact}
 
     def build():
         return [dsd.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()) for (n, s, d), _, _ in reqs]
 
     handles = build()
     torch.cuda.synchronize()
+    refused_plain = 0
     t0 = time.perf_counter()
     for g, (_, h, op) in zip(handles, reqs):
-        {"app": dsd.core_app, "core": dsd.clique_core, "exact": dsd.core_exact}[op](g, h)
+        try:
+            calls[op](g, h)
+        except dsd.DsdError as e:
+            if e.status != -5:
+                raise
+            refused_plain += 1
     t_plain = time.perf_counter() - t0
     for g in handles:
         g.free()
@@ -256,18 +452,24 @@ def serve_leg(n_requests: int, seed: int):
             outs = [f.result() for f in futs]
             total = time.perf_counter() - start
         assert all(st == 0 and r["status"] in (0, -5) for st, r in outs)
+        refused = sum(1 for _, r in outs if r["status"] == -5)
         for g in hs:
             g.free()
-        return total, lat
+        served = [lat[i] for i, (_, r) in enumerate(outs) if r["status"] == 0]
+        return total, served, refused
 
-    t_sat, _ = run(None)
-    qps_sat = n_requests / t_sat
-    t_half, lat = run(0.5 * qps_sat)
+    t_sat, _, refused = run(None)
+    served_n = n_requests - refused
+    qps_sat = served_n / t_sat
+    t_half, lat, _ = run(0.5 * n_requests / t_sat)
     srv.close()
     lat_ms = np.sort(np.asarray(lat)) * 1000.0
     return {"requests": n_requests, "rmat20_requests": n_rmat, "mix": "70% app / 20% core / 10% exact",
-            "plain_qps": n_requests / t_plain, "served_qps_saturation": qps_sat,
-            "offered_qps": 0.5 * qps_sat, "served_qps_at_offered": n_requests / t_half,
+            "workers": int(os.environ.get("DSD_SERVER_WORKERS", "4")),
+            "refused": refused, "refused_plain": refused_plain,
+            "plain_qps": (n_requests - refused_plain) / t_plain, "served_qps_saturation": qps_sat,
+            "overlap_speedup": (t_plain / t_sat), "offered_qps": 0.5 * n_requests / t_sat,
+            "served_qps_at_offered": served_n / t_half,
             "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99))}
 
 
@@ -276,10 +478,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_1e6", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat22_h4", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--legs", default="chung_lu_1e6:5,rmat22_h5:1",
+                    help="further workloads as name:steps, comma-separated ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-graphs", type=int, default=512,
+    ap.add_argument("--batch-graphs", type=int, default=8192,
                     help="graphs of the batched mixture in the batched-vs-plain leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=192,
                     help="requests in the serving leg (0: skip)")
@@ -288,124 +492,42 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is not sharded "
               f"across GPUs", file=sys.stderr)
         return 2
-    import numpy as np
-    import torch
-
-    from paper_1906_00341_amd import dsd
-
-    (n, src, dst), h = make_graph(args.workload, args.seed)
-    dev = torch.device("cuda:0")
-    ts = torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev)
-    td = torch.from_numpy(np.ascontiguousarray(dst, np.int32)).to(dev)
-    core_t = torch.zeros(n, dtype=torch.uint64, device=dev)
-    app_t = torch.zeros(n, dtype=torch.uint8, device=dev)
-    exact_t = torch.zeros(n, dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-
-    def step(time_kernels=False):
-        rec = {}
-        g = dsd.build_csr(n, ts, td)
-        rec["build"] = g.stats()
-        g.set_kernel_timing(time_kernels)
-        _, km = dsd.clique_core(g, h, out=core_t)
-        rec["core"] = g.stats()
-        rec["kmax"] = km
-        _, km2, dens = dsd.core_app(g, h, out=app_t)
-        rec["app"] = g.stats()
-        _, rho = dsd.core_exact(g, h, out=exact_t)
-        rec["exact"] = g.stats()
-        rec["rho"] = rho
-        rec["m"] = g.info()[1]
-        g.free()
-        return rec
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    recs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        recs.append(step())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / args.steps
-    # one more step, right after the timed ones, with every launch of the
-    # peel's main kernel bracketed by HIP events on the graph's stream (each
-    # bracketed launch costs the host ~20 us, so the timed steps run without)
-    inst = step(time_kernels=True)["core"]
-
-    core = recs[-1]["core"]
-    mu = core["num_cliques"]
-    avg = lambda key, stage: sum(r[stage][key] for r in recs) / len(recs)
-    k3_ms = avg("k3_ms", "core")
-    k4_ms = avg("k4_ms", "core")
-    # roofline of the peel's dominant kernel (the round kernels' main kernel or
-    # the tail engine, whichever took longer), every launch of the instrumented
-    # step timed with HIP events; the other one beside it
-    def roof(kernel, total_ms, launches, total_bytes):
-        launches = max(launches, 1)
-        bytes_call = total_bytes / launches
-        ms_call = total_ms / launches
-        achieved = bytes_call / (ms_call / 1e3) / 1e9 if ms_call > 0 else 0.0
-        return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel, args.workload),
-                "bytes_per_launch": bytes_call, "ms_per_launch": ms_call, "launches_per_step": launches,
-                "timing": "HIP events around every launch of one extra step after the timed ones"}
-
-    main_roof = roof(MAIN_KERNEL.get(inst["k4_main_kind"]), inst["k4_main_ms"], inst["k4_main_launches"],
-                     main_kernel_bytes(inst))
-    main_roof.update({"pairs_per_step": inst["k4_main_pairs"], "nbrs_per_step": inst["k4_main_nbrs"]})
-    tail_roof = roof(TAIL_KERNEL, inst["k4_tail_ms"], inst["k4_tail_launches"], tail_kernel_bytes(inst))
-    tail_roof.update({"pairs_per_step": inst["k4_tail_pairs"], "tail_vertices": inst["k4_tail_vertices"],
-                      "grid_rounds": inst["k4_tail_grid_rounds"], "grid_pairs": inst["k4_tail_grid_pairs"],
-                      "grid_ms": inst["k4_tail_grid_ms"]})
-    if inst["k4_tail_ms"] > inst["k4_main_ms"]:
-        dominant, other = tail_roof, main_roof
-    else:
-        dominant, other = main_roof, tail_roof
+    head = run_workload(args.workload, args.seed, args.steps, args.warmup)
     out = {
         "metric": METRIC,
-        "value": mu / (ms_per_step / 1e3),
+        "value": head["value"],
         "unit": "h-cliques/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "h": h, "n": n, "m": recs[-1]["m"], "seed": args.seed,
-                   "num_cliques": mu, "kmax": recs[-1]["kmax"], "rho_opt": str(recs[-1]["rho"])},
-        "stages_ms": {
-            "build_orient": avg("t_total_ms", "build"),
-            "clique_degrees": avg("t_enum_ms", "core"),
-            "peel": avg("t_peel_ms", "core"),
-            "core_app": avg("t_total_ms", "app"),
-            "core_exact_locate_gpu": avg("t_locate_ms", "exact"),
-            "core_exact_host_network": avg("t_flow_build_ms", "exact"),
-            "core_exact_host_maxflow": avg("t_flow_ms", "exact"),
-            "core_exact_flow_setup": avg("t_flow_setup_ms", "exact"),
-            "core_exact_search": avg("t_exact_ms", "exact"),
-            "core_exact_total": avg("t_total_ms", "exact"),
-        },
-        "kernel_rates": {
-            "enum_h_cliques_per_s": mu / (k3_ms / 1e3) if k3_ms else None,
-            "peel_edges_per_s": recs[-1]["m"] / (k4_ms / 1e3) if k4_ms else None,
-            "peel_rounds": core["peel_rounds"], "peel_levels": core["peel_levels"],
-            "enum_hbm_frac": k3_bytes(core) / (k3_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k3_ms else None,
-            "peel_hbm_frac": k4_bytes(core, h) / (k4_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k4_ms else None,
-        },
-        "roofline": dominant,
-        "roofline_other": other,
+        "config": head["config"],
+        "stages_ms": head["stages_ms"],
+        "kernel_rates": head["kernel_rates"],
+        "roofline": head["roofline"],
+        "roofline_other": head["roofline_other"],
     }
+    legs = {}
+    for spec in [x for x in args.legs.split(",") if x]:
+        name, _, k = spec.partition(":")
+        r = run_workload(name, args.seed, int(k or 1), 1)
+        legs[name] = {"value": r["value"], "unit": "h-cliques/s", "ms_per_step": r["ms_per_step"],
+                      "steps": int(k or 1), "config": r["config"], "stages_ms": r["stages_ms"],
+                      "kernel_rates": r["kernel_rates"], "roofline": r["roofline"]}
+    if legs:
+        out["legs"] = legs
     if args.batch_graphs > 0:
         out["batch"] = batch_leg(args.batch_graphs, 7)
     if args.serve_requests > 0:
         out["serve"] = serve_leg(args.serve_requests, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
+    out["paper_figures"] = PAPER_FIGURES
     print(json.dumps(out), flush=True)
     return 0
 

@@ -42,8 +42,9 @@ typedef enum {
     DSD_ENOMEM = -2,     /* device or host allocation failed */
     DSD_EDEVICE = -3,    /* HIP runtime error or no GPU */
     DSD_EOVERFLOW = -4,  /* a count or a scaled flow capacity would overflow 64 bits */
-    DSD_EUNSUPPORTED = -5, /* graph shape beyond a documented limit: an out-neighbourhood above 1280
-                              vertices for h >= 4, or an exact-step component above 10^8 h-cliques */
+    DSD_EUNSUPPORTED = -5, /* graph shape beyond a documented limit: an out-neighbourhood above 2048
+                              vertices for h >= 4, or an exact-step network above its limit (10^8
+                              h-cliques for h >= 4; 2^31 residual arcs) */
     DSD_EBUSY = -6,       /* server: no free slot, or the request already runs */
     DSD_ETIMEDOUT = -7,   /* server: the request is not done within the wait */
     DSD_ECANCELED = -8    /* server: the request was cancelled */
@@ -85,7 +86,10 @@ typedef struct {
      *   3  h = 3 triangle lists: pairs walked, row items;
      *   4  x-star pattern frontier pass: adjacency entries walked, frontier vertices;
      *   5  4-loop pattern pass;
-     *   0  none (h >= 4) */
+     *   6  h >= 4 arc discovery in the frontier vertices' neighbourhoods
+     *      C_v: out-list entries probed, members of the sets C_v
+     *      (k4_main_entries: row entries scanned to form them);
+     *   0  none (h >= 4 with an out-list longer than 2048) */
     double k4_main_ms;
     uint64_t k4_main_launches, k4_main_pairs, k4_main_nbrs;
     /* minimum cuts of the exact step computed on the GPU (the others ran on
@@ -119,6 +123,12 @@ typedef struct {
     uint64_t locate_rho1_num, locate_rho1_den, locate_k1;
     uint64_t locate_rho2_num, locate_rho2_den, locate_k2;
     uint64_t locate_components;
+    /* k4_main_kind 6: row entries the peel's main kernel scanned; the
+     * second kernel of those rounds (the clique counting), timed like the
+     * main kernel */
+    uint64_t k4_main_entries;
+    double k4_main2_ms;
+    uint64_t k4_main2_launches;
 } dsd_stats;
 
 /*
@@ -153,7 +163,6 @@ dsd_status dsd_release_cache(void);
  */
 dsd_status dsd_clique_degrees(dsd_graph g, int h, int out_mem, uint64_t *deg,
                               uint64_t *num_cliques);
-
 
 /*
  * (k, Psi)-core decomposition (Definition 6, Algorithm 3): core[v] = the
@@ -195,13 +204,21 @@ dsd_status dsd_peel_app(dsd_graph g, int h, int out_mem, uint8_t *member, dsd_ra
 /*
  * CoreExact (Algorithm 4): the clique-densest subgraph (Problem 1).  The GPU
  * decomposes the graph, locates the densest subgraph with Pruning1 and
- * Pruning2 and labels the components of the located core; the binary search
- * over alpha with minimum cuts (Algorithm 1's network, Goldberg's network for
- * h = 2) runs on the host over those components only.  member[v] = 1 for the
- * vertices of one densest subgraph; rho_opt its exact density.
- * member: length n bytes, residency out_mem.  rho_opt may be NULL.
- * DSD_EUNSUPPORTED when a located component holds more than 10^8 h-cliques
- * (its network, about h arcs per clique, would not fit the host step).
+ * Pruning2 (Section 6.1), labels the components of the located core and
+ * counts their h-cliques.  The search over alpha then visits those components
+ * only, in descending density: each is tested at the best density found so
+ * far and, while a denser set turns up, re-tested at that set's density (a
+ * Dinkelbach iteration over the same minimum-cut tests as Algorithm 4's
+ * binary search, on Algorithm 1's network, Goldberg's for h = 2).  A network
+ * of at least 2^21 residual arcs gets its minimum cut on the GPU
+ * (push-relabel), a smaller one on the host; the networks are built on the
+ * host (h = 3 components of 8192 edges and more: on the GPU).
+ * member[v] = 1 for the vertices of one densest subgraph; rho_opt its exact
+ * density.  member: length n bytes, residency out_mem.  rho_opt may be NULL.
+ * DSD_EUNSUPPORTED, after the locate step (whose figures dsd_last_stats then
+ * holds), when a network would hold more than 10^8 h-cliques (about h arcs
+ * each; DSD_EXACT_MAX_CLIQUES moves the limit) or more than 2^31 residual
+ * arcs; the check counts before anything is built.
  */
 dsd_status dsd_core_exact(dsd_graph g, int h, int out_mem, uint8_t *member,
                           dsd_rational *rho_opt);

@@ -74,6 +74,9 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k4_main_launches = kt.main_launches;
     G->stats.k4_main_pairs = kt.main_pairs;
     G->stats.k4_main_nbrs = kt.main_nbrs;
+    G->stats.k4_main_entries = kt.main_entries;
+    G->stats.k4_main2_ms = kt.main2_ms;
+    G->stats.k4_main2_launches = kt.main2_launches;
     G->stats.k4_launches = kt.k4_launches;
     G->stats.k4_main_kind = (uint64_t)kt.main_kind;
     G->stats.k4_tail_ms = kt.tail_ms;

@@ -49,7 +49,7 @@ __device__ __forceinline__ u64 binom_sat_dev(u64 x, int r) {
     return (u64)acc;
 }
 
-constexpr int NCLASS = 5;
+constexpr int NCLASS = 6;
 
 // class of a root by its out-degree; -1 = no clique can be rooted here
 __device__ __forceinline__ int root_class(int d, int R) {
@@ -59,7 +59,8 @@ __device__ __forceinline__ int root_class(int d, int R) {
     if (d <= 256) return 1;
     if (d <= 768) return 2;
     if (d <= 1280) return 3;
-    return 4;   // beyond the bitmap kernels
+    if (d <= 2048) return 4;
+    return 5;   // beyond the bitmap kernels
 }
 
 __device__ __forceinline__ u64 sat_add(u64 a, u64 b) { return (a + b < a) ? ~0ull : a + b; }
@@ -140,6 +141,14 @@ static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t 
             k_engine_block<R, 1280, 12, 20, true, EnumCtx><<<blocks, BLOCK, 0, s>>>(c, g.row_ptr, g.col, g.dag_off,
                                                                                   cnt[3], nullptr, gS);
         }
+        if (cnt[4]) {
+            // hubs of out-degree 1281..2048: 32-word bitmap rows in global memory
+            c.roots = lists + off[4];
+            int blocks = grid_for(cnt[4], 1, 512);
+            u64 *gS = sc.get_n<u64>((int64_t)blocks * 2048 * 32);
+            k_engine_block<R, 2048, 12, 32, true, EnumCtx><<<blocks, BLOCK, 0, s>>>(c, g.row_ptr, g.col, g.dag_off,
+                                                                                  cnt[4], nullptr, gS);
+        }
     }
 }
 
@@ -156,8 +165,8 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
     fill_u64(deg, 0, n, s);
     int32_t *cursor = sc.get_n<int32_t>(NCLASS);
     u64 *bound = sc.get_n<u64>(1);
-    DSD_HIP(hipMemsetAsync(cursor, 0, NCLASS * sizeof(int32_t), s));
-    DSD_HIP(hipMemsetAsync(bound, 0, sizeof(u64), s));
+    fill_i32(cursor, 0, NCLASS, s);
+    fill_u64(bound, 0, 1, s);
     int blocks = grid_for(n, BLOCK, 4096);
     k_classify<<<blocks, BLOCK, 0, s>>>(g.row_ptr, g.dag_off, mask, n, R, 0, cursor, nullptr, nullptr, bound);
     int32_t hc[NCLASS];
@@ -166,14 +175,14 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
     DSD_HIP(hipMemcpyAsync(&hb, bound, sizeof(u64), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     if (hb == ~0ull || hb > ~0ull / (u64)h) return false;          // counts could overflow 64 bits
-    if (hc[4]) throw Error(-5, "an out-neighbourhood exceeds 1280 vertices (limit of the bitmap kernels, h >= 4)");
+    if (hc[5]) throw Error(-5, "an out-neighbourhood exceeds 2048 vertices (limit of the bitmap kernels, h >= 4)");
     int32_t off[NCLASS + 1];
     off[0] = 0;
     for (int c = 0; c < NCLASS; c++) off[c + 1] = off[c] + hc[c];
     int32_t *lists = sc.get_n<int32_t>(off[NCLASS]);
     int32_t *d_off = sc.get_n<int32_t>(NCLASS + 1);
     DSD_HIP(hipMemcpyAsync(d_off, off, sizeof(off), hipMemcpyHostToDevice, s));
-    DSD_HIP(hipMemsetAsync(cursor, 0, NCLASS * sizeof(int32_t), s));
+    fill_i32(cursor, 0, NCLASS, s);
     k_classify<<<blocks, BLOCK, 0, s>>>(g.row_ptr, g.dag_off, mask, n, R, 1, cursor, lists, d_off, bound);
     EnumCtx ctx{nullptr, mask, deg};
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -38,7 +38,11 @@ struct KernelTimes {
     // (h = 3) or frontier vertices (h = 2)
     double main_ms = 0;
     u64 main_launches = 0, main_pairs = 0, main_nbrs = 0;
-    int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass
+    u64 main_entries = 0;   // h >= 4 root mode: row entries scanned for the frontier vertices' C_v
+    double main2_ms = 0;    // h >= 4 root mode: the counting kernel, timed like the main kernel
+    u64 main2_launches = 0;
+    int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass,
+                        // 6 h >= 4 root-mode block kernel
     bool time_main = false;   // bracket every main-kernel launch with HIP events (main_ms)
     // the tail engine (h = 3 with triangle lists, h = 2): its time (HIP
     // events around every launch, with time_main), launches (one per peel

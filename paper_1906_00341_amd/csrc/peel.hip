@@ -76,7 +76,9 @@ struct PeelCtl {
     int32_t nT[2];     // row items of the frontier (triangle lists)
     int32_t pending;   // tail mode: a round has been started and not yet finished
     int32_t nTouch;    // x-star pattern: survivors whose degree fell this round
-    u64 work[2];       // main kernel's pairs and neighbours over the whole peel (when counted)
+    int32_t nBig[2];   // h >= 4 root mode: single-workgroup items of the frontier
+    int32_t ticket;    // root mode: workgroups of the counting kernel that have finished (0 between rounds)
+    u64 work[3];       // main kernel's pairs, neighbours and (h >= 4) row entries over the whole peel (when counted)
 };
 
 // one graph of the batch (a single graph is a batch of one)
@@ -135,6 +137,13 @@ struct PeelBufs {
     int32_t minpeel;     // min-degree mode: every round removes the minimum-degree vertices
     const u64 *eset;     // h >= 4: open-addressing set of the edges among the peel's vertices
     int32_t eset_bits;   // (2^eset_bits slots, keys (lo << 32 | hi) in rank space)
+    int32_t rootmode;    // h >= 4: the frontier vertices' own cliques (k_root_edges / k_root_count)
+    int64_t *Big;        // [2][bigcap] root mode: (v << 32 | chunk) single-workgroup items
+    int64_t bigcap;
+    u64 *rbits;          // [2][rcap] root mode: bitmap rows of G[C_v] for the sliced vertices
+    int64_t rcap;
+    int64_t *rbase;      // [n] first word of v's bitmap rows in its round's half
+    int32_t *rdone;      // [n] counting workgroups of v that have finished (0 between rounds)
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
@@ -144,6 +153,22 @@ constexpr int WIDE_OUT = 32;            // neighbours w with |N+(w)| >= this get
 constexpr int SMALL_HASH_BITS = 7;      // per-wave hash for degree <= SMALL_DEG
 constexpr int TL_CHUNK = 128;           // pairs per row item (two per lane), triangle lists
 constexpr int CHUNK4 = 64;              // h >= 4: neighbours per chunk item of a frontier vertex (one wave)
+constexpr int ROOT_CAP = 2048;          // h >= 4, root mode: members of C_v one workgroup holds
+constexpr int ROOT_HB = 12;             // its hash: 2^12 >= 2 * ROOT_CAP slots
+constexpr int ROOT_SW = ROOT_CAP * 32;  // words of one workgroup's bitmap rows in global memory
+constexpr int ROOT_SLICE = ROOT_SW + 32; // and their mask words
+constexpr int ROOT_WAVE_MAX = 64;       // rows up to this long: one wave per frontier vertex
+constexpr int ROOT_SL = 64;             // members of C_v per item of a sliced vertex (a slice)
+constexpr int ROOT_SUB = ROOT_SL / WAVES_PER_BLOCK;  // workgroups per slice: one wave per member
+
+// words per bitmap row of a vertex whose row holds d entries (|C_v| <= d)
+__device__ __forceinline__ int root_words(int64_t d) { return d <= 256 ? 4 : d <= 768 ? 12 : d <= 1280 ? 20 : 32; }
+// words of a sliced vertex's region: bitmap rows (d * W), member counts (d),
+// the owner mask (W), then the members' ids (two per word) and their number
+__device__ __forceinline__ int64_t root_region(int64_t d) {
+    const int W = root_words(d);
+    return d * W + d + W + (d + 1) / 2 + 1;
+}
 constexpr u64 ESET_EMPTY = ~0ull;
 
 // Edge membership for the h >= 4 peel: one probe sequence in a table of
@@ -236,6 +261,36 @@ __device__ __forceinline__ void wave_add_by_graph(int32_t g, T *base, size_t str
 // chunk items of a large frontier vertex, and the slots of its neighbourhood
 // hash (h = 3)
 __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int which) {
+    if (b.rootmode) {
+        // root mode: a short row is one wave item (T); a row of at most
+        // ROOT_CAP entries gets bitmap rows in its half of the arena and one
+        // item per ROOT_SL-member slice (B); a longer row, or one the arena
+        // has no room for, a single-workgroup item per ROOT_CAP neighbours (Big)
+        const int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
+        if (d == 0) return;
+        if (d <= ROOT_WAVE_MAX) {
+            const int32_t pos = atomicAdd(&b.ctl->nT[which], 1);
+            b.T[(size_t)which * b.tcap + pos] = (int64_t)x << 32;
+            return;
+        }
+        if (d <= ROOT_CAP) {
+            const int64_t words = root_region(d);
+            const int64_t off = (int64_t)atomicAdd((unsigned long long *)&b.ctl->htop[which], (unsigned long long)words);
+            if (off + words <= b.rcap) {
+                b.rbase[x] = off;
+                const int32_t nsl = (int32_t)((d + ROOT_SL - 1) / ROOT_SL);
+                const int32_t base = atomicAdd(&b.ctl->nB[which], nsl);
+                int64_t *Bw = b.B + (size_t)which * b.bcap;
+                for (int32_t c = 0; c < nsl; c++) Bw[base + c] = ((int64_t)x << 32) | c;
+                return;
+            }
+        }
+        const int32_t nc = (int32_t)((d + ROOT_CAP - 1) / ROOT_CAP);
+        const int32_t base = atomicAdd(&b.ctl->nBig[which], nc);
+        int64_t *Gw = b.Big + (size_t)which * b.bigcap;
+        for (int32_t c = 0; c < nc; c++) Gw[base + c] = ((int64_t)x << 32) | c;
+        return;
+    }
     if (b.h >= 4) {
         // h >= 4: one item per CHUNK4 neighbours; k_peel_items expands them
         const int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
@@ -539,6 +594,7 @@ __device__ __forceinline__ void finish_global(PeelCtl *c) {
     c->nTouch = 0;
     c->htop[cur] = 0;
     c->nW = 0;
+    c->nBig[cur] = 0;
     for (int i = 0; i < 8; i++) c->nitems[i] = 0;
     c->cur = cur ^ 1;
     c->round += 1;
@@ -1459,6 +1515,658 @@ __global__ __launch_bounds__(BLOCK) void k_eset_fill(PeelBufs b, const int32_t *
     }
 }
 
+
+// ---------------------------------------------------------------- h >= 4, root mode
+//
+// The cliques a frontier vertex v destroys are {v} plus the (h-1)-cliques of
+// G[C_v], C_v = the neighbours of v allowed in this round (alive at its
+// start and not a frontier vertex of smaller rank: the owner rule).  An item
+// is v itself: its row is scanned once into C_v (rank order, so an arc of the
+// sub-DAG on C_v goes from a smaller to a larger local index), the arcs are
+// found by probing the out-lists of C_v's members against a hash of C_v, and
+// the members' (h-1)-clique counts come from the bitmap counting of the
+// enumeration engine, with no work per clique.  Every member loses its count
+// and v's total is the number of cliques it destroys.  A neighbour of clique-
+// degree 0 is in no alive clique and is left out of C_v (a neighbour x that
+// shares a clique with v keeps a degree >= 1 until v itself takes that clique
+// away, so a 0 read while other items decrement x is still final for v).
+// When C_v would exceed ROOT_CAP members, each chunk item of v takes its
+// ROOT_CAP neighbours w in turn and counts the (h-2)-cliques of
+// N+(w) ∩ C_v, one level shallower: every clique through v is seen once, from
+// its member of smallest rank after v.
+
+// the members of C_v (or of N+(w) ∩ C_v) one block keeps
+struct RootAccept {
+    PeelBufs b;
+    int32_t v, r;
+    __device__ __forceinline__ bool accept(int64_t, int32_t x) const {
+        return allowed(b.stamp[x], r, x, v) && b.deg[x] != 0;
+    }
+};
+struct RootAcceptIn {           // also adjacent to v: a binary search in v's row (sorted by rank)
+    PeelBufs b;
+    int32_t v, r;
+    int64_t s0, s1;
+    __device__ __forceinline__ bool accept(int64_t, int32_t x) const {
+        return allowed(b.stamp[x], r, x, v) && b.deg[x] != 0 && bsearch_i32(b.col, s0, s1, x) >= 0;
+    }
+};
+
+// allowed entries of col[s0, s0 + d), counted over the block
+template <class Acc>
+__device__ int block_count_accepted(const Acc &acc, const int32_t *col, int64_t s0, int64_t d, int32_t *wtmp) {
+    int32_t c = 0;
+    for (int64_t i = threadIdx.x; i < d; i += BLOCK) c += acc.accept(0, col[s0 + i]) ? 1 : 0;
+    c = wave_sum(c);
+    if (lane() == 0) wtmp[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    int32_t t = 0;
+    for (int i = 0; i < WAVES_PER_BLOCK; i++) t += wtmp[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ void hash_insert16(int32_t *keys, uint16_t *vals, int bits, int32_t x, int v) {
+    const uint32_t m = (1u << bits) - 1u;
+    uint32_t slot = hash_slot(x, bits);
+    while (true) {
+        const int32_t prev = atomicCAS(&keys[slot], HASH_EMPTY, x);
+        if (prev == HASH_EMPTY || prev == x) {
+            vals[slot] = (uint16_t)v;
+            return;
+        }
+        slot = (slot + 1) & m;
+    }
+}
+
+__device__ __forceinline__ int hash_find16(const int32_t *keys, const uint16_t *vals, int bits, int32_t x) {
+    const uint32_t m = (1u << bits) - 1u;
+    uint32_t slot = hash_slot(x, bits);
+    while (true) {
+        const int32_t k = keys[slot];
+        if (k == x) return vals[slot];
+        if (k == HASH_EMPTY) return -1;
+        slot = (slot + 1) & m;
+    }
+}
+
+struct RootLds {
+    int32_t C[ROOT_CAP];
+    int32_t key[1 << ROOT_HB];
+    uint16_t val[1 << ROOT_HB];
+    int32_t pre[ROOT_CAP];
+    u64 cnt[ROOT_CAP];
+    int32_t wtmp[WAVES_PER_BLOCK];
+    u64 tot[WAVES_PER_BLOCK];
+};
+
+// One member x of a candidate set, on one wave: the cliques of the set's
+// vertex through x, from the bitmap rows (S, W words each, restricted to
+// mask).  As first member x passes to every y above it the count of the
+// RR-cliques x < y < ... (lanes take the y's, 64 at a time); as last member
+// it counts the (RR-1)-cliques below it.  The counts of the y's and of x go
+// to cnt (global or LDS); returns the number with x first (every lane).
+// sA/sB/q: this wave's LDS (W words, W words, 2 * WAVE ids).
+template <int RR, int W>
+__device__ u64 root_member_work(int x, const u64 *S, const u64 *mask, u64 *cnt, u64 *sA, u64 *sB, int32_t *q) {
+    const int L = lane();
+    for (int w = L; w < W; w += WAVE) {
+        sA[w] = row_above<W>(S, x, w) & mask[w];
+        sB[w] = row_below<W>(S, x, w) & mask[w];
+    }
+    __builtin_amdgcn_wave_barrier();
+    u64 first = 0, last = 0;
+    for (int role = 0; role < 2; role++) {
+        const u64 *X = role == 0 ? sA : sB;
+        // the set bits of X go through a queue of 2 * WAVE ids; whenever it
+        // holds a wave's worth (and at the end, whatever is left) each lane
+        // takes one y
+        auto drain = [&](int take) {
+            if (L < take) {
+                const int y = q[L];
+                if constexpr (RR == 2) {
+                    if (role == 0) {
+                        atomicAdd(&cnt[y], 1ull);
+                        first += 1;
+                    } else {
+                        last += 1;
+                    }
+                } else if constexpr (RR == 3) {
+                    // popcounts streamed over the words at and above y's
+                    u64 cy = 0;
+#pragma unroll 4
+                    for (int k = y >> 6; k < W; k++) cy += (u64)__popcll(X[k] & row_above<W>(S, y, k));
+                    if (role == 0) {
+                        if (cy) {
+                            atomicAdd(&cnt[y], cy);
+                            first += cy;
+                        }
+                    } else {
+                        last += cy;
+                    }
+                } else {
+                    u64 M2[W];
+#pragma unroll
+                    for (int k = 0; k < W; k++) M2[k] = X[k] & row_above<W>(S, y, k);
+                    if (role == 0) {
+                        const u64 cy = forward<RR - 3, W>(M2, S, cnt);
+                        if (cy) {
+                            atomicAdd(&cnt[y], cy);
+                            first += cy;
+                        }
+                    } else {
+                        last += count_in<RR - 2, W>(M2, S);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+        int qn = 0;
+        for (int w = 0; w < W; w++) {
+            const u64 m = X[w];
+            if (((m >> L) & 1ull) != 0) q[qn + __popcll(m & lanemask_lt())] = w * 64 + L;
+            qn += __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            if (qn >= WAVE) {
+                drain(WAVE);
+                // the rest of the queue (fewer than WAVE ids) to its front
+                const int rest = qn - WAVE;
+                int32_t keep = 0;
+                if (L < rest) keep = q[WAVE + L];
+                __builtin_amdgcn_wave_barrier();
+                if (L < rest) q[L] = keep;
+                qn = rest;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (qn > 0) drain(qn);
+    }
+    first = wave_sum(first);
+    last = wave_sum(last);
+    if (L == 0 && first + last) atomicAdd(&cnt[x], first + last);
+    __builtin_amdgcn_wave_barrier();
+    return first;
+}
+
+template <int RR>
+__device__ u64 root_member(int x, int W, const u64 *S, const u64 *mask, u64 *cnt, u64 *sA, u64 *sB, int32_t *q) {
+    if (W == 4) return root_member_work<RR, 4>(x, S, mask, cnt, sA, sB, q);
+    if (W == 12) return root_member_work<RR, 12>(x, S, mask, cnt, sA, sB, q);
+    if (W == 20) return root_member_work<RR, 20>(x, S, mask, cnt, sA, sB, q);
+    return root_member_work<RR, 32>(x, S, mask, cnt, sA, sB, q);
+}
+
+// The RR-cliques of the sub-DAG on L.C[0, dd) (rank order): the members'
+// counts in L.cnt, the total returned to every thread.  S: this block's
+// bitmap rows in global memory (ROOT_SW words, then W mask words).  pairs:
+// out-list entries probed (thread 0).  sA/sB/q: the calling wave's LDS for
+// root_member.
+template <int RR>
+__device__ u64 root_count(const PeelBufs &b, int dd, RootLds &L, u64 *S, u64 *pairs, u64 *sA, u64 *sB, int32_t *q) {
+    for (int i = threadIdx.x; i < (1 << ROOT_HB); i += BLOCK) L.key[i] = HASH_EMPTY;
+    __syncthreads();
+    const int W = dd <= 256 ? 4 : dd <= 768 ? 12 : dd <= 1280 ? 20 : 32;
+    for (int i = threadIdx.x; i < dd; i += BLOCK) {
+        const int32_t x = L.C[i];
+        hash_insert16(L.key, L.val, ROOT_HB, x, i);
+        L.cnt[i] = 0;
+        L.pre[i] = (int32_t)(b.row_ptr[x + 1] - b.dag_off[x]);
+    }
+    for (int i = threadIdx.x; i < dd * W; i += BLOCK) S[i] = 0;
+    u64 *mask = S + ROOT_SW;                           // every member counts (the accept test applied the owner rule)
+    for (int w = threadIdx.x; w < W; w += BLOCK) {
+        const int rem = dd - w * 64;
+        mask[w] = rem >= 64 ? ~0ull : (rem > 0 ? (1ull << rem) - 1ull : 0ull);
+    }
+    __syncthreads();
+    const int32_t tot_pairs = block_incl_scan_lds(L.pre, dd, L.wtmp);
+    if (threadIdx.x == 0) *pairs += (u64)tot_pairs;
+    for (int32_t base = 0; base < tot_pairs; base += BLOCK) {
+        const int32_t p = base + threadIdx.x;
+        if (p >= tot_pairs) continue;
+        const int i = upper_bound_i32(L.pre, dd, p);
+        const int32_t off = p - (i ? L.pre[i - 1] : 0);
+        const int32_t y = b.col[b.dag_off[L.C[i]] + off];
+        const int j = hash_find16(L.key, L.val, ROOT_HB, y);
+        if (j < 0) continue;
+        atomicOr(&S[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
+        atomicOr(&S[(size_t)j * W + (i >> 6)], 1ull << (i & 63));
+    }
+    __threadfence_block();
+    __syncthreads();
+    u64 hits = 0;
+    for (int x = threadIdx.x / WAVE; x < dd; x += WAVES_PER_BLOCK)
+        hits += root_member<RR>(x, W, S, mask, L.cnt, sA, sB, q);
+    if (lane() == 0) L.tot[threadIdx.x / WAVE] = hits;
+    __syncthreads();
+    u64 total = 0;
+    for (int i = 0; i < WAVES_PER_BLOCK; i++) total += L.tot[i];
+    __syncthreads();
+    return total;
+}
+
+// every member of L.C[0, dd) that survives the round loses its count
+__device__ __forceinline__ void root_flush(const PeelBufs &b, int dd, const RootLds &L, int32_t r) {
+    for (int i = threadIdx.x; i < dd; i += BLOCK) {
+        const u64 c = L.cnt[i];
+        const int32_t x = L.C[i];
+        if (c && b.stamp[x] > r) dec_deg(b, x, c, r);
+    }
+    __syncthreads();
+}
+
+// the main kernel's counted work (root mode): lane 0 of every wave holds its
+// wave's tallies; one atomic each per block
+__device__ __forceinline__ void add_work3(const PeelBufs &b, u64 pairs, u64 cands, u64 entries) {
+    __shared__ u64 sW[3][WAVES_PER_BLOCK];
+    const int wv = threadIdx.x / WAVE;
+    if (lane() == 0) {
+        sW[0][wv] = pairs;
+        sW[1][wv] = cands;
+        sW[2][wv] = entries;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        u64 t = 0;
+        for (int i = 0; i < WAVES_PER_BLOCK; i++) t += sW[threadIdx.x][i];
+        if (t) atomicAdd(&b.ctl->work[threadIdx.x], t);
+    }
+}
+
+// C'_v: the neighbours of v alive at the start of the round (frontier
+// members included).  A stamp only changes within a round from ALIVE to the
+// round's number or the next one's, so every workgroup of v, in both
+// kernels, finds the same list in the same (rank) order.  The owner rule is
+// applied afterwards through a mask: the members that are frontier vertices
+// of smaller rank than v take no part in v's cliques.
+struct RootStable {
+    PeelBufs b;
+    int32_t r;
+    __device__ __forceinline__ bool accept(int64_t, int32_t x) const { return b.stamp[x] >= r; }
+};
+
+// A single-workgroup item (v, chunk) of Big: v's whole C_v in one workgroup
+// (its chunk 0), or, when C_v exceeds ROOT_CAP members, the (h-2)-cliques of
+// N+(w) ∩ C_v for every neighbour w of this chunk.
+template <int R>
+__device__ void root_big_item(const PeelBufs &b, int32_t v, int32_t ch, int32_t r, RootLds &L, u64 *S, u64 &pairs,
+                              u64 &cands, u64 &entries, u64 *sA, u64 *sB, int32_t *q) {
+    if (b.deg[v] == 0) return;                         // a frontier vertex's degree is fixed in its round
+    const int64_t s0 = b.row_ptr[v], d = b.row_ptr[v + 1] - s0;
+    const RootAccept acc{b, v, r};
+    int dd;
+    if (d <= ROOT_CAP) {
+        dd = block_load_candidates(acc, 0, b.col, s0, (int)d, L.C, L.wtmp);
+        entries += (u64)d;
+    } else {
+        dd = block_count_accepted(acc, b.col, s0, d, L.wtmp);
+        entries += (u64)d;
+        if (dd <= ROOT_CAP) {
+            if (ch != 0) return;                       // chunk 0 takes the whole vertex
+            // the accepted entries in row order, ROOT_CAP at a time (a
+            // degree falling to 0 meanwhile only drops an entry: dd stays a bound)
+            int got = 0;
+            for (int64_t o = 0; o < d; o += ROOT_CAP) {
+                const int part = (int)min((int64_t)ROOT_CAP, d - o);
+                got += block_load_candidates(acc, 0, b.col, s0 + o, part, L.C + got, L.wtmp);
+            }
+            dd = got;
+        } else {
+            // C_v too large for one workgroup: the neighbours w of this chunk in turn
+            const int64_t w0 = (int64_t)ch * ROOT_CAP, w1 = min(d, w0 + ROOT_CAP);
+            const RootAcceptIn accw{b, v, r, s0, s0 + d};
+            u64 destroyed = 0;
+            for (int64_t e = s0 + w0; e < s0 + w1; e++) {
+                const int32_t w = b.col[e];
+                // w's degree may be falling under other items: one thread decides for the block
+                if (threadIdx.x == 0) L.wtmp[0] = acc.accept(0, w) ? 1 : 0;
+                __syncthreads();
+                const bool take = L.wtmp[0] != 0;
+                __syncthreads();
+                if (!take) continue;
+                const int64_t o0 = b.dag_off[w];
+                const int dw = (int)(b.row_ptr[w + 1] - o0);   // <= maxdout <= ROOT_CAP in root mode
+                if (dw < R - 1) continue;
+                const int de = block_load_candidates(accw, 0, b.col, o0, dw, L.C, L.wtmp);
+                entries += (u64)dw;
+                if (de < R - 1) continue;
+                cands += (u64)de;
+                const u64 t = root_count<R - 1>(b, de, L, S, &pairs, sA, sB, q);
+                root_flush(b, de, L, r);
+                if (threadIdx.x == 0 && t) {
+                    if (b.stamp[w] > r) dec_deg(b, w, t, r);
+                    destroyed += t;
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) add_destroyed(b, v, destroyed);
+            return;
+        }
+    }
+    if (dd < R) return;
+    cands += (u64)dd;
+    const u64 t = root_count<R>(b, dd, L, S, &pairs, sA, sB, q);
+    root_flush(b, dd, L, r);
+    if (threadIdx.x == 0) add_destroyed(b, v, t);
+}
+
+// first index in the sorted list a[0, n) holding x, or -1
+__device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n && a[lo] == x ? lo : -1;
+}
+
+// Arc discovery.  Sliced vertices (rows of ROOT_WAVE_MAX + 1 .. ROOT_CAP
+// entries): an item (v, slice) stands for ROOT_SUB workgroups; each builds
+// C'_v in LDS and gives each of its waves one member x, whose lanes walk
+// N+(x) and find their entries in C'_v by binary search (both lists are in
+// rank order), setting both bits of every arc of G[C'_v] in v's bitmap rows
+// (each arc is found once, from its lower end).  The first workgroup of v
+// also stores C'_v, its size and the owner mask in v's region.  Wave items
+// (rows of at most ROOT_WAVE_MAX entries): one wave does the whole count,
+// C_v in one 64-bit word per member.
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
+    __shared__ int32_t sC[ROOT_CAP];
+    __shared__ int32_t wtmp[WAVES_PER_BLOCK];
+    __shared__ int32_t wC[WAVES_PER_BLOCK][64];
+    __shared__ int32_t wKey[WAVES_PER_BLOCK][128];
+    __shared__ int32_t wVal[WAVES_PER_BLOCK][128];
+    __shared__ int32_t wPre[WAVES_PER_BLOCK][64];
+    __shared__ int64_t wSt[WAVES_PER_BLOCK][64];
+    __shared__ u64 wCnt[WAVES_PER_BLOCK][64];
+    __shared__ u64 wS[WAVES_PER_BLOCK][64];
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur;
+    if (c->nF[cur] == 0) return;
+    const int32_t r = c->round, nG = c->nB[cur], nI = c->nT[cur];
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    u64 *bits = b.rbits + (size_t)cur * b.rcap;
+    const int wv = threadIdx.x / WAVE, L = lane();
+    u64 pairs = 0, cands = 0, entries = 0;
+    for (int64_t it = blockIdx.x; it < (int64_t)nG * ROOT_SUB; it += gridDim.x) {
+        const int64_t item = Bc[it / ROOT_SUB];
+        const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
+        const int sub = (int)(it % ROOT_SUB);
+        if (b.deg[v] == 0) continue;                   // block-uniform: fixed in v's round
+        const int64_t s0 = b.row_ptr[v];
+        const int d = (int)(b.row_ptr[v + 1] - s0);    // <= ROOT_CAP for a sliced vertex
+        const int m0 = sl * ROOT_SL + sub * WAVES_PER_BLOCK;
+        const int dd = block_load_candidates(RootStable{b, r}, 0, b.col, s0, d, sC, wtmp);
+        const int W = root_words(d);
+        u64 *S = bits + b.rbase[v];
+        if (sl == 0 && sub == 0) {
+            // C'_v, its size and the owner mask, for the counting kernel
+            entries += (u64)d;
+            cands += (u64)dd;
+            u64 *mask = S + (int64_t)d * W + d;
+            int32_t *ids = (int32_t *)(mask + W);
+            for (int i = threadIdx.x; i < dd; i += BLOCK) ids[i] = sC[i];
+            for (int q = threadIdx.x; q < W; q += BLOCK) {
+                u64 wmask = 0;
+                for (int j = 0; j < 64 && q * 64 + j < dd; j++) {
+                    const int32_t x = sC[q * 64 + j];
+                    if (allowed(b.stamp[x], r, x, v)) wmask |= 1ull << j;
+                }
+                mask[q] = wmask;
+            }
+            if (threadIdx.x == 0) ((int64_t *)ids)[(d + 1) / 2] = dd;
+        }
+        const int m = m0 + wv;
+        if (dd >= R && m < dd) {
+            const int32_t x = sC[m];
+            const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
+            if (L == 0) pairs += (u64)(o1 - o0);
+            for (int64_t e = o0 + L; e < o1; e += WAVE) {
+                const int j = lds_find(sC, dd, b.col[e]);
+                if (j >= 0) {
+                    atomicOr(&S[(size_t)m * W + (j >> 6)], 1ull << (j & 63));
+                    atomicOr(&S[(size_t)j * W + (m >> 6)], 1ull << (m & 63));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // wave items
+    for (int i = L; i < 128; i += WAVE) wKey[wv][i] = HASH_EMPTY;
+    wCnt[wv][L] = 0;
+    wS[wv][L] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t *Tc = b.T + (size_t)cur * b.tcap;
+    DestroyedTally tally;
+    u64 wpairs = 0, wcands = 0, wentries = 0;
+    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; it < nI; it += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+        const int32_t v = (int32_t)(Tc[it] >> 32);
+        if (b.deg[v] == 0) continue;                   // wave-uniform
+        const int64_t s0 = b.row_ptr[v];
+        const int d = (int)(b.row_ptr[v + 1] - s0);    // <= ROOT_WAVE_MAX
+        int32_t x = -1;
+        bool keep = false;
+        if (L < d) {
+            x = b.col[s0 + L];
+            keep = allowed(b.stamp[x], r, x, v) && b.deg[x] != 0;
+        }
+        const u64 km = __ballot(keep);
+        const int dd = __popcll(km);
+        wentries += (u64)d;
+        if (dd < R) continue;                          // wave-uniform
+        wcands += (u64)dd;
+        const int li = __popcll(km & lanemask_lt());   // rank order kept
+        if (keep) {
+            wC[wv][li] = x;
+            hash_insert(wKey[wv], wVal[wv], 7, x, li);
+        }
+        int32_t len = 0;
+        int64_t st = 0;
+        if (keep) {
+            st = b.dag_off[x];
+            len = (int32_t)(b.row_ptr[x + 1] - st);
+        }
+        const int32_t inc = wave_incl_scan(len);
+        if (keep) {
+            wPre[wv][li] = inc;
+            wSt[wv][li] = st;
+        }
+        const int32_t tot = __shfl(inc, WAVE - 1, WAVE);
+        wpairs += (u64)tot;
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t base = 0; base < tot; base += WAVE) {
+            const int32_t p = base + L;
+            if (p < tot) {
+                const int i = upper_bound_i32(wPre[wv], dd, p);
+                const int32_t off = p - (i ? wPre[wv][i - 1] : 0);
+                const int32_t y = b.col[wSt[wv][i] + off];
+                const int j = hash_find(wKey[wv], wVal[wv], 7, y);
+                if (j >= 0) {
+                    atomicOr(&wS[wv][i], 1ull << j);
+                    atomicOr(&wS[wv][j], 1ull << i);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        u64 t = 0;
+        if (L < dd) t = bitmap_node_work<R, 1>(L, &wS[wv][0], &wCnt[wv][0]);
+        t = wave_sum(t);
+        __builtin_amdgcn_wave_barrier();
+        const u64 cL = L < dd ? wCnt[wv][L] : 0;
+        const int32_t xL = L < dd ? wC[wv][L] : 0;
+        if (cL && b.stamp[xL] > r) dec_deg(b, xL, cL, r);
+        if (L == 0) tally.add(b, v, t);
+        __builtin_amdgcn_wave_barrier();
+        for (int i = L; i < 128; i += WAVE) wKey[wv][i] = HASH_EMPTY;
+        wCnt[wv][L] = 0;
+        wS[wv][L] = 0;
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (L == 0) tally.flush(b);
+    if (b.count_work) {
+        // lane 0 of every wave: its wave items and its members' probes;
+        // thread 0 also the stored lists'
+        add_work3(b, wpairs + (L == 0 ? pairs : 0), wcands + (threadIdx.x == 0 ? cands : 0),
+                  wentries + (threadIdx.x == 0 ? entries : 0));
+    }
+}
+
+// One member x of a sliced vertex's C'_v, on one wave: the cliques of v
+// through x, from the bitmap rows (S, W words each, restricted to the owner
+// mask).  As first member x passes to every y above it the count of the
+// cliques x < y < ... (lanes take the y's, 64 at a time); as last member it
+// counts the (R-1)-cliques below it.  The counts of y and x go to cnt
+// (global, v's region); returns the number with x first (every lane).
+template <int R, int W>
+__device__ u64 root_member_work(int x, const u64 *S, const u64 *mask, u64 *cnt, int32_t *q) {
+    const int L = lane();
+    u64 A[W], B[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        A[w] = row_above<W>(S, x, w) & mask[w];
+        B[w] = row_below<W>(S, x, w) & mask[w];
+    }
+    u64 first = 0, last = 0;
+    for (int role = 0; role < 2; role++) {
+        int qn = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const u64 m = role == 0 ? A[w] : B[w];
+            if (((m >> L) & 1ull) != 0) q[qn + __popcll(m & lanemask_lt())] = w * 64 + L;
+            qn += __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            if (qn >= WAVE || (w == W - 1 && qn > 0)) {
+                const int take = qn < WAVE ? qn : WAVE;
+                if (L < take) {
+                    const int y = q[L];
+                    u64 M2[W];
+#pragma unroll
+                    for (int k = 0; k < W; k++) M2[k] = (role == 0 ? A[k] : B[k]) & row_above<W>(S, y, k);
+                    if (role == 0) {
+                        u64 cy;
+                        if constexpr (R == 3) cy = popc_w<W>(M2);
+                        else cy = forward<R - 3, W>(M2, S, cnt);
+                        if (cy) {
+                            atomicAdd(&cnt[y], cy);
+                            first += cy;
+                        }
+                    } else {
+                        if constexpr (R == 3) last += popc_w<W>(M2);
+                        else last += count_in<R - 2, W>(M2, S);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                // the rest of the queue to its front
+                const int rest = qn - take;
+                int32_t keep = 0;
+                if (L < rest) keep = q[take + L];
+                __builtin_amdgcn_wave_barrier();
+                if (L < rest) q[L] = keep;
+                qn = rest;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    first = wave_sum(first);
+    last = wave_sum(last);
+    if (L == 0 && first + last) atomicAdd(&cnt[x], first + last);
+    return first;
+}
+
+template <int R>
+__device__ u64 root_member(int x, int W, const u64 *S, const u64 *mask, u64 *cnt, int32_t *q) {
+    if (W == 4) return root_member_work<R, 4>(x, S, mask, cnt, q);
+    if (W == 12) return root_member_work<R, 12>(x, S, mask, cnt, q);
+    if (W == 20) return root_member_work<R, 20>(x, S, mask, cnt, q);
+    return root_member_work<R, 32>(x, S, mask, cnt, q);
+}
+
+// Counting.  Sliced vertices: one wave per member of C'_v that the owner
+// mask allows; the last workgroup of v hands the members' counts to their
+// degrees and clears v's region for later rounds.  Single-workgroup items
+// follow.
+// fin (one graph, outside tail mode): the last workgroup also ends the round.
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int fin) {
+    __shared__ RootLds L;
+    __shared__ int32_t sQ[WAVES_PER_BLOCK][2 * WAVE];
+    __shared__ u64 sAB[WAVES_PER_BLOCK][2][32];
+    PeelCtl *c = b.ctl;
+    const int32_t cur = c->cur;
+    const bool any = c->nF[cur] != 0;
+    const int32_t r = c->round, nG = any ? c->nB[cur] : 0, nBig = any ? c->nBig[cur] : 0;
+    const int64_t *Bc = b.B + (size_t)cur * b.bcap;
+    u64 *bits = b.rbits + (size_t)cur * b.rcap;
+    const int wv = threadIdx.x / WAVE;
+    u64 pairs = 0, cands = 0, entries = 0;
+    for (int64_t it = blockIdx.x; it < (int64_t)nG * ROOT_SUB; it += gridDim.x) {
+        const int64_t item = Bc[it / ROOT_SUB];
+        const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
+        const int sub = (int)(it % ROOT_SUB);
+        if (b.deg[v] == 0) continue;                   // its items made no arcs either
+        const int d = (int)(b.row_ptr[v + 1] - b.row_ptr[v]);
+        const int W = root_words(d);
+        u64 *S = bits + b.rbase[v];
+        u64 *cnt = S + (int64_t)d * W;
+        const u64 *mask = cnt + d;
+        const int32_t *ids = (const int32_t *)(mask + W);
+        const int dd = (int)((const int64_t *)ids)[(d + 1) / 2];
+        const int m = sl * ROOT_SL + sub * WAVES_PER_BLOCK + wv;
+        u64 t = 0;
+        if (dd >= R && m < dd && ((mask[m >> 6] >> (m & 63)) & 1ull))
+            t = root_member<R>(m, W, S, mask, cnt, sAB[wv][0], sAB[wv][1], sQ[wv]);
+        if (lane() == 0 && t) add_destroyed(b, v, t);
+        // completion: the last workgroup of v flushes the counts and clears
+        // the region.  Every thread fences first: its atomics on v's counts
+        // must be performed before its workgroup counts itself done.
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nsl = (d + ROOT_SL - 1) / ROOT_SL;
+            L.wtmp[0] = atomicAdd(&b.rdone[v], 1) == nsl * ROOT_SUB - 1 ? 1 : 0;
+        }
+        __syncthreads();
+        if (L.wtmp[0]) {
+            __threadfence();
+            for (int i = threadIdx.x; i < dd; i += BLOCK) {
+                const u64 ci = cnt[i];
+                const int32_t x = ids[i];
+                if (ci && b.stamp[x] > r) dec_deg(b, x, ci, r);
+            }
+            __syncthreads();                           // every count and id read before the region is cleared
+            const int64_t words = root_region(d);
+            for (int64_t i = threadIdx.x; i < words; i += BLOCK) S[i] = 0;
+            if (threadIdx.x == 0) b.rdone[v] = 0;
+        }
+        __syncthreads();
+    }
+    const int64_t *Gc = b.Big + (size_t)cur * b.bigcap;
+    u64 *Sg = gS + (size_t)blockIdx.x * ROOT_SLICE;
+    for (int64_t it = blockIdx.x; it < nBig; it += gridDim.x) {
+        const int64_t item = Gc[it];
+        root_big_item<R>(b, (int32_t)(item >> 32), (int32_t)(item & 0xffffffff), r, L, Sg, pairs, cands, entries,
+                         sAB[wv][0], sAB[wv][1], sQ[wv]);
+    }
+    if (b.count_work) add_work3(b, threadIdx.x == 0 ? pairs : 0, threadIdx.x == 0 ? cands : 0,
+                                threadIdx.x == 0 ? entries : 0);
+    if (fin) {
+        // the last workgroup to finish ends the round (what k_finish_one
+        // does); every thread's writes are performed before its workgroup
+        // counts itself done
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (atomicAdd(&c->ticket, 1) == (int32_t)gridDim.x - 1) {
+                __threadfence();
+                c->ticket = 0;
+                finish_graph(b, 0);
+                finish_global(c);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- adjacency compaction
 //
 // Between rounds, rows of removed vertices and entries pointing at them are
@@ -1532,6 +2240,10 @@ __global__ void k_reset_chunks(PeelBufs b) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         b.ctl->nB[b.ctl->cur] = 0;
         b.ctl->htop[b.ctl->cur] = 0;
+        if (b.rootmode) {
+            b.ctl->nT[b.ctl->cur] = 0;
+            b.ctl->nBig[b.ctl->cur] = 0;
+        }
     }
 }
 __global__ void k_rechunk(PeelBufs b) {
@@ -2353,6 +3065,7 @@ __global__ __launch_bounds__(TE_HBLOCK) void k_te_heavy(TeState *ts, const int64
 // from a process-wide pool that only grows, so a call pays for event
 // creation only the first time it needs that many; a second peel running at
 // the same time (another thread) goes untimed.
+template <int SLOT>
 class LaunchTimer {
 public:
     explicit LaunchTimer(bool want) : lk_(pool_mu(), std::try_to_lock) { on_ = want && lk_.owns_lock(); }
@@ -2605,7 +3318,13 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             b.lval = sc.get_n<uint32_t>((int64_t)gloop * b.lsize);
         }
     }
-    b.count_work = kt != nullptr && h <= 3;
+    // h >= 4: one item per frontier vertex (root mode) unless an out-list is
+    // longer than a block holds (then the (v, w) items below);
+    // DSD_PEEL_ROOT=0 turns root mode off
+    const char *rm_env = std::getenv("DSD_PEEL_ROOT");
+    const bool rootmode = h >= 4 && pattern == 0 && g.maxdout <= ROOT_CAP && !(rm_env && rm_env[0] == '0');
+    b.rootmode = rootmode ? 1 : 0;
+    b.count_work = kt != nullptr && (h <= 3 || rootmode);
     b.ctl = sc.get_n<PeelCtl>(1);
     b.gs = sc.get_n<GraphState>(G);
     b.stamp = sc.get_n<int32_t>(n);
@@ -2641,8 +3360,31 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         b.W = sc.get_n<int64_t>(b.wcap);
     }
     const int R = h - 2;
-    u64 *gS = nullptr;
-    if (h >= 4) {
+    u64 *gS = nullptr, *gSr = nullptr;
+    constexpr int ROOT_GRID = 512, ROOT_EDGE_GRID = 1024;
+    if (rootmode) {
+        // a vertex joins at most one frontier: one wave item, at most
+        // 1 + deg / ROOT_SL slice items, or at most 1 + deg / ROOT_CAP
+        // single-workgroup items
+        b.bcap = (int64_t)n + 2 * g.m / ROOT_SL + 1;
+        b.B = sc.get_n<int64_t>(2 * b.bcap);
+        b.tcap = (int64_t)n + 1;
+        b.T = sc.get_n<int64_t>(2 * b.tcap);
+        b.bigcap = (int64_t)n + 2 * g.m / ROOT_CAP + 1;
+        b.Big = sc.get_n<int64_t>(2 * b.bigcap);
+        // bitmap rows of one round's sliced vertices (a vertex that finds no
+        // room becomes a single-workgroup item); cleared once here, then by
+        // the last counting workgroup of every vertex that used them
+        b.rcap = std::min<int64_t>((int64_t)1 << 26, std::max<int64_t>((int64_t)1 << 16, 16 * g.m));
+        // DSD_ROOT_ARENA_WORDS overrides the arena size (0: every vertex a single-workgroup item)
+        if (const char *ra = std::getenv("DSD_ROOT_ARENA_WORDS")) b.rcap = std::max<int64_t>(1, std::atoll(ra));
+        b.rbits = sc.get_n<u64>(2 * b.rcap);
+        fill_u64(b.rbits, 0, 2 * b.rcap, s);
+        b.rbase = sc.get_n<int64_t>(n);
+        b.rdone = sc.get_n<int32_t>(n);
+        fill_i32(b.rdone, 0, n, s);
+        gSr = sc.get_n<u64>((int64_t)ROOT_GRID * ROOT_SLICE);
+    } else if (h >= 4) {
         // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK4
         b.bcap = (int64_t)n + 2 * g.m / CHUNK4 + 1;
         b.B = sc.get_n<int64_t>(2 * b.bcap);
@@ -2652,7 +3394,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         b.item_w = sc.get_n<int32_t>(5 * b.item_cap);
         if (R >= 3) gS = sc.get_n<u64>((int64_t)256 * 1280 * 20);
         if (g.maxdout > 1280 && R >= 3)
-            throw Error(-5, "an out-neighbourhood exceeds 1280 vertices (limit of the bitmap kernels, h >= 5)");
+            throw Error(-5, "an out-neighbourhood exceeds 1280 vertices (limit of the (v, w) item kernels, h >= 5, "
+                            "with the per-vertex counting turned off)");
     }
     const u64 *mu_dev = grp ? grp->mu : nullptr;
     if (!mu_dev) {
@@ -2668,7 +3411,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     DSD_HIP(hipMemcpyAsync(pinned, &b.ctl->n_alive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DSD_HIP(hipStreamSynchronize(s));
     int64_t n_alive = pinned[0];
-    if (h >= 4 && n_alive > 0) {
+    if (h >= 4 && !rootmode && n_alive > 0) {
         // the edges among the starting vertices, at most half the slots filled
         const int64_t pairs = n_alive * (n_alive - 1) / 2;
         const int64_t edges = std::max<int64_t>(1, std::min<int64_t>(g.m, pairs));
@@ -2690,7 +3433,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     // tail mode from this many alive vertices on (the count only falls)
     constexpr int64_t TAIL_ALIVE = 16384;
     bool tail = false;
-    LaunchTimer main_timer(kt != nullptr && kt->time_main && h <= 3);
+    LaunchTimer<0> main_timer(kt != nullptr && kt->time_main && (h <= 3 || rootmode));
+    LaunchTimer<1> main2_timer(kt != nullptr && kt->time_main && rootmode);
     // the lists need no adjacency: dead entries are skipped by their bit
     int64_t steps = 0, chunk = 4;
     const int64_t max_steps = 4 * (int64_t)n + 64;
@@ -2729,6 +3473,23 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                 k_h3_fill<<<gf, BLOCK, 0, s>>>(b);
                 main_timer.launch(k_h3_probe, dim3(gp), dim3(BLOCK), s, b);
                 k_h3_flush<<<gf, BLOCK, 0, s>>>(b);
+            } else if (rootmode) {
+                const int fin = !tail && G == 1 ? 1 : 0;
+                switch (h) {
+                    case 4:
+                        main_timer.launch(k_root_edges<3>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
+                        main2_timer.launch(k_root_count<3>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        break;
+                    case 5:
+                        main_timer.launch(k_root_edges<4>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
+                        main2_timer.launch(k_root_count<4>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        break;
+                    case 6:
+                        main_timer.launch(k_root_edges<5>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
+                        main2_timer.launch(k_root_count<5>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        break;
+                    default: throw Error(-1, "h outside [2, 6]");
+                }
             } else {
                 k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
                 switch (R) {
@@ -2740,6 +3501,8 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             }
             if (tail) {
                 // the next k_tail_level ends this round
+            } else if (rootmode && G == 1) {
+                // the counting kernel's last workgroup ended it
             } else if (G == 1) {
                 k_finish_one<<<1, 1, 0, s>>>(b);
             } else {
@@ -2765,10 +3528,13 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         u64 launches = 0;
         kt->main_ms += main_timer.total_ms(&launches);
         kt->main_launches += launches;
+        kt->main2_ms += main2_timer.total_ms(&launches);
+        kt->main2_launches += launches;
         if (b.pattern == 1) kt->main_kind = 4;
         else if (b.pattern == 2) kt->main_kind = 5;
         else if (h == 2) kt->main_kind = 1;
         else if (h == 3) kt->main_kind = listed ? 3 : 2;
+        else if (rootmode) kt->main_kind = 6;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
@@ -2781,6 +3547,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
     if (kt && b.count_work) {
         kt->main_pairs += fin.work[0];
         kt->main_nbrs += fin.work[1];
+        kt->main_entries += fin.work[2];
     }
     res.rounds = fin.round;
     res.graph_levels.resize(G);

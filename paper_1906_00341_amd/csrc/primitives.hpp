@@ -17,6 +17,8 @@ namespace dsd {
 class Scratch {
 public:
     explicit Scratch(size_t min_chunk = (size_t)64 << 20) : min_chunk_(min_chunk) {}
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
     ~Scratch();
     void *get(size_t bytes);
     void recycle();

@@ -10,8 +10,10 @@ Names follow the C ABI: ``build_csr``, ``clique_degrees``, ``clique_core``,
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from fractions import Fraction
 
 import numpy as np
@@ -67,7 +69,8 @@ class Stats(C.Structure):
                 ("k4_tail_grid_rounds", C.c_uint64), ("k4_tail_grid_pairs", C.c_uint64),
                 ("locate_rho1_num", C.c_uint64), ("locate_rho1_den", C.c_uint64), ("locate_k1", C.c_uint64),
                 ("locate_rho2_num", C.c_uint64), ("locate_rho2_den", C.c_uint64), ("locate_k2", C.c_uint64),
-                ("locate_components", C.c_uint64)]
+                ("locate_components", C.c_uint64), ("k4_main_entries", C.c_uint64),
+                ("k4_main2_ms", C.c_double), ("k4_main2_launches", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -129,7 +132,30 @@ def load(path: str = LIB_PATH):
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = I
     _lib = lib
+    atexit.register(_release_at_exit)
     return lib
+
+
+# Handles and servers still alive when the interpreter exits are released
+# here, from an atexit hook: it runs while the HIP runtime is still up,
+# before the interpreter clears modules and before the C library runs the
+# runtime's own exit handlers.  A finalizer that ran later would call into a
+# runtime that is already gone.
+_live_graphs = weakref.WeakSet()
+_live_servers = weakref.WeakSet()
+_exiting = False
+
+
+def _release_at_exit():
+    global _exiting
+    if _lib is None or _exiting:
+        return
+    for s in list(_live_servers):
+        s.close()
+    for g in list(_live_graphs):
+        g.free()
+    _lib.dsd_release_cache()
+    _exiting = True
 
 
 def _check(rc: int):
@@ -159,6 +185,7 @@ class Graph:
 
     def __init__(self, handle):
         self._h = handle
+        _live_graphs.add(self)
 
     @property
     def handle(self):
@@ -170,9 +197,9 @@ class Graph:
         return int(n.value), int(m.value)
 
     def free(self):
-        if self._h is not None and _lib is not None:
+        if self._h is not None and _lib is not None and not _exiting:
             _lib.dsd_graph_free(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.free()
@@ -352,6 +379,7 @@ class Server:
         self._s = C.c_void_p()
         _check(lib.dsd_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(self._s)))
         self._keep = {}
+        _live_servers.add(self)
 
     def submit(self, g: Graph, h: int, op, out=None) -> int:
         p, mem, k = (None, DSD_MEM_HOST, None) if out is None else _ptr(out)
@@ -379,10 +407,10 @@ class Server:
         return rc
 
     def close(self):
-        if self._s is not None and _lib is not None:
+        if self._s is not None and _lib is not None and not _exiting:
             _lib.dsd_server_destroy(self._s)
-            self._s = None
-            self._keep.clear()
+        self._s = None
+        self._keep.clear()
 
     def __del__(self):
         self.close()

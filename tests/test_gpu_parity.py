@@ -146,10 +146,10 @@ def test_complete_graph(h):
     assert rho == Fraction(math.comb(40, h), 40) and mem.all()
 
 
-@pytest.mark.parametrize("n,h", [(300, 4), (800, 4), (1281, 4), (300, 5), (100, 6)])
+@pytest.mark.parametrize("n,h", [(300, 4), (800, 4), (1281, 4), (1700, 4), (2049, 4), (300, 5), (100, 6)])
 def test_complete_graph_wide_neighbourhoods(n, h):
     # out-neighbourhoods up to n - 1 vertices: every bitmap class of the
-    # engine, up to its 1280-vertex limit
+    # engine, up to its 2048-vertex limit (the hub class: 1281 .. 2048)
     _, s, d = synth.complete_graph(n)
     g = dsd.build_csr(n, s, d)
     deg, mu = dsd.clique_degrees(g, h)
@@ -161,13 +161,93 @@ def test_complete_graph_wide_neighbourhoods(n, h):
 
 
 def test_out_degree_limit():
-    n, s, d = synth.complete_graph(1282)
+    n, s, d = synth.complete_graph(2050)
     g = dsd.build_csr(n, s, d)
     with pytest.raises(dsd.DsdError) as e:
         dsd.clique_degrees(g, 4)
     assert e.value.status == -5
     deg, mu = dsd.clique_degrees(g, 3)      # h <= 3 has no such limit
-    assert mu == math.comb(1282, 3) and (deg == math.comb(1281, 2)).all()
+    assert mu == math.comb(2050, 3) and (deg == math.comb(2049, 2)).all()
+
+
+def test_hub_with_sparse_out_neighbourhood():
+    """A hub whose 1,400 neighbours all rank above it (each also has 1,401
+    leaves of its own) and are joined to each other sparsely: the hub's
+    out-neighbourhood of 1,400 takes the 1,281 .. 2,048 class of the
+    enumeration and of the per-vertex peel counting at h = 4, 5, 6, with few
+    cliques, against the oracle."""
+    rng = np.random.default_rng(3)
+    k, leaves = 1400, 1401
+    hub = 0
+    sat = np.arange(1, k + 1)
+    src = [np.full(k, hub), ]
+    dst = [sat]
+    # sparse random pairs among the satellites, plus a few dense spots
+    a = rng.integers(1, k + 1, size=6 * k)
+    b = rng.integers(1, k + 1, size=6 * k)
+    src.append(a)
+    dst.append(b)
+    blk = rng.choice(sat, size=12, replace=False)
+    iu, ju = np.triu_indices(12, 1)
+    src.append(blk[iu])
+    dst.append(blk[ju])
+    base = k + 1
+    for i, x in enumerate(sat):
+        src.append(np.full(leaves, x))
+        dst.append(np.arange(base, base + leaves))
+        base += leaves
+    n = base
+    s = np.concatenate(src).astype(np.int32)
+    d = np.concatenate(dst).astype(np.int32)
+    g = dsd.build_csr(n, s, d)
+    og = oracle.Graph(n, s, d)
+    for h in (4, 5, 6):
+        deg, mu = dsd.clique_degrees(g, h)
+        deg_o, mu_o = og.clique_degrees(h)
+        assert mu == mu_o
+        np.testing.assert_array_equal(deg, deg_o)
+        core, km = dsd.clique_core(g, h)
+        core_o, km_o = og.core_decomposition(h)
+        assert km == km_o
+        np.testing.assert_array_equal(core, core_o)
+
+
+@pytest.mark.parametrize("h", [4])
+def test_hub_class_k1500_plus_noise(h):
+    """A 1,500-vertex clique (every root of out-degree 1,281 .. 1,499 takes
+    the hub class of the engine and of the per-vertex peel counting) beside a
+    sparse ER graph with a planted block: clique-degrees and core numbers are
+    the closed form C(1499, h-1) on the clique and the oracle's on the rest;
+    CoreApp returns the clique."""
+    k = 1500
+    _, s1, d1 = synth.complete_graph(k)
+    n2, s2, d2 = synth.er_planted(n=3000, m=20000, plant=40, p=0.6, seed=h)
+    n = k + n2
+    perm = np.random.default_rng(h).permutation(n).astype(np.int32)
+    s = perm[np.concatenate([s1, s2 + k])]
+    d = perm[np.concatenate([d1, d2 + k])]
+    g = dsd.build_csr(n, s, d)
+    og = oracle.Graph(n2, s2, d2)
+    deg_o, mu_o = og.clique_degrees(h)
+    core_o, _ = og.core_decomposition(h)
+    in_k = np.zeros(n, bool)
+    in_k[perm[:k]] = True
+    want_deg = np.zeros(n, np.uint64)
+    want_deg[perm[:k]] = math.comb(k - 1, h - 1)
+    want_deg[perm[k:]] = deg_o
+    want_core = np.zeros(n, np.uint64)
+    want_core[perm[:k]] = math.comb(k - 1, h - 1)
+    want_core[perm[k:]] = core_o
+    deg, mu = dsd.clique_degrees(g, h)
+    assert mu == math.comb(k, h) + mu_o
+    np.testing.assert_array_equal(deg, want_deg)
+    core, km = dsd.clique_core(g, h)
+    assert km == math.comb(k - 1, h - 1)
+    np.testing.assert_array_equal(core, want_core)
+    mem, km2, dens = dsd.core_app(g, h)
+    assert km2 == km
+    np.testing.assert_array_equal(mem.astype(bool), in_k)
+    assert dens == Fraction(math.comb(k, h), k)
 
 
 @pytest.mark.parametrize("parts,hs", [([400, 300, 250, 200, 100], (2, 3, 4)),
