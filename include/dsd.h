@@ -165,6 +165,22 @@ dsd_status dsd_clique_degrees(dsd_graph g, int h, int out_mem, uint64_t *deg,
                               uint64_t *num_cliques);
 
 /*
+ * dsd_clique_degrees for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, but the call allocates
+ * nothing (no hipMalloc, hipFree or pinned host memory).  Its working memory
+ * is one fixed device array of 112 MiB inside the library, which every GPU the
+ * library runs on holds until the process ends.  The caller still passes the
+ * output; the handle's CSR was allocated by dsd_build_csr.
+ * Limit: n <= 2^22 vertices (DSD_EINVAL beyond).  Calls on one GPU share the
+ * array: calls that overlap on one GPU (two threads, or two streams in
+ * flight) race and must be serialised by the caller.  Every other error as
+ * dsd_clique_degrees.
+ */
+dsd_status dsd_clique_degrees_noalloc(dsd_graph g, int h, int out_mem, uint64_t *deg,
+                                      uint64_t *num_cliques);
+
+/*
  * (k, Psi)-core decomposition (Definition 6, Algorithm 3): core[v] = the
  * clique-core number of v; *kmax = the largest one.  Computed by a
  * round-synchronous peel that removes every vertex of clique-degree <= k at

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdsd.so")
 SOURCES = ["primitives.hip", "csr.hip", "enum.hip", "tlist.hip", "peel.hip", "cc.hip", "api.hip", "pattern.hip", "batch.hip", "flow.hip", "exact.cpp",
-           "server.cpp"]
+           "server.cpp", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Werror=infinite-recursion", "-Werror=return-type",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]

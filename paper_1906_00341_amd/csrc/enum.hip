@@ -102,7 +102,7 @@ __global__ void k_classify(const int64_t *row_ptr, const int64_t *dag_off, const
 
 template <int R>
 static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t *lists, const int32_t *off,
-                          const int32_t *cnt, hipStream_t s, Scratch &sc) {
+                          const int32_t *cnt, hipStream_t s, Scratch &sc, int gs_blocks) {
     EnumCtx c = base;
     if (cnt[0]) {
         c.roots = lists + off[0];
@@ -136,7 +136,7 @@ static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t 
         }
         if (cnt[3]) {
             c.roots = lists + off[3];
-            int blocks = grid_for(cnt[3], 1, 512);
+            int blocks = grid_for(cnt[3], 1, gs_blocks);
             u64 *gS = sc.get_n<u64>((int64_t)blocks * 1280 * 20);
             k_engine_block<R, 1280, 12, 20, true, EnumCtx><<<blocks, BLOCK, 0, s>>>(c, g.row_ptr, g.col, g.dag_off,
                                                                                   cnt[3], nullptr, gS);
@@ -144,7 +144,7 @@ static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t 
         if (cnt[4]) {
             // hubs of out-degree 1281..2048: 32-word bitmap rows in global memory
             c.roots = lists + off[4];
-            int blocks = grid_for(cnt[4], 1, 512);
+            int blocks = grid_for(cnt[4], 1, gs_blocks);
             u64 *gS = sc.get_n<u64>((int64_t)blocks * 2048 * 32);
             k_engine_block<R, 2048, 12, 32, true, EnumCtx><<<blocks, BLOCK, 0, s>>>(c, g.row_ptr, g.col, g.dag_off,
                                                                                   cnt[4], nullptr, gS);
@@ -153,7 +153,7 @@ static void launch_engine(const DevGraph &g, const EnumCtx &base, const int32_t 
 }
 
 bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
-                    KernelTimes *kt) {
+                    KernelTimes *kt, int gs_blocks) {
     const int32_t n = g.n;
     if (n == 0) return true;
     if (h == 2) {
@@ -192,10 +192,10 @@ bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hip
         DSD_HIP(hipEventRecord(e0, s));
     }
     switch (R) {
-        case 2: launch_engine<2>(g, ctx, lists, off, hc, s, sc); break;
-        case 3: launch_engine<3>(g, ctx, lists, off, hc, s, sc); break;
-        case 4: launch_engine<4>(g, ctx, lists, off, hc, s, sc); break;
-        case 5: launch_engine<5>(g, ctx, lists, off, hc, s, sc); break;
+        case 2: launch_engine<2>(g, ctx, lists, off, hc, s, sc, gs_blocks); break;
+        case 3: launch_engine<3>(g, ctx, lists, off, hc, s, sc, gs_blocks); break;
+        case 4: launch_engine<4>(g, ctx, lists, off, hc, s, sc, gs_blocks); break;
+        case 5: launch_engine<5>(g, ctx, lists, off, hc, s, sc, gs_blocks); break;
         default: throw Error(-1, "h outside [2, 6]");
     }
     if (kt) {

@@ -67,8 +67,10 @@ void free_graph(DevGraph &g);
 // deg[r] (rank space, length n) = number of h-cliques containing r inside the
 // subgraph induced by mask (mask == nullptr: whole graph).  deg is
 // overwritten.  Returns false if the counts could overflow 64 bits.
+// gs_blocks caps the grid of the class whose bitmaps live in global scratch
+// (gs_blocks * 1280 * 20 words of sc).
 bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
-                    KernelTimes *kt = nullptr);
+                    KernelTimes *kt = nullptr, int gs_blocks = 512);
 
 // ---- triangle lists (h = 3) ----
 // Row v is pairs[2 voff[v] .. 2 voff[v+1]): a pair (a, b) for every triangle

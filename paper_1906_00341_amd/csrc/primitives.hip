@@ -25,6 +25,7 @@ constexpr size_t POOL_MAX = (size_t)16 << 30;
 }  // namespace
 
 Scratch::~Scratch() {
+    if (external_) return;
     for (auto &c : chunks_) (void)hipFree(c.first);
 }
 
@@ -52,6 +53,11 @@ void *thread_pinned() {
 }
 
 void Scratch::recycle() {
+    if (external_) {
+        cur_ = 0;
+        off_ = 0;
+        return;
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = -1;
     ChunkPool &P = chunk_pool();
@@ -85,6 +91,11 @@ void *Scratch::get(size_t bytes) {
         }
         cur_++;
         off_ = 0;
+    }
+    if (external_) {
+        cur_ = 0;
+        off_ = 0;
+        throw Error(-2, "the request needs more than the fixed scratch buffer holds");
     }
     size_t sz = bytes > min_chunk_ ? bytes : min_chunk_;
     char *p = nullptr;

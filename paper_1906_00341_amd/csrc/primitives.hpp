@@ -17,6 +17,9 @@ namespace dsd {
 class Scratch {
 public:
     explicit Scratch(size_t min_chunk = (size_t)64 << 20) : min_chunk_(min_chunk) {}
+    // a scratch over a caller-owned device buffer: it never allocates, frees
+    // or recycles the buffer; a request beyond it throws DSD_ENOMEM
+    Scratch(void *buf, size_t bytes) : min_chunk_(0), external_(true) { chunks_.push_back({(char *)buf, bytes}); }
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
     ~Scratch();
@@ -30,6 +33,7 @@ private:
     std::vector<std::pair<char *, size_t>> chunks_;
     size_t cur_ = 0, off_ = 0;
     size_t min_chunk_;
+    bool external_ = false;
 };
 
 // out[i] = sum_{j<i} in[j]; returns nothing, total = out[n-1] + in[n-1].  in == out allowed.

@@ -32,7 +32,7 @@ DSD_EBUSY, DSD_ETIMEDOUT, DSD_ECANCELED = -6, -7, -8
 OP_DEGREES, OP_CORE, OP_APP, OP_EXACT, OP_PEEL = 0, 1, 2, 3, 4
 OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT, "peel": OP_PEEL}
 
-EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees",
+EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees", "dsd_clique_degrees_noalloc",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
            "dsd_pattern_degrees", "dsd_pattern_core",
            "dsd_last_stats", "dsd_set_kernel_timing", "dsd_release_cache",
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.dsd_graph_free.argtypes = [P]
     lib.dsd_release_cache.argtypes = []
     lib.dsd_clique_degrees.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_clique_degrees_noalloc.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_clique_core.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
     lib.dsd_peel_app.argtypes = [P, I, I, P, C.POINTER(Rational), C.POINTER(I64), C.POINTER(I64)]
@@ -246,6 +247,16 @@ def clique_degrees(g: Graph, h: int, out=None):
     out, p, mem = _out_u64(g, out)
     mu = C.c_uint64()
     _check(_lib.dsd_clique_degrees(g.handle, int(h), mem, p, C.byref(mu)))
+    n, _ = g.info()
+    return out[:n] if isinstance(out, np.ndarray) else out, int(mu.value)
+
+
+def clique_degrees_noalloc(g: Graph, h: int, out=None):
+    """dsd_clique_degrees_noalloc -> (deg[n], mu): the same results with no
+    device allocation (a fixed scratch array inside the library)."""
+    out, p, mem = _out_u64(g, out)
+    mu = C.c_uint64()
+    _check(_lib.dsd_clique_degrees_noalloc(g.handle, int(h), mem, p, C.byref(mu)))
     n, _ = g.info()
     return out[:n] if isinstance(out, np.ndarray) else out, int(mu.value)
 
