@@ -15,10 +15,11 @@ the exact step's flow network (about four arcs per clique) cannot be built
 in device memory; the library refuses it with DSD_EUNSUPPORTED after the
 locate step, and the step records that refusal.
 
-Further legs: the same graph at h = 5, the Chung-Lu graph (n = 10^6, h = 3,
-where CoreExact runs to the end), the batched mixture (8,192 graphs, batched
-vs a plain per-graph loop), the server under load, and the CPU oracle on a
-bounded sample of the headline family.
+Further legs: the Chung-Lu graph (n = 10^6, h = 3, where CoreExact runs to
+the end), the batched mixture (8,192 graphs, batched vs a plain per-graph
+loop), the server under load, and the CPU oracle on a bounded sample of the
+headline family.  The same R-MAT graph at h = 5 is a leg on request
+(``--legs rmat22_h5:1``): its step takes minutes.
 
 Prints one JSON line.  ``value`` is whole-pass throughput in h-cliques/s
 (mu(G, Psi) divided by the time of one step).
@@ -57,6 +58,11 @@ PAPER_FIGURES = {
     "core_app_vs_peel_app_triangle": {"SSCA n=1e5": 20, "R-MAT n=1e5": 201},
     "note": "CoreApp wall times at h = 2 from the paper's EMcore comparison table; speed-ups from section 8",
 }
+
+
+def say(msg: str):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def make_graph(name: str, seed: int):
@@ -212,20 +218,29 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
         g.free()
         return rec
 
-    for _ in range(warmup):
+    def progress(what, t):
+        say(f"{name} {what}: {1000.0 * (time.perf_counter() - t):.0f} ms")
+
+    for i in range(warmup):
+        t = time.perf_counter()
         step()
+        progress(f"warmup step {i + 1}/{warmup}", t)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         recs.append(step())
+        # one line per step, after it (the host already waited for its results)
+        progress(f"timed step {i + 1}/{steps}", t0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / steps
     # one more step, right after the timed ones, with every launch of the
     # peel's main kernels bracketed by HIP events on the graph's stream (each
     # bracketed launch costs the host ~20 us, so the timed steps run without)
+    t = time.perf_counter()
     inst = step(time_kernels=True)["core"]
+    progress("step with per-launch kernel timing", t)
 
     core = recs[-1]["core"]
     ex = recs[-1]["exact"]
@@ -307,6 +322,7 @@ def cpu_baseline(workload: str, seed: int):
         n, s, d = synth.chung_lu(seed=seed, **dict(w["kw"], n=600_000))
         stages = "clique-degrees + core decomposition + CoreApp"
     g = oracle.Graph(n, s, d)
+    say(f"cpu baseline: oracle on n={n}, h={h}")
     t0 = time.perf_counter()
     _, mu = g.clique_degrees(h)
     g.core_decomposition(h)
@@ -314,6 +330,7 @@ def cpu_baseline(workload: str, seed: int):
     if workload == "er_2000":
         g.exact(h, "core")
     t = time.perf_counter() - t0
+    say(f"cpu baseline: {t:.1f} s")
     return {"value": mu / t, "unit": "h-cliques/s", "cores": 1, "kind": "oracle",
             "sample": f"{w['gen']} generator of {workload} at n={n} (m={g.m}, h={h}, mu={mu}); {stages}; "
                       f"{t:.2f} s, one thread"}
@@ -350,6 +367,7 @@ def batch_leg(n_graphs: int, seed: int):
         dsd.clique_core(g, h)
         mu += g.stats()["num_cliques"]
     t_plain = time.perf_counter() - t0
+    say(f"batch leg: plain loop over {n_graphs} graphs {t_plain:.2f} s")
     # every graph again, from scratch: the batch must not reuse the plain
     # loop's cached decompositions
     for g in handles:
@@ -363,6 +381,7 @@ def batch_leg(n_graphs: int, seed: int):
     t0 = time.perf_counter()
     res = dsd.batch_run(handles, hs, "core")
     t_batch = time.perf_counter() - t0
+    say(f"batch leg: one batch {t_batch:.2f} s")
     assert all(r["status"] == 0 for r in res)
     assert sum(r["num_cliques"] for r in res) == mu
     m = sum(g.info()[1] for g in handles)
@@ -421,6 +440,7 @@ def serve_leg(n_requests: int, seed: int):
                 raise
             refused_plain += 1
     t_plain = time.perf_counter() - t0
+    say(f"serve leg: {n_requests} sequential plain calls {t_plain:.2f} s")
     for g in handles:
         g.free()
 
@@ -459,9 +479,11 @@ def serve_leg(n_requests: int, seed: int):
         return total, served, refused
 
     t_sat, _, refused = run(None)
+    say(f"serve leg: saturation pass {t_sat:.2f} s")
     served_n = n_requests - refused
     qps_sat = served_n / t_sat
     t_half, lat, _ = run(0.5 * n_requests / t_sat)
+    say(f"serve leg: half-rate pass {t_half:.2f} s")
     srv.close()
     lat_ms = np.sort(np.asarray(lat)) * 1000.0
     return {"requests": n_requests, "rmat20_requests": n_rmat, "mix": "70% app / 20% core / 10% exact",
@@ -480,7 +502,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22_h4", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--legs", default="chung_lu_1e6:5,rmat22_h5:1",
+    ap.add_argument("--legs", default="chung_lu_1e6:5",
                     help="further workloads as name:steps, comma-separated ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=8192,

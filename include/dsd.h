@@ -125,10 +125,12 @@ typedef struct {
     uint64_t locate_components;
     /* k4_main_kind 6: row entries the peel's main kernel scanned; the
      * second kernel of those rounds (the clique counting), timed like the
-     * main kernel */
+     * main kernel, and the 64-bit bitmap words it ANDed and counted at its
+     * first level (all of its work for h = 4; counted with the kernel's work) */
     uint64_t k4_main_entries;
     double k4_main2_ms;
     uint64_t k4_main2_launches;
+    uint64_t k4_main2_words;
 } dsd_stats;
 
 /*

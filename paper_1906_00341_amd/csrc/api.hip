@@ -77,6 +77,7 @@ void end_stats(dsd_graph_s *G, const KernelTimes &kt) {
     G->stats.k4_main_entries = kt.main_entries;
     G->stats.k4_main2_ms = kt.main2_ms;
     G->stats.k4_main2_launches = kt.main2_launches;
+    G->stats.k4_main2_words = kt.main2_words;
     G->stats.k4_launches = kt.k4_launches;
     G->stats.k4_main_kind = (uint64_t)kt.main_kind;
     G->stats.k4_tail_ms = kt.tail_ms;
@@ -477,6 +478,7 @@ dsd_status dsd_build_csr(int32_t n, int64_t num_pairs, const int32_t *src, const
         G->stats.t_total_ms = tm.stop();
         G->stats.t_orient_ms = t;
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         *out = holder.release();
         return DSD_OK;
     })
@@ -521,6 +523,7 @@ dsd_status dsd_clique_degrees(dsd_graph G, int h, int out_mem, uint64_t *deg, ui
         check_h(h);
         if (G->g.n > 0) check_out(deg, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         u64 *d = G->sc.get_n<u64>(G->g.n);
@@ -542,6 +545,7 @@ dsd_status dsd_clique_core(dsd_graph G, int h, int out_mem, uint64_t *core, uint
         check_h(h);
         if (G->g.n > 0) check_out(core, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         const Decomp &D = decompose(G, h);
@@ -724,6 +728,7 @@ dsd_status dsd_core_app(dsd_graph G, int h, int out_mem, uint8_t *member, uint64
         const int32_t n = G->g.n;
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         uint8_t *best = G->sc.get_n<uint8_t>(n);
@@ -743,6 +748,7 @@ dsd_status dsd_peel_app(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_ra
         const int32_t n = G->g.n;
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         uint8_t *best = G->sc.get_n<uint8_t>(n);
@@ -768,6 +774,7 @@ dsd_status dsd_core_exact_query(dsd_graph G, int h, int32_t nq, const int32_t *q
         const int32_t n = G->g.n;
         check_out(member, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         uint8_t *res = G->sc.get_n<uint8_t>(n);
@@ -786,6 +793,7 @@ dsd_status dsd_core_exact(dsd_graph G, int h, int out_mem, uint8_t *member, dsd_
         const int32_t n = G->g.n;
         if (n > 0) check_out(member, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         uint8_t *res = G->sc.get_n<uint8_t>(n);

@@ -342,6 +342,7 @@ void run_app_alone(dsd_graph_s *Gi, int h, int out_mem, void *out, dsd_result &r
     auto t0 = std::chrono::steady_clock::now();
     const int32_t n = Gi->g.n;
     Gi->sc.reset();
+    ScratchRelease release_scratch{Gi};
     begin_stats(Gi);
     uint8_t *best = Gi->sc.get_n<uint8_t>(n);
     dsd_rational dens{0, 1};
@@ -365,6 +366,7 @@ void run_exact(dsd_graph_s *Gi, int h, int out_mem, void *out, dsd_result &r) {
     auto t0 = std::chrono::steady_clock::now();
     const int32_t n = Gi->g.n;
     Gi->sc.reset();
+    ScratchRelease release_scratch{Gi};
     begin_stats(Gi);
     uint8_t *res = Gi->sc.get_n<uint8_t>(n);
     const dsd_rational rho = core_exact_run(Gi, h, res);

@@ -41,6 +41,7 @@ struct KernelTimes {
     u64 main_entries = 0;   // h >= 4 root mode: row entries scanned for the frontier vertices' C_v
     double main2_ms = 0;    // h >= 4 root mode: the counting kernel, timed like the main kernel
     u64 main2_launches = 0;
+    u64 main2_words = 0;    // h >= 4 root mode: 64-bit bitmap words the counting kernel ANDed and counted (first level)
     int main_kind = 0;   // 1 edge pass, 2 triangle probe, 3 triangle lists, 4 x-star frontier pass, 5 4-loop pass,
                         // 6 h >= 4 root-mode block kernel
     bool time_main = false;   // bracket every main-kernel launch with HIP events (main_ms)

@@ -49,6 +49,18 @@ struct dsd_graph_s {
 
 namespace dsd {
 
+// A call's scratch goes back to the shared chunk pool when the call returns
+// (error or not), once the handle's stream is idle: an idle handle holds only
+// its own arrays (keep), so thousands of handles cost their CSRs, not a
+// scratch chunk each.
+struct ScratchRelease {
+    dsd_graph_s *G;
+    ~ScratchRelease() {
+        (void)hipStreamSynchronize(G->stream);
+        G->sc.recycle();
+    }
+};
+
 // records the message for dsd_last_error and returns the status
 dsd_status fail(int st, const std::string &msg);
 

@@ -112,6 +112,7 @@ dsd_status dsd_pattern_degrees(dsd_graph G, int pattern, int x, int out_mem, uin
         const int32_t n = G->g.n;
         if (n > 0) check_out(deg, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         Timer tm(G->stream);
         u64 *d = G->sc.get_n<u64>(n);
@@ -132,6 +133,7 @@ dsd_status dsd_pattern_core(dsd_graph G, int pattern, int x, int out_mem, uint64
         const int32_t n = G->g.n;
         if (n > 0) check_out(core, out_mem);
         G->sc.reset();
+        ScratchRelease release_scratch{G};
         begin_stats(G);
         hipStream_t s = G->stream;
         Timer tm(s);

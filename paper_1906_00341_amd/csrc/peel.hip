@@ -78,7 +78,9 @@ struct PeelCtl {
     int32_t nTouch;    // x-star pattern: survivors whose degree fell this round
     int32_t nBig[2];   // h >= 4 root mode: single-workgroup items of the frontier
     int32_t ticket;    // root mode: workgroups of the counting kernel that have finished (0 between rounds)
-    u64 work[3];       // main kernel's pairs, neighbours and (h >= 4) row entries over the whole peel (when counted)
+    int64_t hprev;     // root mode: arena words the previous round used (its half is cleared in this round)
+    u64 work[4];       // main kernel's pairs, neighbours and (h >= 4) row entries, counting kernel's bitmap
+                       // words, over the whole peel (when counted)
 };
 
 // one graph of the batch (a single graph is a batch of one)
@@ -87,6 +89,7 @@ struct GraphState {
     u64 kcand;         // smallest alive degree, gathered when a level opens
     u64 mu_alive;      // cliques among the graph's alive vertices
     u64 destroyed;     // cliques destroyed in this round
+    u64 destroyed_m;   // root mode: per-member counts of this round's cliques (each clique h - 1 times)
     int64_t n_alive;
     int64_t lv_base;   // first entry of the graph's level table
     int32_t nF[2];     // the graph's frontier sizes
@@ -140,10 +143,9 @@ struct PeelBufs {
     int32_t rootmode;    // h >= 4: the frontier vertices' own cliques (k_root_edges / k_root_count)
     int64_t *Big;        // [2][bigcap] root mode: (v << 32 | chunk) single-workgroup items
     int64_t bigcap;
-    u64 *rbits;          // [2][rcap] root mode: bitmap rows of G[C_v] for the sliced vertices
+    u64 *rbits;          // [2][rcap] root mode: bitmap rows of the sliced vertices' neighbourhoods
     int64_t rcap;
-    int64_t *rbase;      // [n] first word of v's bitmap rows in its round's half
-    int32_t *rdone;      // [n] counting workgroups of v that have finished (0 between rounds)
+    int64_t *rbase;      // [n] first word of v's region in its round's half
 };
 
 constexpr int SMALL_DEG = 64;           // h = 3: larger frontier vertices are split into chunks
@@ -163,11 +165,12 @@ constexpr int ROOT_SUB = ROOT_SL / WAVES_PER_BLOCK;  // workgroups per slice: on
 
 // words per bitmap row of a vertex whose row holds d entries (|C_v| <= d)
 __device__ __forceinline__ int root_words(int64_t d) { return d <= 256 ? 4 : d <= 768 ? 12 : d <= 1280 ? 20 : 32; }
-// words of a sliced vertex's region: bitmap rows (d * W), member counts (d),
-// the owner mask (W), then the members' ids (two per word) and their number
+// words of a sliced vertex's region: one bitmap row per entry of v's row
+// (d * W; bit j of row i: entries i and j are adjacent), then the mask of
+// the entries that take part in v's cliques (W)
 __device__ __forceinline__ int64_t root_region(int64_t d) {
     const int W = root_words(d);
-    return d * W + d + W + (d + 1) / 2 + 1;
+    return d * W + W;
 }
 constexpr u64 ESET_EMPTY = ~0ull;
 
@@ -571,8 +574,9 @@ __device__ __forceinline__ void finish_graph(const PeelBufs &b, int32_t g) {
         s.kcand = ~0ull;
     }
     s.n_alive -= s.nF[cur];
-    s.mu_alive -= s.destroyed;
+    s.mu_alive -= s.destroyed + (s.destroyed_m ? s.destroyed_m / (u64)(b.h - 1) : 0ull);
     s.destroyed = 0;
+    s.destroyed_m = 0;
     s.nF[cur] = 0;
     s.sel = (s.nF[nx] == 0 && s.n_alive > 0) ? 1 : 0;
     if (s.sel) atomicAdd(&c->nsel[nx], 1);
@@ -592,6 +596,7 @@ __device__ __forceinline__ void finish_global(PeelCtl *c) {
     c->nB[cur] = 0;
     c->nT[cur] = 0;
     c->nTouch = 0;
+    c->hprev = c->htop[cur];
     c->htop[cur] = 0;
     c->nW = 0;
     c->nBig[cur] = 0;
@@ -1773,18 +1778,6 @@ __device__ __forceinline__ void add_work3(const PeelBufs &b, u64 pairs, u64 cand
     }
 }
 
-// C'_v: the neighbours of v alive at the start of the round (frontier
-// members included).  A stamp only changes within a round from ALIVE to the
-// round's number or the next one's, so every workgroup of v, in both
-// kernels, finds the same list in the same (rank) order.  The owner rule is
-// applied afterwards through a mask: the members that are frontier vertices
-// of smaller rank than v take no part in v's cliques.
-struct RootStable {
-    PeelBufs b;
-    int32_t r;
-    __device__ __forceinline__ bool accept(int64_t, int32_t x) const { return b.stamp[x] >= r; }
-};
-
 // A single-workgroup item (v, chunk) of Big: v's whole C_v in one workgroup
 // (its chunk 0), or, when C_v exceeds ROOT_CAP members, the (h-2)-cliques of
 // N+(w) ∩ C_v for every neighbour w of this chunk.
@@ -1861,19 +1854,28 @@ __device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
     return lo < n && a[lo] == x ? lo : -1;
 }
 
-// Arc discovery.  Sliced vertices (rows of ROOT_WAVE_MAX + 1 .. ROOT_CAP
-// entries): an item (v, slice) stands for ROOT_SUB workgroups; each builds
-// C'_v in LDS and gives each of its waves one member x, whose lanes walk
-// N+(x) and find their entries in C'_v by binary search (both lists are in
-// rank order), setting both bits of every arc of G[C'_v] in v's bitmap rows
+// cliques counted per member of a sliced vertex (each clique once for every
+// one of its h - 1 members besides v)
+__device__ __forceinline__ void add_destroyed_m(const PeelBufs &b, int32_t v, u64 t) {
+    if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed_m, t);
+}
+
+// Arc discovery.  A sliced vertex v (a row of ROOT_WAVE_MAX + 1 .. ROOT_CAP
+// entries) has a region in this round's half of the arena: one bitmap row
+// per entry of v's row, indexed by row position, and the mask of the entries
+// that take part in v's cliques (alive, and not a frontier vertex of smaller
+// rank: the owner rule).  An item (v, slice) stands for ROOT_SUB
+// workgroups; each copies v's row to LDS and gives each of its waves one
+// entry x, whose lanes walk N+(x) and find their entries in v's row by
+// binary search (both are in rank order), setting both bits of every arc
 // (each arc is found once, from its lower end).  The first workgroup of v
-// also stores C'_v, its size and the owner mask in v's region.  Wave items
-// (rows of at most ROOT_WAVE_MAX entries): one wave does the whole count,
-// C_v in one 64-bit word per member.
+// also writes the mask.  Wave items (rows of at most ROOT_WAVE_MAX entries):
+// one wave does the whole count, C_v in one 64-bit word per member.  Before
+// any of that, the previous round's regions in the other half are cleared:
+// nothing reads them any more, and the next round allocates there.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
-    __shared__ int32_t sC[ROOT_CAP];
-    __shared__ int32_t wtmp[WAVES_PER_BLOCK];
+    __shared__ int32_t sR[ROOT_CAP];
     __shared__ int32_t wC[WAVES_PER_BLOCK][64];
     __shared__ int32_t wKey[WAVES_PER_BLOCK][128];
     __shared__ int32_t wVal[WAVES_PER_BLOCK][128];
@@ -1885,6 +1887,12 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     const int32_t cur = c->cur;
     if (c->nF[cur] == 0) return;
     const int32_t r = c->round, nG = c->nB[cur], nI = c->nT[cur];
+    {
+        const int64_t hz = c->hprev < b.rcap ? c->hprev : b.rcap;
+        u64 *old = b.rbits + (size_t)(cur ^ 1) * b.rcap;
+        for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < hz; i += (int64_t)gridDim.x * BLOCK)
+            old[i] = 0;
+    }
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     u64 *bits = b.rbits + (size_t)cur * b.rcap;
     const int wv = threadIdx.x / WAVE, L = lane();
@@ -1896,37 +1904,38 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
         if (b.deg[v] == 0) continue;                   // block-uniform: fixed in v's round
         const int64_t s0 = b.row_ptr[v];
         const int d = (int)(b.row_ptr[v + 1] - s0);    // <= ROOT_CAP for a sliced vertex
-        const int m0 = sl * ROOT_SL + sub * WAVES_PER_BLOCK;
-        const int dd = block_load_candidates(RootStable{b, r}, 0, b.col, s0, d, sC, wtmp);
+        for (int i = threadIdx.x; i < d; i += BLOCK) sR[i] = b.col[s0 + i];
+        __syncthreads();
         const int W = root_words(d);
         u64 *S = bits + b.rbase[v];
         if (sl == 0 && sub == 0) {
-            // C'_v, its size and the owner mask, for the counting kernel
-            entries += (u64)d;
-            cands += (u64)dd;
-            u64 *mask = S + (int64_t)d * W + d;
-            int32_t *ids = (int32_t *)(mask + W);
-            for (int i = threadIdx.x; i < dd; i += BLOCK) ids[i] = sC[i];
-            for (int q = threadIdx.x; q < W; q += BLOCK) {
-                u64 wmask = 0;
-                for (int j = 0; j < 64 && q * 64 + j < dd; j++) {
-                    const int32_t x = sC[q * 64 + j];
-                    if (allowed(b.stamp[x], r, x, v)) wmask |= 1ull << j;
+            // the mask: wave wv takes word base / 64 + wv of each pass
+            u64 *mask = S + (int64_t)d * W;
+            for (int base = 0; base < W * 64; base += BLOCK) {
+                const int i = base + threadIdx.x;
+                bool ok = false;
+                if (i < d) {
+                    const int32_t x = sR[i];
+                    ok = allowed(b.stamp[x], r, x, v);
                 }
-                mask[q] = wmask;
+                const u64 bm = __ballot(ok);
+                if (L == 0 && (i >> 6) < W) mask[i >> 6] = bm;
+                if (L == 0) cands += (u64)__popcll(bm);
             }
-            if (threadIdx.x == 0) ((int64_t *)ids)[(d + 1) / 2] = dd;
+            if (threadIdx.x == 0) entries += (u64)d;
         }
-        const int m = m0 + wv;
-        if (dd >= R && m < dd) {
-            const int32_t x = sC[m];
-            const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
-            if (L == 0) pairs += (u64)(o1 - o0);
-            for (int64_t e = o0 + L; e < o1; e += WAVE) {
-                const int j = lds_find(sC, dd, b.col[e]);
-                if (j >= 0) {
-                    atomicOr(&S[(size_t)m * W + (j >> 6)], 1ull << (j & 63));
-                    atomicOr(&S[(size_t)j * W + (m >> 6)], 1ull << (m & 63));
+        const int m = sl * ROOT_SL + sub * WAVES_PER_BLOCK + wv;
+        if (m < d) {
+            const int32_t x = sR[m];
+            if (allowed(b.stamp[x], r, x, v)) {            // wave-uniform
+                const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
+                if (L == 0) pairs += (u64)(o1 - o0);
+                for (int64_t e = o0 + L; e < o1; e += WAVE) {
+                    const int j = lds_find(sR, d, b.col[e]);
+                    if (j >= 0) {
+                        atomicOr(&S[(size_t)m * W + (j >> 6)], 1ull << (j & 63));
+                        atomicOr(&S[(size_t)j * W + (m >> 6)], 1ull << (m & 63));
+                    }
                 }
             }
         }
@@ -2005,87 +2014,76 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     }
     if (L == 0) tally.flush(b);
     if (b.count_work) {
-        // lane 0 of every wave: its wave items and its members' probes;
-        // thread 0 also the stored lists'
-        add_work3(b, wpairs + (L == 0 ? pairs : 0), wcands + (threadIdx.x == 0 ? cands : 0),
+        // lane 0 of every wave: its wave items, its entries' probes and the
+        // masks it wrote; thread 0 also the scanned rows
+        add_work3(b, wpairs + (L == 0 ? pairs : 0), wcands + (L == 0 ? cands : 0),
                   wentries + (threadIdx.x == 0 ? entries : 0));
     }
 }
 
-// One member x of a sliced vertex's C'_v, on one wave: the cliques of v
-// through x, from the bitmap rows (S, W words each, restricted to the owner
-// mask).  As first member x passes to every y above it the count of the
-// cliques x < y < ... (lanes take the y's, 64 at a time); as last member it
-// counts the (R-1)-cliques below it.  The counts of y and x go to cnt
-// (global, v's region); returns the number with x first (every lane).
+// One entry x of a sliced vertex v's row, on one wave: the R-cliques of v's
+// candidate graph that hold x, i.e. the (R-1)-cliques among x's neighbours
+// there, N = row x & mask (in LDS).  Lanes take the members y of N (through
+// a queue of 2 * WAVE ids, 64 at a time) and count the (R-2)-cliques above y
+// in N & N(y).  Returns the count to every lane; *words gets the 64-bit
+// words this lane ANDed and counted at the first level.
 template <int R, int W>
-__device__ u64 root_member_work(int x, const u64 *S, const u64 *mask, u64 *cnt, int32_t *q) {
+__device__ u64 root_own_work(int x, const u64 *S, const u64 *mask, u64 *sN, int32_t *q, u64 *words) {
     const int L = lane();
-    u64 A[W], B[W];
+    for (int w = L; w < W; w += WAVE) sN[w] = S[(size_t)x * W + w] & mask[w];
+    __builtin_amdgcn_wave_barrier();
+    u64 c = 0, nw = 0;
+    auto drain = [&](int take) {
+        if (L < take) {
+            const int y = q[L];
+            nw += (u64)(W - (y >> 6));
+            if constexpr (R == 3) {
+                for (int k = y >> 6; k < W; k++) c += (u64)__popcll(sN[k] & row_above<W>(S, y, k));
+            } else {
+                u64 M2[W];
 #pragma unroll
-    for (int w = 0; w < W; w++) {
-        A[w] = row_above<W>(S, x, w) & mask[w];
-        B[w] = row_below<W>(S, x, w) & mask[w];
-    }
-    u64 first = 0, last = 0;
-    for (int role = 0; role < 2; role++) {
-        int qn = 0;
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            const u64 m = role == 0 ? A[w] : B[w];
-            if (((m >> L) & 1ull) != 0) q[qn + __popcll(m & lanemask_lt())] = w * 64 + L;
-            qn += __popcll(m);
-            __builtin_amdgcn_wave_barrier();
-            if (qn >= WAVE || (w == W - 1 && qn > 0)) {
-                const int take = qn < WAVE ? qn : WAVE;
-                if (L < take) {
-                    const int y = q[L];
-                    u64 M2[W];
-#pragma unroll
-                    for (int k = 0; k < W; k++) M2[k] = (role == 0 ? A[k] : B[k]) & row_above<W>(S, y, k);
-                    if (role == 0) {
-                        u64 cy;
-                        if constexpr (R == 3) cy = popc_w<W>(M2);
-                        else cy = forward<R - 3, W>(M2, S, cnt);
-                        if (cy) {
-                            atomicAdd(&cnt[y], cy);
-                            first += cy;
-                        }
-                    } else {
-                        if constexpr (R == 3) last += popc_w<W>(M2);
-                        else last += count_in<R - 2, W>(M2, S);
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                // the rest of the queue to its front
-                const int rest = qn - take;
-                int32_t keep = 0;
-                if (L < rest) keep = q[take + L];
-                __builtin_amdgcn_wave_barrier();
-                if (L < rest) q[L] = keep;
-                qn = rest;
-                __builtin_amdgcn_wave_barrier();
+                for (int k = 0; k < W; k++) M2[k] = sN[k] & row_above<W>(S, y, k);
+                c += count_in<R - 2, W>(M2, S);
             }
         }
+        __builtin_amdgcn_wave_barrier();
+    };
+    int qn = 0;
+    for (int w = 0; w < W; w++) {
+        const u64 m = sN[w];
+        if (((m >> L) & 1ull) != 0) q[qn + __popcll(m & lanemask_lt())] = w * 64 + L;
+        qn += __popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        if (qn >= WAVE) {
+            drain(WAVE);
+            // the rest of the queue (fewer than WAVE ids) to its front
+            const int rest = qn - WAVE;
+            int32_t keep = 0;
+            if (L < rest) keep = q[WAVE + L];
+            __builtin_amdgcn_wave_barrier();
+            if (L < rest) q[L] = keep;
+            qn = rest;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
-    first = wave_sum(first);
-    last = wave_sum(last);
-    if (L == 0 && first + last) atomicAdd(&cnt[x], first + last);
-    return first;
+    if (qn > 0) drain(qn);
+    *words += nw;
+    return wave_sum(c);
 }
 
 template <int R>
-__device__ u64 root_member(int x, int W, const u64 *S, const u64 *mask, u64 *cnt, int32_t *q) {
-    if (W == 4) return root_member_work<R, 4>(x, S, mask, cnt, q);
-    if (W == 12) return root_member_work<R, 12>(x, S, mask, cnt, q);
-    if (W == 20) return root_member_work<R, 20>(x, S, mask, cnt, q);
-    return root_member_work<R, 32>(x, S, mask, cnt, q);
+__device__ u64 root_own(int x, int W, const u64 *S, const u64 *mask, u64 *sN, int32_t *q, u64 *words) {
+    if (W == 4) return root_own_work<R, 4>(x, S, mask, sN, q, words);
+    if (W == 12) return root_own_work<R, 12>(x, S, mask, sN, q, words);
+    if (W == 20) return root_own_work<R, 20>(x, S, mask, sN, q, words);
+    return root_own_work<R, 32>(x, S, mask, sN, q, words);
 }
 
-// Counting.  Sliced vertices: one wave per member of C'_v that the owner
-// mask allows; the last workgroup of v hands the members' counts to their
-// degrees and clears v's region for later rounds.  Single-workgroup items
-// follow.
+// Counting.  Sliced vertices: one wave per entry of v's row that the mask
+// lets take part; the wave counts the cliques of v that hold its entry x
+// and takes them off x's degree at once (x a survivor).  No entry waits for
+// another: each clique is counted once by every one of its members.
+// Single-workgroup items follow.
 // fin (one graph, outside tail mode): the last workgroup also ends the round.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int fin) {
@@ -2097,49 +2095,29 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int f
     const bool any = c->nF[cur] != 0;
     const int32_t r = c->round, nG = any ? c->nB[cur] : 0, nBig = any ? c->nBig[cur] : 0;
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
-    u64 *bits = b.rbits + (size_t)cur * b.rcap;
+    const u64 *bits = b.rbits + (size_t)cur * b.rcap;
     const int wv = threadIdx.x / WAVE;
-    u64 pairs = 0, cands = 0, entries = 0;
-    for (int64_t it = blockIdx.x; it < (int64_t)nG * ROOT_SUB; it += gridDim.x) {
-        const int64_t item = Bc[it / ROOT_SUB];
+    u64 pairs = 0, cands = 0, entries = 0, words = 0;
+    // wave tasks: entry (slice item, offset) of a sliced vertex
+    const int64_t ntask = (int64_t)nG * ROOT_SL, nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+    for (int64_t t = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; t < ntask; t += nwaves) {
+        const int64_t item = Bc[t / ROOT_SL];
         const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
-        const int sub = (int)(it % ROOT_SUB);
+        const int m = sl * ROOT_SL + (int)(t % ROOT_SL);
         if (b.deg[v] == 0) continue;                   // its items made no arcs either
-        const int d = (int)(b.row_ptr[v + 1] - b.row_ptr[v]);
+        const int64_t s0 = b.row_ptr[v];
+        const int d = (int)(b.row_ptr[v + 1] - s0);
+        if (m >= d) continue;
         const int W = root_words(d);
-        u64 *S = bits + b.rbase[v];
-        u64 *cnt = S + (int64_t)d * W;
-        const u64 *mask = cnt + d;
-        const int32_t *ids = (const int32_t *)(mask + W);
-        const int dd = (int)((const int64_t *)ids)[(d + 1) / 2];
-        const int m = sl * ROOT_SL + sub * WAVES_PER_BLOCK + wv;
-        u64 t = 0;
-        if (dd >= R && m < dd && ((mask[m >> 6] >> (m & 63)) & 1ull))
-            t = root_member<R>(m, W, S, mask, cnt, sAB[wv][0], sAB[wv][1], sQ[wv]);
-        if (lane() == 0 && t) add_destroyed(b, v, t);
-        // completion: the last workgroup of v flushes the counts and clears
-        // the region.  Every thread fences first: its atomics on v's counts
-        // must be performed before its workgroup counts itself done.
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int nsl = (d + ROOT_SL - 1) / ROOT_SL;
-            L.wtmp[0] = atomicAdd(&b.rdone[v], 1) == nsl * ROOT_SUB - 1 ? 1 : 0;
+        const u64 *S = bits + b.rbase[v];
+        const u64 *mask = S + (int64_t)d * W;
+        if (((mask[m >> 6] >> (m & 63)) & 1ull) == 0) continue;
+        const u64 cx = root_own<R>(m, W, S, mask, sAB[wv][0], sQ[wv], &words);
+        if (cx && lane() == 0) {
+            const int32_t x = b.col[s0 + m];
+            if (b.stamp[x] > r) dec_deg(b, x, cx, r);
+            add_destroyed_m(b, v, cx);
         }
-        __syncthreads();
-        if (L.wtmp[0]) {
-            __threadfence();
-            for (int i = threadIdx.x; i < dd; i += BLOCK) {
-                const u64 ci = cnt[i];
-                const int32_t x = ids[i];
-                if (ci && b.stamp[x] > r) dec_deg(b, x, ci, r);
-            }
-            __syncthreads();                           // every count and id read before the region is cleared
-            const int64_t words = root_region(d);
-            for (int64_t i = threadIdx.x; i < words; i += BLOCK) S[i] = 0;
-            if (threadIdx.x == 0) b.rdone[v] = 0;
-        }
-        __syncthreads();
     }
     const int64_t *Gc = b.Big + (size_t)cur * b.bigcap;
     u64 *Sg = gS + (size_t)blockIdx.x * ROOT_SLICE;
@@ -2148,8 +2126,11 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int f
         root_big_item<R>(b, (int32_t)(item >> 32), (int32_t)(item & 0xffffffff), r, L, Sg, pairs, cands, entries,
                          sAB[wv][0], sAB[wv][1], sQ[wv]);
     }
-    if (b.count_work) add_work3(b, threadIdx.x == 0 ? pairs : 0, threadIdx.x == 0 ? cands : 0,
-                                threadIdx.x == 0 ? entries : 0);
+    if (b.count_work) {
+        add_work3(b, threadIdx.x == 0 ? pairs : 0, threadIdx.x == 0 ? cands : 0, threadIdx.x == 0 ? entries : 0);
+        const u64 wsum = wave_sum(words);
+        if (lane() == 0 && wsum) atomicAdd(&c->work[3], wsum);
+    }
     if (fin) {
         // the last workgroup to finish ends the round (what k_finish_one
         // does); every thread's writes are performed before its workgroup
@@ -3373,16 +3354,14 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         b.bigcap = (int64_t)n + 2 * g.m / ROOT_CAP + 1;
         b.Big = sc.get_n<int64_t>(2 * b.bigcap);
         // bitmap rows of one round's sliced vertices (a vertex that finds no
-        // room becomes a single-workgroup item); cleared once here, then by
-        // the last counting workgroup of every vertex that used them
+        // room becomes a single-workgroup item); cleared once here, then a
+        // round's regions by the next round's arc-discovery kernel
         b.rcap = std::min<int64_t>((int64_t)1 << 26, std::max<int64_t>((int64_t)1 << 16, 16 * g.m));
         // DSD_ROOT_ARENA_WORDS overrides the arena size (0: every vertex a single-workgroup item)
         if (const char *ra = std::getenv("DSD_ROOT_ARENA_WORDS")) b.rcap = std::max<int64_t>(1, std::atoll(ra));
         b.rbits = sc.get_n<u64>(2 * b.rcap);
         fill_u64(b.rbits, 0, 2 * b.rcap, s);
         b.rbase = sc.get_n<int64_t>(n);
-        b.rdone = sc.get_n<int32_t>(n);
-        fill_i32(b.rdone, 0, n, s);
         gSr = sc.get_n<u64>((int64_t)ROOT_GRID * ROOT_SLICE);
     } else if (h >= 4) {
         // a vertex joins at most one frontier; its chunks number <= 1 + deg / CHUNK4
@@ -3548,6 +3527,7 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         kt->main_pairs += fin.work[0];
         kt->main_nbrs += fin.work[1];
         kt->main_entries += fin.work[2];
+        kt->main2_words += fin.work[3];
     }
     res.rounds = fin.round;
     res.graph_levels.resize(G);

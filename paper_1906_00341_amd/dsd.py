@@ -70,7 +70,8 @@ class Stats(C.Structure):
                 ("locate_rho1_num", C.c_uint64), ("locate_rho1_den", C.c_uint64), ("locate_k1", C.c_uint64),
                 ("locate_rho2_num", C.c_uint64), ("locate_rho2_den", C.c_uint64), ("locate_k2", C.c_uint64),
                 ("locate_components", C.c_uint64), ("k4_main_entries", C.c_uint64),
-                ("k4_main2_ms", C.c_double), ("k4_main2_launches", C.c_uint64)]
+                ("k4_main2_ms", C.c_double), ("k4_main2_launches", C.c_uint64),
+                ("k4_main2_words", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
