@@ -77,7 +77,6 @@ struct PeelCtl {
     int32_t pending;   // tail mode: a round has been started and not yet finished
     int32_t nTouch;    // x-star pattern: survivors whose degree fell this round
     int32_t nBig[2];   // h >= 4 root mode: single-workgroup items of the frontier
-    int32_t ticket;    // root mode: workgroups of the counting kernel that have finished (0 between rounds)
     int64_t hprev;     // root mode: arena words the previous round used (its half is cleared in this round)
     u64 work[4];       // main kernel's pairs, neighbours and (h >= 4) row entries, counting kernel's bitmap
                        // words, over the whole peel (when counted)
@@ -2083,10 +2082,11 @@ __device__ u64 root_own(int x, int W, const u64 *S, const u64 *mask, u64 *sN, in
 // lets take part; the wave counts the cliques of v that hold its entry x
 // and takes them off x's degree at once (x a survivor).  No entry waits for
 // another: each clique is counted once by every one of its members.
-// Single-workgroup items follow.
-// fin (one graph, outside tail mode): the last workgroup also ends the round.
+// Single-workgroup items follow.  (The round ends in its own kernel: ending
+// it in the last workgroup to finish would cost every workgroup a
+// device-scope fence, which writes back its L2, every round.)
 template <int R>
-__global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int fin) {
+__global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
     __shared__ RootLds L;
     __shared__ int32_t sQ[WAVES_PER_BLOCK][2 * WAVE];
     __shared__ u64 sAB[WAVES_PER_BLOCK][2][32];
@@ -2130,21 +2130,6 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS, int f
         add_work3(b, threadIdx.x == 0 ? pairs : 0, threadIdx.x == 0 ? cands : 0, threadIdx.x == 0 ? entries : 0);
         const u64 wsum = wave_sum(words);
         if (lane() == 0 && wsum) atomicAdd(&c->work[3], wsum);
-    }
-    if (fin) {
-        // the last workgroup to finish ends the round (what k_finish_one
-        // does); every thread's writes are performed before its workgroup
-        // counts itself done
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (atomicAdd(&c->ticket, 1) == (int32_t)gridDim.x - 1) {
-                __threadfence();
-                c->ticket = 0;
-                finish_graph(b, 0);
-                finish_global(c);
-            }
-        }
     }
 }
 
@@ -3453,19 +3438,18 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                 main_timer.launch(k_h3_probe, dim3(gp), dim3(BLOCK), s, b);
                 k_h3_flush<<<gf, BLOCK, 0, s>>>(b);
             } else if (rootmode) {
-                const int fin = !tail && G == 1 ? 1 : 0;
                 switch (h) {
                     case 4:
                         main_timer.launch(k_root_edges<3>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<3>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        main2_timer.launch(k_root_count<3>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
                         break;
                     case 5:
                         main_timer.launch(k_root_edges<4>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<4>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        main2_timer.launch(k_root_count<4>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
                         break;
                     case 6:
                         main_timer.launch(k_root_edges<5>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<5>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr, fin);
+                        main2_timer.launch(k_root_count<5>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
                         break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
@@ -3480,8 +3464,6 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
             }
             if (tail) {
                 // the next k_tail_level ends this round
-            } else if (rootmode && G == 1) {
-                // the counting kernel's last workgroup ended it
             } else if (G == 1) {
                 k_finish_one<<<1, 1, 0, s>>>(b);
             } else {
