@@ -109,11 +109,24 @@ def main_kernel_bytes(st: dict) -> float:
     return 4.0 * st["k4_main_pairs"] + 20.0 * st["k4_main_nbrs"]
 
 
-def main2_kernel_bytes(st: dict) -> float:
-    """Counting of h >= 4 (k_root_count): every member of a candidate set C_v
-    its stamp, and an 8-byte read-modify-write of its degree when it loses
-    cliques (4 + 16 B).  Its bitmap rows are scratch that stays in L2."""
-    return 20.0 * st["k4_main_nbrs"]
+# Integer ALU peak for the counting kernel's unit of work, one 64-bit bitmap
+# word ANDed and counted: two 32-bit ANDs and two 32-bit popcounts (each
+# adding into the running count), 4 VALU operations per lane; 256 CUs x 4
+# SIMDs x 16 lanes issue 64 lane-operations per CU per clock at 2.4 GHz.
+ALU_WORD_PEAK = 256 * 64 * 2.4e9 / 4 / 1e12     # 9.83 Tword/s
+
+
+def roof_alu(kernel, total_ms, launches, words):
+    """Roofline of a kernel bound by integer ALU work on bitmap words."""
+    launches = max(launches, 1)
+    words_call = words / launches
+    ms_call = total_ms / launches
+    achieved = words_call / (ms_call / 1e3) / 1e12 if ms_call > 0 else 0.0
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": ALU_WORD_PEAK,
+            "unit": "Tword/s (64-bit AND + popcount)", "frac": achieved / ALU_WORD_PEAK, "traffic": None,
+            "words_per_launch": words_call, "ms_per_launch": ms_call, "launches_per_step": launches,
+            "ms_per_step": total_ms,
+            "timing": "HIP events around every launch of one extra step after the timed ones"}
 
 
 def k4_bytes(st: dict, h: int) -> float:
@@ -121,11 +134,13 @@ def k4_bytes(st: dict, h: int) -> float:
     every edge from both ends (32 B per edge); h = 3 reads the out-list of
     every neighbour of every removed vertex (4 B per entry of
     sum_v deg(v) d+(v)) and decrements survivors (24 B per edge); h >= 4
-    the bytes of its two kernels above."""
+    the arc-discovery kernel's bytes above, plus, for the counting kernel,
+    every member's stamp and an 8-byte read-modify-write of its degree
+    (20 B; its bitmap rows are the arc kernel's output, read from L2)."""
     if h == 2:
         return 32.0 * st["m"]
     if h >= 4 and st["k4_main_kind"] == 6:
-        return main_kernel_bytes(st) + main2_kernel_bytes(st)
+        return main_kernel_bytes(st) + 20.0 * st["k4_main_nbrs"]
     return 4.0 * st["s2"] + 24.0 * st["m"]
 
 
@@ -254,8 +269,9 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
     cands[0].update({"pairs_per_step": inst["k4_main_pairs"], "members_per_step": inst["k4_main_nbrs"],
                      "row_entries_per_step": inst["k4_main_entries"]})
     if kind in MAIN2_KERNEL:
-        r2 = roof(MAIN2_KERNEL[kind], name, inst["k4_main2_ms"], inst["k4_main2_launches"],
-                  main2_kernel_bytes(inst))
+        # k_root_count: the bitmap words it ANDs and counts (its first level:
+        # all of its work at h = 4) against the ALU peak
+        r2 = roof_alu(MAIN2_KERNEL[kind], inst["k4_main2_ms"], inst["k4_main2_launches"], inst["k4_main2_words"])
         r2.update({"members_per_step": inst["k4_main_nbrs"]})
         cands.append(r2)
     if inst["k4_tail_launches"]:

@@ -2078,16 +2078,17 @@ __device__ u64 root_own(int x, int W, const u64 *S, const u64 *mask, u64 *sN, in
     return root_own_work<R, 32>(x, S, mask, sN, q, words);
 }
 
-// Counting.  Sliced vertices: one wave per entry of v's row that the mask
-// lets take part; the wave counts the cliques of v that hold its entry x
-// and takes them off x's degree at once (x a survivor).  No entry waits for
-// another: each clique is counted once by every one of its members.
-// Single-workgroup items follow.  (The round ends in its own kernel: ending
-// it in the last workgroup to finish would cost every workgroup a
-// device-scope fence, which writes back its L2, every round.)
-template <int R>
+// Counting.  SLICED: one wave per entry of a sliced vertex v's row that the
+// mask lets take part; the wave counts the cliques of v that hold its entry
+// x and takes them off x's degree at once (x a survivor).  No entry waits
+// for another: each clique is counted once by every one of its members.
+// BIG: the single-workgroup items, whose 56 KB of LDS would hold the sliced
+// counting to two workgroups per CU; they run as a launch of their own.
+// (The round ends in its own kernel too: ending it in the last workgroup to
+// finish would cost every workgroup a device-scope fence, which writes back
+// its L2, every round.)
+template <int R, bool SLICED, bool BIG>
 __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
-    __shared__ RootLds L;
     __shared__ int32_t sQ[WAVES_PER_BLOCK][2 * WAVE];
     __shared__ u64 sAB[WAVES_PER_BLOCK][2][32];
     PeelCtl *c = b.ctl;
@@ -2099,7 +2100,7 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
     const int wv = threadIdx.x / WAVE;
     u64 pairs = 0, cands = 0, entries = 0, words = 0;
     // wave tasks: entry (slice item, offset) of a sliced vertex
-    const int64_t ntask = (int64_t)nG * ROOT_SL, nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+    const int64_t ntask = SLICED ? (int64_t)nG * ROOT_SL : 0, nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
     for (int64_t t = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; t < ntask; t += nwaves) {
         const int64_t item = Bc[t / ROOT_SL];
         const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
@@ -2119,12 +2120,18 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
             add_destroyed_m(b, v, cx);
         }
     }
-    const int64_t *Gc = b.Big + (size_t)cur * b.bigcap;
-    u64 *Sg = gS + (size_t)blockIdx.x * ROOT_SLICE;
-    for (int64_t it = blockIdx.x; it < nBig; it += gridDim.x) {
-        const int64_t item = Gc[it];
-        root_big_item<R>(b, (int32_t)(item >> 32), (int32_t)(item & 0xffffffff), r, L, Sg, pairs, cands, entries,
-                         sAB[wv][0], sAB[wv][1], sQ[wv]);
+    if constexpr (BIG) {
+        __shared__ RootLds L;
+        const int64_t *Gc = b.Big + (size_t)cur * b.bigcap;
+        u64 *Sg = gS + (size_t)blockIdx.x * ROOT_SLICE;
+        for (int64_t it = blockIdx.x; it < nBig; it += gridDim.x) {
+            const int64_t item = Gc[it];
+            root_big_item<R>(b, (int32_t)(item >> 32), (int32_t)(item & 0xffffffff), r, L, Sg, pairs, cands,
+                             entries, sAB[wv][0], sAB[wv][1], sQ[wv]);
+        }
+    } else {
+        (void)nBig;
+        (void)gS;
     }
     if (b.count_work) {
         add_work3(b, threadIdx.x == 0 ? pairs : 0, threadIdx.x == 0 ? cands : 0, threadIdx.x == 0 ? entries : 0);
@@ -3441,15 +3448,18 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
                 switch (h) {
                     case 4:
                         main_timer.launch(k_root_edges<3>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<3>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        main2_timer.launch(k_root_count<3, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        k_root_count<3, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
                         break;
                     case 5:
                         main_timer.launch(k_root_edges<4>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<4>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        main2_timer.launch(k_root_count<4, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        k_root_count<4, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
                         break;
                     case 6:
                         main_timer.launch(k_root_edges<5>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<5>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        main2_timer.launch(k_root_count<5, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
+                        k_root_count<5, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
                         break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
