@@ -77,7 +77,6 @@ struct PeelCtl {
     int32_t pending;   // tail mode: a round has been started and not yet finished
     int32_t nTouch;    // x-star pattern: survivors whose degree fell this round
     int32_t nBig[2];   // h >= 4 root mode: single-workgroup items of the frontier
-    int64_t hprev;     // root mode: arena words the previous round used (its half is cleared in this round)
     u64 work[4];       // main kernel's pairs, neighbours and (h >= 4) row entries, counting kernel's bitmap
                        // words, over the whole peel (when counted)
 };
@@ -165,8 +164,9 @@ constexpr int ROOT_SUB = ROOT_SL / WAVES_PER_BLOCK;  // workgroups per slice: on
 // words per bitmap row of a vertex whose row holds d entries (|C_v| <= d)
 __device__ __forceinline__ int root_words(int64_t d) { return d <= 256 ? 4 : d <= 768 ? 12 : d <= 1280 ? 20 : 32; }
 // words of a sliced vertex's region: one bitmap row per entry of v's row
-// (d * W; bit j of row i: entries i and j are adjacent), then the mask of
-// the entries that take part in v's cliques (W)
+// (d * W; bit j > i of row i: entries i and j are adjacent; only the words
+// from i / 64 up are written), then the mask of the entries that take part
+// in v's cliques (W)
 __device__ __forceinline__ int64_t root_region(int64_t d) {
     const int W = root_words(d);
     return d * W + W;
@@ -595,7 +595,6 @@ __device__ __forceinline__ void finish_global(PeelCtl *c) {
     c->nB[cur] = 0;
     c->nT[cur] = 0;
     c->nTouch = 0;
-    c->hprev = c->htop[cur];
     c->htop[cur] = 0;
     c->nW = 0;
     c->nBig[cur] = 0;
@@ -1866,12 +1865,13 @@ __device__ __forceinline__ void add_destroyed_m(const PeelBufs &b, int32_t v, u6
 // rank: the owner rule).  An item (v, slice) stands for ROOT_SUB
 // workgroups; each copies v's row to LDS and gives each of its waves one
 // entry x, whose lanes walk N+(x) and find their entries in v's row by
-// binary search (both are in rank order), setting both bits of every arc
-// (each arc is found once, from its lower end).  The first workgroup of v
-// also writes the mask.  Wave items (rows of at most ROOT_WAVE_MAX entries):
-// one wave does the whole count, C_v in one 64-bit word per member.  Before
-// any of that, the previous round's regions in the other half are cleared:
-// nothing reads them any more, and the next round allocates there.
+// binary search (both are in rank order), setting the bit of every arc
+// (each arc is found once, from its lower end, and set in the lower end's
+// row, which the wave builds in LDS and writes out whole: rows hold only the
+// bits above their own entry, so no region needs clearing and no arc an
+// atomic in global memory).  The first workgroup of v also writes the mask.
+// Wave items (rows of at most ROOT_WAVE_MAX entries): one wave does the
+// whole count, C_v in one 64-bit word per member.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     __shared__ int32_t sR[ROOT_CAP];
@@ -1882,16 +1882,11 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     __shared__ int64_t wSt[WAVES_PER_BLOCK][64];
     __shared__ u64 wCnt[WAVES_PER_BLOCK][64];
     __shared__ u64 wS[WAVES_PER_BLOCK][64];
+    __shared__ u64 wRow[WAVES_PER_BLOCK][32];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
     if (c->nF[cur] == 0) return;
     const int32_t r = c->round, nG = c->nB[cur], nI = c->nT[cur];
-    {
-        const int64_t hz = c->hprev < b.rcap ? c->hprev : b.rcap;
-        u64 *old = b.rbits + (size_t)(cur ^ 1) * b.rcap;
-        for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < hz; i += (int64_t)gridDim.x * BLOCK)
-            old[i] = 0;
-    }
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     u64 *bits = b.rbits + (size_t)cur * b.rcap;
     const int wv = threadIdx.x / WAVE, L = lane();
@@ -1927,15 +1922,19 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
         if (m < d) {
             const int32_t x = sR[m];
             if (allowed(b.stamp[x], r, x, v)) {            // wave-uniform
+                // the upper part of row m (bits j > m) in LDS, then written
+                // out whole from word m / 64 on
+                u64 *rw = wRow[wv];
+                for (int w = L; w < W; w += WAVE) rw[w] = 0;
+                __builtin_amdgcn_wave_barrier();
                 const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
                 if (L == 0) pairs += (u64)(o1 - o0);
                 for (int64_t e = o0 + L; e < o1; e += WAVE) {
                     const int j = lds_find(sR, d, b.col[e]);
-                    if (j >= 0) {
-                        atomicOr(&S[(size_t)m * W + (j >> 6)], 1ull << (j & 63));
-                        atomicOr(&S[(size_t)j * W + (m >> 6)], 1ull << (m & 63));
-                    }
+                    if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
                 }
+                __builtin_amdgcn_wave_barrier();
+                for (int w = (m >> 6) + L; w < W; w += WAVE) S[(size_t)m * W + w] = rw[w];
             }
         }
         __syncthreads();
@@ -2022,14 +2021,26 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
 
 // One entry x of a sliced vertex v's row, on one wave: the R-cliques of v's
 // candidate graph that hold x, i.e. the (R-1)-cliques among x's neighbours
-// there, N = row x & mask (in LDS).  Lanes take the members y of N (through
+// there, N (in LDS): the bits above x from row x, those below x from the
+// rows of the entries before it (bit x of each), restricted to the mask.  Lanes take the members y of N (through
 // a queue of 2 * WAVE ids, 64 at a time) and count the (R-2)-cliques above y
 // in N & N(y).  Returns the count to every lane; *words gets the 64-bit
 // words this lane ANDed and counted at the first level.
 template <int R, int W>
 __device__ u64 root_own_work(int x, const u64 *S, const u64 *mask, u64 *sN, int32_t *q, u64 *words) {
-    const int L = lane();
-    for (int w = L; w < W; w += WAVE) sN[w] = S[(size_t)x * W + w] & mask[w];
+    const int L = lane(), xw = x >> 6;
+    // x's neighbours: above x from its own row, below x from bit x of the
+    // rows before it (one 64-bit ballot per 64 rows)
+    for (int w = L; w < W; w += WAVE) sN[w] = w >= xw ? S[(size_t)x * W + w] : 0ull;
+    __builtin_amdgcn_wave_barrier();
+    for (int j0 = 0; j0 < x; j0 += WAVE) {
+        const int j = j0 + L;
+        const bool bit = j < x && ((S[(size_t)j * W + xw] >> (x & 63)) & 1ull);
+        const u64 bw = __ballot(bit);
+        if (L == 0) sN[j0 >> 6] |= bw;
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int w = L; w < W; w += WAVE) sN[w] &= mask[w];
     __builtin_amdgcn_wave_barrier();
     u64 c = 0, nw = 0;
     auto drain = [&](int take) {
@@ -3346,13 +3357,12 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         b.bigcap = (int64_t)n + 2 * g.m / ROOT_CAP + 1;
         b.Big = sc.get_n<int64_t>(2 * b.bigcap);
         // bitmap rows of one round's sliced vertices (a vertex that finds no
-        // room becomes a single-workgroup item); cleared once here, then a
-        // round's regions by the next round's arc-discovery kernel
+        // room becomes a single-workgroup item); every word read is written
+        // in the same round (or masked out), so nothing is cleared
         b.rcap = std::min<int64_t>((int64_t)1 << 26, std::max<int64_t>((int64_t)1 << 16, 16 * g.m));
         // DSD_ROOT_ARENA_WORDS overrides the arena size (0: every vertex a single-workgroup item)
         if (const char *ra = std::getenv("DSD_ROOT_ARENA_WORDS")) b.rcap = std::max<int64_t>(1, std::atoll(ra));
         b.rbits = sc.get_n<u64>(2 * b.rcap);
-        fill_u64(b.rbits, 0, 2 * b.rcap, s);
         b.rbase = sc.get_n<int64_t>(n);
         gSr = sc.get_n<u64>((int64_t)ROOT_GRID * ROOT_SLICE);
     } else if (h >= 4) {
