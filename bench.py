@@ -320,8 +320,9 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
 
 def cpu_baseline(workload: str, seed: int):
     """The CPU oracle, single-threaded, on a bounded sample of the workload's
-    family.  R-MAT: the same generator at scale 14 (16,384 vertices),
-    clique-degrees + core decomposition + CoreApp at the workload's h.
+    family.  R-MAT: the same generator at scale 15 (32,768 vertices; about
+    20 s of one core), clique-degrees + core decomposition + CoreApp at the
+    workload's h.
     Chung-Lu: the same generator at n = 600,000, the same stages.  ER: the
     whole 2,000-vertex graph and the whole path."""
     import oracle
@@ -332,7 +333,7 @@ def cpu_baseline(workload: str, seed: int):
         n, s, d = synth.er_planted(seed=seed, **w["kw"])
         stages = "clique-degrees + core decomposition + CoreApp + CoreExact"
     elif w["gen"] == "rmat":
-        n, s, d = synth.rmat(seed=seed, **dict(w["kw"], scale=14))
+        n, s, d = synth.rmat(seed=seed, **dict(w["kw"], scale=15))
         stages = "clique-degrees + core decomposition + CoreApp"
     else:
         n, s, d = synth.chung_lu(seed=seed, **dict(w["kw"], n=600_000))

@@ -156,14 +156,24 @@ def induced(og, mask):
 def test_rmat22_higher_order_cliques(rmat22, h):
     """R-MAT scale 22 (n = 4,194,304, 67,108,864 edge draws): the oracle
     cannot list its 10^11 - 10^13 cliques, so the decomposition is checked by
-    what pins it at any size: clique-degrees of sampled vertices against the
-    oracle, sum of degrees = h mu, core <= degree, every sampled level set
-    R_c = {core >= c} has least clique-degree exactly c inside itself
-    (counted by a separate enumeration of its induced subgraph), and the
-    vertex of least
-    clique-degree in each such R_c, which certifies it, has the same count in
-    the oracle.  At h = 4 CoreApp must return exactly the k_max-core, with
-    the density the separate count gives it."""
+    what pins it at any size.
+      * sum of degrees = h mu, core <= degree;
+      * clique-degrees across the whole degree range: 48 sampled vertices of
+        degree <= 1,500 against the oracle; the 20 largest hubs and 20
+        vertices sampled from degree ranks 20 .. 20,000 against the
+        (h-1)-cliques of their induced neighbourhoods, counted by a separate
+        enumeration (another graph, another h), with the oracle recounting
+        those of at most 2*10^7;
+      * every level set R_c = {core >= c} of the top region (at h = 4 every
+        level whose R_c has at most 30,000 vertices, up to 300 levels; at
+        h = 5, where every R_c holds the 10^12 cliques of the k_max-core,
+        the 12 highest levels of at most 4,000 vertices) has least
+        clique-degree exactly c
+        inside itself (so R_c is a c-core and c is the degree at which its
+        level opens), counted by a separate enumeration of its induced
+        subgraph; for sampled levels the oracle recounts the vertex of least
+        degree; at h = 4 CoreApp returns exactly the k_max-core with the
+        density that separate count gives it."""
     n, og, g = rmat22
     deg_g, mu_g = dsd.clique_degrees(g, h)
     core_g, km = dsd.clique_core(g, h)
@@ -172,36 +182,85 @@ def test_rmat22_higher_order_cliques(rmat22, h):
     assert (core_g <= deg_g).all()
     assert int(core_g.max()) == km
 
-    off, _ = og.adjacency()
+    off, adj = og.adjacency()
     deg = np.diff(off)
+    rows = np.repeat(np.arange(og.n, dtype=np.int32), deg)
     rng = np.random.default_rng(100 + h)
     sample = rng.choice(np.nonzero((deg >= 1) & (deg <= 1500))[0], 48, replace=False)
     for v in sample:
         assert og.clique_degree_of(h, int(v)) == int(deg_g[v]), int(v)
 
+    # hubs: the h-cliques through v are the (h-1)-cliques of G[N(v)]
+    by_deg = np.argsort(-deg, kind="stable")
+    hubs = np.concatenate([by_deg[:20], by_deg[rng.choice(np.arange(20, 20_000), 20, replace=False)]])
+    oracle_hubs = 0
+    upper = rows < adj
+    for v in hubs:
+        nb = adj[off[v]:off[v + 1]]
+        inn = np.zeros(og.n, bool)
+        inn[nb] = True
+        e = upper & inn[rows] & inn[adj]
+        loc = np.full(og.n, -1, np.int64)
+        loc[nb] = np.arange(nb.size)
+        s2, d2 = loc[rows[e]].astype(np.int32), loc[adj[e]].astype(np.int32)
+        sub = dsd.build_csr(nb.size, s2, d2)
+        _, mu_nb = dsd.clique_degrees(sub, h - 1)
+        sub.free()
+        assert mu_nb == int(deg_g[v]), (int(v), int(deg[v]))
+        if mu_nb <= 20_000_000:
+            assert oracle.Graph(nb.size, s2, d2).clique_degrees(h - 1)[1] == mu_nb, int(v)
+            oracle_hubs += 1
+    print(f"  hubs: {hubs.size} checked (max degree {int(deg[by_deg[0]])}), {oracle_hubs} recounted by the oracle",
+          flush=True)
+
+    mem_app = dens_app = None
     if h == 4:
         mem_app, km_app, dens_app = dsd.core_app(g, h)
         np.testing.assert_array_equal(mem_app.astype(bool), core_g == km)
         assert km_app == km
 
-    # sampled level sets, top first: each must be a c-core; the vertex of
-    # least clique-degree inside it (the one that certifies that) is recounted
-    # by the oracle on the induced subgraph
-    levels = np.unique(core_g)
+    # the top region: the highest levels, each R_c of at most 4,000 vertices
+    lv, cnt = np.unique(core_g, return_counts=True)
+    levels, sizes = lv[::-1], np.cumsum(cnt[::-1])
+    ntop, vmax = (300, 30_000) if h == 4 else (12, 4_000)
+    top = levels[:ntop][sizes[:ntop] <= vmax]
+    assert top.size >= 1 and top[0] == km
+    region = core_g >= top[-1]
+    ridx = np.nonzero(region)[0]
+    e = upper & region[rows] & region[adj]
+    rl = np.full(og.n, -1, np.int64)
+    rl[ridx] = np.arange(ridx.size)
+    rs, rd = rl[rows[e]], rl[adj[e]]
+    rcore = core_g[ridx]
     checked = 0
-    for c in levels[np.linspace(1, levels.size - 1, 4).astype(int)][::-1]:
+    picks = set(np.linspace(0, top.size - 1, 4).astype(int).tolist())
+    for i, c in enumerate(top):
+        keep = rcore >= c
+        ke = keep[rs] & keep[rd]
+        sub_idx = np.nonzero(keep)[0]
+        sl = np.full(ridx.size, -1, np.int64)
+        sl[sub_idx] = np.arange(sub_idx.size)
+        s2, d2 = sl[rs[ke]].astype(np.int32), sl[rd[ke]].astype(np.int32)
+        sub = dsd.build_csr(sub_idx.size, s2, d2)
+        d_in, mu_in = dsd.clique_degrees(sub, h)
+        sub.free()
+        j = int(np.argmin(d_in))
+        # R_c is a c-core, and c is the smallest degree when its level opens
+        assert int(d_in[j]) == int(c), int(c)
+        if h == 4 and c == km:
+            assert dens_app == Fraction(mu_in, sub_idx.size)
+        if i in picks and int(d_in[j]) <= 200_000_000:
+            assert oracle.Graph(sub_idx.size, s2, d2).clique_degree_of(h, j) == int(d_in[j])
+            checked += 1
+    print(f"  top region: {top.size} level sets of up to {ridx.size} vertices checked, {checked} oracle recounts",
+          flush=True)
+    # sampled level sets below the top region, each a c-core
+    low = levels[levels < top[-1]]
+    for c in low[np.linspace(0, low.size - 1, 5).astype(int)[1:-1]]:
         mask = core_g >= c
         idx, s2, d2 = induced(og, mask)
         sub = dsd.build_csr(idx.size, s2, d2)
         d_in, mu_in = dsd.clique_degrees(sub, h)
-        j = int(np.argmin(d_in))
-        print(f"  R_{int(c)}: {idx.size} vertices, {mu_in} cliques, least degree {int(d_in[j])}", flush=True)
-        # R_c is a c-core, and c is the smallest degree when its level opens
-        assert int(d_in[j]) == int(c), int(c)
-        if h == 4 and c == km:
-            assert dens_app == Fraction(mu_in, idx.size)
-        if int(d_in[j]) <= 200_000_000:
-            assert oracle.Graph(idx.size, s2, d2).clique_degree_of(h, j) == int(d_in[j])
-            checked += 1
         sub.free()
-    assert checked >= 2
+        print(f"  R_{int(c)}: {idx.size} vertices, least degree {int(d_in.min())}", flush=True)
+        assert int(d_in.min()) == int(c), int(c)
