@@ -3053,6 +3053,7 @@ template <int SLOT>
 class LaunchTimer {
 public:
     explicit LaunchTimer(bool want) : lk_(pool_mu(), std::try_to_lock) { on_ = want && lk_.owns_lock(); }
+    bool on() const { return on_; }
     // launch kernel k on s, timed when the timer is on
     template <typename... Args>
     void launch(void (*k)(Args...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
@@ -3095,6 +3096,24 @@ private:
     std::unique_lock<std::mutex> lk_;
     bool on_ = false;
     size_t used_ = 0;
+};
+
+// The captured round graphs of one peel (plain and tail mode) and the
+// stream they are captured on; destroyed with the peel, or when the
+// adjacency they name is compacted.
+struct RoundGraphs {
+    hipStream_t cs = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    void reset() {
+        for (auto &e : exec) {
+            if (e) (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    }
+    ~RoundGraphs() {
+        reset();
+        if (cs) (void)hipStreamDestroy(cs);
+    }
 };
 
 template <int R>
@@ -3426,70 +3445,97 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         compacted_at = n_alive;
     }
     const bool engine = (listed || h == 2) && G == 1 && !min_degree && pattern == 0;
+    // DSD_PEEL_GRAPH=1: every round's kernels replayed from a captured HIP
+    // graph instead of launched one by one (not with per-launch timing)
+    const char *pg = std::getenv("DSD_PEEL_GRAPH");
+    const bool use_graph = pg && pg[0] == '1' && !main_timer.on() && !main2_timer.on();
+    RoundGraphs graphs;
+    if (use_graph) DSD_HIP(hipStreamCreateWithFlags(&graphs.cs, hipStreamNonBlocking));
     while (n_alive > 0) {
         if (engine && n_alive <= TE_MAX && tail_engine(b, h, n, n_alive, s, sc, kt)) break;
         if (compacting && n_alive < compacted_at / 2) {
             compact_adjacency(b, s, sc);
             compacted_at = n_alive;
+            graphs.reset();
         }
         if (n_alive <= TAIL_ALIVE) tail = true;
         const int gp = tail ? gtail : gprobe, gq = tail ? gtail : gproc, gf = tail ? gtail : gbuild;
-        for (int64_t i = 0; i < chunk; i++) {
+        // one round's kernels; they read the round's state from the device,
+        // so the same sequence serves every round until the adjacency
+        // (a kernel argument) is compacted
+        auto one_round = [&](hipStream_t st) {
             if (tail) {
-                k_tail_level<<<1, TAIL_BLOCK, 0, s>>>(b);
+                k_tail_level<<<1, TAIL_BLOCK, 0, st>>>(b);
             } else {
-                k_level_min<<<gmin, BLOCK, 0, s>>>(b);
-                k_level_build<<<gbuild, BLOCK, 0, s>>>(b);
+                k_level_min<<<gmin, BLOCK, 0, st>>>(b);
+                k_level_build<<<gbuild, BLOCK, 0, st>>>(b);
             }
             if (b.pattern == 1) {
-                main_timer.launch(k_star_front, dim3(gq), dim3(BLOCK), s, b);
-                k_star_touch<<<gq, BLOCK, 0, s>>>(b);
+                main_timer.launch(k_star_front, dim3(gq), dim3(BLOCK), st, b);
+                k_star_touch<<<gq, BLOCK, 0, st>>>(b);
             } else if (b.pattern == 2) {
-                main_timer.launch(k_loop_process, dim3(gloop), dim3(BLOCK), s, b);
+                main_timer.launch(k_loop_process, dim3(gloop), dim3(BLOCK), st, b);
             } else if (h == 2) {
-                main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), s, b);
+                main_timer.launch(k_process_h2, dim3(gq), dim3(BLOCK), st, b);
             } else if (listed) {
-                main_timer.launch(k_tl_process, dim3(gp), dim3(BLOCK), s, b);
+                main_timer.launch(k_tl_process, dim3(gp), dim3(BLOCK), st, b);
             } else if (h == 3) {
-                k_h3_fill<<<gf, BLOCK, 0, s>>>(b);
-                main_timer.launch(k_h3_probe, dim3(gp), dim3(BLOCK), s, b);
-                k_h3_flush<<<gf, BLOCK, 0, s>>>(b);
+                k_h3_fill<<<gf, BLOCK, 0, st>>>(b);
+                main_timer.launch(k_h3_probe, dim3(gp), dim3(BLOCK), st, b);
+                k_h3_flush<<<gf, BLOCK, 0, st>>>(b);
             } else if (rootmode) {
                 switch (h) {
                     case 4:
-                        main_timer.launch(k_root_edges<3>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<3, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
-                        k_root_count<3, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
+                        main_timer.launch(k_root_edges<3>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), st, b);
+                        main2_timer.launch(k_root_count<3, true, false>, dim3(ROOT_GRID), dim3(BLOCK), st, b, gSr);
+                        k_root_count<3, false, true><<<ROOT_GRID, BLOCK, 0, st>>>(b, gSr);
                         break;
                     case 5:
-                        main_timer.launch(k_root_edges<4>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<4, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
-                        k_root_count<4, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
+                        main_timer.launch(k_root_edges<4>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), st, b);
+                        main2_timer.launch(k_root_count<4, true, false>, dim3(ROOT_GRID), dim3(BLOCK), st, b, gSr);
+                        k_root_count<4, false, true><<<ROOT_GRID, BLOCK, 0, st>>>(b, gSr);
                         break;
                     case 6:
-                        main_timer.launch(k_root_edges<5>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), s, b);
-                        main2_timer.launch(k_root_count<5, true, false>, dim3(ROOT_GRID), dim3(BLOCK), s, b, gSr);
-                        k_root_count<5, false, true><<<ROOT_GRID, BLOCK, 0, s>>>(b, gSr);
+                        main_timer.launch(k_root_edges<5>, dim3(ROOT_EDGE_GRID), dim3(BLOCK), st, b);
+                        main2_timer.launch(k_root_count<5, true, false>, dim3(ROOT_GRID), dim3(BLOCK), st, b, gSr);
+                        k_root_count<5, false, true><<<ROOT_GRID, BLOCK, 0, st>>>(b, gSr);
                         break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
             } else {
-                k_peel_items<<<gproc, BLOCK, 0, s>>>(b, R);
+                k_peel_items<<<gproc, BLOCK, 0, st>>>(b, R);
                 switch (R) {
-                    case 2: launch_peel_items<2>(b, s, gS, g.maxdout); break;
-                    case 3: launch_peel_items<3>(b, s, gS, g.maxdout); break;
-                    case 4: launch_peel_items<4>(b, s, gS, g.maxdout); break;
+                    case 2: launch_peel_items<2>(b, st, gS, g.maxdout); break;
+                    case 3: launch_peel_items<3>(b, st, gS, g.maxdout); break;
+                    case 4: launch_peel_items<4>(b, st, gS, g.maxdout); break;
                     default: throw Error(-1, "h outside [2, 6]");
                 }
             }
             if (tail) {
                 // the next k_tail_level ends this round
             } else if (G == 1) {
-                k_finish_one<<<1, 1, 0, s>>>(b);
+                k_finish_one<<<1, 1, 0, st>>>(b);
             } else {
-                k_finish_graphs<<<grid_for(G, 256), 256, 0, s>>>(b);
-                k_finish_global<<<1, 1, 0, s>>>(b);
+                k_finish_graphs<<<grid_for(G, 256), 256, 0, st>>>(b);
+                k_finish_global<<<1, 1, 0, st>>>(b);
             }
+        };
+        if (use_graph) {
+            hipGraphExec_t &ge = graphs.exec[tail ? 1 : 0];
+            if (!ge) {
+                // captured on a stream of its own (the graph's stream may be
+                // the null stream, which cannot be captured), replayed on s
+                DSD_HIP(hipStreamBeginCapture(graphs.cs, hipStreamCaptureModeThreadLocal));
+                one_round(graphs.cs);
+                hipGraph_t gr = nullptr;
+                DSD_HIP(hipStreamEndCapture(graphs.cs, &gr));
+                const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (ie != hipSuccess) throw Error(-3, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            for (int64_t i = 0; i < chunk; i++) DSD_HIP(hipGraphLaunch(ge, s));
+        } else {
+            for (int64_t i = 0; i < chunk; i++) one_round(s);
         }
         if (tail) k_tail_finish<<<1, TAIL_BLOCK, 0, s>>>(b);
         steps += chunk;
