@@ -183,6 +183,42 @@ dsd_status dsd_clique_degrees_noalloc(dsd_graph g, int h, int out_mem, uint64_t 
                                       uint64_t *num_cliques);
 
 /*
+ * Launch tuning of the clique enumeration (the configuration of this
+ * library's kernels, not a step of the method).  The enumeration bins DAG
+ * roots into classes by out-degree, one launch each: h >= 4: class 0 up to
+ * 64 (a wave per root), 1 up to 256, 2 up to 768, 3 up to 1,280 and 4 up to
+ * 2,048 (workgroups with bitmaps in LDS for 1-2, in global memory for 3-4);
+ * h = 3: class 0 up to 64, 1 up to 2,048, 2 larger.  Each launch's grid is
+ * capped (workgroups loop over the class's roots).
+ *
+ * dsd_autotune times every class present in g's roots at h in [3, 6] under
+ * a set of caps (the faster of two launches each), keeps the fastest cap per
+ * (GPU architecture, h, class) in a process-wide table that every later
+ * enumeration (single graphs, batches, peels' recounts) uses, and, with path
+ * non-NULL, writes the table to that JSON file, merged over the entries the
+ * file already holds: one flat object of "arch/hH/cC": cap pairs, e.g.
+ * "gfx950/h4/c2": 1024.  out (capacity cap entries, may be NULL with cap 0)
+ * receives one dsd_tune_result per measured class; *count (may be NULL) the
+ * number of measured classes.  Results never depend on the caps.
+ * dsd_tune_load replaces the table with a file's entries (path NULL: back
+ * to the built-in caps); DSD_EINVAL for an unreadable or malformed file.
+ * Without either call the environment variable DSD_TUNE_FILE, read once at
+ * the first enumeration, names a file to load (a missing or malformed one
+ * leaves the built-in caps).
+ */
+typedef struct {
+    int32_t cls;          /* class (above) */
+    int32_t roots;        /* roots in the class */
+    int32_t cap_default;  /* built-in grid cap, workgroups */
+    int32_t cap_best;     /* the fastest cap measured */
+    double ms_default;    /* one launch of the class at the built-in cap, ms */
+    double ms_best;       /* one launch at the chosen cap, ms */
+} dsd_tune_result;
+
+dsd_status dsd_autotune(dsd_graph g, int h, const char *path, int32_t cap, dsd_tune_result *out, int32_t *count);
+dsd_status dsd_tune_load(const char *path);
+
+/*
  * (k, Psi)-core decomposition (Definition 6, Algorithm 3): core[v] = the
  * clique-core number of v; *kmax = the largest one.  Computed by a
  * round-synchronous peel that removes every vertex of clique-degree <= k at

@@ -511,6 +511,33 @@ dsd_status dsd_release_cache(void) {
     return DSD_OK;
 }
 
+dsd_status dsd_autotune(dsd_graph G, int h, const char *path, int32_t cap, dsd_tune_result *out, int32_t *count) {
+    if (!G) return fail(DSD_EINVAL, "NULL graph");
+    if (cap < 0 || (cap > 0 && !out)) return fail(DSD_EINVAL, "bad result array");
+    if (h < 3 || h > 6) return fail(DSD_EINVAL, "tuning needs h in [3, 6]");
+    DSD_TRY({
+        check_device();
+        G->sc.reset();
+        ScratchRelease release_scratch{G};
+        const std::vector<TuneResult> res = autotune(G->g, h, G->stream, G->sc);
+        if (path) tune_write(path);
+        int32_t k = 0;
+        for (const TuneResult &r : res) {
+            if (k < cap) out[k] = dsd_tune_result{r.cls, r.roots, r.cap_default, r.cap_best, r.ms_default, r.ms_best};
+            k++;
+        }
+        if (count) *count = k;
+        return DSD_OK;
+    })
+}
+
+dsd_status dsd_tune_load(const char *path) {
+    DSD_TRY({
+        tune_load(path);
+        return DSD_OK;
+    })
+}
+
 dsd_status dsd_set_kernel_timing(dsd_graph g, int on) {
     if (!g) return fail(DSD_EINVAL, "NULL graph");
     g->time_main = on != 0;

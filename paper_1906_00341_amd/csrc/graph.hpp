@@ -8,6 +8,8 @@
 // rank_of.
 #pragma once
 
+#include <vector>
+
 #include "exact.hpp"
 #include "primitives.hpp"
 
@@ -72,6 +74,23 @@ void free_graph(DevGraph &g);
 // (gs_blocks * 1280 * 20 words of sc).
 bool clique_degrees(const DevGraph &g, int h, const uint8_t *mask, u64 *deg, hipStream_t s, Scratch &sc,
                     KernelTimes *kt = nullptr, int gs_blocks = 512);
+
+// ---- launch-grid tuning of the clique enumeration ----
+// One class's measurement: its roots, the default and the chosen grid cap
+// (workgroups), and the time of one launch at each (ms).
+struct TuneResult {
+    int cls;
+    int32_t roots;
+    int cap_default, cap_best;
+    double ms_default, ms_best;
+};
+// times every class of g's roots at h under a set of grid caps and keeps the
+// fastest in the process-wide table (key: architecture, h, class)
+std::vector<TuneResult> autotune(const DevGraph &g, int h, hipStream_t s, Scratch &sc);
+// replaces the table with the JSON file's entries (nullptr: back to the defaults)
+void tune_load(const char *path);
+// writes the table, merged over the file's existing entries, to path
+void tune_write(const char *path);
 
 // ---- triangle lists (h = 3) ----
 // Row v is pairs[2 voff[v] .. 2 voff[v+1]): a pair (a, b) for every triangle

@@ -33,6 +33,7 @@ OP_DEGREES, OP_CORE, OP_APP, OP_EXACT, OP_PEEL = 0, 1, 2, 3, 4
 OPS = {"degrees": OP_DEGREES, "core": OP_CORE, "app": OP_APP, "exact": OP_EXACT, "peel": OP_PEEL}
 
 EXPORTS = ["dsd_build_csr", "dsd_graph_info", "dsd_graph_free", "dsd_clique_degrees", "dsd_clique_degrees_noalloc",
+           "dsd_autotune", "dsd_tune_load",
            "dsd_clique_core", "dsd_core_app", "dsd_peel_app", "dsd_core_exact", "dsd_core_exact_query",
            "dsd_pattern_degrees", "dsd_pattern_core",
            "dsd_last_stats", "dsd_set_kernel_timing", "dsd_release_cache",
@@ -48,6 +49,14 @@ class DsdError(RuntimeError):
 
 class Rational(C.Structure):
     _fields_ = [("num", C.c_uint64), ("den", C.c_uint64)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("cls", C.c_int32), ("roots", C.c_int32), ("cap_default", C.c_int32), ("cap_best", C.c_int32),
+                ("ms_default", C.c_double), ("ms_best", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -114,6 +123,8 @@ def load(path: str = LIB_PATH):
     lib.dsd_release_cache.argtypes = []
     lib.dsd_clique_degrees.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_clique_degrees_noalloc.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
+    lib.dsd_autotune.argtypes = [P, I, C.c_char_p, I32, C.POINTER(TuneResult), C.POINTER(I32)]
+    lib.dsd_tune_load.argtypes = [C.c_char_p]
     lib.dsd_clique_core.argtypes = [P, I, I, P, C.POINTER(C.c_uint64)]
     lib.dsd_core_app.argtypes = [P, I, I, P, C.POINTER(C.c_uint64), C.POINTER(Rational)]
     lib.dsd_peel_app.argtypes = [P, I, I, P, C.POINTER(Rational), C.POINTER(I64), C.POINTER(I64)]
@@ -260,6 +271,25 @@ def clique_degrees_noalloc(g: Graph, h: int, out=None):
     _check(_lib.dsd_clique_degrees_noalloc(g.handle, int(h), mem, p, C.byref(mu)))
     n, _ = g.info()
     return out[:n] if isinstance(out, np.ndarray) else out, int(mu.value)
+
+
+def autotune(g: Graph, h: int, path=None):
+    """dsd_autotune -> one dict per measured class of the enumeration's
+    roots (class, roots, default and chosen grid caps, their launch times);
+    the chosen caps go to the library's table and, with path, to that JSON
+    file."""
+    cap = 8
+    res = (TuneResult * cap)()
+    cnt = C.c_int32()
+    p = None if path is None else os.fsencode(path)
+    _check(load().dsd_autotune(g.handle, int(h), p, cap, res, C.byref(cnt)))
+    return [res[i].as_dict() for i in range(min(cnt.value, cap))]
+
+
+def tune_load(path=None):
+    """dsd_tune_load: the enumeration's grid caps from a JSON file written by
+    autotune (None: back to the built-in caps)."""
+    _check(load().dsd_tune_load(None if path is None else os.fsencode(path)))
 
 
 def release_cache():

@@ -73,7 +73,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         import pytest
         pytest.skip("no C compiler")
-    structs = {"dsd_stats": dsd.Stats, "dsd_result": dsd.Result, "dsd_rational": dsd.Rational}
+    structs = {"dsd_stats": dsd.Stats, "dsd_result": dsd.Result, "dsd_rational": dsd.Rational,
+               "dsd_tune_result": dsd.TuneResult}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsd.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
