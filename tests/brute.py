@@ -75,11 +75,13 @@ def densest(n, edges, h):
     mu = np.zeros(allS.size, dtype=np.int64)
     for c in masks:
         mu += ((allS & c) == c)
-    size = np.array([bin(int(s)).count("1") for s in allS], dtype=np.int64)
+    size = np.zeros(allS.size, dtype=np.int64)
+    for v in range(n):
+        size += (allS >> v) & 1
     ratio = mu / size
     top = ratio.max()
     best = max(Fraction(int(mu[i]), int(size[i])) for i in np.nonzero(ratio >= top - 1e-9)[0])
-    arg = [int(allS[i]) for i in range(allS.size) if mu[i] * best.denominator == best.numerator * size[i]]
+    arg = allS[np.nonzero(mu * best.denominator == best.numerator * size)[0]].tolist()
     if best == 0:
         arg = []
     return best, arg

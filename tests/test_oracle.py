@@ -233,6 +233,22 @@ def test_bounds_and_exact_on_random_small(seed, h):
         assert km == kmax and h * dens >= best
 
 
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_exact_against_exhaustive_search_n20(seed, h):
+    """Algorithms 1 and 4 against the definition itself (Problem 1): the
+    densest of all 2^20 - 1 vertex subsets, and its maximisers."""
+    n = 20
+    edges = brute.random_graph(n, 0.45, 700 + 10 * seed + h)
+    g = G(n, edges)
+    best, argmax = brute.densest(n, edges, h)
+    for route in ("whole", "core"):
+        mem, rho, _ = g.exact(h, route)
+        assert rho == best, (route, rho, best)
+        if best > 0:
+            assert sum(1 << v for v in members(mem)) in set(argmax)
+
+
 # ------------------------------------------------------- Section 6.1 pruning
 
 def test_fig6_locate(fixtures):
@@ -337,6 +353,32 @@ def test_two_exact_routes_agree(seed):
             _, mu = brute.clique_degrees(n, edges, h, members(m)) if n <= 30 else (None, None)
             if mu is not None:
                 assert Fraction(mu, len(members(m))) == r1
+
+
+@pytest.mark.parametrize("chunk", range(20))
+def test_two_exact_routes_agree_many(chunk):
+    """Route 0 (Algorithm 1 on the whole graph) and route 1 (Algorithm 4 on
+    the located cores) on 500 random graphs of 8 - 200 vertices, h = 2 - 5
+    (25 per chunk): the same rho_opt, attained by both returned sets."""
+    rng = np.random.default_rng(9000 + chunk)
+    for _ in range(25):
+        n = int(rng.integers(8, 201))
+        h = int(rng.integers(2, 6))
+        p = float(rng.uniform(0.03, 0.25)) if n > 60 else float(rng.uniform(0.08, 0.5))
+        edges = brute.random_graph(n, p, int(rng.integers(1 << 30)))
+        g = G(n, edges)
+        m1, r1, _ = g.exact(h, "whole")
+        m2, r2, _ = g.exact(h, "core")
+        assert r1 == r2, (n, h, r1, r2)
+        if r1 > 0:
+            for m in (m1, m2):
+                sel = np.zeros(n, bool)
+                sel[members(m)] = True
+                sub = [(u, v) for u, v in edges if sel[u] and sel[v]]
+                idx = np.nonzero(sel)[0]
+                loc = {int(v): i for i, v in enumerate(idx)}
+                og = G(idx.size, [(loc[u], loc[v]) for u, v in sub])
+                assert Fraction(og.clique_degrees(h)[1], idx.size) == r1
 
 
 def test_exact_routes_agree_on_er_config():
