@@ -1929,9 +1929,19 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
                 __builtin_amdgcn_wave_barrier();
                 const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
                 if (L == 0) pairs += (u64)(o1 - o0);
-                for (int64_t e = o0 + L; e < o1; e += WAVE) {
-                    const int j = lds_find(sR, d, b.col[e]);
-                    if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
+                // four out-list entries loaded ahead of their searches
+                for (int64_t e0 = o0; e0 < o1; e0 += 4 * WAVE) {
+                    int32_t y[4];
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        const int64_t e = e0 + t * WAVE + L;
+                        y[t] = e < o1 ? b.col[e] : -1;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        const int j = y[t] >= 0 ? lds_find(sR, d, y[t]) : -1;
+                        if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
+                    }
                 }
                 __builtin_amdgcn_wave_barrier();
                 for (int w = (m >> 6) + L; w < W; w += WAVE) S[(size_t)m * W + w] = rw[w];
@@ -2033,11 +2043,20 @@ __device__ u64 root_own_work(int x, const u64 *S, const u64 *mask, u64 *sN, int3
     // rows before it (one 64-bit ballot per 64 rows)
     for (int w = L; w < W; w += WAVE) sN[w] = w >= xw ? S[(size_t)x * W + w] : 0ull;
     __builtin_amdgcn_wave_barrier();
-    for (int j0 = 0; j0 < x; j0 += WAVE) {
-        const int j = j0 + L;
-        const bool bit = j < x && ((S[(size_t)j * W + xw] >> (x & 63)) & 1ull);
-        const u64 bw = __ballot(bit);
-        if (L == 0) sN[j0 >> 6] |= bw;
+    // eight loads in flight per lane before their ballots
+    constexpr int GB = 8;
+    for (int j0 = 0; j0 < x; j0 += GB * WAVE) {
+        u64 v[GB];
+#pragma unroll
+        for (int t = 0; t < GB; t++) {
+            const int j = j0 + t * WAVE + L;
+            v[t] = j < x ? S[(size_t)j * W + xw] : 0ull;
+        }
+#pragma unroll
+        for (int t = 0; t < GB; t++) {
+            const u64 bw = __ballot(((v[t] >> (x & 63)) & 1ull) != 0);
+            if (L == 0 && j0 + t * WAVE < x) sN[(j0 >> 6) + t] |= bw;
+        }
         __builtin_amdgcn_wave_barrier();
     }
     for (int w = L; w < W; w += WAVE) sN[w] &= mask[w];
