@@ -2067,7 +2067,11 @@ __device__ u64 root_own_work(int x, const u64 *S, const u64 *mask, u64 *sN, int3
             const int y = q[L];
             nw += (u64)(W - (y >> 6));
             if constexpr (R == 3) {
-                for (int k = y >> 6; k < W; k++) c += (u64)__popcll(sN[k] & row_above<W>(S, y, k));
+                // every word at or above y's, all loads issued before their counts
+                const int yw = y >> 6;
+#pragma unroll
+                for (int k = 0; k < W; k++)
+                    if (k >= yw) c += (u64)__popcll(sN[k] & row_above<W>(S, y, k));
             } else {
                 u64 M2[W];
 #pragma unroll
