@@ -1841,6 +1841,19 @@ __device__ void root_big_item(const PeelBufs &b, int32_t v, int32_t ch, int32_t 
     if (threadIdx.x == 0) add_destroyed(b, v, t);
 }
 
+// index of x in the sorted list a[0, n), n <= 2048, or -1: a lower bound
+// by halving steps of fixed count, so that independent searches of one lane
+// interleave
+__device__ __forceinline__ int lds_find_fixed(const int32_t *a, int n, int32_t x) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 1024; step > 0; step >>= 1) {
+        const int q = pos + step;
+        if (q <= n && a[q - 1] < x) pos = q;
+    }
+    return pos < n && a[pos] == x ? pos : -1;
+}
+
 // first index in the sorted list a[0, n) holding x, or -1
 __device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
     int lo = 0, hi = n;
@@ -1939,7 +1952,7 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
                     }
 #pragma unroll
                     for (int t = 0; t < 4; t++) {
-                        const int j = y[t] >= 0 ? lds_find(sR, d, y[t]) : -1;
+                        const int j = y[t] >= 0 ? lds_find_fixed(sR, d, y[t]) : -1;
                         if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
                     }
                 }
