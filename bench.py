@@ -348,9 +348,24 @@ def cpu_baseline(workload: str, seed: int):
         g.exact(h, "core")
     t = time.perf_counter() - t0
     say(f"cpu baseline: {t:.1f} s")
-    return {"value": mu / t, "unit": "h-cliques/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w['gen']} generator of {workload} at n={n} (m={g.m}, h={h}, mu={mu}); {stages}; "
-                      f"{t:.2f} s, one thread"}
+    out = {"value": mu / t, "unit": "h-cliques/s", "cores": 1, "kind": "oracle",
+           "sample": f"{w['gen']} generator of {workload} at n={n} (m={g.m}, h={h}, mu={mu}); {stages}; "
+                     f"{t:.2f} s, one thread"}
+    if w["gen"] == "rmat":
+        # the secondary CPU line: the oracle's listing on OpenMP threads,
+        # clique-degrees only, on a larger graph of the same family
+        n2, s2, d2 = synth.rmat(seed=seed, **dict(w["kw"], scale=18))
+        g2 = oracle.Graph(n2, s2, d2)
+        say(f"cpu baseline: OpenMP clique-degrees on n={n2}, h={h}")
+        t0 = time.perf_counter()
+        _, mu2, nt = oracle.clique_degrees_omp(g2, h)
+        t2 = time.perf_counter() - t0
+        say(f"cpu baseline: OpenMP {t2:.1f} s on {nt} threads")
+        out["openmp"] = {"value": mu2 / t2, "unit": "h-cliques/s", "cores": nt,
+                         "kind": "secondary CPU line: the oracle's clique listing on OpenMP threads (oracle/omp_enum.c)",
+                         "sample": f"rmat generator at scale 18 (n={n2}, m={g2.m}, h={h}, mu={mu2}); "
+                                   f"clique-degrees only; {t2:.2f} s"}
+    return out
 
 
 def _batch_graphs(specs, threads=16):

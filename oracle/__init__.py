@@ -3,7 +3,10 @@
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It wraps the
 plain single-threaded C library in ``oracle.c`` (built with gcc by
-``oracle/buildlib.py``) and shares no code with the GPU library.
+``oracle/buildlib.py``) and shares no code with the GPU library.  For the
+benchmark's secondary CPU line only, ``omp_enum.c`` runs the same clique
+listing on OpenMP threads (``clique_degrees_omp``, checked against
+``Graph.clique_degrees``).
 
 All counts are exact integers and all densities are ``fractions.Fraction``.
 """
@@ -221,3 +224,32 @@ class Graph:
 
 def graph(n, src, dst) -> Graph:
     return Graph(n, src, dst)
+
+
+_omp = None
+
+
+def clique_degrees_omp(g: Graph, h: int):
+    """The benchmark's secondary CPU line: the same listing as
+    ``Graph.clique_degrees`` (each h-clique once, from its smallest-id
+    member) with the roots spread over OpenMP threads (``oracle/omp_enum.c``).
+    Returns (deg, mu, threads)."""
+    global _omp
+    if _omp is None:
+        path = os.path.join(_HERE, "liboracle_omp.so")
+        if not os.path.exists(path):
+            build(force=True)
+        lib = C.CDLL(path)
+        lib.omp_clique_degrees.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                           C.POINTER(C.c_uint64)]
+        lib.omp_clique_degrees.restype = C.c_int
+        _omp = lib
+    off, adj = g.adjacency()
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    deg = np.zeros(max(1, g.n), dtype=np.uint64)
+    mu = C.c_uint64()
+    nt = _omp.omp_clique_degrees(g.n, off.ctypes.data, adj.ctypes.data, int(h), deg.ctypes.data, C.byref(mu))
+    if nt < 0:
+        raise OracleError("omp_clique_degrees failed")
+    return deg[: g.n], int(mu.value), nt

@@ -664,3 +664,19 @@ def test_pattern_cores_match_fixpoint_definition(seed, pattern, x):
     assert core.tolist() == brute.pattern_core_fixpoint(n, edges, pattern, x)
     deg, _ = g.pattern_degrees(pattern, x)
     assert (core <= deg).all() and kmax == int(core.max())
+
+
+# ------------------------------------------------- the secondary CPU line
+
+@pytest.mark.parametrize("h", [2, 3, 4, 5])
+def test_openmp_enumeration_matches_oracle(h):
+    """The multi-threaded CPU enumeration of the benchmark's secondary CPU
+    line must give the oracle's clique-degrees (Definition 3) exactly."""
+    for seed in (1, 2):
+        n, s, d = synth.rmat(scale=10, seed=seed)
+        g = oracle.Graph(n, s, d)
+        deg, mu = g.clique_degrees(h)
+        deg2, mu2, nt = oracle.clique_degrees_omp(g, h)
+        assert nt >= 1
+        assert mu2 == mu
+        np.testing.assert_array_equal(deg2, deg)
