@@ -17,9 +17,10 @@ locate step, and the step records that refusal.
 
 Further legs: the Chung-Lu graph (n = 10^6, h = 3, where CoreExact runs to
 the end), the batched mixture (8,192 graphs, batched vs a plain per-graph
-loop), the server under load, and the CPU oracle on a bounded sample of the
-headline family.  The same R-MAT graph at h = 5 is a leg on request
-(``--legs rmat22_h5:1``): its step takes minutes.
+loop), the server under load, the CPU oracle on a bounded sample of the
+headline family and the OpenMP enumeration beside it, and the same R-MAT
+graph at h = 5: one step (about 80 s), without warm-up or per-launch
+timing.
 
 Prints one JSON line.  ``value`` is whole-pass throughput in h-cliques/s
 (mu(G, Psi) divided by the time of one step).
@@ -193,8 +194,10 @@ def roof(kernel, workload, total_ms, launches, total_bytes):
             "timing": "HIP events around every launch of one extra step after the timed ones"}
 
 
-def run_workload(name: str, seed: int, steps: int, warmup: int):
-    """Timed steps of one workload; returns the record of the bench line."""
+def run_workload(name: str, seed: int, steps: int, warmup: int, instrument: bool = True):
+    """Timed steps of one workload; returns the record of the bench line.
+    instrument=False skips the step with per-launch kernel timing (no
+    roofline then)."""
     import numpy as np
     import torch
 
@@ -253,9 +256,12 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
     # one more step, right after the timed ones, with every launch of the
     # peel's main kernels bracketed by HIP events on the graph's stream (each
     # bracketed launch costs the host ~20 us, so the timed steps run without)
-    t = time.perf_counter()
-    inst = step(time_kernels=True)["core"]
-    progress("step with per-launch kernel timing", t)
+    if instrument:
+        t = time.perf_counter()
+        inst = step(time_kernels=True)["core"]
+        progress("step with per-launch kernel timing", t)
+    else:
+        inst = recs[-1]["core"]
 
     core = recs[-1]["core"]
     ex = recs[-1]["exact"]
@@ -264,17 +270,18 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
     k3_ms = avg("k3_ms", "core")
     k4_ms = avg("k4_ms", "core")
     kind = inst["k4_main_kind"]
-    cands = [roof(MAIN_KERNEL.get(kind), name, inst["k4_main_ms"], inst["k4_main_launches"],
+    cands = [] if not instrument else [roof(MAIN_KERNEL.get(kind), name, inst["k4_main_ms"], inst["k4_main_launches"],
                   main_kernel_bytes(inst))]
-    cands[0].update({"pairs_per_step": inst["k4_main_pairs"], "members_per_step": inst["k4_main_nbrs"],
-                     "row_entries_per_step": inst["k4_main_entries"]})
-    if kind in MAIN2_KERNEL:
+    if cands:
+        cands[0].update({"pairs_per_step": inst["k4_main_pairs"], "members_per_step": inst["k4_main_nbrs"],
+                         "row_entries_per_step": inst["k4_main_entries"]})
+    if instrument and kind in MAIN2_KERNEL:
         # k_root_count: the bitmap words it ANDs and counts (its first level:
         # all of its work at h = 4) against the ALU peak
         r2 = roof_alu(MAIN2_KERNEL[kind], inst["k4_main2_ms"], inst["k4_main2_launches"], inst["k4_main2_words"])
         r2.update({"members_per_step": inst["k4_main_nbrs"]})
         cands.append(r2)
-    if inst["k4_tail_launches"]:
+    if instrument and inst["k4_tail_launches"]:
         t = roof(TAIL_KERNEL, name, inst["k4_tail_ms"], inst["k4_tail_launches"], tail_kernel_bytes(inst))
         t.update({"pairs_per_step": inst["k4_tail_pairs"], "tail_vertices": inst["k4_tail_vertices"],
                   "grid_rounds": inst["k4_tail_grid_rounds"], "grid_pairs": inst["k4_tail_grid_pairs"],
@@ -313,7 +320,7 @@ def run_workload(name: str, seed: int, steps: int, warmup: int):
             "enum_hbm_frac": k3_bytes(core) / (k3_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k3_ms else None,
             "peel_hbm_frac": k4_bytes(inst, h) / (k4_ms / 1e3) / 1e9 / HBM_PEAK_GBS if k4_ms else None,
         },
-        "roofline": cands[0],
+        "roofline": cands[0] if cands else None,
         "roofline_other": cands[1:],
     }
 
@@ -534,8 +541,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22_h4", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--legs", default="chung_lu_1e6:5",
-                    help="further workloads as name:steps, comma-separated ('' for none)")
+    ap.add_argument("--legs", default="chung_lu_1e6:5,rmat22_h5:1:0",
+                    help="further workloads as name:steps[:warmup], comma-separated ('' for none); "
+                         "a leg with warmup 0 also skips the step with per-launch kernel timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=8192,
                     help="graphs of the batched mixture in the batched-vs-plain leg (0: skip)")
@@ -568,10 +576,13 @@ def main() -> int:
     }
     legs = {}
     for spec in [x for x in args.legs.split(",") if x]:
-        name, _, k = spec.partition(":")
-        r = run_workload(name, args.seed, int(k or 1), 1)
+        parts = spec.split(":")
+        name = parts[0]
+        k = int(parts[1]) if len(parts) > 1 and parts[1] else 1
+        wu = int(parts[2]) if len(parts) > 2 and parts[2] else 1
+        r = run_workload(name, args.seed, k, wu, instrument=wu > 0)
         legs[name] = {"value": r["value"], "unit": "h-cliques/s", "ms_per_step": r["ms_per_step"],
-                      "steps": int(k or 1), "config": r["config"], "stages_ms": r["stages_ms"],
+                      "steps": k, "warmup": wu, "config": r["config"], "stages_ms": r["stages_ms"],
                       "kernel_rates": r["kernel_rates"], "roofline": r["roofline"]}
     if legs:
         out["legs"] = legs
