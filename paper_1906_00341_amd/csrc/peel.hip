@@ -159,10 +159,16 @@ constexpr int ROOT_SW = ROOT_CAP * 32;  // words of one workgroup's bitmap rows 
 constexpr int ROOT_SLICE = ROOT_SW + 32; // and their mask words
 constexpr int ROOT_WAVE_MAX = 64;       // rows up to this long: one wave per frontier vertex
 constexpr int ROOT_SL = 64;             // members of C_v per item of a sliced vertex (a slice)
+constexpr int ROOT_SLICED_H4 = 4096;    // h = 4: rows up to this long are sliced (64-word bitmap rows)
 constexpr int ROOT_SUB = ROOT_SL / WAVES_PER_BLOCK;  // workgroups per slice: one wave per member
 
 // words per bitmap row of a vertex whose row holds d entries (|C_v| <= d)
-__device__ __forceinline__ int root_words(int64_t d) { return d <= 256 ? 4 : d <= 768 ? 12 : d <= 1280 ? 20 : 32; }
+__device__ __forceinline__ int root_words(int64_t d) {
+    return d <= 256 ? 4 : d <= 768 ? 12 : d <= 1280 ? 20 : d <= 2048 ? 32 : 64;
+}
+// the longest row a sliced vertex may have: at h = 4 the counting keeps no
+// per-lane word arrays, so its rows may take 64 words
+__device__ __forceinline__ int64_t root_sliced_max(int h) { return h == 4 ? ROOT_SLICED_H4 : ROOT_CAP; }
 // words of a sliced vertex's region: one bitmap row per entry of v's row
 // (d * W; bit j > i of row i: entries i and j are adjacent; only the words
 // from i / 64 up are written), then the mask of the entries that take part
@@ -265,9 +271,10 @@ __device__ __forceinline__ void wave_add_by_graph(int32_t g, T *base, size_t str
 __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int which) {
     if (b.rootmode) {
         // root mode: a short row is one wave item (T); a row of at most
-        // ROOT_CAP entries gets bitmap rows in its half of the arena and one
-        // item per ROOT_SL-member slice (B); a longer row, or one the arena
-        // has no room for, a single-workgroup item per ROOT_CAP neighbours (Big)
+        // root_sliced_max entries gets bitmap rows in its half of the arena
+        // and one item per ROOT_SL-member slice (B); a longer row, or one the
+        // arena has no room for, a single-workgroup item per ROOT_CAP
+        // neighbours (Big)
         const int64_t d = b.row_ptr[x + 1] - b.row_ptr[x];
         if (d == 0) return;
         if (d <= ROOT_WAVE_MAX) {
@@ -275,7 +282,7 @@ __device__ __forceinline__ void push_chunks(const PeelBufs &b, int32_t x, int wh
             b.T[(size_t)which * b.tcap + pos] = (int64_t)x << 32;
             return;
         }
-        if (d <= ROOT_CAP) {
+        if (d <= root_sliced_max(b.h)) {
             const int64_t words = root_region(d);
             const int64_t off = (int64_t)atomicAdd((unsigned long long *)&b.ctl->htop[which], (unsigned long long)words);
             if (off + words <= b.rcap) {
@@ -1841,13 +1848,13 @@ __device__ void root_big_item(const PeelBufs &b, int32_t v, int32_t ch, int32_t 
     if (threadIdx.x == 0) add_destroyed(b, v, t);
 }
 
-// index of x in the sorted list a[0, n), n <= 2048, or -1: a lower bound
+// index of x in the sorted list a[0, n), n <= 4096, or -1: a lower bound
 // by halving steps of fixed count, so that independent searches of one lane
 // interleave
 __device__ __forceinline__ int lds_find_fixed(const int32_t *a, int n, int32_t x) {
     int pos = 0;
 #pragma unroll
-    for (int step = 1024; step > 0; step >>= 1) {
+    for (int step = 2048; step > 0; step >>= 1) {
         const int q = pos + step;
         if (q <= n && a[q - 1] < x) pos = q;
     }
@@ -1871,7 +1878,7 @@ __device__ __forceinline__ void add_destroyed_m(const PeelBufs &b, int32_t v, u6
     if (t) atomicAdd(&b.gs[graph_of(b, v)].destroyed_m, t);
 }
 
-// Arc discovery.  A sliced vertex v (a row of ROOT_WAVE_MAX + 1 .. ROOT_CAP
+// Arc discovery.  A sliced vertex v (a row of ROOT_WAVE_MAX + 1 .. 2048 (4096 at h = 4)
 // entries) has a region in this round's half of the arena: one bitmap row
 // per entry of v's row, indexed by row position, and the mask of the entries
 // that take part in v's cliques (alive, and not a frontier vertex of smaller
@@ -1887,7 +1894,7 @@ __device__ __forceinline__ void add_destroyed_m(const PeelBufs &b, int32_t v, u6
 // whole count, C_v in one 64-bit word per member.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
-    __shared__ int32_t sR[ROOT_CAP];
+    __shared__ int32_t sR[ROOT_SLICED_H4];
     __shared__ int32_t wC[WAVES_PER_BLOCK][64];
     __shared__ int32_t wKey[WAVES_PER_BLOCK][128];
     __shared__ int32_t wVal[WAVES_PER_BLOCK][128];
@@ -1895,7 +1902,7 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     __shared__ int64_t wSt[WAVES_PER_BLOCK][64];
     __shared__ u64 wCnt[WAVES_PER_BLOCK][64];
     __shared__ u64 wS[WAVES_PER_BLOCK][64];
-    __shared__ u64 wRow[WAVES_PER_BLOCK][32];
+    __shared__ u64 wRow[WAVES_PER_BLOCK][64];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
     if (c->nF[cur] == 0) return;
@@ -1910,7 +1917,7 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
         const int sub = (int)(it % ROOT_SUB);
         if (b.deg[v] == 0) continue;                   // block-uniform: fixed in v's round
         const int64_t s0 = b.row_ptr[v];
-        const int d = (int)(b.row_ptr[v + 1] - s0);    // <= ROOT_CAP for a sliced vertex
+        const int d = (int)(b.row_ptr[v + 1] - s0);    // <= root_sliced_max(h) for a sliced vertex
         for (int i = threadIdx.x; i < d; i += BLOCK) sR[i] = b.col[s0 + i];
         __syncthreads();
         const int W = root_words(d);
@@ -2122,6 +2129,9 @@ __device__ u64 root_own(int x, int W, const u64 *S, const u64 *mask, u64 *sN, in
     if (W == 4) return root_own_work<R, 4>(x, S, mask, sN, q, words);
     if (W == 12) return root_own_work<R, 12>(x, S, mask, sN, q, words);
     if (W == 20) return root_own_work<R, 20>(x, S, mask, sN, q, words);
+    if constexpr (R == 3) {
+        if (W == 64) return root_own_work<R, 64>(x, S, mask, sN, q, words);
+    }
     return root_own_work<R, 32>(x, S, mask, sN, q, words);
 }
 
@@ -2137,6 +2147,7 @@ __device__ u64 root_own(int x, int W, const u64 *S, const u64 *mask, u64 *sN, in
 template <int R, bool SLICED, bool BIG>
 __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
     __shared__ int32_t sQ[WAVES_PER_BLOCK][2 * WAVE];
+    __shared__ u64 sN64[WAVES_PER_BLOCK][64];
     __shared__ u64 sAB[WAVES_PER_BLOCK][2][32];
     PeelCtl *c = b.ctl;
     const int32_t cur = c->cur;
@@ -2160,7 +2171,7 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
         const u64 *S = bits + b.rbase[v];
         const u64 *mask = S + (int64_t)d * W;
         if (((mask[m >> 6] >> (m & 63)) & 1ull) == 0) continue;
-        const u64 cx = root_own<R>(m, W, S, mask, sAB[wv][0], sQ[wv], &words);
+        const u64 cx = root_own<R>(m, W, S, mask, sN64[wv], sQ[wv], &words);
         if (cx && lane() == 0) {
             const int32_t x = b.col[s0 + m];
             if (b.stamp[x] > r) dec_deg(b, x, cx, r);

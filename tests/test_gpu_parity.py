@@ -212,6 +212,49 @@ def test_hub_with_sparse_out_neighbourhood():
         np.testing.assert_array_equal(core, core_o)
 
 
+@pytest.mark.parametrize("k", [2400, 3500, 4500])
+def test_hub_rows_beyond_2048(k):
+    """A hub whose row holds k entries is removed while that row is long: k - 4
+    of its neighbours have no clique and leave in the first round (before
+    any compaction of the adjacency), and the other four, which with the hub
+    form a K5, also belong to a K10 and so outlast it; the hub leaves next,
+    alone, with its whole row.  At h = 4 a row of up to 4,096 entries takes
+    the sliced counting with 64-word bitmap rows, a longer one a single
+    workgroup; at h = 5 every row beyond 2,048 entries takes a single
+    workgroup.  Clique-degrees, cores and CoreApp against the oracle."""
+    hub = 0
+    sat = np.arange(1, k + 1)
+    extra = np.arange(k + 1, k + 7)                  # 6 more vertices of the K10
+    src, dst = [np.full(k, hub)], [sat]
+    quad = sat[:4]
+    ten = np.concatenate([quad, extra])
+    iu, ju = np.triu_indices(ten.size, 1)
+    src.append(ten[iu])
+    dst.append(ten[ju])
+    n = k + 7
+    s = np.concatenate(src).astype(np.int32)
+    d = np.concatenate(dst).astype(np.int32)
+    perm = np.random.default_rng(k).permutation(n).astype(np.int32)
+    s, d = perm[s], perm[d]
+    g = dsd.build_csr(n, s, d)
+    og = oracle.Graph(n, s, d)
+    for h in (4, 5):
+        deg, mu = dsd.clique_degrees(g, h)
+        deg_o, mu_o = og.clique_degrees(h)
+        assert mu == mu_o
+        np.testing.assert_array_equal(deg, deg_o)
+        core, km = dsd.clique_core(g, h)
+        core_o, km_o = og.core_decomposition(h)
+        assert km == km_o
+        np.testing.assert_array_equal(core, core_o)
+        # the hub left at its own level, below the K10's
+        assert 0 < core_o[perm[hub]] < km_o
+        mem, km2, dens = dsd.core_app(g, h)
+        mem_o, km2_o, dens_o = og.inc_app(h)
+        assert km2 == km2_o and dens == dens_o
+        np.testing.assert_array_equal(mem.astype(bool), mem_o)
+
+
 @pytest.mark.parametrize("h", [4])
 def test_hub_class_k1500_plus_noise(h):
     """A 1,500-vertex clique (every root of out-degree 1,281 .. 1,499 takes
