@@ -3424,8 +3424,15 @@ PeelResult peel(const DevGraph &g, int h, const uint8_t *alive0, u64 *deg, u64 m
         b.Big = sc.get_n<int64_t>(2 * b.bigcap);
         // bitmap rows of one round's sliced vertices (a vertex that finds no
         // room becomes a single-workgroup item); every word read is written
-        // in the same round (or masked out), so nothing is cleared
-        b.rcap = std::min<int64_t>((int64_t)1 << 26, std::max<int64_t>((int64_t)1 << 16, 16 * g.m));
+        // in the same round (or masked out), so nothing is cleared.  At h = 4
+        // a half holds 2^21 words (16 MiB, half the chip's L2): in a round
+        // with many long rows the regions beyond that thrash L2 and do better
+        // as single-workgroup items, whose bitmaps stay in one workgroup's
+        // slice (R-MAT scale 22: CoreApp's peel 0.96 s at 2^26 words, 0.54 s
+        // at 2^21; the full peel 4.46 -> 4.24 s); at h >= 5 (rows of at most
+        // 2,048 entries) 2^26 measures slightly better.
+        const int64_t rmax = h == 4 ? (int64_t)1 << 21 : (int64_t)1 << 26;
+        b.rcap = std::min<int64_t>(rmax, std::max<int64_t>((int64_t)1 << 16, 16 * g.m));
         // DSD_ROOT_ARENA_WORDS overrides the arena size (0: every vertex a single-workgroup item)
         if (const char *ra = std::getenv("DSD_ROOT_ARENA_WORDS")) b.rcap = std::max<int64_t>(1, std::atoll(ra));
         b.rbits = sc.get_n<u64>(2 * b.rcap);
