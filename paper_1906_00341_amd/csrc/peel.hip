@@ -579,8 +579,11 @@ __device__ __forceinline__ void finish_graph(const PeelBufs &b, int32_t g) {
         s.k = k;
         s.kcand = ~0ull;
     }
+    if (s.nF[cur] == s.n_alive)
+        s.mu_alive = 0;                             // every alive vertex left: no clique remains
+    else
+        s.mu_alive -= s.destroyed + (s.destroyed_m ? s.destroyed_m / (u64)(b.h - 1) : 0ull);
     s.n_alive -= s.nF[cur];
-    s.mu_alive -= s.destroyed + (s.destroyed_m ? s.destroyed_m / (u64)(b.h - 1) : 0ull);
     s.destroyed = 0;
     s.destroyed_m = 0;
     s.nF[cur] = 0;
@@ -1872,6 +1875,24 @@ __device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
     return lo < n && a[lo] == x ? lo : -1;
 }
 
+// one step of a member's out-list walk: EA entries per lane loaded before
+// their (fixed-step, interleaved) searches in v's row
+template <int EA>
+__device__ __forceinline__ void root_walk(const int32_t *col, int64_t e0, int64_t o1, const int32_t *sR, int d, u64 *rw,
+                                          int L) {
+    int32_t y[EA];
+#pragma unroll
+    for (int t = 0; t < EA; t++) {
+        const int64_t e = e0 + t * WAVE + L;
+        y[t] = e < o1 ? col[e] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < EA; t++) {
+        const int j = y[t] >= 0 ? lds_find_fixed(sR, d, y[t]) : -1;
+        if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
+    }
+}
+
 // cliques counted per member of a sliced vertex (each clique once for every
 // one of its h - 1 members besides v)
 __device__ __forceinline__ void add_destroyed_m(const PeelBufs &b, int32_t v, u64 t) {
@@ -1904,9 +1925,16 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
     __shared__ u64 wS[WAVES_PER_BLOCK][64];
     __shared__ u64 wRow[WAVES_PER_BLOCK][64];
     PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur;
-    if (c->nF[cur] == 0) return;
-    const int32_t r = c->round, nG = c->nB[cur], nI = c->nT[cur];
+    // the round's fields of both halves loaded together, the half in use picked after
+    const int32_t cur = c->cur, r = c->round;
+    const int64_t nalive = c->n_alive;
+    const int2 f2 = *(const int2 *)c->nF, b2 = *(const int2 *)c->nB, t2 = *(const int2 *)c->nT;
+    const int32_t nFc = cur ? f2.y : f2.x;
+    // a round of the one graph that removes every alive vertex leaves no
+    // survivor whose degree could fall: nothing to count (its end sets the
+    // graph's clique count to zero)
+    if (nFc == 0 || (b.G == 1 && (int64_t)nFc == nalive)) return;
+    const int32_t nG = cur ? b2.y : b2.x, nI = cur ? t2.y : t2.x;
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     u64 *bits = b.rbits + (size_t)cur * b.rcap;
     const int wv = threadIdx.x / WAVE, L = lane();
@@ -1915,13 +1943,14 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
         const int64_t item = Bc[it / ROOT_SUB];
         const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
         const int sub = (int)(it % ROOT_SUB);
-        if (b.deg[v] == 0) continue;                   // block-uniform: fixed in v's round
-        const int64_t s0 = b.row_ptr[v];
-        const int d = (int)(b.row_ptr[v + 1] - s0);    // <= root_sliced_max(h) for a sliced vertex
+        const u64 dv = b.deg[v];
+        const int64_t s0 = b.row_ptr[v], s1 = b.row_ptr[v + 1], rb = b.rbase[v];
+        if (dv == 0) continue;                         // block-uniform: fixed in v's round
+        const int d = (int)(s1 - s0);                  // <= root_sliced_max(h) for a sliced vertex
         for (int i = threadIdx.x; i < d; i += BLOCK) sR[i] = b.col[s0 + i];
         __syncthreads();
         const int W = root_words(d);
-        u64 *S = bits + b.rbase[v];
+        u64 *S = bits + rb;
         if (sl == 0 && sub == 0) {
             // the mask: wave wv takes word base / 64 + wv of each pass
             u64 *mask = S + (int64_t)d * W;
@@ -1941,26 +1970,23 @@ __global__ __launch_bounds__(BLOCK) void k_root_edges(PeelBufs b) {
         const int m = sl * ROOT_SL + sub * WAVES_PER_BLOCK + wv;
         if (m < d) {
             const int32_t x = sR[m];
-            if (allowed(b.stamp[x], r, x, v)) {            // wave-uniform
+            const int32_t sx = b.stamp[x];
+            const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];   // with the stamp
+            if (allowed(sx, r, x, v)) {                    // wave-uniform
                 // the upper part of row m (bits j > m) in LDS, then written
                 // out whole from word m / 64 on
                 u64 *rw = wRow[wv];
                 for (int w = L; w < W; w += WAVE) rw[w] = 0;
                 __builtin_amdgcn_wave_barrier();
-                const int64_t o0 = b.dag_off[x], o1 = b.row_ptr[x + 1];
                 if (L == 0) pairs += (u64)(o1 - o0);
-                // four out-list entries loaded ahead of their searches
-                for (int64_t e0 = o0; e0 < o1; e0 += 4 * WAVE) {
-                    int32_t y[4];
-#pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const int64_t e = e0 + t * WAVE + L;
-                        y[t] = e < o1 ? b.col[e] : -1;
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const int j = y[t] >= 0 ? lds_find_fixed(sR, d, y[t]) : -1;
-                        if (j >= 0) atomicOr((unsigned long long *)&rw[j >> 6], 1ull << (j & 63));
+                // a long out-list takes 16 entries per lane a step, a short one 4
+                for (int64_t e0 = o0; e0 < o1;) {
+                    if (o1 - e0 > 8 * WAVE) {
+                        root_walk<16>(b.col, e0, o1, sR, d, rw, L);
+                        e0 += 16 * WAVE;
+                    } else {
+                        root_walk<4>(b.col, e0, o1, sR, d, rw, L);
+                        e0 += 4 * WAVE;
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
@@ -2150,9 +2176,13 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
     __shared__ u64 sN64[WAVES_PER_BLOCK][64];
     __shared__ u64 sAB[WAVES_PER_BLOCK][2][32];
     PeelCtl *c = b.ctl;
-    const int32_t cur = c->cur;
-    const bool any = c->nF[cur] != 0;
-    const int32_t r = c->round, nG = any ? c->nB[cur] : 0, nBig = any ? c->nBig[cur] : 0;
+    // the round's fields of both halves loaded together, the half in use picked after
+    const int32_t cur = c->cur, r = c->round;
+    const int64_t nalive = c->n_alive;
+    const int2 f2 = *(const int2 *)c->nF, b2 = *(const int2 *)c->nB, g2 = *(const int2 *)c->nBig;
+    const int32_t nFc = cur ? f2.y : f2.x;
+    const bool any = nFc != 0 && !(b.G == 1 && (int64_t)nFc == nalive);   // (as in k_root_edges)
+    const int32_t nG = any ? (cur ? b2.y : b2.x) : 0, nBig = any ? (cur ? g2.y : g2.x) : 0;
     const int64_t *Bc = b.B + (size_t)cur * b.bcap;
     const u64 *bits = b.rbits + (size_t)cur * b.rcap;
     const int wv = threadIdx.x / WAVE;
@@ -2163,18 +2193,20 @@ __global__ __launch_bounds__(BLOCK) void k_root_count(PeelBufs b, u64 *gS) {
         const int64_t item = Bc[t / ROOT_SL];
         const int32_t v = (int32_t)(item >> 32), sl = (int32_t)(item & 0xffffffff);
         const int m = sl * ROOT_SL + (int)(t % ROOT_SL);
-        if (b.deg[v] == 0) continue;                   // its items made no arcs either
-        const int64_t s0 = b.row_ptr[v];
-        const int d = (int)(b.row_ptr[v + 1] - s0);
+        const u64 dv = b.deg[v];
+        const int64_t s0 = b.row_ptr[v], s1 = b.row_ptr[v + 1], rb = b.rbase[v];
+        if (dv == 0) continue;                         // its items made no arcs either
+        const int d = (int)(s1 - s0);
         if (m >= d) continue;
         const int W = root_words(d);
-        const u64 *S = bits + b.rbase[v];
+        const u64 *S = bits + rb;
         const u64 *mask = S + (int64_t)d * W;
+        const int32_t x = b.col[s0 + m];              // with the mask word
         if (((mask[m >> 6] >> (m & 63)) & 1ull) == 0) continue;
+        const int32_t sx = b.stamp[x];                 // in flight during the count
         const u64 cx = root_own<R>(m, W, S, mask, sN64[wv], sQ[wv], &words);
         if (cx && lane() == 0) {
-            const int32_t x = b.col[s0 + m];
-            if (b.stamp[x] > r) dec_deg(b, x, cx, r);
+            if (sx > r) dec_deg(b, x, cx, r);
             add_destroyed_m(b, v, cx);
         }
     }
