@@ -692,7 +692,18 @@ u64 core_app_run(dsd_graph_s *G, int h, uint8_t *best, dsd_rational *density) {
             }
             // stop once every vertex outside W has gamma < kmax (its clique-core number is smaller)
             if (w >= n || gamma_at(w) < kmax) break;
-            w = std::min<int64_t>(n, 2 * w);
+            // W doubles (Algorithm 6), or, when more vertices than that have
+            // gamma >= the k_max found so far, grows to take all of them at
+            // once (up to 8 |W|): the stopping test can pass only once they
+            // are all in W, and the core it returns does not depend on the
+            // sizes W passes through
+            int64_t lo = w, hi = n;                    // first position whose gamma < kmax
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (gamma_at(mid) >= kmax) lo = mid + 1;
+                else hi = mid;
+            }
+            w = std::min<int64_t>(n, std::max<int64_t>(2 * w, std::min<int64_t>(lo, 8 * w)));
         }
     }
     if (density) *density = kmax > 0 ? make_rational(best_mu, best_size) : dsd_rational{0, 1};
